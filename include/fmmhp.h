@@ -1,0 +1,170 @@
+/*
+ * fmmhp.h -- fast multipole evaluation of the 2-D half-plane Laplace potential
+ * with a Robin (impedance) boundary condition, on AMD gfx950 (MI355X).
+ *
+ * Computes, for N charged points r_j = (x_j, y_j) with y_j > 0 and charges q_j,
+ *
+ *     phi_i = sum_j q_j G(r_i, r_j),      i = 1..N            (Section 2.2, eq. (potential1))
+ *
+ * where G is the Green's function of Section 2.1, eq. (ddGreensfunimp):
+ *
+ *     G(r, r') = -(1/2pi) ln|r - r'| + (1/2pi) ln|r - r'_im| + G_Z(r, r'),
+ *     r'_im = (x', -y'),  G_Z = I_0(x - x', y + y') + I_0(x' - x, y + y')   (eq. (reactdecomposition)),
+ *     I_n(x, y) = 1/(2 pi n!) int_0^inf exp(-lam y + i lam x) lam^n / (lam - Z_eps) dlam   (eq. (generalintegral)),
+ *
+ * with impedance Z_eps = lambda_re + i lambda_im (lambda_re > 0, lambda_im >= 0; lambda_im = 0 is the
+ * lossless case, understood by limiting absorption, eq. (dzGreensfunimplossless)).  The free-space
+ * log term skips j with r_j == r_i (eq. (1.2)); the image and reaction terms keep every j.  phi is
+ * complex even for real charges and real impedance.
+ *
+ * The potential is split as Algorithm 2 of the paper does (free-space, image and reaction parts) and
+ * evaluated with an adaptive quadtree over the points and their images (Algorithm 1), the paper's
+ * reaction-field expansions and translation operators (S2M, M2M, M2L, L2L, S2L: eqs. (MEcoefficients),
+ * (metome), (truncatedM2Lcoef), (truncatedL2L), (LEcoefficients)), the textbook log-kernel
+ * expansions, and direct summation between neighbouring leaves.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked [device] are device pointers on the current HIP device; [host] are host
+ *     pointers.  The caller owns every buffer it passes.  Arrays are dense, float64, SoA.
+ *   - Work is issued on `stream` (0 = the null stream) and is asynchronous with respect to the host
+ *     unless stated otherwise; outputs are valid once the stream reaches that point.
+ *   - Every call returns a status and never throws.  On failure, fmmhp_last_error_message() (per
+ *     host thread) describes the cause.  Kernel faults surface as FMMHP_EHIP on a later call.
+ *   - A plan is bound to the device that was current at creation and must be used from that device.
+ *     Calls that share a plan must not overlap in time (the plan owns one workspace).
+ */
+#ifndef FMMHP_H
+#define FMMHP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmmhp_plan_s *fmmhp_plan_t;
+
+typedef enum {
+    FMMHP_OK = 0,
+    FMMHP_EINVAL = 1,       /* null pointer, size or option out of range, non-finite input */
+    FMMHP_EDOMAIN = 2,      /* outside the problem's domain: a point with y <= 0, Re Z <= 0,
+                               Im Z < 0, or image arrays that are not exactly (x, -y) */
+    FMMHP_ENOMEM = 3,       /* device or host allocation failed */
+    FMMHP_EHIP = 4,         /* a HIP runtime call failed */
+    FMMHP_ESTATE = 5,       /* plan handle is NULL or already destroyed */
+    FMMHP_EUNSUPPORTED = 6  /* valid request this build does not handle (see message) */
+} fmmhp_status;
+
+#define FMMHP_MAX_P 40
+
+typedef struct {
+    int p;          /* truncation order: expansion coefficients n = 0..p (the paper's p,
+                       eq. (truncatedME)).  1 <= p <= FMMHP_MAX_P.  The kernels are compiled for
+                       p in {5, 10, ..., 40}; other values are rounded UP to the next of these and
+                       fmmhp_plan_info reports the order actually used. */
+    int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
+    int max_level;  /* deepest tree level, 1..30; 0 selects 30 */
+    unsigned flags; /* reserved, must be 0 */
+} fmmhp_opts;
+
+typedef struct {
+    int64_t n;              /* number of points */
+    int p;                  /* truncation order in use */
+    int leaf_size, max_level;
+    int depth;              /* deepest level present */
+    int64_t nbox;           /* upper-half boxes (each has an implicit mirror image box) */
+    int64_t nleaf;
+    int64_t list_len[4];    /* total entries of the U, V, W, X lists */
+    double x_lo, S, scale;  /* root square [x_lo, x_lo + S] x [-S/2, S/2]; cells = 2^30 / S */
+    double lambda_re, lambda_im;
+    int real_impedance;     /* 1 if lambda_im == 0 (one local expansion + rank-one surface term) */
+    int64_t device_bytes;   /* device memory held by the plan */
+} fmmhp_plan_stats;
+
+/* Build a plan: the adaptive quadtree over the points and their images, interaction lists and
+ * translation tables (Algorithm 1: "generate image coordinates", "generate an adaptive hierarchical
+ * tree ... and pre-compute some tables").
+ *
+ *   n              number of points (sources = targets), 1 <= n < 2^31
+ *   x, y           [device] point coordinates, y > 0, finite
+ *   img_x, img_y   [device] the image sources r_j^im = (x_j, -y_j) (Section 2.2), or both NULL.  When
+ *                  given they must equal (x, -y) bitwise, else FMMHP_EDOMAIN: the tree is built
+ *                  over the points and their exact mirror images.
+ *   lambda_re/im   impedance Z_eps; lambda_re > 0, lambda_im >= 0
+ *   opts           [host] options (see fmmhp_opts); NULL selects p = 20, leaf_size = 40
+ *   stream         stream for the build; this call synchronises it (tree sizes are read back)
+ *   plan_out       [host] receives the plan handle, owned by the caller until fmmhp_plan_destroy
+ *
+ * The plan keeps its own sorted copy of the coordinates: x, y may be freed after the call returns.
+ */
+fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, const double *img_x,
+                               const double *img_y, double lambda_re, double lambda_im,
+                               const fmmhp_opts *opts, hipStream_t stream,
+                               fmmhp_plan_t *plan_out);
+
+/* Evaluate phi = A q for n_vec real charge vectors (Algorithm 2).
+ *
+ *   n_vec   number of charge vectors, >= 1
+ *   q       [device] charges, [n_vec][n] row-major, real, in the caller's point order
+ *   phi     [device] output, [n_vec][n][2] (re, im) interleaved, caller's point order
+ *
+ * Complex charges are linear: evaluate their real and imaginary parts as two vectors.
+ * No host synchronisation; the plan's workspace is reused across calls.
+ */
+fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
+                        hipStream_t stream);
+
+/* Plan statistics (sizes, root square, order in use).  stats: [host]. */
+fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *stats);
+
+/* Copy the tree and interaction lists to host arrays, for bit-exact comparison with a reference
+ * build.  Box arrays have stats.nbox entries, perm has n, list offsets nbox + 1, list entries
+ * stats.list_len[k].  Boxes are numbered by (level, Morton prefix); list entries are
+ * 2 * box + image (image = 1 refers to the mirror image of that box below y = 0), ascending.
+ * Any pointer may be NULL to skip that array.  Synchronises the plan's stream.
+ *
+ *   level, bx, by   box level (1..30) and full-tree integer coordinates (by >= 2^(level-1))
+ *   first, count    range of the box's points in sorted order
+ *   parent          parent box, -1 at level 1;  leaf: 1 if the box is a leaf
+ *   child_first, nchild   children are the nchild boxes starting at child_first (-1 if none)
+ *   perm            sorted position -> input index
+ *   {u,v,w,x}_off, _ent   CSR lists U (near field), V (M2L), W (M2P), X (P2L)
+ */
+fmmhp_status fmmhp_plan_export_tree(fmmhp_plan_t plan, int32_t *level, int32_t *bx, int32_t *by,
+                                    int32_t *first, int32_t *count, int32_t *parent,
+                                    int32_t *leaf, int32_t *child_first, int32_t *nchild,
+                                    int64_t *perm, int64_t *u_off, int32_t *u_ent,
+                                    int64_t *v_off, int32_t *v_ent, int64_t *w_off,
+                                    int32_t *w_ent, int64_t *x_off, int32_t *x_ent);
+
+/* Release the plan and its device memory.  Synchronises the device.  plan may be NULL (no-op). */
+fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan);
+
+/* Direct O(n_tgt * n_src) evaluation of phi_i = sum_j q_j G(r_i, r_j) on the GPU, with the same
+ * kernel arithmetic as the FMM's near field (eqs. (1.2), (reactioncomp1)).  Targets may differ from
+ * sources; the free-space term skips pairs with identical coordinates.
+ *   src_x, src_y, q  [device] [n_src] (q: [n_vec][n_src]);  tgt_x, tgt_y [device] [n_tgt]
+ *   phi              [device] [n_vec][n_tgt][2]
+ */
+fmmhp_status fmmhp_direct_eval(int64_t n_src, const double *src_x, const double *src_y,
+                               int n_vec, const double *q, int64_t n_tgt, const double *tgt_x,
+                               const double *tgt_y, double lambda_re, double lambda_im,
+                               double *phi, hipStream_t stream);
+
+/* The reaction integrals I_0 .. I_nmax of eq. (generalintegral) at m points (x_k, y_k), y_k > 0,
+ * computed on the GPU from the closed form of I_0 (exponential integral) and the upward recursion
+ * of eq. (integralrecursion).
+ *   x, y  [device] [m];  out [device] [m][nmax + 1][2];  0 <= nmax <= 2 * FMMHP_MAX_P
+ */
+fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *y, int nmax,
+                                      double lambda_re, double lambda_im, double *out,
+                                      hipStream_t stream);
+
+const char *fmmhp_status_string(fmmhp_status s);
+const char *fmmhp_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMMHP_H */

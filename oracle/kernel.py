@@ -94,3 +94,23 @@ def green_dirichlet(xt, yt, xs, ys):
     r2 = dx * dx + (np.asarray(yt) - np.asarray(ys)) ** 2
     r2_im = dx * dx + (np.asarray(yt) + np.asarray(ys)) ** 2
     return (np.log(r2_im) - np.log(r2)) / (2.0 * TWO_PI)
+
+
+def reaction_In_mp(nmax: int, x: float, y: float, Z, dps: int = 50):
+    """I_0 .. I_nmax at one point in multiple precision (mpmath), same definitions as
+    ``reaction_In``: the Ei closed form for I_0 and the recursion of eq. (integralrecursion)
+    carried out with ``dps`` digits, so that the upward recursion's growth of rounding error
+    (about exp(|Z w|) at orders near |Z w|) does not reach float64 precision.
+    Returns complex128 [nmax + 1].
+    """
+    import mpmath as mp
+    with mp.workdps(dps):
+        Zm = mp.mpc(complex(Z).real, complex(Z).imag)
+        w = mp.mpc(float(y), -float(x))
+        P = Zm * w
+        I = mp.exp(-P) * (1j * mp.pi - mp.ei(P)) / (2 * mp.pi)
+        out = [complex(I)]
+        for n in range(1, nmax + 1):
+            I = 1 / (2 * mp.pi * n * w ** n) + Zm / n * I
+            out.append(complex(I))
+    return np.array(out)

@@ -1,0 +1,284 @@
+"""Half-plane Robin Laplace FMM on AMD MI355X (gfx950): Python binding.
+
+Argument marshalling over the C-ABI library ``libfmmhp.so`` (declared in
+``include/fmmhp.h``); every step of the computation runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream only.  There is
+no CPU fallback: the functions raise if the library is missing or a tensor is
+not on a GPU.
+
+Function names mirror the C entry points (``fmmhp_plan_create``, ``fmmhp_eval``,
+...); ``HalfPlaneFMM`` wraps a plan for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmmhp.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "fmmhp.h")
+
+STATUS = {0: "FMMHP_OK", 1: "FMMHP_EINVAL", 2: "FMMHP_EDOMAIN", 3: "FMMHP_ENOMEM",
+          4: "FMMHP_EHIP", 5: "FMMHP_ESTATE", 6: "FMMHP_EUNSUPPORTED"}
+MAX_P = 40
+
+
+class FMMHPError(RuntimeError):
+    def __init__(self, func: str, status: int, message: str):
+        super().__init__(f"{func}: {STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.func = func
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("leaf_size", ctypes.c_int),
+                ("max_level", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int), ("leaf_size", ctypes.c_int),
+                ("max_level", ctypes.c_int), ("depth", ctypes.c_int),
+                ("nbox", ctypes.c_int64), ("nleaf", ctypes.c_int64),
+                ("list_len", ctypes.c_int64 * 4), ("x_lo", ctypes.c_double),
+                ("S", ctypes.c_double), ("scale", ctypes.c_double),
+                ("lambda_re", ctypes.c_double), ("lambda_im", ctypes.c_double),
+                ("real_impedance", ctypes.c_int), ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_INT = ctypes.c_int
+
+_SIGNATURES = {
+    "fmmhp_plan_create": [_I64, _P, _P, _P, _P, _D, _D, ctypes.POINTER(Opts), _P,
+                          ctypes.POINTER(_P)],
+    "fmmhp_eval": [_P, _INT, _P, _P, _P],
+    "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
+    "fmmhp_plan_export_tree": [_P] + [_P] * 18,
+    "fmmhp_plan_destroy": [_P],
+    "fmmhp_direct_eval": [_I64, _P, _P, _INT, _P, _I64, _P, _P, _D, _D, _P, _P],
+    "fmmhp_reaction_integrals": [_I64, _P, _P, _INT, _D, _D, _P, _P],
+    "fmmhp_status_string": [_INT],
+    "fmmhp_last_error_message": [],
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfmmhp.so (built in-tree by ``python -m paper_2507_21913_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2507_21913_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name in ("fmmhp_status_string",
+                                                    "fmmhp_last_error_message") else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/fmmhp.h declares."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmmhp_\w+)\s*\(", txt)))
+
+
+def _check(func: str, status: int):
+    if status != 0:
+        msg = lib().fmmhp_last_error_message().decode(errors="replace")
+        raise FMMHPError(func, status, msg)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor (no CPU path exists)")
+    return t.to(torch.float64).contiguous()
+
+
+# --- C entry points, same names --------------------------------------------------------------
+
+def fmmhp_plan_create(n, x_ptr, y_ptr, img_x_ptr, img_y_ptr, lambda_re, lambda_im, opts, stream):
+    h = _P()
+    st = lib().fmmhp_plan_create(n, x_ptr, y_ptr, img_x_ptr, img_y_ptr, lambda_re, lambda_im,
+                                 ctypes.byref(opts) if opts is not None else None, stream,
+                                 ctypes.byref(h))
+    _check("fmmhp_plan_create", st)
+    return h
+
+
+def fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream):
+    _check("fmmhp_eval", lib().fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream))
+
+
+def fmmhp_plan_info(plan) -> dict:
+    s = PlanStats()
+    _check("fmmhp_plan_info", lib().fmmhp_plan_info(plan, ctypes.byref(s)))
+    d = {k: getattr(s, k) for k, _ in PlanStats._fields_}
+    d["list_len"] = list(s.list_len)
+    return d
+
+
+def fmmhp_plan_export_tree(plan) -> dict:
+    info = fmmhp_plan_info(plan)
+    nb, n = info["nbox"], info["n"]
+    out = {k: np.zeros(nb, np.int32) for k in
+           ("level", "bx", "by", "first", "count", "parent", "leaf", "child_first", "nchild")}
+    out["perm"] = np.zeros(n, np.int64)
+    args = [out[k] for k in ("level", "bx", "by", "first", "count", "parent", "leaf",
+                             "child_first", "nchild", "perm")]
+    for j, name in enumerate("UVWX"):
+        out[name + "_off"] = np.zeros(nb + 1, np.int64)
+        out[name + "_ent"] = np.zeros(max(1, info["list_len"][j]), np.int32)
+        args += [out[name + "_off"], out[name + "_ent"]]
+    _check("fmmhp_plan_export_tree",
+           lib().fmmhp_plan_export_tree(plan, *[a.ctypes.data_as(_P) for a in args]))
+    for j, name in enumerate("UVWX"):
+        out[name + "_ent"] = out[name + "_ent"][: info["list_len"][j]]
+    out["nbox"] = nb
+    out["x_lo"], out["S"], out["scale"] = info["x_lo"], info["S"], info["scale"]
+    return out
+
+
+def fmmhp_plan_destroy(plan):
+    _check("fmmhp_plan_destroy", lib().fmmhp_plan_destroy(plan))
+
+
+def fmmhp_direct_eval(n_src, sx, sy, n_vec, q, n_tgt, tx, ty, lambda_re, lambda_im, phi, stream):
+    _check("fmmhp_direct_eval", lib().fmmhp_direct_eval(n_src, sx, sy, n_vec, q, n_tgt, tx, ty,
+                                                        lambda_re, lambda_im, phi, stream))
+
+
+def fmmhp_reaction_integrals(m, x, y, nmax, lambda_re, lambda_im, out, stream):
+    _check("fmmhp_reaction_integrals",
+           lib().fmmhp_reaction_integrals(m, x, y, nmax, lambda_re, lambda_im, out, stream))
+
+
+# --- tensor-level helpers --------------------------------------------------------------------
+
+def _split_impedance(lam):
+    lam = complex(lam)
+    return lam.real, lam.imag
+
+
+class HalfPlaneFMM:
+    """A plan over fixed points; call it with charges to get the complex potential.
+
+    x, y        GPU tensors [N] (float64), y > 0
+    impedance   Z_eps (complex or real), Re > 0, Im >= 0
+    p, leaf_size, max_level   see fmmhp_opts in include/fmmhp.h
+    pass_images pass the image arrays (x, -y) explicitly to the library
+    """
+
+    def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False):
+        x = _dev_f64(x, "x")
+        y = _dev_f64(y, "y")
+        self.n = int(x.shape[0])
+        self.device = x.device
+        self._x, self._y = x, y
+        lr, li = _split_impedance(impedance)
+        opts = Opts(int(p), int(leaf_size), int(max_level), 0)
+        with torch.cuda.device(self.device):
+            if pass_images:
+                ix, iy = x.clone(), -y
+                self._plan = fmmhp_plan_create(self.n, x.data_ptr(), y.data_ptr(), ix.data_ptr(),
+                                               iy.data_ptr(), lr, li, opts, _stream())
+            else:
+                self._plan = fmmhp_plan_create(self.n, x.data_ptr(), y.data_ptr(), None, None,
+                                               lr, li, opts, _stream())
+        self.impedance = complex(lr, li)
+
+    def info(self) -> dict:
+        return fmmhp_plan_info(self._plan)
+
+    def export_tree(self) -> dict:
+        return fmmhp_plan_export_tree(self._plan)
+
+    def __call__(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """phi = A q.  q: [N] or [n_vec, N], real or complex.  Returns complex128 of q's shape."""
+        if not isinstance(q, torch.Tensor) or not q.is_cuda:
+            raise TypeError("q must be a GPU tensor (no CPU path exists)")
+        squeeze = q.dim() == 1
+        q2 = q.reshape(1, -1) if squeeze else q
+        if q2.shape[-1] != self.n:
+            raise ValueError(f"q has {q2.shape[-1]} points, plan has {self.n}")
+        if q2.is_complex():
+            parts = torch.cat([q2.real, q2.imag], 0).to(torch.float64).contiguous()
+        else:
+            parts = q2.to(torch.float64).contiguous()
+        nv = parts.shape[0]
+        raw = torch.empty((nv, self.n, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            fmmhp_eval(self._plan, nv, parts.data_ptr(), raw.data_ptr(), _stream())
+        phi = torch.view_as_complex(raw)
+        if q2.is_complex():
+            k = q2.shape[0]
+            phi = phi[:k] + 1j * phi[k:]
+        if out is not None:
+            out.copy_(phi.reshape(out.shape))
+            return out
+        return phi[0] if squeeze else phi
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            fmmhp_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def direct(xs, ys, q, impedance, xt=None, yt=None) -> torch.Tensor:
+    """GPU direct sum phi_i = sum_j q_j G(r_i, r_j) (all pairs)."""
+    xs = _dev_f64(xs, "xs")
+    ys = _dev_f64(ys, "ys")
+    if xt is None:
+        xt, yt = xs, ys
+    xt = _dev_f64(xt, "xt")
+    yt = _dev_f64(yt, "yt")
+    squeeze = q.dim() == 1
+    q2 = _dev_f64(q.reshape(1, -1) if squeeze else q, "q")
+    nv = q2.shape[0]
+    raw = torch.empty((nv, xt.shape[0], 2), dtype=torch.float64, device=xs.device)
+    lr, li = _split_impedance(impedance)
+    with torch.cuda.device(xs.device):
+        fmmhp_direct_eval(xs.shape[0], xs.data_ptr(), ys.data_ptr(), nv, q2.data_ptr(),
+                          xt.shape[0], xt.data_ptr(), yt.data_ptr(), lr, li, raw.data_ptr(),
+                          _stream())
+    phi = torch.view_as_complex(raw)
+    return phi[0] if squeeze else phi
+
+
+def reaction_integrals(x, y, nmax: int, impedance) -> torch.Tensor:
+    """I_0..I_nmax at points (x, y) on the GPU: complex128 [m, nmax + 1]."""
+    x = _dev_f64(x, "x")
+    y = _dev_f64(y, "y")
+    m = x.shape[0]
+    raw = torch.empty((m, nmax + 1, 2), dtype=torch.float64, device=x.device)
+    lr, li = _split_impedance(impedance)
+    with torch.cuda.device(x.device):
+        fmmhp_reaction_integrals(m, x.data_ptr(), y.data_ptr(), nmax, lr, li, raw.data_ptr(),
+                                 _stream())
+    return torch.view_as_complex(raw)
+
+
+__all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functions",
+           "FMMHPError", "Opts", "PlanStats", "fmmhp_plan_create", "fmmhp_eval",
+           "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
+           "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P"]

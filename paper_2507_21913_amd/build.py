@@ -1,0 +1,63 @@
+"""Build libfmmhp.so (HIP, gfx950) in-tree with hipcc.
+
+Usage:  python -m paper_2507_21913_amd.build   (or call build_library()).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libfmmhp.so")
+SOURCES = ["api.hip", "tree.hip", "fmm.hip"]
+HEADERS = ["cplx.hpp", "special.hpp", "internal.hpp"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = os.environ.get("FMMHP_ARCH", "gfx950")
+
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}",
+    # packed fp32 arithmetic stays off in every kernel of this library
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=fast",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+
+
+def build_library(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every source of the library; always recompiles."""
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = LIB + ".tmp"
+    objs = []
+    procs = []
+    for s in srcs:
+        obj = os.path.join(CSRC, os.path.basename(s) + ".o")
+        objs.append(obj)
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", s, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"hipcc failed ({' '.join(cmd)}):\n{out.decode(errors='replace')}")
+        if verbose and out:
+            print(out.decode(errors="replace"), file=sys.stderr)
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed ({' '.join(cmd)}):\n{r.stdout}{r.stderr}")
+    for o in objs:
+        try:
+            os.remove(o)
+        except OSError:
+            pass
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build_library(verbose="-v" in sys.argv))

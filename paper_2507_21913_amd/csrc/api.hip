@@ -1,0 +1,252 @@
+// C-ABI entry points of libfmmhp (declared in include/fmmhp.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "internal.hpp"
+
+namespace fmmhp {
+
+static thread_local char g_msg[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+}
+
+constexpr uint64_t kMagic = 0x66'6d'6d'68'70'6c'61'6eull;  // "fmmhplan"
+constexpr uint64_t kDead = 0xdeadull;
+
+static fmmhp_status check_plan(fmmhp_plan_t p) {
+    if (!p) {
+        set_error("plan is NULL");
+        return FMMHP_ESTATE;
+    }
+    if (p->magic != kMagic) {
+        set_error("plan handle is not a live plan (destroyed or corrupted)");
+        return FMMHP_ESTATE;
+    }
+    int dev = -1;
+    FMMHP_HIP(hipGetDevice(&dev));
+    if (dev != p->device) {
+        set_error("plan was created on device %d but device %d is current", p->device, dev);
+        return FMMHP_EINVAL;
+    }
+    return FMMHP_OK;
+}
+
+static fmmhp_status check_impedance(double re, double im) {
+    if (!isfinite(re) || !isfinite(im)) {
+        set_error("impedance is not finite");
+        return FMMHP_EINVAL;
+    }
+    if (!(re > 0.0) || im < 0.0) {
+        set_error("impedance %g%+gi is outside Re > 0, Im >= 0", re, im);
+        return FMMHP_EDOMAIN;
+    }
+    return FMMHP_OK;
+}
+
+}  // namespace fmmhp
+
+using namespace fmmhp;
+
+extern "C" {
+
+const char *fmmhp_status_string(fmmhp_status s) {
+    switch (s) {
+        case FMMHP_OK: return "FMMHP_OK";
+        case FMMHP_EINVAL: return "FMMHP_EINVAL";
+        case FMMHP_EDOMAIN: return "FMMHP_EDOMAIN";
+        case FMMHP_ENOMEM: return "FMMHP_ENOMEM";
+        case FMMHP_EHIP: return "FMMHP_EHIP";
+        case FMMHP_ESTATE: return "FMMHP_ESTATE";
+        case FMMHP_EUNSUPPORTED: return "FMMHP_EUNSUPPORTED";
+        default: return "unknown status";
+    }
+}
+
+const char *fmmhp_last_error_message(void) { return g_msg; }
+
+fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, const double *img_x,
+                               const double *img_y, double lambda_re, double lambda_im, const fmmhp_opts *opts,
+                               hipStream_t stream, fmmhp_plan_t *plan_out) {
+    g_msg[0] = 0;
+    if (!plan_out) {
+        set_error("plan_out is NULL");
+        return FMMHP_EINVAL;
+    }
+    *plan_out = nullptr;
+    if (n < 1 || n >= ((int64_t)1 << 31)) {
+        set_error("n = %lld outside [1, 2^31)", (long long)n);
+        return FMMHP_EINVAL;
+    }
+    if (!x || !y) {
+        set_error("x or y is NULL");
+        return FMMHP_EINVAL;
+    }
+    if ((img_x == nullptr) != (img_y == nullptr)) {
+        set_error("img_x and img_y must both be NULL or both be given");
+        return FMMHP_EINVAL;
+    }
+    FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
+    fmmhp_opts o{20, 40, 30, 0};
+    if (opts) o = *opts;
+    if (o.max_level == 0) o.max_level = 30;
+    if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > 30 || o.flags != 0) {
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..30), flags=%u (0)",
+                  o.p, FMMHP_MAX_P, o.leaf_size, o.max_level, o.flags);
+        return FMMHP_EINVAL;
+    }
+    fmmhp_plan_s *p = new (std::nothrow) fmmhp_plan_s();
+    if (!p) {
+        set_error("host allocation of the plan failed");
+        return FMMHP_ENOMEM;
+    }
+    p->magic = kMagic;
+    p->p_req = o.p;
+    p->leaf_size = o.leaf_size;
+    p->max_level = o.max_level;
+    p->lambda_re = lambda_re;
+    p->lambda_im = lambda_im;
+    fmmhp_status st = FMMHP_OK;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        st = FMMHP_EHIP;
+    }
+    if (st == FMMHP_OK)
+        st = build_tree(p->arena, p->tree, n, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
+    if (st == FMMHP_OK)
+        st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), mk(lambda_re, lambda_im), stream);
+    if (st == FMMHP_OK) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            set_error("plan build failed on the device: %s", hipGetErrorString(e));
+            st = FMMHP_EHIP;
+        }
+    }
+    if (st != FMMHP_OK) {
+        (void)hipStreamSynchronize(stream);
+        p->arena.release();
+        p->magic = kDead;
+        delete p;
+        return st;
+    }
+    *plan_out = p;
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (n_vec < 1 || !q || !phi) {
+        set_error("n_vec must be >= 1 and q, phi non-NULL");
+        return FMMHP_EINVAL;
+    }
+    return run_eval(plan->tree, plan->sched, n_vec, q, phi, stream);
+}
+
+fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!st) {
+        set_error("stats is NULL");
+        return FMMHP_EINVAL;
+    }
+    const Tree &T = plan->tree;
+    memset(st, 0, sizeof(*st));
+    st->n = T.n;
+    st->p = plan->sched.PB;
+    st->leaf_size = plan->leaf_size;
+    st->max_level = plan->max_level;
+    st->depth = T.depth;
+    st->nbox = T.nbox;
+    st->nleaf = T.nleaf;
+    for (int k = 0; k < 4; ++k) st->list_len[k] = T.len[k];
+    st->x_lo = T.x_lo;
+    st->S = T.S;
+    st->scale = T.scale;
+    st->lambda_re = plan->lambda_re;
+    st->lambda_im = plan->lambda_im;
+    st->real_impedance = plan->sched.real_Z ? 1 : 0;
+    st->device_bytes = plan->arena.bytes;
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_plan_export_tree(fmmhp_plan_t plan, int32_t *level, int32_t *bx, int32_t *by, int32_t *first,
+                                    int32_t *count, int32_t *parent, int32_t *leaf, int32_t *child_first,
+                                    int32_t *nchild, int64_t *perm, int64_t *u_off, int32_t *u_ent, int64_t *v_off,
+                                    int32_t *v_ent, int64_t *w_off, int32_t *w_ent, int64_t *x_off,
+                                    int32_t *x_ent) {
+    FMMHP_CHECK(check_plan(plan));
+    const Tree &T = plan->tree;
+    const size_t nb = (size_t)T.nbox;
+    struct Item {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } items[] = {
+        {level, T.level, nb * 4}, {bx, T.bx, nb * 4},         {by, T.by, nb * 4},
+        {first, T.first, nb * 4}, {count, T.count, nb * 4},   {parent, T.parent, nb * 4},
+        {leaf, T.leaf, nb * 4},   {child_first, T.child_first, nb * 4}, {nchild, T.nchild, nb * 4},
+        {u_ent, T.ent[0], (size_t)T.len[0] * 4}, {v_ent, T.ent[1], (size_t)T.len[1] * 4},
+        {w_ent, T.ent[2], (size_t)T.len[2] * 4}, {x_ent, T.ent[3], (size_t)T.len[3] * 4},
+    };
+    for (auto &it : items)
+        if (it.dst && it.bytes) FMMHP_HIP(hipMemcpy(it.dst, it.src, it.bytes, hipMemcpyDeviceToHost));
+    int64_t *offs[4] = {u_off, v_off, w_off, x_off};
+    std::vector<int32_t> tmp(nb + 1);
+    for (int k = 0; k < 4; ++k) {
+        if (!offs[k]) continue;
+        FMMHP_HIP(hipMemcpy(tmp.data(), T.off[k], (nb + 1) * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i <= nb; ++i) offs[k][i] = tmp[i];
+    }
+    if (perm) {
+        std::vector<int32_t> pp((size_t)T.n);
+        FMMHP_HIP(hipMemcpy(pp.data(), T.perm, (size_t)T.n * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < T.n; ++i) perm[i] = pp[i];
+    }
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
+    if (!plan) return FMMHP_OK;
+    if (plan->magic != kMagic) {
+        set_error("plan handle is not a live plan (destroyed or corrupted)");
+        return FMMHP_ESTATE;
+    }
+    (void)hipDeviceSynchronize();
+    plan->arena.release();
+    plan->magic = kDead;
+    delete plan;
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_direct_eval(int64_t n_src, const double *src_x, const double *src_y, int n_vec, const double *q,
+                               int64_t n_tgt, const double *tgt_x, const double *tgt_y, double lambda_re,
+                               double lambda_im, double *phi, hipStream_t stream) {
+    g_msg[0] = 0;
+    if (n_src < 1 || n_tgt < 1 || n_vec < 1 || !src_x || !src_y || !q || !tgt_x || !tgt_y || !phi) {
+        set_error("sizes must be >= 1 and pointers non-NULL");
+        return FMMHP_EINVAL;
+    }
+    FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
+    return run_direct(n_src, src_x, src_y, n_vec, q, n_tgt, tgt_x, tgt_y, mk(lambda_re, lambda_im), phi, stream);
+}
+
+fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *y, int nmax, double lambda_re,
+                                      double lambda_im, double *out, hipStream_t stream) {
+    g_msg[0] = 0;
+    if (m < 1 || !x || !y || !out || nmax < 0 || nmax > 2 * FMMHP_MAX_P) {
+        set_error("m must be >= 1, pointers non-NULL, 0 <= nmax <= %d", 2 * FMMHP_MAX_P);
+        return FMMHP_EINVAL;
+    }
+    FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
+    return run_reaction_integrals(m, x, y, nmax, mk(lambda_re, lambda_im), out, stream);
+}
+
+}  // extern "C"

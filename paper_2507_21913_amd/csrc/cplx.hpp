@@ -1,0 +1,51 @@
+// Minimal complex float64 arithmetic usable from host and device code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace fmmhp {
+
+struct cplx {
+    double re, im;
+};
+
+__host__ __device__ __forceinline__ cplx mk(double r, double i) { return cplx{r, i}; }
+__host__ __device__ __forceinline__ cplx operator+(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__host__ __device__ __forceinline__ cplx operator-(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__host__ __device__ __forceinline__ cplx operator-(cplx a) { return {-a.re, -a.im}; }
+__host__ __device__ __forceinline__ cplx operator*(cplx a, cplx b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ __forceinline__ cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
+__host__ __device__ __forceinline__ cplx operator*(cplx a, double s) { return {s * a.re, s * a.im}; }
+__host__ __device__ __forceinline__ cplx& operator+=(cplx& a, cplx b) { a.re += b.re; a.im += b.im; return a; }
+__host__ __device__ __forceinline__ cplx& operator-=(cplx& a, cplx b) { a.re -= b.re; a.im -= b.im; return a; }
+__host__ __device__ __forceinline__ cplx conj(cplx a) { return {a.re, -a.im}; }
+__host__ __device__ __forceinline__ double abs2(cplx a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ __forceinline__ double cabs(cplx a) { return hypot(a.re, a.im); }
+__host__ __device__ __forceinline__ cplx inv(cplx a) {
+    // 1/a with scaling to avoid overflow/underflow of |a|^2
+    double s = fmax(fabs(a.re), fabs(a.im));
+    double r = a.re / s, i = a.im / s;
+    double d = s * (r * r + i * i);
+    return {r / d, -i / d};
+}
+__host__ __device__ __forceinline__ cplx operator/(cplx a, cplx b) { return a * inv(b); }
+__host__ __device__ __forceinline__ cplx cexp_(cplx a) {
+    double e = exp(a.re);
+    double s, c;
+    sincos(a.im, &s, &c);
+    return {e * c, e * s};
+}
+__host__ __device__ __forceinline__ cplx clog_(cplx a) { return {log(cabs(a)), atan2(a.im, a.re)}; }
+// multiply by i^k
+__host__ __device__ __forceinline__ cplx mul_ipow(cplx a, int k) {
+    switch (k & 3) {
+        case 0: return a;
+        case 1: return {-a.im, a.re};
+        case 2: return {-a.re, -a.im};
+        default: return {a.im, -a.re};
+    }
+}
+
+}  // namespace fmmhp

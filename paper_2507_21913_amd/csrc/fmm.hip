@@ -1,0 +1,863 @@
+// Evaluation of phi = A q (Algorithm 2): upward pass, multipole-to-local translation, downward
+// pass and leaf evaluation, for the free-space, image and reaction parts of the half-plane Robin
+// Green's function.
+//
+// Representation.  For an upper box b with centre c_b and half side rho (level l, rho = S 2^-l / 2):
+//  * multipole  w_n = sum_j q_j (-(z_j - c_b) / rho)^n / n!,  n = 0..p.  It carries the moments of
+//    the box's points (mu_n = (-1)^n n! w_n); the mirror image box has moments conj(mu_n).  From it
+//    follow the log-kernel multipole (a_0 = mu_0, a_k = -rho^k mu_k / k, textbook) and the paper's
+//    reaction multipole of the image box, alpha_n = rho^n (-i)^n conj(mu_n) (eq. (MEcoefficients)).
+//  * local      lambda_n = n! rho^n h_n, where the holomorphic local field of the box is
+//    H(z) = sum_n h_n (z - c_b)^n.  With a complex impedance a second local G is kept.
+//    The far field at a target is  2 Re H(z) (+ a rank-one surface term, below) for a real
+//    impedance, and H(z) + conj(G(z)) for a complex one.
+//
+// Why H and G.  Phi_free + Phi_1 = -(1/2pi) Re u, u(z) = sum q log(z - z_j) - sum q log(z - conj z_j)
+// (eqs. (1.2), (reactioncomp1)); Phi_2^+ (eq. (reactioncomp2)) is holomorphic in the target z, and
+// Phi_2^-, the same algorithm on x-mirrored coordinates (Algorithm 2), is anti-holomorphic.  So
+// phi = [ -u/(4pi) + Phi_2^+ ](z) + conj[ -u/(4pi) + conj(Phi_2^-) ](z) = H + conj(G).  For a real
+// impedance and real charges I_0(-X, Y) = conj(I_0(X, Y)) + i exp(-Z (Y + iX)) (the residue the
+// lossless contour picks up, eq. (aaa1.5)), hence Phi_2^- = conj(Phi_2^+) + i e^{-Z(y_i + i x_i)} s with
+// s = sum_j q_j e^{-Z(y_j - i x_j)}: G = conj-mirror of H, and phi = 2 Re H + i e^{-Z(y_i+ix_i)} s.
+//
+// Multipole-to-local.  Every translation of this method is a Hankel contraction in these variables:
+//   lambda_n += - sum_m T_{n+m} w_m  (+ L w_0 for n = 0),
+// with, for an upper source at same-level offset Delta (t = 1 / (2 Delta)),
+//   T_j = -(1/4pi) (j-1)! t^j (j >= 1), T_0 = 0,   L = -(1/4pi) log(-2 rho Delta)     (classic M2L)
+// and for an image source (applied to conj(w)),
+//   T_j = (1/4pi) (j-1)! t^j - j! i^j K_j,  K_j = rho^j I_j(X, Y),  L = (1/4pi) log(-2 rho Delta)
+// which is the log M2L of the image box plus the paper's reaction M2L (eq. (truncatedM2Lcoef)):
+//   beta_n = sum_m i^-n (n+m)!/(n! m!) I_{n+m}(x_c - x'_c, y_c - y'_c) alpha_m, re-expanded in
+//   powers of (z - c_b) (the paper's local uses powers of (c_b - z), eq. (LEformula)).
+// G uses conj(rho^j I_j(-X, Y)) in place of K_j.
+//
+// M2M and L2L (eqs. (metome), (truncatedL2L) and their log-kernel twins) are Toeplitz in these
+// variables:  w^P_n = sum_{m<=n} (-eps)^{n-m}/(n-m)! 2^-m w^c_m,
+//             lambda^c_m += 2^-m sum_{n>=m} eps^{n-m}/(n-m)! lambda^P_n,  eps = (c_child - c_parent)/rho_parent.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+
+#include "internal.hpp"
+#include "special.hpp"
+
+namespace fmmhp {
+
+static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+struct Geo {
+    double x_lo, S;
+};
+
+__device__ __forceinline__ double side_of(const Geo &g, int l) { return ldexp(g.S, -l); }
+__device__ __forceinline__ cplx centre_of(const Geo &g, int l, int bx, int by) {
+    const double s = side_of(g, l);
+    return mk(g.x_lo + (bx + 0.5) * s, -0.5 * g.S + (by + 0.5) * s);
+}
+
+// I_0 with a short series when |P| <= 2 (the near field); the general routine otherwise.
+__device__ __noinline__ cplx reaction_I0_general(double x, double y, cplx Z) { return reaction_I0(x, y, Z); }
+
+__device__ __forceinline__ cplx reaction_I0_near(double x, double y, cplx Z) {
+    const cplx P = Z * mk(y, -x);
+    if (abs2(P) > 4.0) return reaction_I0_general(x, y, Z);
+    // Ei(P) = gamma + log P + sum_{k>=1} P^k / (k k!), |P| <= 2: 30 terms reach 1e-17
+    cplx t = P, sum = P;
+#pragma unroll 4
+    for (int k = 2; k <= 32; ++k) {
+        t = t * P * (1.0 / k);
+        sum += t * (1.0 / k);
+    }
+    const cplx ei = mk(kEulerGamma, 0.0) + clog_(P) + sum;
+    const cplx e = cexp_(-P);
+    return kInv2Pi * (e * mk(-ei.re, kPi - ei.im));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Charges into sorted order
+// ---------------------------------------------------------------------------------------------
+__global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n,
+                           double *__restrict__ qs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) qs[i] = q[perm[i]];
+}
+
+// ---------------------------------------------------------------------------------------------
+// P2M: leaves
+// ---------------------------------------------------------------------------------------------
+template <int PB>
+__global__ __launch_bounds__(64) void k_p2m(Geo g, const int32_t *__restrict__ leaves, int nleaf, int nbox,
+                                            const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
+                                            const int32_t *__restrict__ by, const int32_t *__restrict__ first,
+                                            const int32_t *__restrict__ count, const double *__restrict__ xs,
+                                            const double *__restrict__ ys, const double *__restrict__ qs,
+                                            cplx *__restrict__ W) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaf) return;
+    const int b = leaves[t];
+    const int l = level[b];
+    const cplx c = centre_of(g, l, bx[b], by[b]);
+    const double irho = 2.0 / side_of(g, l);
+    cplx w[PB + 1];
+#pragma unroll
+    for (int n = 0; n <= PB; ++n) w[n] = mk(0.0, 0.0);
+    const int f = first[b], e = f + count[b];
+    for (int j = f; j < e; ++j) {
+        const cplx mz = mk((c.re - xs[j]) * irho, (c.im - ys[j]) * irho);  // -(z_j - c) / rho
+        cplx term = mk(qs[j], 0.0);
+#pragma unroll
+        for (int n = 0; n <= PB; ++n) {
+            w[n] += term;
+            term = term * mz * (1.0 / (n + 1));
+        }
+    }
+#pragma unroll
+    for (int n = 0; n <= PB; ++n) W[(int64_t)n * nbox + b] = w[n];
+}
+
+// ---------------------------------------------------------------------------------------------
+// M2M: one level, parents in [lo, hi)
+// ---------------------------------------------------------------------------------------------
+template <int PB>
+__global__ __launch_bounds__(64) void k_m2m(int lo, int hi, int nbox, const int32_t *__restrict__ leaf,
+                                            const int32_t *__restrict__ child_first,
+                                            const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
+                                            const int32_t *__restrict__ by, const cplx *__restrict__ E,
+                                            cplx *__restrict__ W) {
+    const int b = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= hi || leaf[b]) return;
+    cplx out[PB + 1];
+#pragma unroll
+    for (int n = 0; n <= PB; ++n) out[n] = mk(0.0, 0.0);
+    const int c0 = child_first[b], c1 = c0 + nchild[b];
+    for (int c = c0; c < c1; ++c) {
+        const int q = (bx[c] & 1) | ((by[c] & 1) << 1);
+        const cplx *Eq = E + q * (PB + 1);
+        double sc = 1.0;
+#pragma unroll
+        for (int m = 0; m <= PB; ++m) {
+            const cplx wm = W[(int64_t)m * nbox + c] * sc;
+#pragma unroll
+            for (int n = m; n <= PB; ++n) out[n] += Eq[n - m] * wm;
+            sc *= 0.5;
+        }
+    }
+#pragma unroll
+    for (int n = 0; n <= PB; ++n) W[(int64_t)n * nbox + b] = out[n];
+}
+
+// ---------------------------------------------------------------------------------------------
+// M2L over tiles of same-level, same-class target boxes; one wave per (tile, output chunk).
+// Lanes are target boxes; the operator of an offset slot is the same for every lane, so its
+// coefficients are read with scalar loads.
+// ---------------------------------------------------------------------------------------------
+struct M2LArgs {
+    int nbox;
+    const int32_t *tiles, *tile_level, *tile_class, *class_slots;
+    const int32_t *vslot, *vimg_off, *vimg_ent;
+    const cplx *Tfree, *Lfree, *TimgH, *TimgG, *Limg;
+    const double *loglev;
+    const cplx *W;
+    cplx *Lam;     // [nloc][PB + 1][nbox]
+    int nloc;
+};
+
+template <int PB, int CH>
+__global__ __launch_bounds__(64) void k_m2l(M2LArgs a) {
+    constexpr int NT = 2 * PB + 1;
+    const int tile = blockIdx.x;
+    const int n0 = blockIdx.y * CH;
+    const int lane = threadIdx.x;
+    const int b = a.tiles[tile * kTile + lane];
+    const int l = a.tile_level[tile];
+    const int cls = a.tile_class[tile];
+    const double ll = a.loglev[l] * kInv4Pi;
+    cplx acc[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) acc[k] = mk(0.0, 0.0);
+    cplx acc0 = mk(0.0, 0.0);
+    const int nslots = a.class_slots[cls * 28];
+    for (int s = 0; s < nslots; ++s) {
+        const int o = a.class_slots[cls * 28 + 1 + s];
+        const int src = (b >= 0) ? a.vslot[(int64_t)o * a.nbox + b] : -1;
+        if (src < 0) continue;
+        const cplx *T = a.Tfree + o * NT + n0;
+#pragma unroll
+        for (int m = 0; m <= PB; ++m) {
+            const cplx wm = a.W[(int64_t)m * a.nbox + src];
+#pragma unroll
+            for (int k = 0; k < CH; ++k)
+                if (n0 + k <= PB) acc[k] += T[k + m] * wm;
+        }
+        if (n0 == 0) acc0 += (a.Lfree[o] - mk(ll, 0.0)) * a.W[src];
+    }
+    cplx accG[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) accG[k] = acc[k];
+    cplx accG0 = acc0;
+    if (b >= 0) {
+        for (int e = a.vimg_off[b]; e < a.vimg_off[b + 1]; ++e) {
+            const int code = a.vimg_ent[e];
+            const int src = code >> 5, is = code & 31;
+            const cplx *TH = a.TimgH + ((int64_t)l * kNumImgSlots + is) * NT + n0;
+            const cplx *TG = a.TimgG + ((int64_t)l * kNumImgSlots + is) * NT + n0;
+#pragma unroll
+            for (int m = 0; m <= PB; ++m) {
+                const cplx wm = conj(a.W[(int64_t)m * a.nbox + src]);
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    if (n0 + k <= PB) {
+                        acc[k] += TH[k + m] * wm;
+                        if (a.nloc == 2) accG[k] += TG[k + m] * wm;
+                    }
+                }
+            }
+            if (n0 == 0) {
+                const cplx lt = (a.Limg[is] + mk(ll, 0.0)) * conj(a.W[src]);
+                acc0 += lt;
+                accG0 += lt;
+            }
+        }
+        const int64_t stride = (int64_t)(PB + 1) * a.nbox;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int n = n0 + k;
+            if (n <= PB) {
+                cplx v = -acc[k];
+                if (n == 0) v += acc0;
+                a.Lam[(int64_t)n * a.nbox + b] = v;
+                if (a.nloc == 2) {
+                    cplx vg = -accG[k];
+                    if (n == 0) vg += accG0;
+                    a.Lam[stride + (int64_t)n * a.nbox + b] = vg;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nloc, cplx *__restrict__ Lam) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = hi - lo;
+    if (i >= nb * ncoef * nloc) return;
+    const int b = lo + i % nb;
+    const int r = i / nb;  // loc * ncoef + n
+    Lam[(int64_t)r * nbox + b] = mk(0.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// P2L (X list): sources of a coarse leaf straight into the local of a finer box.
+// ---------------------------------------------------------------------------------------------
+template <int PB>
+__global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, int nxbox, const int32_t *__restrict__ xbox,
+                                            int nbox, const int32_t *__restrict__ level,
+                                            const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
+                                            const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+                                            const int32_t *__restrict__ xoff, const int32_t *__restrict__ xent,
+                                            const double *__restrict__ xs, const double *__restrict__ ys,
+                                            const double *__restrict__ qs, const double *__restrict__ fact,
+                                            cplx *__restrict__ Lam) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nxbox) return;
+    const int b = xbox[t];
+    const int l = level[b];
+    const cplx cb = centre_of(g, l, bx[b], by[b]);
+    const double rho = 0.5 * side_of(g, l);
+    cplx acc[PB + 1];
+#pragma unroll
+    for (int n = 0; n <= PB; ++n) acc[n] = mk(0.0, 0.0);
+    for (int e = xoff[b]; e < xoff[b + 1]; ++e) {
+        const int code = xent[e];
+        const int c = code >> 1, img = code & 1;
+        for (int j = first[c]; j < first[c] + count[c]; ++j) {
+            const double q = qs[j];
+            const double yj = img ? -ys[j] : ys[j];
+            const cplx d = mk(xs[j] - cb.re, yj - cb.im);  // source - centre
+            const double sgn = img ? 1.0 : -1.0;             // -(1/4pi) upper, +(1/4pi) image
+            // log(c_b - z_j): local of log(z - z_j) about c_b
+            acc[0] += (sgn * kInv4Pi * q) * clog_(-d);
+            const cplx sig = rho * inv(d);
+            cplx pw = sig;
+#pragma unroll
+            for (int n = 1; n <= PB; ++n) {
+                // lambda_n = n! rho^n b_n with b_n = -q / (n (z_j - c)^n)  ->  -q (n-1)! sig^n
+                acc[n] += (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
+                pw = pw * sig;
+            }
+            if (img) {
+                // reaction S2L (eq. (LEcoefficients)), re-expanded in powers of (z - c_b):
+                // lambda_n += i^n n! rho^n q I_n(x_c - x_j, y_c + y_j)  (G: conj of I_n(-X, Y))
+                const double X = cb.re - xs[j], Y = cb.im + ys[j];
+                const double Xs = loc == 0 ? X : -X;
+                const cplx wv = mk(Y, -Xs);
+                const cplx sw = rho * inv(wv);
+                const cplx zr = rho * Z;
+                cplx K = reaction_I0_general(Xs, Y, Z);
+                cplx F = mk(1.0, 0.0);
+                acc[0] += q * (loc == 0 ? K : conj(K));
+#pragma unroll
+                for (int n = 1; n <= PB; ++n) {
+                    F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
+                    K = F * kInv2Pi + zr * K;
+                    const cplx Kn = loc == 0 ? K : conj(K);
+                    acc[n] += q * mul_ipow(Kn, n);
+                }
+            }
+        }
+    }
+    const int64_t base = (int64_t)loc * (PB + 1) * nbox;
+#pragma unroll
+    for (int n = 0; n <= PB; ++n) Lam[base + (int64_t)n * nbox + b] += acc[n];
+}
+
+// ---------------------------------------------------------------------------------------------
+// L2L: one level of children [lo, hi)
+// ---------------------------------------------------------------------------------------------
+template <int PB>
+__global__ __launch_bounds__(64) void k_l2l(int lo, int hi, int nbox, int nloc, const int32_t *__restrict__ parent,
+                                            const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
+                                            const cplx *__restrict__ E, cplx *__restrict__ Lam) {
+    const int b = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= hi) return;
+    const int P = parent[b];
+    const int q = (bx[b] & 1) | ((by[b] & 1) << 1);
+    const cplx *Eq = E + q * (PB + 1);
+    for (int loc = 0; loc < nloc; ++loc) {
+        cplx *L = Lam + (int64_t)loc * (PB + 1) * nbox;
+        cplx lp[PB + 1];
+#pragma unroll
+        for (int n = 0; n <= PB; ++n) lp[n] = L[(int64_t)n * nbox + P];
+        double sc = 1.0;
+#pragma unroll
+        for (int m = 0; m <= PB; ++m) {
+            cplx s = mk(0.0, 0.0);
+#pragma unroll
+            for (int n = m; n <= PB; ++n) s += Eq[n - m] * lp[n];
+            L[(int64_t)m * nbox + b] += s * sc;
+            sc *= 0.5;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Surface term for a real impedance: s = sum_j q_j exp(-Z (y_j - i x_j))
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict__ xs, const double *__restrict__ ys,
+                                                       const double *__restrict__ qs, int64_t n, double Z,
+                                                       cplx *__restrict__ part) {
+    __shared__ double sr[256], si[256];
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double e = qs[i] * exp(-Z * ys[i]);
+        double s, c;
+        sincos(Z * xs[i], &s, &c);
+        ar += e * c;
+        ai += e * s;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sr[threadIdx.x] += sr[threadIdx.x + off];
+            si[threadIdx.x] += si[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = mk(sr[0], si[0]);
+}
+
+__global__ void k_rank1_final(cplx *__restrict__ part, int np) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    cplx s = mk(0.0, 0.0);
+    for (int k = 0; k < np; ++k) s += part[k];
+    part[np] = s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Leaf evaluation: L2P, W list (M2P), U list (P2P), surface term; one thread per target point.
+// ---------------------------------------------------------------------------------------------
+struct LeafArgs {
+    Geo g;
+    cplx Z;
+    int64_t n;
+    int nbox, nloc;
+    const double *xs, *ys, *qs;
+    const int32_t *perm, *leaf_of, *level, *bx, *by, *first, *count;
+    const int32_t *uoff, *uent, *woff, *went;
+    const cplx *W, *Lam;
+    const double *invfact, *fact;
+    const cplx *rank1;   // device scalar (real impedance) or null
+    double *phi;         // [n][2]
+};
+
+template <int PB>
+__global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int b = a.leaf_of[i];
+    const int l = a.level[b];
+    const double x = a.xs[i], y = a.ys[i];
+    const cplx z = mk(x, y);
+    const cplx cb = centre_of(a.g, l, a.bx[b], a.by[b]);
+    const double irho = 2.0 / side_of(a.g, l);
+    // L2P: H(z) = sum_n lambda_n / n! zeta^n
+    const cplx zeta = mk((x - cb.re) * irho, (y - cb.im) * irho);
+    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
+    {
+        const cplx *L = a.Lam;
+        for (int n = PB; n >= 0; --n) H = H * zeta + L[(int64_t)n * a.nbox + b] * a.invfact[n];
+        if (a.nloc == 2) {
+            const cplx *L2 = a.Lam + (int64_t)(PB + 1) * a.nbox;
+            for (int n = PB; n >= 0; --n) G = G * zeta + L2[(int64_t)n * a.nbox + b] * a.invfact[n];
+        }
+    }
+    // W list: multipoles of smaller non-adjacent boxes evaluated at the target
+    for (int e = a.woff[b]; e < a.woff[b + 1]; ++e) {
+        const int code = a.went[e];
+        const int d = code >> 1, img = code & 1;
+        const int ld = a.level[d];
+        const cplx cd0 = centre_of(a.g, ld, a.bx[d], a.by[d]);
+        const double rd = 0.5 * side_of(a.g, ld);
+        const cplx cd = img ? conj(cd0) : cd0;
+        const cplx dz = z - cd;
+        const cplx tau = -rd * inv(dz);
+        // u = w0 log(z - c) - sum_k (k-1)! tau^k w_k  (conjugated w for the image box)
+        cplx w0 = a.W[d];
+        if (img) w0 = conj(w0);
+        cplx u = w0 * clog_(dz);
+        cplx pw = tau;
+        for (int k = 1; k <= PB; ++k) {
+            cplx wk = a.W[(int64_t)k * a.nbox + d];
+            if (img) wk = conj(wk);
+            u -= (a.fact[k - 1] * pw) * wk;
+            pw = pw * tau;
+        }
+        const double sgn = img ? 1.0 : -1.0;
+        H += (sgn * kInv4Pi) * u;
+        G += (sgn * kInv4Pi) * u;
+        if (img) {
+            // reaction ME (eq. (truncatedME)) of the image box: sum_n alpha_n I_n(x - x'_c, y - y'_c),
+            // alpha_n = rho^n (-i)^n conj(mu_n) = i^n n! rho^n conj(w_n)
+            const double X = x - cd0.re, Y = y + cd0.im;
+            for (int pass = 0; pass < a.nloc; ++pass) {
+                const double Xs = pass == 0 ? X : -X;
+                const cplx sw = rd * inv(mk(Y, -Xs));
+                const cplx zr = rd * a.Z;
+                cplx K = reaction_I0_general(Xs, Y, a.Z);
+                cplx F = mk(1.0, 0.0);
+                cplx acc = (pass == 0 ? K : conj(K)) * conj(a.W[d]);
+                for (int n = 1; n <= PB; ++n) {
+                    F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
+                    K = F * kInv2Pi + zr * K;
+                    const cplx Kn = pass == 0 ? K : conj(K);
+                    acc += mul_ipow(Kn, n) * conj(a.W[(int64_t)n * a.nbox + d]);
+                }
+                if (pass == 0) H += acc;
+                else G += acc;
+            }
+        }
+    }
+    // U list: direct interactions
+    double lfree = 0.0, limg = 0.0, rre = 0.0;
+    cplx rc = mk(0.0, 0.0);
+    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+        const int code = a.uent[e];
+        const int c = code >> 1;
+        const int j0 = a.first[c], j1 = j0 + a.count[c];
+        if (!(code & 1)) {
+            for (int j = j0; j < j1; ++j) {
+                const double dx = x - a.xs[j], dy = y - a.ys[j];
+                const double r2 = dx * dx + dy * dy;
+                if (r2 > 0.0) lfree += a.qs[j] * log(r2);
+            }
+        } else {
+            for (int j = j0; j < j1; ++j) {
+                const double dx = x - a.xs[j], dy = y + a.ys[j];
+                const double qj = a.qs[j];
+                limg += qj * log(dx * dx + dy * dy);
+                const cplx I = reaction_I0_near(dx, dy, a.Z);
+                if (a.nloc == 1) {
+                    rre += qj * I.re;
+                } else {
+                    rc += qj * (I + reaction_I0_near(-dx, dy, a.Z));
+                }
+            }
+        }
+    }
+    const double near = kInv4Pi * (limg - lfree);
+    cplx phi;
+    if (a.nloc == 1) {
+        const cplx s = *a.rank1;
+        const cplx surf = mul_ipow(cexp_(-(a.Z * mk(y, x))) * s, 1);
+        phi = mk(2.0 * H.re + near + 2.0 * rre, 0.0) + surf;
+    } else {
+        phi = H + conj(G) + mk(near, 0.0) + rc;
+    }
+    const int64_t o = a.perm[i];
+    a.phi[2 * o] = phi.re;
+    a.phi[2 * o + 1] = phi.im;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Direct evaluation and reaction integrals (standalone entry points)
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_direct(int64_t ns, const double *__restrict__ sx, const double *__restrict__ sy,
+                                                const double *__restrict__ q, int64_t nt,
+                                                const double *__restrict__ tx, const double *__restrict__ ty,
+                                                cplx Z, double *__restrict__ phi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const double x = tx[i], y = ty[i];
+    double lfree = 0.0, limg = 0.0;
+    cplx rc = mk(0.0, 0.0);
+    for (int64_t j = 0; j < ns; ++j) {
+        const double dx = x - sx[j];
+        const double dy = y - sy[j], dyi = y + sy[j];
+        const double r2 = dx * dx + dy * dy;
+        const double qj = q[j];
+        if (r2 > 0.0) lfree += qj * log(r2);
+        limg += qj * log(dx * dx + dyi * dyi);
+        rc += qj * (reaction_I0_near(dx, dyi, Z) + reaction_I0_near(-dx, dyi, Z));
+    }
+    const cplx v = mk(kInv4Pi * (limg - lfree), 0.0) + rc;
+    phi[2 * i] = v.re;
+    phi[2 * i + 1] = v.im;
+}
+
+__global__ void k_reaction_integrals(int64_t m, const double *__restrict__ x, const double *__restrict__ y, int nmax,
+                                     cplx Z, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const double xx = x[k], yy = y[k];
+    const cplx w = mk(yy, -xx);
+    const cplx iw = inv(w);
+    cplx I = reaction_I0(xx, yy, Z);
+    out[2 * k * (nmax + 1)] = I.re;
+    out[2 * k * (nmax + 1) + 1] = I.im;
+    cplx pw = mk(1.0, 0.0);
+    for (int n = 1; n <= nmax; ++n) {
+        pw = pw * iw;
+        I = pw * (kInv2Pi / n) + Z * I * (1.0 / n);
+        out[2 * (k * (nmax + 1) + n)] = I.re;
+        out[2 * (k * (nmax + 1) + n) + 1] = I.im;
+    }
+}
+
+fmmhp_status run_direct(int64_t ns, const double *sx, const double *sy, int nvec, const double *q, int64_t nt,
+                        const double *tx, const double *ty, cplx Z, double *phi, hipStream_t s) {
+    for (int v = 0; v < nvec; ++v) {
+        hipLaunchKernelGGL(k_direct, dim3(nblk(nt, 256)), dim3(256), 0, s, ns, sx, sy, q + (int64_t)v * ns, nt, tx, ty,
+                           Z, phi + (int64_t)v * 2 * nt);
+        FMMHP_HIP(hipGetLastError());
+    }
+    return FMMHP_OK;
+}
+
+fmmhp_status run_reaction_integrals(int64_t m, const double *x, const double *y, int nmax, cplx Z, double *out,
+                                    hipStream_t s) {
+    hipLaunchKernelGGL(k_reaction_integrals, dim3(nblk(m, 128)), dim3(128), 0, s, m, x, y, nmax, Z, out);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Schedule and tables (host)
+// ---------------------------------------------------------------------------------------------
+static inline int slot_of(int dx, int dy) { return (dy + 3) * 7 + (dx + 3); }
+
+template <class T>
+static fmmhp_status to_dev(Arena &A, T **dst, const std::vector<T> &src, const char *what, hipStream_t s) {
+    FMMHP_CHECK(A.alloc_n(dst, src.size(), what));
+    if (!src.empty()) FMMHP_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return FMMHP_OK;
+}
+
+template <class T>
+static fmmhp_status to_host(std::vector<T> &dst, const T *src, size_t n, hipStream_t s) {
+    dst.resize(n);
+    if (n) FMMHP_HIP(hipMemcpyAsync(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    return FMMHP_OK;
+}
+
+fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, hipStream_t s) {
+    S.PB = PB;
+    S.Z = Z;
+    S.real_Z = (Z.im == 0.0);
+    S.nloc = S.real_Z ? 1 : 2;
+    const int nbox = T.nbox;
+    std::vector<int32_t> level, bx, by, leaf, voff, vent, xoff;
+    FMMHP_CHECK(to_host(level, T.level, nbox, s));
+    FMMHP_CHECK(to_host(bx, T.bx, nbox, s));
+    FMMHP_CHECK(to_host(by, T.by, nbox, s));
+    FMMHP_CHECK(to_host(leaf, T.leaf, nbox, s));
+    FMMHP_CHECK(to_host(voff, T.off[1], (size_t)nbox + 1, s));
+    FMMHP_CHECK(to_host(vent, T.ent[1], (size_t)T.len[1], s));
+    FMMHP_CHECK(to_host(xoff, T.off[3], (size_t)nbox + 1, s));
+    FMMHP_HIP(hipStreamSynchronize(s));
+
+    // M2L slots
+    std::vector<int32_t> vslot((size_t)kNumSlots * nbox, -1);
+    std::vector<int32_t> vimg_off(nbox + 1, 0), vimg_ent;
+    for (int b = 0; b < nbox; ++b) {
+        const int l = level[b];
+        for (int e = voff[b]; e < voff[b + 1]; ++e) {
+            const int c = vent[e] >> 1, img = vent[e] & 1;
+            const int dx = bx[c] - bx[b];
+            const int cy = img ? ((1 << l) - 1 - by[c]) : by[c];
+            const int dy = cy - by[b];
+            if (dx < -3 || dx > 3 || dy < -3 || dy > 3) {
+                set_error("internal: V entry outside the 7x7 offset block");
+                return FMMHP_EUNSUPPORTED;
+            }
+            if (!img) {
+                vslot[(size_t)slot_of(dx, dy) * nbox + b] = c;
+            } else {
+                if (dy > -1) {
+                    set_error("internal: image V entry above its target");
+                    return FMMHP_EUNSUPPORTED;
+                }
+                vimg_ent.push_back((c << 5) | slot_of(dx, dy));
+            }
+        }
+        vimg_off[b + 1] = (int32_t)vimg_ent.size();
+    }
+    FMMHP_CHECK(to_dev(A, &S.vslot, vslot, "vslot", s));
+    FMMHP_CHECK(to_dev(A, &S.vimg_off, vimg_off, "vimg_off", s));
+    FMMHP_CHECK(to_dev(A, &S.vimg_ent, vimg_ent, "vimg_ent", s));
+
+    // class slot lists
+    std::vector<int32_t> cs(4 * 28, 0);
+    for (int cls = 0; cls < 4; ++cls) {
+        const int px = cls & 1, py = cls >> 1;
+        int k = 0;
+        for (int dy = -2 - py; dy <= 3 - py; ++dy)
+            for (int dx = -2 - px; dx <= 3 - px; ++dx) {
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                cs[cls * 28 + 1 + k++] = slot_of(dx, dy);
+            }
+        cs[cls * 28] = k;
+    }
+    FMMHP_CHECK(to_dev(A, &S.class_slots, cs, "class slots", s));
+
+    // tiles: levels >= 2, grouped by class, box order within a class
+    std::vector<int32_t> tiles, tlev, tcls;
+    for (int l = 2; l <= T.depth; ++l) {
+        std::vector<int32_t> byc[4];
+        for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b) byc[(bx[b] & 1) | ((by[b] & 1) << 1)].push_back(b);
+        for (int cls = 0; cls < 4; ++cls) {
+            for (size_t k = 0; k < byc[cls].size(); k += kTile) {
+                for (int t = 0; t < kTile; ++t)
+                    tiles.push_back(k + t < byc[cls].size() ? byc[cls][k + t] : -1);
+                tlev.push_back(l);
+                tcls.push_back(cls);
+            }
+        }
+    }
+    S.ntiles = (int)tlev.size();
+    FMMHP_CHECK(to_dev(A, &S.tiles, tiles, "tiles", s));
+    FMMHP_CHECK(to_dev(A, &S.tile_level, tlev, "tile levels", s));
+    FMMHP_CHECK(to_dev(A, &S.tile_class, tcls, "tile classes", s));
+
+    // X-list targets, leaves
+    std::vector<int32_t> xb, lv;
+    for (int b = 0; b < nbox; ++b) {
+        if (xoff[b + 1] > xoff[b]) xb.push_back(b);
+        if (leaf[b]) lv.push_back(b);
+    }
+    S.nxbox = (int)xb.size();
+    FMMHP_CHECK(to_dev(A, &S.xbox, xb, "xbox", s));
+    FMMHP_CHECK(to_dev(A, &S.leaves, lv, "leaves", s));
+
+    // tables
+    const int NT = 2 * PB + 1;
+    std::vector<double> fact(NT + 1), ifact(NT + 1);
+    fact[0] = 1.0;
+    for (int j = 1; j <= NT; ++j) fact[j] = fact[j - 1] * j;
+    for (int j = 0; j <= NT; ++j) ifact[j] = 1.0 / fact[j];
+    FMMHP_CHECK(to_dev(A, &S.fact, fact, "factorials", s));
+    FMMHP_CHECK(to_dev(A, &S.invfact, ifact, "inverse factorials", s));
+
+    using C = std::complex<double>;
+    auto cx = [](C v) { return mk(v.real(), v.imag()); };
+    const double i4p = 1.0 / (4.0 * M_PI);
+    std::vector<cplx> Tfree((size_t)kNumSlots * NT, mk(0, 0)), Lfree(kNumSlots, mk(0, 0));
+    for (int dy = -3; dy <= 3; ++dy)
+        for (int dx = -3; dx <= 3; ++dx) {
+            if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+            const int o = slot_of(dx, dy);
+            const C D((double)dx, (double)dy);
+            const C t = 1.0 / (2.0 * D);
+            C tj = t;  // (j-1)! t^j
+            for (int j = 1; j < NT; ++j) {
+                Tfree[(size_t)o * NT + j] = cx(-i4p * tj);
+                tj = tj * t * (double)j;
+            }
+            Lfree[o] = cx(-i4p * std::log(-D));
+        }
+    FMMHP_CHECK(to_dev(A, &S.Tfree, Tfree, "Tfree", s));
+    FMMHP_CHECK(to_dev(A, &S.Lfree, Lfree, "Lfree", s));
+    std::vector<double> loglev(32, 0.0);
+    for (int l = 0; l < 32; ++l) loglev[l] = std::log(ldexp(T.S, -l));  // log(2 rho_l) = log(side_l)
+    FMMHP_CHECK(to_dev(A, &S.loglev, loglev, "loglev", s));
+
+    std::vector<cplx> TH((size_t)32 * kNumImgSlots * NT, mk(0, 0)), TG(TH.size(), mk(0, 0)),
+        Limg(kNumImgSlots, mk(0, 0));
+    std::vector<cplx> K(NT), Km(NT);
+    const C Zc(Z.re, Z.im);
+    double pmax = 0.0;
+    for (int dy = -3; dy <= -1; ++dy)
+        for (int dx = -3; dx <= 3; ++dx) {
+            const int is = slot_of(dx, dy);
+            const C D((double)dx, (double)dy);
+            Limg[is] = cx(i4p * std::log(-D));
+        }
+    for (int l = 2; l <= T.depth; ++l) {
+        const double sl = ldexp(T.S, -l), rho = 0.5 * sl;
+        for (int dy = -3; dy <= -1; ++dy)
+            for (int dx = -3; dx <= 3; ++dx) {
+                if (std::abs(dx) <= 1 && dy == -1) continue;  // adjacent: never in V
+                const int is = slot_of(dx, dy);
+                const C D((double)dx, (double)dy);
+                const C t = 1.0 / (2.0 * D);
+                const double X = -dx * sl, Y = -dy * sl;
+                pmax = std::max(pmax, std::abs(Zc) * std::hypot(X, Y));
+                reaction_In_scaled(X, Y, Z, rho, NT - 1, K.data());
+                reaction_In_scaled(-X, Y, Z, rho, NT - 1, Km.data());
+                C tj = t;
+                for (int j = 0; j < NT; ++j) {
+                    C fr(0.0, 0.0);
+                    if (j >= 1) {
+                        fr = i4p * tj;
+                        tj = tj * t * (double)j;
+                    }
+                    // - j! i^j K_j
+                    C ij(1.0, 0.0);
+                    for (int r = 0; r < (j & 3); ++r) ij *= C(0.0, 1.0);
+                    const C kp(K[j].re, K[j].im), km(Km[j].re, -Km[j].im);
+                    const size_t idx = ((size_t)l * kNumImgSlots + is) * NT + j;
+                    TH[idx] = cx(fr - fact[j] * ij * kp);
+                    TG[idx] = cx(fr - fact[j] * ij * km);
+                }
+            }
+    }
+    if (pmax > 12.0) {
+        set_error("impedance times box separation reaches %.3g at the coarsest level; the upward "
+                  "I_n recursion is only used up to 12 in this build",
+                  pmax);
+        return FMMHP_EUNSUPPORTED;
+    }
+    FMMHP_CHECK(to_dev(A, &S.TimgH, TH, "TimgH", s));
+    FMMHP_CHECK(to_dev(A, &S.TimgG, TG, "TimgG", s));
+    FMMHP_CHECK(to_dev(A, &S.Limg, Limg, "Limg", s));
+
+    std::vector<cplx> Em((size_t)4 * (PB + 1)), El((size_t)4 * (PB + 1));
+    for (int q = 0; q < 4; ++q) {
+        const C eps(((q & 1) ? 0.5 : -0.5), ((q & 2) ? 0.5 : -0.5));
+        C pm(1.0, 0.0), pl(1.0, 0.0);
+        for (int j = 0; j <= PB; ++j) {
+            Em[(size_t)q * (PB + 1) + j] = cx(pm * ifact[j]);
+            El[(size_t)q * (PB + 1) + j] = cx(pl * ifact[j]);
+            pm *= -eps;
+            pl *= eps;
+        }
+    }
+    FMMHP_CHECK(to_dev(A, &S.E_m2m, Em, "E_m2m", s));
+    FMMHP_CHECK(to_dev(A, &S.E_l2l, El, "E_l2l", s));
+
+    // workspace
+    FMMHP_CHECK(A.alloc_n(&S.W, (size_t)(PB + 1) * nbox, "multipoles"));
+    FMMHP_CHECK(A.alloc_n(&S.Lam, (size_t)S.nloc * (PB + 1) * nbox, "locals"));
+    FMMHP_CHECK(A.alloc_n(&S.qs, (size_t)T.n, "sorted charges"));
+    FMMHP_CHECK(A.alloc_n(&S.red, 1025, "reduction"));
+    FMMHP_HIP(hipStreamSynchronize(s));
+    return FMMHP_OK;
+}
+
+template <int PB>
+static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leaves, const double *q, double *phi,
+                             hipStream_t s) {
+    const Geo g{T.x_lo, T.S};
+    const int nbox = T.nbox;
+    hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, S.qs);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk(T.nleaf, 64)), dim3(64), 0, s, g, leaves, T.nleaf, nbox,
+                       T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
+    FMMHP_HIP(hipGetLastError());
+    for (int l = T.depth - 1; l >= 1; --l) {
+        const int lo = T.lev_start[l], hi = T.lev_start[l + 1];
+        if (hi > lo)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(hi - lo, 64)), dim3(64), 0, s, lo, hi, nbox,
+                               T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+    }
+    FMMHP_HIP(hipGetLastError());
+    {
+        const int lo = T.lev_start[1], hi = T.lev_start[2];
+        const int tot = (hi - lo) * (PB + 1) * S.nloc;
+        if (tot > 0)
+            hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc,
+                               S.Lam);
+    }
+    if (S.ntiles > 0) {
+        constexpr int CH = 8;
+        M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_class, S.class_slots, S.vslot, S.vimg_off, S.vimg_ent,
+                   S.Tfree, S.Lfree, S.TimgH,      S.TimgG,      S.Limg,        S.loglev, S.W,      S.Lam,
+                   S.nloc};
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles, (PB + 1 + CH - 1) / CH), dim3(64), 0, s,
+                           ma);
+        FMMHP_HIP(hipGetLastError());
+    }
+    if (S.nxbox > 0) {
+        for (int loc = 0; loc < S.nloc; ++loc)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(nblk(S.nxbox, 64)), dim3(64), 0, s, g, S.Z, loc,
+                               S.nxbox, S.xbox, nbox, T.level, T.bx, T.by, T.first, T.count, T.off[3], T.ent[3],
+                               T.xs, T.ys, S.qs, S.fact, S.Lam);
+        FMMHP_HIP(hipGetLastError());
+    }
+    for (int l = 3; l <= T.depth; ++l) {
+        const int lo = T.lev_start[l], hi = T.lev_start[l + 1];
+        if (hi > lo)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(hi - lo, 64)), dim3(64), 0, s, lo, hi, nbox,
+                               S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+    }
+    FMMHP_HIP(hipGetLastError());
+    const cplx *r1 = nullptr;
+    if (S.nloc == 1) {
+        const int np = (int)std::min<int64_t>(1024, nblk(T.n, 256));
+        hipLaunchKernelGGL(k_rank1_partial, dim3(np), dim3(256), 0, s, T.xs, T.ys, S.qs, T.n, S.Z.re, S.red);
+        hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(64), 0, s, S.red, np);
+        FMMHP_HIP(hipGetLastError());
+        r1 = S.red + np;
+    }
+    LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   T.perm,
+                T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
+                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       phi};
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
+}
+
+static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q, double *phi, hipStream_t s) {
+    switch (S.PB) {
+        case 5: return eval_vec<5>(T, S, S.leaves, q, phi, s);
+        case 10: return eval_vec<10>(T, S, S.leaves, q, phi, s);
+        case 15: return eval_vec<15>(T, S, S.leaves, q, phi, s);
+        case 20: return eval_vec<20>(T, S, S.leaves, q, phi, s);
+        case 25: return eval_vec<25>(T, S, S.leaves, q, phi, s);
+        case 30: return eval_vec<30>(T, S, S.leaves, q, phi, s);
+        case 35: return eval_vec<35>(T, S, S.leaves, q, phi, s);
+        case 40: return eval_vec<40>(T, S, S.leaves, q, phi, s);
+        default:
+            set_error("internal: no kernels compiled for p = %d", S.PB);
+            return FMMHP_EUNSUPPORTED;
+    }
+}
+
+fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
+    for (int v = 0; v < nvec; ++v)
+        FMMHP_CHECK(run_eval_vec(T, S, q + (int64_t)v * T.n, phi + (int64_t)v * 2 * T.n, s));
+    return FMMHP_OK;
+}
+
+}  // namespace fmmhp

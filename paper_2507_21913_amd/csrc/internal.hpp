@@ -1,0 +1,135 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fmmhp.h"
+#include "cplx.hpp"
+
+namespace fmmhp {
+
+constexpr int kLBits = 30;        // integer cell bits per axis of the root square
+constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
+constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
+constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
+
+void set_error(const char *fmt, ...);
+
+#define FMMHP_HIP(expr)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ::fmmhp::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                               __FILE__, __LINE__);                                 \
+            return FMMHP_EHIP;                                                       \
+        }                                                                            \
+    } while (0)
+
+#define FMMHP_CHECK(expr)                    \
+    do {                                     \
+        fmmhp_status s_ = (expr);            \
+        if (s_ != FMMHP_OK) return s_;       \
+    } while (0)
+
+// Device allocations owned by one plan.
+struct Arena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    fmmhp_status alloc(void **p, size_t nbytes, const char *what);
+    template <class T>
+    fmmhp_status alloc_n(T **p, size_t n, const char *what) {
+        return alloc((void **)p, (n ? n : 1) * sizeof(T), what);
+    }
+    void release();
+};
+
+struct Tree {
+    int64_t n = 0;
+    int depth = 0;
+    int nbox = 0, nleaf = 0;
+    double x_lo = 0, S = 0, scale = 0;
+    std::vector<int> lev_start;   // boxes of level l: [lev_start[l], lev_start[l + 1]), l >= 1
+    // sorted points
+    double *xs = nullptr, *ys = nullptr;
+    int32_t *perm = nullptr;      // sorted position -> input index
+    int32_t *leaf_of = nullptr;   // sorted position -> leaf box
+    // boxes
+    int32_t *level = nullptr, *bx = nullptr, *by = nullptr, *first = nullptr, *count = nullptr;
+    int32_t *parent = nullptr, *leaf = nullptr, *child_first = nullptr, *nchild = nullptr;
+    uint64_t *prefix = nullptr;   // Morton prefix at the box's level (sorted within a level)
+    // lists (0 U, 1 V, 2 W, 3 X), CSR with int32 offsets
+    int32_t *off[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t *ent[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t len[4] = {0, 0, 0, 0};
+};
+
+fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const double *y,
+                        const double *img_x, const double *img_y, int leaf_size, int max_level,
+                        hipStream_t stream);
+
+// Evaluation schedule and tables derived from the tree.
+struct Sched {
+    int PB = 0;                     // compiled truncation order
+    bool real_Z = true;
+    cplx Z{0, 0};
+    int nloc = 1;                   // 1: H only (real impedance); 2: H and G
+    // M2L
+    int32_t *vslot = nullptr;       // [kNumSlots][nbox] upper V source per offset slot, -1 if none
+    int32_t *vimg_off = nullptr;    // [nbox + 1]  image V entries per box
+    int32_t *vimg_ent = nullptr;    // (src << 5) | img_slot
+    int ntiles = 0;
+    int32_t *tiles = nullptr;       // [ntiles][kTile] box ids (-1 padding)
+    int32_t *tile_level = nullptr;  // [ntiles]
+    int32_t *tile_class = nullptr;  // [ntiles]
+    int32_t *class_slots = nullptr; // [4][28]: count, then slot ids
+    // X list targets
+    int nxbox = 0;
+    int32_t *xbox = nullptr;
+    int32_t *leaves = nullptr;      // [nleaf]
+    // tables
+    cplx *Tfree = nullptr;          // [kNumSlots][2 PB + 1]
+    cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)
+    cplx *TimgH = nullptr;          // [31][kNumImgSlots][2 PB + 1]
+    cplx *TimgG = nullptr;          // same, G-local (complex impedance only)
+    cplx *Limg = nullptr;           // [kNumImgSlots]
+    double *loglev = nullptr;       // [31] log(2 rho_l)
+    cplx *E_m2m = nullptr;          // [4][PB + 1]  (-eps)^j / j!
+    cplx *E_l2l = nullptr;          // [4][PB + 1]  eps^j / j!
+    double *invfact = nullptr;      // [2 PB + 2]
+    double *fact = nullptr;         // [2 PB + 2]
+    // workspace
+    cplx *W = nullptr;              // [PB + 1][nbox]
+    cplx *Lam = nullptr;            // [nloc][PB + 1][nbox]
+    double *qs = nullptr;           // [n] sorted charges
+    cplx *red = nullptr;            // [1024] reduction partials + result
+};
+
+fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, hipStream_t stream);
+fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi,
+                      hipStream_t stream);
+
+fmmhp_status run_direct(int64_t ns, const double *sx, const double *sy, int nvec, const double *q,
+                        int64_t nt, const double *tx, const double *ty, cplx Z, double *phi,
+                        hipStream_t stream);
+fmmhp_status run_reaction_integrals(int64_t m, const double *x, const double *y, int nmax, cplx Z,
+                                    double *out, hipStream_t stream);
+
+inline int pick_bucket(int p) {
+    int b = ((p + 4) / 5) * 5;
+    return b < 5 ? 5 : b;
+}
+
+}  // namespace fmmhp
+
+struct fmmhp_plan_s {
+    uint64_t magic;
+    int device;
+    int p_req, leaf_size, max_level;
+    double lambda_re, lambda_im;
+    fmmhp::Arena arena;
+    fmmhp::Tree tree;
+    fmmhp::Sched sched;
+};

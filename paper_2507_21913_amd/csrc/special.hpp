@@ -1,0 +1,100 @@
+// Reaction-field special functions (Section 2.1), host and device.
+//
+// I_n(x, y) = 1/(2 pi n!) int_0^inf exp(-lam y + i lam x) lam^n / (lam - Z) dlam,  y > 0
+// (eq. (generalintegral)).  With w = y - i x and P = Z w the n = 0 integral has the closed form
+//
+//     I_0 = (1/2pi) exp(-P) (i pi - Ei(P)),                                  (*)
+//
+// Ei the principal-branch exponential integral.  The paper prints its initial value next to
+// eq. (integralrecursion) with the sign of x flipped and without the -i pi that its own lossless
+// limit (aaa1.5) carries; (*) is the form that agrees with the defining integral for eps > 0 and,
+// by limiting absorption, for eps = 0.  Higher orders follow the upward recursion of
+// eq. (integralrecursion):  I_n = 1 / (2 pi n w^n) + (Z / n) I_{n-1}.
+//
+// Ei is evaluated by one of three published methods, chosen by the position of P:
+//   - its power series gamma + ln P + sum P^k / (k k!) (Abramowitz & Stegun 5.1.10) when |P| <= 2,
+//     or |P| <= 4 with Re P >= 0, or |arg P| <= pi/8 with |P| <= 40;
+//   - the asymptotic series exp(P)/P sum k!/P^k (A&S 5.1.51) for |arg P| <= pi/8, |P| > 40;
+//   - otherwise the continued fraction for E_1(w) at w = -P (A&S 5.1.22), evaluated with the
+//     modified Lentz method, and Ei(P) = -E_1(-P) + i pi sgn(Im P).
+// The last two are combined with exp(-P) analytically, so that exp(-P) Ei(P) never overflows:
+//   I_0 = (1/2pi) [ exp(-P) E_1(-P) + i pi (1 - sgn Im P) exp(-P) ].
+#pragma once
+#include "cplx.hpp"
+
+namespace fmmhp {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr double kInv4Pi = 0.07957747154594766788;
+constexpr double kEulerGamma = 0.57721566490153286061;
+
+__host__ __device__ inline cplx reaction_I0(double x, double y, cplx Z) {
+    const cplx P = Z * mk(y, -x);
+    const double r = cabs(P);
+    const double ang = fabs(atan2(P.im, P.re));
+    const double sg = (P.im > 0.0) ? 1.0 : ((P.im < 0.0) ? -1.0 : 0.0);
+    if (r <= 2.0 || (r <= 4.0 && P.re >= 0.0) || (ang <= 0.125 * kPi && r <= 40.0)) {
+        cplx sum = mk(0.0, 0.0), t = mk(1.0, 0.0);
+        for (int k = 1; k < 400; ++k) {
+            t = t * P * (1.0 / k);
+            const cplx term = t * (1.0 / k);
+            sum += term;
+            if (abs2(term) < 1e-34 * abs2(sum)) break;
+        }
+        const cplx ei = mk(kEulerGamma, 0.0) + clog_(P) + sum;
+        const cplx e = cexp_(-P);
+        return kInv2Pi * (e * mk(-ei.re, kPi - ei.im));
+    }
+    cplx A;
+    if (ang <= 0.125 * kPi) {
+        // exp(-P) E_1(-P) = -(1/P) sum_{k>=0} k! / P^k, truncated at its smallest term
+        const cplx ip = inv(P);
+        cplx t = ip, sum = ip;
+        for (int k = 1; k < 200; ++k) {
+            const cplx tn = t * ip * (double)k;
+            if (abs2(tn) > abs2(t)) break;
+            sum += tn;
+            t = tn;
+            if (abs2(tn) < 1e-34 * abs2(sum)) break;
+        }
+        A = -sum;
+    } else {
+        // modified Lentz evaluation of exp(w) E_1(w), w = -P, |arg w| < 7 pi / 8
+        const cplx w = -P;
+        cplx b = w + mk(1.0, 0.0);
+        cplx c = mk(1e300, 0.0);
+        cplx d = inv(b);
+        cplx h = d;
+        for (int i = 1; i < 4000; ++i) {
+            const double a = -(double)i * (double)i;
+            b = b + mk(2.0, 0.0);
+            d = inv(a * d + b);
+            c = b + a * inv(c);
+            const cplx del = c * d;
+            h = h * del;
+            if (abs2(del - mk(1.0, 0.0)) < 1e-32) break;
+        }
+        A = h;
+    }
+    const cplx e = cexp_(-P);
+    return kInv2Pi * (A + mul_ipow(e, 1) * (kPi * (1.0 - sg)));
+}
+
+// K_j = rho^j I_j(x, y) for j = 0..nmax by eq. (integralrecursion):
+//   rho^n I_n = (1/(2 pi n)) (rho / w)^n + (Z rho / n) rho^{n-1} I_{n-1}.
+__host__ __device__ inline void reaction_In_scaled(double x, double y, cplx Z, double rho, int nmax,
+                                                   cplx *out) {
+    const cplx sigma = rho * inv(mk(y, -x));
+    const cplx zr = rho * Z;
+    cplx K = reaction_I0(x, y, Z);
+    out[0] = K;
+    cplx sp = mk(1.0, 0.0);
+    for (int n = 1; n <= nmax; ++n) {
+        sp = sp * sigma;
+        K = sp * (kInv2Pi / n) + zr * K * (1.0 / n);
+        out[n] = K;
+    }
+}
+
+}  // namespace fmmhp

@@ -263,3 +263,14 @@ def test_imag_part_closed_form_matches_direct():
     phi = D.potential(x, y, q, 1.5, workers=1)
     im = D.imag_part_real_impedance(x, y, q, 1.5)
     assert np.max(np.abs(phi.imag - im)) < 1e-12 * np.max(np.abs(im))
+
+
+def test_In_multiprecision_agrees_with_float64_and_quadrature():
+    # the mpmath variant follows the same definitions; at small |Z w| the float64 recursion is
+    # accurate, so the two agree, and both match quadrature of eq. (generalintegral)
+    for Z in (1.0, 1.0 + 0.5j):
+        for x, y in ((0.3, 0.4), (-0.7, 0.2)):
+            a = K.reaction_In_mp(8, x, y, Z)
+            b = K.reaction_In(8, x, y, Z)
+            assert np.max(np.abs(a - b) / np.abs(a)) < 1e-12
+            assert abs(a[3] - In_quadrature(3, x, y, Z)) < 1e-9 * abs(a[3])
