@@ -1,0 +1,166 @@
+#!/usr/bin/env python
+"""Throughput of the half-plane Robin FMM evaluation on one MI355X.
+
+One step = one fmmhp_eval (Algorithm 2: P2M, M2M, M2L, P2L, L2L, L2P + M2P + near field and
+the surface term) over the 1,048,576-point uniform workload (x ~ U[0,1], y ~ U[1e-3, 1.001],
+charges U[-1,1], impedance 1.0) with the plan (tree, lists, tables) already built and all
+inputs resident in device memory.  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--p 30] [--leaf 40]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X fp64 vector (and matrix) peak
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--p", type=int, default=30)
+    ap.add_argument("--leaf", type=int, default=40)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=128,
+                    help="targets of the oracle's direct sum timed for the CPU baseline")
+    ap.add_argument("--quiet-extra", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, k):
+    """Time the CPU oracle (plain float64 direct sum) on k sampled targets x all sources."""
+    import workloads
+    from oracle import direct as D
+    idx = workloads.sample_targets(w.n, k, seed=777)
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    D.potential(w.x, w.y, w.q[0], w.impedance, xt=w.x[idx], yt=w.y[idx], workers=workers)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt / 1e6, "unit": "Mpts/s", "cores": workers, "kind": "oracle",
+            "sample": f"{k} targets x {w.n} sources (direct sum, float64), {dt:.1f} s",
+            "extrapolated_full_s": dt * w.n / k}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported by this "
+              "build (the path has no multi-GPU code; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2507_21913_amd as F
+    import workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.uniform_1m(seed=1, n=a.n, p=a.p, leaf_size=a.leaf)
+    x = torch.as_tensor(w.x, device=dev)
+    y = torch.as_tensor(w.y, device=dev)
+    q = torch.as_tensor(w.q[0], device=dev)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = F.HalfPlaneFMM(x, y, w.impedance, p=a.p, leaf_size=a.leaf)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    out = torch.empty(w.n, dtype=torch.complex128, device=dev)
+    for _ in range(a.warmup):
+        plan(q, out=out)
+    torch.cuda.synchronize()
+
+    # timed region: K evals, phase events recorded on the eval stream
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        plan(q, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    phases, nev = plan.phase_times()
+    plan.set_timing(False)
+    phase_avg = {k: v / max(1, nev) for k, v in phases.items()}
+
+    # accuracy against the stored oracle sample (direct sum at 256 targets x all sources)
+    rel = None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    try:
+        from make_golden import load
+        g = load("uniform_1m") if a.n == (1 << 20) else None
+        if g is not None:
+            idx, ref = g
+            got = out.cpu().numpy()[idx]
+            rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    except Exception as ex:  # noqa: BLE001
+        print(f"accuracy check skipped: {ex}", file=sys.stderr)
+
+    # roofline of the dominant kernel, from algorithmic work per launch / measured launch time
+    P1 = info["p"] + 1
+    m2l_flops = 8.0 * P1 * P1 * (info["m2l_pairs"][0] + info["m2l_pairs"][1])
+    dom = max(("m2l", "leaf"), key=lambda k: phase_avg[k])
+    if dom == "m2l":
+        achieved = m2l_flops / (phase_avg["m2l"] * 1e-3) / 1e12
+        roof = {"kernel": "k_m2l", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_launch": m2l_flops}
+    else:
+        # near field: a pair costs one float64 log plus 8 flops (counted as 28 flops,
+        # the log taken at 20 float64 operations); L2P and M2P are added at 8 (p+1) per target
+        pairs = info["p2p_pairs"][0] + info["p2p_pairs"][1]
+        fl = 28.0 * pairs + 8.0 * P1 * info["n"]
+        achieved = fl / (phase_avg["leaf"] * 1e-3) / 1e12
+        roof = {"kernel": "k_leaf", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_launch": fl}
+
+    res = {
+        "metric": "Mpts/s FMM eval at 1M pts, rel-l2 1e-10 vs direct; fwd+bwd and batched vs plain",
+        "value": w.n / (ms * 1e-3) / 1e6,
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform_1m: N=1,048,576 uniform in [0,1]x[1e-3,1.001], charges U[-1,1], "
+                               "impedance 1.0, sources=targets, 1 charge vector",
+                   "n": w.n, "p": info["p"], "leaf_size": a.leaf, "impedance": 1.0},
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, a.cpu_sample)
+    if not a.quiet_extra:
+        res["rel_l2_vs_oracle_sample"] = rel
+        res["plan_ms"] = plan_ms
+        res["plan_plus_eval_mpts_s"] = w.n / ((plan_ms + ms) * 1e-3) / 1e6
+        res["phase_ms"] = {k: round(v, 5) for k, v in phase_avg.items()}
+        res["tree"] = {"nbox": info["nbox"], "nleaf": info["nleaf"], "depth": info["depth"],
+                       "list_len": info["list_len"], "p2p_pairs": info["p2p_pairs"],
+                       "m2l_pairs": info["m2l_pairs"], "device_bytes": info["device_bytes"]}
+    print(json.dumps(res), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

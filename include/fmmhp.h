@@ -80,7 +80,22 @@ typedef struct {
     double lambda_re, lambda_im;
     int real_impedance;     /* 1 if lambda_im == 0 (one local expansion + rank-one surface term) */
     int64_t device_bytes;   /* device memory held by the plan */
+    int64_t p2p_pairs[2];   /* near-field (target, source) pairs per charge vector: upper sources,
+                               image sources (the U list expanded to points) */
+    int64_t m2l_pairs[2];   /* M2L (target box, source box) pairs: upper, image (the V list) */
 } fmmhp_plan_stats;
+
+/* Phases of fmmhp_eval whose device time fmmhp_plan_phase_times reports. */
+enum {
+    FMMHP_PHASE_P2M = 0,    /* charge gather and leaf multipoles (S2M) */
+    FMMHP_PHASE_M2M = 1,    /* upward pass, one launch per level */
+    FMMHP_PHASE_M2L = 2,    /* multipole-to-local over all levels, one launch */
+    FMMHP_PHASE_P2L = 3,    /* X list */
+    FMMHP_PHASE_L2L = 4,    /* downward pass, one launch per level */
+    FMMHP_PHASE_SURF = 5,   /* surface term sum (real impedance) */
+    FMMHP_PHASE_LEAF = 6,   /* L2P, W list, U list and output, one launch */
+    FMMHP_NUM_PHASES = 7
+};
 
 /* Build a plan: the adaptive quadtree over the points and their images, interaction lists and
  * translation tables (Algorithm 1: "generate image coordinates", "generate an adaptive hierarchical
@@ -137,6 +152,16 @@ fmmhp_status fmmhp_plan_export_tree(fmmhp_plan_t plan, int32_t *level, int32_t *
                                     int64_t *perm, int64_t *u_off, int32_t *u_ent,
                                     int64_t *v_off, int32_t *v_ent, int64_t *w_off,
                                     int32_t *w_ent, int64_t *x_off, int32_t *x_ent);
+
+/* Per-phase device timing of fmmhp_eval (profiling aid).  enable = 1 clears the totals and starts
+ * recording HIP events around every phase of every subsequent eval on that eval's stream;
+ * enable = 0 stops recording.  Recording adds one event per phase boundary. */
+fmmhp_status fmmhp_plan_set_timing(fmmhp_plan_t plan, int enable);
+
+/* Totals since timing was enabled: ms[k] = summed device milliseconds of phase k
+ * (k < FMMHP_NUM_PHASES), n_evals = number of charge vectors evaluated.  Waits for the recorded
+ * events.  ms: [host] FMMHP_NUM_PHASES doubles; n_evals: [host], may be NULL. */
+fmmhp_status fmmhp_plan_phase_times(fmmhp_plan_t plan, double *ms, int64_t *n_evals);
 
 /* Release the plan and its device memory.  Synchronises the device.  plan may be NULL (no-op). */
 fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan);

@@ -46,7 +46,11 @@ class PlanStats(ctypes.Structure):
                 ("list_len", ctypes.c_int64 * 4), ("x_lo", ctypes.c_double),
                 ("S", ctypes.c_double), ("scale", ctypes.c_double),
                 ("lambda_re", ctypes.c_double), ("lambda_im", ctypes.c_double),
-                ("real_impedance", ctypes.c_int), ("device_bytes", ctypes.c_int64)]
+                ("real_impedance", ctypes.c_int), ("device_bytes", ctypes.c_int64),
+                ("p2p_pairs", ctypes.c_int64 * 2), ("m2l_pairs", ctypes.c_int64 * 2)]
+
+
+PHASES = ("p2m", "m2m", "m2l", "p2l", "l2l", "surface", "leaf")
 
 
 _lib = None
@@ -64,6 +68,8 @@ _SIGNATURES = {
     "fmmhp_plan_destroy": [_P],
     "fmmhp_direct_eval": [_I64, _P, _P, _INT, _P, _I64, _P, _P, _D, _D, _P, _P],
     "fmmhp_reaction_integrals": [_I64, _P, _P, _INT, _D, _D, _P, _P],
+    "fmmhp_plan_set_timing": [_P, _INT],
+    "fmmhp_plan_phase_times": [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)],
     "fmmhp_status_string": [_INT],
     "fmmhp_last_error_message": [],
 }
@@ -128,8 +134,20 @@ def fmmhp_plan_info(plan) -> dict:
     s = PlanStats()
     _check("fmmhp_plan_info", lib().fmmhp_plan_info(plan, ctypes.byref(s)))
     d = {k: getattr(s, k) for k, _ in PlanStats._fields_}
-    d["list_len"] = list(s.list_len)
+    for k in ("list_len", "p2p_pairs", "m2l_pairs"):
+        d[k] = list(getattr(s, k))
     return d
+
+
+def fmmhp_plan_set_timing(plan, enable: bool):
+    _check("fmmhp_plan_set_timing", lib().fmmhp_plan_set_timing(plan, int(bool(enable))))
+
+
+def fmmhp_plan_phase_times(plan) -> tuple[dict, int]:
+    ms = (_D * len(PHASES))()
+    n = _I64()
+    _check("fmmhp_plan_phase_times", lib().fmmhp_plan_phase_times(plan, ms, ctypes.byref(n)))
+    return {k: ms[i] for i, k in enumerate(PHASES)}, n.value
 
 
 def fmmhp_plan_export_tree(plan) -> dict:
@@ -207,6 +225,13 @@ class HalfPlaneFMM:
     def export_tree(self) -> dict:
         return fmmhp_plan_export_tree(self._plan)
 
+    def set_timing(self, enable: bool):
+        fmmhp_plan_set_timing(self._plan, enable)
+
+    def phase_times(self) -> tuple[dict, int]:
+        """(ms per phase summed since set_timing(True), number of vectors evaluated)."""
+        return fmmhp_plan_phase_times(self._plan)
+
     def __call__(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """phi = A q.  q: [N] or [n_vec, N], real or complex.  Returns complex128 of q's shape."""
         if not isinstance(q, torch.Tensor) or not q.is_cuda:
@@ -281,4 +306,5 @@ def reaction_integrals(x, y, nmax: int, impedance) -> torch.Tensor:
 __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functions",
            "FMMHPError", "Opts", "PlanStats", "fmmhp_plan_create", "fmmhp_eval",
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
-           "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P"]
+           "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
+           "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES"]

@@ -174,6 +174,39 @@ fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {
     st->lambda_im = plan->lambda_im;
     st->real_impedance = plan->sched.real_Z ? 1 : 0;
     st->device_bytes = plan->arena.bytes;
+    for (int k = 0; k < 2; ++k) {
+        st->p2p_pairs[k] = plan->sched.p2p_pairs[k];
+        st->m2l_pairs[k] = plan->sched.m2l_pairs[k];
+    }
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_plan_set_timing(fmmhp_plan_t plan, int enable) {
+    FMMHP_CHECK(check_plan(plan));
+    Sched &S = plan->sched;
+    if (!S.events) {
+        S.events = new (std::nothrow) std::vector<hipEvent_t>();
+        if (!S.events) {
+            set_error("host allocation failed");
+            return FMMHP_ENOMEM;
+        }
+    }
+    FMMHP_CHECK(collect_phase_times(S));
+    for (double &v : S.phase_ms) v = 0.0;
+    S.timed_evals = 0;
+    S.timing = enable != 0;
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_plan_phase_times(fmmhp_plan_t plan, double *ms, int64_t *n_evals) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!ms) {
+        set_error("ms is NULL");
+        return FMMHP_EINVAL;
+    }
+    FMMHP_CHECK(collect_phase_times(plan->sched));
+    for (int k = 0; k < FMMHP_NUM_PHASES; ++k) ms[k] = plan->sched.phase_ms[k];
+    if (n_evals) *n_evals = plan->sched.timed_evals;
     return FMMHP_OK;
 }
 
@@ -220,6 +253,11 @@ fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
         return FMMHP_ESTATE;
     }
     (void)hipDeviceSynchronize();
+    if (plan->sched.events) {
+        for (auto e : *plan->sched.events) (void)hipEventDestroy(e);
+        delete plan->sched.events;
+        plan->sched.events = nullptr;
+    }
     plan->arena.release();
     plan->magic = kDead;
     delete plan;

@@ -38,6 +38,13 @@ __host__ __device__ __forceinline__ cplx cexp_(cplx a) {
     return {e * c, e * s};
 }
 __host__ __device__ __forceinline__ cplx clog_(cplx a) { return {log(cabs(a)), atan2(a.im, a.re)}; }
+// acc += a * b with four fused multiply-adds
+__host__ __device__ __forceinline__ void cfma(cplx &acc, cplx a, cplx b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
 // multiply by i^k
 __host__ __device__ __forceinline__ cplx mul_ipow(cplx a, int k) {
     switch (k & 3) {

@@ -118,40 +118,36 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const int32_t *__restrict__ l
 }
 
 // ---------------------------------------------------------------------------------------------
-// M2M: one level, parents in [lo, hi)
+// M2M: one level, parents in [lo, lo + nb); one thread per (parent, coefficient)
 // ---------------------------------------------------------------------------------------------
 template <int PB>
-__global__ __launch_bounds__(64) void k_m2m(int lo, int hi, int nbox, const int32_t *__restrict__ leaf,
-                                            const int32_t *__restrict__ child_first,
-                                            const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
-                                            const int32_t *__restrict__ by, const cplx *__restrict__ E,
-                                            cplx *__restrict__ W) {
-    const int b = lo + blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= hi || leaf[b]) return;
-    cplx out[PB + 1];
-#pragma unroll
-    for (int n = 0; n <= PB; ++n) out[n] = mk(0.0, 0.0);
+__global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int32_t *__restrict__ leaf,
+                                             const int32_t *__restrict__ child_first,
+                                             const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
+                                             const int32_t *__restrict__ by, const cplx *__restrict__ E,
+                                             cplx *__restrict__ W) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * (PB + 1)) return;
+    const int b = lo + t % nb, n = t / nb;
+    if (leaf[b]) return;
+    cplx out = mk(0.0, 0.0);
     const int c0 = child_first[b], c1 = c0 + nchild[b];
     for (int c = c0; c < c1; ++c) {
-        const int q = (bx[c] & 1) | ((by[c] & 1) << 1);
-        const cplx *Eq = E + q * (PB + 1);
-        double sc = 1.0;
-#pragma unroll
-        for (int m = 0; m <= PB; ++m) {
-            const cplx wm = W[(int64_t)m * nbox + c] * sc;
-#pragma unroll
-            for (int n = m; n <= PB; ++n) out[n] += Eq[n - m] * wm;
+        const cplx *Eq = E + ((bx[c] & 1) | ((by[c] & 1) << 1)) * (PB + 1) + n;
+        double sc = 1.0;  // 2^-m
+        for (int m = 0; m <= n; ++m) {
+            cfma(out, Eq[-m], W[(int64_t)m * nbox + c] * sc);
             sc *= 0.5;
         }
     }
-#pragma unroll
-    for (int n = 0; n <= PB; ++n) W[(int64_t)n * nbox + b] = out[n];
+    W[(int64_t)n * nbox + b] = out;
 }
 
 // ---------------------------------------------------------------------------------------------
-// M2L over tiles of same-level, same-class target boxes; one wave per (tile, output chunk).
-// Lanes are target boxes; the operator of an offset slot is the same for every lane, so its
-// coefficients are read with scalar loads.
+// M2L over tiles of same-level, same-class target boxes; one wave per (tile, chunk of CH output
+// coefficients).  Lanes are target boxes; the operator of an offset slot is the same for every
+// lane, so its coefficients are read with scalar loads.  Operator rows are zero-padded to
+// m2l_row(PB) entries so that every chunk runs the same branch-free inner loop.
 // ---------------------------------------------------------------------------------------------
 struct M2LArgs {
     int nbox;
@@ -166,7 +162,7 @@ struct M2LArgs {
 
 template <int PB, int CH>
 __global__ __launch_bounds__(64) void k_m2l(M2LArgs a) {
-    constexpr int NT = 2 * PB + 1;
+    constexpr int NTP = m2l_row(PB);
     const int tile = blockIdx.x;
     const int n0 = blockIdx.y * CH;
     const int lane = threadIdx.x;
@@ -183,56 +179,61 @@ __global__ __launch_bounds__(64) void k_m2l(M2LArgs a) {
         const int o = a.class_slots[cls * 28 + 1 + s];
         const int src = (b >= 0) ? a.vslot[(int64_t)o * a.nbox + b] : -1;
         if (src < 0) continue;
-        const cplx *T = a.Tfree + o * NT + n0;
+        const cplx *T = a.Tfree + o * NTP + n0;
 #pragma unroll
         for (int m = 0; m <= PB; ++m) {
             const cplx wm = a.W[(int64_t)m * a.nbox + src];
 #pragma unroll
-            for (int k = 0; k < CH; ++k)
-                if (n0 + k <= PB) acc[k] += T[k + m] * wm;
+            for (int k = 0; k < CH; ++k) cfma(acc[k], T[k + m], wm);
         }
-        if (n0 == 0) acc0 += (a.Lfree[o] - mk(ll, 0.0)) * a.W[src];
+        if (n0 == 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), a.W[src]);
     }
+    if (b < 0) return;
     cplx accG[CH];
 #pragma unroll
     for (int k = 0; k < CH; ++k) accG[k] = acc[k];
     cplx accG0 = acc0;
-    if (b >= 0) {
-        for (int e = a.vimg_off[b]; e < a.vimg_off[b + 1]; ++e) {
-            const int code = a.vimg_ent[e];
-            const int src = code >> 5, is = code & 31;
-            const cplx *TH = a.TimgH + ((int64_t)l * kNumImgSlots + is) * NT + n0;
-            const cplx *TG = a.TimgG + ((int64_t)l * kNumImgSlots + is) * NT + n0;
+    for (int e = a.vimg_off[b]; e < a.vimg_off[b + 1]; ++e) {
+        const int code = a.vimg_ent[e];
+        const int src = code >> 5, is = code & 31;
+        const cplx *TH = a.TimgH + ((int64_t)l * kNumImgSlots + is) * NTP + n0;
+        if (a.nloc == 1) {
+#pragma unroll
+            for (int m = 0; m <= PB; ++m) {
+                const cplx wm = conj(a.W[(int64_t)m * a.nbox + src]);
+#pragma unroll
+                for (int k = 0; k < CH; ++k) cfma(acc[k], TH[k + m], wm);
+            }
+        } else {
+            const cplx *TG = a.TimgG + ((int64_t)l * kNumImgSlots + is) * NTP + n0;
 #pragma unroll
             for (int m = 0; m <= PB; ++m) {
                 const cplx wm = conj(a.W[(int64_t)m * a.nbox + src]);
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
-                    if (n0 + k <= PB) {
-                        acc[k] += TH[k + m] * wm;
-                        if (a.nloc == 2) accG[k] += TG[k + m] * wm;
-                    }
+                    cfma(acc[k], TH[k + m], wm);
+                    cfma(accG[k], TG[k + m], wm);
                 }
-            }
-            if (n0 == 0) {
-                const cplx lt = (a.Limg[is] + mk(ll, 0.0)) * conj(a.W[src]);
-                acc0 += lt;
-                accG0 += lt;
             }
         }
-        const int64_t stride = (int64_t)(PB + 1) * a.nbox;
+        if (n0 == 0) {
+            const cplx lt = (a.Limg[is] + mk(ll, 0.0)) * conj(a.W[src]);
+            acc0 += lt;
+            accG0 += lt;
+        }
+    }
+    const int64_t stride = (int64_t)(PB + 1) * a.nbox;
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int n = n0 + k;
-            if (n <= PB) {
-                cplx v = -acc[k];
-                if (n == 0) v += acc0;
-                a.Lam[(int64_t)n * a.nbox + b] = v;
-                if (a.nloc == 2) {
-                    cplx vg = -accG[k];
-                    if (n == 0) vg += accG0;
-                    a.Lam[stride + (int64_t)n * a.nbox + b] = vg;
-                }
+    for (int k = 0; k < CH; ++k) {
+        const int n = n0 + k;
+        if (n <= PB) {
+            cplx v = -acc[k];
+            if (n == 0) v += acc0;
+            a.Lam[(int64_t)n * a.nbox + b] = v;
+            if (a.nloc == 2) {
+                cplx vg = -accG[k];
+                if (n == 0) vg += accG0;
+                a.Lam[stride + (int64_t)n * a.nbox + b] = vg;
             }
         }
     }
@@ -248,96 +249,91 @@ __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nloc, cplx *
 }
 
 // ---------------------------------------------------------------------------------------------
-// P2L (X list): sources of a coarse leaf straight into the local of a finer box.
+// P2L (X list): sources of a coarse leaf straight into the local of a finer box.  One wave per
+// target box; lanes take source points, write their p + 1 contributions to LDS, and lane n sums
+// coefficient n over the chunk in a fixed order.
 // ---------------------------------------------------------------------------------------------
 template <int PB>
-__global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, int nxbox, const int32_t *__restrict__ xbox,
-                                            int nbox, const int32_t *__restrict__ level,
-                                            const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
-                                            const int32_t *__restrict__ first, const int32_t *__restrict__ count,
-                                            const int32_t *__restrict__ xoff, const int32_t *__restrict__ xent,
-                                            const double *__restrict__ xs, const double *__restrict__ ys,
-                                            const double *__restrict__ qs, const double *__restrict__ fact,
-                                            cplx *__restrict__ Lam) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nxbox) return;
-    const int b = xbox[t];
+__global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, const int32_t *__restrict__ xbox, int nbox,
+                                            const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
+                                            const int32_t *__restrict__ by, const int32_t *__restrict__ first,
+                                            const int32_t *__restrict__ count, const int32_t *__restrict__ xoff,
+                                            const int32_t *__restrict__ xent, const double *__restrict__ xs,
+                                            const double *__restrict__ ys, const double *__restrict__ qs,
+                                            const double *__restrict__ fact, cplx *__restrict__ Lam) {
+    __shared__ cplx contrib[64][PB + 1];
+    const int b = xbox[blockIdx.x];
+    const int lane = threadIdx.x;
     const int l = level[b];
     const cplx cb = centre_of(g, l, bx[b], by[b]);
     const double rho = 0.5 * side_of(g, l);
-    cplx acc[PB + 1];
-#pragma unroll
-    for (int n = 0; n <= PB; ++n) acc[n] = mk(0.0, 0.0);
+    cplx acc = mk(0.0, 0.0);
     for (int e = xoff[b]; e < xoff[b + 1]; ++e) {
         const int code = xent[e];
         const int c = code >> 1, img = code & 1;
-        for (int j = first[c]; j < first[c] + count[c]; ++j) {
-            const double q = qs[j];
-            const double yj = img ? -ys[j] : ys[j];
-            const cplx d = mk(xs[j] - cb.re, yj - cb.im);  // source - centre
-            const double sgn = img ? 1.0 : -1.0;             // -(1/4pi) upper, +(1/4pi) image
-            // log(c_b - z_j): local of log(z - z_j) about c_b
-            acc[0] += (sgn * kInv4Pi * q) * clog_(-d);
-            const cplx sig = rho * inv(d);
-            cplx pw = sig;
-#pragma unroll
-            for (int n = 1; n <= PB; ++n) {
-                // lambda_n = n! rho^n b_n with b_n = -q / (n (z_j - c)^n)  ->  -q (n-1)! sig^n
-                acc[n] += (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
-                pw = pw * sig;
-            }
-            if (img) {
-                // reaction S2L (eq. (LEcoefficients)), re-expanded in powers of (z - c_b):
-                // lambda_n += i^n n! rho^n q I_n(x_c - x_j, y_c + y_j)  (G: conj of I_n(-X, Y))
-                const double X = cb.re - xs[j], Y = cb.im + ys[j];
-                const double Xs = loc == 0 ? X : -X;
-                const cplx wv = mk(Y, -Xs);
-                const cplx sw = rho * inv(wv);
-                const cplx zr = rho * Z;
-                cplx K = reaction_I0_general(Xs, Y, Z);
-                cplx F = mk(1.0, 0.0);
-                acc[0] += q * (loc == 0 ? K : conj(K));
-#pragma unroll
+        const int j0 = first[c], j1 = j0 + count[c];
+        for (int jb = j0; jb < j1; jb += 64) {
+            const int j = jb + lane;
+            cplx *out = contrib[lane];
+            if (j < j1) {
+                const double q = qs[j];
+                const double yj = img ? -ys[j] : ys[j];
+                const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
+                const double sgn = img ? 1.0 : -1.0;            // -(1/4pi) upper, +(1/4pi) image
+                // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
+                out[0] = (sgn * kInv4Pi * q) * clog_(-d);
+                const cplx sig = rho * inv(d);
+                cplx pw = sig;
                 for (int n = 1; n <= PB; ++n) {
-                    F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
-                    K = F * kInv2Pi + zr * K;
-                    const cplx Kn = loc == 0 ? K : conj(K);
-                    acc[n] += q * mul_ipow(Kn, n);
+                    out[n] = (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
+                    pw = pw * sig;
                 }
+                if (img) {
+                    // reaction S2L (eq. (LEcoefficients)) re-expanded in powers of (z - c_b):
+                    // lambda_n += i^n n! rho^n q I_n(x_c - x_j, y_c + y_j)  (G: conj of I_n(-X, Y))
+                    const double X = cb.re - xs[j], Y = cb.im + ys[j];
+                    const double Xs = loc == 0 ? X : -X;
+                    const cplx sw = rho * inv(mk(Y, -Xs));
+                    const cplx zr = rho * Z;
+                    cplx K = reaction_I0_general(Xs, Y, Z);
+                    cplx F = mk(1.0, 0.0);
+                    out[0] += q * (loc == 0 ? K : conj(K));
+                    for (int n = 1; n <= PB; ++n) {
+                        F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
+                        K = F * kInv2Pi + zr * K;
+                        out[n] += q * mul_ipow(loc == 0 ? K : conj(K), n);
+                    }
+                }
+            } else {
+                for (int n = 0; n <= PB; ++n) out[n] = mk(0.0, 0.0);
             }
+            __syncthreads();
+            if (lane <= PB)
+                for (int k = 0; k < 64; ++k) acc += contrib[k][lane];
+            __syncthreads();
         }
     }
-    const int64_t base = (int64_t)loc * (PB + 1) * nbox;
-#pragma unroll
-    for (int n = 0; n <= PB; ++n) Lam[base + (int64_t)n * nbox + b] += acc[n];
+    if (lane <= PB) Lam[(int64_t)loc * (PB + 1) * nbox + (int64_t)lane * nbox + b] += acc;
 }
 
 // ---------------------------------------------------------------------------------------------
-// L2L: one level of children [lo, hi)
+// L2L: one level of children [lo, lo + nb); one thread per (child, coefficient)
 // ---------------------------------------------------------------------------------------------
 template <int PB>
-__global__ __launch_bounds__(64) void k_l2l(int lo, int hi, int nbox, int nloc, const int32_t *__restrict__ parent,
-                                            const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
-                                            const cplx *__restrict__ E, cplx *__restrict__ Lam) {
-    const int b = lo + blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= hi) return;
+__global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc, const int32_t *__restrict__ parent,
+                                             const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
+                                             const cplx *__restrict__ E, cplx *__restrict__ Lam) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * (PB + 1)) return;
+    const int b = lo + t % nb, m = t / nb;
     const int P = parent[b];
-    const int q = (bx[b] & 1) | ((by[b] & 1) << 1);
-    const cplx *Eq = E + q * (PB + 1);
+    const cplx *Eq = E + ((bx[b] & 1) | ((by[b] & 1) << 1)) * (PB + 1) - m;
+    const double sc = ldexp(1.0, -m);
     for (int loc = 0; loc < nloc; ++loc) {
         cplx *L = Lam + (int64_t)loc * (PB + 1) * nbox;
-        cplx lp[PB + 1];
-#pragma unroll
-        for (int n = 0; n <= PB; ++n) lp[n] = L[(int64_t)n * nbox + P];
-        double sc = 1.0;
-#pragma unroll
-        for (int m = 0; m <= PB; ++m) {
-            cplx s = mk(0.0, 0.0);
-#pragma unroll
-            for (int n = m; n <= PB; ++n) s += Eq[n - m] * lp[n];
-            L[(int64_t)m * nbox + b] += s * sc;
-            sc *= 0.5;
-        }
+        cplx s = mk(0.0, 0.0);
+        for (int n = m; n <= PB; ++n) cfma(s, Eq[n], L[(int64_t)n * nbox + P]);
+        L[(int64_t)m * nbox + b] += s * sc;
     }
 }
 
@@ -369,15 +365,30 @@ __global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = mk(sr[0], si[0]);
 }
 
-__global__ void k_rank1_final(cplx *__restrict__ part, int np) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    cplx s = mk(0.0, 0.0);
-    for (int k = 0; k < np; ++k) s += part[k];
-    part[np] = s;
+__global__ __launch_bounds__(256) void k_rank1_final(cplx *__restrict__ part, int np) {
+    __shared__ double sr[256], si[256];
+    double ar = 0.0, ai = 0.0;
+    for (int k = threadIdx.x; k < np; k += 256) {
+        ar += part[k].re;
+        ai += part[k].im;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sr[threadIdx.x] += sr[threadIdx.x + off];
+            si[threadIdx.x] += si[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[np] = mk(sr[0], si[0]);
 }
 
 // ---------------------------------------------------------------------------------------------
-// Leaf evaluation: L2P, W list (M2P), U list (P2P), surface term; one thread per target point.
+// Leaf evaluation.  k_leaf: L2P, the log parts of the U list and the surface term, one thread per
+// target point, writes phi.  k_leaf_extra: the rarer W list (M2P) and the reaction part of the U
+// list's image entries, for the targets whose leaf has them; adds to phi.
 // ---------------------------------------------------------------------------------------------
 struct LeafArgs {
     Geo g;
@@ -390,6 +401,8 @@ struct LeafArgs {
     const cplx *W, *Lam;
     const double *invfact, *fact;
     const cplx *rank1;   // device scalar (real impedance) or null
+    const int32_t *extra_pts;
+    int64_t n_extra;
     double *phi;         // [n][2]
 };
 
@@ -400,20 +413,69 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     const int b = a.leaf_of[i];
     const int l = a.level[b];
     const double x = a.xs[i], y = a.ys[i];
-    const cplx z = mk(x, y);
     const cplx cb = centre_of(a.g, l, a.bx[b], a.by[b]);
     const double irho = 2.0 / side_of(a.g, l);
     // L2P: H(z) = sum_n lambda_n / n! zeta^n
     const cplx zeta = mk((x - cb.re) * irho, (y - cb.im) * irho);
     cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
     {
-        const cplx *L = a.Lam;
-        for (int n = PB; n >= 0; --n) H = H * zeta + L[(int64_t)n * a.nbox + b] * a.invfact[n];
+        const cplx *L = a.Lam + b;
+        for (int n = PB; n >= 0; --n) {
+            cplx t = L[(int64_t)n * a.nbox] * a.invfact[n];
+            cfma(t, H, zeta);
+            H = t;
+        }
         if (a.nloc == 2) {
-            const cplx *L2 = a.Lam + (int64_t)(PB + 1) * a.nbox;
-            for (int n = PB; n >= 0; --n) G = G * zeta + L2[(int64_t)n * a.nbox + b] * a.invfact[n];
+            const cplx *L2 = a.Lam + (int64_t)(PB + 1) * a.nbox + b;
+            for (int n = PB; n >= 0; --n) {
+                cplx t = L2[(int64_t)n * a.nbox] * a.invfact[n];
+                cfma(t, G, zeta);
+                G = t;
+            }
         }
     }
+    // U list, log terms
+    double lfree = 0.0, limg = 0.0;
+    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+        const int code = a.uent[e];
+        const int c = code >> 1;
+        const int j0 = a.first[c], j1 = j0 + a.count[c];
+        if (!(code & 1)) {
+            for (int j = j0; j < j1; ++j) {
+                const double dx = x - a.xs[j], dy = y - a.ys[j];
+                const double r2 = fma(dx, dx, dy * dy);
+                if (r2 > 0.0) lfree = fma(a.qs[j], log(r2), lfree);
+            }
+        } else {
+            for (int j = j0; j < j1; ++j) {
+                const double dx = x - a.xs[j], dy = y + a.ys[j];
+                limg = fma(a.qs[j], log(fma(dx, dx, dy * dy)), limg);
+            }
+        }
+    }
+    const double near = kInv4Pi * (limg - lfree);
+    cplx phi;
+    if (a.nloc == 1) {
+        const cplx s = *a.rank1;
+        const cplx surf = mul_ipow(cexp_(-(a.Z * mk(y, x))) * s, 1);
+        phi = mk(2.0 * H.re + near, 0.0) + surf;
+    } else {
+        phi = H + conj(G) + mk(near, 0.0);
+    }
+    const int64_t o = a.perm[i];
+    a.phi[2 * o] = phi.re;
+    a.phi[2 * o + 1] = phi.im;
+}
+
+template <int PB>
+__global__ __launch_bounds__(128) void k_leaf_extra(LeafArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_extra) return;
+    const int64_t i = a.extra_pts[t];
+    const int b = a.leaf_of[i];
+    const double x = a.xs[i], y = a.ys[i];
+    const cplx z = mk(x, y);
+    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
     // W list: multipoles of smaller non-adjacent boxes evaluated at the target
     for (int e = a.woff[b]; e < a.woff[b + 1]; ++e) {
         const int code = a.went[e];
@@ -460,45 +522,33 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
             }
         }
     }
-    // U list: direct interactions
-    double lfree = 0.0, limg = 0.0, rre = 0.0;
+    // reaction part of the U list's image entries
+    double rre = 0.0;
     cplx rc = mk(0.0, 0.0);
     for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
         const int code = a.uent[e];
+        if (!(code & 1)) continue;
         const int c = code >> 1;
         const int j0 = a.first[c], j1 = j0 + a.count[c];
-        if (!(code & 1)) {
-            for (int j = j0; j < j1; ++j) {
-                const double dx = x - a.xs[j], dy = y - a.ys[j];
-                const double r2 = dx * dx + dy * dy;
-                if (r2 > 0.0) lfree += a.qs[j] * log(r2);
-            }
-        } else {
-            for (int j = j0; j < j1; ++j) {
-                const double dx = x - a.xs[j], dy = y + a.ys[j];
-                const double qj = a.qs[j];
-                limg += qj * log(dx * dx + dy * dy);
-                const cplx I = reaction_I0_near(dx, dy, a.Z);
-                if (a.nloc == 1) {
-                    rre += qj * I.re;
-                } else {
-                    rc += qj * (I + reaction_I0_near(-dx, dy, a.Z));
-                }
+        for (int j = j0; j < j1; ++j) {
+            const double dx = x - a.xs[j], dy = y + a.ys[j];
+            const double qj = a.qs[j];
+            const cplx I = reaction_I0_near(dx, dy, a.Z);
+            if (a.nloc == 1) {
+                rre += qj * I.re;
+            } else {
+                rc += qj * (I + reaction_I0_near(-dx, dy, a.Z));
             }
         }
     }
-    const double near = kInv4Pi * (limg - lfree);
-    cplx phi;
-    if (a.nloc == 1) {
-        const cplx s = *a.rank1;
-        const cplx surf = mul_ipow(cexp_(-(a.Z * mk(y, x))) * s, 1);
-        phi = mk(2.0 * H.re + near + 2.0 * rre, 0.0) + surf;
-    } else {
-        phi = H + conj(G) + mk(near, 0.0) + rc;
-    }
     const int64_t o = a.perm[i];
-    a.phi[2 * o] = phi.re;
-    a.phi[2 * o + 1] = phi.im;
+    if (a.nloc == 1) {
+        a.phi[2 * o] += 2.0 * (H.re + rre);
+    } else {
+        const cplx v = H + conj(G) + rc;
+        a.phi[2 * o] += v.re;
+        a.phi[2 * o + 1] += v.im;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -596,7 +646,17 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     FMMHP_CHECK(to_host(voff, T.off[1], (size_t)nbox + 1, s));
     FMMHP_CHECK(to_host(vent, T.ent[1], (size_t)T.len[1], s));
     FMMHP_CHECK(to_host(xoff, T.off[3], (size_t)nbox + 1, s));
+    std::vector<int32_t> uoff, uent, cnt;
+    FMMHP_CHECK(to_host(uoff, T.off[0], (size_t)nbox + 1, s));
+    FMMHP_CHECK(to_host(uent, T.ent[0], (size_t)T.len[0], s));
+    FMMHP_CHECK(to_host(cnt, T.count, (size_t)nbox, s));
     FMMHP_HIP(hipStreamSynchronize(s));
+    S.p2p_pairs[0] = S.p2p_pairs[1] = 0;
+    for (int b = 0; b < nbox; ++b)
+        for (int e = uoff[b]; e < uoff[b + 1]; ++e)
+            S.p2p_pairs[uent[e] & 1] += (int64_t)cnt[b] * cnt[uent[e] >> 1];
+    S.m2l_pairs[0] = S.m2l_pairs[1] = 0;
+    for (size_t e = 0; e < vent.size(); ++e) S.m2l_pairs[vent[e] & 1] += 1;
 
     // M2L slots
     std::vector<int32_t> vslot((size_t)kNumSlots * nbox, -1);
@@ -670,9 +730,24 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     S.nxbox = (int)xb.size();
     FMMHP_CHECK(to_dev(A, &S.xbox, xb, "xbox", s));
     FMMHP_CHECK(to_dev(A, &S.leaves, lv, "leaves", s));
+    {
+        std::vector<int32_t> woff, first, ex;
+        FMMHP_CHECK(to_host(woff, T.off[2], (size_t)nbox + 1, s));
+        FMMHP_CHECK(to_host(first, T.first, (size_t)nbox, s));
+        FMMHP_HIP(hipStreamSynchronize(s));
+        for (int b : lv) {
+            bool need = woff[b + 1] > woff[b];
+            for (int e = uoff[b]; e < uoff[b + 1] && !need; ++e) need = (uent[e] & 1) != 0;
+            if (need)
+                for (int j = first[b]; j < first[b] + cnt[b]; ++j) ex.push_back(j);
+        }
+        S.n_extra = (int64_t)ex.size();
+        FMMHP_CHECK(to_dev(A, &S.extra_pts, ex, "extra points", s));
+    }
 
     // tables
     const int NT = 2 * PB + 1;
+    const int NTP = m2l_row(PB);
     std::vector<double> fact(NT + 1), ifact(NT + 1);
     fact[0] = 1.0;
     for (int j = 1; j <= NT; ++j) fact[j] = fact[j - 1] * j;
@@ -683,7 +758,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     using C = std::complex<double>;
     auto cx = [](C v) { return mk(v.real(), v.imag()); };
     const double i4p = 1.0 / (4.0 * M_PI);
-    std::vector<cplx> Tfree((size_t)kNumSlots * NT, mk(0, 0)), Lfree(kNumSlots, mk(0, 0));
+    std::vector<cplx> Tfree((size_t)kNumSlots * NTP, mk(0, 0)), Lfree(kNumSlots, mk(0, 0));
     for (int dy = -3; dy <= 3; ++dy)
         for (int dx = -3; dx <= 3; ++dx) {
             if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
@@ -692,7 +767,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
             const C t = 1.0 / (2.0 * D);
             C tj = t;  // (j-1)! t^j
             for (int j = 1; j < NT; ++j) {
-                Tfree[(size_t)o * NT + j] = cx(-i4p * tj);
+                Tfree[(size_t)o * NTP + j] = cx(-i4p * tj);
                 tj = tj * t * (double)j;
             }
             Lfree[o] = cx(-i4p * std::log(-D));
@@ -703,7 +778,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     for (int l = 0; l < 32; ++l) loglev[l] = std::log(ldexp(T.S, -l));  // log(2 rho_l) = log(side_l)
     FMMHP_CHECK(to_dev(A, &S.loglev, loglev, "loglev", s));
 
-    std::vector<cplx> TH((size_t)32 * kNumImgSlots * NT, mk(0, 0)), TG(TH.size(), mk(0, 0)),
+    std::vector<cplx> TH((size_t)32 * kNumImgSlots * NTP, mk(0, 0)), TG(TH.size(), mk(0, 0)),
         Limg(kNumImgSlots, mk(0, 0));
     std::vector<cplx> K(NT), Km(NT);
     const C Zc(Z.re, Z.im);
@@ -737,7 +812,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
                     C ij(1.0, 0.0);
                     for (int r = 0; r < (j & 3); ++r) ij *= C(0.0, 1.0);
                     const C kp(K[j].re, K[j].im), km(Km[j].re, -Km[j].im);
-                    const size_t idx = ((size_t)l * kNumImgSlots + is) * NT + j;
+                    const size_t idx = ((size_t)l * kNumImgSlots + is) * NTP + j;
                     TH[idx] = cx(fr - fact[j] * ij * kp);
                     TG[idx] = cx(fr - fact[j] * ij * km);
                 }
@@ -776,22 +851,47 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     return FMMHP_OK;
 }
 
+// Phase markers: when timing is on, one event per phase boundary on the eval stream.
+struct Marks {
+    hipEvent_t ev[FMMHP_NUM_PHASES + 1];
+    bool on = false;
+    fmmhp_status init(const Sched &S) {
+        on = S.timing;
+        if (!on) return FMMHP_OK;
+        for (auto &e : ev) FMMHP_HIP(hipEventCreate(&e));
+        return FMMHP_OK;
+    }
+    fmmhp_status mark(int k, hipStream_t s) {
+        if (on) FMMHP_HIP(hipEventRecord(ev[k], s));
+        return FMMHP_OK;
+    }
+    void commit(const Sched &S) {
+        if (!on) return;
+        for (auto &e : ev) S.events->push_back(e);
+    }
+};
+
 template <int PB>
 static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leaves, const double *q, double *phi,
                              hipStream_t s) {
     const Geo g{T.x_lo, T.S};
     const int nbox = T.nbox;
+    Marks mk_;
+    FMMHP_CHECK(mk_.init(S));
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2M, s));
     hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, S.qs);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk(T.nleaf, 64)), dim3(64), 0, s, g, leaves, T.nleaf, nbox,
                        T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
     FMMHP_HIP(hipGetLastError());
-    for (int l = T.depth - 1; l >= 1; --l) {
-        const int lo = T.lev_start[l], hi = T.lev_start[l + 1];
-        if (hi > lo)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(hi - lo, 64)), dim3(64), 0, s, lo, hi, nbox,
-                               T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
+    for (int l = T.depth - 1; l >= 2; --l) {
+        const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
+        if (nb > 0)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk((int64_t)nb * (PB + 1), 256)), dim3(256), 0, s,
+                               lo, nb, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
     }
     FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
     {
         const int lo = T.lev_start[1], hi = T.lev_start[2];
         const int tot = (hi - lo) * (PB + 1) * S.nloc;
@@ -800,7 +900,7 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
                                S.Lam);
     }
     if (S.ntiles > 0) {
-        constexpr int CH = 8;
+        constexpr int CH = kM2LChunk;
         M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_class, S.class_slots, S.vslot, S.vimg_off, S.vimg_ent,
                    S.Tfree, S.Lfree, S.TimgH,      S.TimgG,      S.Limg,        S.loglev, S.W,      S.Lam,
                    S.nloc};
@@ -808,33 +908,41 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
                            ma);
         FMMHP_HIP(hipGetLastError());
     }
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
     if (S.nxbox > 0) {
         for (int loc = 0; loc < S.nloc; ++loc)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(nblk(S.nxbox, 64)), dim3(64), 0, s, g, S.Z, loc,
-                               S.nxbox, S.xbox, nbox, T.level, T.bx, T.by, T.first, T.count, T.off[3], T.ent[3],
-                               T.xs, T.ys, S.qs, S.fact, S.Lam);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(S.nxbox), dim3(64), 0, s, g, S.Z, loc, S.xbox, nbox,
+                               T.level, T.bx, T.by, T.first, T.count, T.off[3], T.ent[3], T.xs, T.ys, S.qs, S.fact,
+                               S.Lam);
         FMMHP_HIP(hipGetLastError());
     }
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_L2L, s));
     for (int l = 3; l <= T.depth; ++l) {
-        const int lo = T.lev_start[l], hi = T.lev_start[l + 1];
-        if (hi > lo)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(hi - lo, 64)), dim3(64), 0, s, lo, hi, nbox,
-                               S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+        const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
+        if (nb > 0)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk((int64_t)nb * (PB + 1), 256)), dim3(256), 0, s,
+                               lo, nb, nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     }
     FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
     const cplx *r1 = nullptr;
     if (S.nloc == 1) {
         const int np = (int)std::min<int64_t>(1024, nblk(T.n, 256));
         hipLaunchKernelGGL(k_rank1_partial, dim3(np), dim3(256), 0, s, T.xs, T.ys, S.qs, T.n, S.Z.re, S.red);
-        hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(64), 0, s, S.red, np);
+        hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(256), 0, s, S.red, np);
         FMMHP_HIP(hipGetLastError());
         r1 = S.red + np;
     }
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
     LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   T.perm,
                 T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
-                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       phi};
+                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.extra_pts, S.n_extra, phi};
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
+    if (S.n_extra > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_extra<PB>), dim3(nblk(S.n_extra, 128)), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
+    mk_.commit(S);
     return FMMHP_OK;
 }
 
@@ -857,6 +965,24 @@ static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q,
 fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
     for (int v = 0; v < nvec; ++v)
         FMMHP_CHECK(run_eval_vec(T, S, q + (int64_t)v * T.n, phi + (int64_t)v * 2 * T.n, s));
+    return FMMHP_OK;
+}
+
+fmmhp_status collect_phase_times(Sched &S) {
+    if (!S.events) return FMMHP_OK;
+    auto &ev = *S.events;
+    const int G = FMMHP_NUM_PHASES + 1;
+    for (size_t g0 = 0; g0 + G <= ev.size(); g0 += G) {
+        FMMHP_HIP(hipEventSynchronize(ev[g0 + G - 1]));
+        for (int k = 0; k < FMMHP_NUM_PHASES; ++k) {
+            float ms = 0.f;
+            FMMHP_HIP(hipEventElapsedTime(&ms, ev[g0 + k], ev[g0 + k + 1]));
+            S.phase_ms[k] += ms;
+        }
+        S.timed_evals += 1;
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.clear();
     return FMMHP_OK;
 }
 

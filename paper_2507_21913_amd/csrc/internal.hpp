@@ -15,6 +15,13 @@ constexpr int kLBits = 30;        // integer cell bits per axis of the root squa
 constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
+constexpr int kM2LChunk = 8;      // output coefficients per M2L wave
+
+// M2L operator rows are zero-padded so that every chunk of kM2LChunk outputs reads in bounds:
+// ceil((PB + 1) / kM2LChunk) * kM2LChunk + PB entries.
+__host__ __device__ constexpr int m2l_row(int PB) {
+    return ((PB + kM2LChunk) / kM2LChunk) * kM2LChunk + PB;
+}
 
 void set_error(const char *fmt, ...);
 
@@ -89,10 +96,12 @@ struct Sched {
     int nxbox = 0;
     int32_t *xbox = nullptr;
     int32_t *leaves = nullptr;      // [nleaf]
+    int64_t n_extra = 0;
+    int32_t *extra_pts = nullptr;   // sorted points whose leaf has W entries or image U entries
     // tables
-    cplx *Tfree = nullptr;          // [kNumSlots][2 PB + 1]
+    cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)
-    cplx *TimgH = nullptr;          // [31][kNumImgSlots][2 PB + 1]
+    cplx *TimgH = nullptr;          // [32][kNumImgSlots][m2l_row(PB)]
     cplx *TimgG = nullptr;          // same, G-local (complex impedance only)
     cplx *Limg = nullptr;           // [kNumImgSlots]
     double *loglev = nullptr;       // [31] log(2 rho_l)
@@ -105,12 +114,21 @@ struct Sched {
     cplx *Lam = nullptr;            // [nloc][PB + 1][nbox]
     double *qs = nullptr;           // [n] sorted charges
     cplx *red = nullptr;            // [1024] reduction partials + result
+    // algorithmic work counts
+    int64_t p2p_pairs[2] = {0, 0};
+    int64_t m2l_pairs[2] = {0, 0};
+    // phase timing (profiling aid)
+    bool timing = false;
+    std::vector<hipEvent_t> *events = nullptr;   // groups of (FMMHP_NUM_PHASES + 1)
+    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t timed_evals = 0;
 };
 
 fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, hipStream_t stream);
 fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
 
+fmmhp_status collect_phase_times(Sched &S);
 fmmhp_status run_direct(int64_t ns, const double *sx, const double *sy, int nvec, const double *q,
                         int64_t nt, const double *tx, const double *ty, cplx Z, double *phi,
                         hipStream_t stream);

@@ -1,0 +1,64 @@
+"""Write the stored oracle values used by the full-size GPU parity tests and bench.py.
+
+Calls only the CPU oracle (``oracle.direct``) and the seeded generators (``workloads``):
+for each full-size workload, the direct-sum potential at a fixed-seed sample of targets
+against ALL sources, written as text (index, Re phi, Im phi).
+
+    python tests/golden/make_golden.py [name ...]
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+from oracle import direct as D  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N_SAMPLE = 256
+
+GOLDEN = {
+    "uniform_1m": lambda: workloads.uniform_1m(seed=1),
+    "curve_4m": lambda: workloads.curve_4m(seed=1),
+    "diff_1m": lambda: workloads.diff_1m(seed=1),
+}
+
+
+def path_for(name: str) -> str:
+    return os.path.join(HERE, f"{name}_direct_sample{N_SAMPLE}.txt")
+
+
+def write(name: str) -> str:
+    w = GOLDEN[name]()
+    idx = workloads.sample_targets(w.n, N_SAMPLE)
+    t0 = time.time()
+    phi = D.potential(w.x, w.y, w.q[0], w.impedance, xt=w.x[idx], yt=w.y[idx])
+    dt = time.time() - t0
+    p = path_for(name)
+    with open(p, "w") as f:
+        f.write(f"# oracle direct sum, workload {name} (seed 1, N={w.n}, impedance {w.impedance}), "
+                f"{N_SAMPLE} sampled targets x all sources; columns: index re im\n")
+        for i, v in zip(idx, phi):
+            f.write(f"{int(i)} {v.real:.17e} {v.imag:.17e}\n")
+    print(f"{name}: {dt:.1f} s -> {p}", flush=True)
+    return p
+
+
+def load(name: str):
+    """(indices, complex values) from a stored file, or None if absent."""
+    p = path_for(name)
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return a[:, 0].astype(np.int64), a[:, 1] + 1j * a[:, 2]
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(GOLDEN)):
+        write(name)
