@@ -245,9 +245,17 @@ class HalfPlaneFMM:
         else:
             parts = q2.to(torch.float64).contiguous()
         nv = parts.shape[0]
-        raw = torch.empty((nv, self.n, 2), dtype=torch.float64, device=self.device)
+        direct_out = (out is not None and not q2.is_complex() and out.dtype == torch.complex128
+                      and out.is_contiguous() and out.device == self.device
+                      and out.numel() == nv * self.n)
+        if direct_out:
+            raw = torch.view_as_real(out)
+        else:
+            raw = torch.empty((nv, self.n, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             fmmhp_eval(self._plan, nv, parts.data_ptr(), raw.data_ptr(), _stream())
+        if direct_out:
+            return out
         phi = torch.view_as_complex(raw)
         if q2.is_complex():
             k = q2.shape[0]

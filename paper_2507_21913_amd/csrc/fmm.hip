@@ -60,19 +60,35 @@ __device__ __forceinline__ cplx centre_of(const Geo &g, int l, int bx, int by) {
 // I_0 with a short series when |P| <= 2 (the near field); the general routine otherwise.
 __device__ __noinline__ cplx reaction_I0_general(double x, double y, cplx Z) { return reaction_I0(x, y, Z); }
 
+__constant__ EiSeries kEiSeries;
+
+// Ei(P) - gamma - log P = sum_{k=1..K} P^k / (k k!) by Horner, K chosen from |P| so that the first
+// omitted term is below 1e-18 of the leading one: K = 12 for |P| <= 1/4, 20 for |P| <= 1, 30 for
+// |P| <= 2.
+__device__ __forceinline__ cplx ei_series_small(cplx P, double r2) {
+    const int K = r2 <= 0.0625 ? 12 : (r2 <= 1.0 ? 20 : 30);
+    cplx h = mk(kEiSeries.c[K], 0.0);
+    for (int k = K - 1; k >= 1; --k) {
+        cplx t = mk(kEiSeries.c[k], 0.0);
+        cfma(t, h, P);
+        h = t;
+    }
+    return h * P;
+}
+
 __device__ __forceinline__ cplx reaction_I0_near(double x, double y, cplx Z) {
     const cplx P = Z * mk(y, -x);
-    if (abs2(P) > 4.0) return reaction_I0_general(x, y, Z);
-    // Ei(P) = gamma + log P + sum_{k>=1} P^k / (k k!), |P| <= 2: 30 terms reach 1e-17
-    cplx t = P, sum = P;
-#pragma unroll 4
-    for (int k = 2; k <= 32; ++k) {
-        t = t * P * (1.0 / k);
-        sum += t * (1.0 / k);
-    }
-    const cplx ei = mk(kEulerGamma, 0.0) + clog_(P) + sum;
+    const double r2 = abs2(P);
+    if (r2 > 4.0) return reaction_I0_general(x, y, Z);
+    const cplx ei = mk(kEulerGamma, 0.0) + clog_(P) + ei_series_small(P, r2);
     const cplx e = cexp_(-P);
     return kInv2Pi * (e * mk(-ei.re, kPi - ei.im));
+}
+
+__global__ void k_pack_xy(const double *__restrict__ xs, const double *__restrict__ ys, int64_t n,
+                          double2 *__restrict__ xy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) xy[i] = make_double2(xs[i], ys[i]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -118,29 +134,55 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const int32_t *__restrict__ l
 }
 
 // ---------------------------------------------------------------------------------------------
-// M2M: one level, parents in [lo, lo + nb); one thread per (parent, coefficient)
+// M2M: one level.  A block takes kM2MParents consecutive boxes of the level; their children are a
+// contiguous range of the next level, whose multipoles are staged in LDS once.  Thread
+// (parent, n) then forms w^P_n = sum_children sum_{m<=n} (-eps)^{n-m}/(n-m)! 2^-m w^c_m.
 // ---------------------------------------------------------------------------------------------
+constexpr int kM2MParents = 16;
+
 template <int PB>
 __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int32_t *__restrict__ leaf,
                                              const int32_t *__restrict__ child_first,
                                              const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
                                              const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                              cplx *__restrict__ W) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * (PB + 1)) return;
-    const int b = lo + t % nb, n = t / nb;
-    if (leaf[b]) return;
-    cplx out = mk(0.0, 0.0);
-    const int c0 = child_first[b], c1 = c0 + nchild[b];
-    for (int c = c0; c < c1; ++c) {
-        const cplx *Eq = E + ((bx[c] & 1) | ((by[c] & 1) << 1)) * (PB + 1) + n;
-        double sc = 1.0;  // 2^-m
-        for (int m = 0; m <= n; ++m) {
-            cfma(out, Eq[-m], W[(int64_t)m * nbox + c] * sc);
-            sc *= 0.5;
-        }
+    __shared__ cplx sw[(PB + 1) * 4 * kM2MParents];
+    __shared__ cplx sE[4 * (PB + 1)];
+    __shared__ int s_range[2];
+    const int p0 = lo + blockIdx.x * kM2MParents;
+    const int p1 = min(p0 + kM2MParents, lo + nb);
+    if (threadIdx.x == 0) {
+        int clo = 0x7fffffff, chi = -1;
+        for (int p = p0; p < p1; ++p)
+            if (!leaf[p]) {
+                clo = min(clo, child_first[p]);
+                chi = max(chi, child_first[p] + nchild[p]);
+            }
+        s_range[0] = clo;
+        s_range[1] = chi;
     }
-    W[(int64_t)n * nbox + b] = out;
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += 256) sE[k] = E[k];
+    __syncthreads();
+    const int clo = s_range[0], nc = s_range[1] - s_range[0];
+    if (nc <= 0) return;
+    for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += 256) {
+        const int m = idx / nc, k = idx - m * nc;
+        sw[m * 4 * kM2MParents + k] = W[(int64_t)m * nbox + clo + k] * ldexp(1.0, -m);
+    }
+    __syncthreads();
+    const int pi = threadIdx.x % kM2MParents;
+    const int p = p0 + pi;
+    if (p >= p1 || leaf[p]) return;
+    const int c0 = child_first[p] - clo, c1 = c0 + nchild[p];
+    for (int n = threadIdx.x / kM2MParents; n <= PB; n += 256 / kM2MParents) {
+        cplx out = mk(0.0, 0.0);
+        for (int c = c0; c < c1; ++c) {
+            const int gc = clo + c;
+            const cplx *Eq = sE + ((bx[gc] & 1) | ((by[gc] & 1) << 1)) * (PB + 1) + n;
+            for (int m = 0; m <= n; ++m) cfma(out, Eq[-m], sw[m * 4 * kM2MParents + c]);
+        }
+        W[(int64_t)n * nbox + p] = out;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -151,77 +193,71 @@ __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int
 // ---------------------------------------------------------------------------------------------
 struct M2LArgs {
     int nbox;
-    const int32_t *tiles, *tile_level, *tile_class, *class_slots;
-    const int32_t *vslot, *vimg_off, *vimg_ent;
-    const cplx *Tfree, *Lfree, *TimgH, *TimgG, *Limg;
+    const int32_t *tiles, *tile_level, *tile_src_off, *tile_src;
+    const int16_t *tile_slot;
+    const uint64_t *tile_mask;
+    const cplx *Tfree, *Lfree;
     const double *loglev;
     const cplx *W;
     cplx *Lam;     // [nloc][PB + 1][nbox]
     int nloc;
 };
 
+// One workgroup per tile of up to 64 same-level target boxes (lane = target), kM2LWaves waves;
+// wave w owns output coefficients [w CH, w CH + CH).  The tile's distinct V sources have their
+// multipoles staged in LDS, kM2LPhase coefficients at a time, and every (target, offset slot)
+// pair reads its source from there.  The operator of a slot is the same for all lanes and is
+// read with scalar loads.
 template <int PB, int CH>
-__global__ __launch_bounds__(64) void k_m2l(M2LArgs a) {
+__global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
     constexpr int NTP = m2l_row(PB);
+    constexpr int NPH = (PB + kM2LPhase) / kM2LPhase;
+    __shared__ cplx sW[kM2LPhase * kM2LMaxSrc];
     const int tile = blockIdx.x;
-    const int n0 = blockIdx.y * CH;
-    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n0 = wave * CH;
+    const int lane = threadIdx.x & 63;
     const int b = a.tiles[tile * kTile + lane];
     const int l = a.tile_level[tile];
-    const int cls = a.tile_class[tile];
     const double ll = a.loglev[l] * kInv4Pi;
+    const int s0 = a.tile_src_off[tile];
+    const int ns = a.tile_src_off[tile + 1] - s0;
+    const uint64_t mask = a.tile_mask[tile];
+    const int16_t *slot = a.tile_slot + (int64_t)tile * kNumSlots * kTile + lane;
     cplx acc[CH];
 #pragma unroll
     for (int k = 0; k < CH; ++k) acc[k] = mk(0.0, 0.0);
     cplx acc0 = mk(0.0, 0.0);
-    const int nslots = a.class_slots[cls * 28];
-    for (int s = 0; s < nslots; ++s) {
-        const int o = a.class_slots[cls * 28 + 1 + s];
-        const int src = (b >= 0) ? a.vslot[(int64_t)o * a.nbox + b] : -1;
-        if (src < 0) continue;
-        const cplx *T = a.Tfree + o * NTP + n0;
 #pragma unroll
-        for (int m = 0; m <= PB; ++m) {
-            const cplx wm = a.W[(int64_t)m * a.nbox + src];
-#pragma unroll
-            for (int k = 0; k < CH; ++k) cfma(acc[k], T[k + m], wm);
+    for (int ph = 0; ph < NPH; ++ph) {
+        const int m0 = ph * kM2LPhase;
+        const int mc = (PB + 1 - m0) < kM2LPhase ? (PB + 1 - m0) : kM2LPhase;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < mc * ns; idx += 64 * m2l_waves(PB)) {
+            const int mm = idx / ns, sj = idx - mm * ns;
+            sW[idx] = a.W[(int64_t)(m0 + mm) * a.nbox + a.tile_src[s0 + sj]];
         }
-        if (n0 == 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), a.W[src]);
-    }
-    if (b < 0) return;
-    cplx accG[CH];
+        __syncthreads();
+        uint64_t rest = mask;
+        while (rest) {
+            const int o = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            const int li = slot[o * kTile];
+            if (li < 0) continue;
+            const cplx *T = a.Tfree + o * NTP + n0 + m0;
+            const cplx *w = sW + li;
 #pragma unroll
-    for (int k = 0; k < CH; ++k) accG[k] = acc[k];
-    cplx accG0 = acc0;
-    for (int e = a.vimg_off[b]; e < a.vimg_off[b + 1]; ++e) {
-        const int code = a.vimg_ent[e];
-        const int src = code >> 5, is = code & 31;
-        const cplx *TH = a.TimgH + ((int64_t)l * kNumImgSlots + is) * NTP + n0;
-        if (a.nloc == 1) {
+            for (int mm = 0; mm < kM2LPhase; ++mm) {
+                if (mm < mc) {
+                    const cplx wm = w[mm * ns];
 #pragma unroll
-            for (int m = 0; m <= PB; ++m) {
-                const cplx wm = conj(a.W[(int64_t)m * a.nbox + src]);
-#pragma unroll
-                for (int k = 0; k < CH; ++k) cfma(acc[k], TH[k + m], wm);
-            }
-        } else {
-            const cplx *TG = a.TimgG + ((int64_t)l * kNumImgSlots + is) * NTP + n0;
-#pragma unroll
-            for (int m = 0; m <= PB; ++m) {
-                const cplx wm = conj(a.W[(int64_t)m * a.nbox + src]);
-#pragma unroll
-                for (int k = 0; k < CH; ++k) {
-                    cfma(acc[k], TH[k + m], wm);
-                    cfma(accG[k], TG[k + m], wm);
+                    for (int k = 0; k < CH; ++k) cfma(acc[k], T[k + mm], wm);
                 }
             }
-        }
-        if (n0 == 0) {
-            const cplx lt = (a.Limg[is] + mk(ll, 0.0)) * conj(a.W[src]);
-            acc0 += lt;
-            accG0 += lt;
+            if (ph == 0 && n0 == 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), w[0]);
         }
     }
+    if (b < 0) return;
     const int64_t stride = (int64_t)(PB + 1) * a.nbox;
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
@@ -230,13 +266,44 @@ __global__ __launch_bounds__(64) void k_m2l(M2LArgs a) {
             cplx v = -acc[k];
             if (n == 0) v += acc0;
             a.Lam[(int64_t)n * a.nbox + b] = v;
-            if (a.nloc == 2) {
-                cplx vg = -accG[k];
-                if (n == 0) vg += accG0;
-                a.Lam[stride + (int64_t)n * a.nbox + b] = vg;
-            }
+            if (a.nloc == 2) a.Lam[stride + (int64_t)n * a.nbox + b] = v;
         }
     }
+}
+
+// Image V entries (target boxes in the two rows nearest y = 0 at each level): log M2L of the image
+// box plus the reaction M2L, one thread per (target box, output coefficient); adds to the locals
+// written by k_m2l.
+template <int PB>
+__global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restrict__ ibox, int nbox, int nloc,
+                                                 const int32_t *__restrict__ level,
+                                                 const int32_t *__restrict__ vimg_off,
+                                                 const int32_t *__restrict__ vimg_ent, const cplx *__restrict__ TH,
+                                                 const cplx *__restrict__ TG, const cplx *__restrict__ Limg,
+                                                 const double *__restrict__ loglev, const cplx *__restrict__ W,
+                                                 cplx *__restrict__ Lam) {
+    constexpr int NTP = m2l_row(PB);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nib * (PB + 1)) return;
+    const int b = ibox[t % nib], n = t / nib;
+    const int l = level[b];
+    const double ll = loglev[l] * kInv4Pi;
+    cplx aH = mk(0.0, 0.0), aG = mk(0.0, 0.0), a0 = mk(0.0, 0.0);
+    for (int e = vimg_off[b]; e < vimg_off[b + 1]; ++e) {
+        const int code = vimg_ent[e];
+        const int src = code >> 5, is = code & 31;
+        const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
+        const cplx *tg = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
+#pragma unroll
+        for (int m = 0; m <= PB; ++m) {
+            const cplx wm = conj(W[(int64_t)m * nbox + src]);
+            cfma(aH, th[m], wm);
+            if (nloc == 2) cfma(aG, tg[m], wm);
+        }
+        if (n == 0) cfma(a0, Limg[is] + mk(ll, 0.0), conj(W[src]));
+    }
+    Lam[(int64_t)n * nbox + b] += a0 - aH;
+    if (nloc == 2) Lam[(int64_t)(PB + 1) * nbox + (int64_t)n * nbox + b] += a0 - aG;
 }
 
 __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nloc, cplx *__restrict__ Lam) {
@@ -317,23 +384,39 @@ __global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, const int32_
 }
 
 // ---------------------------------------------------------------------------------------------
-// L2L: one level of children [lo, lo + nb); one thread per (child, coefficient)
+// L2L: one level of children.  A block takes kL2LChildren consecutive children and stages each
+// child's parent local in LDS (siblings share cache lines).  Thread (child, m) adds
+// 2^-m sum_{n>=m} eps^{n-m}/(n-m)! lambda^P_n to lambda^c_m.
 // ---------------------------------------------------------------------------------------------
+constexpr int kL2LChildren = 64;
+
 template <int PB>
 __global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc, const int32_t *__restrict__ parent,
                                              const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
                                              const cplx *__restrict__ E, cplx *__restrict__ Lam) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * (PB + 1)) return;
-    const int b = lo + t % nb, m = t / nb;
-    const int P = parent[b];
-    const cplx *Eq = E + ((bx[b] & 1) | ((by[b] & 1) << 1)) * (PB + 1) - m;
-    const double sc = ldexp(1.0, -m);
+    __shared__ cplx sl[(PB + 1) * kL2LChildren];
+    __shared__ cplx sE[4 * (PB + 1)];
+    const int c0 = lo + blockIdx.x * kL2LChildren;
+    const int nc = min(kL2LChildren, lo + nb - c0);
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += 256) sE[k] = E[k];
+    const int ci = threadIdx.x % kL2LChildren;
+    const int c = c0 + ci;
+    const int q = ci < nc ? ((bx[c] & 1) | ((by[c] & 1) << 1)) : 0;
     for (int loc = 0; loc < nloc; ++loc) {
         cplx *L = Lam + (int64_t)loc * (PB + 1) * nbox;
-        cplx s = mk(0.0, 0.0);
-        for (int n = m; n <= PB; ++n) cfma(s, Eq[n], L[(int64_t)n * nbox + P]);
-        L[(int64_t)m * nbox + b] += s * sc;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += 256) {
+            const int n = idx / nc, k = idx - n * nc;
+            sl[n * kL2LChildren + k] = L[(int64_t)n * nbox + parent[c0 + k]];
+        }
+        __syncthreads();
+        if (ci >= nc) continue;
+        for (int m = threadIdx.x / kL2LChildren; m <= PB; m += 256 / kL2LChildren) {
+            const cplx *Eq = sE + q * (PB + 1) - m;
+            cplx s = mk(0.0, 0.0);
+            for (int n = m; n <= PB; ++n) cfma(s, Eq[n], sl[n * kL2LChildren + ci]);
+            L[(int64_t)m * nbox + c] += s * ldexp(1.0, -m);
+        }
     }
 }
 
@@ -396,13 +479,15 @@ struct LeafArgs {
     int64_t n;
     int nbox, nloc;
     const double *xs, *ys, *qs;
+    const double2 *xy;
     const int32_t *perm, *leaf_of, *level, *bx, *by, *first, *count;
     const int32_t *uoff, *uent, *woff, *went;
     const cplx *W, *Lam;
     const double *invfact, *fact;
     const cplx *rank1;   // device scalar (real impedance) or null
-    const int32_t *extra_pts;
-    int64_t n_extra;
+    const int32_t *wpts;     // targets whose leaf has a W list
+    int64_t n_wpts;
+    const int32_t *rpts;     // targets whose leaf has image U entries
     double *phi;         // [n][2]
 };
 
@@ -436,20 +521,23 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     }
     // U list, log terms
     double lfree = 0.0, limg = 0.0;
+    const double2 *__restrict__ xy = a.xy;
     for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
         const int code = a.uent[e];
         const int c = code >> 1;
         const int j0 = a.first[c], j1 = j0 + a.count[c];
         if (!(code & 1)) {
             for (int j = j0; j < j1; ++j) {
-                const double dx = x - a.xs[j], dy = y - a.ys[j];
+                const double2 pj = xy[j];
+                const double dx = x - pj.x, dy = y - pj.y;
                 const double r2 = fma(dx, dx, dy * dy);
-                if (r2 > 0.0) lfree = fma(a.qs[j], log(r2), lfree);
+                if (r2 > 0.0) lfree = fma(a.qs[j], log_pos(r2), lfree);
             }
         } else {
             for (int j = j0; j < j1; ++j) {
-                const double dx = x - a.xs[j], dy = y + a.ys[j];
-                limg = fma(a.qs[j], log(fma(dx, dx, dy * dy)), limg);
+                const double2 pj = xy[j];
+                const double dx = x - pj.x, dy = y + pj.y;
+                limg = fma(a.qs[j], log_pos(fma(dx, dx, dy * dy)), limg);
             }
         }
     }
@@ -467,16 +555,17 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     a.phi[2 * o + 1] = phi.im;
 }
 
+// W list for the targets whose leaf has one: multipoles of smaller non-adjacent boxes evaluated
+// at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to phi.
 template <int PB>
-__global__ __launch_bounds__(128) void k_leaf_extra(LeafArgs a) {
+__global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n_extra) return;
-    const int64_t i = a.extra_pts[t];
+    if (t >= a.n_wpts) return;
+    const int64_t i = a.wpts[t];
     const int b = a.leaf_of[i];
     const double x = a.xs[i], y = a.ys[i];
     const cplx z = mk(x, y);
     cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
-    // W list: multipoles of smaller non-adjacent boxes evaluated at the target
     for (int e = a.woff[b]; e < a.woff[b + 1]; ++e) {
         const int code = a.went[e];
         const int d = code >> 1, img = code & 1;
@@ -491,6 +580,7 @@ __global__ __launch_bounds__(128) void k_leaf_extra(LeafArgs a) {
         if (img) w0 = conj(w0);
         cplx u = w0 * clog_(dz);
         cplx pw = tau;
+#pragma unroll
         for (int k = 1; k <= PB; ++k) {
             cplx wk = a.W[(int64_t)k * a.nbox + d];
             if (img) wk = conj(wk);
@@ -511,6 +601,7 @@ __global__ __launch_bounds__(128) void k_leaf_extra(LeafArgs a) {
                 cplx K = reaction_I0_general(Xs, Y, a.Z);
                 cplx F = mk(1.0, 0.0);
                 cplx acc = (pass == 0 ? K : conj(K)) * conj(a.W[d]);
+#pragma unroll
                 for (int n = 1; n <= PB; ++n) {
                     F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
                     K = F * kInv2Pi + zr * K;
@@ -522,32 +613,62 @@ __global__ __launch_bounds__(128) void k_leaf_extra(LeafArgs a) {
             }
         }
     }
-    // reaction part of the U list's image entries
-    double rre = 0.0;
-    cplx rc = mk(0.0, 0.0);
-    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
-        const int code = a.uent[e];
-        if (!(code & 1)) continue;
-        const int c = code >> 1;
-        const int j0 = a.first[c], j1 = j0 + a.count[c];
-        for (int j = j0; j < j1; ++j) {
-            const double dx = x - a.xs[j], dy = y + a.ys[j];
-            const double qj = a.qs[j];
-            const cplx I = reaction_I0_near(dx, dy, a.Z);
-            if (a.nloc == 1) {
-                rre += qj * I.re;
-            } else {
-                rc += qj * (I + reaction_I0_near(-dx, dy, a.Z));
-            }
-        }
-    }
     const int64_t o = a.perm[i];
     if (a.nloc == 1) {
-        a.phi[2 * o] += 2.0 * (H.re + rre);
+        a.phi[2 * o] += 2.0 * H.re;
     } else {
-        const cplx v = H + conj(G) + rc;
+        const cplx v = H + conj(G);
         a.phi[2 * o] += v.re;
         a.phi[2 * o + 1] += v.im;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Reaction part of the near field: sum over the image sources of a leaf's U list of
+// q_j [I_0(X, Y) + I_0(-X, Y)], X = x_i - x_j, Y = y_i + y_j (eq. (reactdecomposition)); for a
+// real impedance only 2 Re I_0(X, Y) (the rest is the surface term).  One wave per leaf that
+// touches y = 0; lanes take image sources, a fixed-order butterfly sums them.  Adds to phi.
+__global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
+    const int i = a.rpts[blockIdx.x];
+    const int b = a.leaf_of[i];
+    const int lane = threadIdx.x;
+    {
+        const double x = a.xs[i], y = a.ys[i];
+        double sr = 0.0, si = 0.0;
+        for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+            const int code = a.uent[e];
+            if (!(code & 1)) continue;
+            const int c = code >> 1;
+            const int j1 = a.first[c] + a.count[c];
+            for (int j = a.first[c] + lane; j < j1; j += 64) {
+                const double dx = x - a.xs[j], dy = y + a.ys[j];
+                const double qj = a.qs[j];
+                const cplx I = reaction_I0_near(dx, dy, a.Z);
+                if (a.nloc == 1) {
+                    sr += qj * I.re;
+                } else {
+                    const cplx v = I + reaction_I0_near(-dx, dy, a.Z);
+                    sr += qj * v.re;
+                    si += qj * v.im;
+                }
+            }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) {
+            const int64_t o = a.perm[i];
+            if (a.nloc == 1) {
+                a.phi[2 * o] += 2.0 * sr;
+            } else {
+                a.phi[2 * o] += sr;
+                a.phi[2 * o + 1] += si;
+            }
+        }
     }
 }
 
@@ -568,8 +689,8 @@ __global__ __launch_bounds__(256) void k_direct(int64_t ns, const double *__rest
         const double dy = y - sy[j], dyi = y + sy[j];
         const double r2 = dx * dx + dy * dy;
         const double qj = q[j];
-        if (r2 > 0.0) lfree += qj * log(r2);
-        limg += qj * log(dx * dx + dyi * dyi);
+        if (r2 > 0.0) lfree += qj * log_pos(r2);
+        limg += qj * log_pos(dx * dx + dyi * dyi);
         rc += qj * (reaction_I0_near(dx, dyi, Z) + reaction_I0_near(-dx, dyi, Z));
     }
     const cplx v = mk(kInv4Pi * (limg - lfree), 0.0) + rc;
@@ -684,42 +805,71 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
         }
         vimg_off[b + 1] = (int32_t)vimg_ent.size();
     }
-    FMMHP_CHECK(to_dev(A, &S.vslot, vslot, "vslot", s));
     FMMHP_CHECK(to_dev(A, &S.vimg_off, vimg_off, "vimg_off", s));
+    {
+        std::vector<int32_t> ib;
+        for (int b = 0; b < nbox; ++b)
+            if (vimg_off[b + 1] > vimg_off[b]) ib.push_back(b);
+        S.nibox = (int)ib.size();
+        FMMHP_CHECK(to_dev(A, &S.ibox, ib, "image V boxes", s));
+    }
     FMMHP_CHECK(to_dev(A, &S.vimg_ent, vimg_ent, "vimg_ent", s));
 
-    // class slot lists
-    std::vector<int32_t> cs(4 * 28, 0);
-    for (int cls = 0; cls < 4; ++cls) {
-        const int px = cls & 1, py = cls >> 1;
-        int k = 0;
-        for (int dy = -2 - py; dy <= 3 - py; ++dy)
-            for (int dx = -2 - px; dx <= 3 - px; ++dx) {
-                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-                cs[cls * 28 + 1 + k++] = slot_of(dx, dy);
+    // M2L tiles: up to kTile consecutive boxes of one level whose distinct upper V sources fit the
+    // LDS staging buffer (a tile that does not fit is split in halves).
+    std::vector<int32_t> tiles, tlev, tsoff(1, 0), tsrc;
+    std::vector<int16_t> tslot;
+    std::vector<uint64_t> tmask;
+    {
+        std::vector<std::pair<int, int>> todo;  // [lo, hi) box ranges
+        for (int l = 2; l <= T.depth; ++l)
+            for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; b += kTile)
+                todo.push_back({b, std::min(b + kTile, T.lev_start[l + 1])});
+        std::vector<int32_t> uniq;
+        for (size_t ti = 0; ti < todo.size(); ++ti) {
+            const int lo = todo[ti].first, hi = todo[ti].second;
+            uniq.clear();
+            for (int b = lo; b < hi; ++b)
+                for (int o = 0; o < kNumSlots; ++o) {
+                    const int c = vslot[(size_t)o * nbox + b];
+                    if (c >= 0) uniq.push_back(c);
+                }
+            std::sort(uniq.begin(), uniq.end());
+            uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+            if ((int)uniq.size() > kM2LMaxSrc) {
+                const int mid = lo + (hi - lo) / 2;
+                todo.push_back({lo, mid});
+                todo.push_back({mid, hi});
+                continue;
             }
-        cs[cls * 28] = k;
-    }
-    FMMHP_CHECK(to_dev(A, &S.class_slots, cs, "class slots", s));
-
-    // tiles: levels >= 2, grouped by class, box order within a class
-    std::vector<int32_t> tiles, tlev, tcls;
-    for (int l = 2; l <= T.depth; ++l) {
-        std::vector<int32_t> byc[4];
-        for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b) byc[(bx[b] & 1) | ((by[b] & 1) << 1)].push_back(b);
-        for (int cls = 0; cls < 4; ++cls) {
-            for (size_t k = 0; k < byc[cls].size(); k += kTile) {
-                for (int t = 0; t < kTile; ++t)
-                    tiles.push_back(k + t < byc[cls].size() ? byc[cls][k + t] : -1);
-                tlev.push_back(l);
-                tcls.push_back(cls);
+            const size_t t0 = tslot.size();
+            tslot.resize(t0 + (size_t)kNumSlots * kTile, (int16_t)-1);
+            uint64_t msk = 0;
+            for (int lane = 0; lane < kTile; ++lane) {
+                const int b = lo + lane;
+                tiles.push_back(b < hi ? b : -1);
+                if (b >= hi) continue;
+                for (int o = 0; o < kNumSlots; ++o) {
+                    const int c = vslot[(size_t)o * nbox + b];
+                    if (c < 0) continue;
+                    const int li = (int)(std::lower_bound(uniq.begin(), uniq.end(), c) - uniq.begin());
+                    tslot[t0 + (size_t)o * kTile + lane] = (int16_t)li;
+                    msk |= 1ull << o;
+                }
             }
+            tlev.push_back(level[lo]);
+            tmask.push_back(msk);
+            tsrc.insert(tsrc.end(), uniq.begin(), uniq.end());
+            tsoff.push_back((int32_t)tsrc.size());
         }
     }
     S.ntiles = (int)tlev.size();
     FMMHP_CHECK(to_dev(A, &S.tiles, tiles, "tiles", s));
     FMMHP_CHECK(to_dev(A, &S.tile_level, tlev, "tile levels", s));
-    FMMHP_CHECK(to_dev(A, &S.tile_class, tcls, "tile classes", s));
+    FMMHP_CHECK(to_dev(A, &S.tile_src_off, tsoff, "tile source offsets", s));
+    FMMHP_CHECK(to_dev(A, &S.tile_src, tsrc, "tile sources", s));
+    FMMHP_CHECK(to_dev(A, &S.tile_slot, tslot, "tile slots", s));
+    FMMHP_CHECK(to_dev(A, &S.tile_mask, tmask, "tile masks", s));
 
     // X-list targets, leaves
     std::vector<int32_t> xb, lv;
@@ -731,18 +881,22 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     FMMHP_CHECK(to_dev(A, &S.xbox, xb, "xbox", s));
     FMMHP_CHECK(to_dev(A, &S.leaves, lv, "leaves", s));
     {
-        std::vector<int32_t> woff, first, ex;
+        std::vector<int32_t> woff, first, wp, rl;
         FMMHP_CHECK(to_host(woff, T.off[2], (size_t)nbox + 1, s));
         FMMHP_CHECK(to_host(first, T.first, (size_t)nbox, s));
         FMMHP_HIP(hipStreamSynchronize(s));
         for (int b : lv) {
-            bool need = woff[b + 1] > woff[b];
-            for (int e = uoff[b]; e < uoff[b + 1] && !need; ++e) need = (uent[e] & 1) != 0;
-            if (need)
-                for (int j = first[b]; j < first[b] + cnt[b]; ++j) ex.push_back(j);
+            if (woff[b + 1] > woff[b])
+                for (int j = first[b]; j < first[b] + cnt[b]; ++j) wp.push_back(j);
+            bool img = false;
+            for (int e = uoff[b]; e < uoff[b + 1] && !img; ++e) img = (uent[e] & 1) != 0;
+            if (img)
+                for (int j = first[b]; j < first[b] + cnt[b]; ++j) rl.push_back(j);
         }
-        S.n_extra = (int64_t)ex.size();
-        FMMHP_CHECK(to_dev(A, &S.extra_pts, ex, "extra points", s));
+        S.n_wpts = (int64_t)wp.size();
+        S.n_rpts = (int64_t)rl.size();
+        FMMHP_CHECK(to_dev(A, &S.wpts, wp, "W-list targets", s));
+        FMMHP_CHECK(to_dev(A, &S.rpts, rl, "near-axis targets", s));
     }
 
     // tables
@@ -846,6 +1000,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     FMMHP_CHECK(A.alloc_n(&S.W, (size_t)(PB + 1) * nbox, "multipoles"));
     FMMHP_CHECK(A.alloc_n(&S.Lam, (size_t)S.nloc * (PB + 1) * nbox, "locals"));
     FMMHP_CHECK(A.alloc_n(&S.qs, (size_t)T.n, "sorted charges"));
+    FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
+    hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
+    FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(A.alloc_n(&S.red, 1025, "reduction"));
     FMMHP_HIP(hipStreamSynchronize(s));
     return FMMHP_OK;
@@ -887,8 +1044,8 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     for (int l = T.depth - 1; l >= 2; --l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk((int64_t)nb * (PB + 1), 256)), dim3(256), 0, s,
-                               lo, nb, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents)), dim3(256), 0, s, lo, nb,
+                               nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
@@ -901,11 +1058,14 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     }
     if (S.ntiles > 0) {
         constexpr int CH = kM2LChunk;
-        M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_class, S.class_slots, S.vslot, S.vimg_off, S.vimg_ent,
-                   S.Tfree, S.Lfree, S.TimgH,      S.TimgG,      S.Limg,        S.loglev, S.W,      S.Lam,
-                   S.nloc};
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles, (PB + 1 + CH - 1) / CH), dim3(64), 0, s,
-                           ma);
+        static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
+        M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
+                   S.Tfree, S.Lfree, S.loglev,     S.W,            S.Lam,      S.nloc};
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles), dim3(64 * m2l_waves(PB)), 0, s, ma);
+        if (S.nibox > 0)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)S.nibox * (PB + 1), 256)),
+                               dim3(256), 0, s, S.nibox, S.ibox, nbox, S.nloc, T.level, S.vimg_off, S.vimg_ent,
+                               S.TimgH, S.TimgG, S.Limg, S.loglev, S.W, S.Lam);
         FMMHP_HIP(hipGetLastError());
     }
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
@@ -920,8 +1080,8 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     for (int l = 3; l <= T.depth; ++l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk((int64_t)nb * (PB + 1), 256)), dim3(256), 0, s,
-                               lo, nb, nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren)), dim3(256), 0, s, lo, nb,
+                               nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
@@ -934,12 +1094,14 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
         r1 = S.red + np;
     }
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
-    LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   T.perm,
+    LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   S.xy,  T.perm,
                 T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
-                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.extra_pts, S.n_extra, phi};
+                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.wpts,   S.n_wpts, S.rpts,
+                phi};
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
-    if (S.n_extra > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_extra<PB>), dim3(nblk(S.n_extra, 128)), dim3(128), 0, s, la);
+    if (S.n_rpts > 0) hipLaunchKernelGGL(k_near_reaction, dim3((unsigned)S.n_rpts), dim3(64), 0, s, la);
+    if (S.n_wpts > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
     mk_.commit(S);

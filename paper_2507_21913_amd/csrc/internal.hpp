@@ -16,6 +16,11 @@ constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
 constexpr int kM2LChunk = 8;      // output coefficients per M2L wave
+constexpr int kM2LPhase = 16;     // multipole coefficients staged in LDS per phase
+constexpr int kM2LMaxSrc = 200;   // distinct V sources per tile (LDS: 16 * 200 * 16 B)
+
+// Waves per M2L workgroup: one per chunk of kM2LChunk output coefficients.
+__host__ __device__ constexpr int m2l_waves(int PB) { return (PB + kM2LChunk) / kM2LChunk; }
 
 // M2L operator rows are zero-padded so that every chunk of kM2LChunk outputs reads in bounds:
 // ceil((PB + 1) / kM2LChunk) * kM2LChunk + PB entries.
@@ -84,20 +89,26 @@ struct Sched {
     cplx Z{0, 0};
     int nloc = 1;                   // 1: H only (real impedance); 2: H and G
     // M2L
-    int32_t *vslot = nullptr;       // [kNumSlots][nbox] upper V source per offset slot, -1 if none
     int32_t *vimg_off = nullptr;    // [nbox + 1]  image V entries per box
     int32_t *vimg_ent = nullptr;    // (src << 5) | img_slot
+    int nibox = 0;
+    int32_t *ibox = nullptr;        // boxes with image V entries
     int ntiles = 0;
     int32_t *tiles = nullptr;       // [ntiles][kTile] box ids (-1 padding)
     int32_t *tile_level = nullptr;  // [ntiles]
-    int32_t *tile_class = nullptr;  // [ntiles]
-    int32_t *class_slots = nullptr; // [4][28]: count, then slot ids
+    int32_t *tile_src_off = nullptr;  // [ntiles + 1] distinct upper V sources of each tile
+    int32_t *tile_src = nullptr;
+    int16_t *tile_slot = nullptr;   // [ntiles][kNumSlots][kTile] index into the tile's sources, -1
+    uint64_t *tile_mask = nullptr;  // [ntiles] slots used by any lane of the tile
     // X list targets
     int nxbox = 0;
     int32_t *xbox = nullptr;
     int32_t *leaves = nullptr;      // [nleaf]
-    int64_t n_extra = 0;
-    int32_t *extra_pts = nullptr;   // sorted points whose leaf has W entries or image U entries
+    int64_t n_wpts = 0;
+    int32_t *wpts = nullptr;        // sorted points whose leaf has a W list
+    int64_t n_rpts = 0;
+    int32_t *rpts = nullptr;        // sorted points whose leaf has image U entries
+    double2 *xy = nullptr;          // [n] sorted (x, y) pairs
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)

@@ -28,6 +28,54 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kInv2Pi = 0.15915494309189533577;
 constexpr double kInv4Pi = 0.07957747154594766788;
 constexpr double kEulerGamma = 0.57721566490153286061;
+constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 with its low 32 bits cleared
+constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+
+// Natural logarithm of a positive, finite, normal double.  x = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, and atanh s = s sum_k s^(2k) / (2k + 1)
+// truncated after k = 10 (the first omitted term is below 1e-17 relative).  e ln 2 is added in two
+// parts so that e * kLn2Hi is exact.  Used where a log of a squared distance is needed per pair.
+// 1 / (m + 1) comes from the hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double log_pos(double x) {
+    int e;
+    double m = frexp(x, &e);  // m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double num = m - 1.0, den = m + 1.0;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const double s = num * r;
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double s_2 = 2.0 * s;
+    const double lm = fma(s_2, s2 * p, s_2);
+    const double ed = (double)e;
+    return fma(ed, kLn2Hi, fma(ed, kLn2Lo, lm));
+}
+
+// 1 / (k k!) for k = 1..32: coefficients of the power series of Ei.
+struct EiSeries {
+    double c[33];
+    constexpr EiSeries() : c() {
+        double f = 1.0;
+        for (int k = 1; k <= 32; ++k) {
+            f *= k;
+            c[k] = 1.0 / (k * f);
+        }
+    }
+};
 
 __host__ __device__ inline cplx reaction_I0(double x, double y, cplx Z) {
     const cplx P = Z * mk(y, -x);
