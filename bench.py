@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="targets of the oracle's direct sum timed for the CPU baseline")
     ap.add_argument("--quiet-extra", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -97,6 +99,13 @@ def main():
     phases, nev = plan.phase_times()
     plan.set_timing(False)
     phase_avg = {k: v / max(1, nev) for k, v in phases.items()}
+
+    if a.calibrate_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # accuracy against the stored oracle sample (direct sum at 256 targets x all sources)
     rel = None

@@ -1,0 +1,110 @@
+"""GPU parity at the full workload sizes (1,048,576 and 4,194,304 points), in the launch
+configuration bench.py times (p = 30, leaf 40):
+
+* tree and interaction lists bit-exact against the reference build;
+* potentials against the oracle's direct sum at 256 stored sample targets (all sources), written
+  by tests/golden/make_golden.py: rel-l2 <= 1e-10;
+* for a real impedance, the imaginary part at ALL targets against its exact O(N) closed form;
+* error vs p decreasing geometrically (p = 10, 20, 30).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2507_21913_amd as F
+import workloads
+from oracle import direct as D
+from oracle import tree as T
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+from make_golden import load  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _compare_trees(got, ref):
+    assert got["nbox"] == ref["nbox"]
+    for k in ("level", "bx", "by", "first", "count", "parent", "leaf", "child_first", "nchild", "perm"):
+        assert np.array_equal(got[k], ref[k]), k
+    for name in "UVWX":
+        assert np.array_equal(got[name + "_off"], ref[name + "_off"]), name
+        assert np.array_equal(got[name + "_ent"], ref[name + "_ent"]), name
+
+
+@pytest.fixture(scope="module")
+def uniform():
+    w = workloads.uniform_1m(seed=1)
+    return w, _t(w.x), _t(w.y), _t(w.q[0])
+
+
+def test_uniform_1m_tree_bitexact(uniform):
+    w, x, y, _ = uniform
+    plan = F.HalfPlaneFMM(x, y, 1.0, p=30, leaf_size=40)
+    got = plan.export_tree()
+    ref = T.build(w.x, w.y, 40)
+    _compare_trees(got, ref)
+
+
+def test_uniform_1m_p30_vs_oracle_sample_and_exact_imag(uniform):
+    w, x, y, q = uniform
+    plan = F.HalfPlaneFMM(x, y, 1.0, p=30, leaf_size=40)
+    phi = plan(q).cpu().numpy()
+    idx, ref = load("uniform_1m")
+    err = D.rel_l2(phi[idx], ref)
+    im = D.imag_part_real_impedance(w.x, w.y, w.q[0], 1.0)
+    err_im = float(np.max(np.abs(phi.imag - im)) / np.max(np.abs(im)))
+    print(f"uniform_1m p=30: rel-l2 at 256 targets {err:.3e}; Im part max rel {err_im:.3e}", flush=True)
+    assert err < 1e-10
+    assert err_im < 1e-12
+
+
+def test_uniform_1m_error_vs_p(uniform):
+    w, x, y, q = uniform
+    idx, ref = load("uniform_1m")
+    errs = {}
+    for p in (10, 20, 30):
+        plan = F.HalfPlaneFMM(x, y, 1.0, p=p, leaf_size=40)
+        errs[p] = D.rel_l2(plan(q).cpu().numpy()[idx], ref)
+        plan.close()
+    print("uniform_1m rel-l2 vs p:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs[20] < 0.01 * errs[10]
+    assert errs[30] < 1e-10
+
+
+def test_curve_4m_tree_bitexact_and_potential():
+    w = workloads.curve_4m(seed=1)
+    x, y, q = _t(w.x), _t(w.y), _t(w.q[0])
+    plan = F.HalfPlaneFMM(x, y, w.impedance, p=30, leaf_size=40)
+    info = plan.info()
+    print(f"curve_4m: depth {info['depth']} boxes {info['nbox']} lists {info['list_len']}", flush=True)
+    phi = plan(q).cpu().numpy()
+    idx, ref = load("curve_4m")
+    err = D.rel_l2(phi[idx], ref)
+    print(f"curve_4m p=30 impedance {w.impedance}: rel-l2 at 256 targets {err:.3e}", flush=True)
+    assert err < 1e-10
+    got = plan.export_tree()
+    plan.close()
+    del x, y, q
+    ref_tree = T.build(w.x, w.y, 40)
+    _compare_trees(got, ref_tree)
+
+
+def test_diff_1m_potential():
+    w = workloads.diff_1m(seed=1)
+    plan = F.HalfPlaneFMM(_t(w.x), _t(w.y), w.impedance, p=30, leaf_size=40)
+    phi = plan(_t(w.q[0])).cpu().numpy()
+    idx, ref = load("diff_1m")
+    err = D.rel_l2(phi[idx], ref)
+    im = D.imag_part_real_impedance(w.x, w.y, w.q[0], 2.0)
+    err_im = float(np.max(np.abs(phi.imag - im)) / np.max(np.abs(im)))
+    print(f"diff_1m p=30 impedance 2: rel-l2 {err:.3e}, Im max rel {err_im:.3e}", flush=True)
+    assert err < 1e-10
+    assert err_im < 1e-12
