@@ -6,7 +6,11 @@ the surface term) over the 1,048,576-point uniform workload (x ~ U[0,1], y ~ U[1
 charges U[-1,1], impedance 1.0) with the plan (tree, lists, tables) already built and all
 inputs resident in device memory.  Prints ONE JSON line.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--p 30] [--leaf 40]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--tol 1e-10 | --p P --leaf L]
+
+By default the truncation order p and the leaf size come from the library's autotuner
+(fmmhp_tune) for a target relative l2 error of 1e-10, measured against the GPU direct sum at 256
+targets; the bench output is then checked against the CPU oracle's stored direct-sum sample.
 """
 from __future__ import annotations
 
@@ -29,8 +33,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--p", type=int, default=30)
-    ap.add_argument("--leaf", type=int, default=40)
+    ap.add_argument("--p", type=int, default=0, help="truncation order (0: autotune for --tol)")
+    ap.add_argument("--leaf", type=int, default=0, help="leaf size (0: autotune, or 40 with --p)")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-p30", action="store_true", help="skip the extra p=30 measurement")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128,
@@ -74,9 +80,19 @@ def main():
     y = torch.as_tensor(w.y, device=dev)
     q = torch.as_tensor(w.q[0], device=dev)
 
+    tuned = None
+    p_use, leaf_use = a.p, a.leaf
+    if a.p == 0:
+        t0 = time.perf_counter()
+        tuned = F.tune(x, y, q, w.impedance, tol=a.tol)
+        tuned["tune_s"] = time.perf_counter() - t0
+        p_use, leaf_use = tuned["p"], tuned["leaf_size"]
+    elif a.leaf == 0:
+        leaf_use = 40
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = F.HalfPlaneFMM(x, y, w.impedance, p=a.p, leaf_size=a.leaf)
+    plan = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
@@ -109,6 +125,7 @@ def main():
 
     # accuracy against the stored oracle sample (direct sum at 256 targets x all sources)
     rel = None
+    g = None
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     try:
         from make_golden import load
@@ -123,19 +140,19 @@ def main():
     # roofline of the dominant kernel, from algorithmic work per launch / measured launch time
     P1 = info["p"] + 1
     m2l_flops = 8.0 * P1 * P1 * (info["m2l_pairs"][0] + info["m2l_pairs"][1])
-    dom = max(("m2l", "leaf"), key=lambda k: phase_avg[k])
+    dom = max(("m2l", "near"), key=lambda k: phase_avg[k])
     if dom == "m2l":
         achieved = m2l_flops / (phase_avg["m2l"] * 1e-3) / 1e12
         roof = {"kernel": "k_m2l", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                 "flops_per_launch": m2l_flops}
     else:
-        # near field: a pair costs one float64 log plus 8 flops (counted as 28 flops,
-        # the log taken at 20 float64 operations); L2P and M2P are added at 8 (p+1) per target
+        # near field (k_near): 27 float64 flops per pair, counted from its compiled inner loop
+        # (12 FMA incl. the table-assisted log, 2 add, 1 mul); image-source pairs counted alike
         pairs = info["p2p_pairs"][0] + info["p2p_pairs"][1]
-        fl = 28.0 * pairs + 8.0 * P1 * info["n"]
-        achieved = fl / (phase_avg["leaf"] * 1e-3) / 1e12
-        roof = {"kernel": "k_leaf", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+        fl = 27.0 * pairs
+        achieved = fl / (phase_avg["near"] * 1e-3) / 1e12
+        roof = {"kernel": "k_near", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                 "flops_per_launch": fl}
 
@@ -154,13 +171,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": "uniform_1m: N=1,048,576 uniform in [0,1]x[1e-3,1.001], charges U[-1,1], "
                                "impedance 1.0, sources=targets, 1 charge vector",
-                   "n": w.n, "p": info["p"], "leaf_size": a.leaf, "impedance": 1.0},
+                   "n": w.n, "p": info["p"], "leaf_size": leaf_use, "impedance": 1.0,
+                   "tolerance": a.tol if tuned else None},
         "roofline": roof,
     }
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, a.cpu_sample)
     if not a.quiet_extra:
         res["rel_l2_vs_oracle_sample"] = rel
+        if tuned:
+            res["autotune"] = tuned
+        if not a.no_p30 and not (p_use == 30 and leaf_use == 40):
+            plan30 = F.HalfPlaneFMM(x, y, w.impedance, p=30, leaf_size=40)
+            for _ in range(2):
+                plan30(q, out=out)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(10):
+                plan30(q, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms30 = e0.elapsed_time(e1) / 10
+            rel30 = None
+            if g is not None:
+                rel30 = float(np.linalg.norm(out.cpu().numpy()[g[0]] - g[1]) / np.linalg.norm(g[1]))
+            res["p30_leaf40"] = {"mpts_s": w.n / (ms30 * 1e-3) / 1e6, "ms_per_step": ms30,
+                                 "rel_l2_vs_oracle_sample": rel30}
+            plan30.close()
         res["plan_ms"] = plan_ms
         res["plan_plus_eval_mpts_s"] = w.n / ((plan_ms + ms) * 1e-3) / 1e6
         res["phase_ms"] = {k: round(v, 5) for k, v in phase_avg.items()}

@@ -93,8 +93,9 @@ enum {
     FMMHP_PHASE_P2L = 3,    /* X list */
     FMMHP_PHASE_L2L = 4,    /* downward pass, one launch per level */
     FMMHP_PHASE_SURF = 5,   /* surface term sum (real impedance) */
-    FMMHP_PHASE_LEAF = 6,   /* L2P, W list, U list and output, one launch */
-    FMMHP_NUM_PHASES = 7
+    FMMHP_PHASE_LEAF = 6,   /* L2P, W list and output (after the near field has joined) */
+    FMMHP_PHASE_NEAR = 7,   /* near field (U list), on the plan's side stream, concurrent with 1-5 */
+    FMMHP_NUM_PHASES = 8
 };
 
 /* Build a plan: the adaptive quadtree over the points and their images, interaction lists and
@@ -185,6 +186,30 @@ fmmhp_status fmmhp_direct_eval(int64_t n_src, const double *src_x, const double 
 fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *y, int nmax,
                                       double lambda_re, double lambda_im, double *out,
                                       hipStream_t stream);
+
+/* Autotuner: choose the truncation order p and the leaf size for a point set, an impedance and an
+ * accuracy target (p from tolerance, leaf size from measured eval time).
+ *
+ * The error of a candidate is measured, not modelled: the FMM potential is compared with the
+ * GPU direct sum (fmmhp_direct_eval) at `sample` fixed targets (indices floor(k n / sample)),
+ * for the given charges.  For each candidate leaf size the smallest p in {5, 10, ..., 40} whose
+ * relative l2 error is at most tol is kept, and the (p, leaf) pair with the fastest median
+ * fmmhp_eval time (n_vec vectors) wins.
+ *
+ *   n, x, y, lambda_re, lambda_im   as for fmmhp_plan_create ([device] x, y)
+ *   q            [device] [n] charges used for the trial evaluations
+ *   tol          target relative l2 error, > 0
+ *   n_vec        vectors per timed eval (>= 1)
+ *   leaf_sizes   [host] candidate leaf sizes (n_leaf entries), or NULL for {24, 32, 40, 48, 64, 96}
+ *   sample       targets in the accuracy sample, 1..n (0 selects min(n, 256))
+ *   best         [host] receives the chosen options (p, leaf_size; max_level 0, flags 0)
+ *   err, eval_ms [host, may be NULL] the chosen pair's measured error and median eval time
+ * Returns FMMHP_EUNSUPPORTED if no candidate reaches tol at p = 40.  Synchronises the stream;
+ * allocates and frees its own temporaries. */
+fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, const double *q,
+                        double lambda_re, double lambda_im, double tol, int n_vec,
+                        const int *leaf_sizes, int n_leaf, int sample, fmmhp_opts *best,
+                        double *err, double *eval_ms, hipStream_t stream);
 
 const char *fmmhp_status_string(fmmhp_status s);
 const char *fmmhp_last_error_message(void);

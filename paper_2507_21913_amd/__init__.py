@@ -50,7 +50,7 @@ class PlanStats(ctypes.Structure):
                 ("p2p_pairs", ctypes.c_int64 * 2), ("m2l_pairs", ctypes.c_int64 * 2)]
 
 
-PHASES = ("p2m", "m2m", "m2l", "p2l", "l2l", "surface", "leaf")
+PHASES = ("p2m", "m2m", "m2l", "p2l", "l2l", "surface", "leaf", "near")
 
 
 _lib = None
@@ -70,6 +70,8 @@ _SIGNATURES = {
     "fmmhp_reaction_integrals": [_I64, _P, _P, _INT, _D, _D, _P, _P],
     "fmmhp_plan_set_timing": [_P, _INT],
     "fmmhp_plan_phase_times": [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)],
+    "fmmhp_tune": [_I64, _P, _P, _P, _D, _D, _D, _INT, _P, _INT, _INT, ctypes.POINTER(Opts),
+                   ctypes.POINTER(_D), ctypes.POINTER(_D), _P],
     "fmmhp_status_string": [_INT],
     "fmmhp_last_error_message": [],
 }
@@ -183,6 +185,33 @@ def fmmhp_direct_eval(n_src, sx, sy, n_vec, q, n_tgt, tx, ty, lambda_re, lambda_
 def fmmhp_reaction_integrals(m, x, y, nmax, lambda_re, lambda_im, out, stream):
     _check("fmmhp_reaction_integrals",
            lib().fmmhp_reaction_integrals(m, x, y, nmax, lambda_re, lambda_im, out, stream))
+
+
+def fmmhp_tune(n, x_ptr, y_ptr, q_ptr, lambda_re, lambda_im, tol, n_vec, leaf_sizes, sample,
+               stream):
+    best = Opts()
+    err = _D()
+    ms = _D()
+    if leaf_sizes:
+        arr = (_INT * len(leaf_sizes))(*leaf_sizes)
+        la, nl = ctypes.cast(arr, _P), len(leaf_sizes)
+    else:
+        la, nl = None, 0
+    _check("fmmhp_tune", lib().fmmhp_tune(n, x_ptr, y_ptr, q_ptr, lambda_re, lambda_im, tol, n_vec,
+                                          la, nl, sample, ctypes.byref(best), ctypes.byref(err),
+                                          ctypes.byref(ms), stream))
+    return {"p": best.p, "leaf_size": best.leaf_size, "rel_l2": err.value, "eval_ms": ms.value}
+
+
+def tune(x, y, q, impedance, tol=1e-10, n_vec=1, leaf_sizes=None, sample=0) -> dict:
+    """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error."""
+    x = _dev_f64(x, "x")
+    y = _dev_f64(y, "y")
+    q = _dev_f64(q, "q")
+    lr, li = _split_impedance(impedance)
+    with torch.cuda.device(x.device):
+        return fmmhp_tune(x.shape[0], x.data_ptr(), y.data_ptr(), q.data_ptr(), lr, li, tol, n_vec,
+                          leaf_sizes, sample, _stream())
 
 
 # --- tensor-level helpers --------------------------------------------------------------------
@@ -315,4 +344,4 @@ __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functi
            "FMMHPError", "Opts", "PlanStats", "fmmhp_plan_create", "fmmhp_eval",
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
-           "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES"]
+           "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune"]

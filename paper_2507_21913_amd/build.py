@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmmhp.so")
-SOURCES = ["api.hip", "tree.hip", "fmm.hip"]
+SOURCES = ["api.hip", "tree.hip", "fmm.hip", "tune.hip"]
 HEADERS = ["cplx.hpp", "special.hpp", "internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -133,6 +133,9 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
     }
     if (st != FMMHP_OK) {
         (void)hipStreamSynchronize(stream);
+        if (p->sched.ev_fork) (void)hipEventDestroy(p->sched.ev_fork);
+        if (p->sched.ev_join) (void)hipEventDestroy(p->sched.ev_join);
+        if (p->sched.side) (void)hipStreamDestroy(p->sched.side);
         p->arena.release();
         p->magic = kDead;
         delete p;
@@ -258,6 +261,9 @@ fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
         delete plan->sched.events;
         plan->sched.events = nullptr;
     }
+    if (plan->sched.ev_fork) (void)hipEventDestroy(plan->sched.ev_fork);
+    if (plan->sched.ev_join) (void)hipEventDestroy(plan->sched.ev_join);
+    if (plan->sched.side) (void)hipStreamDestroy(plan->sched.side);
     plan->arena.release();
     plan->magic = kDead;
     delete plan;

@@ -488,9 +488,48 @@ struct LeafArgs {
     const int32_t *wpts;     // targets whose leaf has a W list
     int64_t n_wpts;
     const int32_t *rpts;     // targets whose leaf has image U entries
+    const double2 *logtab;   // [kLogTable] (1/c_k, -log(1/c_k))
+    double2 *near;           // [n] near-field sums per sorted target
     double *phi;         // [n][2]
 };
 
+// Near field, log terms of the U list: one thread per target (sorted order), writes near[i].
+__global__ __launch_bounds__(256) void k_near(LeafArgs a) {
+    __shared__ double2 s_logtab[kLogTable];
+    if (threadIdx.x < kLogTable) s_logtab[threadIdx.x] = a.logtab[threadIdx.x];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int b = a.leaf_of[i];
+    const double2 pi = a.xy[i];
+    const double x = pi.x, y = pi.y;
+    double lfree = 0.0, limg = 0.0;
+    const double2 *__restrict__ xy = a.xy;
+    const double2 *__restrict__ tab = s_logtab;
+    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+        const int code = a.uent[e];
+        const int c = code >> 1;
+        const int j0 = a.first[c], j1 = j0 + a.count[c];
+        if (!(code & 1)) {
+            for (int j = j0; j < j1; ++j) {
+                const double2 pj = xy[j];
+                const double dx = x - pj.x, dy = y - pj.y;
+                const double r2 = fma(dx, dx, dy * dy);
+                const double qm = r2 > 0.0 ? a.qs[j] : 0.0;  // skip the self pair (eq. (1.2))
+                lfree = fma(qm, log_tab(r2 > 0.0 ? r2 : 1.0, tab), lfree);
+            }
+        } else {
+            for (int j = j0; j < j1; ++j) {
+                const double2 pj = xy[j];
+                const double dx = x - pj.x, dy = y + pj.y;
+                limg = fma(a.qs[j], log_tab(fma(dx, dx, dy * dy), tab), limg);
+            }
+        }
+    }
+    a.near[i] = make_double2(kInv4Pi * (limg - lfree), 0.0);
+}
+
+// L2P of the local(s), plus the near-field sums and the surface term; writes phi in caller order.
 template <int PB>
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -505,6 +544,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
     {
         const cplx *L = a.Lam + b;
+#pragma unroll
         for (int n = PB; n >= 0; --n) {
             cplx t = L[(int64_t)n * a.nbox] * a.invfact[n];
             cfma(t, H, zeta);
@@ -512,6 +552,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
         }
         if (a.nloc == 2) {
             const cplx *L2 = a.Lam + (int64_t)(PB + 1) * a.nbox + b;
+#pragma unroll
             for (int n = PB; n >= 0; --n) {
                 cplx t = L2[(int64_t)n * a.nbox] * a.invfact[n];
                 cfma(t, G, zeta);
@@ -519,36 +560,14 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
             }
         }
     }
-    // U list, log terms
-    double lfree = 0.0, limg = 0.0;
-    const double2 *__restrict__ xy = a.xy;
-    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
-        const int code = a.uent[e];
-        const int c = code >> 1;
-        const int j0 = a.first[c], j1 = j0 + a.count[c];
-        if (!(code & 1)) {
-            for (int j = j0; j < j1; ++j) {
-                const double2 pj = xy[j];
-                const double dx = x - pj.x, dy = y - pj.y;
-                const double r2 = fma(dx, dx, dy * dy);
-                if (r2 > 0.0) lfree = fma(a.qs[j], log_pos(r2), lfree);
-            }
-        } else {
-            for (int j = j0; j < j1; ++j) {
-                const double2 pj = xy[j];
-                const double dx = x - pj.x, dy = y + pj.y;
-                limg = fma(a.qs[j], log_pos(fma(dx, dx, dy * dy)), limg);
-            }
-        }
-    }
-    const double near = kInv4Pi * (limg - lfree);
+    const double2 nr = a.near[i];
     cplx phi;
     if (a.nloc == 1) {
         const cplx s = *a.rank1;
         const cplx surf = mul_ipow(cexp_(-(a.Z * mk(y, x))) * s, 1);
-        phi = mk(2.0 * H.re + near, 0.0) + surf;
+        phi = mk(2.0 * H.re + nr.x, nr.y) + surf;
     } else {
-        phi = H + conj(G) + mk(near, 0.0);
+        phi = H + conj(G) + mk(nr.x, nr.y);
     }
     const int64_t o = a.perm[i];
     a.phi[2 * o] = phi.re;
@@ -661,13 +680,14 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
         sr = wave_sum(sr);
         si = wave_sum(si);
         if (lane == 0) {
-            const int64_t o = a.perm[i];
+            double2 v = a.near[i];
             if (a.nloc == 1) {
-                a.phi[2 * o] += 2.0 * sr;
+                v.x += 2.0 * sr;
             } else {
-                a.phi[2 * o] += sr;
-                a.phi[2 * o + 1] += si;
+                v.x += sr;
+                v.y += si;
             }
+            a.near[i] = v;
         }
     }
 }
@@ -994,6 +1014,11 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
         }
     }
     FMMHP_CHECK(to_dev(A, &S.E_m2m, Em, "E_m2m", s));
+    {
+        std::vector<double2> lt(kLogTable);
+        for (int k = 0; k < kLogTable; ++k) log_table_entry(k, &lt[k].x, &lt[k].y);
+        FMMHP_CHECK(to_dev(A, &S.logtab, lt, "log table", s));
+    }
     FMMHP_CHECK(to_dev(A, &S.E_l2l, El, "E_l2l", s));
 
     // workspace
@@ -1001,6 +1026,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     FMMHP_CHECK(A.alloc_n(&S.Lam, (size_t)S.nloc * (PB + 1) * nbox, "locals"));
     FMMHP_CHECK(A.alloc_n(&S.qs, (size_t)T.n, "sorted charges"));
     FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
+    FMMHP_CHECK(A.alloc_n(&S.near, (size_t)T.n, "near-field sums"));
+    FMMHP_HIP(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
     hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(A.alloc_n(&S.red, 1025, "reduction"));
@@ -1010,12 +1039,15 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
 
 // Phase markers: when timing is on, one event per phase boundary on the eval stream.
 struct Marks {
-    hipEvent_t ev[FMMHP_NUM_PHASES + 1];
+    hipEvent_t ev[FMMHP_NUM_PHASES + 1];  // main-stream boundaries; the NEAR slot pair is unused
+    hipEvent_t near0 = nullptr, near1 = nullptr;
     bool on = false;
     fmmhp_status init(const Sched &S) {
         on = S.timing;
         if (!on) return FMMHP_OK;
         for (auto &e : ev) FMMHP_HIP(hipEventCreate(&e));
+        FMMHP_HIP(hipEventCreate(&near0));
+        FMMHP_HIP(hipEventCreate(&near1));
         return FMMHP_OK;
     }
     fmmhp_status mark(int k, hipStream_t s) {
@@ -1025,6 +1057,8 @@ struct Marks {
     void commit(const Sched &S) {
         if (!on) return;
         for (auto &e : ev) S.events->push_back(e);
+        S.events->push_back(near0);
+        S.events->push_back(near1);
     }
 };
 
@@ -1037,6 +1071,21 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     FMMHP_CHECK(mk_.init(S));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2M, s));
     hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, S.qs);
+    // the near field needs only the sorted charges: run it on the side stream, concurrently with
+    // the far-field chain, and join before the final leaf kernel
+    const cplx *r1 = (S.nloc == 1) ? S.red + std::min<int64_t>(1024, nblk(T.n, 256)) : nullptr;
+    LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   S.xy,  T.perm,
+                T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
+                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.wpts,   S.n_wpts, S.rpts,
+                S.logtab,  S.near, phi};
+    FMMHP_HIP(hipEventRecord(S.ev_fork, s));
+    FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
+    if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
+    hipLaunchKernelGGL(k_near, dim3(nblk(T.n, 256)), dim3(256), 0, S.side, la);
+    if (S.n_rpts > 0) hipLaunchKernelGGL(k_near_reaction, dim3((unsigned)S.n_rpts), dim3(64), 0, S.side, la);
+    FMMHP_HIP(hipGetLastError());
+    if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
+    FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk(T.nleaf, 64)), dim3(64), 0, s, g, leaves, T.nleaf, nbox,
                        T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
     FMMHP_HIP(hipGetLastError());
@@ -1057,7 +1106,7 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
                                S.Lam);
     }
     if (S.ntiles > 0) {
-        constexpr int CH = kM2LChunk;
+        constexpr int CH = m2l_chunk(PB);
         static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
         M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
                    S.Tfree, S.Lfree, S.loglev,     S.W,            S.Lam,      S.nloc};
@@ -1085,24 +1134,19 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
-    const cplx *r1 = nullptr;
     if (S.nloc == 1) {
         const int np = (int)std::min<int64_t>(1024, nblk(T.n, 256));
         hipLaunchKernelGGL(k_rank1_partial, dim3(np), dim3(256), 0, s, T.xs, T.ys, S.qs, T.n, S.Z.re, S.red);
         hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(256), 0, s, S.red, np);
         FMMHP_HIP(hipGetLastError());
-        r1 = S.red + np;
     }
+    FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
-    LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   S.xy,  T.perm,
-                T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
-                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.wpts,   S.n_wpts, S.rpts,
-                phi};
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
-    if (S.n_rpts > 0) hipLaunchKernelGGL(k_near_reaction, dim3((unsigned)S.n_rpts), dim3(64), 0, s, la);
     if (S.n_wpts > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(mk_.mark(FMMHP_PHASE_NEAR, s));
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
     mk_.commit(S);
     return FMMHP_OK;
@@ -1133,12 +1177,16 @@ fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, 
 fmmhp_status collect_phase_times(Sched &S) {
     if (!S.events) return FMMHP_OK;
     auto &ev = *S.events;
-    const int G = FMMHP_NUM_PHASES + 1;
+    const int G = FMMHP_NUM_PHASES + 3;  // main boundaries + side-stream near pair
     for (size_t g0 = 0; g0 + G <= ev.size(); g0 += G) {
+        FMMHP_HIP(hipEventSynchronize(ev[g0 + FMMHP_NUM_PHASES]));
         FMMHP_HIP(hipEventSynchronize(ev[g0 + G - 1]));
         for (int k = 0; k < FMMHP_NUM_PHASES; ++k) {
             float ms = 0.f;
-            FMMHP_HIP(hipEventElapsedTime(&ms, ev[g0 + k], ev[g0 + k + 1]));
+            if (k == FMMHP_PHASE_NEAR)
+                FMMHP_HIP(hipEventElapsedTime(&ms, ev[g0 + G - 2], ev[g0 + G - 1]));
+            else if (k < FMMHP_PHASE_NEAR)
+                FMMHP_HIP(hipEventElapsedTime(&ms, ev[g0 + k], ev[g0 + k + 1]));
             S.phase_ms[k] += ms;
         }
         S.timed_evals += 1;

@@ -15,18 +15,18 @@ constexpr int kLBits = 30;        // integer cell bits per axis of the root squa
 constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
-constexpr int kM2LChunk = 8;      // output coefficients per M2L wave
+constexpr int kM2LChunkMax = 8;   // at most this many output coefficients per M2L wave
 constexpr int kM2LPhase = 16;     // multipole coefficients staged in LDS per phase
 constexpr int kM2LMaxSrc = 200;   // distinct V sources per tile (LDS: 16 * 200 * 16 B)
 
-// Waves per M2L workgroup: one per chunk of kM2LChunk output coefficients.
-__host__ __device__ constexpr int m2l_waves(int PB) { return (PB + kM2LChunk) / kM2LChunk; }
+// Waves per M2L workgroup, each owning m2l_chunk(PB) consecutive output coefficients: the fewest
+// waves of at most kM2LChunkMax outputs, with the outputs spread evenly over them.
+__host__ __device__ constexpr int m2l_waves(int PB) { return (PB + kM2LChunkMax) / kM2LChunkMax; }
+__host__ __device__ constexpr int m2l_chunk(int PB) { return (PB + m2l_waves(PB)) / m2l_waves(PB); }
 
-// M2L operator rows are zero-padded so that every chunk of kM2LChunk outputs reads in bounds:
-// ceil((PB + 1) / kM2LChunk) * kM2LChunk + PB entries.
-__host__ __device__ constexpr int m2l_row(int PB) {
-    return ((PB + kM2LChunk) / kM2LChunk) * kM2LChunk + PB;
-}
+// M2L operator rows are zero-padded so that every chunk reads in bounds:
+// m2l_waves(PB) * m2l_chunk(PB) + PB entries.
+__host__ __device__ constexpr int m2l_row(int PB) { return m2l_waves(PB) * m2l_chunk(PB) + PB; }
 
 void set_error(const char *fmt, ...);
 
@@ -109,6 +109,10 @@ struct Sched {
     int64_t n_rpts = 0;
     int32_t *rpts = nullptr;        // sorted points whose leaf has image U entries
     double2 *xy = nullptr;          // [n] sorted (x, y) pairs
+    double2 *logtab = nullptr;      // near-field log table
+    double2 *near = nullptr;        // [n] near-field sums
+    hipStream_t side = nullptr;     // side stream for the near field (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)

@@ -1,0 +1,156 @@
+// Autotuner (declared in include/fmmhp.h): p from a measured error against the GPU direct sum,
+// leaf size from measured eval time.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace fmmhp {
+
+__global__ void k_gather_sample(const double *__restrict__ x, const double *__restrict__ y, int64_t n, int m,
+                                double *__restrict__ sx, double *__restrict__ sy) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int64_t i = (int64_t)((double)k * (double)n / (double)m);
+    sx[k] = x[i];
+    sy[k] = y[i];
+}
+
+__global__ void k_gather_phi(const double *__restrict__ phi, int64_t n, int m, double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int64_t i = (int64_t)((double)k * (double)n / (double)m);
+    out[2 * k] = phi[2 * i];
+    out[2 * k + 1] = phi[2 * i + 1];
+}
+
+struct DevTmp {
+    std::vector<void *> p;
+    ~DevTmp() {
+        for (void *q : p) (void)hipFree(q);
+    }
+    template <class T>
+    fmmhp_status get(T **ptr, size_t n) {
+        void *q = nullptr;
+        if (hipMalloc(&q, (n ? n : 1) * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("autotuner: device allocation of %zu bytes failed", n * sizeof(T));
+            return FMMHP_ENOMEM;
+        }
+        p.push_back(q);
+        *ptr = (T *)q;
+        return FMMHP_OK;
+    }
+};
+
+}  // namespace fmmhp
+
+using namespace fmmhp;
+
+extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, const double *q, double lambda_re,
+                                   double lambda_im, double tol, int n_vec, const int *leaf_sizes, int n_leaf,
+                                   int sample, fmmhp_opts *best, double *err_out, double *ms_out, hipStream_t s) {
+    if (!x || !y || !q || !best || n < 1 || !(tol > 0.0) || n_vec < 1 || (leaf_sizes && n_leaf < 1) ||
+        sample < 0 || sample > n) {
+        set_error("fmmhp_tune: invalid arguments");
+        return FMMHP_EINVAL;
+    }
+    static const int kDefaultLeaves[] = {24, 32, 40, 48, 64, 96};
+    if (!leaf_sizes) {
+        leaf_sizes = kDefaultLeaves;
+        n_leaf = 6;
+    }
+    const int m = sample ? sample : (int)std::min<int64_t>(n, 256);
+    DevTmp tmp;
+    double *sx, *sy, *ref, *phi, *got, *qv;
+    FMMHP_CHECK(tmp.get(&sx, m));
+    FMMHP_CHECK(tmp.get(&sy, m));
+    FMMHP_CHECK(tmp.get(&ref, 2 * (size_t)m));
+    FMMHP_CHECK(tmp.get(&got, 2 * (size_t)m));
+    FMMHP_CHECK(tmp.get(&phi, 2 * (size_t)n * n_vec));
+    FMMHP_CHECK(tmp.get(&qv, (size_t)n * n_vec));
+    for (int v = 0; v < n_vec; ++v)
+        FMMHP_HIP(hipMemcpyAsync(qv + (size_t)v * n, q, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_gather_sample, dim3((m + 127) / 128), dim3(128), 0, s, x, y, n, m, sx, sy);
+    FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(fmmhp_direct_eval(n, x, y, 1, q, m, sx, sy, lambda_re, lambda_im, ref, s));
+    std::vector<double> href(2 * (size_t)m), hgot(2 * (size_t)m);
+    FMMHP_HIP(hipMemcpyAsync(href.data(), ref, href.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FMMHP_HIP(hipStreamSynchronize(s));
+    double nref = 0.0;
+    for (double v : href) nref += v * v;
+    nref = sqrt(nref);
+    hipEvent_t e0, e1;
+    FMMHP_HIP(hipEventCreate(&e0));
+    FMMHP_HIP(hipEventCreate(&e1));
+    double best_ms = INFINITY, best_err = 0.0;
+    fmmhp_opts bo{0, 0, 0, 0};
+    int p_start = 5;
+    fmmhp_status st = FMMHP_OK;
+    for (int li = 0; li < n_leaf && st == FMMHP_OK; ++li) {
+        for (int p = p_start; p <= FMMHP_MAX_P; p += 5) {
+            fmmhp_opts o{p, leaf_sizes[li], 0, 0};
+            fmmhp_plan_t plan = nullptr;
+            st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &o, s, &plan);
+            if (st == FMMHP_EUNSUPPORTED) {  // e.g. tables beyond the recursion's range at this leaf size
+                st = FMMHP_OK;
+                break;
+            }
+            if (st != FMMHP_OK) break;
+            st = fmmhp_eval(plan, 1, q, phi, s);
+            if (st == FMMHP_OK) {
+                hipLaunchKernelGGL(k_gather_phi, dim3((m + 127) / 128), dim3(128), 0, s, phi, n, m, got);
+                if (hipMemcpyAsync(hgot.data(), got, hgot.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    set_error("autotuner: device copy failed");
+                    st = FMMHP_EHIP;
+                }
+            }
+            double e = INFINITY;
+            if (st == FMMHP_OK) {
+                double d = 0.0;
+                for (size_t k = 0; k < hgot.size(); ++k) d += (hgot[k] - href[k]) * (hgot[k] - href[k]);
+                e = sqrt(d) / nref;
+            }
+            if (st == FMMHP_OK && e <= tol) {
+                std::vector<float> t;
+                for (int r = 0; r < 5 && st == FMMHP_OK; ++r) {
+                    (void)hipEventRecord(e0, s);
+                    st = fmmhp_eval(plan, n_vec, qv, phi, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t.push_back(ms);
+                }
+                std::sort(t.begin(), t.end());
+                const double med = t[t.size() / 2];
+                if (st == FMMHP_OK && med < best_ms) {
+                    best_ms = med;
+                    best_err = e;
+                    bo = o;
+                }
+                (void)fmmhp_plan_destroy(plan);
+                // the next leaf size rarely needs a smaller p: start one step below
+                p_start = std::max(5, p - 5);
+                break;
+            }
+            (void)fmmhp_plan_destroy(plan);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FMMHP_OK) return st;
+    if (!(best_ms < INFINITY)) {
+        set_error("fmmhp_tune: no candidate reached rel-l2 %g at p <= %d", tol, FMMHP_MAX_P);
+        return FMMHP_EUNSUPPORTED;
+    }
+    *best = bo;
+    if (err_out) *err_out = best_err;
+    if (ms_out) *ms_out = best_ms;
+    return FMMHP_OK;
+}
