@@ -131,6 +131,31 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
                         hipStream_t stream);
 
+/* Adjoint of fmmhp_eval for one real charge vector: gradients of a real loss l of phi with respect
+ * to the charges, the point positions and the impedance (the reverse-mode step of phi = A q; the
+ * paper's Green's function, eqs. (1.2) and (reactdecomposition), differentiated).
+ *
+ *   q          [device] charges [n], real, caller's point order (those of the forward call)
+ *   grad_phi   [device] incoming gradient [n][2]: g_i = dl/dRe phi_i + i dl/dIm phi_i
+ *   grad_q     [device] output [n]: dl/dq_j = Re sum_i conj(g_i) G(r_i, r_j), or NULL
+ *   grad_x, grad_y  [device] outputs [n]: dl/dx_k, dl/dy_k, or NULL.  A point moves as a target
+ *              and as a source; both are included, so are its own image and reaction terms.
+ *   grad_lambda [host] output [2]: (dl/dRe Z, dl/dIm Z), or NULL.  When given, the call
+ *              synchronises the stream.
+ *
+ * The potential's gradient fields come from the same expansions as phi (derivatives of the local
+ * expansions, the multipole series and the near-field kernels), so their accuracy follows p like
+ * phi's.  dl/dZ uses the scale homogeneity of the Green's function, G_Z(s r, s r') = G_{sZ}(r, r')
+ * up to the log of s for skipped coincident pairs.  Cost: three evaluations (one gradient pass for
+ * q, two potential-and-gradient passes for Re and Im of conj(g)); two potential passes when only
+ * grad_q is asked for.  The first call allocates the adjoint workspace (about 150 bytes per
+ * point), owned by the plan.  Calls on one plan must be ordered (one stream, or synchronised).
+ * Errors: FMMHP_EINVAL for a NULL q or grad_phi; with all outputs NULL the call does nothing.
+ */
+fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *grad_phi,
+                            double *grad_q, double *grad_x, double *grad_y,
+                            double *grad_lambda, hipStream_t stream);
+
 /* Plan statistics (sizes, root square, order in use).  stats: [host]. */
 fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *stats);
 

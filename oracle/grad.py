@@ -120,3 +120,78 @@ def potential_dZ(xs, ys, q, Z, idx=None):
         ii = idx[b0:b0 + 64]
         out[b0:b0 + 64] = _dZ_green(xs[ii, None], ys[ii, None], xs[None, :], ys[None, :], Z) @ q
     return out
+
+
+# --- multiprocess sampling at large N (the same formulas, blocked over targets and sources) ----
+
+_SRC = {}
+
+
+def _grad_block(xt, yt, xs, ys, C, Z, chunk):
+    """[2, n_vec, len(xt)] gradient of Phi[C_v] at a block of targets."""
+    nv = C.shape[0]
+    acc = np.zeros((2, nv, xt.shape[0]), dtype=np.complex128)
+    for s0 in range(0, xs.shape[0], chunk):
+        s1 = min(xs.shape[0], s0 + chunk)
+        kx, ky = _grad_green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z)
+        acc[0] += C[:, s0:s1] @ kx.T
+        acc[1] += C[:, s0:s1] @ ky.T
+    return acc
+
+
+def _dZ_block(xt, yt, xs, ys, C, Z, chunk):
+    nv = C.shape[0]
+    acc = np.zeros((nv, xt.shape[0]), dtype=np.complex128)
+    for s0 in range(0, xs.shape[0], chunk):
+        s1 = min(xs.shape[0], s0 + chunk)
+        acc += C[:, s0:s1] @ _dZ_green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z).T
+    return acc
+
+
+def _init_worker(xs, ys, C, Z):
+    _SRC.update(xs=xs, ys=ys, C=C, Z=Z)
+
+
+def _work(args):
+    kind, xt, yt, chunk = args
+    f = _grad_block if kind == "grad" else _dZ_block
+    return f(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["C"], _SRC["Z"], chunk)
+
+
+def _run(kind, xs, ys, C, Z, xt, yt, workers, target_block=8, chunk=1 << 14):
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    blocks = [(kind, xt[i:i + target_block], yt[i:i + target_block], chunk)
+              for i in range(0, xt.shape[0], target_block)]
+    if workers <= 1 or len(blocks) <= 1:
+        _init_worker(xs, ys, C, complex(Z))
+        parts = [_work(b) for b in blocks]
+    else:
+        with ProcessPoolExecutor(max_workers=workers, initializer=_init_worker,
+                                 initargs=(xs, ys, C, complex(Z))) as ex:
+            parts = list(ex.map(_work, blocks))
+    return np.concatenate(parts, axis=-1)
+
+
+def sampled_gradients(xs, ys, q, Z, g, idx, workers=None, want_Z=False):
+    """direct_gradients at the indices idx against ALL sources, over a process pool.  grad_Z
+    (an all-pairs sum) only when want_Z."""
+    from . import direct as D
+    xs = np.ascontiguousarray(xs, dtype=np.float64)
+    ys = np.ascontiguousarray(ys, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    cg = np.conj(np.asarray(g, dtype=np.complex128))
+    idx = np.asarray(idx)
+    xt, yt = xs[idx], ys[idx]
+    grad_q = np.real(D.potential(xs, ys, cg, Z, xt=xt, yt=yt, workers=workers))
+    C = np.ascontiguousarray(np.stack([q.astype(np.complex128), cg]))
+    gr = _run("grad", xs, ys, C, Z, xt, yt, workers)
+    out = {"grad_q": grad_q,
+           "grad_x": np.real(cg[idx] * gr[0, 0] + q[idx] * gr[0, 1]),
+           "grad_y": np.real(cg[idx] * gr[1, 0] + q[idx] * gr[1, 1])}
+    if want_Z:
+        dphi = _run("dZ", xs, ys, np.ascontiguousarray(q[None, :].astype(np.complex128)), Z, xs, ys, workers)[0]
+        out["grad_Z"] = np.conj(np.sum(cg * dphi))
+    return out

@@ -63,6 +63,7 @@ _SIGNATURES = {
     "fmmhp_plan_create": [_I64, _P, _P, _P, _P, _D, _D, ctypes.POINTER(Opts), _P,
                           ctypes.POINTER(_P)],
     "fmmhp_eval": [_P, _INT, _P, _P, _P],
+    "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
     "fmmhp_plan_export_tree": [_P] + [_P] * 18,
     "fmmhp_plan_destroy": [_P],
@@ -130,6 +131,15 @@ def fmmhp_plan_create(n, x_ptr, y_ptr, img_x_ptr, img_y_ptr, lambda_re, lambda_i
 
 def fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream):
     _check("fmmhp_eval", lib().fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream))
+
+
+def fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr, grad_y_ptr, want_lambda,
+                   stream):
+    """Returns (dl/dRe Z, dl/dIm Z) when want_lambda, else None."""
+    gl = (_D * 2)() if want_lambda else None
+    _check("fmmhp_backward", lib().fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr,
+                                                  grad_y_ptr, gl, stream))
+    return (gl[0], gl[1]) if want_lambda else None
 
 
 def fmmhp_plan_info(plan) -> dict:
@@ -294,6 +304,31 @@ class HalfPlaneFMM:
             return out
         return phi[0] if squeeze else phi
 
+    def backward(self, q: torch.Tensor, grad_phi: torch.Tensor, want_q=True, want_x=True,
+                 want_y=True, want_lambda=True) -> dict:
+        """Gradients of a real loss l given g = dl/dRe phi + i dl/dIm phi (complex [N]) for real
+        charges q [N]: {"q", "x", "y": float64 [N], "lambda": complex dl/dRe Z + i dl/dIm Z}."""
+        if not isinstance(q, torch.Tensor) or not q.is_cuda or q.is_complex():
+            raise TypeError("q must be a real GPU tensor")
+        if q.numel() != self.n or grad_phi.numel() != self.n:
+            raise ValueError("q and grad_phi must have one entry per point")
+        qd = q.reshape(-1).to(torch.float64).contiguous()
+        gr = torch.view_as_real(grad_phi.reshape(-1).to(torch.complex128).contiguous())
+        out = {}
+        ptr = {}
+        for k, want in (("q", want_q), ("x", want_x), ("y", want_y)):
+            if want:
+                out[k] = torch.empty(self.n, dtype=torch.float64, device=self.device)
+                ptr[k] = out[k].data_ptr()
+            else:
+                ptr[k] = None
+        with torch.cuda.device(self.device):
+            gl = fmmhp_backward(self._plan, qd.data_ptr(), gr.data_ptr(), ptr["q"], ptr["x"],
+                                ptr["y"], bool(want_lambda), _stream())
+        if want_lambda:
+            out["lambda"] = complex(gl[0], gl[1])
+        return out
+
     def close(self):
         if getattr(self, "_plan", None):
             fmmhp_plan_destroy(self._plan)
@@ -304,6 +339,43 @@ class HalfPlaneFMM:
             self.close()
         except Exception:
             pass
+
+
+class _PotentialFn(torch.autograd.Function):
+    """phi = A(x, y, Z) q with the adjoint of fmmhp_backward."""
+
+    @staticmethod
+    def forward(ctx, x, y, q, lam, p, leaf_size):
+        plan = HalfPlaneFMM(x.detach(), y.detach(), complex(lam.detach().cpu().item()), p=p,
+                            leaf_size=leaf_size)
+        phi = plan(q.detach())
+        ctx.plan = plan
+        ctx.lam_dtype = lam.dtype
+        ctx.save_for_backward(q)
+        return phi
+
+    @staticmethod
+    def backward(ctx, g):
+        (q,) = ctx.saved_tensors
+        nx, ny, nq, nl = ctx.needs_input_grad[:4]
+        r = ctx.plan.backward(q.detach(), g, want_q=nq, want_x=nx, want_y=ny, want_lambda=nl)
+        gl = None
+        if nl:
+            v = r["lambda"] if ctx.lam_dtype.is_complex else r["lambda"].real
+            gl = torch.tensor(v, dtype=ctx.lam_dtype)
+        return r.get("x"), r.get("y"), r.get("q"), gl, None, None
+
+
+def potential(x, y, q, impedance, p=20, leaf_size=40) -> torch.Tensor:
+    """Differentiable phi_i = sum_j q_j G(r_i, r_j) over the points (x, y) for real charges q:
+    gradients flow to x, y, q and, when it is a tensor, to the impedance (real or complex).
+    The plan (tree, lists, tables) is rebuilt per call."""
+    if q.is_complex():
+        raise TypeError("potential() takes real charges; use HalfPlaneFMM for complex ones")
+    if not isinstance(impedance, torch.Tensor):
+        impedance = torch.tensor(complex(impedance) if isinstance(impedance, complex) else float(impedance),
+                                 dtype=torch.complex128 if isinstance(impedance, complex) else torch.float64)
+    return _PotentialFn.apply(x, y, q, impedance, int(p), int(leaf_size))
 
 
 def direct(xs, ys, q, impedance, xt=None, yt=None) -> torch.Tensor:
@@ -344,4 +416,5 @@ __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functi
            "FMMHPError", "Opts", "PlanStats", "fmmhp_plan_create", "fmmhp_eval",
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
-           "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune"]
+           "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune",
+           "fmmhp_backward", "potential"]

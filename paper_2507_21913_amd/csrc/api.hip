@@ -154,6 +154,25 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
     return run_eval(plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
+fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
+                            double *grad_x, double *grad_y, double *grad_lambda, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!q || !grad_phi) {
+        set_error("q and grad_phi must be non-NULL");
+        return FMMHP_EINVAL;
+    }
+    cplx zsum{0.0, 0.0};
+    FMMHP_CHECK(run_backward(plan->arena, plan->tree, plan->sched, q, grad_phi, grad_q, grad_x, grad_y,
+                             grad_lambda ? &zsum : nullptr, stream));
+    if (grad_lambda) {
+        // dl_c/dZ = zsum / Z;  (dl/dRe Z, dl/dIm Z) = (Re, -Im) of it
+        const cplx d = zsum * inv(plan->sched.Z);
+        grad_lambda[0] = d.re;
+        grad_lambda[1] = -d.im;
+    }
+    return FMMHP_OK;
+}
+
 fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {
     FMMHP_CHECK(check_plan(plan));
     if (!st) {

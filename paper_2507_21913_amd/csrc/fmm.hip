@@ -469,10 +469,23 @@ __global__ __launch_bounds__(256) void k_rank1_final(cplx *__restrict__ part, in
 }
 
 // ---------------------------------------------------------------------------------------------
-// Leaf evaluation.  k_leaf: L2P, the log parts of the U list and the surface term, one thread per
-// target point, writes phi.  k_leaf_extra: the rarer W list (M2P) and the reaction part of the U
-// list's image entries, for the targets whose leaf has them; adds to phi.
+// Leaf evaluation.  k_near: the log parts of the U list; k_near_reaction: the reaction part of the
+// U list's image entries, for the targets whose leaf has them; k_leaf: L2P of the local(s) plus
+// the near-field sums and the surface term; k_leaf_w: the rarer W list (M2P).
+//
+// Each kernel has three modes: kPhi (the potential, in caller order), kGrad (the gradient
+// (d_x phi, d_y phi) only) and kPhiGrad (both).  Gradients follow from the same expansions: the
+// far field is 2 Re H + surface (real impedance) or H + conj(G) with H, G holomorphic in the
+// target z, so d_x = 2 Re H', d_y = -2 Im H' (resp. d_x = H' + conj(G'), d_y = i H' - i conj(G'));
+// the surface term i e^{-Z(y + ix)} s has d_x = Z e^{-Z(y+ix)} s and d_y = -i Z e^{-Z(y+ix)} s.
+// Near-field kernel derivatives: d_x log|r - r'| = (x - x') / |r - r'|^2 (and alike in y), and
+// d_x I_0(X, Y) = i I_1(X, Y), d_y I_0(X, Y) = -I_1(X, Y), I_1 = 1 / (2 pi w) + Z I_0, w = Y - iX
+// (differentiating eq. (generalintegral) under the integral; eq. (integralrecursion) for n = 1).
 // ---------------------------------------------------------------------------------------------
+enum LeafMode { kPhi = 0, kGrad = 1, kPhiGrad = 2 };
+__host__ __device__ constexpr bool has_phi(int m) { return m != kGrad; }
+__host__ __device__ constexpr bool has_grad(int m) { return m != kPhi; }
+
 struct LeafArgs {
     Geo g;
     cplx Z;
@@ -489,21 +502,28 @@ struct LeafArgs {
     int64_t n_wpts;
     const int32_t *rpts;     // targets whose leaf has image U entries
     const double2 *logtab;   // [kLogTable] (1/c_k, -log(1/c_k))
-    double2 *near;           // [n] near-field sums per sorted target
-    double *phi;         // [n][2]
+    double2 *near;           // [n] near-field potential per sorted target
+    cplx *near_gx, *near_gy; // [n] near-field gradient per sorted target (gradient modes)
+    double *qc;              // [n] sum of the charges coincident with each sorted target, or null
+    double *phi;             // [n][2] potential, caller order (potential modes)
+    cplx *gx, *gy;           // [n] gradient, caller order (gradient modes)
 };
 
-// Near field, log terms of the U list: one thread per target (sorted order), writes near[i].
+// Near field, log terms of the U list: one thread per target (sorted order).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     __shared__ double2 s_logtab[kLogTable];
-    if (threadIdx.x < kLogTable) s_logtab[threadIdx.x] = a.logtab[threadIdx.x];
-    __syncthreads();
+    if (has_phi(MODE)) {
+        if (threadIdx.x < kLogTable) s_logtab[threadIdx.x] = a.logtab[threadIdx.x];
+        __syncthreads();
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int b = a.leaf_of[i];
     const double2 pi = a.xy[i];
     const double x = pi.x, y = pi.y;
     double lfree = 0.0, limg = 0.0;
+    double fx = 0.0, fy = 0.0, mx = 0.0, my = 0.0, qc = 0.0;
     const double2 *__restrict__ xy = a.xy;
     const double2 *__restrict__ tab = s_logtab;
     for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
@@ -515,22 +535,42 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 const double2 pj = xy[j];
                 const double dx = x - pj.x, dy = y - pj.y;
                 const double r2 = fma(dx, dx, dy * dy);
-                const double qm = r2 > 0.0 ? a.qs[j] : 0.0;  // skip the self pair (eq. (1.2))
-                lfree = fma(qm, log_tab(r2 > 0.0 ? r2 : 1.0, tab), lfree);
+                const bool nz = r2 > 0.0;
+                const double qj = a.qs[j];
+                const double qm = nz ? qj : 0.0;  // skip the self pair (eq. (1.2))
+                if (has_phi(MODE)) lfree = fma(qm, log_tab(nz ? r2 : 1.0, tab), lfree);
+                if (has_grad(MODE)) {
+                    const double s = qm * rcp_pos(nz ? r2 : 1.0);
+                    fx = fma(s, dx, fx);
+                    fy = fma(s, dy, fy);
+                    qc += nz ? 0.0 : qj;
+                }
             }
         } else {
             for (int j = j0; j < j1; ++j) {
                 const double2 pj = xy[j];
                 const double dx = x - pj.x, dy = y + pj.y;
-                limg = fma(a.qs[j], log_tab(fma(dx, dx, dy * dy), tab), limg);
+                const double r2 = fma(dx, dx, dy * dy);
+                const double qj = a.qs[j];
+                if (has_phi(MODE)) limg = fma(qj, log_tab(r2, tab), limg);
+                if (has_grad(MODE)) {
+                    const double s = qj * rcp_pos(r2);
+                    mx = fma(s, dx, mx);
+                    my = fma(s, dy, my);
+                }
             }
         }
     }
-    a.near[i] = make_double2(kInv4Pi * (limg - lfree), 0.0);
+    if (has_phi(MODE)) a.near[i] = make_double2(kInv4Pi * (limg - lfree), 0.0);
+    if (has_grad(MODE)) {
+        a.near_gx[i] = mk(kInv2Pi * (mx - fx), 0.0);
+        a.near_gy[i] = mk(kInv2Pi * (my - fy), 0.0);
+        if (a.qc) a.qc[i] = qc;
+    }
 }
 
-// L2P of the local(s), plus the near-field sums and the surface term; writes phi in caller order.
-template <int PB>
+// L2P of the local(s), plus the near-field sums and the surface term; writes caller order.
+template <int PB, int MODE>
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
@@ -539,44 +579,63 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     const double x = a.xs[i], y = a.ys[i];
     const cplx cb = centre_of(a.g, l, a.bx[b], a.by[b]);
     const double irho = 2.0 / side_of(a.g, l);
-    // L2P: H(z) = sum_n lambda_n / n! zeta^n
+    // L2P: H(z) = sum_n lambda_n / n! zeta^n, H'(z) = irho sum_{n>=1} lambda_n / (n-1)! zeta^(n-1)
     const cplx zeta = mk((x - cb.re) * irho, (y - cb.im) * irho);
-    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
-    {
-        const cplx *L = a.Lam + b;
+    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0), Hd = mk(0.0, 0.0), Gd = mk(0.0, 0.0);
+    for (int loc = 0; loc < a.nloc; ++loc) {
+        const cplx *L = a.Lam + (int64_t)loc * (PB + 1) * a.nbox + b;
+        cplx h = mk(0.0, 0.0), hd = mk(0.0, 0.0);
 #pragma unroll
         for (int n = PB; n >= 0; --n) {
-            cplx t = L[(int64_t)n * a.nbox] * a.invfact[n];
-            cfma(t, H, zeta);
-            H = t;
-        }
-        if (a.nloc == 2) {
-            const cplx *L2 = a.Lam + (int64_t)(PB + 1) * a.nbox + b;
-#pragma unroll
-            for (int n = PB; n >= 0; --n) {
-                cplx t = L2[(int64_t)n * a.nbox] * a.invfact[n];
-                cfma(t, G, zeta);
-                G = t;
+            const cplx ln = L[(int64_t)n * a.nbox];
+            if (has_phi(MODE)) {
+                cplx t = ln * a.invfact[n];
+                cfma(t, h, zeta);
+                h = t;
+            }
+            if (has_grad(MODE) && n >= 1) {
+                cplx t = ln * a.invfact[n - 1];
+                cfma(t, hd, zeta);
+                hd = t;
             }
         }
-    }
-    const double2 nr = a.near[i];
-    cplx phi;
-    if (a.nloc == 1) {
-        const cplx s = *a.rank1;
-        const cplx surf = mul_ipow(cexp_(-(a.Z * mk(y, x))) * s, 1);
-        phi = mk(2.0 * H.re + nr.x, nr.y) + surf;
-    } else {
-        phi = H + conj(G) + mk(nr.x, nr.y);
+        if (loc == 0) {
+            H = h;
+            Hd = irho * hd;
+        } else {
+            G = h;
+            Gd = irho * hd;
+        }
     }
     const int64_t o = a.perm[i];
-    a.phi[2 * o] = phi.re;
-    a.phi[2 * o + 1] = phi.im;
+    cplx E = mk(0.0, 0.0);  // e^{-Z(y + ix)} s (real impedance)
+    if (a.nloc == 1) E = cexp_(-(a.Z * mk(y, x))) * (*a.rank1);
+    if (has_phi(MODE)) {
+        const double2 nr = a.near[i];
+        cplx phi;
+        if (a.nloc == 1) phi = mk(2.0 * H.re + nr.x, nr.y) + mul_ipow(E, 1);
+        else phi = H + conj(G) + mk(nr.x, nr.y);
+        a.phi[2 * o] = phi.re;
+        a.phi[2 * o + 1] = phi.im;
+    }
+    if (has_grad(MODE)) {
+        cplx gx = a.near_gx[i], gy = a.near_gy[i];
+        if (a.nloc == 1) {
+            const cplx ZE = a.Z * E;
+            gx += mk(2.0 * Hd.re, 0.0) + ZE;
+            gy += mk(-2.0 * Hd.im, 0.0) + mul_ipow(ZE, 3);
+        } else {
+            gx += Hd + conj(Gd);
+            gy += mul_ipow(Hd - conj(Gd), 1);
+        }
+        a.gx[o] = gx;
+        a.gy[o] = gy;
+    }
 }
 
 // W list for the targets whose leaf has one: multipoles of smaller non-adjacent boxes evaluated
-// at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to phi.
-template <int PB>
+// at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to the outputs.
+template <int PB, int MODE>
 __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n_wpts) return;
@@ -584,7 +643,7 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     const int b = a.leaf_of[i];
     const double x = a.xs[i], y = a.ys[i];
     const cplx z = mk(x, y);
-    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0);
+    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0), Hd = mk(0.0, 0.0), Gd = mk(0.0, 0.0);
     for (int e = a.woff[b]; e < a.woff[b + 1]; ++e) {
         const int code = a.went[e];
         const int d = code >> 1, img = code & 1;
@@ -593,25 +652,34 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
         const double rd = 0.5 * side_of(a.g, ld);
         const cplx cd = img ? conj(cd0) : cd0;
         const cplx dz = z - cd;
-        const cplx tau = -rd * inv(dz);
-        // u = w0 log(z - c) - sum_k (k-1)! tau^k w_k  (conjugated w for the image box)
+        const cplx idz = inv(dz);
+        const cplx tau = -rd * idz;
+        // u = w0 log(z - c) - sum_k (k-1)! tau^k w_k,  u' = (w0 + sum_k k! tau^k w_k) / (z - c)
+        // (conjugated w for the image box)
         cplx w0 = a.W[d];
         if (img) w0 = conj(w0);
-        cplx u = w0 * clog_(dz);
+        cplx u = mk(0.0, 0.0), ud = w0;
+        if (has_phi(MODE)) u = w0 * clog_(dz);
         cplx pw = tau;
 #pragma unroll
         for (int k = 1; k <= PB; ++k) {
             cplx wk = a.W[(int64_t)k * a.nbox + d];
             if (img) wk = conj(wk);
-            u -= (a.fact[k - 1] * pw) * wk;
+            const cplx pk = pw * wk;
+            if (has_phi(MODE)) u -= a.fact[k - 1] * pk;
+            if (has_grad(MODE)) ud += a.fact[k] * pk;
             pw = pw * tau;
         }
-        const double sgn = img ? 1.0 : -1.0;
-        H += (sgn * kInv4Pi) * u;
-        G += (sgn * kInv4Pi) * u;
+        const double sgn = (img ? 1.0 : -1.0) * kInv4Pi;
+        H += sgn * u;
+        G += sgn * u;
+        ud = sgn * (ud * idz);
+        Hd += ud;
+        Gd += ud;
         if (img) {
             // reaction ME (eq. (truncatedME)) of the image box: sum_n alpha_n I_n(x - x'_c, y - y'_c),
-            // alpha_n = rho^n (-i)^n conj(mu_n) = i^n n! rho^n conj(w_n)
+            // alpha_n = rho^n (-i)^n conj(mu_n) = i^n n! rho^n conj(w_n); with K_n = n! rho^n I_n its
+            // z-derivative is (1/rho) sum_n i^(n+1) K_(n+1) conj(w_n)
             const double X = x - cd0.re, Y = y + cd0.im;
             for (int pass = 0; pass < a.nloc; ++pass) {
                 const double Xs = pass == 0 ? X : -X;
@@ -619,26 +687,46 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
                 const cplx zr = rd * a.Z;
                 cplx K = reaction_I0_general(Xs, Y, a.Z);
                 cplx F = mk(1.0, 0.0);
-                cplx acc = (pass == 0 ? K : conj(K)) * conj(a.W[d]);
+                cplx acc = mk(0.0, 0.0), accd = mk(0.0, 0.0);
+                if (has_phi(MODE)) acc = (pass == 0 ? K : conj(K)) * conj(a.W[d]);
+                constexpr int NTOP = has_grad(MODE) ? PB + 1 : PB;
 #pragma unroll
-                for (int n = 1; n <= PB; ++n) {
+                for (int n = 1; n <= NTOP; ++n) {
                     F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
                     K = F * kInv2Pi + zr * K;
-                    const cplx Kn = pass == 0 ? K : conj(K);
-                    acc += mul_ipow(Kn, n) * conj(a.W[(int64_t)n * a.nbox + d]);
+                    const cplx Kn = mul_ipow(pass == 0 ? K : conj(K), n);
+                    if (has_phi(MODE) && n <= PB) acc += Kn * conj(a.W[(int64_t)n * a.nbox + d]);
+                    if (has_grad(MODE)) accd += Kn * conj(a.W[(int64_t)(n - 1) * a.nbox + d]);
                 }
-                if (pass == 0) H += acc;
-                else G += acc;
+                accd = accd * (1.0 / rd);
+                if (pass == 0) {
+                    H += acc;
+                    Hd += accd;
+                } else {
+                    G += acc;
+                    Gd += accd;
+                }
             }
         }
     }
     const int64_t o = a.perm[i];
-    if (a.nloc == 1) {
-        a.phi[2 * o] += 2.0 * H.re;
-    } else {
-        const cplx v = H + conj(G);
-        a.phi[2 * o] += v.re;
-        a.phi[2 * o + 1] += v.im;
+    if (has_phi(MODE)) {
+        if (a.nloc == 1) {
+            a.phi[2 * o] += 2.0 * H.re;
+        } else {
+            const cplx v = H + conj(G);
+            a.phi[2 * o] += v.re;
+            a.phi[2 * o + 1] += v.im;
+        }
+    }
+    if (has_grad(MODE)) {
+        if (a.nloc == 1) {
+            a.gx[o] += mk(2.0 * Hd.re, 0.0);
+            a.gy[o] += mk(-2.0 * Hd.im, 0.0);
+        } else {
+            a.gx[o] += Hd + conj(Gd);
+            a.gy[o] += mul_ipow(Hd - conj(Gd), 1);
+        }
     }
 }
 
@@ -650,36 +738,50 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Reaction part of the near field: sum over the image sources of a leaf's U list of
 // q_j [I_0(X, Y) + I_0(-X, Y)], X = x_i - x_j, Y = y_i + y_j (eq. (reactdecomposition)); for a
-// real impedance only 2 Re I_0(X, Y) (the rest is the surface term).  One wave per leaf that
-// touches y = 0; lanes take image sources, a fixed-order butterfly sums them.  Adds to phi.
+// real impedance only 2 Re I_0(X, Y) (the rest is the surface term).  One wave per target whose
+// leaf touches y = 0; lanes take image sources, a fixed-order butterfly sums them.  Adds to the
+// near-field sums.
+template <int MODE>
 __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
     const int i = a.rpts[blockIdx.x];
     const int b = a.leaf_of[i];
     const int lane = threadIdx.x;
-    {
-        const double x = a.xs[i], y = a.ys[i];
-        double sr = 0.0, si = 0.0;
-        for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
-            const int code = a.uent[e];
-            if (!(code & 1)) continue;
-            const int c = code >> 1;
-            const int j1 = a.first[c] + a.count[c];
-            for (int j = a.first[c] + lane; j < j1; j += 64) {
-                const double dx = x - a.xs[j], dy = y + a.ys[j];
-                const double qj = a.qs[j];
-                const cplx I = reaction_I0_near(dx, dy, a.Z);
-                if (a.nloc == 1) {
-                    sr += qj * I.re;
-                } else {
-                    const cplx v = I + reaction_I0_near(-dx, dy, a.Z);
+    const double x = a.xs[i], y = a.ys[i];
+    double sr = 0.0, si = 0.0;
+    cplx s1p = mk(0.0, 0.0), s1m = mk(0.0, 0.0);  // sum q I_1(X, Y), sum q I_1(-X, Y)
+    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+        const int code = a.uent[e];
+        if (!(code & 1)) continue;
+        const int c = code >> 1;
+        const int j1 = a.first[c] + a.count[c];
+        for (int j = a.first[c] + lane; j < j1; j += 64) {
+            const double dx = x - a.xs[j], dy = y + a.ys[j];
+            const double qj = a.qs[j];
+            const cplx I = reaction_I0_near(dx, dy, a.Z);
+            if (has_grad(MODE)) s1p += qj * (kInv2Pi * inv(mk(dy, -dx)) + a.Z * I);
+            if (a.nloc == 1) {
+                if (has_phi(MODE)) sr += qj * I.re;
+            } else {
+                const cplx Im_ = reaction_I0_near(-dx, dy, a.Z);
+                if (has_phi(MODE)) {
+                    const cplx v = I + Im_;
                     sr += qj * v.re;
                     si += qj * v.im;
                 }
+                if (has_grad(MODE)) s1m += qj * (kInv2Pi * inv(mk(dy, dx)) + a.Z * Im_);
             }
         }
+    }
+    if (has_phi(MODE)) {
         sr = wave_sum(sr);
         si = wave_sum(si);
-        if (lane == 0) {
+    }
+    if (has_grad(MODE)) {
+        s1p = mk(wave_sum(s1p.re), wave_sum(s1p.im));
+        s1m = mk(wave_sum(s1m.re), wave_sum(s1m.im));
+    }
+    if (lane == 0) {
+        if (has_phi(MODE)) {
             double2 v = a.near[i];
             if (a.nloc == 1) {
                 v.x += 2.0 * sr;
@@ -688,6 +790,16 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
                 v.y += si;
             }
             a.near[i] = v;
+        }
+        if (has_grad(MODE)) {
+            if (a.nloc == 1) {
+                // d_x 2 Re sum q I_0 = 2 Re(i S1) ; d_y = -2 Re S1
+                a.near_gx[i] += mk(-2.0 * s1p.im, 0.0);
+                a.near_gy[i] += mk(-2.0 * s1p.re, 0.0);
+            } else {
+                a.near_gx[i] += mul_ipow(s1p - s1m, 1);
+                a.near_gy[i] -= s1p + s1m;
+            }
         }
     }
 }
@@ -1062,9 +1174,17 @@ struct Marks {
     }
 };
 
-template <int PB>
-static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leaves, const double *q, double *phi,
-                             hipStream_t s) {
+// Outputs of one evaluation pass (caller order): the potential and/or its gradient, and the
+// coincident-charge sums (sorted order) used by the impedance gradient.
+struct PassOut {
+    double *phi = nullptr;      // [n][2]
+    cplx *gx = nullptr, *gy = nullptr;
+    double *qc = nullptr;
+};
+
+template <int PB, int MODE>
+static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leaves, const double *q,
+                             const PassOut &out, hipStream_t s) {
     const Geo g{T.x_lo, T.S};
     const int nbox = T.nbox;
     Marks mk_;
@@ -1077,12 +1197,14 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   S.xy,  T.perm,
                 T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
                 T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.wpts,   S.n_wpts, S.rpts,
-                S.logtab,  S.near, phi};
+                S.logtab,  S.near, S.bw.near_gx, S.bw.near_gy, out.qc, out.phi, out.gx, out.gy};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
-    hipLaunchKernelGGL(k_near, dim3(nblk(T.n, 256)), dim3(256), 0, S.side, la);
-    if (S.n_rpts > 0) hipLaunchKernelGGL(k_near_reaction, dim3((unsigned)S.n_rpts), dim3(64), 0, S.side, la);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE>), dim3(nblk(T.n, 256)), dim3(256), 0, S.side, la);
+    if (S.n_rpts > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE>), dim3((unsigned)S.n_rpts), dim3(64), 0, S.side,
+                           la);
     FMMHP_HIP(hipGetLastError());
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
     FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
@@ -1142,9 +1264,9 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     }
     FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, MODE>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
     if (S.n_wpts > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, s, la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, MODE>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_NEAR, s));
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
@@ -1152,16 +1274,17 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     return FMMHP_OK;
 }
 
-static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q, double *phi, hipStream_t s) {
+template <int MODE>
+static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
     switch (S.PB) {
-        case 5: return eval_vec<5>(T, S, S.leaves, q, phi, s);
-        case 10: return eval_vec<10>(T, S, S.leaves, q, phi, s);
-        case 15: return eval_vec<15>(T, S, S.leaves, q, phi, s);
-        case 20: return eval_vec<20>(T, S, S.leaves, q, phi, s);
-        case 25: return eval_vec<25>(T, S, S.leaves, q, phi, s);
-        case 30: return eval_vec<30>(T, S, S.leaves, q, phi, s);
-        case 35: return eval_vec<35>(T, S, S.leaves, q, phi, s);
-        case 40: return eval_vec<40>(T, S, S.leaves, q, phi, s);
+        case 5: return eval_vec<5, MODE>(T, S, S.leaves, q, out, s);
+        case 10: return eval_vec<10, MODE>(T, S, S.leaves, q, out, s);
+        case 15: return eval_vec<15, MODE>(T, S, S.leaves, q, out, s);
+        case 20: return eval_vec<20, MODE>(T, S, S.leaves, q, out, s);
+        case 25: return eval_vec<25, MODE>(T, S, S.leaves, q, out, s);
+        case 30: return eval_vec<30, MODE>(T, S, S.leaves, q, out, s);
+        case 35: return eval_vec<35, MODE>(T, S, S.leaves, q, out, s);
+        case 40: return eval_vec<40, MODE>(T, S, S.leaves, q, out, s);
         default:
             set_error("internal: no kernels compiled for p = %d", S.PB);
             return FMMHP_EUNSUPPORTED;
@@ -1169,8 +1292,141 @@ static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q,
 }
 
 fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
-    for (int v = 0; v < nvec; ++v)
-        FMMHP_CHECK(run_eval_vec(T, S, q + (int64_t)v * T.n, phi + (int64_t)v * 2 * T.n, s));
+    for (int v = 0; v < nvec; ++v) {
+        PassOut o;
+        o.phi = phi + (int64_t)v * 2 * T.n;
+        FMMHP_CHECK(run_eval_vec<kPhi>(T, S, q + (int64_t)v * T.n, o, s));
+    }
+    return FMMHP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint.  For a real loss l of the complex potential, with incoming g_i = dl/dRe phi_i +
+// i dl/dIm phi_i (so l = sum_i Re(conj(g_i) phi_i) to first order) and c = conj(g):
+//   dl/dq_j = Re Phi[c](r_j)                                  (G(r, r') = G(r', r), eq. (greensfunsymm))
+//   dl/dx_k = Re D_x(k),  D_x(k) = c_k d_x Phi[q](r_k) + q_k d_x Phi[c](r_k)     (alike in y)
+// with Phi[c](r) = sum_j c_j G(r, r_j).  Phi[c] = Phi[Re c] + i Phi[Im c] uses two real passes.
+// The impedance gradient comes from the scale homogeneity of the Green's function: the two log
+// terms are invariant under r -> s r in pairs and the reaction term depends on Z and the
+// coordinates only through Z (y - i x), so G_Z(s r, s r') = G_{sZ}(r, r') up to (1/2pi) log s per
+// skipped coincident pair, and
+//   Z dl_c/dZ = sum_k [(x_k - x0) D_x(k) + y_k D_y(k)] - (1/2pi) sum_{r_i == r_j} c_i q_j,
+// l_c = sum_i c_i phi_i, for any x0 (translation invariance in x; the root centre is used).
+// dl/dZ is reported as dl/dRe Z + i dl/dIm Z = conj(dl_c/dZ) (phi is holomorphic in Z).
+// ---------------------------------------------------------------------------------------------
+__global__ void k_split_conj(const double *__restrict__ g, int64_t n, double *__restrict__ cr,
+                             double *__restrict__ ci) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n) {
+        cr[o] = g[2 * o];
+        ci[o] = -g[2 * o + 1];
+    }
+}
+
+struct BwdArgs {
+    int64_t n;
+    double x0;
+    const double *xs, *ys;
+    const int32_t *perm;
+    const double *q, *g;         // caller order
+    const cplx *phr, *phi_i;     // Phi[Re c], Phi[Im c]            (caller order)
+    const cplx *gxq, *gyq;       // grad Phi[q]
+    const cplx *gxr, *gyr, *gxi, *gyi;  // grad Phi[Re c], grad Phi[Im c]
+    const double *qc;            // sorted
+    double *grad_q, *grad_x, *grad_y;
+    cplx *part;                  // [gridDim.x] partial sums of the impedance identity
+    int want_pos;
+};
+
+__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs a) {
+    __shared__ double sr[256], si[256];
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+        const int64_t o = a.perm[i];
+        if (a.grad_q) a.grad_q[o] = a.phr[o].re - a.phi_i[o].im;
+        if (!a.want_pos) continue;
+        const cplx c = mk(a.g[2 * o], -a.g[2 * o + 1]);
+        const double qv = a.q[o];
+        const cplx gcx = a.gxr[o] + mul_ipow(a.gxi[o], 1);
+        const cplx gcy = a.gyr[o] + mul_ipow(a.gyi[o], 1);
+        const cplx Dx = c * a.gxq[o] + qv * gcx;
+        const cplx Dy = c * a.gyq[o] + qv * gcy;
+        if (a.grad_x) a.grad_x[o] = Dx.re;
+        if (a.grad_y) a.grad_y[o] = Dy.re;
+        const cplx v = (a.xs[i] - a.x0) * Dx + a.ys[i] * Dy - kInv2Pi * (a.qc[i] * c);
+        ar += v.re;
+        ai += v.im;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sr[threadIdx.x] += sr[threadIdx.x + off];
+            si[threadIdx.x] += si[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.part[blockIdx.x] = mk(sr[0], si[0]);
+}
+
+static fmmhp_status ensure_bwd(Arena &A, const Tree &T, Sched &S) {
+    if (S.bw.ready) return FMMHP_OK;
+    const size_t n = (size_t)T.n;
+    BwdWork &b = S.bw;
+    FMMHP_CHECK(A.alloc_n(&b.cr, n, "adjoint charges (re)"));
+    FMMHP_CHECK(A.alloc_n(&b.ci, n, "adjoint charges (im)"));
+    FMMHP_CHECK(A.alloc_n(&b.qc, n, "coincident charge sums"));
+    cplx **bufs[] = {&b.phr, &b.phi_i, &b.gxq, &b.gyq, &b.gxr, &b.gyr, &b.gxi, &b.gyi, &b.near_gx, &b.near_gy};
+    for (cplx **pp : bufs) FMMHP_CHECK(A.alloc_n(pp, n, "adjoint fields"));
+    FMMHP_CHECK(A.alloc_n(&b.red, 1025, "adjoint reduction"));
+    b.ready = true;
+    return FMMHP_OK;
+}
+
+fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
+                          double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t s) {
+    FMMHP_CHECK(ensure_bwd(A, T, S));
+    BwdWork &b = S.bw;
+    const bool pos = grad_x || grad_y || zsum_host;
+    if (!pos && !grad_q) return FMMHP_OK;
+    hipLaunchKernelGGL(k_split_conj, dim3(nblk(T.n, 256)), dim3(256), 0, s, g, T.n, b.cr, b.ci);
+    FMMHP_HIP(hipGetLastError());
+    PassOut pr, pi;
+    pr.phi = (double *)b.phr;
+    pi.phi = (double *)b.phi_i;
+    if (pos) {
+        PassOut pq;
+        pq.gx = b.gxq;
+        pq.gy = b.gyq;
+        pq.qc = b.qc;
+        FMMHP_CHECK(run_eval_vec<kGrad>(T, S, q, pq, s));
+        pr.gx = b.gxr;
+        pr.gy = b.gyr;
+        pi.gx = b.gxi;
+        pi.gy = b.gyi;
+        if (grad_q) {
+            FMMHP_CHECK(run_eval_vec<kPhiGrad>(T, S, b.cr, pr, s));
+            FMMHP_CHECK(run_eval_vec<kPhiGrad>(T, S, b.ci, pi, s));
+        } else {
+            FMMHP_CHECK(run_eval_vec<kGrad>(T, S, b.cr, pr, s));
+            FMMHP_CHECK(run_eval_vec<kGrad>(T, S, b.ci, pi, s));
+        }
+    } else {
+        FMMHP_CHECK(run_eval_vec<kPhi>(T, S, b.cr, pr, s));
+        FMMHP_CHECK(run_eval_vec<kPhi>(T, S, b.ci, pi, s));
+    }
+    const int np = (int)std::min<int64_t>(1024, nblk(T.n, 256));
+    BwdArgs ba{T.n,   T.x_lo + 0.5 * T.S, T.xs,  T.ys,  T.perm, q,      g,      b.phr,  b.phi_i, b.gxq, b.gyq,
+               b.gxr, b.gyr,              b.gxi, b.gyi, b.qc,   grad_q, grad_x, grad_y, b.red,   pos ? 1 : 0};
+    hipLaunchKernelGGL(k_bwd_combine, dim3(np), dim3(256), 0, s, ba);
+    FMMHP_HIP(hipGetLastError());
+    if (zsum_host) {
+        hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(256), 0, s, b.red, np);
+        FMMHP_HIP(hipGetLastError());
+        FMMHP_HIP(hipMemcpyAsync(zsum_host, b.red + np, sizeof(cplx), hipMemcpyDeviceToHost, s));
+        FMMHP_HIP(hipStreamSynchronize(s));
+    }
     return FMMHP_OK;
 }
 

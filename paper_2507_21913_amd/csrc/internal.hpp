@@ -82,6 +82,17 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
                         const double *img_x, const double *img_y, int leaf_size, int max_level,
                         hipStream_t stream);
 
+// Adjoint workspace, allocated on the first backward call: [n] per array.
+struct BwdWork {
+    bool ready = false;
+    double *cr = nullptr, *ci = nullptr;  // conj(g) as two real charge vectors (caller order)
+    double *qc = nullptr;                 // coincident charge sums (sorted order)
+    cplx *phr = nullptr, *phi_i = nullptr;
+    cplx *gxq = nullptr, *gyq = nullptr, *gxr = nullptr, *gyr = nullptr, *gxi = nullptr, *gyi = nullptr;
+    cplx *near_gx = nullptr, *near_gy = nullptr;  // near-field gradient (sorted order)
+    cplx *red = nullptr;                  // [1025] reduction partials + result
+};
+
 // Evaluation schedule and tables derived from the tree.
 struct Sched {
     int PB = 0;                     // compiled truncation order
@@ -129,6 +140,7 @@ struct Sched {
     cplx *Lam = nullptr;            // [nloc][PB + 1][nbox]
     double *qs = nullptr;           // [n] sorted charges
     cplx *red = nullptr;            // [1024] reduction partials + result
+    BwdWork bw;
     // algorithmic work counts
     int64_t p2p_pairs[2] = {0, 0};
     int64_t m2l_pairs[2] = {0, 0};
@@ -142,6 +154,9 @@ struct Sched {
 fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, hipStream_t stream);
 fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
+
+fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
+                          double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t stream);
 
 fmmhp_status collect_phase_times(Sched &S);
 fmmhp_status run_direct(int64_t ns, const double *sx, const double *sy, int nvec, const double *q,

@@ -31,6 +31,14 @@ constexpr double kEulerGamma = 0.57721566490153286061;
 constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 with its low 32 bits cleared
 constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
 
+// 1 / x for a positive normal double whose reciprocal is normal: the hardware reciprocal refined by
+// two Newton steps (each squares the relative error).
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Natural logarithm of a positive, finite, normal double.  x = 2^e m with m in [sqrt(1/2), sqrt(2)),
 // log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, and atanh s = s sum_k s^(2k) / (2k + 1)
 // truncated after k = 10 (the first omitted term is below 1e-17 relative).  e ln 2 is added in two

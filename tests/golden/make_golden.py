@@ -1,10 +1,11 @@
 """Write the stored oracle values used by the full-size GPU parity tests and bench.py.
 
-Calls only the CPU oracle (``oracle.direct``) and the seeded generators (``workloads``):
-for each full-size workload, the direct-sum potential at a fixed-seed sample of targets
-against ALL sources, written as text (index, Re phi, Im phi).
+Calls only the CPU oracle (``oracle.direct``, ``oracle.grad``) and the seeded generators
+(``workloads``): for each full-size workload, the direct-sum potential at a fixed-seed sample of
+targets against ALL sources, written as text (index, Re phi, Im phi); for the differentiation
+workload also the direct-sum gradients at a sample of indices (index, dl/dq, dl/dx, dl/dy).
 
-    python tests/golden/make_golden.py [name ...]
+    python tests/golden/make_golden.py [name ... | grad:name ...]
 """
 from __future__ import annotations
 
@@ -50,6 +51,44 @@ def write(name: str) -> str:
     return p
 
 
+GRAD_GOLDEN = {
+    # incoming gradient g = w + i w' of the differentiation workload (loss l = Re sum conj(g) phi)
+    "diff_1m": lambda: workloads.diff_1m(seed=1),
+}
+
+
+def grad_path_for(name: str) -> str:
+    return os.path.join(HERE, f"{name}_grad_sample{N_SAMPLE}.txt")
+
+
+def write_grad(name: str) -> str:
+    from oracle import grad as GR
+    w = GRAD_GOLDEN[name]()
+    g = w.extra["loss_w"] + 1j * w.extra["loss_w_im"]
+    idx = workloads.sample_targets(w.n, N_SAMPLE, seed=4242)
+    t0 = time.time()
+    r = GR.sampled_gradients(w.x, w.y, w.q[0], w.impedance, g, idx)
+    dt = time.time() - t0
+    p = grad_path_for(name)
+    with open(p, "w") as f:
+        f.write(f"# oracle direct-sum gradients, workload {name} (seed 1, N={w.n}, impedance "
+                f"{w.impedance}), g = loss_w + i loss_w_im, {N_SAMPLE} sampled indices x all "
+                f"sources; columns: index dl/dq dl/dx dl/dy\n")
+        for k, i in enumerate(idx):
+            f.write(f"{int(i)} {r['grad_q'][k]:.17e} {r['grad_x'][k]:.17e} {r['grad_y'][k]:.17e}\n")
+    print(f"{name} gradients: {dt:.1f} s -> {p}", flush=True)
+    return p
+
+
+def load_grad(name: str):
+    """(indices, [n, 3] array of dl/dq, dl/dx, dl/dy) from a stored file, or None if absent."""
+    p = grad_path_for(name)
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return a[:, 0].astype(np.int64), a[:, 1:4]
+
+
 def load(name: str):
     """(indices, complex values) from a stored file, or None if absent."""
     p = path_for(name)
@@ -60,5 +99,8 @@ def load(name: str):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(GOLDEN)):
-        write(name)
+    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN]):
+        if name.startswith("grad:"):
+            write_grad(name[5:])
+        else:
+            write(name)

@@ -109,3 +109,14 @@ def test_direct_gradients_subset_matches_full():
     for k in ("grad_q", "grad_x", "grad_y"):
         assert np.allclose(sub[k], full[k][idx], rtol=1e-14, atol=1e-14)
     assert sub["grad_Z"] == pytest.approx(full["grad_Z"], rel=1e-14)
+
+
+def test_sampled_gradients_matches_direct():
+    x, y, q, g = _problem(n=200, seed=5)
+    Z = 1.0 + 0.5j
+    ref = GR.direct_gradients(x, y, q, Z, g)
+    idx = np.array([0, 17, 99, 150, 199])
+    got = GR.sampled_gradients(x, y, q, Z, g, idx, workers=2, want_Z=True)
+    for k in ("grad_q", "grad_x", "grad_y"):
+        assert np.allclose(got[k], ref[k][idx], rtol=1e-12, atol=1e-12)
+    assert abs(got["grad_Z"] - ref["grad_Z"]) <= 1e-12 * abs(ref["grad_Z"])

@@ -89,6 +89,7 @@ def diff_1m(seed: int = 1, n: int = 1 << 20, p: int = 30,
                 leaf_size, name="diff_1m")
     rng = np.random.default_rng(seed + 1000)
     w.extra["loss_w"] = rng.standard_normal(n)
+    w.extra["loss_w_im"] = rng.standard_normal(n)
     return w
 
 
