@@ -4,7 +4,8 @@
 One step = one fmmhp_eval (Algorithm 2: P2M, M2M, M2L, P2L, L2L, L2P + M2P + near field and
 the surface term) over the 1,048,576-point uniform workload (x ~ U[0,1], y ~ U[1e-3, 1.001],
 charges U[-1,1], impedance 1.0) with the plan (tree, lists, tables) already built and all
-inputs resident in device memory.  Prints ONE JSON line.
+inputs resident in device memory.  Prints ONE JSON line.  Extra fields: the p = 30 rate, the
+forward + adjoint rate (fmmhp_backward), plan time, per-phase times.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--tol 1e-10 | --p P --leaf L]
 
@@ -198,6 +199,27 @@ def main():
             res["p30_leaf40"] = {"mpts_s": w.n / (ms30 * 1e-3) / 1e6, "ms_per_step": ms30,
                                  "rel_l2_vs_oracle_sample": rel30}
             plan30.close()
+        # forward + adjoint (dl/dq, dl/dx, dl/dy, dl/dZ) for one incoming gradient, same plan
+        rng = np.random.default_rng(7)
+        gg = torch.as_tensor(rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n), device=dev)
+        for _ in range(2):
+            plan.backward(q, gg, want_lambda=False)
+        torch.cuda.synchronize()
+        nb = max(1, a.steps // 4)
+        e0.record()
+        for _ in range(nb):
+            plan(q, out=out)
+            plan.backward(q, gg, want_lambda=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fb = e0.elapsed_time(e1) / nb
+        t0 = time.perf_counter()
+        plan.backward(q, gg)
+        bwd_lambda_ms = (time.perf_counter() - t0) * 1e3
+        res["fwd_bwd"] = {"mpts_s": w.n / (ms_fb * 1e-3) / 1e6, "ms_per_step": ms_fb,
+                          "bwd_over_fwd": (ms_fb - ms) / ms,
+                          "outputs": "phi; dl/dq, dl/dx, dl/dy",
+                          "bwd_with_dl_dZ_wall_ms": bwd_lambda_ms}
         res["plan_ms"] = plan_ms
         res["plan_plus_eval_mpts_s"] = w.n / ((plan_ms + ms) * 1e-3) / 1e6
         res["phase_ms"] = {k: round(v, 5) for k, v in phase_avg.items()}
