@@ -83,6 +83,7 @@ typedef struct {
     int64_t p2p_pairs[2];   /* near-field (target, source) pairs per charge vector: upper sources,
                                image sources (the U list expanded to points) */
     int64_t m2l_pairs[2];   /* M2L (target box, source box) pairs: upper, image (the V list) */
+    int32_t n_inst;         /* instances (1 for fmmhp_plan_create) */
 } fmmhp_plan_stats;
 
 /* Phases of fmmhp_eval whose device time fmmhp_plan_phase_times reports. */
@@ -119,14 +120,38 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
                                const fmmhp_opts *opts, hipStream_t stream,
                                fmmhp_plan_t *plan_out);
 
-/* Evaluate phi = A q for n_vec real charge vectors (Algorithm 2).
+/* Build a batched plan: n_inst independent problems ("instances") in one forest, each with its own
+ * points, root square and impedance; every evaluation runs all instances in the same launches
+ * (Algorithm 1 per instance).
+ *
+ *   n_inst    number of instances, 1 <= n_inst <= 512
+ *   offsets   [host] [n_inst + 1] point ranges: instance k owns points offsets[k] .. offsets[k+1]-1;
+ *             offsets[0] = 0, strictly increasing (no empty instance), total < 2^31
+ *   x, y      [device] coordinates of all points, instance after instance (y > 0)
+ *   lambda    [host] [n_inst][2] impedance (re, im) of each instance, re > 0, im >= 0
+ *   opts      [host] as for fmmhp_plan_create; with n_inst > 1 the cells have 27 bits per axis, so
+ *             max_level <= 27
+ *
+ * n_inst = 1 gives the same plan as fmmhp_plan_create.  Errors as for fmmhp_plan_create, plus
+ * FMMHP_EINVAL for bad offsets or n_inst.  Sources and targets coincide within each instance;
+ * instances do not interact.
+ */
+fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const double *x,
+                                     const double *y, const double *lambda,
+                                     const fmmhp_opts *opts, hipStream_t stream,
+                                     fmmhp_plan_t *plan_out);
+
+/* Evaluate phi = A q for n_vec real charge vectors (Algorithm 2), over every instance of the plan.
  *
  *   n_vec   number of charge vectors, >= 1
- *   q       [device] charges, [n_vec][n] row-major, real, in the caller's point order
+ *   q       [device] charges, [n_vec][n] row-major, real, in the caller's point order (n = all
+ *           points of all instances)
  *   phi     [device] output, [n_vec][n][2] (re, im) interleaved, caller's point order
  *
- * Complex charges are linear: evaluate their real and imaginary parts as two vectors.
- * No host synchronisation; the plan's workspace is reused across calls.
+ * Vectors are evaluated eight at a time where possible: the near field computes each pair's kernel
+ * once for the eight, the far-field kernels take the vector as a grid dimension.  The first call
+ * with n_vec >= 8 grows the plan's workspace for eight vectors.  Complex charges are linear:
+ * evaluate their real and imaginary parts as two vectors.  No host synchronisation.
  */
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
                         hipStream_t stream);
@@ -140,8 +165,8 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
  *   grad_q     [device] output [n]: dl/dq_j = Re sum_i conj(g_i) G(r_i, r_j), or NULL
  *   grad_x, grad_y  [device] outputs [n]: dl/dx_k, dl/dy_k, or NULL.  A point moves as a target
  *              and as a source; both are included, so are its own image and reaction terms.
- *   grad_lambda [host] output [2]: (dl/dRe Z, dl/dIm Z), or NULL.  When given, the call
- *              synchronises the stream.
+ *   grad_lambda [host] output [n_inst][2]: (dl/dRe Z_k, dl/dIm Z_k) per instance, or NULL.  When
+ *              given, the call synchronises the stream.
  *
  * The potential's gradient fields come from the same expansions as phi (derivatives of the local
  * expansions, the multipole series and the near-field kernels), so their accuracy follows p like

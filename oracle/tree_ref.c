@@ -13,7 +13,8 @@
  *            root square is [x_lo, x_lo + S] x [-S/2, S/2]: symmetric about y = 0,
  *            so every box below the root lies wholly in one half plane, and the
  *            lower half is the exact mirror image of the upper half.
- *  Cells     L = 30 bits per axis, scale = 2^L / S (one IEEE division).
+ *  Cells     L = 30 bits per axis (27 for an instance of a forest), scale = 2^L / S (one
+ *            IEEE division).
  *            ix = clamp(floor((x - x_lo) * scale), 0, 2^L - 1)
  *            iy_up = clamp(floor(y * scale), 0, 2^(L-1) - 1)
  *            iy = 2^(L-1) + iy_up for a point, 2^(L-1) - 1 - iy_up for its image.
@@ -46,7 +47,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define LBITS 30
+/* Cell bits per axis of the build in progress (set by tree_ref_build; one build at a time). */
+static int LBITS = 30;
 
 typedef struct Node {
     int level;
@@ -252,7 +254,9 @@ void tree_ref_free(TreeRef *t) {
 
 /* Build the tree and lists.  Returns NULL on allocation failure or bad input. */
 TreeRef *tree_ref_build(int64_t n, const double *x, const double *y, int leaf_size,
-                        int max_level) {
+                        int max_level, int lbits) {
+    if (lbits < 2 || lbits > 30) return NULL;
+    LBITS = lbits;
     if (n <= 0 || leaf_size < 1 || max_level < 1 || max_level > LBITS) return NULL;
     TreeRef *t = (TreeRef *)calloc(1, sizeof(TreeRef));
     if (!t) return NULL;

@@ -47,7 +47,8 @@ class PlanStats(ctypes.Structure):
                 ("S", ctypes.c_double), ("scale", ctypes.c_double),
                 ("lambda_re", ctypes.c_double), ("lambda_im", ctypes.c_double),
                 ("real_impedance", ctypes.c_int), ("device_bytes", ctypes.c_int64),
-                ("p2p_pairs", ctypes.c_int64 * 2), ("m2l_pairs", ctypes.c_int64 * 2)]
+                ("p2p_pairs", ctypes.c_int64 * 2), ("m2l_pairs", ctypes.c_int64 * 2),
+                ("n_inst", ctypes.c_int32)]
 
 
 PHASES = ("p2m", "m2m", "m2l", "p2l", "l2l", "surface", "leaf", "near")
@@ -62,6 +63,7 @@ _INT = ctypes.c_int
 _SIGNATURES = {
     "fmmhp_plan_create": [_I64, _P, _P, _P, _P, _D, _D, ctypes.POINTER(Opts), _P,
                           ctypes.POINTER(_P)],
+    "fmmhp_batch_plan_create": [_INT, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(_P)],
     "fmmhp_eval": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
@@ -129,17 +131,29 @@ def fmmhp_plan_create(n, x_ptr, y_ptr, img_x_ptr, img_y_ptr, lambda_re, lambda_i
     return h
 
 
+def fmmhp_batch_plan_create(n_inst, offsets, x_ptr, y_ptr, lambdas, opts, stream):
+    """offsets: sequence of n_inst + 1 ints; lambdas: sequence of n_inst complex impedances."""
+    h = _P()
+    off = (_I64 * (n_inst + 1))(*[int(v) for v in offsets])
+    lam = (_D * (2 * n_inst))(*[v for z in lambdas for v in (complex(z).real, complex(z).imag)])
+    st = lib().fmmhp_batch_plan_create(n_inst, ctypes.cast(off, _P), x_ptr, y_ptr, ctypes.cast(lam, _P),
+                                       ctypes.byref(opts) if opts is not None else None, stream,
+                                       ctypes.byref(h))
+    _check("fmmhp_batch_plan_create", st)
+    return h
+
+
 def fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream):
     _check("fmmhp_eval", lib().fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream))
 
 
 def fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr, grad_y_ptr, want_lambda,
-                   stream):
-    """Returns (dl/dRe Z, dl/dIm Z) when want_lambda, else None."""
-    gl = (_D * 2)() if want_lambda else None
+                   stream, n_inst=1):
+    """Returns [(dl/dRe Z_k, dl/dIm Z_k)] per instance when want_lambda, else None."""
+    gl = (_D * (2 * n_inst))() if want_lambda else None
     _check("fmmhp_backward", lib().fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr,
                                                   grad_y_ptr, gl, stream))
-    return (gl[0], gl[1]) if want_lambda else None
+    return [(gl[2 * k], gl[2 * k + 1]) for k in range(n_inst)] if want_lambda else None
 
 
 def fmmhp_plan_info(plan) -> dict:
@@ -257,6 +271,33 @@ class HalfPlaneFMM:
                 self._plan = fmmhp_plan_create(self.n, x.data_ptr(), y.data_ptr(), None, None,
                                                lr, li, opts, _stream())
         self.impedance = complex(lr, li)
+        self.n_inst = 1
+
+    @classmethod
+    def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0):
+        """A forest plan over n_inst independent instances: points offsets[k]..offsets[k+1]-1 of
+        (x, y) form instance k with impedance impedances[k].  Evaluation takes charges for all
+        points (instance after instance) and runs every instance in the same launches."""
+        self = cls.__new__(cls)
+        x = _dev_f64(x, "x")
+        y = _dev_f64(y, "y")
+        self.n = int(x.shape[0])
+        self.device = x.device
+        self._x, self._y = x, y
+        offsets = [int(v) for v in offsets]
+        if len(offsets) < 2 or offsets[-1] != self.n:
+            raise ValueError("offsets must have n_inst + 1 entries ending at the point count")
+        self.n_inst = len(offsets) - 1
+        self.offsets = offsets
+        imps = [complex(z) for z in impedances]
+        if len(imps) != self.n_inst:
+            raise ValueError("one impedance per instance")
+        opts = Opts(int(p), int(leaf_size), int(max_level), 0)
+        with torch.cuda.device(self.device):
+            self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,
+                                                 opts, _stream())
+        self.impedance = imps[0] if self.n_inst == 1 else imps
+        return self
 
     def info(self) -> dict:
         return fmmhp_plan_info(self._plan)
@@ -324,9 +365,10 @@ class HalfPlaneFMM:
                 ptr[k] = None
         with torch.cuda.device(self.device):
             gl = fmmhp_backward(self._plan, qd.data_ptr(), gr.data_ptr(), ptr["q"], ptr["x"],
-                                ptr["y"], bool(want_lambda), _stream())
+                                ptr["y"], bool(want_lambda), _stream(), self.n_inst)
         if want_lambda:
-            out["lambda"] = complex(gl[0], gl[1])
+            lam = [complex(a, b) for a, b in gl]
+            out["lambda"] = lam[0] if self.n_inst == 1 else lam
         return out
 
     def close(self):
@@ -417,4 +459,4 @@ __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functi
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
            "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune",
-           "fmmhp_backward", "potential"]
+           "fmmhp_backward", "potential", "fmmhp_batch_plan_create"]

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -74,6 +75,60 @@ const char *fmmhp_status_string(fmmhp_status s) {
 
 const char *fmmhp_last_error_message(void) { return g_msg; }
 
+// Shared by the plain and batched plan builders: n_inst instances, point ranges off[0..n_inst].
+static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x, const double *y,
+                                const double *img_x, const double *img_y, const cplx *Zs, const fmmhp_opts *opts,
+                                hipStream_t stream, fmmhp_plan_t *plan_out) {
+    const int lb = n_inst == 1 ? kLBits : kLBitsForest;
+    fmmhp_opts o{20, 40, lb, 0};
+    if (opts) o = *opts;
+    if (o.max_level == 0) o.max_level = lb;
+    if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb || o.flags != 0) {
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (0)", o.p,
+                  FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags);
+        return FMMHP_EINVAL;
+    }
+    fmmhp_plan_s *p = new (std::nothrow) fmmhp_plan_s();
+    if (!p) {
+        set_error("host allocation of the plan failed");
+        return FMMHP_ENOMEM;
+    }
+    p->magic = kMagic;
+    p->p_req = o.p;
+    p->leaf_size = o.leaf_size;
+    p->max_level = o.max_level;
+    p->lambda_re = Zs[0].re;
+    p->lambda_im = Zs[0].im;
+    p->Zs.assign(Zs, Zs + n_inst);
+    fmmhp_status st = FMMHP_OK;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        st = FMMHP_EHIP;
+    }
+    if (st == FMMHP_OK)
+        st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
+    if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
+    if (st == FMMHP_OK) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            set_error("plan build failed on the device: %s", hipGetErrorString(e));
+            st = FMMHP_EHIP;
+        }
+    }
+    if (st != FMMHP_OK) {
+        (void)hipStreamSynchronize(stream);
+        if (p->sched.ev_fork) (void)hipEventDestroy(p->sched.ev_fork);
+        if (p->sched.ev_join) (void)hipEventDestroy(p->sched.ev_join);
+        if (p->sched.side) (void)hipStreamDestroy(p->sched.side);
+        p->arena.release();
+        p->magic = kDead;
+        delete p;
+        return st;
+    }
+    *plan_out = p;
+    return FMMHP_OK;
+}
+
 fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, const double *img_x,
                                const double *img_y, double lambda_re, double lambda_im, const fmmhp_opts *opts,
                                hipStream_t stream, fmmhp_plan_t *plan_out) {
@@ -96,53 +151,47 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
         return FMMHP_EINVAL;
     }
     FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
-    fmmhp_opts o{20, 40, 30, 0};
-    if (opts) o = *opts;
-    if (o.max_level == 0) o.max_level = 30;
-    if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > 30 || o.flags != 0) {
-        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..30), flags=%u (0)",
-                  o.p, FMMHP_MAX_P, o.leaf_size, o.max_level, o.flags);
+    const int64_t off[2] = {0, n};
+    const cplx Z = mk(lambda_re, lambda_im);
+    return create_plan(1, off, x, y, img_x, img_y, &Z, opts, stream, plan_out);
+}
+
+fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const double *x, const double *y,
+                                     const double *lambda, const fmmhp_opts *opts, hipStream_t stream,
+                                     fmmhp_plan_t *plan_out) {
+    g_msg[0] = 0;
+    if (!plan_out) {
+        set_error("plan_out is NULL");
         return FMMHP_EINVAL;
     }
-    fmmhp_plan_s *p = new (std::nothrow) fmmhp_plan_s();
-    if (!p) {
-        set_error("host allocation of the plan failed");
-        return FMMHP_ENOMEM;
+    *plan_out = nullptr;
+    if (n_inst < 1 || n_inst > kMaxInstances) {
+        set_error("n_inst = %d outside [1, %d]", n_inst, kMaxInstances);
+        return FMMHP_EINVAL;
     }
-    p->magic = kMagic;
-    p->p_req = o.p;
-    p->leaf_size = o.leaf_size;
-    p->max_level = o.max_level;
-    p->lambda_re = lambda_re;
-    p->lambda_im = lambda_im;
-    fmmhp_status st = FMMHP_OK;
-    if (hipGetDevice(&p->device) != hipSuccess) {
-        set_error("hipGetDevice failed");
-        st = FMMHP_EHIP;
+    if (!offsets || !x || !y || !lambda) {
+        set_error("offsets, x, y and lambda must be non-NULL");
+        return FMMHP_EINVAL;
     }
-    if (st == FMMHP_OK)
-        st = build_tree(p->arena, p->tree, n, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
-    if (st == FMMHP_OK)
-        st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), mk(lambda_re, lambda_im), stream);
-    if (st == FMMHP_OK) {
-        hipError_t e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) {
-            set_error("plan build failed on the device: %s", hipGetErrorString(e));
-            st = FMMHP_EHIP;
+    if (offsets[0] != 0) {
+        set_error("offsets[0] must be 0");
+        return FMMHP_EINVAL;
+    }
+    for (int k = 0; k < n_inst; ++k)
+        if (offsets[k + 1] <= offsets[k]) {
+            set_error("instance %d is empty or offsets decrease", k);
+            return FMMHP_EINVAL;
         }
+    if (offsets[n_inst] >= ((int64_t)1 << 31)) {
+        set_error("total point count %lld outside [1, 2^31)", (long long)offsets[n_inst]);
+        return FMMHP_EINVAL;
     }
-    if (st != FMMHP_OK) {
-        (void)hipStreamSynchronize(stream);
-        if (p->sched.ev_fork) (void)hipEventDestroy(p->sched.ev_fork);
-        if (p->sched.ev_join) (void)hipEventDestroy(p->sched.ev_join);
-        if (p->sched.side) (void)hipStreamDestroy(p->sched.side);
-        p->arena.release();
-        p->magic = kDead;
-        delete p;
-        return st;
+    std::vector<cplx> Zs(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        FMMHP_CHECK(check_impedance(lambda[2 * k], lambda[2 * k + 1]));
+        Zs[k] = mk(lambda[2 * k], lambda[2 * k + 1]);
     }
-    *plan_out = p;
-    return FMMHP_OK;
+    return create_plan(n_inst, offsets, x, y, nullptr, nullptr, Zs.data(), opts, stream, plan_out);
 }
 
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipStream_t stream) {
@@ -151,7 +200,7 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
         set_error("n_vec must be >= 1 and q, phi non-NULL");
         return FMMHP_EINVAL;
     }
-    return run_eval(plan->tree, plan->sched, n_vec, q, phi, stream);
+    return run_eval(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
 fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
@@ -161,14 +210,16 @@ fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *gr
         set_error("q and grad_phi must be non-NULL");
         return FMMHP_EINVAL;
     }
-    cplx zsum{0.0, 0.0};
+    std::vector<cplx> zsum(plan->tree.n_inst, mk(0.0, 0.0));
     FMMHP_CHECK(run_backward(plan->arena, plan->tree, plan->sched, q, grad_phi, grad_q, grad_x, grad_y,
-                             grad_lambda ? &zsum : nullptr, stream));
+                             grad_lambda ? zsum.data() : nullptr, stream));
     if (grad_lambda) {
-        // dl_c/dZ = zsum / Z;  (dl/dRe Z, dl/dIm Z) = (Re, -Im) of it
-        const cplx d = zsum * inv(plan->sched.Z);
-        grad_lambda[0] = d.re;
-        grad_lambda[1] = -d.im;
+        // per instance: dl_c/dZ_k = zsum_k / Z_k;  (dl/dRe Z_k, dl/dIm Z_k) = (Re, -Im) of it
+        for (int k = 0; k < plan->tree.n_inst; ++k) {
+            const cplx d = zsum[k] * inv(plan->Zs[k]);
+            grad_lambda[2 * k] = d.re;
+            grad_lambda[2 * k + 1] = -d.im;
+        }
     }
     return FMMHP_OK;
 }
@@ -196,6 +247,7 @@ fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {
     st->lambda_im = plan->lambda_im;
     st->real_impedance = plan->sched.real_Z ? 1 : 0;
     st->device_bytes = plan->arena.bytes;
+    st->n_inst = T.n_inst;
     for (int k = 0; k < 2; ++k) {
         st->p2p_pairs[k] = plan->sched.p2p_pairs[k];
         st->m2l_pairs[k] = plan->sched.m2l_pairs[k];

@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <complex>
 
@@ -50,6 +51,9 @@ static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1
 struct Geo {
     double x_lo, S;
 };
+
+// Root square and impedance of each instance (one for a plain plan).
+__device__ __forceinline__ Geo geo_of(const InstInfo *ii, int k) { return Geo{ii[k].x_lo, ii[k].S}; }
 
 __device__ __forceinline__ double side_of(const Geo &g, int l) { return ldexp(g.S, -l); }
 __device__ __forceinline__ cplx centre_of(const Geo &g, int l, int bx, int by) {
@@ -94,17 +98,21 @@ __global__ void k_pack_xy(const double *__restrict__ xs, const double *__restric
 // ---------------------------------------------------------------------------------------------
 // Charges into sorted order
 // ---------------------------------------------------------------------------------------------
-__global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n,
+// nv charge vectors [nv][n] (caller order) -> qs[i * nv + v] (sorted, vectors interleaved)
+__global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n, int nv,
                            double *__restrict__ qs) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) qs[i] = q[perm[i]];
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    for (int v = 0; v < nv; ++v) qs[i * nv + v] = q[(int64_t)v * n + o];
 }
 
 // ---------------------------------------------------------------------------------------------
 // P2M: leaves
 // ---------------------------------------------------------------------------------------------
 template <int PB>
-__global__ __launch_bounds__(64) void k_p2m(Geo g, const int32_t *__restrict__ leaves, int nleaf, int nbox,
+__global__ __launch_bounds__(64) void k_p2m(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
+                                            const int32_t *__restrict__ leaves, int nleaf, int nbox, int nv,
                                             const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
                                             const int32_t *__restrict__ by, const int32_t *__restrict__ first,
                                             const int32_t *__restrict__ count, const double *__restrict__ xs,
@@ -112,8 +120,11 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const int32_t *__restrict__ l
                                             cplx *__restrict__ W) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nleaf) return;
+    const int v = blockIdx.y;  // charge vector
+    W += (int64_t)v * (PB + 1) * nbox;
     const int b = leaves[t];
     const int l = level[b];
+    const Geo g = geo_of(ii, inst[b]);
     const cplx c = centre_of(g, l, bx[b], by[b]);
     const double irho = 2.0 / side_of(g, l);
     cplx w[PB + 1];
@@ -122,7 +133,7 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const int32_t *__restrict__ l
     const int f = first[b], e = f + count[b];
     for (int j = f; j < e; ++j) {
         const cplx mz = mk((c.re - xs[j]) * irho, (c.im - ys[j]) * irho);  // -(z_j - c) / rho
-        cplx term = mk(qs[j], 0.0);
+        cplx term = mk(qs[(int64_t)j * nv + v], 0.0);
 #pragma unroll
         for (int n = 0; n <= PB; ++n) {
             w[n] += term;
@@ -149,6 +160,7 @@ __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int
     __shared__ cplx sw[(PB + 1) * 4 * kM2MParents];
     __shared__ cplx sE[4 * (PB + 1)];
     __shared__ int s_range[2];
+    W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
     const int p0 = lo + blockIdx.x * kM2MParents;
     const int p1 = min(p0 + kM2MParents, lo + nb);
     if (threadIdx.x == 0) {
@@ -197,9 +209,9 @@ struct M2LArgs {
     const int16_t *tile_slot;
     const uint64_t *tile_mask;
     const cplx *Tfree, *Lfree;
-    const double *loglev;
-    const cplx *W;
-    cplx *Lam;     // [nloc][PB + 1][nbox]
+    const double *logside;   // [nbox] log(side) of each box
+    const cplx *W;           // [nv][PB + 1][nbox]
+    cplx *Lam;               // [nv][nloc][PB + 1][nbox]
     int nloc;
 };
 
@@ -218,8 +230,9 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
     const int n0 = wave * CH;
     const int lane = threadIdx.x & 63;
     const int b = a.tiles[tile * kTile + lane];
-    const int l = a.tile_level[tile];
-    const double ll = a.loglev[l] * kInv4Pi;
+    const double ll = b >= 0 ? a.logside[b] * kInv4Pi : 0.0;
+    const cplx *W = a.W + (int64_t)blockIdx.y * (PB + 1) * a.nbox;            // charge vector
+    cplx *Lam = a.Lam + (int64_t)blockIdx.y * a.nloc * (PB + 1) * a.nbox;
     const int s0 = a.tile_src_off[tile];
     const int ns = a.tile_src_off[tile + 1] - s0;
     const uint64_t mask = a.tile_mask[tile];
@@ -235,7 +248,7 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
         __syncthreads();
         for (int idx = threadIdx.x; idx < mc * ns; idx += 64 * m2l_waves(PB)) {
             const int mm = idx / ns, sj = idx - mm * ns;
-            sW[idx] = a.W[(int64_t)(m0 + mm) * a.nbox + a.tile_src[s0 + sj]];
+            sW[idx] = W[(int64_t)(m0 + mm) * a.nbox + a.tile_src[s0 + sj]];
         }
         __syncthreads();
         uint64_t rest = mask;
@@ -265,8 +278,8 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
         if (n <= PB) {
             cplx v = -acc[k];
             if (n == 0) v += acc0;
-            a.Lam[(int64_t)n * a.nbox + b] = v;
-            if (a.nloc == 2) a.Lam[stride + (int64_t)n * a.nbox + b] = v;
+            Lam[(int64_t)n * a.nbox + b] = v;
+            if (a.nloc == 2) Lam[stride + (int64_t)n * a.nbox + b] = v;
         }
     }
 }
@@ -276,18 +289,20 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
 // written by k_m2l.
 template <int PB>
 __global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restrict__ ibox, int nbox, int nloc,
-                                                 const int32_t *__restrict__ level,
+                                                 const int32_t *__restrict__ ibase,
                                                  const int32_t *__restrict__ vimg_off,
                                                  const int32_t *__restrict__ vimg_ent, const cplx *__restrict__ TH,
                                                  const cplx *__restrict__ TG, const cplx *__restrict__ Limg,
-                                                 const double *__restrict__ loglev, const cplx *__restrict__ W,
+                                                 const double *__restrict__ logside, const cplx *__restrict__ W,
                                                  cplx *__restrict__ Lam) {
     constexpr int NTP = m2l_row(PB);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nib * (PB + 1)) return;
+    W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
+    Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;
     const int b = ibox[t % nib], n = t / nib;
-    const int l = level[b];
-    const double ll = loglev[l] * kInv4Pi;
+    const int l = ibase[b];  // table block of the box's (instance, level)
+    const double ll = logside[b] * kInv4Pi;
     cplx aH = mk(0.0, 0.0), aG = mk(0.0, 0.0), a0 = mk(0.0, 0.0);
     for (int e = vimg_off[b]; e < vimg_off[b + 1]; ++e) {
         const int code = vimg_ent[e];
@@ -306,12 +321,12 @@ __global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restr
     if (nloc == 2) Lam[(int64_t)(PB + 1) * nbox + (int64_t)n * nbox + b] += a0 - aG;
 }
 
-__global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nloc, cplx *__restrict__ Lam) {
+__global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nrow, cplx *__restrict__ Lam) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nb = hi - lo;
-    if (i >= nb * ncoef * nloc) return;
+    if (i >= nb * ncoef * nrow) return;
     const int b = lo + i % nb;
-    const int r = i / nb;  // loc * ncoef + n
+    const int r = i / nb;  // (vector * nloc + loc) * ncoef + n
     Lam[(int64_t)r * nbox + b] = mk(0.0, 0.0);
 }
 
@@ -321,7 +336,8 @@ __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nloc, cplx *
 // coefficient n over the chunk in a fixed order.
 // ---------------------------------------------------------------------------------------------
 template <int PB>
-__global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, const int32_t *__restrict__ xbox, int nbox,
+__global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst, int nv,
+                                            int nloc, int loc, const int32_t *__restrict__ xbox, int nbox,
                                             const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
                                             const int32_t *__restrict__ by, const int32_t *__restrict__ first,
                                             const int32_t *__restrict__ count, const int32_t *__restrict__ xoff,
@@ -330,8 +346,11 @@ __global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, const int32_
                                             const double *__restrict__ fact, cplx *__restrict__ Lam) {
     __shared__ cplx contrib[64][PB + 1];
     const int b = xbox[blockIdx.x];
+    const int v = blockIdx.y;  // charge vector
     const int lane = threadIdx.x;
     const int l = level[b];
+    const Geo g = geo_of(ii, inst[b]);
+    const cplx Z = ii[inst[b]].Z;
     const cplx cb = centre_of(g, l, bx[b], by[b]);
     const double rho = 0.5 * side_of(g, l);
     cplx acc = mk(0.0, 0.0);
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, const int32_
             const int j = jb + lane;
             cplx *out = contrib[lane];
             if (j < j1) {
-                const double q = qs[j];
+                const double q = qs[(int64_t)j * nv + v];
                 const double yj = img ? -ys[j] : ys[j];
                 const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
                 const double sgn = img ? 1.0 : -1.0;            // -(1/4pi) upper, +(1/4pi) image
@@ -380,7 +399,7 @@ __global__ __launch_bounds__(64) void k_p2l(Geo g, cplx Z, int loc, const int32_
             __syncthreads();
         }
     }
-    if (lane <= PB) Lam[(int64_t)loc * (PB + 1) * nbox + (int64_t)lane * nbox + b] += acc;
+    if (lane <= PB) Lam[((int64_t)v * nloc + loc) * (PB + 1) * nbox + (int64_t)lane * nbox + b] += acc;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -396,6 +415,7 @@ __global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc,
                                              const cplx *__restrict__ E, cplx *__restrict__ Lam) {
     __shared__ cplx sl[(PB + 1) * kL2LChildren];
     __shared__ cplx sE[4 * (PB + 1)];
+    Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;  // charge vector
     const int c0 = lo + blockIdx.x * kL2LChildren;
     const int nc = min(kL2LChildren, lo + nb - c0);
     for (int k = threadIdx.x; k < 4 * (PB + 1); k += 256) sE[k] = E[k];
@@ -421,22 +441,14 @@ __global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc,
 }
 
 // ---------------------------------------------------------------------------------------------
-// Surface term for a real impedance: s = sum_j q_j exp(-Z (y_j - i x_j))
+// Surface term for a real impedance: s_k = sum_{j in instance k} q_j exp(-Z_k (y_j - i x_j)) per
+// instance and charge vector.  Partial sums over point chunks that never straddle instances, then
+// a fixed-order sum over each instance's chunks.
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict__ xs, const double *__restrict__ ys,
-                                                       const double *__restrict__ qs, int64_t n, double Z,
-                                                       cplx *__restrict__ part) {
+__device__ __forceinline__ cplx block_sum(cplx v) {
     __shared__ double sr[256], si[256];
-    double ar = 0.0, ai = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const double e = qs[i] * exp(-Z * ys[i]);
-        double s, c;
-        sincos(Z * xs[i], &s, &c);
-        ar += e * c;
-        ai += e * s;
-    }
-    sr[threadIdx.x] = ar;
-    si[threadIdx.x] = ai;
+    sr[threadIdx.x] = v.re;
+    si[threadIdx.x] = v.im;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) {
@@ -445,27 +457,40 @@ __global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict_
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = mk(sr[0], si[0]);
+    return mk(sr[0], si[0]);
 }
 
-__global__ __launch_bounds__(256) void k_rank1_final(cplx *__restrict__ part, int np) {
-    __shared__ double sr[256], si[256];
+__global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict__ xs, const double *__restrict__ ys,
+                                                       const double *__restrict__ qs, int nv,
+                                                       const PtChunk *__restrict__ ch, int nch,
+                                                       const InstInfo *__restrict__ ii, cplx *__restrict__ part) {
+    const PtChunk c = ch[blockIdx.x];
+    const int v = blockIdx.y;
+    const double Z = ii[c.inst].Z.re;
     double ar = 0.0, ai = 0.0;
-    for (int k = threadIdx.x; k < np; k += 256) {
-        ar += part[k].re;
-        ai += part[k].im;
+    for (int64_t i = c.start + threadIdx.x; i < c.end; i += 256) {
+        const double e = qs[i * nv + v] * exp(-Z * ys[i]);
+        double sn, cs;
+        sincos(Z * xs[i], &sn, &cs);
+        ar += e * cs;
+        ai += e * sn;
     }
-    sr[threadIdx.x] = ar;
-    si[threadIdx.x] = ai;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sr[threadIdx.x] += sr[threadIdx.x + off];
-            si[threadIdx.x] += si[threadIdx.x + off];
-        }
-        __syncthreads();
+    const cplx t = block_sum(mk(ar, ai));
+    if (threadIdx.x == 0) part[(int64_t)v * nch + blockIdx.x] = t;
+}
+
+// out[v][k] = sum of part[v][c] over the chunks c of instance k, in chunk order
+__global__ __launch_bounds__(256) void k_rank1_final(const cplx *__restrict__ part, int nch,
+                                                     const int32_t *__restrict__ inst_ch, int n_inst,
+                                                     cplx *__restrict__ out) {
+    const int k = blockIdx.x, v = blockIdx.y;
+    double ar = 0.0, ai = 0.0;
+    for (int c = inst_ch[k] + threadIdx.x; c < inst_ch[k + 1]; c += 256) {
+        ar += part[(int64_t)v * nch + c].re;
+        ai += part[(int64_t)v * nch + c].im;
     }
-    if (threadIdx.x == 0) part[np] = mk(sr[0], si[0]);
+    const cplx t = block_sum(mk(ar, ai));
+    if (threadIdx.x == 0) out[(int64_t)v * n_inst + k] = t;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -487,8 +512,10 @@ __host__ __device__ constexpr bool has_phi(int m) { return m != kGrad; }
 __host__ __device__ constexpr bool has_grad(int m) { return m != kPhi; }
 
 struct LeafArgs {
-    Geo g;
-    cplx Z;
+    const InstInfo *ii;      // [n_inst]
+    const int32_t *inst;     // box -> instance
+    int n_inst;
+    int nv;                  // charge vectors in this pass (interleaved in qs)
     int64_t n;
     int nbox, nloc;
     const double *xs, *ys, *qs;
@@ -497,21 +524,23 @@ struct LeafArgs {
     const int32_t *uoff, *uent, *woff, *went;
     const cplx *W, *Lam;
     const double *invfact, *fact;
-    const cplx *rank1;   // device scalar (real impedance) or null
+    const cplx *rank1;       // [nv][n_inst] surface sums (real impedance) or null
     const int32_t *wpts;     // targets whose leaf has a W list
     int64_t n_wpts;
     const int32_t *rpts;     // targets whose leaf has image U entries
     const double2 *logtab;   // [kLogTable] (1/c_k, -log(1/c_k))
-    double2 *near;           // [n] near-field potential per sorted target
+    double2 *near;           // [nv][n] near-field potential per sorted target
     cplx *near_gx, *near_gy; // [n] near-field gradient per sorted target (gradient modes)
     double *qc;              // [n] sum of the charges coincident with each sorted target, or null
-    double *phi;             // [n][2] potential, caller order (potential modes)
+    double *phi;             // [nv][n][2] potential, caller order (potential modes)
     cplx *gx, *gy;           // [n] gradient, caller order (gradient modes)
 };
 
-// Near field, log terms of the U list: one thread per target (sorted order).
-template <int MODE>
+// Near field, log terms of the U list: one thread per target (sorted order).  NV charge vectors
+// share each pair's kernel value.
+template <int MODE, int NV>
 __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
+    static_assert(NV == 1 || MODE == kPhi, "several vectors in the potential mode only");
     __shared__ double2 s_logtab[kLogTable];
     if (has_phi(MODE)) {
         if (threadIdx.x < kLogTable) s_logtab[threadIdx.x] = a.logtab[threadIdx.x];
@@ -522,10 +551,13 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     const int b = a.leaf_of[i];
     const double2 pi = a.xy[i];
     const double x = pi.x, y = pi.y;
-    double lfree = 0.0, limg = 0.0;
+    double lfree[NV], limg[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lfree[v] = limg[v] = 0.0;
     double fx = 0.0, fy = 0.0, mx = 0.0, my = 0.0, qc = 0.0;
     const double2 *__restrict__ xy = a.xy;
     const double2 *__restrict__ tab = s_logtab;
+    const double *__restrict__ qs = a.qs;
     for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
         const int code = a.uent[e];
         const int c = code >> 1;
@@ -535,14 +567,17 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 const double2 pj = xy[j];
                 const double dx = x - pj.x, dy = y - pj.y;
                 const double r2 = fma(dx, dx, dy * dy);
-                const bool nz = r2 > 0.0;
-                const double qj = a.qs[j];
-                const double qm = nz ? qj : 0.0;  // skip the self pair (eq. (1.2))
-                if (has_phi(MODE)) lfree = fma(qm, log_tab(nz ? r2 : 1.0, tab), lfree);
+                const bool nz = r2 > 0.0;  // skip the self pair (eq. (1.2))
+                if (has_phi(MODE)) {
+                    const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
+                }
                 if (has_grad(MODE)) {
-                    const double s = qm * rcp_pos(nz ? r2 : 1.0);
-                    fx = fma(s, dx, fx);
-                    fy = fma(s, dy, fy);
+                    const double qj = qs[j];
+                    const double sc = (nz ? qj : 0.0) * rcp_pos(nz ? r2 : 1.0);
+                    fx = fma(sc, dx, fx);
+                    fy = fma(sc, dy, fy);
                     qc += nz ? 0.0 : qj;
                 }
             }
@@ -551,17 +586,23 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 const double2 pj = xy[j];
                 const double dx = x - pj.x, dy = y + pj.y;
                 const double r2 = fma(dx, dx, dy * dy);
-                const double qj = a.qs[j];
-                if (has_phi(MODE)) limg = fma(qj, log_tab(r2, tab), limg);
+                if (has_phi(MODE)) {
+                    const double lg = log_tab(r2, tab);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
+                }
                 if (has_grad(MODE)) {
-                    const double s = qj * rcp_pos(r2);
-                    mx = fma(s, dx, mx);
-                    my = fma(s, dy, my);
+                    const double sc = qs[j] * rcp_pos(r2);
+                    mx = fma(sc, dx, mx);
+                    my = fma(sc, dy, my);
                 }
             }
         }
     }
-    if (has_phi(MODE)) a.near[i] = make_double2(kInv4Pi * (limg - lfree), 0.0);
+    if (has_phi(MODE)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
+    }
     if (has_grad(MODE)) {
         a.near_gx[i] = mk(kInv2Pi * (mx - fx), 0.0);
         a.near_gy[i] = mk(kInv2Pi * (my - fy), 0.0);
@@ -574,16 +615,20 @@ template <int PB, int MODE>
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
+    const int v = blockIdx.y;  // charge vector
     const int b = a.leaf_of[i];
     const int l = a.level[b];
+    const int k = a.inst[b];
+    const Geo g = geo_of(a.ii, k);
+    const cplx Zk = a.ii[k].Z;
     const double x = a.xs[i], y = a.ys[i];
-    const cplx cb = centre_of(a.g, l, a.bx[b], a.by[b]);
-    const double irho = 2.0 / side_of(a.g, l);
+    const cplx cb = centre_of(g, l, a.bx[b], a.by[b]);
+    const double irho = 2.0 / side_of(g, l);
     // L2P: H(z) = sum_n lambda_n / n! zeta^n, H'(z) = irho sum_{n>=1} lambda_n / (n-1)! zeta^(n-1)
     const cplx zeta = mk((x - cb.re) * irho, (y - cb.im) * irho);
     cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0), Hd = mk(0.0, 0.0), Gd = mk(0.0, 0.0);
     for (int loc = 0; loc < a.nloc; ++loc) {
-        const cplx *L = a.Lam + (int64_t)loc * (PB + 1) * a.nbox + b;
+        const cplx *L = a.Lam + ((int64_t)v * a.nloc + loc) * (PB + 1) * a.nbox + b;
         cplx h = mk(0.0, 0.0), hd = mk(0.0, 0.0);
 #pragma unroll
         for (int n = PB; n >= 0; --n) {
@@ -609,19 +654,20 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     }
     const int64_t o = a.perm[i];
     cplx E = mk(0.0, 0.0);  // e^{-Z(y + ix)} s (real impedance)
-    if (a.nloc == 1) E = cexp_(-(a.Z * mk(y, x))) * (*a.rank1);
+    if (a.nloc == 1) E = cexp_(-(Zk * mk(y, x))) * a.rank1[(int64_t)v * a.n_inst + k];
     if (has_phi(MODE)) {
-        const double2 nr = a.near[i];
+        const double2 nr = a.near[(int64_t)v * a.n + i];
         cplx phi;
         if (a.nloc == 1) phi = mk(2.0 * H.re + nr.x, nr.y) + mul_ipow(E, 1);
         else phi = H + conj(G) + mk(nr.x, nr.y);
-        a.phi[2 * o] = phi.re;
-        a.phi[2 * o + 1] = phi.im;
+        double *out = a.phi + (int64_t)v * 2 * a.n;
+        out[2 * o] = phi.re;
+        out[2 * o + 1] = phi.im;
     }
     if (has_grad(MODE)) {
         cplx gx = a.near_gx[i], gy = a.near_gy[i];
         if (a.nloc == 1) {
-            const cplx ZE = a.Z * E;
+            const cplx ZE = Zk * E;
             gx += mk(2.0 * Hd.re, 0.0) + ZE;
             gy += mk(-2.0 * Hd.im, 0.0) + mul_ipow(ZE, 3);
         } else {
@@ -639,8 +685,12 @@ template <int PB, int MODE>
 __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n_wpts) return;
+    const int v = blockIdx.y;  // charge vector
+    const cplx *__restrict__ Wv = a.W + (int64_t)v * (PB + 1) * a.nbox;
     const int64_t i = a.wpts[t];
     const int b = a.leaf_of[i];
+    const Geo g = geo_of(a.ii, a.inst[b]);
+    const cplx Zk = a.ii[a.inst[b]].Z;
     const double x = a.xs[i], y = a.ys[i];
     const cplx z = mk(x, y);
     cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0), Hd = mk(0.0, 0.0), Gd = mk(0.0, 0.0);
@@ -648,22 +698,22 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
         const int code = a.went[e];
         const int d = code >> 1, img = code & 1;
         const int ld = a.level[d];
-        const cplx cd0 = centre_of(a.g, ld, a.bx[d], a.by[d]);
-        const double rd = 0.5 * side_of(a.g, ld);
+        const cplx cd0 = centre_of(g, ld, a.bx[d], a.by[d]);
+        const double rd = 0.5 * side_of(g, ld);
         const cplx cd = img ? conj(cd0) : cd0;
         const cplx dz = z - cd;
         const cplx idz = inv(dz);
         const cplx tau = -rd * idz;
         // u = w0 log(z - c) - sum_k (k-1)! tau^k w_k,  u' = (w0 + sum_k k! tau^k w_k) / (z - c)
         // (conjugated w for the image box)
-        cplx w0 = a.W[d];
+        cplx w0 = Wv[d];
         if (img) w0 = conj(w0);
         cplx u = mk(0.0, 0.0), ud = w0;
         if (has_phi(MODE)) u = w0 * clog_(dz);
         cplx pw = tau;
 #pragma unroll
         for (int k = 1; k <= PB; ++k) {
-            cplx wk = a.W[(int64_t)k * a.nbox + d];
+            cplx wk = Wv[(int64_t)k * a.nbox + d];
             if (img) wk = conj(wk);
             const cplx pk = pw * wk;
             if (has_phi(MODE)) u -= a.fact[k - 1] * pk;
@@ -684,19 +734,19 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
             for (int pass = 0; pass < a.nloc; ++pass) {
                 const double Xs = pass == 0 ? X : -X;
                 const cplx sw = rd * inv(mk(Y, -Xs));
-                const cplx zr = rd * a.Z;
-                cplx K = reaction_I0_general(Xs, Y, a.Z);
+                const cplx zr = rd * Zk;
+                cplx K = reaction_I0_general(Xs, Y, Zk);
                 cplx F = mk(1.0, 0.0);
                 cplx acc = mk(0.0, 0.0), accd = mk(0.0, 0.0);
-                if (has_phi(MODE)) acc = (pass == 0 ? K : conj(K)) * conj(a.W[d]);
+                if (has_phi(MODE)) acc = (pass == 0 ? K : conj(K)) * conj(Wv[d]);
                 constexpr int NTOP = has_grad(MODE) ? PB + 1 : PB;
 #pragma unroll
                 for (int n = 1; n <= NTOP; ++n) {
                     F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
                     K = F * kInv2Pi + zr * K;
                     const cplx Kn = mul_ipow(pass == 0 ? K : conj(K), n);
-                    if (has_phi(MODE) && n <= PB) acc += Kn * conj(a.W[(int64_t)n * a.nbox + d]);
-                    if (has_grad(MODE)) accd += Kn * conj(a.W[(int64_t)(n - 1) * a.nbox + d]);
+                    if (has_phi(MODE) && n <= PB) acc += Kn * conj(Wv[(int64_t)n * a.nbox + d]);
+                    if (has_grad(MODE)) accd += Kn * conj(Wv[(int64_t)(n - 1) * a.nbox + d]);
                 }
                 accd = accd * (1.0 / rd);
                 if (pass == 0) {
@@ -711,12 +761,13 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     }
     const int64_t o = a.perm[i];
     if (has_phi(MODE)) {
+        double *out = a.phi + (int64_t)v * 2 * a.n;
         if (a.nloc == 1) {
-            a.phi[2 * o] += 2.0 * H.re;
+            out[2 * o] += 2.0 * H.re;
         } else {
-            const cplx v = H + conj(G);
-            a.phi[2 * o] += v.re;
-            a.phi[2 * o + 1] += v.im;
+            const cplx hv = H + conj(G);
+            out[2 * o] += hv.re;
+            out[2 * o + 1] += hv.im;
         }
     }
     if (has_grad(MODE)) {
@@ -739,15 +790,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Reaction part of the near field: sum over the image sources of a leaf's U list of
 // q_j [I_0(X, Y) + I_0(-X, Y)], X = x_i - x_j, Y = y_i + y_j (eq. (reactdecomposition)); for a
 // real impedance only 2 Re I_0(X, Y) (the rest is the surface term).  One wave per target whose
-// leaf touches y = 0; lanes take image sources, a fixed-order butterfly sums them.  Adds to the
-// near-field sums.
-template <int MODE>
+// leaf touches y = 0; lanes take image sources, a fixed-order butterfly sums them.  NV charge
+// vectors share each pair's kernel value.  Adds to the near-field sums.
+template <int MODE, int NV>
 __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
+    static_assert(NV == 1 || MODE == kPhi, "several vectors in the potential mode only");
     const int i = a.rpts[blockIdx.x];
     const int b = a.leaf_of[i];
+    const cplx Z = a.ii[a.inst[b]].Z;
     const int lane = threadIdx.x;
     const double x = a.xs[i], y = a.ys[i];
-    double sr = 0.0, si = 0.0;
+    double sr[NV], si[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sr[v] = si[v] = 0.0;
     cplx s1p = mk(0.0, 0.0), s1m = mk(0.0, 0.0);  // sum q I_1(X, Y), sum q I_1(-X, Y)
     for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
         const int code = a.uent[e];
@@ -756,25 +811,34 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
         const int j1 = a.first[c] + a.count[c];
         for (int j = a.first[c] + lane; j < j1; j += 64) {
             const double dx = x - a.xs[j], dy = y + a.ys[j];
-            const double qj = a.qs[j];
-            const cplx I = reaction_I0_near(dx, dy, a.Z);
-            if (has_grad(MODE)) s1p += qj * (kInv2Pi * inv(mk(dy, -dx)) + a.Z * I);
+            const cplx I = reaction_I0_near(dx, dy, Z);
+            if (has_grad(MODE)) s1p += a.qs[j] * (kInv2Pi * inv(mk(dy, -dx)) + Z * I);
             if (a.nloc == 1) {
-                if (has_phi(MODE)) sr += qj * I.re;
-            } else {
-                const cplx Im_ = reaction_I0_near(-dx, dy, a.Z);
                 if (has_phi(MODE)) {
-                    const cplx v = I + Im_;
-                    sr += qj * v.re;
-                    si += qj * v.im;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sr[v] += a.qs[(int64_t)j * NV + v] * I.re;
                 }
-                if (has_grad(MODE)) s1m += qj * (kInv2Pi * inv(mk(dy, dx)) + a.Z * Im_);
+            } else {
+                const cplx Im_ = reaction_I0_near(-dx, dy, Z);
+                if (has_phi(MODE)) {
+                    const cplx hv = I + Im_;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const double qj = a.qs[(int64_t)j * NV + v];
+                        sr[v] += qj * hv.re;
+                        si[v] += qj * hv.im;
+                    }
+                }
+                if (has_grad(MODE)) s1m += a.qs[j] * (kInv2Pi * inv(mk(dy, dx)) + Z * Im_);
             }
         }
     }
     if (has_phi(MODE)) {
-        sr = wave_sum(sr);
-        si = wave_sum(si);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            sr[v] = wave_sum(sr[v]);
+            si[v] = wave_sum(si[v]);
+        }
     }
     if (has_grad(MODE)) {
         s1p = mk(wave_sum(s1p.re), wave_sum(s1p.im));
@@ -782,14 +846,18 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
     }
     if (lane == 0) {
         if (has_phi(MODE)) {
-            double2 v = a.near[i];
-            if (a.nloc == 1) {
-                v.x += 2.0 * sr;
-            } else {
-                v.x += sr;
-                v.y += si;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double2 *nv_ = a.near + (int64_t)v * a.n + i;
+                double2 hv = *nv_;
+                if (a.nloc == 1) {
+                    hv.x += 2.0 * sr[v];
+                } else {
+                    hv.x += sr[v];
+                    hv.y += si[v];
+                }
+                *nv_ = hv;
             }
-            a.near[i] = v;
         }
         if (has_grad(MODE)) {
             if (a.nloc == 1) {
@@ -885,13 +953,17 @@ static fmmhp_status to_host(std::vector<T> &dst, const T *src, size_t n, hipStre
     return FMMHP_OK;
 }
 
-fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, hipStream_t s) {
+static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv);
+
+fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cplx *Zs, hipStream_t s) {
     S.PB = PB;
-    S.Z = Z;
-    S.real_Z = (Z.im == 0.0);
+    S.Z = Zs[0];
+    S.real_Z = true;
+    for (int k = 0; k < T.n_inst; ++k) S.real_Z = S.real_Z && Zs[k].im == 0.0;
     S.nloc = S.real_Z ? 1 : 2;
     const int nbox = T.nbox;
-    std::vector<int32_t> level, bx, by, leaf, voff, vent, xoff;
+    std::vector<int32_t> level, bx, by, leaf, voff, vent, xoff, binst;
+    FMMHP_CHECK(to_host(binst, T.inst, nbox, s));
     FMMHP_CHECK(to_host(level, T.level, nbox, s));
     FMMHP_CHECK(to_host(bx, T.bx, nbox, s));
     FMMHP_CHECK(to_host(by, T.by, nbox, s));
@@ -1060,14 +1132,37 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
         }
     FMMHP_CHECK(to_dev(A, &S.Tfree, Tfree, "Tfree", s));
     FMMHP_CHECK(to_dev(A, &S.Lfree, Lfree, "Lfree", s));
-    std::vector<double> loglev(32, 0.0);
-    for (int l = 0; l < 32; ++l) loglev[l] = std::log(ldexp(T.S, -l));  // log(2 rho_l) = log(side_l)
-    FMMHP_CHECK(to_dev(A, &S.loglev, loglev, "loglev", s));
+    {
+        std::vector<double> ls(nbox);
+        for (int b = 0; b < nbox; ++b) ls[b] = std::log(ldexp(T.inst_S[binst[b]], -level[b]));  // log(2 rho)
+        FMMHP_CHECK(to_dev(A, &S.logside, ls, "log side", s));
+        std::vector<InstInfo> ii(T.n_inst);
+        for (int k = 0; k < T.n_inst; ++k) ii[k] = InstInfo{T.inst_xlo[k], T.inst_S[k], Zs[k]};
+        FMMHP_CHECK(to_dev(A, &S.inst_info, ii, "instance info", s));
+    }
 
-    std::vector<cplx> TH((size_t)32 * kNumImgSlots * NTP, mk(0, 0)), TG(TH.size(), mk(0, 0)),
+    // image M2L tables: one block of kNumImgSlots operators per (instance, level) that has image V
+    // entries; ibase[b] is the block of box b
+    std::vector<int32_t> ibase(nbox, -1);
+    std::vector<std::pair<int, int>> blocks;  // (instance, level)
+    {
+        std::map<std::pair<int, int>, int> bid;
+        for (int b = 0; b < nbox; ++b) {
+            if (vimg_off[b + 1] == vimg_off[b]) continue;
+            const auto key = std::make_pair(binst[b], level[b]);
+            auto it = bid.find(key);
+            if (it == bid.end()) {
+                it = bid.emplace(key, (int)blocks.size()).first;
+                blocks.push_back(key);
+            }
+            ibase[b] = it->second;
+        }
+    }
+    FMMHP_CHECK(to_dev(A, &S.ibase, ibase, "image table blocks", s));
+    const size_t nblkimg = std::max<size_t>(1, blocks.size());
+    std::vector<cplx> TH(nblkimg * kNumImgSlots * NTP, mk(0, 0)), TG(TH.size(), mk(0, 0)),
         Limg(kNumImgSlots, mk(0, 0));
     std::vector<cplx> K(NT), Km(NT);
-    const C Zc(Z.re, Z.im);
     double pmax = 0.0;
     for (int dy = -3; dy <= -1; ++dy)
         for (int dx = -3; dx <= 3; ++dx) {
@@ -1075,8 +1170,11 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
             const C D((double)dx, (double)dy);
             Limg[is] = cx(i4p * std::log(-D));
         }
-    for (int l = 2; l <= T.depth; ++l) {
-        const double sl = ldexp(T.S, -l), rho = 0.5 * sl;
+    for (size_t bi = 0; bi < blocks.size(); ++bi) {
+        const int k = blocks[bi].first, l = blocks[bi].second;
+        const cplx Z = Zs[k];
+        const C Zc(Z.re, Z.im);
+        const double sl = ldexp(T.inst_S[k], -l), rho = 0.5 * sl;
         for (int dy = -3; dy <= -1; ++dy)
             for (int dx = -3; dx <= 3; ++dx) {
                 if (std::abs(dx) <= 1 && dy == -1) continue;  // adjacent: never in V
@@ -1098,7 +1196,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
                     C ij(1.0, 0.0);
                     for (int r = 0; r < (j & 3); ++r) ij *= C(0.0, 1.0);
                     const C kp(K[j].re, K[j].im), km(Km[j].re, -Km[j].im);
-                    const size_t idx = ((size_t)l * kNumImgSlots + is) * NTP + j;
+                    const size_t idx = (bi * kNumImgSlots + is) * NTP + j;
                     TH[idx] = cx(fr - fact[j] * ij * kp);
                     TG[idx] = cx(fr - fact[j] * ij * km);
                 }
@@ -1133,18 +1231,27 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, h
     }
     FMMHP_CHECK(to_dev(A, &S.E_l2l, El, "E_l2l", s));
 
+    // surface-term chunks: at most kSurfChunk points, within one instance
+    {
+        std::vector<PtChunk> ch;
+        std::vector<int32_t> ich(T.n_inst + 1, 0);
+        for (int k = 0; k < T.n_inst; ++k) {
+            for (int64_t a0 = T.inst_off[k]; a0 < T.inst_off[k + 1]; a0 += kSurfChunk)
+                ch.push_back(PtChunk{a0, std::min(T.inst_off[k + 1], a0 + kSurfChunk), k, 0});
+            ich[k + 1] = (int32_t)ch.size();
+        }
+        S.n_rch = (int)ch.size();
+        FMMHP_CHECK(to_dev(A, &S.rch, ch, "surface chunks", s));
+        FMMHP_CHECK(to_dev(A, &S.inst_ch, ich, "instance chunk ranges", s));
+    }
     // workspace
-    FMMHP_CHECK(A.alloc_n(&S.W, (size_t)(PB + 1) * nbox, "multipoles"));
-    FMMHP_CHECK(A.alloc_n(&S.Lam, (size_t)S.nloc * (PB + 1) * nbox, "locals"));
-    FMMHP_CHECK(A.alloc_n(&S.qs, (size_t)T.n, "sorted charges"));
+    FMMHP_CHECK(ensure_vec_ws(A, T, S, 1));
     FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
-    FMMHP_CHECK(A.alloc_n(&S.near, (size_t)T.n, "near-field sums"));
     FMMHP_HIP(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking));
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
     hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
     FMMHP_HIP(hipGetLastError());
-    FMMHP_CHECK(A.alloc_n(&S.red, 1025, "reduction"));
     FMMHP_HIP(hipStreamSynchronize(s));
     return FMMHP_OK;
 }
@@ -1176,97 +1283,100 @@ struct Marks {
 
 // Outputs of one evaluation pass (caller order): the potential and/or its gradient, and the
 // coincident-charge sums (sorted order) used by the impedance gradient.
+// Outputs of one evaluation pass (caller order): the potential and/or its gradient, and the
+// coincident-charge sums (sorted order) used by the impedance gradient.
 struct PassOut {
-    double *phi = nullptr;      // [n][2]
+    double *phi = nullptr;      // [nv][n][2]
     cplx *gx = nullptr, *gy = nullptr;
     double *qc = nullptr;
 };
 
-template <int PB, int MODE>
-static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leaves, const double *q,
-                             const PassOut &out, hipStream_t s) {
-    const Geo g{T.x_lo, T.S};
+// One pass over NV charge vectors q [NV][n] (caller order).  Far-field kernels take the vector
+// from blockIdx.y; the near-field kernels share each pair's kernel value among the NV vectors.
+template <int PB, int MODE, int NV>
+static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
     const int nbox = T.nbox;
     Marks mk_;
     FMMHP_CHECK(mk_.init(S));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2M, s));
-    hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, S.qs);
+    hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, NV, S.qs);
     // the near field needs only the sorted charges: run it on the side stream, concurrently with
     // the far-field chain, and join before the final leaf kernel
-    const cplx *r1 = (S.nloc == 1) ? S.red + std::min<int64_t>(1024, nblk(T.n, 256)) : nullptr;
-    LeafArgs la{g,         S.Z,   T.n,      nbox,     S.nloc,   T.xs,     T.ys,     S.qs,   S.xy,  T.perm,
-                T.leaf_of, T.level, T.bx,   T.by,     T.first,  T.count,  T.off[0], T.ent[0], T.off[2],
-                T.ent[2],  S.W,   S.Lam,    S.invfact, S.fact,  r1,       S.wpts,   S.n_wpts, S.rpts,
-                S.logtab,  S.near, S.bw.near_gx, S.bw.near_gy, out.qc, out.phi, out.gx, out.gy};
+    LeafArgs la{S.inst_info, T.inst,    T.n_inst, NV,       T.n,      nbox,     S.nloc,   T.xs,     T.ys,
+                S.qs,        S.xy,      T.perm,   T.leaf_of, T.level, T.bx,     T.by,     T.first,  T.count,
+                T.off[0],    T.ent[0],  T.off[2], T.ent[2], S.W,      S.Lam,    S.invfact, S.fact,  S.rank1,
+                S.wpts,      S.n_wpts,  S.rpts,   S.logtab, S.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
+                out.phi,     out.gx,    out.gy};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE>), dim3(nblk(T.n, 256)), dim3(256), 0, S.side, la);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), dim3(nblk(T.n, 256)), dim3(256), 0, S.side, la);
     if (S.n_rpts > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE>), dim3((unsigned)S.n_rpts), dim3(64), 0, S.side,
-                           la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
+                           S.side, la);
     FMMHP_HIP(hipGetLastError());
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
     FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk(T.nleaf, 64)), dim3(64), 0, s, g, leaves, T.nleaf, nbox,
-                       T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk(T.nleaf, 64), NV), dim3(64), 0, s, S.inst_info, T.inst,
+                       S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
     for (int l = T.depth - 1; l >= 2; --l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents)), dim3(256), 0, s, lo, nb,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256), 0, s, lo, nb,
                                nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
     {
         const int lo = T.lev_start[1], hi = T.lev_start[2];
-        const int tot = (hi - lo) * (PB + 1) * S.nloc;
+        const int tot = (hi - lo) * (PB + 1) * S.nloc * NV;
         if (tot > 0)
-            hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc,
+            hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc * NV,
                                S.Lam);
     }
     if (S.ntiles > 0) {
         constexpr int CH = m2l_chunk(PB);
         static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
         M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
-                   S.Tfree, S.Lfree, S.loglev,     S.W,            S.Lam,      S.nloc};
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles), dim3(64 * m2l_waves(PB)), 0, s, ma);
+                   S.Tfree, S.Lfree, S.logside,    S.W,            S.Lam,      S.nloc};
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles, NV), dim3(64 * m2l_waves(PB)), 0, s, ma);
         if (S.nibox > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)S.nibox * (PB + 1), 256)),
-                               dim3(256), 0, s, S.nibox, S.ibox, nbox, S.nloc, T.level, S.vimg_off, S.vimg_ent,
-                               S.TimgH, S.TimgG, S.Limg, S.loglev, S.W, S.Lam);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)S.nibox * (PB + 1), 256), NV),
+                               dim3(256), 0, s, S.nibox, S.ibox, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
+                               S.TimgH, S.TimgG, S.Limg, S.logside, S.W, S.Lam);
         FMMHP_HIP(hipGetLastError());
     }
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
     if (S.nxbox > 0) {
         for (int loc = 0; loc < S.nloc; ++loc)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(S.nxbox), dim3(64), 0, s, g, S.Z, loc, S.xbox, nbox,
-                               T.level, T.bx, T.by, T.first, T.count, T.off[3], T.ent[3], T.xs, T.ys, S.qs, S.fact,
-                               S.Lam);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(S.nxbox, NV), dim3(64), 0, s, S.inst_info, T.inst,
+                               NV, S.nloc, loc, S.xbox, nbox, T.level, T.bx, T.by, T.first, T.count, T.off[3],
+                               T.ent[3], T.xs, T.ys, S.qs, S.fact, S.Lam);
         FMMHP_HIP(hipGetLastError());
     }
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_L2L, s));
     for (int l = 3; l <= T.depth; ++l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren)), dim3(256), 0, s, lo, nb,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256), 0, s, lo, nb,
                                nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
     if (S.nloc == 1) {
-        const int np = (int)std::min<int64_t>(1024, nblk(T.n, 256));
-        hipLaunchKernelGGL(k_rank1_partial, dim3(np), dim3(256), 0, s, T.xs, T.ys, S.qs, T.n, S.Z.re, S.red);
-        hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(256), 0, s, S.red, np);
+        hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, s, T.xs, T.ys, S.qs, NV, S.rch, S.n_rch,
+                           S.inst_info, S.red);
+        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, s, S.red, S.n_rch, S.inst_ch, T.n_inst,
+                           S.rank1);
         FMMHP_HIP(hipGetLastError());
     }
     FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, MODE>), dim3(nblk(T.n, 256)), dim3(256), 0, s, la);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, MODE>), dim3(nblk(T.n, 256), NV), dim3(256), 0, s, la);
     if (S.n_wpts > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, MODE>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, s, la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, MODE>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_NEAR, s));
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
@@ -1274,28 +1384,55 @@ static fmmhp_status eval_vec(const Tree &T, const Sched &S, const int32_t *leave
     return FMMHP_OK;
 }
 
-template <int MODE>
-static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
+template <int MODE, int NV>
+static fmmhp_status run_pass(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
     switch (S.PB) {
-        case 5: return eval_vec<5, MODE>(T, S, S.leaves, q, out, s);
-        case 10: return eval_vec<10, MODE>(T, S, S.leaves, q, out, s);
-        case 15: return eval_vec<15, MODE>(T, S, S.leaves, q, out, s);
-        case 20: return eval_vec<20, MODE>(T, S, S.leaves, q, out, s);
-        case 25: return eval_vec<25, MODE>(T, S, S.leaves, q, out, s);
-        case 30: return eval_vec<30, MODE>(T, S, S.leaves, q, out, s);
-        case 35: return eval_vec<35, MODE>(T, S, S.leaves, q, out, s);
-        case 40: return eval_vec<40, MODE>(T, S, S.leaves, q, out, s);
+        case 5: return eval_pass<5, MODE, NV>(T, S, q, out, s);
+        case 10: return eval_pass<10, MODE, NV>(T, S, q, out, s);
+        case 15: return eval_pass<15, MODE, NV>(T, S, q, out, s);
+        case 20: return eval_pass<20, MODE, NV>(T, S, q, out, s);
+        case 25: return eval_pass<25, MODE, NV>(T, S, q, out, s);
+        case 30: return eval_pass<30, MODE, NV>(T, S, q, out, s);
+        case 35: return eval_pass<35, MODE, NV>(T, S, q, out, s);
+        case 40: return eval_pass<40, MODE, NV>(T, S, q, out, s);
         default:
             set_error("internal: no kernels compiled for p = %d", S.PB);
             return FMMHP_EUNSUPPORTED;
     }
 }
 
-fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
-    for (int v = 0; v < nvec; ++v) {
+template <int MODE>
+static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
+    return run_pass<MODE, 1>(T, S, q, out, s);
+}
+
+// Per-vector workspace (multipoles, locals, sorted charges, near-field sums, surface sums) for nv
+// vectors at once; grown on demand, owned by the plan.
+static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
+    if (S.nv_cap >= nv) return FMMHP_OK;
+    const size_t nb = (size_t)T.nbox, P1 = (size_t)S.PB + 1;
+    FMMHP_CHECK(A.alloc_n(&S.W, nv * P1 * nb, "multipoles"));
+    FMMHP_CHECK(A.alloc_n(&S.Lam, nv * (size_t)S.nloc * P1 * nb, "locals"));
+    FMMHP_CHECK(A.alloc_n(&S.qs, nv * (size_t)T.n, "sorted charges"));
+    FMMHP_CHECK(A.alloc_n(&S.near, nv * (size_t)T.n, "near-field sums"));
+    FMMHP_CHECK(A.alloc_n(&S.red, nv * (size_t)S.n_rch, "surface partial sums"));
+    FMMHP_CHECK(A.alloc_n(&S.rank1, nv * (size_t)T.n_inst, "surface sums"));
+    S.nv_cap = nv;
+    return FMMHP_OK;
+}
+
+fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
+    if (nvec >= kVecChunk) FMMHP_CHECK(ensure_vec_ws(A, T, S, kVecChunk));
+    int v = 0;
+    for (; v + kVecChunk <= nvec; v += kVecChunk) {
         PassOut o;
         o.phi = phi + (int64_t)v * 2 * T.n;
-        FMMHP_CHECK(run_eval_vec<kPhi>(T, S, q + (int64_t)v * T.n, o, s));
+        FMMHP_CHECK((run_pass<kPhi, kVecChunk>(T, S, q + (int64_t)v * T.n, o, s)));
+    }
+    for (; v < nvec; ++v) {
+        PassOut o;
+        o.phi = phi + (int64_t)v * 2 * T.n;
+        FMMHP_CHECK((run_pass<kPhi, 1>(T, S, q + (int64_t)v * T.n, o, s)));
     }
     return FMMHP_OK;
 }
@@ -1324,8 +1461,8 @@ __global__ void k_split_conj(const double *__restrict__ g, int64_t n, double *__
 }
 
 struct BwdArgs {
-    int64_t n;
-    double x0;
+    const InstInfo *ii;
+    const PtChunk *ch;           // point chunks, each within one instance
     const double *xs, *ys;
     const int32_t *perm;
     const double *q, *g;         // caller order
@@ -1334,14 +1471,17 @@ struct BwdArgs {
     const cplx *gxr, *gyr, *gxi, *gyi;  // grad Phi[Re c], grad Phi[Im c]
     const double *qc;            // sorted
     double *grad_q, *grad_x, *grad_y;
-    cplx *part;                  // [gridDim.x] partial sums of the impedance identity
+    cplx *part;                  // [n chunks] partial sums of the impedance identity
     int want_pos;
 };
 
+// One block per point chunk; the impedance identity is summed per instance (x0 = the instance's
+// root centre).
 __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs a) {
-    __shared__ double sr[256], si[256];
+    const PtChunk ch = a.ch[blockIdx.x];
+    const double x0 = a.ii[ch.inst].x_lo + 0.5 * a.ii[ch.inst].S;
     double ar = 0.0, ai = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    for (int64_t i = ch.start + threadIdx.x; i < ch.end; i += 256) {
         const int64_t o = a.perm[i];
         if (a.grad_q) a.grad_q[o] = a.phr[o].re - a.phi_i[o].im;
         if (!a.want_pos) continue;
@@ -1353,21 +1493,12 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs a) {
         const cplx Dy = c * a.gyq[o] + qv * gcy;
         if (a.grad_x) a.grad_x[o] = Dx.re;
         if (a.grad_y) a.grad_y[o] = Dy.re;
-        const cplx v = (a.xs[i] - a.x0) * Dx + a.ys[i] * Dy - kInv2Pi * (a.qc[i] * c);
+        const cplx v = (a.xs[i] - x0) * Dx + a.ys[i] * Dy - kInv2Pi * (a.qc[i] * c);
         ar += v.re;
         ai += v.im;
     }
-    sr[threadIdx.x] = ar;
-    si[threadIdx.x] = ai;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sr[threadIdx.x] += sr[threadIdx.x + off];
-            si[threadIdx.x] += si[threadIdx.x + off];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.part[blockIdx.x] = mk(sr[0], si[0]);
+    const cplx t = block_sum(mk(ar, ai));
+    if (threadIdx.x == 0) a.part[blockIdx.x] = t;
 }
 
 static fmmhp_status ensure_bwd(Arena &A, const Tree &T, Sched &S) {
@@ -1379,7 +1510,7 @@ static fmmhp_status ensure_bwd(Arena &A, const Tree &T, Sched &S) {
     FMMHP_CHECK(A.alloc_n(&b.qc, n, "coincident charge sums"));
     cplx **bufs[] = {&b.phr, &b.phi_i, &b.gxq, &b.gyq, &b.gxr, &b.gyr, &b.gxi, &b.gyi, &b.near_gx, &b.near_gy};
     for (cplx **pp : bufs) FMMHP_CHECK(A.alloc_n(pp, n, "adjoint fields"));
-    FMMHP_CHECK(A.alloc_n(&b.red, 1025, "adjoint reduction"));
+    FMMHP_CHECK(A.alloc_n(&b.red, (size_t)S.n_rch + T.n_inst, "adjoint reduction"));
     b.ready = true;
     return FMMHP_OK;
 }
@@ -1416,15 +1547,15 @@ fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, co
         FMMHP_CHECK(run_eval_vec<kPhi>(T, S, b.cr, pr, s));
         FMMHP_CHECK(run_eval_vec<kPhi>(T, S, b.ci, pi, s));
     }
-    const int np = (int)std::min<int64_t>(1024, nblk(T.n, 256));
-    BwdArgs ba{T.n,   T.x_lo + 0.5 * T.S, T.xs,  T.ys,  T.perm, q,      g,      b.phr,  b.phi_i, b.gxq, b.gyq,
-               b.gxr, b.gyr,              b.gxi, b.gyi, b.qc,   grad_q, grad_x, grad_y, b.red,   pos ? 1 : 0};
-    hipLaunchKernelGGL(k_bwd_combine, dim3(np), dim3(256), 0, s, ba);
+    BwdArgs ba{S.inst_info, S.rch,  T.xs,  T.ys,  T.perm, q,      g,      b.phr,  b.phi_i, b.gxq, b.gyq,
+               b.gxr,       b.gyr,  b.gxi, b.gyi, b.qc,   grad_q, grad_x, grad_y, b.red,   pos ? 1 : 0};
+    hipLaunchKernelGGL(k_bwd_combine, dim3(S.n_rch), dim3(256), 0, s, ba);
     FMMHP_HIP(hipGetLastError());
     if (zsum_host) {
-        hipLaunchKernelGGL(k_rank1_final, dim3(1), dim3(256), 0, s, b.red, np);
+        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, 1), dim3(256), 0, s, b.red, S.n_rch, S.inst_ch, T.n_inst,
+                           b.red + S.n_rch);
         FMMHP_HIP(hipGetLastError());
-        FMMHP_HIP(hipMemcpyAsync(zsum_host, b.red + np, sizeof(cplx), hipMemcpyDeviceToHost, s));
+        FMMHP_HIP(hipMemcpyAsync(zsum_host, b.red + S.n_rch, T.n_inst * sizeof(cplx), hipMemcpyDeviceToHost, s));
         FMMHP_HIP(hipStreamSynchronize(s));
     }
     return FMMHP_OK;

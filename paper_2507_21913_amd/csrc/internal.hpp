@@ -12,6 +12,10 @@
 namespace fmmhp {
 
 constexpr int kLBits = 30;        // integer cell bits per axis of the root square
+constexpr int kLBitsForest = 27;  // the same in a forest (instance index in the top key bits)
+constexpr int kMaxInstances = 512;
+constexpr int kVecChunk = 8;        // charge vectors evaluated together
+constexpr int64_t kSurfChunk = 2048;  // points per partial sum of the surface term
 constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
@@ -62,7 +66,12 @@ struct Tree {
     int64_t n = 0;
     int depth = 0;
     int nbox = 0, nleaf = 0;
-    double x_lo = 0, S = 0, scale = 0;
+    double x_lo = 0, S = 0, scale = 0;  // root square of instance 0
+    int n_inst = 1;
+    int lbits = kLBits;
+    std::vector<int64_t> inst_off;      // [n_inst + 1] point ranges of the instances
+    std::vector<double> inst_xlo, inst_S, inst_scale;
+    int32_t *inst = nullptr;            // box -> instance
     std::vector<int> lev_start;   // boxes of level l: [lev_start[l], lev_start[l + 1]), l >= 1
     // sorted points
     double *xs = nullptr, *ys = nullptr;
@@ -78,9 +87,21 @@ struct Tree {
     int64_t len[4] = {0, 0, 0, 0};
 };
 
-fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const double *y,
+fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, const double *x, const double *y,
                         const double *img_x, const double *img_y, int leaf_size, int max_level,
                         hipStream_t stream);
+
+// Root square and impedance of one instance of a plan.
+struct InstInfo {
+    double x_lo, S;
+    cplx Z;
+};
+
+// A range of sorted points within one instance.
+struct PtChunk {
+    int64_t start, end;
+    int32_t inst, pad;
+};
 
 // Adjoint workspace, allocated on the first backward call: [n] per array.
 struct BwdWork {
@@ -90,7 +111,7 @@ struct BwdWork {
     cplx *phr = nullptr, *phi_i = nullptr;
     cplx *gxq = nullptr, *gyq = nullptr, *gxr = nullptr, *gyr = nullptr, *gxi = nullptr, *gyi = nullptr;
     cplx *near_gx = nullptr, *near_gy = nullptr;  // near-field gradient (sorted order)
-    cplx *red = nullptr;                  // [1025] reduction partials + result
+    cplx *red = nullptr;                  // [n chunks + n_inst] reduction partials + results
 };
 
 // Evaluation schedule and tables derived from the tree.
@@ -121,25 +142,33 @@ struct Sched {
     int32_t *rpts = nullptr;        // sorted points whose leaf has image U entries
     double2 *xy = nullptr;          // [n] sorted (x, y) pairs
     double2 *logtab = nullptr;      // near-field log table
-    double2 *near = nullptr;        // [n] near-field sums
+    double2 *near = nullptr;        // [nv_cap][n] near-field sums
     hipStream_t side = nullptr;     // side stream for the near field (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)
-    cplx *TimgH = nullptr;          // [32][kNumImgSlots][m2l_row(PB)]
+    cplx *TimgH = nullptr;          // [blocks][kNumImgSlots][m2l_row(PB)]
     cplx *TimgG = nullptr;          // same, G-local (complex impedance only)
     cplx *Limg = nullptr;           // [kNumImgSlots]
-    double *loglev = nullptr;       // [31] log(2 rho_l)
+    double *logside = nullptr;      // [nbox] log(2 rho) of each box
+    int32_t *ibase = nullptr;       // [nbox] image-table block of the box's (instance, level), or -1
+    InstInfo *inst_info = nullptr;  // [n_inst]
     cplx *E_m2m = nullptr;          // [4][PB + 1]  (-eps)^j / j!
     cplx *E_l2l = nullptr;          // [4][PB + 1]  eps^j / j!
     double *invfact = nullptr;      // [2 PB + 2]
     double *fact = nullptr;         // [2 PB + 2]
-    // workspace
-    cplx *W = nullptr;              // [PB + 1][nbox]
-    cplx *Lam = nullptr;            // [nloc][PB + 1][nbox]
-    double *qs = nullptr;           // [n] sorted charges
-    cplx *red = nullptr;            // [1024] reduction partials + result
+    // surface-term chunks
+    int n_rch = 0;
+    PtChunk *rch = nullptr;         // [n_rch]
+    int32_t *inst_ch = nullptr;     // [n_inst + 1] chunk range of each instance
+    // workspace for nv_cap charge vectors
+    int nv_cap = 0;
+    cplx *W = nullptr;              // [nv][PB + 1][nbox]
+    cplx *Lam = nullptr;            // [nv][nloc][PB + 1][nbox]
+    double *qs = nullptr;           // [n][nv] sorted charges, vectors interleaved
+    cplx *red = nullptr;            // [nv][n_rch] surface partial sums
+    cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
     BwdWork bw;
     // algorithmic work counts
     int64_t p2p_pairs[2] = {0, 0};
@@ -151,8 +180,9 @@ struct Sched {
     int64_t timed_evals = 0;
 };
 
-fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, cplx Z, hipStream_t stream);
-fmmhp_status run_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi,
+// Zs: [T.n_inst] impedance of each instance (host)
+fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cplx *Zs, hipStream_t stream);
+fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
 
 fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
@@ -177,6 +207,7 @@ struct fmmhp_plan_s {
     int device;
     int p_req, leaf_size, max_level;
     double lambda_re, lambda_im;
+    std::vector<fmmhp::cplx> Zs;  // impedance of each instance
     fmmhp::Arena arena;
     fmmhp::Tree tree;
     fmmhp::Sched sched;

@@ -18,6 +18,11 @@
 //      X(b) = { leaf c coarser than b, not adjacent to b, adjacent to parent(b) }
 //    entries 2 * box + image, ascending.
 //
+// A forest of independent instances (batched plans) is one tree whose keys carry the instance
+// index above the Morton bits: each instance has its own root square and quantisation (27-bit
+// cells, so that 9 instance bits fit), boxes are numbered by (level, instance, Morton prefix), and
+// lists never cross instances.  A single instance uses 30-bit cells and no instance bits.
+//
 // The GPU build enumerates these sets structurally (colleagues of b and of its ancestors, and a
 // depth-first walk down the colleagues' subtrees); a reference build elsewhere tests the
 // defining predicates directly, and the two are compared bit for bit.
@@ -169,14 +174,22 @@ struct BBox {
     int pad;
 };
 
+// Points are processed in chunks that never straddle two instances.
+struct Chunk {
+    int64_t start, end;
+    int32_t inst, pad;
+};
+constexpr int64_t kChunk = 4096;
+
 __global__ __launch_bounds__(256) void k_bbox(const double *__restrict__ x, const double *__restrict__ y,
                                               const double *__restrict__ ix, const double *__restrict__ iy,
-                                              int64_t n, BBox *__restrict__ part) {
+                                              const Chunk *__restrict__ chunks, BBox *__restrict__ part) {
     __shared__ double s0[256], s1[256], s2[256];
     __shared__ int s3[256], s4[256];
+    const Chunk ch = chunks[blockIdx.x];
     double xmin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
     int bad = 0, ibad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int64_t i = ch.start + threadIdx.x; i < ch.end; i += 256) {
         const double a = x[i], b = y[i];
         if (!isfinite(a) || !isfinite(b)) bad |= 1;
         else if (!(b > 0.0)) bad |= 2;
@@ -242,17 +255,21 @@ __device__ inline uint64_t compact30(uint64_t v) {
     return v;
 }
 
-__global__ void k_keys(const double *__restrict__ x, const double *__restrict__ y, int64_t n, double xlo,
-                       double scale, uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t full = 1ll << kLBits, half = 1ll << (kLBits - 1);
+// key = instance << 2L | Morton(ix, iy); kChunk / 256 blocks of 256 threads per chunk.
+__global__ void k_keys(const double *__restrict__ x, const double *__restrict__ y, const Chunk *__restrict__ chunks,
+                       const double *__restrict__ xlo, const double *__restrict__ scale, int lb,
+                       uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
+    constexpr int kPer = (int)(kChunk / 256);  // blocks per chunk
+    const Chunk ch = chunks[blockIdx.x / kPer];
+    const int64_t i = ch.start + (int64_t)(blockIdx.x % kPer) * 256 + threadIdx.x;
+    if (i >= ch.end) return;
+    const int64_t full = 1ll << lb, half = 1ll << (lb - 1);
     // (x - x_lo) * scale: a subtraction then a multiplication, each correctly rounded
-    const double fx = floor(__dmul_rn(__dsub_rn(x[i], xlo), scale));
-    const double fy = floor(__dmul_rn(y[i], scale));
+    const double fx = floor(__dmul_rn(__dsub_rn(x[i], xlo[ch.inst]), scale[ch.inst]));
+    const double fy = floor(__dmul_rn(y[i], scale[ch.inst]));
     const int64_t ix = fx < 0.0 ? 0 : (fx > (double)(full - 1) ? full - 1 : (int64_t)fx);
     const int64_t iu = fy < 0.0 ? 0 : (fy > (double)(half - 1) ? half - 1 : (int64_t)fy);
-    keys[i] = spread30((uint64_t)ix) | (spread30((uint64_t)(half + iu)) << 1);
+    keys[i] = ((uint64_t)ch.inst << (2 * lb)) | spread30((uint64_t)ix) | (spread30((uint64_t)(half + iu)) << 1);
     idx[i] = (int32_t)i;
 }
 
@@ -409,7 +426,7 @@ __global__ void k_fill_i32(int32_t *__restrict__ a, int64_t n, int32_t v) {
 }
 
 __global__ void k_level_flags(const uint64_t *__restrict__ keys, const int32_t *__restrict__ act, int64_t n,
-                              int level, int32_t *__restrict__ flag) {
+                              int level, int lb, int32_t *__restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int f = 0;
@@ -417,7 +434,7 @@ __global__ void k_level_flags(const uint64_t *__restrict__ keys, const int32_t *
         if (i == 0 || act[i - 1] != act[i]) {
             f = 1;
         } else {
-            const int sh = 2 * (kLBits - level);
+            const int sh = 2 * (lb - level);
             f = ((keys[i] ^ keys[i - 1]) >> sh) != 0;
         }
     }
@@ -426,19 +443,22 @@ __global__ void k_level_flags(const uint64_t *__restrict__ keys, const int32_t *
 
 __global__ void k_make_boxes(const uint64_t *__restrict__ keys, const int32_t *__restrict__ act,
                              const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
-                             int level, int base, int32_t *__restrict__ b_level, int32_t *__restrict__ b_bx,
+                             int level, int lb, int base, int32_t *__restrict__ b_level, int32_t *__restrict__ b_bx,
                              int32_t *__restrict__ b_by, int32_t *__restrict__ b_first,
-                             int32_t *__restrict__ b_parent, uint64_t *__restrict__ b_prefix) {
+                             int32_t *__restrict__ b_parent, uint64_t *__restrict__ b_prefix,
+                             int32_t *__restrict__ b_inst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !flag[i]) return;
     const int k = base + pos[i];
-    const uint64_t pre = keys[i] >> (2 * (kLBits - level));
+    const uint64_t pre = keys[i] >> (2 * (lb - level));  // instance << 2 level | Morton prefix
+    const uint64_t cell = (1ull << level) - 1;
     b_level[k] = level;
     b_first[k] = (int32_t)i;
     b_parent[k] = act[i] >= 0 ? act[i] : -1;
     b_prefix[k] = pre;
-    b_bx[k] = (int32_t)compact30(pre);
-    b_by[k] = (int32_t)compact30(pre >> 1);
+    b_bx[k] = (int32_t)(compact30(pre) & cell);
+    b_by[k] = (int32_t)(compact30(pre >> 1) & cell);
+    b_inst[k] = (int32_t)(pre >> (2 * level));
 }
 
 __global__ void k_box_counts(int base, int nb, int64_t n, int leaf_size, int level, int max_level,
@@ -486,14 +506,16 @@ __global__ void k_children(int lo, int hi, const int32_t *__restrict__ b_parent,
 // Interaction lists
 // ---------------------------------------------------------------------------------------------
 struct TreeView {
-    const int32_t *level, *bx, *by, *parent, *leaf, *child_first, *nchild;
+    const int32_t *level, *bx, *by, *parent, *leaf, *child_first, *nchild, *inst;
     const uint64_t *prefix;
     const int32_t *lev_start;  // device [32]
     int depth;
+    int lb;                    // cell bits per axis
 };
 
-// Box reference: (index << 1) | image.  Returns -1 if (l, X, Y) (full-tree coordinates) is empty.
-__device__ inline int find_box(const TreeView &t, int l, int64_t X, int64_t Y) {
+// Box reference: (index << 1) | image.  Returns -1 if (l, X, Y) (full-tree coordinates of the
+// instance's tree) is empty.
+__device__ inline int find_box(const TreeView &t, int inst, int l, int64_t X, int64_t Y) {
     if (l < 1 || l > t.depth) return -1;
     const int64_t side = 1ll << l;
     if (X < 0 || X >= side || Y < 0 || Y >= side) return -1;
@@ -502,7 +524,7 @@ __device__ inline int find_box(const TreeView &t, int l, int64_t X, int64_t Y) {
         img = 1;
         Y = side - 1 - Y;
     }
-    const uint64_t pre = spread30((uint64_t)X) | (spread30((uint64_t)Y) << 1);
+    const uint64_t pre = ((uint64_t)inst << (2 * l)) | spread30((uint64_t)X) | (spread30((uint64_t)Y) << 1);
     int lo = t.lev_start[l], hi = t.lev_start[l + 1];
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -520,7 +542,7 @@ struct Span {
 __device__ inline Span ref_span(const TreeView &t, int ref) {
     const int k = ref >> 1;
     const int l = t.level[k];
-    const int64_t w = 1ll << (kLBits - l);
+    const int64_t w = 1ll << (t.lb - l);
     int64_t Y = t.by[k];
     if (ref & 1) Y = (1ll << l) - 1 - Y;
     Span s;
@@ -546,6 +568,7 @@ __global__ void k_lists(TreeView t, int nbox, int32_t *__restrict__ cnt /* [4][n
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbox) return;
     const int l = t.level[b];
+    const int inst = t.inst[b];
     const int64_t bxf = t.bx[b], byf = t.by[b];
     const bool bleaf = t.leaf[b];
     const Span sb = ref_span(t, b << 1);
@@ -568,7 +591,7 @@ __global__ void k_lists(TreeView t, int nbox, int32_t *__restrict__ cnt /* [4][n
         const int64_t PX = bxf >> 1, PY = byf >> 1;
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
-                const int r = find_box(t, l - 1, PX + dx, PY + dy);
+                const int r = find_box(t, inst, l - 1, PX + dx, PY + dy);
                 if (r < 0) continue;
                 const int k = r >> 1;
                 if (t.leaf[k]) continue;
@@ -590,7 +613,7 @@ __global__ void k_lists(TreeView t, int nbox, int32_t *__restrict__ cnt /* [4][n
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     if (dx == 0 && dy == 0) continue;
-                    const int r = find_box(t, la, AX + dx, AY + dy);
+                    const int r = find_box(t, inst, la, AX + dx, AY + dy);
                     if (r < 0 || !t.leaf[r >> 1]) continue;
                     const Span sc = ref_span(t, r);
                     if (adjacent(sc, sb)) {
@@ -607,7 +630,7 @@ __global__ void k_lists(TreeView t, int nbox, int32_t *__restrict__ cnt /* [4][n
         int sp_ = 0;
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
-                const int r = find_box(t, l, bxf + dx, byf + dy);
+                const int r = find_box(t, inst, l, bxf + dx, byf + dy);
                 if (r < 0) continue;
                 const int k = r >> 1;
                 if (t.leaf[k]) {
@@ -665,25 +688,39 @@ __global__ void k_lists(TreeView t, int nbox, int32_t *__restrict__ cnt /* [4][n
 // ---------------------------------------------------------------------------------------------
 // Driver
 // ---------------------------------------------------------------------------------------------
-fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const double *y, const double *img_x,
-                        const double *img_y, int leaf_size, int max_level, hipStream_t s) {
+fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, const double *x, const double *y,
+                        const double *img_x, const double *img_y, int leaf_size, int max_level, hipStream_t s) {
     Scratch sc(s);
+    const int64_t n = inst_off[n_inst];
     T.n = n;
-    // Root square from device reductions
-    const int nb_bbox = (int)std::min<int64_t>(1024, nblocks(n, 256));
+    T.n_inst = n_inst;
+    T.lbits = n_inst == 1 ? kLBits : kLBitsForest;
+    T.inst_off.assign(inst_off, inst_off + n_inst + 1);
+    // chunks of at most kChunk points within one instance
+    std::vector<Chunk> hch;
+    for (int k = 0; k < n_inst; ++k)
+        for (int64_t a = inst_off[k]; a < inst_off[k + 1]; a += kChunk)
+            hch.push_back(Chunk{a, std::min(inst_off[k + 1], a + kChunk), k, 0});
+    const int nch = (int)hch.size();
+    Chunk *chunks = nullptr;
+    FMMHP_CHECK(sc.get(&chunks, nch, "point chunks"));
+    FMMHP_HIP(hipMemcpyAsync(chunks, hch.data(), nch * sizeof(Chunk), hipMemcpyHostToDevice, s));
+    // Root squares from device reductions
     BBox *part = nullptr;
-    FMMHP_CHECK(sc.get(&part, nb_bbox, "bbox partials"));
-    hipLaunchKernelGGL(k_bbox, dim3(nb_bbox), dim3(256), 0, s, x, y, img_x, img_y, n, part);
+    FMMHP_CHECK(sc.get(&part, nch, "bbox partials"));
+    hipLaunchKernelGGL(k_bbox, dim3(nch), dim3(256), 0, s, x, y, img_x, img_y, chunks, part);
     FMMHP_HIP(hipGetLastError());
-    std::vector<BBox> hp(nb_bbox);
-    FMMHP_HIP(hipMemcpyAsync(hp.data(), part, nb_bbox * sizeof(BBox), hipMemcpyDeviceToHost, s));
+    std::vector<BBox> hp(nch);
+    FMMHP_HIP(hipMemcpyAsync(hp.data(), part, nch * sizeof(BBox), hipMemcpyDeviceToHost, s));
     FMMHP_HIP(hipStreamSynchronize(s));
-    double xmin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+    std::vector<double> xmin(n_inst, INFINITY), xmax(n_inst, -INFINITY), ymax(n_inst, -INFINITY);
     int bad = 0, img_bad = 0;
-    for (auto &b : hp) {
-        xmin = std::min(xmin, b.xmin);
-        xmax = std::max(xmax, b.xmax);
-        ymax = std::max(ymax, b.ymax);
+    for (int c = 0; c < nch; ++c) {
+        const BBox &b = hp[c];
+        const int k = hch[c].inst;
+        xmin[k] = std::min(xmin[k], b.xmin);
+        xmax[k] = std::max(xmax[k], b.xmax);
+        ymax[k] = std::max(ymax[k], b.ymax);
         bad |= b.bad;
         img_bad |= b.img_bad;
     }
@@ -699,12 +736,25 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
         set_error("image arrays are not the exact mirror (x, -y) of the points");
         return FMMHP_EDOMAIN;
     }
-    double S = xmax - xmin;
-    if (2.0 * ymax > S) S = 2.0 * ymax;
-    if (!(S > 0.0)) S = 1.0;
-    T.x_lo = xmin;
-    T.S = S;
-    T.scale = ldexp(1.0, kLBits) / S;
+    T.inst_xlo.resize(n_inst);
+    T.inst_S.resize(n_inst);
+    T.inst_scale.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        double S = xmax[k] - xmin[k];
+        if (2.0 * ymax[k] > S) S = 2.0 * ymax[k];
+        if (!(S > 0.0)) S = 1.0;
+        T.inst_xlo[k] = xmin[k];
+        T.inst_S[k] = S;
+        T.inst_scale[k] = ldexp(1.0, T.lbits) / S;
+    }
+    T.x_lo = T.inst_xlo[0];
+    T.S = T.inst_S[0];
+    T.scale = T.inst_scale[0];
+    double *d_xlo = nullptr, *d_scale = nullptr;
+    FMMHP_CHECK(sc.get(&d_xlo, n_inst, "instance x_lo"));
+    FMMHP_CHECK(sc.get(&d_scale, n_inst, "instance scale"));
+    FMMHP_HIP(hipMemcpyAsync(d_xlo, T.inst_xlo.data(), n_inst * sizeof(double), hipMemcpyHostToDevice, s));
+    FMMHP_HIP(hipMemcpyAsync(d_scale, T.inst_scale.data(), n_inst * sizeof(double), hipMemcpyHostToDevice, s));
 
     // keys and sort
     uint64_t *keys = nullptr, *keys2 = nullptr;
@@ -713,7 +763,8 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
     FMMHP_CHECK(sc.get(&keys2, n, "keys (alt)"));
     FMMHP_CHECK(sc.get(&idx, n, "indices"));
     FMMHP_CHECK(sc.get(&idx2, n, "indices (alt)"));
-    hipLaunchKernelGGL(k_keys, dim3(nblocks(n, 256)), dim3(256), 0, s, x, y, n, T.x_lo, T.scale, keys, idx);
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)(kChunk / 256) * nch), dim3(256), 0, s, x, y, chunks, d_xlo, d_scale,
+                       T.lbits, keys, idx);
     FMMHP_HIP(hipGetLastError());
     uint64_t *ks = keys;
     int32_t *vs = idx;
@@ -740,7 +791,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
     // box arrays grow in chunks: keep a capacity and reallocate (build time only)
     int cap = (int)std::min<int64_t>(std::max<int64_t>(1024, 2 * n / std::max(1, leaf_size) + 64), 0x7fffffff);
     int32_t *b_level = nullptr, *b_bx = nullptr, *b_by = nullptr, *b_first = nullptr, *b_count = nullptr,
-            *b_parent = nullptr, *b_leaf = nullptr;
+            *b_parent = nullptr, *b_leaf = nullptr, *b_inst = nullptr;
     uint64_t *b_prefix = nullptr;
     auto alloc_boxes = [&](int c) -> fmmhp_status {
         FMMHP_CHECK(sc.get(&b_level, c, "box level"));
@@ -751,6 +802,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
         FMMHP_CHECK(sc.get(&b_parent, c, "box parent"));
         FMMHP_CHECK(sc.get(&b_leaf, c, "box leaf"));
         FMMHP_CHECK(sc.get(&b_prefix, c, "box prefix"));
+        FMMHP_CHECK(sc.get(&b_inst, c, "box instance"));
         return FMMHP_OK;
     };
     FMMHP_CHECK(alloc_boxes(cap));
@@ -758,7 +810,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
     int total = 0;
     int level = 0;
     for (level = 1; level <= max_level; ++level) {
-        hipLaunchKernelGGL(k_level_flags, dim3(nblocks(n, 256)), dim3(256), 0, s, ks, act, n, level, flag);
+        hipLaunchKernelGGL(k_level_flags, dim3(nblocks(n, 256)), dim3(256), 0, s, ks, act, n, level, T.lbits, flag);
         FMMHP_HIP(hipGetLastError());
         FMMHP_CHECK(exclusive_scan(flag, pos, n, s));
         int32_t nb = 0;
@@ -769,7 +821,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
             // grow: copy existing arrays
             int ncap = (int)std::min<int64_t>(0x7fffffff, std::max<int64_t>(2ll * cap, (int64_t)total + nb));
             int32_t *o_level = b_level, *o_bx = b_bx, *o_by = b_by, *o_first = b_first, *o_count = b_count,
-                    *o_parent = b_parent, *o_leaf = b_leaf;
+                    *o_parent = b_parent, *o_leaf = b_leaf, *o_inst = b_inst;
             uint64_t *o_prefix = b_prefix;
             FMMHP_CHECK(alloc_boxes(ncap));
             const size_t b4 = (size_t)total * 4;
@@ -780,11 +832,12 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
             FMMHP_HIP(hipMemcpyAsync(b_count, o_count, b4, hipMemcpyDeviceToDevice, s));
             FMMHP_HIP(hipMemcpyAsync(b_parent, o_parent, b4, hipMemcpyDeviceToDevice, s));
             FMMHP_HIP(hipMemcpyAsync(b_leaf, o_leaf, b4, hipMemcpyDeviceToDevice, s));
+            FMMHP_HIP(hipMemcpyAsync(b_inst, o_inst, b4, hipMemcpyDeviceToDevice, s));
             FMMHP_HIP(hipMemcpyAsync(b_prefix, o_prefix, (size_t)total * 8, hipMemcpyDeviceToDevice, s));
             cap = ncap;
         }
         hipLaunchKernelGGL(k_make_boxes, dim3(nblocks(n, 256)), dim3(256), 0, s, ks, act, flag, pos, n, level,
-                           total, b_level, b_bx, b_by, b_first, b_parent, b_prefix);
+                           T.lbits, total, b_level, b_bx, b_by, b_first, b_parent, b_prefix, b_inst);
         FMMHP_HIP(hipGetLastError());
         FMMHP_HIP(hipMemsetAsync(nsplit, 0, sizeof(int32_t), s));
         hipLaunchKernelGGL(k_box_counts, dim3(nblocks(nb, 256)), dim3(256), 0, s, total, nb, n, leaf_size, level,
@@ -819,6 +872,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
     FMMHP_CHECK(A.alloc_n(&T.child_first, nbx, "child_first"));
     FMMHP_CHECK(A.alloc_n(&T.nchild, nbx, "nchild"));
     FMMHP_CHECK(A.alloc_n(&T.prefix, nbx, "prefix"));
+    FMMHP_CHECK(A.alloc_n(&T.inst, nbx, "box instance"));
     const size_t b4 = (size_t)nbx * 4;
     FMMHP_HIP(hipMemcpyAsync(T.level, b_level, b4, hipMemcpyDeviceToDevice, s));
     FMMHP_HIP(hipMemcpyAsync(T.bx, b_bx, b4, hipMemcpyDeviceToDevice, s));
@@ -828,6 +882,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
     FMMHP_HIP(hipMemcpyAsync(T.parent, b_parent, b4, hipMemcpyDeviceToDevice, s));
     FMMHP_HIP(hipMemcpyAsync(T.leaf, b_leaf, b4, hipMemcpyDeviceToDevice, s));
     FMMHP_HIP(hipMemcpyAsync(T.prefix, b_prefix, (size_t)nbx * 8, hipMemcpyDeviceToDevice, s));
+    FMMHP_HIP(hipMemcpyAsync(T.inst, b_inst, b4, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nbx, 256)), dim3(256), 0, s, T.child_first, (int64_t)nbx, -1);
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nbx, 256)), dim3(256), 0, s, T.nchild, (int64_t)nbx, 0);
     FMMHP_HIP(hipGetLastError());
@@ -846,7 +901,8 @@ fmmhp_status build_tree(Arena &A, Tree &T, int64_t n, const double *x, const dou
     FMMHP_CHECK(sc.get(&cnt, (size_t)4 * nbx, "list counts"));
     FMMHP_CHECK(sc.get(&err, 1, "list error flag"));
     FMMHP_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
-    TreeView tv{T.level, T.bx, T.by, T.parent, T.leaf, T.child_first, T.nchild, T.prefix, dlev, T.depth};
+    TreeView tv{T.level, T.bx, T.by, T.parent, T.leaf, T.child_first, T.nchild, T.inst, T.prefix, dlev, T.depth,
+                T.lbits};
     hipLaunchKernelGGL(k_lists<false>, dim3(nblocks(nbx, 128)), dim3(128), 0, s, tv, nbx, cnt,
                        (const int32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr,
                        (const int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
