@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="targets of the oracle's direct sum timed for the CPU baseline")
     ap.add_argument("--quiet-extra", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -60,6 +61,80 @@ def cpu_baseline(w, k):
     return {"value": k / dt / 1e6, "unit": "Mpts/s", "cores": workers, "kind": "oracle",
             "sample": f"{k} targets x {w.n} sources (direct sum, float64), {dt:.1f} s",
             "extrapolated_full_s": dt * w.n / k}
+
+
+def batched_extra(dev, p, leaf, steps):
+    """The batched workload (512 instances, N_k log-uniform in [1e3, 2e5], impedances log-uniform
+    in [0.1, 10], 64 charge vectors): one forest plan evaluating all instances and vectors in the
+    same launches (recorded into a HIP graph), against plain plans evaluated one instance and one
+    vector at a time."""
+    import numpy as np
+    import torch
+
+    import paper_2507_21913_amd as F
+    import workloads
+    from golden_io import load_forest
+
+    t0 = time.perf_counter()
+    x, y, off, lams, q = workloads.batched_forest(seed=1)
+    gen_s = time.perf_counter() - t0
+    n, nv = int(off[-1]), q.shape[0]
+    xt = torch.as_tensor(x, device=dev)
+    yt = torch.as_tensor(y, device=dev)
+    qt = torch.as_tensor(q, device=dev)
+    del q
+    st = torch.cuda.Stream(dev)
+    res = {"workload": f"batched_forest: {len(lams)} instances, N={n}, {nv} vectors, impedances "
+                       "log-uniform [0.1, 10]", "p": p, "leaf_size": leaf, "generate_s": gen_s}
+    with torch.cuda.stream(st):
+        t0 = time.perf_counter()
+        plan = F.HalfPlaneFMM.batched(xt, yt, off, lams.tolist(), p=p, leaf_size=leaf, graph=True)
+        st.synchronize()
+        res["plan_ms"] = (time.perf_counter() - t0) * 1e3
+        out = torch.empty((nv, n), dtype=torch.complex128, device=dev)
+        plan(qt, out=out)  # records the graph
+        st.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            plan(qt, out=out)
+        e1.record(st)
+        st.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res["batched_ms_per_step"] = ms
+        res["batched_mpts_s"] = n * nv / (ms * 1e-3) / 1e6
+        g = load_forest()
+        if g is not None:
+            ks, vs, idx, ref = g
+            got = np.array([out[v, off[k] + i].item() for k, v, i in zip(ks, vs, idx)])
+            res["rel_l2_vs_oracle_sample"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        del out
+        info = plan.info()
+        res["tree"] = {"nbox": info["nbox"], "depth": info["depth"], "device_bytes": info["device_bytes"]}
+        plan.close()
+    # plain: one plan per instance, one vector at a time (vector 0 timed; the others are the same work)
+    plans = [F.HalfPlaneFMM(xt[off[k]:off[k + 1]], yt[off[k]:off[k + 1]], float(lams[k]), p=p, leaf_size=leaf)
+             for k in range(len(lams))]
+    out1 = torch.empty(n, dtype=torch.complex128, device=dev)
+    q0 = qt[0].contiguous()
+    for k, pk in enumerate(plans):
+        pk(q0[off[k]:off[k + 1]], out=out1[off[k]:off[k + 1]])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k, pk in enumerate(plans):
+        pk(q0[off[k]:off[k + 1]], out=out1[off[k]:off[k + 1]])
+    e1.record()
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    for pk in plans:
+        pk.close()
+    res["plain_ms_per_vector"] = ms1
+    res["plain_mpts_s"] = n / (ms1 * 1e-3) / 1e6
+    res["batched_over_plain"] = res["batched_mpts_s"] / res["plain_mpts_s"]
+    return res
 
 
 def main():
@@ -129,7 +204,7 @@ def main():
     g = None
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     try:
-        from make_golden import load
+        from golden_io import load
         g = load("uniform_1m") if a.n == (1 << 20) else None
         if g is not None:
             idx, ref = g
@@ -220,6 +295,11 @@ def main():
                           "bwd_over_fwd": (ms_fb - ms) / ms,
                           "outputs": "phi; dl/dq, dl/dx, dl/dy",
                           "bwd_with_dl_dZ_wall_ms": bwd_lambda_ms}
+        if not a.no_batched:
+            plan.close()
+            del out
+            torch.cuda.empty_cache()
+            res["batched"] = batched_extra(dev, 20, 32, 3)
         res["plan_ms"] = plan_ms
         res["plan_plus_eval_mpts_s"] = w.n / ((plan_ms + ms) * 1e-3) / 1e6
         res["phase_ms"] = {k: round(v, 5) for k, v in phase_avg.items()}
@@ -227,7 +307,8 @@ def main():
                        "list_len": info["list_len"], "p2p_pairs": info["p2p_pairs"],
                        "m2l_pairs": info["m2l_pairs"], "device_bytes": info["device_bytes"]}
     print(json.dumps(res), flush=True)
-    plan.close()
+    if a.quiet_extra or a.no_batched:
+        plan.close()
 
 
 if __name__ == "__main__":

@@ -64,9 +64,15 @@ typedef struct {
                        p in {5, 10, ..., 40}; other values are rounded UP to the next of these and
                        fmmhp_plan_info reports the order actually used. */
     int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
-    int max_level;  /* deepest tree level, 1..30; 0 selects 30 */
-    unsigned flags; /* reserved, must be 0 */
+    int max_level;  /* deepest tree level, 1..30 (1..27 for a forest); 0 selects the maximum */
+    unsigned flags; /* 0, or FMMHP_FLAG_GRAPH */
 } fmmhp_opts;
+
+/* fmmhp_eval records its launches into a HIP graph on the first call with a given (n_vec, q, phi,
+ * stream) and replays the graph on later calls with the same four; another combination records a
+ * new graph.  The stream must not be the null stream (graph capture needs a created stream; the
+ * null stream runs eagerly).  Phase timing is unavailable while recording. */
+#define FMMHP_FLAG_GRAPH 1u
 
 typedef struct {
     int64_t n;              /* number of points */

@@ -83,8 +83,9 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     fmmhp_opts o{20, 40, lb, 0};
     if (opts) o = *opts;
     if (o.max_level == 0) o.max_level = lb;
-    if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb || o.flags != 0) {
-        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (0)", o.p,
+    if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
+        (o.flags & ~FMMHP_FLAG_GRAPH) != 0) {
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (0 or 1)", o.p,
                   FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags);
         return FMMHP_EINVAL;
     }
@@ -108,6 +109,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     if (st == FMMHP_OK)
         st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
+    p->sched.use_graph = (o.flags & FMMHP_FLAG_GRAPH) != 0;
     if (st == FMMHP_OK) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
@@ -335,6 +337,7 @@ fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
     if (plan->sched.ev_fork) (void)hipEventDestroy(plan->sched.ev_fork);
     if (plan->sched.ev_join) (void)hipEventDestroy(plan->sched.ev_join);
     if (plan->sched.side) (void)hipStreamDestroy(plan->sched.side);
+    if (plan->sched.graph.exec) (void)hipGraphExecDestroy(plan->sched.graph.exec);
     plan->arena.release();
     plan->magic = kDead;
     delete plan;

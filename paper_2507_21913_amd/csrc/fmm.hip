@@ -937,6 +937,80 @@ fmmhp_status run_reaction_integrals(int64_t m, const double *x, const double *y,
 // ---------------------------------------------------------------------------------------------
 // Schedule and tables (host)
 // ---------------------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------------------
+// Reaction integrals for the M2L tables, on the host in extended precision.  The upward recursion
+// of eq. (integralrecursion) amplifies the rounding error of I_0 by up to about
+// e^{|P|} / sqrt(2 pi |P|), P = Z (y - i x); at coarse levels |P| reaches ~20 when the impedance is
+// large.  The tables are computed once per plan, so they use long double (64-bit significand),
+// which keeps the coefficients to ~1e-11 relative up to |P| = 21 and ~1e-10 at the limit of 24.
+// I_0 uses the same three regimes as the device routine: the power series of Ei, the asymptotic
+// series of e^{-P} E_1(-P) near the positive real axis, and a continued fraction elsewhere.
+// ---------------------------------------------------------------------------------------------
+using CL = std::complex<long double>;
+
+static CL reaction_I0_ld(long double x, long double y, CL Z) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double gamma = 0.577215664901532860606512090082402431L;
+    const CL P = Z * CL(y, -x);
+    const long double r = std::abs(P);
+    const long double ang = std::fabs(std::atan2(P.imag(), P.real()));
+    const long double sg = P.imag() > 0 ? 1.0L : (P.imag() < 0 ? -1.0L : 0.0L);
+    const long double tiny = 1e-40L;
+    CL A;
+    if (r <= 2 || (r <= 4 && P.real() >= 0) || (ang <= 0.125L * pi && r <= 50)) {
+        CL sum(0, 0), t(1, 0);
+        for (int k = 1; k < 600; ++k) {
+            t = t * P / (long double)k;
+            const CL term = t / (long double)k;
+            sum += term;
+            if (std::norm(term) < tiny * std::norm(sum)) break;
+        }
+        const CL ei = gamma + std::log(P) + sum;
+        return (std::exp(-P) * CL(-ei.real(), pi - ei.imag())) / (2 * pi);
+    }
+    if (ang <= 0.125L * pi) {
+        const CL ip = 1.0L / P;
+        CL t = ip, sum = ip;
+        for (int k = 1; k < 400; ++k) {
+            const CL tn = t * ip * (long double)k;
+            if (std::norm(tn) > std::norm(t)) break;
+            sum += tn;
+            t = tn;
+            if (std::norm(tn) < tiny * std::norm(sum)) break;
+        }
+        A = -sum;
+    } else {
+        const CL w = -P;
+        CL b = w + 1.0L, c(1e4000L, 0), d = 1.0L / b, h = d;
+        for (int i = 1; i < 20000; ++i) {
+            const long double a = -(long double)i * (long double)i;
+            b += 2.0L;
+            d = 1.0L / (a * d + b);
+            c = b + a / c;
+            const CL del = c * d;
+            h *= del;
+            if (std::norm(del - 1.0L) < 1e-38L) break;
+        }
+        A = h;
+    }
+    return (A + CL(0, 1) * std::exp(-P) * (pi * (1 - sg))) / (2 * pi);
+}
+
+// rho^j I_j(x, y) for j = 0..nmax (upward recursion in long double), rounded to double.
+static void reaction_In_scaled_ld(double x, double y, cplx Z, double rho, int nmax, cplx *out) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const CL Zl((long double)Z.re, (long double)Z.im);
+    const CL sigma = (long double)rho / CL((long double)y, -(long double)x);
+    const CL zr = (long double)rho * Zl;
+    CL K = reaction_I0_ld(x, y, Zl), sp(1, 0);
+    out[0] = mk((double)K.real(), (double)K.imag());
+    for (int n = 1; n <= nmax; ++n) {
+        sp *= sigma;
+        K = sp / (2 * pi * n) + zr * K / (long double)n;
+        out[n] = mk((double)K.real(), (double)K.imag());
+    }
+}
+
 static inline int slot_of(int dx, int dy) { return (dy + 3) * 7 + (dx + 3); }
 
 template <class T>
@@ -1183,8 +1257,8 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 const C t = 1.0 / (2.0 * D);
                 const double X = -dx * sl, Y = -dy * sl;
                 pmax = std::max(pmax, std::abs(Zc) * std::hypot(X, Y));
-                reaction_In_scaled(X, Y, Z, rho, NT - 1, K.data());
-                reaction_In_scaled(-X, Y, Z, rho, NT - 1, Km.data());
+                reaction_In_scaled_ld(X, Y, Z, rho, NT - 1, K.data());
+                reaction_In_scaled_ld(-X, Y, Z, rho, NT - 1, Km.data());
                 C tj = t;
                 for (int j = 0; j < NT; ++j) {
                     C fr(0.0, 0.0);
@@ -1202,11 +1276,42 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 }
             }
     }
-    if (pmax > 12.0) {
-        set_error("impedance times box separation reaches %.3g at the coarsest level; the upward "
-                  "I_n recursion is only used up to 12 in this build",
-                  pmax);
+    if (pmax > kMaxTablePZ) {
+        set_error("impedance times box separation reaches %.3g at the coarsest level; the M2L tables "
+                  "are accurate up to %.0f",
+                  pmax, kMaxTablePZ);
         return FMMHP_EUNSUPPORTED;
+    }
+    // P2L (X list) and M2P (W list) run the double-precision recursion on the device: keep
+    // |Z| * distance within the range where it loses at most ~4 digits
+    {
+        std::vector<int32_t> went, xent, woff2;
+        FMMHP_CHECK(to_host(woff2, T.off[2], (size_t)nbox + 1, s));
+        FMMHP_CHECK(to_host(went, T.ent[2], (size_t)T.len[2], s));
+        FMMHP_CHECK(to_host(xent, T.ent[3], (size_t)T.len[3], s));
+        FMMHP_HIP(hipStreamSynchronize(s));
+        double wxmax = 0.0;
+        auto reach = [&](int b, int c) {  // |Z| * (centre distance to the image of c + half diagonals)
+            const int k = binst[b];
+            const double Sk = T.inst_S[k];
+            const double sb = ldexp(Sk, -level[b]), sc = ldexp(Sk, -level[c]);
+            const double xb = (bx[b] + 0.5) * sb, yb = -0.5 * Sk + (by[b] + 0.5) * sb;
+            const double xc = (bx[c] + 0.5) * sc, yc = 0.5 * Sk - (by[c] + 0.5) * sc;  // image centre
+            const double d = std::hypot(xb - xc, yb - yc) + 0.7072 * (sb + sc);
+            return std::hypot(Zs[k].re, Zs[k].im) * d;
+        };
+        for (int b = 0; b < nbox; ++b) {
+            for (int e = woff2[b]; e < woff2[b + 1]; ++e)
+                if (went[e] & 1) wxmax = std::max(wxmax, reach(b, went[e] >> 1));
+            for (int e = xoff[b]; e < xoff[b + 1]; ++e)
+                if (xent[e] & 1) wxmax = std::max(wxmax, reach(b, xent[e] >> 1));
+        }
+        if (wxmax > kMaxDevicePZ) {
+            set_error("impedance times distance reaches %.3g on a W or X list entry; the device I_n "
+                      "recursion is used up to %.0f",
+                      wxmax, kMaxDevicePZ);
+            return FMMHP_EUNSUPPORTED;
+        }
     }
     FMMHP_CHECK(to_dev(A, &S.TimgH, TH, "TimgH", s));
     FMMHP_CHECK(to_dev(A, &S.TimgG, TG, "TimgG", s));
@@ -1421,8 +1526,8 @@ static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
     return FMMHP_OK;
 }
 
-fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
-    if (nvec >= kVecChunk) FMMHP_CHECK(ensure_vec_ws(A, T, S, kVecChunk));
+static fmmhp_status enqueue_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi,
+                                 hipStream_t s) {
     int v = 0;
     for (; v + kVecChunk <= nvec; v += kVecChunk) {
         PassOut o;
@@ -1434,6 +1539,36 @@ fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double 
         o.phi = phi + (int64_t)v * 2 * T.n;
         FMMHP_CHECK((run_pass<kPhi, 1>(T, S, q + (int64_t)v * T.n, o, s)));
     }
+    return FMMHP_OK;
+}
+
+fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
+    if (nvec >= kVecChunk) FMMHP_CHECK(ensure_vec_ws(A, T, S, kVecChunk));
+    if (!S.use_graph || S.timing || s == nullptr) return enqueue_eval(T, S, nvec, q, phi, s);
+    auto &G = S.graph;
+    if (!(G.exec && G.q == q && G.phi == phi && G.nvec == nvec && G.stream == s)) {
+        if (G.exec) {
+            FMMHP_HIP(hipGraphExecDestroy(G.exec));
+            G.exec = nullptr;
+        }
+        FMMHP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const fmmhp_status st = enqueue_eval(T, S, nvec, q, phi, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != FMMHP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        FMMHP_HIP(e);
+        const hipError_t ei = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        FMMHP_HIP(ei);
+        G.q = q;
+        G.phi = phi;
+        G.nvec = nvec;
+        G.stream = s;
+    }
+    FMMHP_HIP(hipGraphLaunch(G.exec, s));
     return FMMHP_OK;
 }
 

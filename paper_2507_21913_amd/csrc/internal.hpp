@@ -16,6 +16,8 @@ constexpr int kLBitsForest = 27;  // the same in a forest (instance index in the
 constexpr int kMaxInstances = 512;
 constexpr int kVecChunk = 8;        // charge vectors evaluated together
 constexpr int64_t kSurfChunk = 2048;  // points per partial sum of the surface term
+constexpr double kMaxTablePZ = 24.0;   // |Z| * distance covered by the M2L tables
+constexpr double kMaxDevicePZ = 12.0;  // the same for the device-side I_n recursion (W, X lists)
 constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
@@ -170,6 +172,15 @@ struct Sched {
     cplx *red = nullptr;            // [nv][n_rch] surface partial sums
     cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
     BwdWork bw;
+    // recorded evaluation (FMMHP_FLAG_GRAPH)
+    bool use_graph = false;
+    struct {
+        hipGraphExec_t exec = nullptr;
+        const double *q = nullptr;
+        double *phi = nullptr;
+        int nvec = 0;
+        hipStream_t stream = nullptr;
+    } graph;
     // algorithmic work counts
     int64_t p2p_pairs[2] = {0, 0};
     int64_t m2l_pairs[2] = {0, 0};

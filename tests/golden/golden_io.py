@@ -1,0 +1,53 @@
+"""Readers of the stored oracle values under tests/golden (plain text; no oracle code).
+
+The files are written by make_golden.py, which calls the CPU oracle; bench.py and the GPU tests
+read them through these functions.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N_SAMPLE = 256
+
+
+def path_for(name: str) -> str:
+    return os.path.join(HERE, f"{name}_direct_sample{N_SAMPLE}.txt")
+
+
+def grad_path_for(name: str) -> str:
+    return os.path.join(HERE, f"{name}_grad_sample{N_SAMPLE}.txt")
+
+
+def forest_path() -> str:
+    return os.path.join(HERE, "batched_forest_direct_sample.txt")
+
+
+def load(name: str):
+    """(indices, complex values) from a stored potential file, or None if absent."""
+    p = path_for(name)
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return a[:, 0].astype(np.int64), a[:, 1] + 1j * a[:, 2]
+
+
+def load_grad(name: str):
+    """(indices, [n, 3] array of dl/dq, dl/dx, dl/dy) from a stored file, or None if absent."""
+    p = grad_path_for(name)
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return a[:, 0].astype(np.int64), a[:, 1:4]
+
+
+def load_forest():
+    """(instance, vector, index within the instance, complex value) arrays, or None if absent."""
+    p = forest_path()
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return (a[:, 0].astype(np.int64), a[:, 1].astype(np.int64), a[:, 2].astype(np.int64),
+            a[:, 3] + 1j * a[:, 4])

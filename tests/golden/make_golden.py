@@ -5,7 +5,9 @@ Calls only the CPU oracle (``oracle.direct``, ``oracle.grad``) and the seeded ge
 targets against ALL sources, written as text (index, Re phi, Im phi); for the differentiation
 workload also the direct-sum gradients at a sample of indices (index, dl/dq, dl/dx, dl/dy).
 
-    python tests/golden/make_golden.py [name ... | grad:name ...]
+    python tests/golden/make_golden.py [name ... | grad:name ... | forest]
+
+The readers (load, load_grad, load_forest) live in golden_io.py, which imports no oracle code.
 """
 from __future__ import annotations
 
@@ -21,18 +23,14 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 from oracle import direct as D  # noqa: E402
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-N_SAMPLE = 256
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from golden_io import HERE, N_SAMPLE, forest_path, grad_path_for, load, load_grad, path_for  # noqa: E402,F401
 
 GOLDEN = {
     "uniform_1m": lambda: workloads.uniform_1m(seed=1),
     "curve_4m": lambda: workloads.curve_4m(seed=1),
     "diff_1m": lambda: workloads.diff_1m(seed=1),
 }
-
-
-def path_for(name: str) -> str:
-    return os.path.join(HERE, f"{name}_direct_sample{N_SAMPLE}.txt")
 
 
 def write(name: str) -> str:
@@ -57,10 +55,6 @@ GRAD_GOLDEN = {
 }
 
 
-def grad_path_for(name: str) -> str:
-    return os.path.join(HERE, f"{name}_grad_sample{N_SAMPLE}.txt")
-
-
 def write_grad(name: str) -> str:
     from oracle import grad as GR
     w = GRAD_GOLDEN[name]()
@@ -80,27 +74,36 @@ def write_grad(name: str) -> str:
     return p
 
 
-def load_grad(name: str):
-    """(indices, [n, 3] array of dl/dq, dl/dx, dl/dy) from a stored file, or None if absent."""
-    p = grad_path_for(name)
-    if not os.path.exists(p):
-        return None
-    a = np.loadtxt(p, comments="#")
-    return a[:, 0].astype(np.int64), a[:, 1:4]
+FOREST_SAMPLE = {"instances": (0, 137, 300, 511), "vectors": (0, 63), "targets": 32}
 
 
-def load(name: str):
-    """(indices, complex values) from a stored file, or None if absent."""
-    p = path_for(name)
-    if not os.path.exists(p):
-        return None
-    a = np.loadtxt(p, comments="#")
-    return a[:, 0].astype(np.int64), a[:, 1] + 1j * a[:, 2]
+def write_forest() -> str:
+    """The batched workload (seed 1): direct sums over single instances at a few sampled targets
+    (instances and vectors of FOREST_SAMPLE), from each instance's own generator."""
+    sizes, lams = workloads.batched_forest_spec(seed=1)
+    p = forest_path()
+    t0 = time.time()
+    rows = []
+    for k in FOREST_SAMPLE["instances"]:
+        x, y, q = workloads.batched_forest_instance(1, k, int(sizes[k]), 64)
+        idx = workloads.sample_targets(x.size, FOREST_SAMPLE["targets"], seed=100 + k)
+        for v in FOREST_SAMPLE["vectors"]:
+            phi = D.potential(x, y, q[v], lams[k], xt=x[idx], yt=y[idx])
+            rows += [(k, v, int(i), c) for i, c in zip(idx, phi)]
+    with open(p, "w") as f:
+        f.write("# oracle direct sums over single instances of the batched workload (seed 1); "
+                "columns: instance vector index_in_instance re im\n")
+        for k, v, i, c in rows:
+            f.write(f"{k} {v} {i} {c.real:.17e} {c.imag:.17e}\n")
+    print(f"batched_forest: {time.time() - t0:.1f} s -> {p}", flush=True)
+    return p
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN]):
+    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN] + ["forest"]):
         if name.startswith("grad:"):
             write_grad(name[5:])
+        elif name == "forest":
+            write_forest()
         else:
             write(name)

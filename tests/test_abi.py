@@ -51,7 +51,7 @@ def test_plan_create_validation():
                                    ctypes.byref(h)) == st
     # options
     for o in (F.Opts(0, 40, 0, 0), F.Opts(41, 40, 0, 0), F.Opts(20, 0, 0, 0), F.Opts(20, 40, 31, 0),
-              F.Opts(20, 40, -1, 0), F.Opts(20, 40, 0, 1)):
+              F.Opts(20, 40, -1, 0), F.Opts(20, 40, 0, 2)):
         assert L.fmmhp_plan_create(10, fake, fake, None, None, 1.0, 0.0, ctypes.byref(o), None,
                                    ctypes.byref(h)) == 1
     assert h.value is None
@@ -85,3 +85,34 @@ def test_binding_refuses_cpu_tensors():
         F.HalfPlaneFMM(x, x + 0.1, 1.0)
     with pytest.raises(TypeError):
         F.direct(x, x + 0.1, x, 1.0)
+
+
+def test_batch_plan_create_validation():
+    """Host-side validation of fmmhp_batch_plan_create: no device work happens before it fails."""
+    L = F.lib()
+    h = ctypes.c_void_p()
+    good = F.Opts(20, 40, 0, 0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def call(n_inst, offs, lam, opts=good):
+        o = (ctypes.c_int64 * len(offs))(*offs) if offs is not None else None
+        la = (ctypes.c_double * len(lam))(*lam) if lam is not None else None
+        return L.fmmhp_batch_plan_create(n_inst, o, fake, fake, la, ctypes.byref(opts), None, ctypes.byref(h))
+
+    assert call(0, [0], []) == 1                              # no instance
+    assert call(513, list(range(514)), [1.0, 0.0] * 513) == 1  # too many
+    assert call(2, None, [1.0, 0.0] * 2) == 1                 # NULL offsets
+    assert call(2, [1, 5, 9], [1.0, 0.0] * 2) == 1            # offsets[0] != 0
+    assert call(2, [0, 5, 5], [1.0, 0.0] * 2) == 1            # empty instance
+    assert call(2, [0, 5, 3], [1.0, 0.0] * 2) == 1            # decreasing
+    assert call(2, [0, 5, 1 << 31], [1.0, 0.0] * 2) == 1      # total too large
+    assert call(2, [0, 5, 9], [1.0, 0.0, -1.0, 0.0]) == 2     # impedance outside Re > 0
+    assert call(2, [0, 5, 9], [1.0, 0.0, 1.0, -0.5]) == 2     # Im < 0
+    assert call(2, [0, 5, 9], [1.0, 0.0, 1.0, 0.0], F.Opts(20, 40, 28, 0)) == 1  # max_level > 27 in a forest
+    assert h.value is None
+
+
+def test_backward_validation_without_plan():
+    L = F.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.fmmhp_backward(None, fake, fake, None, None, None, None, None) == 5  # FMMHP_ESTATE

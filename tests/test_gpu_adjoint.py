@@ -17,7 +17,7 @@ import workloads
 from oracle import grad as GR
 
 sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
-from make_golden import load_grad  # noqa: E402
+from golden_io import load_grad  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"

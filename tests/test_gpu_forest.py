@@ -133,3 +133,54 @@ def test_forest_backward_per_instance_impedance_gradient():
         assert D.rel_l2(r["y"].cpu().numpy()[a:b], ref["grad_y"]) < 1e-10
         assert abs(r["lambda"][k] - ref["grad_Z"]) < 1e-10 * abs(ref["grad_Z"]), k
     plan.close()
+
+
+@pytest.mark.parametrize("imps", [[10.0, 7.5, 0.1], [10.0, 8.0 + 2.0j, 6.0]])
+def test_large_impedance_instances_vs_oracle(imps):
+    """The batched workload's largest impedances (|Z| up to 10 on a root square of side 2.02): the
+    coarse-level reaction M2L coefficients need |Z| * distance up to ~21, where the upward I_n
+    recursion amplifies rounding by ~1e8 (extended-precision tables)."""
+    sizes = [2000, 1200, 700]
+    x, y, off, q = _forest(sizes, 31)
+    plan = F.HalfPlaneFMM.batched(_t(x), _t(y), off, imps, p=30, leaf_size=20)
+    phi = plan(_t(q[0])).cpu().numpy()
+    for k in range(len(sizes)):
+        a, b = off[k], off[k + 1]
+        ref = D.potential(x[a:b], y[a:b], q[0, a:b], imps[k], workers=8)
+        err = D.rel_l2(phi[a:b], ref)
+        print(f"instance {k} (n={b - a}, Z={imps[k]}): rel-l2 {err:.2e}", flush=True)
+        assert err < 1e-10, k
+    plan.close()
+
+
+def test_graph_replays_match_eager():
+    """FMMHP_FLAG_GRAPH: the first call records, later calls replay; every replay (with eager work
+    and synchronisations in between) equals the eager evaluation bitwise; new buffers re-record."""
+    sizes = [1500, 900, 2500]
+    imps = [2.0, 5.0, 0.7]
+    x, y, off, q = _forest(sizes, 41, nvec=10)
+    eager = F.HalfPlaneFMM.batched(_t(x), _t(y), off, imps, p=20, leaf_size=24)
+    ref = eager(_t(q)).cpu().numpy()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan = F.HalfPlaneFMM.batched(_t(x), _t(y), off, imps, p=20, leaf_size=24, graph=True)
+        qt = _t(q)
+        out = torch.empty((10, off[-1]), dtype=torch.complex128, device=DEV)
+        for rep in range(4):
+            out.zero_()
+            plan(qt, out=out)
+            st.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), rep
+            eager(_t(q[0]))  # unrelated eager work between replays
+            torch.cuda.synchronize()
+        # new buffers: a new recording (2 q: every operation scales exactly, so 2 phi bitwise)
+        q2 = _t(2.0 * q)
+        out2 = plan(q2)
+        st.synchronize()
+        assert np.array_equal(out2.cpu().numpy(), 2.0 * ref)
+    # the null stream runs eagerly
+    plan_null = F.HalfPlaneFMM.batched(_t(x), _t(y), off, imps, p=20, leaf_size=24, graph=True)
+    assert np.array_equal(plan_null(_t(q)).cpu().numpy(), ref)
+    plan.close()
+    plan_null.close()
+    eager.close()

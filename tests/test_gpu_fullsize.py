@@ -20,7 +20,7 @@ from oracle import direct as D
 from oracle import tree as T
 
 sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
-from make_golden import load  # noqa: E402
+from golden_io import load  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"

@@ -18,7 +18,7 @@ the paper's experiments and the workload list describe:
                      [0,4]x[1e-4,1]; charges N(0,1); impedance 1+0.5i.
 * ``batched_forest`` 512 instances, N_k log-uniform in [1e3, 2e5], each uniform
                      in [0,1]x[0.01,1.01], impedance_k log-uniform in [0.1,10],
-                     64 shared charge vectors N(0,1).
+                     64 charge vectors N(0,1) per instance.
 * ``diff_1m``        N=1,048,576 uniform in [0,1]x[0.01,1.01], charges U[-1,1],
                      impedance 2.0, loss weights w ~ N(0,1).
 * ``example1``       the single source/target pair and expansion centres of the
@@ -37,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "plain_small", "uniform_1m", "curve_4m", "diff_1m",
-    "batched_forest", "example1", "example2", "uniform", "sample_targets",
+    "batched_forest", "batched_forest_spec", "batched_forest_instance", "example1", "example2", "uniform", "sample_targets",
 ]
 
 
@@ -109,20 +109,38 @@ def curve_4m(seed: int = 1, n: int = 1 << 22, p: int = 30,
     return Workload("curve_4m", x, y, q, complex(1.0, 0.5), p, leaf_size)
 
 
-def batched_forest(seed: int = 1, n_inst: int = 512, n_vec: int = 64,
-                   n_min: float = 1e3, n_max: float = 2e5):
-    """List of per-instance Workloads (shared vector count, own impedance)."""
+def batched_forest_spec(seed: int = 1, n_inst: int = 512, n_min: float = 1e3, n_max: float = 2e5):
+    """Sizes N_k = round(exp U[ln n_min, ln n_max)) and real impedances exp U[ln 0.1, ln 10] of the
+    batched workload's instances."""
     rng = np.random.default_rng(seed)
     sizes = np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_inst))).astype(np.int64)
     lams = np.exp(rng.uniform(np.log(0.1), np.log(10.0), n_inst))
-    out = []
+    return sizes, lams
+
+
+def batched_forest_instance(seed: int, k: int, size: int, n_vec: int):
+    """Instance k: points uniform in [0, 1] x [0.01, 1.01] and n_vec charge vectors q ~ N(0, 1),
+    from a generator of its own (seed, k), so any instance can be rebuilt alone."""
+    rng = np.random.default_rng([seed, k])
+    x = rng.uniform(0.0, 1.0, size)
+    y = rng.uniform(0.01, 1.01, size)
+    q = rng.standard_normal((n_vec, size))
+    return x, y, q
+
+
+def batched_forest(seed: int = 1, n_inst: int = 512, n_vec: int = 64,
+                   n_min: float = 1e3, n_max: float = 2e5):
+    """All instances concatenated: (x, y, offsets [n_inst + 1], impedances [n_inst],
+    q [n_vec, sum N_k])."""
+    sizes, lams = batched_forest_spec(seed, n_inst, n_min, n_max)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.empty(off[-1])
+    y = np.empty(off[-1])
+    q = np.empty((n_vec, off[-1]))
     for k in range(n_inst):
-        nk = int(sizes[k])
-        x = rng.uniform(0.0, 1.0, nk)
-        y = rng.uniform(0.01, 1.01, nk)
-        q = rng.standard_normal((n_vec, nk))
-        out.append(Workload(f"forest_{k}", x, y, q, complex(lams[k]), 20, 40))
-    return out
+        a, b = off[k], off[k + 1]
+        x[a:b], y[a:b], q[:, a:b] = batched_forest_instance(seed, k, int(sizes[k]), n_vec)
+    return x, y, off, lams, q
 
 
 def example1():
