@@ -28,6 +28,20 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X fp64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per k_m2l launch measured with rocprofv3 counter runs (2.00 x FETCH_SIZE + 1.00 x
+# WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
+# (p, leaf size): reported only while the kernels are the ones that were measured.
+M2L_TRAFFIC = {("cfaac482d00c7546", 20, 32): 145.6e6}
+
+
+def eval_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fmm.hip", "internal.hpp", "special.hpp", "cplx.hpp"):
+        with open(os.path.join(ROOT, "paper_2507_21913_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -219,8 +233,9 @@ def main():
     dom = max(("m2l", "near"), key=lambda k: phase_avg[k])
     if dom == "m2l":
         achieved = m2l_flops / (phase_avg["m2l"] * 1e-3) / 1e12
+        traffic = M2L_TRAFFIC.get((eval_source_hash(), info["p"], leaf_use))
         roof = {"kernel": "k_m2l", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "flops_per_launch": m2l_flops}
     else:
         # near field (k_near): 27 float64 flops per pair, counted from its compiled inner loop
