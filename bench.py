@@ -289,6 +289,25 @@ def main():
             res["p30_leaf40"] = {"mpts_s": w.n / (ms30 * 1e-3) / 1e6, "ms_per_step": ms30,
                                  "rel_l2_vs_oracle_sample": rel30}
             plan30.close()
+        # the same evaluation with the upper-source M2L on the FP32 matrix cores
+        plan32 = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, m2l_fp32=True)
+        for _ in range(2):
+            plan32(q, out=out)
+        plan32.set_timing(True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            plan32(q, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms32 = e0.elapsed_time(e1) / 10
+        ph32, nev32 = plan32.phase_times()
+        rel32 = None
+        if g is not None:
+            rel32 = float(np.linalg.norm(out.cpu().numpy()[g[0]] - g[1]) / np.linalg.norm(g[1]))
+        res["m2l_fp32"] = {"mpts_s": w.n / (ms32 * 1e-3) / 1e6, "ms_per_step": ms32,
+                           "m2l_ms": ph32["m2l"] / max(1, nev32), "rel_l2_vs_oracle_sample": rel32}
+        plan32.close()
         # forward + adjoint (dl/dq, dl/dx, dl/dy, dl/dZ) for one incoming gradient, same plan
         rng = np.random.default_rng(7)
         gg = torch.as_tensor(rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n), device=dev)

@@ -65,7 +65,7 @@ typedef struct {
                        fmmhp_plan_info reports the order actually used. */
     int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
     int max_level;  /* deepest tree level, 1..30 (1..27 for a forest); 0 selects the maximum */
-    unsigned flags; /* 0, or FMMHP_FLAG_GRAPH */
+    unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH and FMMHP_FLAG_M2L_FP32 */
 } fmmhp_opts;
 
 /* fmmhp_eval records its launches into a HIP graph on the first call with a given (n_vec, q, phi,
@@ -73,6 +73,12 @@ typedef struct {
  * new graph.  The stream must not be the null stream (graph capture needs a created stream; the
  * null stream runs eagerly).  Phase timing is unavailable while recording. */
 #define FMMHP_FLAG_GRAPH 1u
+
+/* The M2L of upper (free-space) sources runs on the FP32 matrix cores (MFMA), with operands scaled
+ * into FP32 range and each offset slot's FP32 sums folded into FP64 (addition 3).  Everything else
+ * stays FP64.  Expect a relative error of ~1e-7 on top of the truncation error: for tolerances of
+ * 1e-6, not 1e-10. */
+#define FMMHP_FLAG_M2L_FP32 2u
 
 typedef struct {
     int64_t n;              /* number of points */

@@ -26,6 +26,7 @@ STATUS = {0: "FMMHP_OK", 1: "FMMHP_EINVAL", 2: "FMMHP_EDOMAIN", 3: "FMMHP_ENOMEM
           4: "FMMHP_EHIP", 5: "FMMHP_ESTATE", 6: "FMMHP_EUNSUPPORTED"}
 MAX_P = 40
 FLAG_GRAPH = 1   # fmmhp_opts.flags: record evaluations into a HIP graph and replay them
+FLAG_M2L_FP32 = 2  # fmmhp_opts.flags: upper-source M2L on the FP32 matrix cores (~1e-7 relative)
 
 
 class FMMHPError(RuntimeError):
@@ -255,17 +256,19 @@ class HalfPlaneFMM:
     pass_images pass the image arrays (x, -y) explicitly to the library
     graph       record each evaluation into a HIP graph and replay it (needs a non-default
                 stream: run under ``torch.cuda.stream(...)``)
+    m2l_fp32    run the upper-source M2L on the FP32 matrix cores (relative error ~1e-7)
     """
 
     def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False,
-                 graph=False):
+                 graph=False, m2l_fp32=False):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         self.n = int(x.shape[0])
         self.device = x.device
         self._x, self._y = x, y
         lr, li = _split_impedance(impedance)
-        opts = Opts(int(p), int(leaf_size), int(max_level), FLAG_GRAPH if graph else 0)
+        opts = Opts(int(p), int(leaf_size), int(max_level),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0))
         with torch.cuda.device(self.device):
             if pass_images:
                 ix, iy = x.clone(), -y
@@ -278,7 +281,8 @@ class HalfPlaneFMM:
         self.n_inst = 1
 
     @classmethod
-    def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False):
+    def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False,
+                m2l_fp32=False):
         """A forest plan over n_inst independent instances: points offsets[k]..offsets[k+1]-1 of
         (x, y) form instance k with impedance impedances[k].  Evaluation takes charges for all
         points (instance after instance) and runs every instance in the same launches."""
@@ -296,7 +300,8 @@ class HalfPlaneFMM:
         imps = [complex(z) for z in impedances]
         if len(imps) != self.n_inst:
             raise ValueError("one impedance per instance")
-        opts = Opts(int(p), int(leaf_size), int(max_level), FLAG_GRAPH if graph else 0)
+        opts = Opts(int(p), int(leaf_size), int(max_level),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0))
         with torch.cuda.device(self.device):
             self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,
                                                  opts, _stream())

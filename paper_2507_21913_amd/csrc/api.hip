@@ -84,8 +84,8 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     if (opts) o = *opts;
     if (o.max_level == 0) o.max_level = lb;
     if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
-        (o.flags & ~FMMHP_FLAG_GRAPH) != 0) {
-        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (0 or 1)", o.p,
+        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32)) != 0) {
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0, 1)", o.p,
                   FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags);
         return FMMHP_EINVAL;
     }
@@ -108,6 +108,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     }
     if (st == FMMHP_OK)
         st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
+    p->sched.m2l_fp32 = (o.flags & FMMHP_FLAG_M2L_FP32) != 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
     p->sched.use_graph = (o.flags & FMMHP_FLAG_GRAPH) != 0;
     if (st == FMMHP_OK) {

@@ -284,6 +284,157 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// M2L of upper sources on the FP32 matrix cores (FMMHP_FLAG_M2L_FP32).  Per offset slot the tile's
+// contraction is a real GEMM in the 2x2 embedding of complex numbers:
+//   [Re acc, Im acc](64 x 2(p+1)) += [Re w'', Im w''](64 x 2(p+1)) * [[Re T'', Im T''], [-Im T'', Re T'']]
+// with the factorial scaling w''_m = m! w_m, T''_{nm} = T_{n+m} / (n! m!), acc''_n = lambda_n / n!,
+// which keeps every operand within FP32 range (|T''_{nm}| <= 2^-(n+m) for separated boxes).  Each
+// wave owns 16 target boxes (one 16-row M tile) and runs v_mfma_f32_16x16x4f32 over K (= 2(p+1)
+// padded to a multiple of 4) and N (padded to a multiple of 16); the FP32 sums of one slot are
+// added into FP64 accumulators before the next slot.  The log term of lambda_0 stays in FP64.
+// Lane layout of the instruction: A[i][k] from lane 16 k + i, B[k][j] from lane 16 k + j,
+// D[4 (l / 16) + r][l % 16] in element r of lane l.
+// ---------------------------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int m2l32_kp(int PB) { return ((2 * (PB + 1) + 3) / 4) * 4; }
+__host__ __device__ constexpr int m2l32_np(int PB) { return ((2 * (PB + 1) + 15) / 16) * 16; }
+
+struct M2L32Args {
+    int nbox;
+    const int32_t *tiles, *tile_src_off, *tile_src;
+    const int16_t *tile_slot;
+    const uint64_t *tile_mask;
+    const float *B;          // [kNumSlots][KP][NP] embedded scaled operators
+    const cplx *Lfree;
+    const double *logside;
+    const double *fact;      // n!
+    const cplx *W;           // [nv][PB + 1][nbox]
+    cplx *Lam;               // [nv][nloc][PB + 1][nbox]
+    int nloc;
+};
+
+template <int PB>
+__global__ __launch_bounds__(256) void k_m2l_f32(M2L32Args a) {
+    constexpr int P1 = PB + 1, KP = m2l32_kp(PB), NP = m2l32_np(PB);
+    constexpr int KS = KP / 4, NT = NP / 16;
+    constexpr int BSZ = KP * NP, BPER = (BSZ + 255) / 256;
+    __shared__ float sA[kM2LMaxSrc * KP];
+    __shared__ float sB[2][BSZ];
+    __shared__ cplx s_acc0[kTile];
+    const int tile = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kq = lane >> 4;
+    const cplx *W = a.W + (int64_t)blockIdx.y * P1 * a.nbox;  // charge vector
+    cplx *Lam = a.Lam + (int64_t)blockIdx.y * a.nloc * P1 * a.nbox;
+    const int s0 = a.tile_src_off[tile];
+    const int ns = a.tile_src_off[tile + 1] - s0;
+    const uint64_t mask = a.tile_mask[tile];
+    const int16_t *slot = a.tile_slot + (int64_t)tile * kNumSlots * kTile;
+    // stage the tile's sources: scaled, embedded, FP32
+    for (int idx = tid; idx < KP * ns; idx += 256) {
+        const int k = idx / ns, sj = idx - k * ns;
+        float v = 0.f;
+        if (k < 2 * P1) {
+            const int m = k < P1 ? k : k - P1;
+            const cplx w = W[(int64_t)m * a.nbox + a.tile_src[s0 + sj]];
+            v = (float)(a.fact[m] * (k < P1 ? w.re : w.im));
+        }
+        sA[sj * KP + k] = v;
+    }
+    // log term of lambda_0 in FP64, one lane per target
+    if (wave == 0) {
+        const int b = a.tiles[tile * kTile + lane];
+        const double ll = b >= 0 ? a.logside[b] * kInv4Pi : 0.0;
+        cplx acc0 = mk(0.0, 0.0);
+        uint64_t rest = mask;
+        while (rest) {
+            const int o = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            const int li = slot[o * kTile + lane];
+            if (li >= 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), W[a.tile_src[s0 + li]]);
+        }
+        s_acc0[lane] = acc0;
+    }
+    f32x4 acc[NT];
+    double acc64[NT][4];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc64[nt][i] = 0.0;
+    }
+    // operator of the first slot into buffer 0; later ones are prefetched into registers while
+    // the current slot runs, then stored to the other buffer
+    uint64_t rest = mask;
+    int o = rest ? __builtin_ctzll(rest) : 0;
+    if (rest)
+        for (int e = tid; e < BSZ; e += 256) sB[0][e] = a.B[(int64_t)o * BSZ + e];
+    __syncthreads();
+    int buf = 0;
+    const int16_t *myslot = slot + wave * 16 + r;  // target row r of this wave's M tile
+    while (rest) {
+        rest &= rest - 1;
+        const int onext = rest ? __builtin_ctzll(rest) : -1;
+        float pre[BPER];
+        if (onext >= 0) {
+#pragma unroll
+            for (int q = 0; q < BPER; ++q) {
+                const int e = tid + 256 * q;
+                pre[q] = e < BSZ ? a.B[(int64_t)onext * BSZ + e] : 0.f;
+            }
+        }
+        const int li = myslot[o * kTile];
+        const float *arow = sA + (li >= 0 ? li : 0) * KP + kq;
+        const float *bcol = sB[buf] + kq * NP + r;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const float av = li >= 0 ? arow[4 * ks] : 0.f;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bcol[4 * ks * NP + 16 * nt], acc[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc64[nt][i] += (double)acc[nt][i];
+            acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (onext >= 0) {
+#pragma unroll
+            for (int q = 0; q < BPER; ++q) {
+                const int e = tid + 256 * q;
+                if (e < BSZ) sB[buf ^ 1][e] = pre[q];
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
+        o = onext;
+    }
+    // lambda_n = -n! acc''_n (+ the log term for n = 0)
+    const int64_t stride = (int64_t)P1 * a.nbox;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int c = 16 * nt + r;
+        if (c >= 2 * P1) continue;
+        const bool im = c >= P1;
+        const int n = im ? c - P1 : c;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = wave * 16 + 4 * kq + i;
+            const int b = a.tiles[tile * kTile + t];
+            if (b < 0) continue;
+            double v = -a.fact[n] * acc64[nt][i];
+            if (n == 0) v += im ? s_acc0[t].im : s_acc0[t].re;
+            double *dst = (double *)(Lam + (int64_t)n * a.nbox + b) + (im ? 1 : 0);
+            *dst = v;
+            if (a.nloc == 2) *((double *)(Lam + stride + (int64_t)n * a.nbox + b) + (im ? 1 : 0)) = v;
+        }
+    }
+}
+
 // Image V entries (target boxes in the two rows nearest y = 0 at each level): log M2L of the image
 // box plus the reaction M2L, one thread per (target box, output coefficient); adds to the locals
 // written by k_m2l.
@@ -1205,6 +1356,24 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             Lfree[o] = cx(-i4p * std::log(-D));
         }
     FMMHP_CHECK(to_dev(A, &S.Tfree, Tfree, "Tfree", s));
+    if (S.m2l_fp32) {
+        // FP32 matrix-core operators: B[o][k][c] of the 2x2 embedding of T''_{nm} = T_{n+m} / (n! m!)
+        const int P1 = PB + 1, KP = m2l32_kp(PB), NP = m2l32_np(PB);
+        std::vector<float> B((size_t)kNumSlots * KP * NP, 0.f);
+        for (int o = 0; o < kNumSlots; ++o)
+            for (int n = 0; n <= PB; ++n)
+                for (int m = 0; m <= PB; ++m) {
+                    const cplx t = Tfree[(size_t)o * NTP + n + m];
+                    const double sc = ifact[n] * ifact[m];
+                    const float tr = (float)(t.re * sc), ti = (float)(t.im * sc);
+                    float *Bo = B.data() + (size_t)o * KP * NP;
+                    Bo[(size_t)m * NP + n] = tr;
+                    Bo[(size_t)m * NP + P1 + n] = ti;
+                    Bo[(size_t)(P1 + m) * NP + n] = -ti;
+                    Bo[(size_t)(P1 + m) * NP + P1 + n] = tr;
+                }
+        FMMHP_CHECK(to_dev(A, &S.Bf32, B, "FP32 M2L operators", s));
+    }
     FMMHP_CHECK(to_dev(A, &S.Lfree, Lfree, "Lfree", s));
     {
         std::vector<double> ls(nbox);
@@ -1444,9 +1613,16 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     if (S.ntiles > 0) {
         constexpr int CH = m2l_chunk(PB);
         static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
-        M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
-                   S.Tfree, S.Lfree, S.logside,    S.W,            S.Lam,      S.nloc};
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles, NV), dim3(64 * m2l_waves(PB)), 0, s, ma);
+        if (S.m2l_fp32) {
+            M2L32Args ma{nbox,    S.tiles, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask, S.Bf32,
+                         S.Lfree, S.logside, S.fact,        S.W,        S.Lam,       S.nloc};
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(S.ntiles, NV), dim3(256), 0, s, ma);
+        } else {
+            M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
+                       S.Tfree, S.Lfree, S.logside,    S.W,            S.Lam,      S.nloc};
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles, NV), dim3(64 * m2l_waves(PB)), 0, s,
+                               ma);
+        }
         if (S.nibox > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)S.nibox * (PB + 1), 256), NV),
                                dim3(256), 0, s, S.nibox, S.ibox, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,

@@ -149,6 +149,8 @@ struct Sched {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
+    bool m2l_fp32 = false;          // FMMHP_FLAG_M2L_FP32: upper-source M2L on the FP32 matrix cores
+    float *Bf32 = nullptr;          // [kNumSlots][KP][NP] embedded scaled operators (FP32 M2L)
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)
     cplx *TimgH = nullptr;          // [blocks][kNumImgSlots][m2l_row(PB)]
     cplx *TimgG = nullptr;          // same, G-local (complex impedance only)
