@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_m2l_f32(M2L32Args a) {
     constexpr int P1 = PB + 1, KP = m2l32_kp(PB), NP = m2l32_np(PB);
     constexpr int KS = KP / 4, NT = NP / 16;
     constexpr int BSZ = KP * NP, BPER = (BSZ + 255) / 256;
-    __shared__ float sA[kM2LMaxSrc * KP];
+    __shared__ float sA[kM2LMaxSrc32 * KP];
     __shared__ float sB[2][BSZ];
     __shared__ cplx s_acc0[kTile];
     const int tile = blockIdx.x;
@@ -687,8 +687,8 @@ struct LeafArgs {
     cplx *gx, *gy;           // [n] gradient, caller order (gradient modes)
 };
 
-// Near field, log terms of the U list: one thread per target (sorted order).  NV charge vectors
-// share each pair's kernel value.
+// Near field, log terms of the U list: one thread per target (sorted order, grid-stride over the
+// targets).  NV charge vectors share each pair's kernel value.
 template <int MODE, int NV>
 __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     static_assert(NV == 1 || MODE == kPhi, "several vectors in the potential mode only");
@@ -697,67 +697,67 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
         if (threadIdx.x < kLogTable) s_logtab[threadIdx.x] = a.logtab[threadIdx.x];
         __syncthreads();
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const int b = a.leaf_of[i];
-    const double2 pi = a.xy[i];
-    const double x = pi.x, y = pi.y;
-    double lfree[NV], limg[NV];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = a.leaf_of[i];
+        const double2 pi = a.xy[i];
+        const double x = pi.x, y = pi.y;
+        double lfree[NV], limg[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) lfree[v] = limg[v] = 0.0;
-    double fx = 0.0, fy = 0.0, mx = 0.0, my = 0.0, qc = 0.0;
-    const double2 *__restrict__ xy = a.xy;
-    const double2 *__restrict__ tab = s_logtab;
-    const double *__restrict__ qs = a.qs;
-    for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
-        const int code = a.uent[e];
-        const int c = code >> 1;
-        const int j0 = a.first[c], j1 = j0 + a.count[c];
-        if (!(code & 1)) {
-            for (int j = j0; j < j1; ++j) {
-                const double2 pj = xy[j];
-                const double dx = x - pj.x, dy = y - pj.y;
-                const double r2 = fma(dx, dx, dy * dy);
-                const bool nz = r2 > 0.0;  // skip the self pair (eq. (1.2))
-                if (has_phi(MODE)) {
-                    const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
+        for (int v = 0; v < NV; ++v) lfree[v] = limg[v] = 0.0;
+        double fx = 0.0, fy = 0.0, mx = 0.0, my = 0.0, qc = 0.0;
+        const double2 *__restrict__ xy = a.xy;
+        const double2 *__restrict__ tab = s_logtab;
+        const double *__restrict__ qs = a.qs;
+        for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+            const int code = a.uent[e];
+            const int c = code >> 1;
+            const int j0 = a.first[c], j1 = j0 + a.count[c];
+            if (!(code & 1)) {
+                for (int j = j0; j < j1; ++j) {
+                    const double2 pj = xy[j];
+                    const double dx = x - pj.x, dy = y - pj.y;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const bool nz = r2 > 0.0;  // skip the self pair (eq. (1.2))
+                    if (has_phi(MODE)) {
+                        const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
+                        for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
+                    }
+                    if (has_grad(MODE)) {
+                        const double qj = qs[j];
+                        const double sc = (nz ? qj : 0.0) * rcp_pos(nz ? r2 : 1.0);
+                        fx = fma(sc, dx, fx);
+                        fy = fma(sc, dy, fy);
+                        qc += nz ? 0.0 : qj;
+                    }
                 }
-                if (has_grad(MODE)) {
-                    const double qj = qs[j];
-                    const double sc = (nz ? qj : 0.0) * rcp_pos(nz ? r2 : 1.0);
-                    fx = fma(sc, dx, fx);
-                    fy = fma(sc, dy, fy);
-                    qc += nz ? 0.0 : qj;
-                }
-            }
-        } else {
-            for (int j = j0; j < j1; ++j) {
-                const double2 pj = xy[j];
-                const double dx = x - pj.x, dy = y + pj.y;
-                const double r2 = fma(dx, dx, dy * dy);
-                if (has_phi(MODE)) {
-                    const double lg = log_tab(r2, tab);
+            } else {
+                for (int j = j0; j < j1; ++j) {
+                    const double2 pj = xy[j];
+                    const double dx = x - pj.x, dy = y + pj.y;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    if (has_phi(MODE)) {
+                        const double lg = log_tab(r2, tab);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
-                }
-                if (has_grad(MODE)) {
-                    const double sc = qs[j] * rcp_pos(r2);
-                    mx = fma(sc, dx, mx);
-                    my = fma(sc, dy, my);
+                        for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
+                    }
+                    if (has_grad(MODE)) {
+                        const double sc = qs[j] * rcp_pos(r2);
+                        mx = fma(sc, dx, mx);
+                        my = fma(sc, dy, my);
+                    }
                 }
             }
         }
-    }
-    if (has_phi(MODE)) {
+        if (has_phi(MODE)) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
-    }
-    if (has_grad(MODE)) {
-        a.near_gx[i] = mk(kInv2Pi * (mx - fx), 0.0);
-        a.near_gy[i] = mk(kInv2Pi * (my - fy), 0.0);
-        if (a.qc) a.qc[i] = qc;
+            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
+        }
+        if (has_grad(MODE)) {
+            a.near_gx[i] = mk(kInv2Pi * (mx - fx), 0.0);
+            a.near_gy[i] = mk(kInv2Pi * (my - fy), 0.0);
+            if (a.qc) a.qc[i] = qc;
+        }
     }
 }
 
@@ -1244,28 +1244,37 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     }
     FMMHP_CHECK(to_dev(A, &S.vimg_ent, vimg_ent, "vimg_ent", s));
 
-    // M2L tiles: up to kTile consecutive boxes of one level whose distinct upper V sources fit the
-    // LDS staging buffer (a tile that does not fit is split in halves).
+    // M2L tiles: up to kTile boxes of one level and one child class (bx & 1, by & 1), consecutive in
+    // Morton order.  Boxes of one class have the same V offsets away from boundaries, so the lanes
+    // of a tile walk the same offset slots.  A tile whose distinct upper V sources do not fit the
+    // LDS staging buffer is split in halves.  The FP32 matrix-core M2L stages all coefficients at
+    // once and takes consecutive boxes of all classes (fewer distinct sources per tile).
     std::vector<int32_t> tiles, tlev, tsoff(1, 0), tsrc;
     std::vector<int16_t> tslot;
     std::vector<uint64_t> tmask;
     {
-        std::vector<std::pair<int, int>> todo;  // [lo, hi) box ranges
+        std::vector<int32_t> seq;                  // boxes grouped by (level, class), Morton order
+        std::vector<std::pair<int, int>> todo;     // [lo, hi) ranges of seq
         for (int l = 2; l <= T.depth; ++l)
-            for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; b += kTile)
-                todo.push_back({b, std::min(b + kTile, T.lev_start[l + 1])});
+            for (int cls = 0; cls < (S.m2l_fp32 ? 1 : 4); ++cls) {
+                const int g0 = (int)seq.size();
+                for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b)
+                    if (S.m2l_fp32 || ((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
+                for (int a0 = g0; a0 < (int)seq.size(); a0 += kTile)
+                    todo.push_back({a0, std::min(a0 + kTile, (int)seq.size())});
+            }
         std::vector<int32_t> uniq;
         for (size_t ti = 0; ti < todo.size(); ++ti) {
             const int lo = todo[ti].first, hi = todo[ti].second;
             uniq.clear();
-            for (int b = lo; b < hi; ++b)
+            for (int q = lo; q < hi; ++q)
                 for (int o = 0; o < kNumSlots; ++o) {
-                    const int c = vslot[(size_t)o * nbox + b];
+                    const int c = vslot[(size_t)o * nbox + seq[q]];
                     if (c >= 0) uniq.push_back(c);
                 }
             std::sort(uniq.begin(), uniq.end());
             uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-            if ((int)uniq.size() > kM2LMaxSrc) {
+            if ((int)uniq.size() > (S.m2l_fp32 ? kM2LMaxSrc32 : kM2LMaxSrc)) {
                 const int mid = lo + (hi - lo) / 2;
                 todo.push_back({lo, mid});
                 todo.push_back({mid, hi});
@@ -1275,9 +1284,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             tslot.resize(t0 + (size_t)kNumSlots * kTile, (int16_t)-1);
             uint64_t msk = 0;
             for (int lane = 0; lane < kTile; ++lane) {
-                const int b = lo + lane;
-                tiles.push_back(b < hi ? b : -1);
-                if (b >= hi) continue;
+                const int q = lo + lane;
+                const int b = q < hi ? seq[q] : -1;
+                tiles.push_back(b);
+                if (b < 0) continue;
                 for (int o = 0; o < kNumSlots; ++o) {
                     const int c = vslot[(size_t)o * nbox + b];
                     if (c < 0) continue;
@@ -1286,7 +1296,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                     msk |= 1ull << o;
                 }
             }
-            tlev.push_back(level[lo]);
+            tlev.push_back(level[seq[lo]]);
             tmask.push_back(msk);
             tsrc.insert(tsrc.end(), uniq.begin(), uniq.end());
             tsoff.push_back((int32_t)tsrc.size());
@@ -1522,6 +1532,12 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     FMMHP_CHECK(ensure_vec_ws(A, T, S, 1));
     FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
     FMMHP_HIP(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking));
+    {
+        int dev = 0, cus = 0;
+        FMMHP_HIP(hipGetDevice(&dev));
+        FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        S.near_blocks = 4 * std::max(1, cus);
+    }
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
     hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
@@ -1584,7 +1600,10 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), dim3(nblk(T.n, 256)), dim3(256), 0, S.side, la);
+    // a bounded grid (four workgroups per CU) leaves room on every CU for the far-field kernels
+    // running concurrently on the main stream
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), dim3((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks)),
+                       dim3(256), 0, S.side, la);
     if (S.n_rpts > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
                            S.side, la);

@@ -22,8 +22,9 @@ constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
 constexpr int kM2LChunkMax = 8;   // at most this many output coefficients per M2L wave
-constexpr int kM2LPhase = 16;     // multipole coefficients staged in LDS per phase
-constexpr int kM2LMaxSrc = 200;   // distinct V sources per tile (LDS: 16 * 200 * 16 B)
+constexpr int kM2LPhase = 8;      // multipole coefficients staged in LDS per phase
+constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 8 * 400 * 16 B)
+constexpr int kM2LMaxSrc32 = 200; // the same for the FP32 matrix-core M2L (all coefficients staged)
 
 // Waves per M2L workgroup, each owning m2l_chunk(PB) consecutive output coefficients: the fewest
 // waves of at most kM2LChunkMax outputs, with the outputs spread evenly over them.
@@ -146,6 +147,7 @@ struct Sched {
     double2 *logtab = nullptr;      // near-field log table
     double2 *near = nullptr;        // [nv_cap][n] near-field sums
     hipStream_t side = nullptr;     // side stream for the near field (default priority)
+    int64_t near_blocks = 1024;     // near-field grid: four workgroups per CU
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
