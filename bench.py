@@ -230,7 +230,10 @@ def main():
     # roofline of the dominant kernel, from algorithmic work per launch / measured launch time
     P1 = info["p"] + 1
     m2l_flops = 8.0 * P1 * P1 * (info["m2l_pairs"][0] + info["m2l_pairs"][1])
-    dom = max(("m2l", "near"), key=lambda k: phase_avg[k])
+    # dominant kernel: the one with the most algorithmic work per launch (the near field runs
+    # concurrently on its own stream, so phase durations overlap)
+    near_flops = 27.0 * (info["p2p_pairs"][0] + info["p2p_pairs"][1])
+    dom = "m2l" if m2l_flops >= near_flops else "near"
     if dom == "m2l":
         achieved = m2l_flops / (phase_avg["m2l"] * 1e-3) / 1e12
         traffic = M2L_TRAFFIC.get((eval_source_hash(), info["p"], leaf_use))
