@@ -694,7 +694,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     static_assert(NV == 1 || MODE == kPhi, "several vectors in the potential mode only");
     __shared__ double2 s_logtab[kLogTable];
     if (has_phi(MODE)) {
-        if (threadIdx.x < kLogTable) s_logtab[threadIdx.x] = a.logtab[threadIdx.x];
+        for (int k = threadIdx.x; k < kLogTable; k += blockDim.x) s_logtab[k] = a.logtab[k];
         __syncthreads();
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {

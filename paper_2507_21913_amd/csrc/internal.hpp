@@ -22,8 +22,8 @@ constexpr int kTile = 64;         // target boxes per M2L tile (one per lane)
 constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
 constexpr int kM2LChunkMax = 8;   // at most this many output coefficients per M2L wave
-constexpr int kM2LPhase = 8;      // multipole coefficients staged in LDS per phase
-constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 8 * 400 * 16 B)
+constexpr int kM2LPhase = 4;      // multipole coefficients staged in LDS per phase
+constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 4 * 400 * 16 B)
 constexpr int kM2LMaxSrc32 = 200; // the same for the FP32 matrix-core M2L (all coefficients staged)
 
 // Waves per M2L workgroup, each owning m2l_chunk(PB) consecutive output coefficients: the fewest

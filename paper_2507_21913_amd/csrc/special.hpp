@@ -74,11 +74,11 @@ __device__ __forceinline__ double log_pos(double x) {
 }
 
 // Table-assisted natural logarithm of a positive finite double (the near-field pair loop).
-// x = 2^e m, m in [1, 2); the top 7 bits of the mantissa select c_k = 1 + (k + 1/2)/128, and
+// x = 2^e m, m in [1, 2); the top 9 bits of the mantissa select c_k = 1 + (k + 1/2)/512, and
 // log x = e ln 2 + L_k + log1p(t),  t = m r_k - 1,  r_k = fl(1/c_k),  L_k = -log(r_k),
-// with |t| <= 2^-8 so that log1p(t) = t - t^2/2 + ... + t^7/7 leaves an error below 2^-66.
-// The table entries (r_k, L_k) are built on the host by log_table_entry.
-constexpr int kLogTable = 128;
+// with |t| <= 2^-10 so that log1p(t) = t - t^2/2 + t^3/3 - t^4/4 + t^5/5 leaves an error below
+// 2^-62.  The table entries (r_k, L_k) are built on the host by log_table_entry.
+constexpr int kLogTable = 512;
 
 inline void log_table_entry(int k, double *r, double *L) {
     const double c = 1.0 + (k + 0.5) / kLogTable;
@@ -90,13 +90,11 @@ __device__ __forceinline__ double log_tab(double x, const double2 *__restrict__ 
     // exponent and mantissa bits (x > 0, normal)
     const unsigned long long u = __double_as_longlong(x);
     const int e = (int)(u >> 52) - 1023;
-    const int k = (int)((u >> 45) & (kLogTable - 1));
+    const int k = (int)((u >> 43) & (kLogTable - 1));
     const double m = __longlong_as_double((u & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
     const double2 rl = tab[k];
     const double t = fma(m, rl.x, -1.0);
-    double p = 1.0 / 7.0;
-    p = fma(p, t, -1.0 / 6.0);
-    p = fma(p, t, 1.0 / 5.0);
+    double p = 1.0 / 5.0;
     p = fma(p, t, -1.0 / 4.0);
     p = fma(p, t, 1.0 / 3.0);
     p = fma(p, t, -1.0 / 2.0);
