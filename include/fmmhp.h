@@ -162,11 +162,24 @@ fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const d
  *
  * Vectors are evaluated eight at a time where possible: the near field computes each pair's kernel
  * once for the eight, the far-field kernels take the vector as a grid dimension.  The first call
- * with n_vec >= 8 grows the plan's workspace for eight vectors.  Complex charges are linear:
- * evaluate their real and imaginary parts as two vectors.  No host synchronisation.
+ * with n_vec >= 8 grows the plan's workspace for eight vectors.  Complex charges: see
+ * fmmhp_eval_complex.  No host synchronisation.
  */
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
                         hipStream_t stream);
+
+/* Evaluate phi = A q for n_vec complex charge vectors: the operator is linear over the reals in the
+ * charges, so phi[q] = phi[Re q] + i phi[Im q], computed as two real passes and combined on the
+ * device (eqs. (potential1), (1.2), (reactioncomp1) with complex q_j).
+ *
+ *   q     [device] charges, [n_vec][n][2] (re, im) interleaved, caller's point order
+ *   phi   [device] output, [n_vec][n][2], caller's point order
+ *
+ * The first call allocates 48 bytes per point of workspace, owned by the plan.  No host
+ * synchronisation.  Errors as for fmmhp_eval.
+ */
+fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
+                                hipStream_t stream);
 
 /* Adjoint of fmmhp_eval for one real charge vector: gradients of a real loss l of phi with respect
  * to the charges, the point positions and the impedance (the reverse-mode step of phi = A q; the

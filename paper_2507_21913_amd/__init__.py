@@ -67,6 +67,7 @@ _SIGNATURES = {
                           ctypes.POINTER(_P)],
     "fmmhp_batch_plan_create": [_INT, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(_P)],
     "fmmhp_eval": [_P, _INT, _P, _P, _P],
+    "fmmhp_eval_complex": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
     "fmmhp_plan_export_tree": [_P] + [_P] * 18,
@@ -156,6 +157,10 @@ def fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr, grad_y_ptr
     _check("fmmhp_backward", lib().fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr,
                                                   grad_y_ptr, gl, stream))
     return [(gl[2 * k], gl[2 * k + 1]) for k in range(n_inst)] if want_lambda else None
+
+
+def fmmhp_eval_complex(plan, n_vec, q_ptr, phi_ptr, stream):
+    _check("fmmhp_eval_complex", lib().fmmhp_eval_complex(plan, n_vec, q_ptr, phi_ptr, stream))
 
 
 def fmmhp_plan_info(plan) -> dict:
@@ -329,26 +334,25 @@ class HalfPlaneFMM:
         q2 = q.reshape(1, -1) if squeeze else q
         if q2.shape[-1] != self.n:
             raise ValueError(f"q has {q2.shape[-1]} points, plan has {self.n}")
+        nv = q2.shape[0]
         if q2.is_complex():
-            parts = torch.cat([q2.real, q2.imag], 0).to(torch.float64).contiguous()
+            parts = torch.view_as_real(q2.to(torch.complex128).contiguous())
         else:
             parts = q2.to(torch.float64).contiguous()
-        nv = parts.shape[0]
-        direct_out = (out is not None and not q2.is_complex() and out.dtype == torch.complex128
-                      and out.is_contiguous() and out.device == self.device
-                      and out.numel() == nv * self.n)
+        direct_out = (out is not None and out.dtype == torch.complex128 and out.is_contiguous()
+                      and out.device == self.device and out.numel() == nv * self.n)
         if direct_out:
             raw = torch.view_as_real(out)
         else:
             raw = torch.empty((nv, self.n, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
-            fmmhp_eval(self._plan, nv, parts.data_ptr(), raw.data_ptr(), _stream())
+            if q2.is_complex():
+                fmmhp_eval_complex(self._plan, nv, parts.data_ptr(), raw.data_ptr(), _stream())
+            else:
+                fmmhp_eval(self._plan, nv, parts.data_ptr(), raw.data_ptr(), _stream())
         if direct_out:
             return out
         phi = torch.view_as_complex(raw)
-        if q2.is_complex():
-            k = q2.shape[0]
-            phi = phi[:k] + 1j * phi[k:]
         if out is not None:
             out.copy_(phi.reshape(out.shape))
             return out
@@ -468,4 +472,4 @@ __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functi
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
            "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune",
-           "fmmhp_backward", "potential", "fmmhp_batch_plan_create"]
+           "fmmhp_backward", "potential", "fmmhp_batch_plan_create", "fmmhp_eval_complex"]

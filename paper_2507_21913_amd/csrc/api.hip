@@ -206,6 +206,15 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
     return run_eval(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
+fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (n_vec < 1 || !q || !phi) {
+        set_error("n_vec must be >= 1 and q, phi non-NULL");
+        return FMMHP_EINVAL;
+    }
+    return run_eval_complex(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
+}
+
 fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
                             double *grad_x, double *grad_y, double *grad_lambda, hipStream_t stream) {
     FMMHP_CHECK(check_plan(plan));

@@ -1768,6 +1768,43 @@ fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Complex charges: phi[q_re + i q_im] = phi[q_re] + i phi[q_im] (the operator is real-linear in the
+// charges), evaluated as two real vectors and combined on the device.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_split_complex(const double *__restrict__ q, int64_t n, double *__restrict__ qr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    qr[i] = q[2 * i];
+    qr[n + i] = q[2 * i + 1];
+}
+
+__global__ void k_combine_complex(const double *__restrict__ p2, int64_t n, double *__restrict__ phi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // p2 = [phi[q_re]; phi[q_im]], each [n][2]
+    phi[2 * i] = p2[2 * i] - p2[2 * n + 2 * i + 1];
+    phi[2 * i + 1] = p2[2 * i + 1] + p2[2 * n + 2 * i];
+}
+
+fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
+                              hipStream_t s) {
+    if (!S.cq) {
+        FMMHP_CHECK(A.alloc_n(&S.cq, (size_t)2 * T.n, "complex-charge split"));
+        FMMHP_CHECK(A.alloc_n(&S.cphi, (size_t)4 * T.n, "complex-charge potentials"));
+    }
+    for (int v = 0; v < nvec; ++v) {
+        hipLaunchKernelGGL(k_split_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, q + (int64_t)v * 2 * T.n, T.n,
+                           S.cq);
+        FMMHP_HIP(hipGetLastError());
+        FMMHP_CHECK(run_eval(A, T, S, 2, S.cq, S.cphi, s));
+        hipLaunchKernelGGL(k_combine_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, S.cphi, T.n,
+                           phi + (int64_t)v * 2 * T.n);
+        FMMHP_HIP(hipGetLastError());
+    }
+    return FMMHP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Adjoint.  For a real loss l of the complex potential, with incoming g_i = dl/dRe phi_i +
 // i dl/dIm phi_i (so l = sum_i Re(conj(g_i) phi_i) to first order) and c = conj(g):
 //   dl/dq_j = Re Phi[c](r_j)                                  (G(r, r') = G(r', r), eq. (greensfunsymm))

@@ -176,6 +176,7 @@ struct Sched {
     cplx *red = nullptr;            // [nv][n_rch] surface partial sums
     cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
     BwdWork bw;
+    double *cq = nullptr, *cphi = nullptr;  // complex-charge workspace ([2][n], [2][n][2])
     // recorded evaluation (FMMHP_FLAG_GRAPH)
     bool use_graph = false;
     struct {
@@ -199,6 +200,8 @@ struct Sched {
 fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cplx *Zs, hipStream_t stream);
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
+fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
+                              hipStream_t stream);
 
 fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
                           double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t stream);

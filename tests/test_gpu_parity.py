@@ -173,3 +173,17 @@ def test_fmm_deterministic_and_multivector():
     qc = torch.complex(q[0], q[1])
     pc = plan(qc).cpu().numpy()
     assert np.allclose(pc, a[0] + 1j * a[1], rtol=0, atol=1e-12 * np.abs(a[:2]).max())
+
+
+@pytest.mark.parametrize("Z", [1.0, 0.7 + 0.4j])
+def test_complex_charges_vs_oracle(Z):
+    """fmmhp_eval_complex: complex charges, split and recombined on the device."""
+    w = workloads.uniform(2500, 17, n_vec=4)
+    qc = w.q[0] + 1j * w.q[1]
+    qc2 = w.q[2] - 0.5j * w.q[3]
+    ref = D.potential(w.x, w.y, np.stack([qc, qc2]), Z, workers=8)
+    plan = F.HalfPlaneFMM(_t(w.x), _t(w.y), Z, p=30, leaf_size=24)
+    got = plan(torch.as_tensor(np.stack([qc, qc2]), device=DEV)).cpu().numpy()
+    for v in range(2):
+        assert D.rel_l2(got[v], ref[v]) < 1e-10, v
+    plan.close()
