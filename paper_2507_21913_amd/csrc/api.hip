@@ -123,6 +123,9 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
         if (p->sched.ev_fork) (void)hipEventDestroy(p->sched.ev_fork);
         if (p->sched.ev_join) (void)hipEventDestroy(p->sched.ev_join);
         if (p->sched.side) (void)hipStreamDestroy(p->sched.side);
+        if (p->sched.side2) (void)hipStreamDestroy(p->sched.side2);
+        if (p->sched.ev_deep_ready) (void)hipEventDestroy(p->sched.ev_deep_ready);
+        if (p->sched.ev_deep_done) (void)hipEventDestroy(p->sched.ev_deep_done);
         p->arena.release();
         p->magic = kDead;
         delete p;
@@ -347,6 +350,9 @@ fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
     if (plan->sched.ev_fork) (void)hipEventDestroy(plan->sched.ev_fork);
     if (plan->sched.ev_join) (void)hipEventDestroy(plan->sched.ev_join);
     if (plan->sched.side) (void)hipStreamDestroy(plan->sched.side);
+    if (plan->sched.side2) (void)hipStreamDestroy(plan->sched.side2);
+    if (plan->sched.ev_deep_ready) (void)hipEventDestroy(plan->sched.ev_deep_ready);
+    if (plan->sched.ev_deep_done) (void)hipEventDestroy(plan->sched.ev_deep_done);
     if (plan->sched.graph.exec) (void)hipGraphExecDestroy(plan->sched.graph.exec);
     plan->arena.release();
     plan->magic = kDead;

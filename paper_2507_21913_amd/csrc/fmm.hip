@@ -205,6 +205,7 @@ __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int
 // ---------------------------------------------------------------------------------------------
 struct M2LArgs {
     int nbox;
+    int tile0;               // first tile of this launch
     const int32_t *tiles, *tile_level, *tile_src_off, *tile_src;
     const int16_t *tile_slot;
     const uint64_t *tile_mask;
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
     constexpr int NTP = m2l_row(PB);
     constexpr int NPH = (PB + kM2LPhase) / kM2LPhase;
     __shared__ cplx sW[kM2LPhase * kM2LMaxSrc];
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x + a.tile0;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n0 = wave * CH;
     const int lane = threadIdx.x & 63;
@@ -303,6 +304,7 @@ __host__ __device__ constexpr int m2l32_np(int PB) { return ((2 * (PB + 1) + 15)
 
 struct M2L32Args {
     int nbox;
+    int tile0;               // first tile of this launch
     const int32_t *tiles, *tile_src_off, *tile_src;
     const int16_t *tile_slot;
     const uint64_t *tile_mask;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(256) void k_m2l_f32(M2L32Args a) {
     __shared__ float sA[kM2LMaxSrc32 * KP];
     __shared__ float sB[2][BSZ];
     __shared__ cplx s_acc0[kTile];
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x + a.tile0;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int r = lane & 15, kq = lane >> 4;
@@ -1241,6 +1243,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             if (vimg_off[b + 1] > vimg_off[b]) ib.push_back(b);
         S.nibox = (int)ib.size();
         FMMHP_CHECK(to_dev(A, &S.ibox, ib, "image V boxes", s));
+        S.ibox_lev.assign(T.depth + 2, 0);
+        for (int l = 0; l <= T.depth + 1; ++l)
+            S.ibox_lev[l] = (int)(std::lower_bound(ib.begin(), ib.end(), T.lev_start[std::max(1, std::min(l, T.depth + 1))]) - ib.begin());
     }
     FMMHP_CHECK(to_dev(A, &S.vimg_ent, vimg_ent, "vimg_ent", s));
 
@@ -1254,16 +1259,18 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     std::vector<uint64_t> tmask;
     {
         std::vector<int32_t> seq;                  // boxes grouped by (level, class), Morton order
-        std::vector<std::pair<int, int>> todo;     // [lo, hi) ranges of seq
-        for (int l = 2; l <= T.depth; ++l)
-            for (int cls = 0; cls < (S.m2l_fp32 ? 1 : 4); ++cls) {
-                const int g0 = (int)seq.size();
-                for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b)
-                    if (S.m2l_fp32 || ((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
-                for (int a0 = g0; a0 < (int)seq.size(); a0 += kTile)
-                    todo.push_back({a0, std::min(a0 + kTile, (int)seq.size())});
-            }
         std::vector<int32_t> uniq;
+        S.tile_lev.assign(T.depth + 2, 0);
+        for (int l = 2; l <= T.depth; ++l) {
+        S.tile_lev[l] = (int)tlev.size();
+        std::vector<std::pair<int, int>> todo;     // [lo, hi) ranges of seq (this level)
+        for (int cls = 0; cls < (S.m2l_fp32 ? 1 : 4); ++cls) {
+            const int g0 = (int)seq.size();
+            for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b)
+                if (S.m2l_fp32 || ((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
+            for (int a0 = g0; a0 < (int)seq.size(); a0 += kTile)
+                todo.push_back({a0, std::min(a0 + kTile, (int)seq.size())});
+        }
         for (size_t ti = 0; ti < todo.size(); ++ti) {
             const int lo = todo[ti].first, hi = todo[ti].second;
             uniq.clear();
@@ -1301,6 +1308,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             tsrc.insert(tsrc.end(), uniq.begin(), uniq.end());
             tsoff.push_back((int32_t)tsrc.size());
         }
+        }
+        S.tile_lev[T.depth + 1] = (int)tlev.size();
+        S.tile_lev[0] = S.tile_lev[1] = 0;
     }
     S.ntiles = (int)tlev.size();
     FMMHP_CHECK(to_dev(A, &S.tiles, tiles, "tiles", s));
@@ -1318,6 +1328,19 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     }
     S.nxbox = (int)xb.size();
     FMMHP_CHECK(to_dev(A, &S.xbox, xb, "xbox", s));
+    S.xbox_lev.assign(T.depth + 2, 0);
+    for (int l = 0; l <= T.depth + 1; ++l)
+        S.xbox_lev[l] = (int)(std::lower_bound(xb.begin(), xb.end(), T.lev_start[std::max(1, std::min(l, T.depth + 1))]) - xb.begin());
+    // deep split: the finest levels holding at least half of the M2L tiles run on a second stream
+    // as soon as their multipoles exist, beside the rest of the upward pass
+    S.deep_level = 0;
+    if (S.ntiles > 0) {
+        for (int l = T.depth; l >= 3; --l)
+            if (2 * (S.tile_lev[T.depth + 1] - S.tile_lev[l]) >= S.ntiles) {
+                S.deep_level = l;
+                break;
+            }
+    }
     FMMHP_CHECK(to_dev(A, &S.leaves, lv, "leaves", s));
     {
         std::vector<int32_t> woff, first, wp, rl;
@@ -1532,6 +1555,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     FMMHP_CHECK(ensure_vec_ws(A, T, S, 1));
     FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
     FMMHP_HIP(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking));
+    FMMHP_HIP(hipStreamCreateWithFlags(&S.side2, hipStreamNonBlocking));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_deep_ready, hipEventDisableTiming));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_deep_done, hipEventDisableTiming));
     {
         int dev = 0, cus = 0;
         FMMHP_HIP(hipGetDevice(&dev));
@@ -1550,6 +1576,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
 struct Marks {
     hipEvent_t ev[FMMHP_NUM_PHASES + 1];  // main-stream boundaries; the NEAR slot pair is unused
     hipEvent_t near0 = nullptr, near1 = nullptr;
+    hipEvent_t deep0 = nullptr, deep1 = nullptr;  // deep-level M2L on the second stream
     bool on = false;
     fmmhp_status init(const Sched &S) {
         on = S.timing;
@@ -1557,6 +1584,8 @@ struct Marks {
         for (auto &e : ev) FMMHP_HIP(hipEventCreate(&e));
         FMMHP_HIP(hipEventCreate(&near0));
         FMMHP_HIP(hipEventCreate(&near1));
+        FMMHP_HIP(hipEventCreate(&deep0));
+        FMMHP_HIP(hipEventCreate(&deep1));
         return FMMHP_OK;
     }
     fmmhp_status mark(int k, hipStream_t s) {
@@ -1568,6 +1597,8 @@ struct Marks {
         for (auto &e : ev) S.events->push_back(e);
         S.events->push_back(near0);
         S.events->push_back(near1);
+        S.events->push_back(deep0);
+        S.events->push_back(deep1);
     }
 };
 
@@ -1614,11 +1645,55 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
                        S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
+    // M2L (+ image M2L, P2L) over the levels [l0, l1) of the tree on stream st
+    auto far_levels = [&](int l0, int l1, hipStream_t st) -> fmmhp_status {
+        const int t0 = S.tile_lev[l0], t1 = S.tile_lev[l1];
+        if (t1 > t0) {
+            constexpr int CH = m2l_chunk(PB);
+            static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
+            if (S.m2l_fp32) {
+                M2L32Args ma{nbox,    t0,        S.tiles, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
+                             S.Bf32,  S.Lfree,   S.logside, S.fact,       S.W,        S.Lam,       S.nloc};
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(t1 - t0, NV), dim3(256), 0, st, ma);
+            } else {
+                M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
+                           S.tile_mask, S.Tfree, S.Lfree, S.logside,  S.W,            S.Lam,      S.nloc};
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)), 0,
+                                   st, ma);
+            }
+        }
+        const int i0 = S.ibox_lev[l0], i1 = S.ibox_lev[l1];
+        if (i1 > i0)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)(i1 - i0) * (PB + 1), 256), NV),
+                               dim3(256), 0, st, i1 - i0, S.ibox + i0, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
+                               S.TimgH, S.TimgG, S.Limg, S.logside, S.W, S.Lam);
+        const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
+        if (x1 > x0)
+            for (int loc = 0; loc < S.nloc; ++loc)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(x1 - x0, NV), dim3(64), 0, st, S.inst_info, T.inst,
+                                   NV, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count, T.off[3],
+                                   T.ent[3], T.xs, T.ys, S.qs, S.fact, S.Lam);
+        FMMHP_HIP(hipGetLastError());
+        return FMMHP_OK;
+    };
+    // the deep levels [ld, depth] start on the second stream once their multipoles exist
+    const int ld = S.deep_level;
+    auto fork_deep = [&]() -> fmmhp_status {
+        FMMHP_HIP(hipEventRecord(S.ev_deep_ready, s));
+        FMMHP_HIP(hipStreamWaitEvent(S.side2, S.ev_deep_ready, 0));
+        if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.deep0, S.side2));
+        FMMHP_CHECK(far_levels(ld, T.depth + 1, S.side2));
+        if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.deep1, S.side2));
+        FMMHP_HIP(hipEventRecord(S.ev_deep_done, S.side2));
+        return FMMHP_OK;
+    };
+    if (ld > 0 && ld > T.depth - 1) FMMHP_CHECK(fork_deep());
     for (int l = T.depth - 1; l >= 2; --l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256), 0, s, lo, nb,
                                nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+        if (ld > 0 && l == ld) FMMHP_CHECK(fork_deep());
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
@@ -1629,39 +1704,20 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
             hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc * NV,
                                S.Lam);
     }
-    if (S.ntiles > 0) {
-        constexpr int CH = m2l_chunk(PB);
-        static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
-        if (S.m2l_fp32) {
-            M2L32Args ma{nbox,    S.tiles, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask, S.Bf32,
-                         S.Lfree, S.logside, S.fact,        S.W,        S.Lam,       S.nloc};
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(S.ntiles, NV), dim3(256), 0, s, ma);
-        } else {
-            M2LArgs ma{nbox,    S.tiles, S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
-                       S.Tfree, S.Lfree, S.logside,    S.W,            S.Lam,      S.nloc};
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(S.ntiles, NV), dim3(64 * m2l_waves(PB)), 0, s,
-                               ma);
-        }
-        if (S.nibox > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)S.nibox * (PB + 1), 256), NV),
-                               dim3(256), 0, s, S.nibox, S.ibox, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
-                               S.TimgH, S.TimgG, S.Limg, S.logside, S.W, S.Lam);
-        FMMHP_HIP(hipGetLastError());
-    }
+    FMMHP_CHECK(far_levels(2, ld > 0 ? ld : T.depth + 1, s));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
-    if (S.nxbox > 0) {
-        for (int loc = 0; loc < S.nloc; ++loc)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(S.nxbox, NV), dim3(64), 0, s, S.inst_info, T.inst,
-                               NV, S.nloc, loc, S.xbox, nbox, T.level, T.bx, T.by, T.first, T.count, T.off[3],
-                               T.ent[3], T.xs, T.ys, S.qs, S.fact, S.Lam);
-        FMMHP_HIP(hipGetLastError());
-    }
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_L2L, s));
     for (int l = 3; l <= T.depth; ++l) {
+        if (ld > 0 && l == ld) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256), 0, s, lo, nb,
                                nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+    }
+    if (ld > 0 && ld > T.depth) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
+    if (mk_.on && ld == 0) {
+        FMMHP_HIP(hipEventRecord(mk_.deep0, s));
+        FMMHP_HIP(hipEventRecord(mk_.deep1, s));
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
@@ -1931,16 +1987,24 @@ fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, co
 fmmhp_status collect_phase_times(Sched &S) {
     if (!S.events) return FMMHP_OK;
     auto &ev = *S.events;
-    const int G = FMMHP_NUM_PHASES + 3;  // main boundaries + side-stream near pair
+    // group: main-stream boundaries [0, NUM_PHASES], near pair, deep-M2L pair
+    const int G = FMMHP_NUM_PHASES + 5;
     for (size_t g0 = 0; g0 + G <= ev.size(); g0 += G) {
+        const size_t n0 = g0 + FMMHP_NUM_PHASES + 1, d0 = n0 + 2;
         FMMHP_HIP(hipEventSynchronize(ev[g0 + FMMHP_NUM_PHASES]));
-        FMMHP_HIP(hipEventSynchronize(ev[g0 + G - 1]));
+        FMMHP_HIP(hipEventSynchronize(ev[n0 + 1]));
+        FMMHP_HIP(hipEventSynchronize(ev[d0 + 1]));
         for (int k = 0; k < FMMHP_NUM_PHASES; ++k) {
             float ms = 0.f;
             if (k == FMMHP_PHASE_NEAR)
-                FMMHP_HIP(hipEventElapsedTime(&ms, ev[g0 + G - 2], ev[g0 + G - 1]));
+                FMMHP_HIP(hipEventElapsedTime(&ms, ev[n0], ev[n0 + 1]));
             else if (k < FMMHP_PHASE_NEAR)
                 FMMHP_HIP(hipEventElapsedTime(&ms, ev[g0 + k], ev[g0 + k + 1]));
+            if (k == FMMHP_PHASE_M2L) {
+                float md = 0.f;
+                FMMHP_HIP(hipEventElapsedTime(&md, ev[d0], ev[d0 + 1]));
+                ms += md;
+            }
             S.phase_ms[k] += ms;
         }
         S.timed_evals += 1;

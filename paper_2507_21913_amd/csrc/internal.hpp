@@ -147,6 +147,10 @@ struct Sched {
     double2 *logtab = nullptr;      // near-field log table
     double2 *near = nullptr;        // [nv_cap][n] near-field sums
     hipStream_t side = nullptr;     // side stream for the near field (default priority)
+    hipStream_t side2 = nullptr;    // second side stream: M2L of the deep levels (default priority)
+    hipEvent_t ev_deep_ready = nullptr, ev_deep_done = nullptr;
+    int deep_level = 0;             // first level of the deep M2L part (0: no split)
+    std::vector<int> tile_lev, ibox_lev, xbox_lev;  // per-level ranges of tiles, image-V and X boxes
     int64_t near_blocks = 1024;     // near-field grid: four workgroups per CU
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
