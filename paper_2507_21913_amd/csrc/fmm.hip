@@ -693,7 +693,6 @@ struct LeafArgs {
 // targets).  NV charge vectors share each pair's kernel value.
 template <int MODE, int NV>
 __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
-    static_assert(NV == 1 || MODE == kPhi, "several vectors in the potential mode only");
     __shared__ double2 s_logtab[kLogTable];
     if (has_phi(MODE)) {
         for (int k = threadIdx.x; k < kLogTable; k += blockDim.x) s_logtab[k] = a.logtab[k];
@@ -706,7 +705,10 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
         double lfree[NV], limg[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) lfree[v] = limg[v] = 0.0;
-        double fx = 0.0, fy = 0.0, mx = 0.0, my = 0.0, qc = 0.0;
+        double fx[NV], fy[NV], mx[NV], my[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fx[v] = fy[v] = mx[v] = my[v] = 0.0;
+        double qc = 0.0;  // coincident charge of vector 0
         const double2 *__restrict__ xy = a.xy;
         const double2 *__restrict__ tab = s_logtab;
         const double *__restrict__ qs = a.qs;
@@ -726,11 +728,15 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                         for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
                     }
                     if (has_grad(MODE)) {
-                        const double qj = qs[j];
-                        const double sc = (nz ? qj : 0.0) * rcp_pos(nz ? r2 : 1.0);
-                        fx = fma(sc, dx, fx);
-                        fy = fma(sc, dy, fy);
-                        qc += nz ? 0.0 : qj;
+                        const double ir = nz ? rcp_pos(nz ? r2 : 1.0) : 0.0;
+                        const double irx = ir * dx, iry = ir * dy;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const double qj = qs[(int64_t)j * NV + v];
+                            fx[v] = fma(qj, irx, fx[v]);
+                            fy[v] = fma(qj, iry, fy[v]);
+                        }
+                        qc += nz ? 0.0 : qs[(int64_t)j * NV];
                     }
                 }
             } else {
@@ -744,9 +750,14 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                         for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
                     }
                     if (has_grad(MODE)) {
-                        const double sc = qs[j] * rcp_pos(r2);
-                        mx = fma(sc, dx, mx);
-                        my = fma(sc, dy, my);
+                        const double ir = rcp_pos(r2);
+                        const double irx = ir * dx, iry = ir * dy;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const double qj = qs[(int64_t)j * NV + v];
+                            mx[v] = fma(qj, irx, mx[v]);
+                            my[v] = fma(qj, iry, my[v]);
+                        }
                     }
                 }
             }
@@ -756,8 +767,11 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
             for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
         }
         if (has_grad(MODE)) {
-            a.near_gx[i] = mk(kInv2Pi * (mx - fx), 0.0);
-            a.near_gy[i] = mk(kInv2Pi * (my - fy), 0.0);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * (mx[v] - fx[v]), 0.0);
+                a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * (my[v] - fy[v]), 0.0);
+            }
             if (a.qc) a.qc[i] = qc;
         }
     }
@@ -818,7 +832,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
         out[2 * o + 1] = phi.im;
     }
     if (has_grad(MODE)) {
-        cplx gx = a.near_gx[i], gy = a.near_gy[i];
+        cplx gx = a.near_gx[(int64_t)v * a.n + i], gy = a.near_gy[(int64_t)v * a.n + i];
         if (a.nloc == 1) {
             const cplx ZE = Zk * E;
             gx += mk(2.0 * Hd.re, 0.0) + ZE;
@@ -827,8 +841,8 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
             gx += Hd + conj(Gd);
             gy += mul_ipow(Hd - conj(Gd), 1);
         }
-        a.gx[o] = gx;
-        a.gy[o] = gy;
+        a.gx[(int64_t)v * a.n + o] = gx;
+        a.gy[(int64_t)v * a.n + o] = gy;
     }
 }
 
@@ -924,12 +938,13 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
         }
     }
     if (has_grad(MODE)) {
+        cplx *gx = a.gx + (int64_t)v * a.n + o, *gy = a.gy + (int64_t)v * a.n + o;
         if (a.nloc == 1) {
-            a.gx[o] += mk(2.0 * Hd.re, 0.0);
-            a.gy[o] += mk(-2.0 * Hd.im, 0.0);
+            *gx += mk(2.0 * Hd.re, 0.0);
+            *gy += mk(-2.0 * Hd.im, 0.0);
         } else {
-            a.gx[o] += Hd + conj(Gd);
-            a.gy[o] += mul_ipow(Hd - conj(Gd), 1);
+            *gx += Hd + conj(Gd);
+            *gy += mul_ipow(Hd - conj(Gd), 1);
         }
     }
 }
@@ -947,7 +962,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 // vectors share each pair's kernel value.  Adds to the near-field sums.
 template <int MODE, int NV>
 __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
-    static_assert(NV == 1 || MODE == kPhi, "several vectors in the potential mode only");
     const int i = a.rpts[blockIdx.x];
     const int b = a.leaf_of[i];
     const cplx Z = a.ii[a.inst[b]].Z;
@@ -956,7 +970,9 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
     double sr[NV], si[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) sr[v] = si[v] = 0.0;
-    cplx s1p = mk(0.0, 0.0), s1m = mk(0.0, 0.0);  // sum q I_1(X, Y), sum q I_1(-X, Y)
+    cplx s1p[NV], s1m[NV];  // sum q I_1(X, Y), sum q I_1(-X, Y) per vector
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s1p[v] = s1m[v] = mk(0.0, 0.0);
     for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
         const int code = a.uent[e];
         if (!(code & 1)) continue;
@@ -965,7 +981,11 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
         for (int j = a.first[c] + lane; j < j1; j += 64) {
             const double dx = x - a.xs[j], dy = y + a.ys[j];
             const cplx I = reaction_I0_near(dx, dy, Z);
-            if (has_grad(MODE)) s1p += a.qs[j] * (kInv2Pi * inv(mk(dy, -dx)) + Z * I);
+            if (has_grad(MODE)) {
+                const cplx I1 = kInv2Pi * inv(mk(dy, -dx)) + Z * I;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s1p[v] += a.qs[(int64_t)j * NV + v] * I1;
+            }
             if (a.nloc == 1) {
                 if (has_phi(MODE)) {
 #pragma unroll
@@ -982,7 +1002,11 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
                         si[v] += qj * hv.im;
                     }
                 }
-                if (has_grad(MODE)) s1m += a.qs[j] * (kInv2Pi * inv(mk(dy, dx)) + Z * Im_);
+                if (has_grad(MODE)) {
+                    const cplx I1m = kInv2Pi * inv(mk(dy, dx)) + Z * Im_;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) s1m[v] += a.qs[(int64_t)j * NV + v] * I1m;
+                }
             }
         }
     }
@@ -994,8 +1018,11 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
         }
     }
     if (has_grad(MODE)) {
-        s1p = mk(wave_sum(s1p.re), wave_sum(s1p.im));
-        s1m = mk(wave_sum(s1m.re), wave_sum(s1m.im));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            s1p[v] = mk(wave_sum(s1p[v].re), wave_sum(s1p[v].im));
+            s1m[v] = mk(wave_sum(s1m[v].re), wave_sum(s1m[v].im));
+        }
     }
     if (lane == 0) {
         if (has_phi(MODE)) {
@@ -1013,13 +1040,17 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
             }
         }
         if (has_grad(MODE)) {
-            if (a.nloc == 1) {
-                // d_x 2 Re sum q I_0 = 2 Re(i S1) ; d_y = -2 Re S1
-                a.near_gx[i] += mk(-2.0 * s1p.im, 0.0);
-                a.near_gy[i] += mk(-2.0 * s1p.re, 0.0);
-            } else {
-                a.near_gx[i] += mul_ipow(s1p - s1m, 1);
-                a.near_gy[i] -= s1p + s1m;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                cplx *gx = a.near_gx + (int64_t)v * a.n + i, *gy = a.near_gy + (int64_t)v * a.n + i;
+                if (a.nloc == 1) {
+                    // d_x 2 Re sum q I_0 = 2 Re(i S1) ; d_y = -2 Re S1
+                    *gx += mk(-2.0 * s1p[v].im, 0.0);
+                    *gy += mk(-2.0 * s1p[v].re, 0.0);
+                } else {
+                    *gx += mul_ipow(s1p[v] - s1m[v], 1);
+                    *gy -= s1p[v] + s1m[v];
+                }
             }
         }
     }
@@ -1757,10 +1788,6 @@ static fmmhp_status run_pass(const Tree &T, const Sched &S, const double *q, con
     }
 }
 
-template <int MODE>
-static fmmhp_status run_eval_vec(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
-    return run_pass<MODE, 1>(T, S, q, out, s);
-}
 
 // Per-vector workspace (multipoles, locals, sorted charges, near-field sums, surface sums) for nv
 // vectors at once; grown on demand, owned by the plan.
@@ -1874,12 +1901,14 @@ fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const
 // l_c = sum_i c_i phi_i, for any x0 (translation invariance in x; the root centre is used).
 // dl/dZ is reported as dl/dRe Z + i dl/dIm Z = conj(dl_c/dZ) (phi is holomorphic in Z).
 // ---------------------------------------------------------------------------------------------
-__global__ void k_split_conj(const double *__restrict__ g, int64_t n, double *__restrict__ cr,
-                             double *__restrict__ ci) {
+// q3 = [q; Re conj(g); Im conj(g)], [3][n] caller order: the three charge vectors of the adjoint
+__global__ void k_stack3(const double *__restrict__ q, const double *__restrict__ g, int64_t n,
+                         double *__restrict__ q3) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o < n) {
-        cr[o] = g[2 * o];
-        ci[o] = -g[2 * o + 1];
+        q3[o] = q[o];
+        q3[n + o] = g[2 * o];
+        q3[2 * n + o] = -g[2 * o + 1];
     }
 }
 
@@ -1928,11 +1957,10 @@ static fmmhp_status ensure_bwd(Arena &A, const Tree &T, Sched &S) {
     if (S.bw.ready) return FMMHP_OK;
     const size_t n = (size_t)T.n;
     BwdWork &b = S.bw;
-    FMMHP_CHECK(A.alloc_n(&b.cr, n, "adjoint charges (re)"));
-    FMMHP_CHECK(A.alloc_n(&b.ci, n, "adjoint charges (im)"));
+    FMMHP_CHECK(A.alloc_n(&b.q3, 3 * n, "adjoint charge vectors"));
     FMMHP_CHECK(A.alloc_n(&b.qc, n, "coincident charge sums"));
-    cplx **bufs[] = {&b.phr, &b.phi_i, &b.gxq, &b.gyq, &b.gxr, &b.gyr, &b.gxi, &b.gyi, &b.near_gx, &b.near_gy};
-    for (cplx **pp : bufs) FMMHP_CHECK(A.alloc_n(pp, n, "adjoint fields"));
+    cplx **bufs[] = {&b.phi3, &b.gx3, &b.gy3, &b.near_gx, &b.near_gy};
+    for (cplx **pp : bufs) FMMHP_CHECK(A.alloc_n(pp, 3 * n, "adjoint fields"));
     FMMHP_CHECK(A.alloc_n(&b.red, (size_t)S.n_rch + T.n_inst, "adjoint reduction"));
     b.ready = true;
     return FMMHP_OK;
@@ -1941,37 +1969,33 @@ static fmmhp_status ensure_bwd(Arena &A, const Tree &T, Sched &S) {
 fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
                           double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t s) {
     FMMHP_CHECK(ensure_bwd(A, T, S));
+    FMMHP_CHECK(ensure_vec_ws(A, T, S, 3));  // multipoles, locals, sums for the three vectors
     BwdWork &b = S.bw;
     const bool pos = grad_x || grad_y || zsum_host;
     if (!pos && !grad_q) return FMMHP_OK;
-    hipLaunchKernelGGL(k_split_conj, dim3(nblk(T.n, 256)), dim3(256), 0, s, g, T.n, b.cr, b.ci);
+    const int64_t n = T.n;
+    hipLaunchKernelGGL(k_stack3, dim3(nblk(n, 256)), dim3(256), 0, s, q, g, n, b.q3);
     FMMHP_HIP(hipGetLastError());
-    PassOut pr, pi;
-    pr.phi = (double *)b.phr;
-    pi.phi = (double *)b.phi_i;
     if (pos) {
-        PassOut pq;
-        pq.gx = b.gxq;
-        pq.gy = b.gyq;
-        pq.qc = b.qc;
-        FMMHP_CHECK(run_eval_vec<kGrad>(T, S, q, pq, s));
-        pr.gx = b.gxr;
-        pr.gy = b.gyr;
-        pi.gx = b.gxi;
-        pi.gy = b.gyi;
-        if (grad_q) {
-            FMMHP_CHECK(run_eval_vec<kPhiGrad>(T, S, b.cr, pr, s));
-            FMMHP_CHECK(run_eval_vec<kPhiGrad>(T, S, b.ci, pi, s));
-        } else {
-            FMMHP_CHECK(run_eval_vec<kGrad>(T, S, b.cr, pr, s));
-            FMMHP_CHECK(run_eval_vec<kGrad>(T, S, b.ci, pi, s));
-        }
+        // one pass over the three vectors: potential and gradient, the near field shared by all three
+        PassOut po;
+        po.phi = (double *)b.phi3;
+        po.gx = b.gx3;
+        po.gy = b.gy3;
+        po.qc = b.qc;
+        FMMHP_CHECK((run_pass<kPhiGrad, 3>(T, S, b.q3, po, s)));
     } else {
-        FMMHP_CHECK(run_eval_vec<kPhi>(T, S, b.cr, pr, s));
-        FMMHP_CHECK(run_eval_vec<kPhi>(T, S, b.ci, pi, s));
+        // dl/dq only: the potentials of Re conj(g) and Im conj(g)
+        for (int v = 1; v < 3; ++v) {
+            PassOut po;
+            po.phi = (double *)(b.phi3 + v * n);
+            FMMHP_CHECK((run_pass<kPhi, 1>(T, S, b.q3 + v * n, po, s)));
+        }
     }
-    BwdArgs ba{S.inst_info, S.rch,  T.xs,  T.ys,  T.perm, q,      g,      b.phr,  b.phi_i, b.gxq, b.gyq,
-               b.gxr,       b.gyr,  b.gxi, b.gyi, b.qc,   grad_q, grad_x, grad_y, b.red,   pos ? 1 : 0};
+    BwdArgs ba{S.inst_info, S.rch,         T.xs,          T.ys,          T.perm,    q,      g,
+               b.phi3 + n,  b.phi3 + 2 * n, b.gx3,         b.gy3,         b.gx3 + n, b.gy3 + n,
+               b.gx3 + 2 * n, b.gy3 + 2 * n, b.qc,         grad_q,        grad_x,    grad_y, b.red,
+               pos ? 1 : 0};
     hipLaunchKernelGGL(k_bwd_combine, dim3(S.n_rch), dim3(256), 0, s, ba);
     FMMHP_HIP(hipGetLastError());
     if (zsum_host) {

@@ -106,14 +106,14 @@ struct PtChunk {
     int32_t inst, pad;
 };
 
-// Adjoint workspace, allocated on the first backward call: [n] per array.
+// Adjoint workspace, allocated on the first backward call.
 struct BwdWork {
     bool ready = false;
-    double *cr = nullptr, *ci = nullptr;  // conj(g) as two real charge vectors (caller order)
-    double *qc = nullptr;                 // coincident charge sums (sorted order)
-    cplx *phr = nullptr, *phi_i = nullptr;
-    cplx *gxq = nullptr, *gyq = nullptr, *gxr = nullptr, *gyr = nullptr, *gxi = nullptr, *gyi = nullptr;
-    cplx *near_gx = nullptr, *near_gy = nullptr;  // near-field gradient (sorted order)
+    double *q3 = nullptr;                 // [3][n] q, Re conj(g), Im conj(g) (caller order)
+    double *qc = nullptr;                 // [n] coincident charge sums of q (sorted order)
+    cplx *phi3 = nullptr;                 // [3][n] potentials (caller order)
+    cplx *gx3 = nullptr, *gy3 = nullptr;  // [3][n] gradients (caller order)
+    cplx *near_gx = nullptr, *near_gy = nullptr;  // [3][n] near-field gradients (sorted order)
     cplx *red = nullptr;                  // [n chunks + n_inst] reduction partials + results
 };
 
