@@ -98,6 +98,16 @@ __global__ void k_pack_xy(const double *__restrict__ xs, const double *__restric
 // ---------------------------------------------------------------------------------------------
 // Charges into sorted order
 // ---------------------------------------------------------------------------------------------
+// U entry (box << 1 | image) -> (first point, count | image << 31) of the box
+__global__ void k_u2(int64_t m, const int32_t *__restrict__ uent, const int32_t *__restrict__ first,
+                     const int32_t *__restrict__ count, int2 *__restrict__ u2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int code = uent[i], c = code >> 1;
+    u2[i] = make_int2(first[c], (int)((unsigned)count[c] | ((unsigned)(code & 1) << 31)));
+}
+
+// ---------------------------------------------------------------------------------------------
 // nv charge vectors [nv][n] (caller order) -> qs[i * nv + v] (sorted, vectors interleaved)
 __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n, int nv,
                            double *__restrict__ qs) {
@@ -108,48 +118,126 @@ __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restri
 }
 
 // ---------------------------------------------------------------------------------------------
-// P2M: leaves
+// P2M: leaves.  kP2MSplit consecutive lanes share a leaf, each summing every kP2MSplit-th point;
+// a butterfly over the lanes combines the partial sums (the same value, bitwise, in every lane).
 // ---------------------------------------------------------------------------------------------
+constexpr int kP2MSplit = 4;
+
 template <int PB>
-__global__ __launch_bounds__(64) void k_p2m(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
-                                            const int32_t *__restrict__ leaves, int nleaf, int nbox, int nv,
-                                            const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
-                                            const int32_t *__restrict__ by, const int32_t *__restrict__ first,
-                                            const int32_t *__restrict__ count, const double *__restrict__ xs,
-                                            const double *__restrict__ ys, const double *__restrict__ qs,
-                                            cplx *__restrict__ W) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nleaf) return;
-    const int v = blockIdx.y;  // charge vector
+__global__ __launch_bounds__(256) void k_p2m(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
+                                             const int32_t *__restrict__ leaves, int nleaf, int nbox, int nv,
+                                             const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
+                                             const int32_t *__restrict__ by, const int32_t *__restrict__ first,
+                                             const int32_t *__restrict__ count, const double *__restrict__ xs,
+                                             const double *__restrict__ ys, const double *__restrict__ qs,
+                                             cplx *__restrict__ W) {
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gt / kP2MSplit, part = gt % kP2MSplit;
+    const bool ok = t < nleaf;  // no early exit: every lane of a leaf group takes part in the butterfly
+    const int v = blockIdx.y;   // charge vector
     W += (int64_t)v * (PB + 1) * nbox;
-    const int b = leaves[t];
-    const int l = level[b];
-    const Geo g = geo_of(ii, inst[b]);
-    const cplx c = centre_of(g, l, bx[b], by[b]);
-    const double irho = 2.0 / side_of(g, l);
+    const int b = ok ? leaves[t] : 0;
     cplx w[PB + 1];
 #pragma unroll
     for (int n = 0; n <= PB; ++n) w[n] = mk(0.0, 0.0);
-    const int f = first[b], e = f + count[b];
-    for (int j = f; j < e; ++j) {
-        const cplx mz = mk((c.re - xs[j]) * irho, (c.im - ys[j]) * irho);  // -(z_j - c) / rho
-        cplx term = mk(qs[(int64_t)j * nv + v], 0.0);
+    if (ok) {
+        const int l = level[b];
+        const Geo g = geo_of(ii, inst[b]);
+        const cplx c = centre_of(g, l, bx[b], by[b]);
+        const double irho = 2.0 / side_of(g, l);
+        const int f = first[b], e = f + count[b];
+        for (int j = f + part; j < e; j += kP2MSplit) {
+            const cplx mz = mk((c.re - xs[j]) * irho, (c.im - ys[j]) * irho);  // -(z_j - c) / rho
+            cplx term = mk(qs[(int64_t)j * nv + v], 0.0);
 #pragma unroll
-        for (int n = 0; n <= PB; ++n) {
-            w[n] += term;
-            term = term * mz * (1.0 / (n + 1));
+            for (int n = 0; n <= PB; ++n) {
+                w[n] += term;
+                term = term * mz * (1.0 / (n + 1));
+            }
         }
     }
 #pragma unroll
-    for (int n = 0; n <= PB; ++n) W[(int64_t)n * nbox + b] = w[n];
+    for (int n = 0; n <= PB; ++n)
+        for (int off = 1; off < kP2MSplit; off <<= 1) {
+            w[n].re += __shfl_xor(w[n].re, off);
+            w[n].im += __shfl_xor(w[n].im, off);
+        }
+    if (ok) {
+#pragma unroll
+        for (int n = 0; n <= PB; ++n)
+            if (n % kP2MSplit == part) W[(int64_t)n * nbox + b] = w[n];
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
-// M2M: one level.  A block takes kM2MParents consecutive boxes of the level; their children are a
-// contiguous range of the next level, whose multipoles are staged in LDS once.  Thread
-// (parent, n) then forms w^P_n = sum_children sum_{m<=n} (-eps)^{n-m}/(n-m)! 2^-m w^c_m.
+// M2M.  A block takes kM2MParents consecutive boxes of a level; their children are a contiguous
+// range of the next level, whose multipoles are staged in LDS once.  Thread (parent, n) then forms
+// w^P_n = sum_children sum_{m<=n} (-eps)^{n-m}/(n-m)! 2^-m w^c_m.
+// k_m2m runs one level; k_m2m_sub runs every level below a cut level, one block per subtree
+// rooted at the cut (a subtree's boxes of one level are a contiguous range), deepest level first.
 // ---------------------------------------------------------------------------------------------
 constexpr int kM2MParents = 16;
+
+template <int PB>
+struct M2MShared {
+    cplx sw[(PB + 1) * 4 * kM2MParents];  // children's multipoles, scaled by 2^-m
+    cplx sE[4 * (PB + 1)];
+    int2 par[kM2MParents];                // (first staged child, number of children) per parent
+    int quad[4 * kM2MParents];            // position of each staged child in its parent
+    int range[2];
+};
+
+// Parents [p0, p1) of one level (p1 - p0 <= kM2MParents); called by every thread of the block
+// with block-uniform bounds.  Two dependent memory round trips (the parents' child ranges, then
+// the children's multipoles and positions); ends with a barrier, so the multipoles written are
+// visible to the whole block.
+template <int PB>
+__device__ void m2m_parents(M2MShared<PB> &sh, int p0, int p1, int nbox, const int32_t *__restrict__ leaf,
+                            const int32_t *__restrict__ child_first, const int32_t *__restrict__ nchild,
+                            const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
+                            cplx *__restrict__ W) {
+    static_assert(kM2MParents <= 64, "the child range is reduced over one wave");
+    if (threadIdx.x < 64) {  // child range of the non-leaf parents, reduced over the first wave
+        const int p = p0 + (int)threadIdx.x;
+        int cf = 0, ncp = 0;
+        if (p < p1 && !leaf[p]) {
+            cf = child_first[p];
+            ncp = nchild[p];
+        }
+        int clo = ncp > 0 ? cf : 0x7fffffff, chi = ncp > 0 ? cf + ncp : -1;
+        for (int off = 32; off > 0; off >>= 1) {
+            clo = min(clo, __shfl_xor(clo, off));
+            chi = max(chi, __shfl_xor(chi, off));
+        }
+        if (threadIdx.x < kM2MParents) sh.par[threadIdx.x] = make_int2(cf - clo, ncp);
+        if (threadIdx.x == 0) {
+            sh.range[0] = clo;
+            sh.range[1] = chi;
+        }
+    }
+    __syncthreads();
+    const int clo = sh.range[0], nc = sh.range[1] - sh.range[0];
+    for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += blockDim.x) {
+        const int m = idx / nc, k = idx - m * nc;
+        sh.sw[m * 4 * kM2MParents + k] = W[(int64_t)m * nbox + clo + k] * ldexp(1.0, -m);
+    }
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) sh.quad[k] = (bx[clo + k] & 1) | ((by[clo + k] & 1) << 1);
+    __syncthreads();
+    const int pi = threadIdx.x % kM2MParents;
+    const int2 pr = sh.par[pi];
+    if (pr.y > 0) {
+        for (int n = threadIdx.x / kM2MParents; n <= PB; n += blockDim.x / kM2MParents) {
+            cplx out = mk(0.0, 0.0);
+            for (int c = pr.x; c < pr.x + pr.y; ++c) {
+                const cplx *Eq = sh.sE + sh.quad[c] * (PB + 1) + n;
+#pragma unroll 4
+                for (int m = 0; m <= n; ++m) cfma(out, Eq[-m], sh.sw[m * 4 * kM2MParents + c]);
+            }
+            W[(int64_t)n * nbox + p0 + pi] = out;
+        }
+    }
+    __syncthreads();
+}
 
 template <int PB>
 __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int32_t *__restrict__ leaf,
@@ -157,43 +245,29 @@ __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int
                                              const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
                                              const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                              cplx *__restrict__ W) {
-    __shared__ cplx sw[(PB + 1) * 4 * kM2MParents];
-    __shared__ cplx sE[4 * (PB + 1)];
-    __shared__ int s_range[2];
+    __shared__ M2MShared<PB> sh;
     W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
     const int p0 = lo + blockIdx.x * kM2MParents;
-    const int p1 = min(p0 + kM2MParents, lo + nb);
-    if (threadIdx.x == 0) {
-        int clo = 0x7fffffff, chi = -1;
-        for (int p = p0; p < p1; ++p)
-            if (!leaf[p]) {
-                clo = min(clo, child_first[p]);
-                chi = max(chi, child_first[p] + nchild[p]);
-            }
-        s_range[0] = clo;
-        s_range[1] = chi;
-    }
-    for (int k = threadIdx.x; k < 4 * (PB + 1); k += 256) sE[k] = E[k];
-    __syncthreads();
-    const int clo = s_range[0], nc = s_range[1] - s_range[0];
-    if (nc <= 0) return;
-    for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += 256) {
-        const int m = idx / nc, k = idx - m * nc;
-        sw[m * 4 * kM2MParents + k] = W[(int64_t)m * nbox + clo + k] * ldexp(1.0, -m);
-    }
-    __syncthreads();
-    const int pi = threadIdx.x % kM2MParents;
-    const int p = p0 + pi;
-    if (p >= p1 || leaf[p]) return;
-    const int c0 = child_first[p] - clo, c1 = c0 + nchild[p];
-    for (int n = threadIdx.x / kM2MParents; n <= PB; n += 256 / kM2MParents) {
-        cplx out = mk(0.0, 0.0);
-        for (int c = c0; c < c1; ++c) {
-            const int gc = clo + c;
-            const cplx *Eq = sE + ((bx[gc] & 1) | ((by[gc] & 1) << 1)) * (PB + 1) + n;
-            for (int m = 0; m <= n; ++m) cfma(out, Eq[-m], sw[m * 4 * kM2MParents + c]);
-        }
-        W[(int64_t)n * nbox + p] = out;
+    m2m_parents<PB>(sh, p0, min(p0 + kM2MParents, lo + nb), nbox, leaf, child_first, nchild, bx, by, W);
+}
+
+// rng: [n_roots][nlev] box ranges (begin, end) of each subtree at the levels cut + k.
+template <int PB>
+__global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restrict__ rng, int nbox,
+                                                 const int32_t *__restrict__ leaf,
+                                                 const int32_t *__restrict__ child_first,
+                                                 const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
+                                                 const int32_t *__restrict__ by, const cplx *__restrict__ E,
+                                                 cplx *__restrict__ W) {
+    __shared__ M2MShared<PB> sh;
+    W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
+    const int2 *R = rng + (int64_t)blockIdx.x * nlev;
+    for (int k = nlev - 2; k >= 0; --k) {
+        const int2 r = R[k];
+        for (int p0 = r.x; p0 < r.y; p0 += kM2MParents)
+            m2m_parents<PB>(sh, p0, min(p0 + kM2MParents, r.y), nbox, leaf, child_first, nchild, bx, by, W);
     }
 }
 
@@ -556,40 +630,87 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
 }
 
 // ---------------------------------------------------------------------------------------------
-// L2L: one level of children.  A block takes kL2LChildren consecutive children and stages each
-// child's parent local in LDS (siblings share cache lines).  Thread (child, m) adds
-// 2^-m sum_{n>=m} eps^{n-m}/(n-m)! lambda^P_n to lambda^c_m.
+// L2L.  A block takes kL2LChildren consecutive children and stages each child's parent local in
+// LDS (siblings share cache lines).  Thread (child, m) adds 2^-m sum_{n>=m} eps^{n-m}/(n-m)!
+// lambda^P_n to lambda^c_m.  k_l2l runs one level of children; k_l2l_sub every level below a cut
+// level, one block per subtree rooted at the cut, top level first.
 // ---------------------------------------------------------------------------------------------
 constexpr int kL2LChildren = 64;
+
+template <int PB>
+struct L2LShared {
+    cplx sl[(PB + 1) * kL2LChildren];
+    cplx sE[4 * (PB + 1)];
+};
+
+// Children [c0, c0 + nc) of one level, nc <= kL2LChildren; called by every thread of the block.
+// The children's own locals are read before the parents' are staged, so that both loads overlap.
+// Ends with a barrier, so the locals written are visible to the whole block.
+template <int PB>
+__device__ void l2l_children(L2LShared<PB> &sh, int c0, int nc, int nbox, int nloc,
+                             const int32_t *__restrict__ parent, const int32_t *__restrict__ bx,
+                             const int32_t *__restrict__ by, cplx *__restrict__ Lam) {
+    constexpr int MS = 256 / kL2LChildren;         // threads per child
+    constexpr int MP = (PB + MS) / MS;             // coefficients per thread
+    const int ci = threadIdx.x % kL2LChildren;
+    const int mt = threadIdx.x / kL2LChildren;
+    const int c = c0 + ci;
+    const int q = ci < nc ? ((bx[c] & 1) | ((by[c] & 1) << 1)) : 0;
+    for (int loc = 0; loc < nloc; ++loc) {
+        cplx *L = Lam + (int64_t)loc * (PB + 1) * nbox;
+        cplx own[MP];
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            const int m = mt + k * MS;
+            own[k] = (ci < nc && m <= PB) ? L[(int64_t)m * nbox + c] : mk(0.0, 0.0);
+        }
+        for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += blockDim.x) {
+            const int n = idx / nc, k = idx - n * nc;
+            sh.sl[n * kL2LChildren + k] = L[(int64_t)n * nbox + parent[c0 + k]];
+        }
+        __syncthreads();
+        if (ci < nc) {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) {
+                const int m = mt + k * MS;
+                if (m <= PB) {
+                    const cplx *Eq = sh.sE + q * (PB + 1) - m;
+                    cplx s = mk(0.0, 0.0);
+#pragma unroll 4
+                    for (int n = m; n <= PB; ++n) cfma(s, Eq[n], sh.sl[n * kL2LChildren + ci]);
+                    L[(int64_t)m * nbox + c] = own[k] + s * ldexp(1.0, -m);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
 
 template <int PB>
 __global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc, const int32_t *__restrict__ parent,
                                              const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
                                              const cplx *__restrict__ E, cplx *__restrict__ Lam) {
-    __shared__ cplx sl[(PB + 1) * kL2LChildren];
-    __shared__ cplx sE[4 * (PB + 1)];
+    __shared__ L2LShared<PB> sh;
     Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;  // charge vector
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
     const int c0 = lo + blockIdx.x * kL2LChildren;
-    const int nc = min(kL2LChildren, lo + nb - c0);
-    for (int k = threadIdx.x; k < 4 * (PB + 1); k += 256) sE[k] = E[k];
-    const int ci = threadIdx.x % kL2LChildren;
-    const int c = c0 + ci;
-    const int q = ci < nc ? ((bx[c] & 1) | ((by[c] & 1) << 1)) : 0;
-    for (int loc = 0; loc < nloc; ++loc) {
-        cplx *L = Lam + (int64_t)loc * (PB + 1) * nbox;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += 256) {
-            const int n = idx / nc, k = idx - n * nc;
-            sl[n * kL2LChildren + k] = L[(int64_t)n * nbox + parent[c0 + k]];
-        }
-        __syncthreads();
-        if (ci >= nc) continue;
-        for (int m = threadIdx.x / kL2LChildren; m <= PB; m += 256 / kL2LChildren) {
-            const cplx *Eq = sE + q * (PB + 1) - m;
-            cplx s = mk(0.0, 0.0);
-            for (int n = m; n <= PB; ++n) cfma(s, Eq[n], sl[n * kL2LChildren + ci]);
-            L[(int64_t)m * nbox + c] += s * ldexp(1.0, -m);
-        }
+    l2l_children<PB>(sh, c0, min(kL2LChildren, lo + nb - c0), nbox, nloc, parent, bx, by, Lam);
+}
+
+template <int PB>
+__global__ __launch_bounds__(256) void k_l2l_sub(int nlev, const int2 *__restrict__ rng, int nbox, int nloc,
+                                                 const int32_t *__restrict__ parent, const int32_t *__restrict__ bx,
+                                                 const int32_t *__restrict__ by, const cplx *__restrict__ E,
+                                                 cplx *__restrict__ Lam) {
+    __shared__ L2LShared<PB> sh;
+    Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;  // charge vector
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
+    __syncthreads();
+    const int2 *R = rng + (int64_t)blockIdx.x * nlev;
+    for (int k = 1; k < nlev; ++k) {
+        const int2 r = R[k];
+        for (int c0 = r.x; c0 < r.y; c0 += kL2LChildren)
+            l2l_children<PB>(sh, c0, min(kL2LChildren, r.y - c0), nbox, nloc, parent, bx, by, Lam);
     }
 }
 
@@ -687,10 +808,14 @@ struct LeafArgs {
     double *qc;              // [n] sum of the charges coincident with each sorted target, or null
     double *phi;             // [nv][n][2] potential, caller order (potential modes)
     cplx *gx, *gy;           // [n] gradient, caller order (gradient modes)
+    const int2 *u2;          // per U entry: (first point, point count | image << 31) of its source box
 };
 
 // Near field, log terms of the U list: one thread per target (sorted order, grid-stride over the
-// targets).  NV charge vectors share each pair's kernel value.
+// targets).  NV charge vectors share each pair's kernel value.  The thread loads each source point
+// (and the next U entry's range) one step ahead of its use, so that the memory latency overlaps
+// the arithmetic; free-space and image terms go into one signed sum,
+// (1/4 pi) sum_j q_j (log r_img^2 - log r^2).
 template <int MODE, int NV>
 __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     __shared__ double2 s_logtab[kLogTable];
@@ -698,79 +823,76 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
         for (int k = threadIdx.x; k < kLogTable; k += blockDim.x) s_logtab[k] = a.logtab[k];
         __syncthreads();
     }
+    const double2 *__restrict__ xy = a.xy;
+    const double2 *__restrict__ tab = s_logtab;
+    const double *__restrict__ qs = a.qs;
+    const int2 *__restrict__ u2 = a.u2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
         const int b = a.leaf_of[i];
         const double2 pi = a.xy[i];
         const double x = pi.x, y = pi.y;
-        double lfree[NV], limg[NV];
+        double acc[NV], gxa[NV], gya[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) lfree[v] = limg[v] = 0.0;
-        double fx[NV], fy[NV], mx[NV], my[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) fx[v] = fy[v] = mx[v] = my[v] = 0.0;
+        for (int v = 0; v < NV; ++v) acc[v] = gxa[v] = gya[v] = 0.0;
         double qc = 0.0;  // coincident charge of vector 0
-        const double2 *__restrict__ xy = a.xy;
-        const double2 *__restrict__ tab = s_logtab;
-        const double *__restrict__ qs = a.qs;
-        for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
-            const int code = a.uent[e];
-            const int c = code >> 1;
-            const int j0 = a.first[c], j1 = j0 + a.count[c];
-            if (!(code & 1)) {
-                for (int j = j0; j < j1; ++j) {
-                    const double2 pj = xy[j];
-                    const double dx = x - pj.x, dy = y - pj.y;
-                    const double r2 = fma(dx, dx, dy * dy);
-                    const bool nz = r2 > 0.0;  // skip the self pair (eq. (1.2))
-                    if (has_phi(MODE)) {
-                        const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
+        // a leaf's U list holds at least the leaf itself, and every listed box holds a point
+        int e = a.uoff[b];
+        const int e1 = a.uoff[b + 1];
+        int2 fc = u2[e];
+        int2 fn = e + 1 < e1 ? u2[e + 1] : fc;  // range of entry e + 1
+        double2 pj = xy[fc.x];
+        double qj[NV];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
-                    }
-                    if (has_grad(MODE)) {
-                        const double ir = nz ? rcp_pos(nz ? r2 : 1.0) : 0.0;
-                        const double irx = ir * dx, iry = ir * dy;
+        for (int v = 0; v < NV; ++v) qj[v] = qs[(int64_t)fc.x * NV + v];
+        while (true) {
+            const int j0 = fc.x, jend = fc.x + (fc.y & 0x7fffffff);
+            const double sg = fc.y < 0 ? 1.0 : -1.0;  // image: + log|r - r_img|, free: - log|r - r'|
+            const bool last = e + 1 >= e1;
+            const int jnext = last ? jend - 1 : fn.x;  // the point loaded after this entry's last
+            for (int j = j0; j < jend; ++j) {
+                const int jp = j + 1 < jend ? j + 1 : jnext;
+                const double2 pn = xy[jp];
+                double qn[NV];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            const double qj = qs[(int64_t)j * NV + v];
-                            fx[v] = fma(qj, irx, fx[v]);
-                            fy[v] = fma(qj, iry, fy[v]);
-                        }
-                        qc += nz ? 0.0 : qs[(int64_t)j * NV];
-                    }
+                for (int v = 0; v < NV; ++v) qn[v] = qs[(int64_t)jp * NV + v];
+                const double dx = x - pj.x, dy = fma(sg, pj.y, y);  // y - y' or y + y'
+                const double r2 = fma(dx, dx, dy * dy);
+                // r2 = 0 only for a coincident free pair (image distances are positive), which is
+                // skipped (eq. (1.2))
+                const bool nz = r2 > 0.0;
+                if (has_phi(MODE)) {
+                    const double sl = sg * log_tab(nz ? r2 : 1.0, tab);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], nz ? sl : 0.0, acc[v]);
                 }
-            } else {
-                for (int j = j0; j < j1; ++j) {
-                    const double2 pj = xy[j];
-                    const double dx = x - pj.x, dy = y + pj.y;
-                    const double r2 = fma(dx, dx, dy * dy);
-                    if (has_phi(MODE)) {
-                        const double lg = log_tab(r2, tab);
+                if (has_grad(MODE)) {
+                    const double sr = sg * rcp_pos(nz ? r2 : 1.0);
+                    const double irx = nz ? sr * dx : 0.0, iry = nz ? sr * dy : 0.0;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
+                    for (int v = 0; v < NV; ++v) {
+                        gxa[v] = fma(qj[v], irx, gxa[v]);
+                        gya[v] = fma(qj[v], iry, gya[v]);
                     }
-                    if (has_grad(MODE)) {
-                        const double ir = rcp_pos(r2);
-                        const double irx = ir * dx, iry = ir * dy;
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            const double qj = qs[(int64_t)j * NV + v];
-                            mx[v] = fma(qj, irx, mx[v]);
-                            my[v] = fma(qj, iry, my[v]);
-                        }
-                    }
+                    qc += nz ? 0.0 : qj[0];
                 }
+                pj = pn;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qj[v] = qn[v];
             }
+            if (last) break;
+            ++e;
+            fc = fn;
+            if (e + 1 < e1) fn = u2[e + 1];
         }
         if (has_phi(MODE)) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
+            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * acc[v], 0.0);
         }
         if (has_grad(MODE)) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * (mx[v] - fx[v]), 0.0);
-                a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * (my[v] - fy[v]), 0.0);
+                a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * gxa[v], 0.0);
+                a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * gya[v], 0.0);
             }
             if (a.qc) a.qc[i] = qc;
         }
@@ -1373,6 +1495,47 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             }
     }
     FMMHP_CHECK(to_dev(A, &S.leaves, lv, "leaves", s));
+    // subtree passes: below the first level (>= 3) with at least four boxes per CU, one block per
+    // subtree runs all of that subtree's M2M (and later L2L) levels; the levels above run one
+    // launch each.  A subtree's boxes at each level are a contiguous range (boxes are ordered by
+    // level, instance, Morton prefix).
+    S.sub_level = 0;
+    {
+        int cus = 0, dev = 0;
+        FMMHP_HIP(hipGetDevice(&dev));
+        FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        for (int l = 3; l < T.depth; ++l)
+            if (T.lev_start[l + 1] - T.lev_start[l] >= 4 * std::max(1, cus)) {
+                S.sub_level = l;
+                break;
+            }
+    }
+    if (S.sub_level > 0) {
+        std::vector<int32_t> cfirst, nch;
+        FMMHP_CHECK(to_host(cfirst, T.child_first, nbox, s));
+        FMMHP_CHECK(to_host(nch, T.nchild, nbox, s));
+        FMMHP_HIP(hipStreamSynchronize(s));
+        const int lc = S.sub_level, r0 = T.lev_start[lc];
+        S.n_sub = T.lev_start[lc + 1] - r0;
+        S.sub_nlev = T.depth - lc + 1;
+        std::vector<int2> rng((size_t)S.n_sub * S.sub_nlev, make_int2(0, 0));
+        for (int r = 0; r < S.n_sub; ++r) {
+            int a = r0 + r, b = a + 1;
+            for (int k = 0; k < S.sub_nlev && a < b; ++k) {
+                rng[(size_t)r * S.sub_nlev + k] = make_int2(a, b);
+                int na = -1, nb = -1;
+                for (int x = a; x < b; ++x)
+                    if (!leaf[x]) {
+                        if (na < 0) na = cfirst[x];
+                        nb = cfirst[x] + nch[x];
+                    }
+                if (na < 0) break;
+                a = na;
+                b = nb;
+            }
+        }
+        FMMHP_CHECK(to_dev(A, &S.sub_rng, rng, "subtree ranges", s));
+    }
     {
         std::vector<int32_t> woff, first, wp, rl;
         FMMHP_CHECK(to_host(woff, T.off[2], (size_t)nbox + 1, s));
@@ -1568,6 +1731,13 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         FMMHP_CHECK(to_dev(A, &S.logtab, lt, "log table", s));
     }
     FMMHP_CHECK(to_dev(A, &S.E_l2l, El, "E_l2l", s));
+    // point range of every U entry's source box, for the near-field walk
+    if (T.len[0] > 0) {
+        FMMHP_CHECK(A.alloc_n(&S.u2, (size_t)T.len[0], "U entry ranges"));
+        hipLaunchKernelGGL(k_u2, dim3(nblk(T.len[0], 256)), dim3(256), 0, s, (int64_t)T.len[0], T.ent[0], T.first,
+                           T.count, S.u2);
+        FMMHP_HIP(hipGetLastError());
+    }
 
     // surface-term chunks: at most kSurfChunk points, within one instance
     {
@@ -1593,7 +1763,8 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         int dev = 0, cus = 0;
         FMMHP_HIP(hipGetDevice(&dev));
         FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        S.near_blocks = 4 * std::max(1, cus);
+        S.cus = std::max(1, cus);
+        S.near_blocks = 2 * S.cus;
     }
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
@@ -1635,8 +1806,6 @@ struct Marks {
 
 // Outputs of one evaluation pass (caller order): the potential and/or its gradient, and the
 // coincident-charge sums (sorted order) used by the impedance gradient.
-// Outputs of one evaluation pass (caller order): the potential and/or its gradient, and the
-// coincident-charge sums (sorted order) used by the impedance gradient.
 struct PassOut {
     double *phi = nullptr;      // [nv][n][2]
     cplx *gx = nullptr, *gy = nullptr;
@@ -1658,11 +1827,11 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
                 S.qs,        S.xy,      T.perm,   T.leaf_of, T.level, T.bx,     T.by,     T.first,  T.count,
                 T.off[0],    T.ent[0],  T.off[2], T.ent[2], S.W,      S.Lam,    S.invfact, S.fact,  S.rank1,
                 S.wpts,      S.n_wpts,  S.rpts,   S.logtab, S.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
-                out.phi,     out.gx,    out.gy};
+                out.phi,     out.gx,    out.gy,   S.u2};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
-    // a bounded grid (four workgroups per CU) leaves room on every CU for the far-field kernels
+    // a bounded grid (two workgroups per CU) leaves room on every CU for the far-field kernels
     // running concurrently on the main stream
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), dim3((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks)),
                        dim3(256), 0, S.side, la);
@@ -1670,10 +1839,19 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
                            S.side, la);
     FMMHP_HIP(hipGetLastError());
+    // the surface sums also need only the sorted charges
+    if (S.nloc == 1 && S.rank1_side) {
+        hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, S.side, T.xs, T.ys, S.qs, NV, S.rch,
+                           S.n_rch, S.inst_info, S.red);
+        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, S.side, S.red, S.n_rch, S.inst_ch,
+                           T.n_inst, S.rank1);
+        FMMHP_HIP(hipGetLastError());
+    }
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
     FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk(T.nleaf, 64), NV), dim3(64), 0, s, S.inst_info, T.inst,
-                       S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count, T.xs, T.ys, S.qs, S.W);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk((int64_t)T.nleaf * kP2MSplit, 256), NV), dim3(256), 0, s,
+                       S.inst_info, T.inst, S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count, T.xs,
+                       T.ys, S.qs, S.W);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
     // M2L (+ image M2L, P2L) over the levels [l0, l1) of the tree on stream st
@@ -1718,13 +1896,20 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         FMMHP_HIP(hipEventRecord(S.ev_deep_done, S.side2));
         return FMMHP_OK;
     };
-    if (ld > 0 && ld > T.depth - 1) FMMHP_CHECK(fork_deep());
-    for (int l = T.depth - 1; l >= 2; --l) {
+    // fork point: once the deep multipoles exist, or (S.fork_late) after the whole upward pass
+    const int lc = S.sub_level;
+    int lf = S.fork_late ? 2 : ld;
+    if (lc > 0 && lf >= lc) lf = T.depth;  // inside the subtree pass: fork right after it
+    if (lc > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_sub, NV), dim3(256), 0, s, S.sub_nlev, S.sub_rng,
+                           nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+    if (ld > 0 && lf > T.depth - 1) FMMHP_CHECK(fork_deep());
+    for (int l = (lc > 0 ? lc : T.depth) - 1; l >= 2; --l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256), 0, s, lo, nb,
                                nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
-        if (ld > 0 && l == ld) FMMHP_CHECK(fork_deep());
+        if (ld > 0 && l == lf) FMMHP_CHECK(fork_deep());
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
@@ -1738,21 +1923,25 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_CHECK(far_levels(2, ld > 0 ? ld : T.depth + 1, s));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_L2L, s));
-    for (int l = 3; l <= T.depth; ++l) {
+    const int l2l_end = lc > 0 ? lc : T.depth;
+    for (int l = 3; l <= l2l_end; ++l) {
         if (ld > 0 && l == ld) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256), 0, s, lo, nb,
                                nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     }
-    if (ld > 0 && ld > T.depth) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
+    if (ld > 0 && ld > l2l_end) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
+    if (lc > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_sub, NV), dim3(256), 0, s, S.sub_nlev, S.sub_rng,
+                           nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     if (mk_.on && ld == 0) {
         FMMHP_HIP(hipEventRecord(mk_.deep0, s));
         FMMHP_HIP(hipEventRecord(mk_.deep1, s));
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
-    if (S.nloc == 1) {
+    if (S.nloc == 1 && !S.rank1_side) {
         hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, s, T.xs, T.ys, S.qs, NV, S.rch, S.n_rch,
                            S.inst_info, S.red);
         hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, s, S.red, S.n_rch, S.inst_ch, T.n_inst,

@@ -143,6 +143,7 @@ struct Sched {
     int32_t *wpts = nullptr;        // sorted points whose leaf has a W list
     int64_t n_rpts = 0;
     int32_t *rpts = nullptr;        // sorted points whose leaf has image U entries
+    int2 *u2 = nullptr;             // [U entries] (first point, count | image << 31) of the source box
     double2 *xy = nullptr;          // [n] sorted (x, y) pairs
     double2 *logtab = nullptr;      // near-field log table
     double2 *near = nullptr;        // [nv_cap][n] near-field sums
@@ -151,7 +152,13 @@ struct Sched {
     hipEvent_t ev_deep_ready = nullptr, ev_deep_done = nullptr;
     int deep_level = 0;             // first level of the deep M2L part (0: no split)
     std::vector<int> tile_lev, ibox_lev, xbox_lev;  // per-level ranges of tiles, image-V and X boxes
-    int64_t near_blocks = 1024;     // near-field grid: four workgroups per CU
+    int cus = 1;                    // compute units of the device
+    int64_t near_blocks = 512;      // near-field grid: two workgroups per CU
+    bool fork_late = false;         // start the deep M2L after the whole upward pass
+    bool rank1_side = true;         // surface sums on the near-field stream
+    int sub_level = 0;              // cut level of the subtree M2M / L2L passes (0: one launch per level)
+    int n_sub = 0, sub_nlev = 0;    // subtrees (the boxes of the cut level), levels cut..depth
+    int2 *sub_rng = nullptr;        // [n_sub][sub_nlev] box range of each subtree per level
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
