@@ -173,17 +173,19 @@ def main():
 
     tuned = None
     p_use, leaf_use = a.p, a.leaf
+    shape = {}  # near-field launch shape (library default unless tuned)
     if a.p == 0:
         t0 = time.perf_counter()
         tuned = F.tune(x, y, q, w.impedance, tol=a.tol)
         tuned["tune_s"] = time.perf_counter() - t0
         p_use, leaf_use = tuned["p"], tuned["leaf_size"]
+        shape = {"near_walk": tuned["near_walk"], "near_groups": tuned["near_groups"]}
     elif a.leaf == 0:
         leaf_use = 40
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use)
+    plan = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, **shape)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
@@ -276,7 +278,8 @@ def main():
         "config": {"workload": "uniform_1m: N=1,048,576 uniform in [0,1]x[1e-3,1.001], charges U[-1,1], "
                                "impedance 1.0, sources=targets, 1 charge vector",
                    "n": w.n, "p": info["p"], "leaf_size": leaf_use, "impedance": 1.0,
-                   "tolerance": a.tol if tuned else None},
+                   "tolerance": a.tol if tuned else None,
+                   "near_walk": info["near_walk"], "near_groups": info["near_groups"]},
         "roofline": roof,
     }
     if not a.no_cpu_baseline:

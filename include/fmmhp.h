@@ -66,6 +66,12 @@ typedef struct {
     int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
     int max_level;  /* deepest tree level, 1..30 (1..27 for a forest); 0 selects the maximum */
     unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH and FMMHP_FLAG_M2L_FP32 */
+    /* Launch shape of the near field (the U-list sums), which runs beside the far-field kernels on
+     * a bounded grid.  Neither changes what is computed beyond rounding; fmmhp_tune picks both by
+     * timing.  0 selects the default for the plan's p. */
+    int near_walk;   /* 0: default; 1: source points loaded one step ahead of their use (hides
+                        memory latency, more instructions per pair); 2: plain walk */
+    int near_groups; /* 0: default; 1..16: near-field workgroups per compute unit */
 } fmmhp_opts;
 
 /* fmmhp_eval records its launches into a HIP graph on the first call with a given (n_vec, q, phi,
@@ -96,6 +102,8 @@ typedef struct {
                                image sources (the U list expanded to points) */
     int64_t m2l_pairs[2];   /* M2L (target box, source box) pairs: upper, image (the V list) */
     int32_t n_inst;         /* instances (1 for fmmhp_plan_create) */
+    int32_t near_walk;      /* near-field launch shape in use (see fmmhp_opts) */
+    int32_t near_groups;
 } fmmhp_plan_stats;
 
 /* Phases of fmmhp_eval whose device time fmmhp_plan_phase_times reports. */
@@ -277,7 +285,8 @@ fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *
  *   n_vec        vectors per timed eval (>= 1)
  *   leaf_sizes   [host] candidate leaf sizes (n_leaf entries), or NULL for {24, 32, 40, 48, 64, 96}
  *   sample       targets in the accuracy sample, 1..n (0 selects min(n, 256))
- *   best         [host] receives the chosen options (p, leaf_size; max_level 0, flags 0)
+ *   best         [host] receives the chosen options (p, leaf_size, and the launch shape
+ *                near_walk, near_groups timed on the chosen plan; max_level 0, flags 0)
  *   err, eval_ms [host, may be NULL] the chosen pair's measured error and median eval time
  * Returns FMMHP_EUNSUPPORTED if no candidate reaches tol at p = 40.  Synchronises the stream;
  * allocates and frees its own temporaries. */

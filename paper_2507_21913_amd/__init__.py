@@ -38,7 +38,8 @@ class FMMHPError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("leaf_size", ctypes.c_int),
-                ("max_level", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("max_level", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("near_walk", ctypes.c_int), ("near_groups", ctypes.c_int)]
 
 
 class PlanStats(ctypes.Structure):
@@ -50,7 +51,8 @@ class PlanStats(ctypes.Structure):
                 ("lambda_re", ctypes.c_double), ("lambda_im", ctypes.c_double),
                 ("real_impedance", ctypes.c_int), ("device_bytes", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64 * 2), ("m2l_pairs", ctypes.c_int64 * 2),
-                ("n_inst", ctypes.c_int32)]
+                ("n_inst", ctypes.c_int32), ("near_walk", ctypes.c_int32),
+                ("near_groups", ctypes.c_int32)]
 
 
 PHASES = ("p2m", "m2m", "m2l", "p2l", "l2l", "surface", "leaf", "near")
@@ -231,11 +233,13 @@ def fmmhp_tune(n, x_ptr, y_ptr, q_ptr, lambda_re, lambda_im, tol, n_vec, leaf_si
     _check("fmmhp_tune", lib().fmmhp_tune(n, x_ptr, y_ptr, q_ptr, lambda_re, lambda_im, tol, n_vec,
                                           la, nl, sample, ctypes.byref(best), ctypes.byref(err),
                                           ctypes.byref(ms), stream))
-    return {"p": best.p, "leaf_size": best.leaf_size, "rel_l2": err.value, "eval_ms": ms.value}
+    return {"p": best.p, "leaf_size": best.leaf_size, "near_walk": best.near_walk,
+            "near_groups": best.near_groups, "rel_l2": err.value, "eval_ms": ms.value}
 
 
 def tune(x, y, q, impedance, tol=1e-10, n_vec=1, leaf_sizes=None, sample=0) -> dict:
-    """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error."""
+    """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error, and the
+    near-field launch shape (near_walk, near_groups) by timing the chosen plan."""
     x = _dev_f64(x, "x")
     y = _dev_f64(y, "y")
     q = _dev_f64(q, "q")
@@ -262,10 +266,11 @@ class HalfPlaneFMM:
     graph       record each evaluation into a HIP graph and replay it (needs a non-default
                 stream: run under ``torch.cuda.stream(...)``)
     m2l_fp32    run the upper-source M2L on the FP32 matrix cores (relative error ~1e-7)
+    near_walk, near_groups   near-field launch shape (0: default; see fmmhp_opts)
     """
 
     def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False,
-                 graph=False, m2l_fp32=False):
+                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         self.n = int(x.shape[0])
@@ -273,7 +278,8 @@ class HalfPlaneFMM:
         self._x, self._y = x, y
         lr, li = _split_impedance(impedance)
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0))
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0),
+                    int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             if pass_images:
                 ix, iy = x.clone(), -y
@@ -287,7 +293,7 @@ class HalfPlaneFMM:
 
     @classmethod
     def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False,
-                m2l_fp32=False):
+                m2l_fp32=False, near_walk=0, near_groups=0):
         """A forest plan over n_inst independent instances: points offsets[k]..offsets[k+1]-1 of
         (x, y) form instance k with impedance impedances[k].  Evaluation takes charges for all
         points (instance after instance) and runs every instance in the same launches."""
@@ -306,7 +312,8 @@ class HalfPlaneFMM:
         if len(imps) != self.n_inst:
             raise ValueError("one impedance per instance")
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0))
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0),
+                    int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,
                                                  opts, _stream())

@@ -80,13 +80,15 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
                                 const double *img_x, const double *img_y, const cplx *Zs, const fmmhp_opts *opts,
                                 hipStream_t stream, fmmhp_plan_t *plan_out) {
     const int lb = n_inst == 1 ? kLBits : kLBitsForest;
-    fmmhp_opts o{20, 40, lb, 0};
+    fmmhp_opts o{20, 40, lb, 0, 0, 0};
     if (opts) o = *opts;
     if (o.max_level == 0) o.max_level = lb;
     if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
-        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32)) != 0) {
-        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0, 1)", o.p,
-                  FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags);
+        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32)) != 0 || o.near_walk < 0 || o.near_walk > 2 ||
+        o.near_groups < 0 || o.near_groups > 16) {
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0, 1), "
+                  "near_walk=%d (0..2), near_groups=%d (0..16)",
+                  o.p, FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags, o.near_walk, o.near_groups);
         return FMMHP_EINVAL;
     }
     fmmhp_plan_s *p = new (std::nothrow) fmmhp_plan_s();
@@ -110,6 +112,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
         st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
     p->sched.m2l_fp32 = (o.flags & FMMHP_FLAG_M2L_FP32) != 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
+    if (st == FMMHP_OK) apply_launch_shape(p->sched, o.near_walk, o.near_groups);
     p->sched.use_graph = (o.flags & FMMHP_FLAG_GRAPH) != 0;
     if (st == FMMHP_OK) {
         hipError_t e = hipStreamSynchronize(stream);
@@ -263,6 +266,8 @@ fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {
     st->real_impedance = plan->sched.real_Z ? 1 : 0;
     st->device_bytes = plan->arena.bytes;
     st->n_inst = T.n_inst;
+    st->near_walk = plan->sched.near_walk;
+    st->near_groups = (int32_t)(plan->sched.near_blocks / std::max(1, plan->sched.cus));
     for (int k = 0; k < 2; ++k) {
         st->p2p_pairs[k] = plan->sched.p2p_pairs[k];
         st->m2l_pairs[k] = plan->sched.m2l_pairs[k];

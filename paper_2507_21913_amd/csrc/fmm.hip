@@ -178,9 +178,34 @@ __global__ __launch_bounds__(256) void k_p2m(const InstInfo *__restrict__ ii, co
 // ---------------------------------------------------------------------------------------------
 constexpr int kM2MParents = 16;
 
+// Coefficient n of a parent's multipole from its children's staged multipoles: children
+// c0 .. c0 + nc - 1, child c's coefficient m (scaled by 2^-m) at sw[m * ld + c], its position in
+// the parent quad[c].  Callers put n in the fastest-varying thread index: the lanes of a wave then
+// read a few children (broadcast) and consecutive shift coefficients (no LDS bank conflicts).
+template <int PB>
+__device__ __forceinline__ cplx m2m_coef(const cplx *sE, const int *quad, const cplx *sw, int ld, int c0, int nc,
+                                         int n) {
+    cplx out = mk(0.0, 0.0);
+    for (int c = c0; c < c0 + nc; ++c) {
+        const cplx *Eq = sE + quad[c] * (PB + 1) + n;
+#pragma unroll 4
+        for (int m = 0; m <= n; ++m) cfma(out, Eq[-m], sw[m * ld + c]);
+    }
+    return out;
+}
+
+// Coefficient m of a child's local from its parent's staged local (coefficient n at sl[n * ld]):
+// sum_{n>=m} Eq[n] sl[n * ld], Eq the child's shift row offset by -m.
+template <int PB>
+__device__ __forceinline__ cplx l2l_coef(const cplx *Eq, const cplx *sl, int ld, int m) {
+    cplx s = mk(0.0, 0.0);
+#pragma unroll 4
+    for (int n = m; n <= PB; ++n) cfma(s, Eq[n], sl[n * ld]);
+    return s;
+}
+
 template <int PB>
 struct M2MShared {
-    cplx sw[(PB + 1) * 4 * kM2MParents];  // children's multipoles, scaled by 2^-m
     cplx sE[4 * (PB + 1)];
     int2 par[kM2MParents];                // (first staged child, number of children) per parent
     int quad[4 * kM2MParents];            // position of each staged child in its parent
@@ -188,11 +213,13 @@ struct M2MShared {
 };
 
 // Parents [p0, p1) of one level (p1 - p0 <= kM2MParents); called by every thread of the block
-// with block-uniform bounds.  Two dependent memory round trips (the parents' child ranges, then
-// the children's multipoles and positions); ends with a barrier, so the multipoles written are
-// visible to the whole block.
+// with block-uniform bounds.  The children's multipoles, scaled by 2^-m, are staged in the LDS
+// rows sw (row length ld >= 4 kM2MParents: coefficient m of staged child k at sw[m * ld + k]).
+// Two dependent memory round trips (the parents' child ranges, then the children's multipoles and
+// positions); ends with a barrier, so the multipoles written are visible to the whole block.
 template <int PB>
-__device__ void m2m_parents(M2MShared<PB> &sh, int p0, int p1, int nbox, const int32_t *__restrict__ leaf,
+__device__ __forceinline__ void m2m_parents(M2MShared<PB> &sh, cplx *sw, int ld, int p0, int p1, int nbox,
+                            const int32_t *__restrict__ leaf,
                             const int32_t *__restrict__ child_first, const int32_t *__restrict__ nchild,
                             const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
                             cplx *__restrict__ W) {
@@ -219,22 +246,14 @@ __device__ void m2m_parents(M2MShared<PB> &sh, int p0, int p1, int nbox, const i
     const int clo = sh.range[0], nc = sh.range[1] - sh.range[0];
     for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += blockDim.x) {
         const int m = idx / nc, k = idx - m * nc;
-        sh.sw[m * 4 * kM2MParents + k] = W[(int64_t)m * nbox + clo + k] * ldexp(1.0, -m);
+        sw[m * ld + k] = W[(int64_t)m * nbox + clo + k] * ldexp(1.0, -m);
     }
     for (int k = threadIdx.x; k < nc; k += blockDim.x) sh.quad[k] = (bx[clo + k] & 1) | ((by[clo + k] & 1) << 1);
     __syncthreads();
-    const int pi = threadIdx.x % kM2MParents;
-    const int2 pr = sh.par[pi];
-    if (pr.y > 0) {
-        for (int n = threadIdx.x / kM2MParents; n <= PB; n += blockDim.x / kM2MParents) {
-            cplx out = mk(0.0, 0.0);
-            for (int c = pr.x; c < pr.x + pr.y; ++c) {
-                const cplx *Eq = sh.sE + sh.quad[c] * (PB + 1) + n;
-#pragma unroll 4
-                for (int m = 0; m <= n; ++m) cfma(out, Eq[-m], sh.sw[m * 4 * kM2MParents + c]);
-            }
-            W[(int64_t)n * nbox + p0 + pi] = out;
-        }
+    for (int idx = threadIdx.x; idx < (p1 - p0) * (PB + 1); idx += blockDim.x) {
+        const int pi = idx / (PB + 1), n = idx - pi * (PB + 1);
+        const int2 pr = sh.par[pi];
+        if (pr.y > 0) W[(int64_t)n * nbox + p0 + pi] = m2m_coef<PB>(sh.sE, sh.quad, sw, ld, pr.x, pr.y, n);
     }
     __syncthreads();
 }
@@ -246,28 +265,104 @@ __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int
                                              const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                              cplx *__restrict__ W) {
     __shared__ M2MShared<PB> sh;
+    extern __shared__ cplx dyn_lds[];  // (PB + 1) x 4 kM2MParents
     W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
     for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
     const int p0 = lo + blockIdx.x * kM2MParents;
-    m2m_parents<PB>(sh, p0, min(p0 + kM2MParents, lo + nb), nbox, leaf, child_first, nchild, bx, by, W);
+    m2m_parents<PB>(sh, dyn_lds, 4 * kM2MParents, p0, min(p0 + kM2MParents, lo + nb), nbox, leaf, child_first, nchild,
+                    bx, by, W);
 }
 
-// rng: [n_roots][nlev] box ranges (begin, end) of each subtree at the levels cut + k.
+// Subtree passes.  rng: [n_roots][nlev] box ranges (begin, end) of each subtree at the levels
+// cut + k.  The block's dynamic LDS holds ld rows slots (ld >= 4 kM2MParents); a subtree whose
+// expansions fit keeps all of them in LDS between levels (one memory round trip to load them,
+// then LDS only), a larger one runs the chunked one-level code level after level.
+constexpr int kSubMaxLev = 32;
+constexpr int kSubMaxSlots = 256;   // resident slots (the host keeps ld within this)
+
+struct SubShared {
+    int base[kSubMaxLev + 1];        // first resident slot of each level
+    int first[kSubMaxLev];           // first box of each level
+    int slot[kSubMaxSlots];          // leaf: -1; else slot of the first child (M2M) / of the parent (L2L)
+    int nch[kSubMaxSlots];           // number of children (M2M)
+    int quad[kSubMaxSlots];          // position of the box in its parent
+};
+
+// Fills ss.base and ss.first from the subtree's ranges; ends with a barrier.
+__device__ __forceinline__ void sub_ranges(SubShared &ss, const int2 *__restrict__ R, int nlev) {
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < nlev; ++k) {
+            const int2 r = R[k];
+            ss.base[k] = tot;
+            ss.first[k] = r.x;
+            tot += r.y - r.x;
+        }
+        ss.base[nlev] = tot;
+    }
+    __syncthreads();
+}
+
+// Level of resident slot i.
+__device__ __forceinline__ int sub_level_of(const SubShared &ss, int nlev, int i) {
+    int k = 0;
+    while (k + 1 < nlev && ss.base[k + 1] <= i) ++k;
+    return k;
+}
+
 template <int PB>
-__global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restrict__ rng, int nbox,
+__global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restrict__ rng, int ld, int nbox,
                                                  const int32_t *__restrict__ leaf,
                                                  const int32_t *__restrict__ child_first,
                                                  const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
                                                  const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                                  cplx *__restrict__ W) {
     __shared__ M2MShared<PB> sh;
+    __shared__ SubShared ss;
+    extern __shared__ cplx dyn_lds[];  // (PB + 1) x ld: slot i, coefficient m at [m * ld + i]
+    cplx *sw = dyn_lds;
     W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
     for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
     const int2 *R = rng + (int64_t)blockIdx.x * nlev;
+    sub_ranges(ss, R, nlev);
+    const int tot = ss.base[nlev];
+    if (tot > ld) {
+        for (int k = nlev - 2; k >= 0; --k) {
+            const int2 r = R[k];
+            for (int p0 = r.x; p0 < r.y; p0 += kM2MParents)
+                m2m_parents<PB>(sh, sw, ld, p0, min(p0 + kM2MParents, r.y), nbox, leaf, child_first, nchild, bx, by,
+                                W);
+        }
+        return;
+    }
+    // every box's structure and multipole (the non-leaf ones are recomputed below before use),
+    // stored scaled by 2^-m as its parent consumes it
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int k = sub_level_of(ss, nlev, i);
+        const int b = ss.first[k] + (i - ss.base[k]);
+        const int lf = leaf[b];
+        ss.slot[i] = lf ? -1 : ss.base[k + 1] + (child_first[b] - ss.first[k + 1]);
+        ss.nch[i] = lf ? 0 : nchild[b];
+        ss.quad[i] = (bx[b] & 1) | ((by[b] & 1) << 1);
+    }
+    for (int idx = threadIdx.x; idx < tot * (PB + 1); idx += blockDim.x) {
+        const int m = idx / tot, i = idx - m * tot;
+        const int k = sub_level_of(ss, nlev, i);
+        const int b = ss.first[k] + (i - ss.base[k]);
+        sw[m * ld + i] = W[(int64_t)m * nbox + b] * ldexp(1.0, -m);
+    }
+    __syncthreads();
     for (int k = nlev - 2; k >= 0; --k) {
-        const int2 r = R[k];
-        for (int p0 = r.x; p0 < r.y; p0 += kM2MParents)
-            m2m_parents<PB>(sh, p0, min(p0 + kM2MParents, r.y), nbox, leaf, child_first, nchild, bx, by, W);
+        const int i0 = ss.base[k], np = ss.base[k + 1] - i0;
+        for (int idx = threadIdx.x; idx < np * (PB + 1); idx += blockDim.x) {
+            const int ip = idx / (PB + 1), n = idx - ip * (PB + 1), i = i0 + ip;
+            const int c0 = ss.slot[i];
+            if (c0 < 0) continue;
+            const cplx out = m2m_coef<PB>(sh.sE, ss.quad, sw, ld, c0, ss.nch[i], n);
+            W[(int64_t)n * nbox + ss.first[k] + (i - i0)] = out;
+            sw[n * ld + i] = out * ldexp(1.0, -n);
+        }
+        __syncthreads();
     }
 }
 
@@ -639,15 +734,15 @@ constexpr int kL2LChildren = 64;
 
 template <int PB>
 struct L2LShared {
-    cplx sl[(PB + 1) * kL2LChildren];
     cplx sE[4 * (PB + 1)];
 };
 
 // Children [c0, c0 + nc) of one level, nc <= kL2LChildren; called by every thread of the block.
-// The children's own locals are read before the parents' are staged, so that both loads overlap.
+// The parents' locals are staged in the LDS rows sl (row length ld >= kL2LChildren).  The
+// children's own locals are read before the parents' are staged, so that both loads overlap.
 // Ends with a barrier, so the locals written are visible to the whole block.
 template <int PB>
-__device__ void l2l_children(L2LShared<PB> &sh, int c0, int nc, int nbox, int nloc,
+__device__ __forceinline__ void l2l_children(L2LShared<PB> &sh, cplx *sl, int ld, int c0, int nc, int nbox, int nloc,
                              const int32_t *__restrict__ parent, const int32_t *__restrict__ bx,
                              const int32_t *__restrict__ by, cplx *__restrict__ Lam) {
     constexpr int MS = 256 / kL2LChildren;         // threads per child
@@ -666,7 +761,7 @@ __device__ void l2l_children(L2LShared<PB> &sh, int c0, int nc, int nbox, int nl
         }
         for (int idx = threadIdx.x; idx < (PB + 1) * nc; idx += blockDim.x) {
             const int n = idx / nc, k = idx - n * nc;
-            sh.sl[n * kL2LChildren + k] = L[(int64_t)n * nbox + parent[c0 + k]];
+            sl[n * ld + k] = L[(int64_t)n * nbox + parent[c0 + k]];
         }
         __syncthreads();
         if (ci < nc) {
@@ -674,10 +769,7 @@ __device__ void l2l_children(L2LShared<PB> &sh, int c0, int nc, int nbox, int nl
             for (int k = 0; k < MP; ++k) {
                 const int m = mt + k * MS;
                 if (m <= PB) {
-                    const cplx *Eq = sh.sE + q * (PB + 1) - m;
-                    cplx s = mk(0.0, 0.0);
-#pragma unroll 4
-                    for (int n = m; n <= PB; ++n) cfma(s, Eq[n], sh.sl[n * kL2LChildren + ci]);
+                    const cplx s = l2l_coef<PB>(sh.sE + q * (PB + 1) - m, sl + ci, ld, m);
                     L[(int64_t)m * nbox + c] = own[k] + s * ldexp(1.0, -m);
                 }
             }
@@ -691,26 +783,63 @@ __global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc,
                                              const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
                                              const cplx *__restrict__ E, cplx *__restrict__ Lam) {
     __shared__ L2LShared<PB> sh;
+    extern __shared__ cplx dyn_lds[];  // (PB + 1) x kL2LChildren
     Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;  // charge vector
     for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
     const int c0 = lo + blockIdx.x * kL2LChildren;
-    l2l_children<PB>(sh, c0, min(kL2LChildren, lo + nb - c0), nbox, nloc, parent, bx, by, Lam);
+    l2l_children<PB>(sh, dyn_lds, kL2LChildren, c0, min(kL2LChildren, lo + nb - c0), nbox, nloc, parent, bx, by,
+                     Lam);
 }
 
 template <int PB>
-__global__ __launch_bounds__(256) void k_l2l_sub(int nlev, const int2 *__restrict__ rng, int nbox, int nloc,
+__global__ __launch_bounds__(256) void k_l2l_sub(int nlev, const int2 *__restrict__ rng, int ld, int nbox, int nloc,
                                                  const int32_t *__restrict__ parent, const int32_t *__restrict__ bx,
                                                  const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                                  cplx *__restrict__ Lam) {
     __shared__ L2LShared<PB> sh;
+    __shared__ SubShared ss;
+    extern __shared__ cplx dyn_lds[];  // (PB + 1) x ld
+    cplx *sl = dyn_lds;
     Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;  // charge vector
     for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
-    __syncthreads();
     const int2 *R = rng + (int64_t)blockIdx.x * nlev;
+    sub_ranges(ss, R, nlev);
+    const int tot = ss.base[nlev];
+    if (tot * nloc > ld) {
+        for (int k = 1; k < nlev; ++k) {
+            const int2 r = R[k];
+            for (int c0 = r.x; c0 < r.y; c0 += kL2LChildren)
+                l2l_children<PB>(sh, sl, ld, c0, min(kL2LChildren, r.y - c0), nbox, nloc, parent, bx, by, Lam);
+        }
+        return;
+    }
+    // resident: slot loc * tot + i holds local loc of box i, coefficient n at sl[n * ld + slot];
+    // the root's local is final (the levels above ran first), the others hold their own M2L/P2L
+    // parts until their level is reached
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int k = sub_level_of(ss, nlev, i);
+        const int b = ss.first[k] + (i - ss.base[k]);
+        ss.slot[i] = k == 0 ? -1 : ss.base[k - 1] + (parent[b] - ss.first[k - 1]);
+        ss.quad[i] = (bx[b] & 1) | ((by[b] & 1) << 1);
+    }
+    for (int idx = threadIdx.x; idx < nloc * tot * (PB + 1); idx += blockDim.x) {
+        const int n = idx / (nloc * tot), r = idx - n * nloc * tot, loc = r / tot, i = r - loc * tot;
+        const int k = sub_level_of(ss, nlev, i);
+        const int b = ss.first[k] + (i - ss.base[k]);
+        sl[n * ld + r] = Lam[((int64_t)loc * (PB + 1) + n) * nbox + b];
+    }
+    __syncthreads();
     for (int k = 1; k < nlev; ++k) {
-        const int2 r = R[k];
-        for (int c0 = r.x; c0 < r.y; c0 += kL2LChildren)
-            l2l_children<PB>(sh, c0, min(kL2LChildren, r.y - c0), nbox, nloc, parent, bx, by, Lam);
+        const int i0 = ss.base[k], nc = ss.base[k + 1] - i0;
+        for (int idx = threadIdx.x; idx < nloc * nc * (PB + 1); idx += blockDim.x) {
+            const int m = idx / (nloc * nc), r = idx - m * nloc * nc, loc = r / nc, i = i0 + (r - loc * nc);
+            const int ps = loc * tot + ss.slot[i], cs = loc * tot + i;
+            const cplx acc = l2l_coef<PB>(sh.sE + ss.quad[i] * (PB + 1) - m, sl + ps, ld, m);
+            const cplx v = sl[m * ld + cs] + acc * ldexp(1.0, -m);
+            sl[m * ld + cs] = v;
+            Lam[((int64_t)loc * (PB + 1) + m) * nbox + ss.first[k] + (i - i0)] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -893,6 +1022,95 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
             for (int v = 0; v < NV; ++v) {
                 a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * gxa[v], 0.0);
                 a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * gya[v], 0.0);
+            }
+            if (a.qc) a.qc[i] = qc;
+        }
+    }
+}
+
+// The same sums with a plain walk: the U list entry by entry, a source point loaded where it is
+// used (fewer instructions per pair; the memory latency is hidden by other waves only), free-space
+// and image terms in separate sums.
+template <int MODE, int NV>
+__global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
+    __shared__ double2 s_logtab[kLogTable];
+    if (has_phi(MODE)) {
+        for (int k = threadIdx.x; k < kLogTable; k += blockDim.x) s_logtab[k] = a.logtab[k];
+        __syncthreads();
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = a.leaf_of[i];
+        const double2 pi = a.xy[i];
+        const double x = pi.x, y = pi.y;
+        double lfree[NV], limg[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) lfree[v] = limg[v] = 0.0;
+        double fx[NV], fy[NV], mx[NV], my[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fx[v] = fy[v] = mx[v] = my[v] = 0.0;
+        double qc = 0.0;  // coincident charge of vector 0
+        const double2 *__restrict__ xy = a.xy;
+        const double2 *__restrict__ tab = s_logtab;
+        const double *__restrict__ qs = a.qs;
+        for (int e = a.uoff[b]; e < a.uoff[b + 1]; ++e) {
+            const int code = a.uent[e];
+            const int c = code >> 1;
+            const int j0 = a.first[c], j1 = j0 + a.count[c];
+            if (!(code & 1)) {
+                for (int j = j0; j < j1; ++j) {
+                    const double2 pj = xy[j];
+                    const double dx = x - pj.x, dy = y - pj.y;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const bool nz = r2 > 0.0;  // skip the self pair (eq. (1.2))
+                    if (has_phi(MODE)) {
+                        const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
+                    }
+                    if (has_grad(MODE)) {
+                        const double ir = nz ? rcp_pos(nz ? r2 : 1.0) : 0.0;
+                        const double irx = ir * dx, iry = ir * dy;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const double qj = qs[(int64_t)j * NV + v];
+                            fx[v] = fma(qj, irx, fx[v]);
+                            fy[v] = fma(qj, iry, fy[v]);
+                        }
+                        qc += nz ? 0.0 : qs[(int64_t)j * NV];
+                    }
+                }
+            } else {
+                for (int j = j0; j < j1; ++j) {
+                    const double2 pj = xy[j];
+                    const double dx = x - pj.x, dy = y + pj.y;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    if (has_phi(MODE)) {
+                        const double lg = log_tab(r2, tab);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
+                    }
+                    if (has_grad(MODE)) {
+                        const double ir = rcp_pos(r2);
+                        const double irx = ir * dx, iry = ir * dy;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const double qj = qs[(int64_t)j * NV + v];
+                            mx[v] = fma(qj, irx, mx[v]);
+                            my[v] = fma(qj, iry, my[v]);
+                        }
+                    }
+                }
+            }
+        }
+        if (has_phi(MODE)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
+        }
+        if (has_grad(MODE)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * (mx[v] - fx[v]), 0.0);
+                a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * (my[v] - fy[v]), 0.0);
             }
             if (a.qc) a.qc[i] = qc;
         }
@@ -1535,6 +1753,17 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             }
         }
         FMMHP_CHECK(to_dev(A, &S.sub_rng, rng, "subtree ranges", s));
+        // resident LDS rows: enough for the largest subtree, within 48 KB of expansions per block
+        int maxtot = 0;
+        for (int r = 0; r < S.n_sub; ++r) {
+            int tot = 0;
+            for (int k = 0; k < S.sub_nlev; ++k)
+                tot += rng[(size_t)r * S.sub_nlev + k].y - rng[(size_t)r * S.sub_nlev + k].x;
+            maxtot = std::max(maxtot, tot);
+        }
+        const int cap = std::min(kSubMaxSlots, (int)(48 * 1024 / ((PB + 1) * sizeof(cplx))));
+        S.sub_ld_m2m = std::max(4 * kM2MParents, std::min(maxtot, cap));
+        S.sub_ld_l2l = std::max(kL2LChildren, std::min(maxtot * S.nloc, cap));
     }
     {
         std::vector<int32_t> woff, first, wp, rl;
@@ -1764,7 +1993,6 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         FMMHP_HIP(hipGetDevice(&dev));
         FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         S.cus = std::max(1, cus);
-        S.near_blocks = 2 * S.cus;
     }
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
@@ -1772,6 +2000,17 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     FMMHP_HIP(hipGetLastError());
     FMMHP_HIP(hipStreamSynchronize(s));
     return FMMHP_OK;
+}
+
+// Launch shape of the near field.  walk: 1 = sources loaded one step ahead, 2 = plain walk;
+// groups: workgroups per CU of its bounded grid.  0 selects the default: the prefetching walk on
+// two workgroups per CU, or for p >= 30 (far-field kernels heavy enough that the near field's
+// instruction count matters more than its latency) the plain walk on four.
+void apply_launch_shape(Sched &S, int walk, int groups) {
+    if (walk == 0) walk = S.PB >= 30 ? 2 : 1;
+    if (groups == 0) groups = walk == 2 ? 4 : 2;
+    S.near_walk = walk;
+    S.near_blocks = (int64_t)groups * S.cus;
 }
 
 // Phase markers: when timing is on, one event per phase boundary on the eval stream.
@@ -1831,10 +2070,13 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
-    // a bounded grid (two workgroups per CU) leaves room on every CU for the far-field kernels
+    // a bounded grid (a few workgroups per CU) leaves room on every CU for the far-field kernels
     // running concurrently on the main stream
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), dim3((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks)),
-                       dim3(256), 0, S.side, la);
+    const dim3 near_grid((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks));
+    if (S.near_walk == 2)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_plain<MODE, NV>), near_grid, dim3(256), 0, S.side, la);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), near_grid, dim3(256), 0, S.side, la);
     if (S.n_rpts > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
                            S.side, la);
@@ -1901,13 +2143,14 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     int lf = S.fork_late ? 2 : ld;
     if (lc > 0 && lf >= lc) lf = T.depth;  // inside the subtree pass: fork right after it
     if (lc > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_sub, NV), dim3(256), 0, s, S.sub_nlev, S.sub_rng,
-                           nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_sub, NV), dim3(256),
+                           (PB + 1) * S.sub_ld_m2m * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_m2m, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
     if (ld > 0 && lf > T.depth - 1) FMMHP_CHECK(fork_deep());
     for (int l = (lc > 0 ? lc : T.depth) - 1; l >= 2; --l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256), 0, s, lo, nb,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256),
+                               (PB + 1) * 4 * kM2MParents * sizeof(cplx), s, lo, nb,
                                nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
         if (ld > 0 && l == lf) FMMHP_CHECK(fork_deep());
     }
@@ -1928,13 +2171,14 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         if (ld > 0 && l == ld) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256), 0, s, lo, nb,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256),
+                               (PB + 1) * kL2LChildren * sizeof(cplx), s, lo, nb,
                                nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     }
     if (ld > 0 && ld > l2l_end) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
     if (lc > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_sub, NV), dim3(256), 0, s, S.sub_nlev, S.sub_rng,
-                           nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_sub, NV), dim3(256),
+                           (PB + 1) * S.sub_ld_l2l * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_l2l, nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     if (mk_.on && ld == 0) {
         FMMHP_HIP(hipEventRecord(mk_.deep0, s));
         FMMHP_HIP(hipEventRecord(mk_.deep1, s));

@@ -153,12 +153,14 @@ struct Sched {
     int deep_level = 0;             // first level of the deep M2L part (0: no split)
     std::vector<int> tile_lev, ibox_lev, xbox_lev;  // per-level ranges of tiles, image-V and X boxes
     int cus = 1;                    // compute units of the device
-    int64_t near_blocks = 512;      // near-field grid: two workgroups per CU
+    int near_walk = 1;              // near-field walk: 1 prefetching, 2 plain
+    int64_t near_blocks = 512;      // near-field grid (workgroups)
     bool fork_late = false;         // start the deep M2L after the whole upward pass
     bool rank1_side = true;         // surface sums on the near-field stream
     int sub_level = 0;              // cut level of the subtree M2M / L2L passes (0: one launch per level)
     int n_sub = 0, sub_nlev = 0;    // subtrees (the boxes of the cut level), levels cut..depth
     int2 *sub_rng = nullptr;        // [n_sub][sub_nlev] box range of each subtree per level
+    int sub_ld_m2m = 0, sub_ld_l2l = 0;  // LDS expansion slots of the subtree passes
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
@@ -209,6 +211,7 @@ struct Sched {
 
 // Zs: [T.n_inst] impedance of each instance (host)
 fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cplx *Zs, hipStream_t stream);
+void apply_launch_shape(Sched &S, int near_walk, int near_groups);
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
 fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,

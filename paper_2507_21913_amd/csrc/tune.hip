@@ -1,5 +1,5 @@
 // Autotuner (declared in include/fmmhp.h): p from a measured error against the GPU direct sum,
-// leaf size from measured eval time.
+// leaf size and the near-field launch shape from measured eval time.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -46,6 +46,24 @@ struct DevTmp {
     }
 };
 
+// Median of five timed evaluations (n_vec vectors).
+static fmmhp_status median_ms(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipEvent_t e0,
+                              hipEvent_t e1, hipStream_t s, double *med) {
+    std::vector<float> t;
+    for (int r = 0; r < 5; ++r) {
+        FMMHP_HIP(hipEventRecord(e0, s));
+        FMMHP_CHECK(fmmhp_eval(plan, n_vec, q, phi, s));
+        FMMHP_HIP(hipEventRecord(e1, s));
+        FMMHP_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        FMMHP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    *med = t[t.size() / 2];
+    return FMMHP_OK;
+}
+
 }  // namespace fmmhp
 
 using namespace fmmhp;
@@ -87,12 +105,12 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
     FMMHP_HIP(hipEventCreate(&e0));
     FMMHP_HIP(hipEventCreate(&e1));
     double best_ms = INFINITY, best_err = 0.0;
-    fmmhp_opts bo{0, 0, 0, 0};
+    fmmhp_opts bo{0, 0, 0, 0, 0, 0};
     int p_start = 5;
     fmmhp_status st = FMMHP_OK;
     for (int li = 0; li < n_leaf && st == FMMHP_OK; ++li) {
         for (int p = p_start; p <= FMMHP_MAX_P; p += 5) {
-            fmmhp_opts o{p, leaf_sizes[li], 0, 0};
+            fmmhp_opts o{p, leaf_sizes[li], 0, 0, 0, 0};
             fmmhp_plan_t plan = nullptr;
             st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &o, s, &plan);
             if (st == FMMHP_EUNSUPPORTED) {  // e.g. tables beyond the recursion's range at this leaf size
@@ -117,18 +135,8 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
                 e = sqrt(d) / nref;
             }
             if (st == FMMHP_OK && e <= tol) {
-                std::vector<float> t;
-                for (int r = 0; r < 5 && st == FMMHP_OK; ++r) {
-                    (void)hipEventRecord(e0, s);
-                    st = fmmhp_eval(plan, n_vec, qv, phi, s);
-                    (void)hipEventRecord(e1, s);
-                    (void)hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    t.push_back(ms);
-                }
-                std::sort(t.begin(), t.end());
-                const double med = t[t.size() / 2];
+                double med = INFINITY;
+                st = median_ms(plan, n_vec, qv, phi, e0, e1, s, &med);
                 if (st == FMMHP_OK && med < best_ms) {
                     best_ms = med;
                     best_err = e;
@@ -140,6 +148,28 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
                 break;
             }
             (void)fmmhp_plan_destroy(plan);
+        }
+    }
+    // launch shape of the near field on the chosen plan
+    if (st == FMMHP_OK && best_ms < INFINITY) {
+        fmmhp_plan_t plan = nullptr;
+        st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &bo, s, &plan);
+        if (st == FMMHP_OK) {
+            static const int kShapes[][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}};
+            double shape_ms = INFINITY;
+            for (const auto &sh : kShapes) {
+                apply_launch_shape(plan->sched, sh[0], sh[1]);
+                double med = INFINITY;
+                st = median_ms(plan, n_vec, qv, phi, e0, e1, s, &med);
+                if (st != FMMHP_OK) break;
+                if (med < shape_ms) {
+                    shape_ms = med;
+                    bo.near_walk = sh[0];
+                    bo.near_groups = sh[1];
+                }
+            }
+            (void)fmmhp_plan_destroy(plan);
+            if (st == FMMHP_OK) best_ms = shape_ms;
         }
     }
     (void)hipEventDestroy(e0);

@@ -1,0 +1,91 @@
+"""GPU checks of the near-field launch shapes (fmmhp_opts.near_walk, near_groups): every shape
+computes the same sums (only the order of additions differs), for the potential, several charge
+vectors at once and the adjoint; the defaults depend on p; the autotuner returns a valid shape.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2507_21913_amd as F
+from oracle import direct as D
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SHAPES = [(1, 1), (1, 2), (1, 16), (2, 4), (2, 8), (0, 0)]
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def _problem(n, seed, nvec=1):
+    """Most points in a band near y = 0 (image U entries, adaptive leaves), the rest uniform,
+    with a few coincident pairs."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    xb = rng.uniform(0.0, 1.0, m)
+    yb = rng.uniform(1e-3, 0.05, m)
+    x = np.concatenate([xb, rng.uniform(0.0, 1.0, n - m)])
+    y = np.concatenate([yb, rng.uniform(1e-3, 1.0, n - m)])
+    x[10:20] = x[0:10]
+    y[10:20] = y[0:10]
+    return x, y, rng.standard_normal((nvec, n))
+
+
+@pytest.mark.parametrize("Z", [1.0, 1.0 + 0.5j])
+def test_shapes_agree_and_match_oracle(Z):
+    x, y, q = _problem(6000, 3)
+    ref = D.potential(x, y, q[0], Z, workers=8)
+    out = {}
+    for w, g in SHAPES:
+        plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=30, leaf_size=16, near_walk=w, near_groups=g)
+        info = plan.info()
+        if w:
+            assert (info["near_walk"], info["near_groups"]) == (w, g)
+        out[(w, g)] = plan(_t(q[0])).cpu().numpy()
+        plan.close()
+        err = D.rel_l2(out[(w, g)], ref)
+        print(f"Z={Z} shape {(w, g)}: rel-l2 vs oracle {err:.2e}", flush=True)
+        assert err < 1e-10
+    base = out[(1, 2)]
+    for k, v in out.items():
+        assert D.rel_l2(v, base) < 1e-13, k
+
+
+def test_shapes_agree_multivector_and_adjoint():
+    x, y, q = _problem(5000, 7, nvec=9)
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(x.size) + 1j * rng.standard_normal(x.size)
+    res = {}
+    for w, gr in [(1, 2), (2, 4)]:
+        plan = F.HalfPlaneFMM(_t(x), _t(y), 2.0, p=20, leaf_size=24, near_walk=w, near_groups=gr)
+        phi = plan(_t(q)).cpu().numpy()
+        b = plan.backward(_t(q[0]), _t(g))
+        res[w] = (phi, {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in b.items()})
+        plan.close()
+    for v in range(9):
+        assert D.rel_l2(res[1][0][v], res[2][0][v]) < 1e-13, v
+    for k in ("q", "x", "y"):
+        assert D.rel_l2(res[1][1][k], res[2][1][k]) < 1e-12, k
+    assert abs(res[1][1]["lambda"] - res[2][1]["lambda"]) < 1e-12 * abs(res[2][1]["lambda"])
+
+
+def test_default_shape_by_order():
+    x, y, _ = _problem(3000, 11)
+    for p, want in ((20, (1, 2)), (30, (2, 4))):
+        plan = F.HalfPlaneFMM(_t(x), _t(y), 1.0, p=p, leaf_size=16)
+        info = plan.info()
+        assert (info["near_walk"], info["near_groups"]) == want, (p, info["near_walk"], info["near_groups"])
+        plan.close()
+
+
+def test_tune_returns_a_shape():
+    x, y, q = _problem(20000, 5)
+    r = F.tune(_t(x), _t(y), _t(q[0]), 1.0, tol=1e-8, leaf_sizes=[24, 40])
+    print("tune:", r, flush=True)
+    assert r["near_walk"] in (1, 2) and 1 <= r["near_groups"] <= 16
+    plan = F.HalfPlaneFMM(_t(x), _t(y), 1.0, p=r["p"], leaf_size=r["leaf_size"], near_walk=r["near_walk"],
+                          near_groups=r["near_groups"])
+    info = plan.info()
+    assert (info["near_walk"], info["near_groups"]) == (r["near_walk"], r["near_groups"])
+    plan.close()
