@@ -104,6 +104,8 @@ typedef struct {
     int32_t n_inst;         /* instances (1 for fmmhp_plan_create) */
     int32_t near_walk;      /* near-field launch shape in use (see fmmhp_opts) */
     int32_t near_groups;
+    int64_t n_sources;      /* sources (n unless the plan has separate targets: then n - n_sources
+                               targets follow the sources in the tree's point set) */
 } fmmhp_plan_stats;
 
 /* Phases of fmmhp_eval whose device time fmmhp_plan_phase_times reports. */
@@ -139,6 +141,23 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
                                const double *img_y, double lambda_re, double lambda_im,
                                const fmmhp_opts *opts, hipStream_t stream,
                                fmmhp_plan_t *plan_out);
+
+/* Build a plan with separate target points: the potential of the sources is wanted at the targets
+ * (the paper's Example 2 evaluates the field of charged circles on a grid that reaches y = 0).
+ *
+ *   n_src, xs, ys  [device] source coordinates, y > 0, finite; n_src >= 1
+ *   n_tgt, xt, yt  [device] target coordinates, y >= 0, finite; n_tgt >= 1, n_src + n_tgt < 2^31
+ *   lambda_re/im, opts, stream, plan_out   as for fmmhp_plan_create
+ *
+ * The tree is built over the sources and the targets together (the targets take part as points
+ * without charge).  fmmhp_eval / fmmhp_eval_complex on this plan take q [n_vec][n_src] and return
+ * phi [n_vec][n_tgt][2].  A target that coincides with a source skips that source's free-space term
+ * (as coincident points do in fmmhp_plan_create); a target on y = 0 is the limit of the potential
+ * from y > 0.  fmmhp_backward returns FMMHP_EUNSUPPORTED for this plan.  xs, ys, xt, yt may be freed
+ * after the call returns. */
+fmmhp_status fmmhp_plan_create_targets(int64_t n_src, const double *xs, const double *ys, int64_t n_tgt,
+                                       const double *xt, const double *yt, double lambda_re, double lambda_im,
+                                       const fmmhp_opts *opts, hipStream_t stream, fmmhp_plan_t *plan_out);
 
 /* Build a batched plan: n_inst independent problems ("instances") in one forest, each with its own
  * points, root square and impedance; every evaluation runs all instances in the same launches

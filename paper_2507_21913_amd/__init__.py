@@ -52,7 +52,7 @@ class PlanStats(ctypes.Structure):
                 ("real_impedance", ctypes.c_int), ("device_bytes", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64 * 2), ("m2l_pairs", ctypes.c_int64 * 2),
                 ("n_inst", ctypes.c_int32), ("near_walk", ctypes.c_int32),
-                ("near_groups", ctypes.c_int32)]
+                ("near_groups", ctypes.c_int32), ("n_sources", ctypes.c_int64)]
 
 
 PHASES = ("p2m", "m2m", "m2l", "p2l", "l2l", "surface", "leaf", "near")
@@ -68,6 +68,8 @@ _SIGNATURES = {
     "fmmhp_plan_create": [_I64, _P, _P, _P, _P, _D, _D, ctypes.POINTER(Opts), _P,
                           ctypes.POINTER(_P)],
     "fmmhp_batch_plan_create": [_INT, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(_P)],
+    "fmmhp_plan_create_targets": [_I64, _P, _P, _I64, _P, _P, _D, _D, ctypes.POINTER(Opts), _P,
+                                  ctypes.POINTER(_P)],
     "fmmhp_eval": [_P, _INT, _P, _P, _P],
     "fmmhp_eval_complex": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
@@ -133,6 +135,16 @@ def fmmhp_plan_create(n, x_ptr, y_ptr, img_x_ptr, img_y_ptr, lambda_re, lambda_i
                                  ctypes.byref(opts) if opts is not None else None, stream,
                                  ctypes.byref(h))
     _check("fmmhp_plan_create", st)
+    return h
+
+
+def fmmhp_plan_create_targets(n_src, xs_ptr, ys_ptr, n_tgt, xt_ptr, yt_ptr, lambda_re, lambda_im, opts,
+                              stream):
+    h = _P()
+    st = lib().fmmhp_plan_create_targets(n_src, xs_ptr, ys_ptr, n_tgt, xt_ptr, yt_ptr, lambda_re, lambda_im,
+                                         ctypes.byref(opts) if opts is not None else None, stream,
+                                         ctypes.byref(h))
+    _check("fmmhp_plan_create_targets", st)
     return h
 
 
@@ -290,6 +302,32 @@ class HalfPlaneFMM:
                                                lr, li, opts, _stream())
         self.impedance = complex(lr, li)
         self.n_inst = 1
+        self.n_out = self.n
+
+    @classmethod
+    def with_targets(cls, xs, ys, xt, yt, impedance, p=20, leaf_size=40, max_level=0, graph=False,
+                     m2l_fp32=False, near_walk=0, near_groups=0):
+        """A plan whose potential is evaluated at separate targets (xt, yt), y >= 0: calling it
+        with charges q [N_src] (or [n_vec, N_src]) returns phi at the N_tgt targets."""
+        self = cls.__new__(cls)
+        xs = _dev_f64(xs, "xs")
+        ys = _dev_f64(ys, "ys")
+        xt = _dev_f64(xt, "xt")
+        yt = _dev_f64(yt, "yt")
+        self.n = int(xs.shape[0])
+        self.n_out = int(xt.shape[0])
+        self.device = xs.device
+        self._x, self._y = xs, ys
+        lr, li = _split_impedance(impedance)
+        opts = Opts(int(p), int(leaf_size), int(max_level),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0),
+                    int(near_walk), int(near_groups))
+        with torch.cuda.device(self.device):
+            self._plan = fmmhp_plan_create_targets(self.n, xs.data_ptr(), ys.data_ptr(), self.n_out,
+                                                   xt.data_ptr(), yt.data_ptr(), lr, li, opts, _stream())
+        self.impedance = complex(lr, li)
+        self.n_inst = 1
+        return self
 
     @classmethod
     def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False,
@@ -318,6 +356,7 @@ class HalfPlaneFMM:
             self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,
                                                  opts, _stream())
         self.impedance = imps[0] if self.n_inst == 1 else imps
+        self.n_out = self.n
         return self
 
     def info(self) -> dict:
@@ -334,7 +373,8 @@ class HalfPlaneFMM:
         return fmmhp_plan_phase_times(self._plan)
 
     def __call__(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        """phi = A q.  q: [N] or [n_vec, N], real or complex.  Returns complex128 of q's shape."""
+        """phi = A q.  q: [N] or [n_vec, N], real or complex.  Returns complex128 [n_out] or
+        [n_vec, n_out] (n_out = N unless the plan has separate targets)."""
         if not isinstance(q, torch.Tensor) or not q.is_cuda:
             raise TypeError("q must be a GPU tensor (no CPU path exists)")
         squeeze = q.dim() == 1
@@ -347,11 +387,11 @@ class HalfPlaneFMM:
         else:
             parts = q2.to(torch.float64).contiguous()
         direct_out = (out is not None and out.dtype == torch.complex128 and out.is_contiguous()
-                      and out.device == self.device and out.numel() == nv * self.n)
+                      and out.device == self.device and out.numel() == nv * self.n_out)
         if direct_out:
             raw = torch.view_as_real(out)
         else:
-            raw = torch.empty((nv, self.n, 2), dtype=torch.float64, device=self.device)
+            raw = torch.empty((nv, self.n_out, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             if q2.is_complex():
                 fmmhp_eval_complex(self._plan, nv, parts.data_ptr(), raw.data_ptr(), _stream())
@@ -475,7 +515,7 @@ def reaction_integrals(x, y, nmax: int, impedance) -> torch.Tensor:
 
 
 __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functions",
-           "FMMHPError", "Opts", "PlanStats", "fmmhp_plan_create", "fmmhp_eval",
+           "FMMHPError", "Opts", "PlanStats", "fmmhp_plan_create", "fmmhp_plan_create_targets", "fmmhp_eval",
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
            "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune",

@@ -77,8 +77,8 @@ const char *fmmhp_last_error_message(void) { return g_msg; }
 
 // Shared by the plain and batched plan builders: n_inst instances, point ranges off[0..n_inst].
 static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x, const double *y,
-                                const double *img_x, const double *img_y, const cplx *Zs, const fmmhp_opts *opts,
-                                hipStream_t stream, fmmhp_plan_t *plan_out) {
+                                const double *img_x, const double *img_y, int64_t src_end, const cplx *Zs,
+                                const fmmhp_opts *opts, hipStream_t stream, fmmhp_plan_t *plan_out) {
     const int lb = n_inst == 1 ? kLBits : kLBitsForest;
     fmmhp_opts o{20, 40, lb, 0, 0, 0};
     if (opts) o = *opts;
@@ -109,7 +109,8 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
         st = FMMHP_EHIP;
     }
     if (st == FMMHP_OK)
-        st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, o.leaf_size, o.max_level, stream);
+        st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, src_end, o.leaf_size, o.max_level,
+                        stream);
     p->sched.m2l_fp32 = (o.flags & FMMHP_FLAG_M2L_FP32) != 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
     if (st == FMMHP_OK) apply_launch_shape(p->sched, o.near_walk, o.near_groups);
@@ -162,7 +163,52 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
     FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
     const int64_t off[2] = {0, n};
     const cplx Z = mk(lambda_re, lambda_im);
-    return create_plan(1, off, x, y, img_x, img_y, &Z, opts, stream, plan_out);
+    return create_plan(1, off, x, y, img_x, img_y, n, &Z, opts, stream, plan_out);
+}
+
+fmmhp_status fmmhp_plan_create_targets(int64_t n_src, const double *xs, const double *ys, int64_t n_tgt,
+                                       const double *xt, const double *yt, double lambda_re, double lambda_im,
+                                       const fmmhp_opts *opts, hipStream_t stream, fmmhp_plan_t *plan_out) {
+    g_msg[0] = 0;
+    if (!plan_out) {
+        set_error("plan_out is NULL");
+        return FMMHP_EINVAL;
+    }
+    *plan_out = nullptr;
+    if (n_src < 1 || n_tgt < 1 || n_src + n_tgt >= ((int64_t)1 << 31)) {
+        set_error("n_src = %lld, n_tgt = %lld: both >= 1 and their sum < 2^31", (long long)n_src,
+                  (long long)n_tgt);
+        return FMMHP_EINVAL;
+    }
+    if (!xs || !ys || !xt || !yt) {
+        set_error("xs, ys, xt and yt must be non-NULL");
+        return FMMHP_EINVAL;
+    }
+    FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
+    // one point set: the sources, then the targets (the tree is built over both)
+    const int64_t n = n_src + n_tgt;
+    double *xy = nullptr;
+    if (hipMalloc(&xy, 2 * (size_t)n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %lld bytes for the combined points failed", (long long)(16 * n));
+        return FMMHP_ENOMEM;
+    }
+    fmmhp_status st = FMMHP_OK;
+    const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(xy, xs, n_src * sizeof(double), d2d, stream) != hipSuccess ||
+        hipMemcpyAsync(xy + n_src, xt, n_tgt * sizeof(double), d2d, stream) != hipSuccess ||
+        hipMemcpyAsync(xy + n, ys, n_src * sizeof(double), d2d, stream) != hipSuccess ||
+        hipMemcpyAsync(xy + n + n_src, yt, n_tgt * sizeof(double), d2d, stream) != hipSuccess) {
+        set_error("copy of the points failed");
+        st = FMMHP_EHIP;
+    }
+    const int64_t off[2] = {0, n};
+    const cplx Z = mk(lambda_re, lambda_im);
+    if (st == FMMHP_OK) st = create_plan(1, off, xy, xy + n, nullptr, nullptr, n_src, &Z, opts, stream, plan_out);
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(xy);
+    if (st == FMMHP_OK) (*plan_out)->n_src = n_src;
+    return st;
 }
 
 fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const double *x, const double *y,
@@ -200,7 +246,45 @@ fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const d
         FMMHP_CHECK(check_impedance(lambda[2 * k], lambda[2 * k + 1]));
         Zs[k] = mk(lambda[2 * k], lambda[2 * k + 1]);
     }
-    return create_plan(n_inst, offsets, x, y, nullptr, nullptr, Zs.data(), opts, stream, plan_out);
+    return create_plan(n_inst, offsets, x, y, nullptr, nullptr, offsets[n_inst], Zs.data(), opts, stream, plan_out);
+}
+
+// q [nv][n_src][w] -> qp [nv][n][w] (zero charges on the target-only points)
+__global__ void k_pad_charges(const double *__restrict__ q, int64_t ns, int64_t n, int w, int nv,
+                              double *__restrict__ qp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * w) return;
+    for (int v = 0; v < nv; ++v) qp[(int64_t)v * n * w + i] = i < ns * w ? q[(int64_t)v * ns * w + i] : 0.0;
+}
+
+// pp [nv][n][2] -> phi [nv][n - ns][2] (the targets' potentials)
+__global__ void k_take_targets(const double *__restrict__ pp, int64_t ns, int64_t n, int nv, double *__restrict__ phi) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = n - ns;
+    if (t >= 2 * nt) return;
+    for (int v = 0; v < nv; ++v) phi[(int64_t)v * 2 * nt + t] = pp[(int64_t)v * 2 * n + 2 * ns + t];
+}
+
+// Evaluation on a plan with separate targets: charges padded to all tree points, potentials of
+// the targets kept.  w = 1 (real charges) or 2 (complex).
+static fmmhp_status eval_targets(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, int w,
+                                 hipStream_t stream) {
+    const int64_t n = plan->tree.n, ns = plan->n_src;
+    if (plan->pad_cap < n_vec) {
+        FMMHP_CHECK(plan->arena.alloc_n(&plan->qpad, (size_t)n_vec * n * 2, "padded charges"));
+        FMMHP_CHECK(plan->arena.alloc_n(&plan->phipad, (size_t)n_vec * n * 2, "potentials at all points"));
+        plan->pad_cap = n_vec;
+    }
+    const unsigned nb = (unsigned)((n * w + 255) / 256);
+    hipLaunchKernelGGL(k_pad_charges, dim3(nb), dim3(256), 0, stream, q, ns, n, w, n_vec, plan->qpad);
+    FMMHP_HIP(hipGetLastError());
+    if (w == 1)
+        FMMHP_CHECK(run_eval(plan->arena, plan->tree, plan->sched, n_vec, plan->qpad, plan->phipad, stream));
+    else
+        FMMHP_CHECK(run_eval_complex(plan->arena, plan->tree, plan->sched, n_vec, plan->qpad, plan->phipad, stream));
+    hipLaunchKernelGGL(k_take_targets, dim3((unsigned)((2 * (n - ns) + 255) / 256)), dim3(256), 0, stream,
+                       plan->phipad, ns, n, n_vec, phi);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
 }
 
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipStream_t stream) {
@@ -209,6 +293,7 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
         set_error("n_vec must be >= 1 and q, phi non-NULL");
         return FMMHP_EINVAL;
     }
+    if (plan->n_src > 0) return eval_targets(plan, n_vec, q, phi, 1, stream);
     return run_eval(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
@@ -218,6 +303,7 @@ fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, d
         set_error("n_vec must be >= 1 and q, phi non-NULL");
         return FMMHP_EINVAL;
     }
+    if (plan->n_src > 0) return eval_targets(plan, n_vec, q, phi, 2, stream);
     return run_eval_complex(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
@@ -227,6 +313,10 @@ fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *gr
     if (!q || !grad_phi) {
         set_error("q and grad_phi must be non-NULL");
         return FMMHP_EINVAL;
+    }
+    if (plan->n_src > 0) {
+        set_error("fmmhp_backward is not available for plans with separate targets");
+        return FMMHP_EUNSUPPORTED;
     }
     std::vector<cplx> zsum(plan->tree.n_inst, mk(0.0, 0.0));
     FMMHP_CHECK(run_backward(plan->arena, plan->tree, plan->sched, q, grad_phi, grad_q, grad_x, grad_y,
@@ -266,6 +356,7 @@ fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {
     st->real_impedance = plan->sched.real_Z ? 1 : 0;
     st->device_bytes = plan->arena.bytes;
     st->n_inst = T.n_inst;
+    st->n_sources = plan->n_src > 0 ? plan->n_src : T.n;
     st->near_walk = plan->sched.near_walk;
     st->near_groups = (int32_t)(plan->sched.near_blocks / std::max(1, plan->sched.cus));
     for (int k = 0; k < 2; ++k) {

@@ -986,8 +986,8 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 for (int v = 0; v < NV; ++v) qn[v] = qs[(int64_t)jp * NV + v];
                 const double dx = x - pj.x, dy = fma(sg, pj.y, y);  // y - y' or y + y'
                 const double r2 = fma(dx, dx, dy * dy);
-                // r2 = 0 only for a coincident free pair (image distances are positive), which is
-                // skipped (eq. (1.2))
+                // r2 = 0 only for a coincident free pair, skipped (eq. (1.2)), or between two
+                // target-only points on y = 0 (no charge); image distances to sources are positive
                 const bool nz = r2 > 0.0;
                 if (has_phi(MODE)) {
                     const double sl = sg * log_tab(nz ? r2 : 1.0, tab);
@@ -1084,13 +1084,15 @@ __global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
                     const double2 pj = xy[j];
                     const double dx = x - pj.x, dy = y + pj.y;
                     const double r2 = fma(dx, dx, dy * dy);
+                    // r2 = 0 only between two target-only points on y = 0 (no charge): skipped
+                    const bool nz = r2 > 0.0;
                     if (has_phi(MODE)) {
-                        const double lg = log_tab(r2, tab);
+                        const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
                     }
                     if (has_grad(MODE)) {
-                        const double ir = rcp_pos(r2);
+                        const double ir = nz ? rcp_pos(nz ? r2 : 1.0) : 0.0;
                         const double irx = ir * dx, iry = ir * dy;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) {
@@ -1320,6 +1322,7 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
         const int j1 = a.first[c] + a.count[c];
         for (int j = a.first[c] + lane; j < j1; j += 64) {
             const double dx = x - a.xs[j], dy = y + a.ys[j];
+            if (!(dy > 0.0)) continue;  // two target-only points on y = 0 (no charge)
             const cplx I = reaction_I0_near(dx, dy, Z);
             if (has_grad(MODE)) {
                 const cplx I1 = kInv2Pi * inv(mk(dy, -dx)) + Z * I;

@@ -90,8 +90,9 @@ struct Tree {
     int64_t len[4] = {0, 0, 0, 0};
 };
 
+// Points from src_end on are target-only (they carry no charge; y = 0 allowed).
 fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, const double *x, const double *y,
-                        const double *img_x, const double *img_y, int leaf_size, int max_level,
+                        const double *img_x, const double *img_y, int64_t src_end, int leaf_size, int max_level,
                         hipStream_t stream);
 
 // Root square and impedance of one instance of a plan.
@@ -237,6 +238,12 @@ inline int pick_bucket(int p) {
 struct fmmhp_plan_s {
     uint64_t magic;
     int device;
+    // separate targets (fmmhp_plan_create_targets): points [0, n_src) are the sources, the rest
+    // target-only; 0 when sources are the targets.  Evaluation pads the charges with zeros and
+    // keeps the targets' potentials.
+    int64_t n_src = 0;
+    double *qpad = nullptr, *phipad = nullptr;  // [cap][n] (x2 for complex charges), [cap][n][2]
+    int pad_cap = 0;
     int p_req, leaf_size, max_level;
     double lambda_re, lambda_im;
     std::vector<fmmhp::cplx> Zs;  // impedance of each instance

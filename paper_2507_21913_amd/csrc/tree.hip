@@ -169,7 +169,7 @@ static fmmhp_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n, h
 // ---------------------------------------------------------------------------------------------
 struct BBox {
     double xmin, xmax, ymax;
-    int bad;        // non-finite coordinate or y <= 0
+    int bad;        // non-finite coordinate, or y <= 0 (a source) or y < 0 (a target-only point)
     int img_bad;    // image arrays not equal to (x, -y)
     int pad;
 };
@@ -181,9 +181,11 @@ struct Chunk {
 };
 constexpr int64_t kChunk = 4096;
 
+// Points from src_end on are target-only (no charge): y = 0 is allowed for them.
 __global__ __launch_bounds__(256) void k_bbox(const double *__restrict__ x, const double *__restrict__ y,
                                               const double *__restrict__ ix, const double *__restrict__ iy,
-                                              const Chunk *__restrict__ chunks, BBox *__restrict__ part) {
+                                              int64_t src_end, const Chunk *__restrict__ chunks,
+                                              BBox *__restrict__ part) {
     __shared__ double s0[256], s1[256], s2[256];
     __shared__ int s3[256], s4[256];
     const Chunk ch = chunks[blockIdx.x];
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(256) void k_bbox(const double *__restrict__ x, cons
     for (int64_t i = ch.start + threadIdx.x; i < ch.end; i += 256) {
         const double a = x[i], b = y[i];
         if (!isfinite(a) || !isfinite(b)) bad |= 1;
-        else if (!(b > 0.0)) bad |= 2;
+        else if (!(b > 0.0) && !(i >= src_end && b == 0.0)) bad |= 2;
         xmin = fmin(xmin, a);
         xmax = fmax(xmax, a);
         ymax = fmax(ymax, b);
@@ -689,7 +691,8 @@ __global__ void k_lists(TreeView t, int nbox, int32_t *__restrict__ cnt /* [4][n
 // Driver
 // ---------------------------------------------------------------------------------------------
 fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, const double *x, const double *y,
-                        const double *img_x, const double *img_y, int leaf_size, int max_level, hipStream_t s) {
+                        const double *img_x, const double *img_y, int64_t src_end, int leaf_size, int max_level,
+                        hipStream_t s) {
     Scratch sc(s);
     const int64_t n = inst_off[n_inst];
     T.n = n;
@@ -708,7 +711,7 @@ fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, 
     // Root squares from device reductions
     BBox *part = nullptr;
     FMMHP_CHECK(sc.get(&part, nch, "bbox partials"));
-    hipLaunchKernelGGL(k_bbox, dim3(nch), dim3(256), 0, s, x, y, img_x, img_y, chunks, part);
+    hipLaunchKernelGGL(k_bbox, dim3(nch), dim3(256), 0, s, x, y, img_x, img_y, src_end, chunks, part);
     FMMHP_HIP(hipGetLastError());
     std::vector<BBox> hp(nch);
     FMMHP_HIP(hipMemcpyAsync(hp.data(), part, nch * sizeof(BBox), hipMemcpyDeviceToHost, s));
@@ -729,7 +732,8 @@ fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, 
         return FMMHP_EINVAL;
     }
     if (bad & 2) {
-        set_error("a point has y <= 0; sources and targets must lie in the open upper half plane");
+        set_error("a source has y <= 0 or a target has y < 0: sources lie in the open upper half plane, "
+                  "targets in the closed one");
         return FMMHP_EDOMAIN;
     }
     if (img_bad) {

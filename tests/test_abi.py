@@ -59,6 +59,21 @@ def test_plan_create_validation():
     assert "options" in L.fmmhp_last_error_message().decode()
 
 
+def test_plan_create_targets_validation():
+    L = F.lib()
+    h = ctypes.c_void_p()
+    good = F.Opts(20, 40, 0, 0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    f = L.fmmhp_plan_create_targets
+    assert f(10, fake, fake, 10, fake, fake, 1.0, 0.0, ctypes.byref(good), None, None) == 1  # NULL plan_out
+    for ns, nt in ((0, 10), (10, 0), (1 << 30, 1 << 30)):
+        assert f(ns, fake, fake, nt, fake, fake, 1.0, 0.0, ctypes.byref(good), None, ctypes.byref(h)) == 1
+    assert f(10, fake, fake, 10, None, fake, 1.0, 0.0, ctypes.byref(good), None, ctypes.byref(h)) == 1
+    assert f(10, fake, None, 10, fake, fake, 1.0, 0.0, ctypes.byref(good), None, ctypes.byref(h)) == 1
+    assert f(10, fake, fake, 10, fake, fake, 1.0, -0.5, ctypes.byref(good), None, ctypes.byref(h)) == 2
+    assert h.value is None
+
+
 def test_null_and_dead_plans():
     L = F.lib()
     assert L.fmmhp_eval(None, 1, None, None, None) == 5

@@ -37,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "plain_small", "uniform_1m", "curve_4m", "diff_1m",
-    "batched_forest", "batched_forest_spec", "batched_forest_instance", "example1", "example2", "uniform", "sample_targets",
+    "batched_forest", "batched_forest_spec", "batched_forest_instance", "example1", "example2", "example2_sized", "uniform", "sample_targets",
 ]
 
 
@@ -170,6 +170,17 @@ def example2(n_source: int, n_field_x: int, n_field_y: int):
                          np.linspace(0.0, 4.2, n_field_y), indexing="xy")
     return dict(src_x=sx, src_y=sy, q=q, tgt_x=gx.ravel(), tgt_y=gy.ravel(),
                 impedance=1.0)
+
+
+def example2_sized(n_total: int):
+    """Example 2 with N_field + 8 N_source = n_total, split evenly between sources and field
+    points (the paper fixes only the sum): N_source = n_total // 16 per circle, and a field mesh of
+    about n_total / 2 points whose spacing is the same in x and y on [-4.4, 4.4] x [0, 4.2]."""
+    n_source = max(1, n_total // 16)
+    n_field = max(4, n_total - 8 * n_source)
+    ny = max(2, int(round(np.sqrt(n_field * 4.2 / 8.8))))
+    nx = max(2, n_field // ny)
+    return example2(n_source, nx, ny)
 
 
 def sample_targets(n: int, k: int, seed: int = 12345) -> np.ndarray:
