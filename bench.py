@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
 # (p, leaf size): reported only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
-M2L_TRAFFIC = {("28a59f5918256669", 20, 32): 167.5e6}
+M2L_TRAFFIC = {("79d8e549df1bfeca", 20, 32): 167.1e6}
 
 
 def eval_source_hash() -> str:
@@ -76,6 +76,54 @@ def cpu_baseline(w, k):
     return {"value": k / dt / 1e6, "unit": "Mpts/s", "cores": workers, "kind": "oracle",
             "sample": f"{k} targets x {w.n} sources (direct sum, float64), {dt:.1f} s",
             "extrapolated_full_s": dt * w.n / k}
+
+
+def example2_extra(dev, sizes=(4000, 1 << 16, 1 << 20), p=10, leaf=32, reps=10):
+    """The paper's Example 2 (eight charged circles, a field mesh reaching y = 0) with separate
+    targets: eval time against N_field + 8 N_source at p = 10 (the paper's O(N) timing), and the
+    rel-l2 error against the stored oracle values at N = 4000 for p = 5..30."""
+    import numpy as np
+    import torch
+
+    import paper_2507_21913_amd as F
+    import workloads
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden"))
+    from golden_io import load_example2
+    out = {"p": p, "leaf_size": leaf, "timing": []}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for n_total in sizes:
+        d = workloads.example2_sized(n_total)
+        t = {k: torch.as_tensor(d[k], device=dev) for k in ("src_x", "src_y", "tgt_x", "tgt_y", "q")}
+        plan = F.HalfPlaneFMM.with_targets(t["src_x"], t["src_y"], t["tgt_x"], t["tgt_y"], d["impedance"],
+                                           p=p, leaf_size=leaf)
+        res = torch.empty(d["tgt_x"].size, dtype=torch.complex128, device=dev)
+        for _ in range(2):
+            plan(t["q"], out=res)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            plan(t["q"], out=res)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        n_pts = d["src_x"].size + d["tgt_x"].size
+        out["timing"].append({"n_field_plus_8n_source": n_pts, "n_source": d["src_x"].size,
+                              "n_field": d["tgt_x"].size, "ms": ms, "mpts_s": n_pts / (ms * 1e-3) / 1e6})
+        plan.close()
+    ref = load_example2()
+    if ref is not None:
+        d = workloads.example2_sized(4000)
+        t = {k: torch.as_tensor(d[k], device=dev) for k in ("src_x", "src_y", "tgt_x", "tgt_y", "q")}
+        errs = {}
+        for pp in (5, 10, 15, 20, 25, 30):
+            plan = F.HalfPlaneFMM.with_targets(t["src_x"], t["src_y"], t["tgt_x"], t["tgt_y"], d["impedance"],
+                                               p=pp, leaf_size=leaf)
+            phi = plan(t["q"]).cpu().numpy()
+            plan.close()
+            errs[pp] = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+        out["rel_l2_vs_oracle_n4000"] = errs
+    return out
 
 
 def batched_extra(dev, p, leaf, steps):
@@ -155,9 +203,8 @@ def batched_extra(dev, p, leaf, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported by this "
-              "build (the path has no multi-GPU code; see DESIGN.md for how it would shard)",
-              file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported (the path has "
+              "no multi-GPU code)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -345,6 +392,7 @@ def main():
                           "bwd_over_fwd": (ms_fb - ms) / ms,
                           "outputs": "phi; dl/dq, dl/dx, dl/dy",
                           "bwd_with_dl_dZ_wall_ms": bwd_lambda_ms}
+        res["example2"] = example2_extra(dev)
         if not a.no_batched:
             plan.close()
             del out

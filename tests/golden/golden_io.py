@@ -25,6 +25,20 @@ def forest_path() -> str:
     return os.path.join(HERE, "batched_forest_direct_sample.txt")
 
 
+def example2_path() -> str:
+    return os.path.join(HERE, "example2_4000_direct.txt")
+
+
+def load_example2():
+    """complex values of the Example 2 direct sum at every field point (N_field + 8 N_source =
+    4000), or None if absent."""
+    p = example2_path()
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return a[:, 1] + 1j * a[:, 2]
+
+
 def load(name: str):
     """(indices, complex values) from a stored potential file, or None if absent."""
     p = path_for(name)

@@ -5,7 +5,7 @@ Calls only the CPU oracle (``oracle.direct``, ``oracle.grad``) and the seeded ge
 targets against ALL sources, written as text (index, Re phi, Im phi); for the differentiation
 workload also the direct-sum gradients at a sample of indices (index, dl/dq, dl/dx, dl/dy).
 
-    python tests/golden/make_golden.py [name ... | grad:name ... | forest]
+    python tests/golden/make_golden.py [name ... | grad:name ... | forest | example2]
 
 The readers (load, load_grad, load_forest) live in golden_io.py, which imports no oracle code.
 """
@@ -99,11 +99,29 @@ def write_forest() -> str:
     return p
 
 
+def write_example2() -> str:
+    """Example 2 of Section 5 with N_field + 8 N_source = 4000: the direct sum at every field point."""
+    from golden_io import example2_path
+    d = workloads.example2_sized(4000)
+    t0 = time.time()
+    phi = D.potential(d["src_x"], d["src_y"], d["q"], d["impedance"], xt=d["tgt_x"], yt=d["tgt_y"])
+    p = example2_path()
+    with open(p, "w") as f:
+        f.write(f"# oracle direct sum, Example 2 (N_field + 8 N_source = 4000: {d['src_x'].size} sources, "
+                f"{d['tgt_x'].size} field points, impedance {d['impedance']}); columns: target index re im\n")
+        for i, v in enumerate(phi):
+            f.write(f"{i} {v.real:.17e} {v.imag:.17e}\n")
+    print(f"example2: {time.time() - t0:.1f} s -> {p}", flush=True)
+    return p
+
+
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN] + ["forest"]):
+    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN] + ["forest", "example2"]):
         if name.startswith("grad:"):
             write_grad(name[5:])
         elif name == "forest":
             write_forest()
+        elif name == "example2":
+            write_example2()
         else:
             write(name)
