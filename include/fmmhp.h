@@ -208,6 +208,22 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
 fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
                                 hipStream_t stream);
 
+/* The field of one real charge vector: the potential and its gradient at the targets (every point,
+ * or the separate targets of fmmhp_plan_create_targets), for field and boundary-integral uses of the
+ * potential (the paper's introduction and conclusion).  The gradient comes from the same expansions
+ * differentiated in the target: the far field H' of the local expansions, d_x log|r - r'| = (x -
+ * x') / |r - r'|^2 and alike in the near field, and d_x I_0 = i I_1, d_y I_0 = -I_1 for the reaction
+ * term (eq. (integralrecursion), n = 1).
+ *
+ *   q              [device] [n_src] real charges (n_src = n for fmmhp_plan_create plans)
+ *   phi            [device] [n_tgt][2] complex potential
+ *   grad_x, grad_y [device] [n_tgt][2] complex d phi / d x and d phi / d y at the targets
+ *
+ * A target that coincides with a source skips that source's free-space term in both.  Asynchronous
+ * on stream. */
+fmmhp_status fmmhp_eval_field(fmmhp_plan_t plan, const double *q, double *phi, double *grad_x, double *grad_y,
+                              hipStream_t stream);
+
 /* Adjoint of fmmhp_eval for one real charge vector: gradients of a real loss l of phi with respect
  * to the charges, the point positions and the impedance (the reverse-mode step of phi = A q; the
  * paper's Green's function, eqs. (1.2) and (reactdecomposition), differentiated).

@@ -175,6 +175,18 @@ def _run(kind, xs, ys, C, Z, xt, yt, workers, target_block=8, chunk=1 << 14):
     return np.concatenate(parts, axis=-1)
 
 
+def field_at(xs, ys, q, Z, xt, yt, workers=None):
+    """(d_x phi, d_y phi) at separate targets (xt, yt), y >= 0, for real or complex charges q [ns]:
+    the target-side kernel derivatives above summed over all sources, over a process pool."""
+    xs = np.ascontiguousarray(xs, dtype=np.float64)
+    ys = np.ascontiguousarray(ys, dtype=np.float64)
+    xt = np.ascontiguousarray(xt, dtype=np.float64)
+    yt = np.ascontiguousarray(yt, dtype=np.float64)
+    C = np.ascontiguousarray(np.asarray(q, dtype=np.complex128)[None, :])
+    g = _run("grad", xs, ys, C, Z, xt, yt, workers)
+    return g[0, 0], g[1, 0]
+
+
 def sampled_gradients(xs, ys, q, Z, g, idx, workers=None, want_Z=False):
     """direct_gradients at the indices idx against ALL sources, over a process pool.  grad_Z
     (an all-pairs sum) only when want_Z."""

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "fmmhp_eval": [_P, _INT, _P, _P, _P],
     "fmmhp_eval_complex": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
+    "fmmhp_eval_field": [_P, _P, _P, _P, _P, _P],
     "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
     "fmmhp_plan_export_tree": [_P] + [_P] * 18,
     "fmmhp_plan_destroy": [_P],
@@ -404,6 +405,21 @@ class HalfPlaneFMM:
             out.copy_(phi.reshape(out.shape))
             return out
         return phi[0] if squeeze else phi
+
+    def field(self, q: torch.Tensor):
+        """(phi, d phi/dx, d phi/dy) at the targets for one real charge vector q [N]: three
+        complex128 tensors [n_out]."""
+        if not isinstance(q, torch.Tensor) or not q.is_cuda or q.is_complex():
+            raise TypeError("q must be a real GPU tensor")
+        if q.numel() != self.n:
+            raise ValueError(f"q has {q.numel()} points, plan has {self.n}")
+        qd = q.reshape(-1).to(torch.float64).contiguous()
+        raw = torch.empty((3, self.n_out, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check("fmmhp_eval_field", lib().fmmhp_eval_field(self._plan, qd.data_ptr(), raw[0].data_ptr(),
+                                                               raw[1].data_ptr(), raw[2].data_ptr(), _stream()))
+        c = torch.view_as_complex(raw)
+        return c[0], c[1], c[2]
 
     def backward(self, q: torch.Tensor, grad_phi: torch.Tensor, want_q=True, want_x=True,
                  want_y=True, want_lambda=True) -> dict:

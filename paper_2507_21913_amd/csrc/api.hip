@@ -307,6 +307,43 @@ fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, d
     return run_eval_complex(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
+// pp [n][2] -> out [n - ns][2] (one vector)
+__global__ void k_take_targets2(const double *__restrict__ pp, int64_t ns, int64_t n, double *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * (n - ns)) return;
+    out[t] = pp[2 * ns + t];
+}
+
+fmmhp_status fmmhp_eval_field(fmmhp_plan_t plan, const double *q, double *phi, double *grad_x, double *grad_y,
+                              hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!q || !phi || !grad_x || !grad_y) {
+        set_error("q, phi, grad_x and grad_y must be non-NULL");
+        return FMMHP_EINVAL;
+    }
+    if (plan->n_src == 0)
+        return run_field(plan->arena, plan->tree, plan->sched, q, phi, (cplx *)grad_x, (cplx *)grad_y, stream);
+    // separate targets: charges padded to all tree points, the targets' values kept
+    const int64_t n = plan->tree.n, ns = plan->n_src;
+    if (plan->pad_cap < 1) {
+        FMMHP_CHECK(plan->arena.alloc_n(&plan->qpad, (size_t)n * 2, "padded charges"));
+        FMMHP_CHECK(plan->arena.alloc_n(&plan->phipad, (size_t)n * 2, "potentials at all points"));
+        plan->pad_cap = 1;
+    }
+    if (!plan->gpad) FMMHP_CHECK(plan->arena.alloc_n(&plan->gpad, (size_t)n * 4, "gradients at all points"));
+    hipLaunchKernelGGL(k_pad_charges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, q, ns, n, 1, 1,
+                       plan->qpad);
+    FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(run_field(plan->arena, plan->tree, plan->sched, plan->qpad, plan->phipad, (cplx *)plan->gpad,
+                          (cplx *)(plan->gpad + 2 * n), stream));
+    const dim3 g((unsigned)((2 * (n - ns) + 255) / 256));
+    hipLaunchKernelGGL(k_take_targets2, g, dim3(256), 0, stream, plan->phipad, ns, n, phi);
+    hipLaunchKernelGGL(k_take_targets2, g, dim3(256), 0, stream, plan->gpad, ns, n, grad_x);
+    hipLaunchKernelGGL(k_take_targets2, g, dim3(256), 0, stream, plan->gpad + 2 * n, ns, n, grad_y);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
+}
+
 fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
                             double *grad_x, double *grad_y, double *grad_lambda, hipStream_t stream) {
     FMMHP_CHECK(check_plan(plan));

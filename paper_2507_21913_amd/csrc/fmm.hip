@@ -2444,6 +2444,18 @@ fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, co
     return FMMHP_OK;
 }
 
+// Potential and gradient (d_x phi, d_y phi) of one real charge vector at every point, caller order:
+// the forward pass in its gradient mode (the same expansions, differentiated in the target).
+fmmhp_status run_field(Arena &A, const Tree &T, Sched &S, const double *q, double *phi, cplx *gx, cplx *gy,
+                       hipStream_t s) {
+    FMMHP_CHECK(ensure_bwd(A, T, S));  // near-field gradient sums
+    PassOut po;
+    po.phi = phi;
+    po.gx = gx;
+    po.gy = gy;
+    return run_pass<kPhiGrad, 1>(T, S, q, po, s);
+}
+
 fmmhp_status collect_phase_times(Sched &S) {
     if (!S.events) return FMMHP_OK;
     auto &ev = *S.events;

@@ -218,6 +218,8 @@ fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double 
 fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                               hipStream_t stream);
 
+fmmhp_status run_field(Arena &A, const Tree &T, Sched &S, const double *q, double *phi, cplx *gx, cplx *gy,
+                       hipStream_t stream);
 fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
                           double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t stream);
 
@@ -243,6 +245,7 @@ struct fmmhp_plan_s {
     // keeps the targets' potentials.
     int64_t n_src = 0;
     double *qpad = nullptr, *phipad = nullptr;  // [cap][n] (x2 for complex charges), [cap][n][2]
+    double *gpad = nullptr;                     // [2][n][2] gradients at all points (fmmhp_eval_field)
     int pad_cap = 0;
     int p_req, leaf_size, max_level;
     double lambda_re, lambda_im;

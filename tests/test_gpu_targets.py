@@ -1,8 +1,8 @@
 """GPU parity of plans with separate targets (fmmhp_plan_create_targets) against the oracle's direct
 sum at the same targets: the paper's Example 2 (Section 5; eight charged unit circles, a field
 mesh on [-4.4, 4.4] x [0, 4.2] that includes y = 0), its error decay in p, targets that coincide
-with sources, a complex impedance, several and complex charge vectors.  Tolerance: rel-l2 1e-10
-at p = 30.
+with sources, a complex impedance, several and complex charge vectors, and the field (potential and
+gradient, fmmhp_eval_field).  Tolerance: rel-l2 1e-10 at p = 30.
 """
 import numpy as np
 import pytest
@@ -98,3 +98,36 @@ def test_multivector_and_complex_charges():
     with pytest.raises(F.FMMHPError):
         plan.backward(_t(Q[0]), _t(np.ones(ns, dtype=complex)))
     plan.close()
+
+
+@pytest.mark.parametrize("Z", [1.0, 1.0 + 0.5j])
+def test_field_at_targets_vs_oracle(ex2, Z):
+    """fmmhp_eval_field on a plan with separate targets: potential and gradient at the Example 2
+    mesh (boundary row included), and the Robin condition d_y phi + Z phi = 0 on y = 0."""
+    from oracle import grad as GR
+    plan = _plan(ex2, 30, Z=Z)
+    phi, gx, gy = (t.cpu().numpy() for t in plan.field(_t(ex2["q"])))
+    plan.close()
+    ref = ex2["ref"] if Z == 1.0 else D.potential(ex2["src_x"], ex2["src_y"], ex2["q"], Z, xt=ex2["tgt_x"],
+                                                  yt=ex2["tgt_y"], workers=8)
+    rx, ry = GR.field_at(ex2["src_x"], ex2["src_y"], ex2["q"], Z, ex2["tgt_x"], ex2["tgt_y"], workers=8)
+    e = (D.rel_l2(phi, ref), D.rel_l2(gx, rx), D.rel_l2(gy, ry))
+    print(f"Z={Z} field at Example 2 mesh: rel-l2 phi {e[0]:.2e} d_x {e[1]:.2e} d_y {e[2]:.2e}", flush=True)
+    assert max(e) < 1e-10
+    b = ex2["tgt_y"] == 0.0
+    res = np.abs(gy[b] + complex(Z) * phi[b])
+    assert np.max(res) < 1e-9 * np.max(np.abs(gy[b]))
+
+
+def test_field_sources_as_targets_vs_oracle():
+    from oracle import grad as GR
+    rng = np.random.default_rng(21)
+    n = 3000
+    x, y, q = rng.uniform(0, 1, n), rng.uniform(0.01, 1.01, n), rng.uniform(-1, 1, n)
+    plan = F.HalfPlaneFMM(_t(x), _t(y), 1.0 + 0.5j, p=30, leaf_size=20)
+    phi, gx, gy = (t.cpu().numpy() for t in plan.field(_t(q)))
+    ref_phi = plan(_t(q)).cpu().numpy()
+    plan.close()
+    rx, ry = GR.potential_gradient(x, y, q, 1.0 + 0.5j)
+    assert np.array_equal(phi, ref_phi) or D.rel_l2(phi, ref_phi) < 1e-14
+    assert D.rel_l2(gx, rx) < 1e-10 and D.rel_l2(gy, ry) < 1e-10

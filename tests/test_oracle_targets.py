@@ -6,7 +6,9 @@
   term of G does), checked by one-sided second-order differences in y;
 * for a real impedance its imaginary part equals the exact O(N) closed form at every target;
 * the Example 2 geometry: eight unit circles, the lowest charge 0.01 above the boundary, total
-  charge 2 pi per circle.
+  charge 2 pi per circle;
+* the field (gradient of the potential) at separate targets against differences of the potential,
+  and the Robin condition d_y phi + Z phi = 0 that it satisfies exactly on the boundary.
 """
 import numpy as np
 import pytest
@@ -75,3 +77,31 @@ def test_example2_geometry():
     assert d["tgt_x"].min() == pytest.approx(-4.4) and d["tgt_x"].max() == pytest.approx(4.4)
     s = workloads.example2_sized(4000)
     assert s["src_x"].size + s["tgt_x"].size <= 4000 and s["src_x"].size == 8 * 250
+
+
+@pytest.mark.parametrize("Z", [1.0, 0.7 + 0.4j])
+def test_field_at_targets_vs_differences(Z):
+    """The oracle's field at separate targets (grad.field_at) against central differences of its
+    direct-sum potential (one-sided in y on the boundary)."""
+    from oracle import grad as GR
+    xs, ys, q = _sources(40, 12)
+    rng = np.random.default_rng(13)
+    xt = rng.uniform(-1, 1, 10)
+    yt = np.concatenate([np.zeros(3), rng.uniform(0.05, 1.0, 7)])
+    gx, gy = GR.field_at(xs, ys, q, Z, xt, yt, workers=1)
+    h = 1e-5
+
+    def phi(dx, dy):
+        return D.potential(xs, ys, q, Z, xt=xt + dx, yt=yt + dy, workers=1)
+
+    fdx = (phi(h, 0.0) - phi(-h, 0.0)) / (2 * h)
+    inner = yt > 0
+    fdy = np.empty_like(fdx)
+    fdy[inner] = ((phi(0.0, h) - phi(0.0, -h)) / (2 * h))[inner]
+    fdy[~inner] = ((-3 * phi(0.0, 0.0) + 4 * phi(0.0, h) - phi(0.0, 2 * h)) / (2 * h))[~inner]
+    scale = 1.0 + np.abs(gx) + np.abs(gy)
+    assert np.all(np.abs(fdx - gx) <= 1e-6 * scale)
+    assert np.all(np.abs(fdy - gy) <= 1e-6 * scale)
+    # on the boundary the field satisfies the Robin condition d_y phi + Z phi = 0 exactly
+    p0 = phi(0.0, 0.0)
+    assert np.all(np.abs(gy[~inner] + complex(Z) * p0[~inner]) <= 1e-12 * (np.abs(gy[~inner]) + 1.0))
