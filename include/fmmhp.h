@@ -65,7 +65,8 @@ typedef struct {
                        fmmhp_plan_info reports the order actually used. */
     int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
     int max_level;  /* deepest tree level, 1..30 (1..27 for a forest); 0 selects the maximum */
-    unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH and FMMHP_FLAG_M2L_FP32 */
+    unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH, FMMHP_FLAG_M2L_FP32 and one of
+                       FMMHP_FLAG_DIRICHLET, FMMHP_FLAG_NEUMANN */
     /* Launch shape of the near field (the U-list sums), which runs beside the far-field kernels on
      * a bounded grid.  Neither changes what is computed beyond rounding; fmmhp_tune picks both by
      * timing.  0 selects the default for the plan's p. */
@@ -85,6 +86,16 @@ typedef struct {
  * stays FP64.  Expect a relative error of ~1e-7 on top of the truncation error: for tolerances of
  * 1e-6, not 1e-10. */
 #define FMMHP_FLAG_M2L_FP32 2u
+
+/* The half-plane Green's functions of eq. (ddd1.2) instead of the Robin one:
+ *   Dirichlet  G = -(1/2pi) ln|r - r'| + (1/2pi) ln|r - r'_im|   (G = 0 on y = 0; the Z -> infinity limit)
+ *   Neumann    G = -(1/2pi) ln|r - r'| - (1/2pi) ln|r - r'_im|   (d_y G = 0 on y = 0)
+ * The same tree and expansions without the reaction part (no reaction M2L, near-field reaction
+ * sums or surface term); the impedance arguments are ignored (not checked), the potential is real
+ * (its imaginary part is zero) and fmmhp_backward reports a zero impedance gradient.  At most one of
+ * the two may be set. */
+#define FMMHP_FLAG_DIRICHLET 4u
+#define FMMHP_FLAG_NEUMANN 8u
 
 typedef struct {
     int64_t n;              /* number of points */

@@ -22,33 +22,33 @@ from .kernel import green, reaction_I0, TWO_PI
 _SRC = {}
 
 
-def _block(xt, yt, xs, ys, q, Z, chunk):
+def _block(xt, yt, xs, ys, q, Z, chunk, bc="robin"):
     """phi for a block of targets against all sources, q shape [n_vec, ns]."""
     nv = q.shape[0]
     acc = np.zeros((nv, xt.shape[0]), dtype=np.complex128)
     for s0 in range(0, xs.shape[0], chunk):
         s1 = min(xs.shape[0], s0 + chunk)
-        G = green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z)
+        G = green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z, bc=bc)
         acc += q[:, s0:s1] @ G.T
     return acc
 
 
-def _init_worker(xs, ys, q, Z):
-    _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"] = xs, ys, q, Z
+def _init_worker(xs, ys, q, Z, bc="robin"):
+    _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"], _SRC["bc"] = xs, ys, q, Z, bc
 
 
 def _work(args):
     xt, yt, chunk = args
-    return _block(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"], chunk)
+    return _block(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"], chunk, _SRC["bc"])
 
 
 def potential(xs, ys, q, Z, xt=None, yt=None, workers: int | None = None,
-              target_block: int = 16, chunk: int = 1 << 16):
+              target_block: int = 16, chunk: int = 1 << 16, bc: str = "robin"):
     """Direct-sum potential at targets (default: targets = sources).
 
     xs, ys : [ns] float64 source coordinates (ys > 0)
     q      : [ns] or [n_vec, ns] charges (real or complex)
-    Z      : complex impedance
+    Z      : complex impedance (ignored for bc = "dirichlet" / "neumann", eq. (ddd1.2))
     Returns complex128 [nt] (or [n_vec, nt]).
     """
     xs = np.ascontiguousarray(xs, dtype=np.float64)
@@ -67,16 +67,16 @@ def potential(xs, ys, q, Z, xt=None, yt=None, workers: int | None = None,
     blocks = [(xt[i:i + target_block], yt[i:i + target_block], chunk)
               for i in range(0, nt, target_block)]
     if workers <= 1 or len(blocks) <= 1:
-        parts = [_block(b[0], b[1], xs, ys, q2, complex(Z), chunk) for b in blocks]
+        parts = [_block(b[0], b[1], xs, ys, q2, complex(Z), chunk, bc) for b in blocks]
     else:
         with ProcessPoolExecutor(max_workers=workers, initializer=_init_worker,
-                                 initargs=(xs, ys, q2, complex(Z))) as ex:
+                                 initargs=(xs, ys, q2, complex(Z), bc)) as ex:
             parts = list(ex.map(_work, blocks))
     out = np.concatenate(parts, axis=1) if parts else np.zeros((q2.shape[0], 0), np.complex128)
     return out[0] if squeeze else out
 
 
-def potential_loops(xs, ys, q, Z, xt=None, yt=None):
+def potential_loops(xs, ys, q, Z, xt=None, yt=None, bc: str = "robin"):
     """Pure-Python double loop over (target, source) pairs; small inputs only.
 
     Written term by term from eqs. (1.2) and (reactioncomp1) as an independent
@@ -93,7 +93,13 @@ def potential_loops(xs, ys, q, Z, xt=None, yt=None):
             dy = float(yt[i]) - float(ys[j])
             if not (dx == 0.0 and dy == 0.0):
                 s += -float(q[j]) * math.log(math.hypot(dx, dy)) / TWO_PI
-            s += float(q[j]) * math.log(math.hypot(dx, float(yt[i]) + float(ys[j]))) / TWO_PI
+            image = float(q[j]) * math.log(math.hypot(dx, float(yt[i]) + float(ys[j]))) / TWO_PI
+            if bc == "neumann":
+                s -= image
+                continue
+            s += image
+            if bc == "dirichlet":
+                continue
             s += float(q[j]) * complex(reaction_I0(dx, float(yt[i]) + float(ys[j]), Z)
                                        + reaction_I0(-dx, float(yt[i]) + float(ys[j]), Z))
         out[i] = s

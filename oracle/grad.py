@@ -30,9 +30,9 @@ import numpy as np
 from .kernel import reaction_I0, reaction_In, green, TWO_PI
 
 
-def _grad_green(xt, yt, xs, ys, Z):
+def _grad_green(xt, yt, xs, ys, Z, bc="robin"):
     """(d_x G, d_y G) at the target, arrays broadcasting like ``green``; free term skipped
-    where r_t == r_s."""
+    where r_t == r_s.  bc = "dirichlet" / "neumann": the kernels of eq. (ddd1.2)."""
     xt = np.asarray(xt, dtype=np.float64)
     yt = np.asarray(yt, dtype=np.float64)
     dx = xt - xs
@@ -42,8 +42,11 @@ def _grad_green(xt, yt, xs, ys, Z):
     ri2 = dx * dx + Y * Y
     same = r2 == 0.0
     inv = np.where(same, 0.0, 1.0 / np.where(same, 1.0, r2))
-    gx = -dx * inv / TWO_PI + dx / ri2 / TWO_PI
-    gy = -dy * inv / TWO_PI + Y / ri2 / TWO_PI
+    isg = -1.0 if bc == "neumann" else 1.0
+    gx = -dx * inv / TWO_PI + isg * dx / ri2 / TWO_PI
+    gy = -dy * inv / TWO_PI + isg * Y / ri2 / TWO_PI
+    if bc != "robin":
+        return gx.astype(np.complex128), gy.astype(np.complex128)
     Ip = reaction_In(1, dx, Y, Z)[1]
     Im = reaction_In(1, -dx, Y, Z)[1]
     gx = gx + 1j * Ip - 1j * Im
@@ -127,13 +130,13 @@ def potential_dZ(xs, ys, q, Z, idx=None):
 _SRC = {}
 
 
-def _grad_block(xt, yt, xs, ys, C, Z, chunk):
+def _grad_block(xt, yt, xs, ys, C, Z, chunk, bc="robin"):
     """[2, n_vec, len(xt)] gradient of Phi[C_v] at a block of targets."""
     nv = C.shape[0]
     acc = np.zeros((2, nv, xt.shape[0]), dtype=np.complex128)
     for s0 in range(0, xs.shape[0], chunk):
         s1 = min(xs.shape[0], s0 + chunk)
-        kx, ky = _grad_green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z)
+        kx, ky = _grad_green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z, bc)
         acc[0] += C[:, s0:s1] @ kx.T
         acc[1] += C[:, s0:s1] @ ky.T
     return acc
@@ -148,17 +151,18 @@ def _dZ_block(xt, yt, xs, ys, C, Z, chunk):
     return acc
 
 
-def _init_worker(xs, ys, C, Z):
-    _SRC.update(xs=xs, ys=ys, C=C, Z=Z)
+def _init_worker(xs, ys, C, Z, bc="robin"):
+    _SRC.update(xs=xs, ys=ys, C=C, Z=Z, bc=bc)
 
 
 def _work(args):
     kind, xt, yt, chunk = args
-    f = _grad_block if kind == "grad" else _dZ_block
-    return f(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["C"], _SRC["Z"], chunk)
+    if kind == "grad":
+        return _grad_block(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["C"], _SRC["Z"], chunk, _SRC["bc"])
+    return _dZ_block(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["C"], _SRC["Z"], chunk)
 
 
-def _run(kind, xs, ys, C, Z, xt, yt, workers, target_block=8, chunk=1 << 14):
+def _run(kind, xs, ys, C, Z, xt, yt, workers, target_block=8, chunk=1 << 14, bc="robin"):
     import os
     from concurrent.futures import ProcessPoolExecutor
     if workers is None:
@@ -166,16 +170,16 @@ def _run(kind, xs, ys, C, Z, xt, yt, workers, target_block=8, chunk=1 << 14):
     blocks = [(kind, xt[i:i + target_block], yt[i:i + target_block], chunk)
               for i in range(0, xt.shape[0], target_block)]
     if workers <= 1 or len(blocks) <= 1:
-        _init_worker(xs, ys, C, complex(Z))
+        _init_worker(xs, ys, C, complex(Z), bc)
         parts = [_work(b) for b in blocks]
     else:
         with ProcessPoolExecutor(max_workers=workers, initializer=_init_worker,
-                                 initargs=(xs, ys, C, complex(Z))) as ex:
+                                 initargs=(xs, ys, C, complex(Z), bc)) as ex:
             parts = list(ex.map(_work, blocks))
     return np.concatenate(parts, axis=-1)
 
 
-def field_at(xs, ys, q, Z, xt, yt, workers=None):
+def field_at(xs, ys, q, Z, xt, yt, workers=None, bc="robin"):
     """(d_x phi, d_y phi) at separate targets (xt, yt), y >= 0, for real or complex charges q [ns]:
     the target-side kernel derivatives above summed over all sources, over a process pool."""
     xs = np.ascontiguousarray(xs, dtype=np.float64)
@@ -183,7 +187,7 @@ def field_at(xs, ys, q, Z, xt, yt, workers=None):
     xt = np.ascontiguousarray(xt, dtype=np.float64)
     yt = np.ascontiguousarray(yt, dtype=np.float64)
     C = np.ascontiguousarray(np.asarray(q, dtype=np.complex128)[None, :])
-    g = _run("grad", xs, ys, C, Z, xt, yt, workers)
+    g = _run("grad", xs, ys, C, Z, xt, yt, workers, bc=bc)
     return g[0, 0], g[1, 0]
 
 

@@ -63,11 +63,13 @@ def reaction_GZ(X, Y, Z):
     return reaction_I0(X, Y, Z) + reaction_I0(-np.asarray(X, dtype=np.float64), Y, Z)
 
 
-def green(xt, yt, xs, ys, Z, skip_self: bool = True):
+def green(xt, yt, xs, ys, Z, skip_self: bool = True, bc: str = "robin"):
     """Full Green's function G(r_t, r_s) (eq. (ddGreensfunimp)), broadcasting.
 
     With skip_self the free-space log term is dropped where r_t == r_s bitwise
     (the j != i rule of eq. (1.2)); the image and reaction terms are kept.
+    bc = "dirichlet" / "neumann" gives the half-plane functions of eq. (ddd1.2)
+    instead: no reaction term, the image log term with + / - (Z is ignored).
     """
     xt = np.asarray(xt, dtype=np.float64)
     yt = np.asarray(yt, dtype=np.float64)
@@ -82,6 +84,12 @@ def green(xt, yt, xs, ys, Z, skip_self: bool = True):
     if skip_self:
         free = np.where(r2 == 0.0, 0.0, free)
     image = np.log(r2_im) / (2.0 * TWO_PI)
+    if bc == "dirichlet":
+        return free + image
+    if bc == "neumann":
+        return free - image
+    if bc != "robin":
+        raise ValueError(f"unknown boundary condition {bc!r}")
     return free + image + reaction_GZ(dx, yt + ys, Z)
 
 

@@ -27,6 +27,15 @@ STATUS = {0: "FMMHP_OK", 1: "FMMHP_EINVAL", 2: "FMMHP_EDOMAIN", 3: "FMMHP_ENOMEM
 MAX_P = 40
 FLAG_GRAPH = 1   # fmmhp_opts.flags: record evaluations into a HIP graph and replay them
 FLAG_M2L_FP32 = 2  # fmmhp_opts.flags: upper-source M2L on the FP32 matrix cores (~1e-7 relative)
+FLAG_DIRICHLET = 4  # fmmhp_opts.flags: Dirichlet half-plane kernel (eq. (ddd1.2), image term +)
+FLAG_NEUMANN = 8    # fmmhp_opts.flags: Neumann half-plane kernel (eq. (ddd1.2), image term -)
+_BC_FLAGS = {"robin": 0, "dirichlet": FLAG_DIRICHLET, "neumann": FLAG_NEUMANN}
+
+
+def _bc_flag(bc: str) -> int:
+    if bc not in _BC_FLAGS:
+        raise ValueError(f"bc must be one of {sorted(_BC_FLAGS)}")
+    return _BC_FLAGS[bc]
 
 
 class FMMHPError(RuntimeError):
@@ -280,10 +289,12 @@ class HalfPlaneFMM:
                 stream: run under ``torch.cuda.stream(...)``)
     m2l_fp32    run the upper-source M2L on the FP32 matrix cores (relative error ~1e-7)
     near_walk, near_groups   near-field launch shape (0: default; see fmmhp_opts)
+    bc          "robin" (the impedance condition), "dirichlet" or "neumann" (eq. (ddd1.2); the
+                impedance is then ignored)
     """
 
     def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False,
-                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0):
+                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0, bc="robin"):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         self.n = int(x.shape[0])
@@ -291,7 +302,7 @@ class HalfPlaneFMM:
         self._x, self._y = x, y
         lr, li = _split_impedance(impedance)
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             if pass_images:
@@ -307,7 +318,7 @@ class HalfPlaneFMM:
 
     @classmethod
     def with_targets(cls, xs, ys, xt, yt, impedance, p=20, leaf_size=40, max_level=0, graph=False,
-                     m2l_fp32=False, near_walk=0, near_groups=0):
+                     m2l_fp32=False, near_walk=0, near_groups=0, bc="robin"):
         """A plan whose potential is evaluated at separate targets (xt, yt), y >= 0: calling it
         with charges q [N_src] (or [n_vec, N_src]) returns phi at the N_tgt targets."""
         self = cls.__new__(cls)
@@ -321,7 +332,7 @@ class HalfPlaneFMM:
         self._x, self._y = xs, ys
         lr, li = _split_impedance(impedance)
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             self._plan = fmmhp_plan_create_targets(self.n, xs.data_ptr(), ys.data_ptr(), self.n_out,
@@ -332,7 +343,7 @@ class HalfPlaneFMM:
 
     @classmethod
     def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False,
-                m2l_fp32=False, near_walk=0, near_groups=0):
+                m2l_fp32=False, near_walk=0, near_groups=0, bc="robin"):
         """A forest plan over n_inst independent instances: points offsets[k]..offsets[k+1]-1 of
         (x, y) form instance k with impedance impedances[k].  Evaluation takes charges for all
         points (instance after instance) and runs every instance in the same launches."""
@@ -351,7 +362,7 @@ class HalfPlaneFMM:
         if len(imps) != self.n_inst:
             raise ValueError("one impedance per instance")
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,

@@ -42,6 +42,11 @@ static fmmhp_status check_plan(fmmhp_plan_t p) {
     return FMMHP_OK;
 }
 
+// Dirichlet and Neumann plans ignore the impedance.
+static bool no_impedance(const fmmhp_opts *opts) {
+    return opts && (opts->flags & (FMMHP_FLAG_DIRICHLET | FMMHP_FLAG_NEUMANN)) != 0;
+}
+
 static fmmhp_status check_impedance(double re, double im) {
     if (!isfinite(re) || !isfinite(im)) {
         set_error("impedance is not finite");
@@ -84,9 +89,11 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     if (opts) o = *opts;
     if (o.max_level == 0) o.max_level = lb;
     if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
-        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32)) != 0 || o.near_walk < 0 || o.near_walk > 2 ||
+        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32 | FMMHP_FLAG_DIRICHLET | FMMHP_FLAG_NEUMANN)) != 0 ||
+        (o.flags & FMMHP_FLAG_DIRICHLET && o.flags & FMMHP_FLAG_NEUMANN) || o.near_walk < 0 || o.near_walk > 2 ||
         o.near_groups < 0 || o.near_groups > 16) {
-        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0, 1), "
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0..3, "
+                  "not both 2 and 3), "
                   "near_walk=%d (0..2), near_groups=%d (0..16)",
                   o.p, FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags, o.near_walk, o.near_groups);
         return FMMHP_EINVAL;
@@ -112,6 +119,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
         st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, src_end, o.leaf_size, o.max_level,
                         stream);
     p->sched.m2l_fp32 = (o.flags & FMMHP_FLAG_M2L_FP32) != 0;
+    p->sched.bc = (o.flags & FMMHP_FLAG_DIRICHLET) ? 1 : (o.flags & FMMHP_FLAG_NEUMANN) ? 2 : 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
     if (st == FMMHP_OK) apply_launch_shape(p->sched, o.near_walk, o.near_groups);
     p->sched.use_graph = (o.flags & FMMHP_FLAG_GRAPH) != 0;
@@ -160,9 +168,9 @@ fmmhp_status fmmhp_plan_create(int64_t n, const double *x, const double *y, cons
         set_error("img_x and img_y must both be NULL or both be given");
         return FMMHP_EINVAL;
     }
-    FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
+    if (!no_impedance(opts)) FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
     const int64_t off[2] = {0, n};
-    const cplx Z = mk(lambda_re, lambda_im);
+    const cplx Z = no_impedance(opts) ? mk(1.0, 0.0) : mk(lambda_re, lambda_im);
     return create_plan(1, off, x, y, img_x, img_y, n, &Z, opts, stream, plan_out);
 }
 
@@ -184,7 +192,7 @@ fmmhp_status fmmhp_plan_create_targets(int64_t n_src, const double *xs, const do
         set_error("xs, ys, xt and yt must be non-NULL");
         return FMMHP_EINVAL;
     }
-    FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
+    if (!no_impedance(opts)) FMMHP_CHECK(check_impedance(lambda_re, lambda_im));
     // one point set: the sources, then the targets (the tree is built over both)
     const int64_t n = n_src + n_tgt;
     double *xy = nullptr;
@@ -203,7 +211,7 @@ fmmhp_status fmmhp_plan_create_targets(int64_t n_src, const double *xs, const do
         st = FMMHP_EHIP;
     }
     const int64_t off[2] = {0, n};
-    const cplx Z = mk(lambda_re, lambda_im);
+    const cplx Z = no_impedance(opts) ? mk(1.0, 0.0) : mk(lambda_re, lambda_im);
     if (st == FMMHP_OK) st = create_plan(1, off, xy, xy + n, nullptr, nullptr, n_src, &Z, opts, stream, plan_out);
     (void)hipStreamSynchronize(stream);
     (void)hipFree(xy);
@@ -243,6 +251,10 @@ fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const d
     }
     std::vector<cplx> Zs(n_inst);
     for (int k = 0; k < n_inst; ++k) {
+        if (no_impedance(opts)) {
+            Zs[k] = mk(1.0, 0.0);
+            continue;
+        }
         FMMHP_CHECK(check_impedance(lambda[2 * k], lambda[2 * k + 1]));
         Zs[k] = mk(lambda[2 * k], lambda[2 * k + 1]);
     }
@@ -356,8 +368,10 @@ fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *gr
         return FMMHP_EUNSUPPORTED;
     }
     std::vector<cplx> zsum(plan->tree.n_inst, mk(0.0, 0.0));
+    // Dirichlet and Neumann kernels do not depend on an impedance: its gradient is zero
+    const bool want_z = grad_lambda && plan->sched.bc == 0;
     FMMHP_CHECK(run_backward(plan->arena, plan->tree, plan->sched, q, grad_phi, grad_q, grad_x, grad_y,
-                             grad_lambda ? zsum.data() : nullptr, stream));
+                             want_z ? zsum.data() : nullptr, stream));
     if (grad_lambda) {
         // per instance: dl_c/dZ_k = zsum_k / Z_k;  (dl/dRe Z_k, dl/dIm Z_k) = (Re, -Im) of it
         for (int k = 0; k < plan->tree.n_inst; ++k) {

@@ -615,8 +615,8 @@ __global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restr
                                                  const int32_t *__restrict__ vimg_off,
                                                  const int32_t *__restrict__ vimg_ent, const cplx *__restrict__ TH,
                                                  const cplx *__restrict__ TG, const cplx *__restrict__ Limg,
-                                                 const double *__restrict__ logside, const cplx *__restrict__ W,
-                                                 cplx *__restrict__ Lam) {
+                                                 const double *__restrict__ logside, double isg,
+                                                 const cplx *__restrict__ W, cplx *__restrict__ Lam) {
     constexpr int NTP = m2l_row(PB);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nib * (PB + 1)) return;
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restr
             cfma(aH, th[m], wm);
             if (nloc == 2) cfma(aG, tg[m], wm);
         }
-        if (n == 0) cfma(a0, Limg[is] + mk(ll, 0.0), conj(W[src]));
+        if (n == 0) cfma(a0, Limg[is] + mk(isg * ll, 0.0), conj(W[src]));
     }
     Lam[(int64_t)n * nbox + b] += a0 - aH;
     if (nloc == 2) Lam[(int64_t)(PB + 1) * nbox + (int64_t)n * nbox + b] += a0 - aG;
@@ -687,7 +687,7 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                 const double q = qs[(int64_t)j * nv + v];
                 const double yj = img ? -ys[j] : ys[j];
                 const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
-                const double sgn = img ? 1.0 : -1.0;            // -(1/4pi) upper, +(1/4pi) image
+                const double sgn = img ? ii[inst[b]].isg : -1.0;  // -(1/4pi) upper, +-(1/4pi) image
                 // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
                 out[0] = (sgn * kInv4Pi * q) * clog_(-d);
                 const cplx sig = rho * inv(d);
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                     out[n] = (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
                     pw = pw * sig;
                 }
-                if (img) {
+                if (img && ii[inst[b]].react) {
                     // reaction S2L (eq. (LEcoefficients)) re-expanded in powers of (z - c_b):
                     // lambda_n += i^n n! rho^n q I_n(x_c - x_j, y_c + y_j)  (G: conj of I_n(-X, Y))
                     const double X = cb.re - xs[j], Y = cb.im + ys[j];
@@ -938,6 +938,7 @@ struct LeafArgs {
     double *phi;             // [nv][n][2] potential, caller order (potential modes)
     cplx *gx, *gy;           // [n] gradient, caller order (gradient modes)
     const int2 *u2;          // per U entry: (first point, point count | image << 31) of its source box
+    double isg;              // sign of the image log term: +1 (Robin, Dirichlet), -1 (Neumann)
 };
 
 // Near field, log terms of the U list: one thread per target (sorted order, grid-stride over the
@@ -975,7 +976,8 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
         for (int v = 0; v < NV; ++v) qj[v] = qs[(int64_t)fc.x * NV + v];
         while (true) {
             const int j0 = fc.x, jend = fc.x + (fc.y & 0x7fffffff);
-            const double sg = fc.y < 0 ? 1.0 : -1.0;  // image: + log|r - r_img|, free: - log|r - r'|
+            const double ysg = fc.y < 0 ? 1.0 : -1.0;   // image: y + y', free: y - y'
+            const double sg = fc.y < 0 ? a.isg : -1.0;  // image: +-log|r - r_img|, free: - log|r - r'|
             const bool last = e + 1 >= e1;
             const int jnext = last ? jend - 1 : fn.x;  // the point loaded after this entry's last
             for (int j = j0; j < jend; ++j) {
@@ -984,7 +986,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 double qn[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) qn[v] = qs[(int64_t)jp * NV + v];
-                const double dx = x - pj.x, dy = fma(sg, pj.y, y);  // y - y' or y + y'
+                const double dx = x - pj.x, dy = fma(ysg, pj.y, y);  // y - y' or y + y'
                 const double r2 = fma(dx, dx, dy * dy);
                 // r2 = 0 only for a coincident free pair, skipped (eq. (1.2)), or between two
                 // target-only points on y = 0 (no charge); image distances to sources are positive
@@ -1106,13 +1108,14 @@ __global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
         }
         if (has_phi(MODE)) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (limg[v] - lfree[v]), 0.0);
+            for (int v = 0; v < NV; ++v)
+                a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (a.isg * limg[v] - lfree[v]), 0.0);
         }
         if (has_grad(MODE)) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * (mx[v] - fx[v]), 0.0);
-                a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * (my[v] - fy[v]), 0.0);
+                a.near_gx[(int64_t)v * a.n + i] = mk(kInv2Pi * (a.isg * mx[v] - fx[v]), 0.0);
+                a.near_gy[(int64_t)v * a.n + i] = mk(kInv2Pi * (a.isg * my[v] - fy[v]), 0.0);
             }
             if (a.qc) a.qc[i] = qc;
         }
@@ -1163,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     }
     const int64_t o = a.perm[i];
     cplx E = mk(0.0, 0.0);  // e^{-Z(y + ix)} s (real impedance)
-    if (a.nloc == 1) E = cexp_(-(Zk * mk(y, x))) * a.rank1[(int64_t)v * a.n_inst + k];
+    if (a.nloc == 1 && a.rank1) E = cexp_(-(Zk * mk(y, x))) * a.rank1[(int64_t)v * a.n_inst + k];
     if (has_phi(MODE)) {
         const double2 nr = a.near[(int64_t)v * a.n + i];
         cplx phi;
@@ -1229,13 +1232,13 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
             if (has_grad(MODE)) ud += a.fact[k] * pk;
             pw = pw * tau;
         }
-        const double sgn = (img ? 1.0 : -1.0) * kInv4Pi;
+        const double sgn = (img ? a.ii[a.inst[b]].isg : -1.0) * kInv4Pi;
         H += sgn * u;
         G += sgn * u;
         ud = sgn * (ud * idz);
         Hd += ud;
         Gd += ud;
-        if (img) {
+        if (img && a.ii[a.inst[b]].react) {
             // reaction ME (eq. (truncatedME)) of the image box: sum_n alpha_n I_n(x - x'_c, y - y'_c),
             // alpha_n = rho^n (-i)^n conj(mu_n) = i^n n! rho^n conj(w_n); with K_n = n! rho^n I_n its
             // z-derivative is (1/rho) sum_n i^(n+1) K_(n+1) conj(w_n)
@@ -1561,7 +1564,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     S.Z = Zs[0];
     S.real_Z = true;
     for (int k = 0; k < T.n_inst; ++k) S.real_Z = S.real_Z && Zs[k].im == 0.0;
+    if (S.bc != 0) S.real_Z = true;  // Dirichlet and Neumann kernels are real
     S.nloc = S.real_Z ? 1 : 2;
+    const bool react = S.bc == 0;
+    const double isg = S.bc == 2 ? -1.0 : 1.0;
     const int nbox = T.nbox;
     std::vector<int32_t> level, bx, by, leaf, voff, vent, xoff, binst;
     FMMHP_CHECK(to_host(binst, T.inst, nbox, s));
@@ -1839,7 +1845,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         for (int b = 0; b < nbox; ++b) ls[b] = std::log(ldexp(T.inst_S[binst[b]], -level[b]));  // log(2 rho)
         FMMHP_CHECK(to_dev(A, &S.logside, ls, "log side", s));
         std::vector<InstInfo> ii(T.n_inst);
-        for (int k = 0; k < T.n_inst; ++k) ii[k] = InstInfo{T.inst_xlo[k], T.inst_S[k], Zs[k]};
+        for (int k = 0; k < T.n_inst; ++k) ii[k] = InstInfo{T.inst_xlo[k], T.inst_S[k], Zs[k], isg, react ? 1 : 0, 0};
         FMMHP_CHECK(to_dev(A, &S.inst_info, ii, "instance info", s));
     }
 
@@ -1870,7 +1876,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         for (int dx = -3; dx <= 3; ++dx) {
             const int is = slot_of(dx, dy);
             const C D((double)dx, (double)dy);
-            Limg[is] = cx(i4p * std::log(-D));
+            Limg[is] = cx(isg * i4p * std::log(-D));
         }
     for (size_t bi = 0; bi < blocks.size(); ++bi) {
         const int k = blocks[bi].first, l = blocks[bi].second;
@@ -1884,14 +1890,19 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 const C D((double)dx, (double)dy);
                 const C t = 1.0 / (2.0 * D);
                 const double X = -dx * sl, Y = -dy * sl;
-                pmax = std::max(pmax, std::abs(Zc) * std::hypot(X, Y));
-                reaction_In_scaled_ld(X, Y, Z, rho, NT - 1, K.data());
-                reaction_In_scaled_ld(-X, Y, Z, rho, NT - 1, Km.data());
+                if (react) {
+                    pmax = std::max(pmax, std::abs(Zc) * std::hypot(X, Y));
+                    reaction_In_scaled_ld(X, Y, Z, rho, NT - 1, K.data());
+                    reaction_In_scaled_ld(-X, Y, Z, rho, NT - 1, Km.data());
+                } else {
+                    std::fill(K.begin(), K.end(), mk(0.0, 0.0));
+                    std::fill(Km.begin(), Km.end(), mk(0.0, 0.0));
+                }
                 C tj = t;
                 for (int j = 0; j < NT; ++j) {
                     C fr(0.0, 0.0);
                     if (j >= 1) {
-                        fr = i4p * tj;
+                        fr = isg * i4p * tj;
                         tj = tj * t * (double)j;
                     }
                     // - j! i^j K_j
@@ -1934,7 +1945,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             for (int e = xoff[b]; e < xoff[b + 1]; ++e)
                 if (xent[e] & 1) wxmax = std::max(wxmax, reach(b, xent[e] >> 1));
         }
-        if (wxmax > kMaxDevicePZ) {
+        if (react && wxmax > kMaxDevicePZ) {
             set_error("impedance times distance reaches %.3g on a W or X list entry; the device I_n "
                       "recursion is used up to %.0f",
                       wxmax, kMaxDevicePZ);
@@ -2067,9 +2078,10 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     // the far-field chain, and join before the final leaf kernel
     LeafArgs la{S.inst_info, T.inst,    T.n_inst, NV,       T.n,      nbox,     S.nloc,   T.xs,     T.ys,
                 S.qs,        S.xy,      T.perm,   T.leaf_of, T.level, T.bx,     T.by,     T.first,  T.count,
-                T.off[0],    T.ent[0],  T.off[2], T.ent[2], S.W,      S.Lam,    S.invfact, S.fact,  S.rank1,
+                T.off[0],    T.ent[0],  T.off[2], T.ent[2], S.W,      S.Lam,    S.invfact, S.fact,
+                S.bc == 0 ? S.rank1 : nullptr,
                 S.wpts,      S.n_wpts,  S.rpts,   S.logtab, S.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
-                out.phi,     out.gx,    out.gy,   S.u2};
+                out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
@@ -2080,12 +2092,12 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_plain<MODE, NV>), near_grid, dim3(256), 0, S.side, la);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), near_grid, dim3(256), 0, S.side, la);
-    if (S.n_rpts > 0)
+    if (S.n_rpts > 0 && S.bc == 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
                            S.side, la);
     FMMHP_HIP(hipGetLastError());
     // the surface sums also need only the sorted charges
-    if (S.nloc == 1 && S.rank1_side) {
+    if (S.nloc == 1 && S.bc == 0 && S.rank1_side) {
         hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, S.side, T.xs, T.ys, S.qs, NV, S.rch,
                            S.n_rch, S.inst_info, S.red);
         hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, S.side, S.red, S.n_rch, S.inst_ch,
@@ -2120,7 +2132,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         if (i1 > i0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)(i1 - i0) * (PB + 1), 256), NV),
                                dim3(256), 0, st, i1 - i0, S.ibox + i0, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
-                               S.TimgH, S.TimgG, S.Limg, S.logside, S.W, S.Lam);
+                               S.TimgH, S.TimgG, S.Limg, S.logside, S.bc == 2 ? -1.0 : 1.0, S.W, S.Lam);
         const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
         if (x1 > x0)
             for (int loc = 0; loc < S.nloc; ++loc)
@@ -2188,7 +2200,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     }
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
-    if (S.nloc == 1 && !S.rank1_side) {
+    if (S.nloc == 1 && S.bc == 0 && !S.rank1_side) {
         hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, s, T.xs, T.ys, S.qs, NV, S.rch, S.n_rch,
                            S.inst_info, S.red);
         hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, s, S.red, S.n_rch, S.inst_ch, T.n_inst,

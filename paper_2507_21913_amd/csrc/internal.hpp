@@ -99,6 +99,9 @@ fmmhp_status build_tree(Arena &A, Tree &T, int n_inst, const int64_t *inst_off, 
 struct InstInfo {
     double x_lo, S;
     cplx Z;
+    double isg;      // sign of the image log term: +1 (Robin, Dirichlet) or -1 (Neumann)
+    int32_t react;   // 1: the reaction term G_Z is present (Robin); 0: Dirichlet or Neumann
+    int32_t pad;
 };
 
 // A range of sorted points within one instance.
@@ -121,6 +124,7 @@ struct BwdWork {
 // Evaluation schedule and tables derived from the tree.
 struct Sched {
     int PB = 0;                     // compiled truncation order
+    int bc = 0;                     // boundary condition: 0 Robin, 1 Dirichlet, 2 Neumann
     bool real_Z = true;
     cplx Z{0, 0};
     int nloc = 1;                   // 1: H only (real impedance); 2: H and G
