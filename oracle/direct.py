@@ -76,6 +76,30 @@ def potential(xs, ys, q, Z, xt=None, yt=None, workers: int | None = None,
     return out[0] if squeeze else out
 
 
+def double_layer(xs, ys, nx, ny, mu, Z, xt=None, yt=None, bc: str = "robin", chunk: int = 1 << 12):
+    """Double-layer potential sum_j mu_j n_j . grad_{r_j} G(r_i, r_j) (``kernel.green_dlp``) at
+    the targets (default: the sources), mu real or complex [ns] or [n_vec, ns]."""
+    from .kernel import green_dlp
+    xs = np.asarray(xs, dtype=np.float64)
+    ys = np.asarray(ys, dtype=np.float64)
+    mu = np.asarray(mu)
+    squeeze = mu.ndim == 1
+    m2 = mu[None, :] if squeeze else mu
+    if xt is None:
+        xt, yt = xs, ys
+    xt = np.asarray(xt, dtype=np.float64)
+    yt = np.asarray(yt, dtype=np.float64)
+    out = np.zeros((m2.shape[0], xt.shape[0]), dtype=np.complex128)
+    for t0 in range(0, xt.shape[0], 64):
+        t1 = min(xt.shape[0], t0 + 64)
+        for s0 in range(0, xs.shape[0], chunk):
+            s1 = min(xs.shape[0], s0 + chunk)
+            K = green_dlp(xt[t0:t1, None], yt[t0:t1, None], xs[None, s0:s1], ys[None, s0:s1],
+                          np.asarray(nx)[None, s0:s1], np.asarray(ny)[None, s0:s1], Z, bc=bc)
+            out[:, t0:t1] += m2[:, s0:s1] @ K.T
+    return out[0] if squeeze else out
+
+
 def potential_loops(xs, ys, q, Z, xt=None, yt=None, bc: str = "robin"):
     """Pure-Python double loop over (target, source) pairs; small inputs only.
 

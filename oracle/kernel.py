@@ -93,6 +93,39 @@ def green(xt, yt, xs, ys, Z, skip_self: bool = True, bc: str = "robin"):
     return free + image + reaction_GZ(dx, yt + ys, Z)
 
 
+def green_dlp(xt, yt, xs, ys, nx, ny, Z, bc: str = "robin"):
+    """Double-layer kernel n_s . grad_{r_s} G(r_t, r_s) for a unit normal (nx, ny) at the source,
+    broadcasting, from the derivatives of each term of G with respect to the source point:
+
+      free      -(1/2pi) ln|r_t - r_s|         ->  (1/2pi) (nx dx + ny dy) / r^2   (dx = x_t - x_s)
+      image     (1/2pi) ln|r_t - r_s^im|       ->  (1/2pi) (-nx dx + ny Y) / r_im^2   (Y = y_t + y_s)
+      reaction  I_0(X, Y) + I_0(-X, Y), X = dx ->  nx (-i I_1(X, Y) + i I_1(-X, Y)) - ny (I_1(X, Y) + I_1(-X, Y))
+
+    (d_X I_0 = i I_1 and d_Y I_0 = -I_1, eq. (integralrecursion) with n = 1).  The free term is
+    skipped where r_t == r_s; bc = "dirichlet" / "neumann" as in ``green``.
+    """
+    xt = np.asarray(xt, dtype=np.float64)
+    yt = np.asarray(yt, dtype=np.float64)
+    dx = xt - xs
+    dy = yt - ys
+    Y = yt + ys
+    r2 = dx * dx + dy * dy
+    ri2 = dx * dx + Y * Y
+    same = r2 == 0.0
+    inv = np.where(same, 0.0, 1.0 / np.where(same, 1.0, r2))
+    free = (nx * dx + ny * dy) * inv / TWO_PI
+    image = (-nx * dx + ny * Y) / ri2 / TWO_PI
+    if bc == "dirichlet":
+        return (free + image).astype(np.complex128)
+    if bc == "neumann":
+        return (free - image).astype(np.complex128)
+    if bc != "robin":
+        raise ValueError(f"unknown boundary condition {bc!r}")
+    Ip = reaction_In(1, dx, Y, Z)[1]
+    Im = reaction_In(1, -dx, Y, Z)[1]
+    return free + image + nx * (-1j * Ip + 1j * Im) - ny * (Ip + Im)
+
+
 def green_dirichlet(xt, yt, xs, ys):
     """Dirichlet half-plane Green's function (eq. (ddd1.2), image term with '+'):
 
