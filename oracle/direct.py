@@ -17,38 +17,46 @@ from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
-from .kernel import green, reaction_I0, TWO_PI
+from .kernel import green, green_dlp, reaction_I0, TWO_PI
 
 _SRC = {}
 
 
-def _block(xt, yt, xs, ys, q, Z, chunk, bc="robin"):
-    """phi for a block of targets against all sources, q shape [n_vec, ns]."""
+def _block(xt, yt, xs, ys, q, Z, chunk, bc="robin", normals=None):
+    """phi for a block of targets against all sources, q shape [n_vec, ns]; with normals = (nx, ny)
+    the double-layer kernel ``green_dlp`` replaces G."""
     nv = q.shape[0]
     acc = np.zeros((nv, xt.shape[0]), dtype=np.complex128)
     for s0 in range(0, xs.shape[0], chunk):
         s1 = min(xs.shape[0], s0 + chunk)
-        G = green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z, bc=bc)
+        if normals is None:
+            G = green(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1], Z, bc=bc)
+        else:
+            G = green_dlp(xt[:, None], yt[:, None], xs[None, s0:s1], ys[None, s0:s1],
+                          normals[0][None, s0:s1], normals[1][None, s0:s1], Z, bc=bc)
         acc += q[:, s0:s1] @ G.T
     return acc
 
 
-def _init_worker(xs, ys, q, Z, bc="robin"):
+def _init_worker(xs, ys, q, Z, bc="robin", normals=None):
     _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"], _SRC["bc"] = xs, ys, q, Z, bc
+    _SRC["normals"] = normals
 
 
 def _work(args):
     xt, yt, chunk = args
-    return _block(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"], chunk, _SRC["bc"])
+    return _block(xt, yt, _SRC["xs"], _SRC["ys"], _SRC["q"], _SRC["Z"], chunk, _SRC["bc"], _SRC["normals"])
 
 
 def potential(xs, ys, q, Z, xt=None, yt=None, workers: int | None = None,
-              target_block: int = 16, chunk: int = 1 << 16, bc: str = "robin"):
+              target_block: int = 16, chunk: int = 1 << 16, bc: str = "robin", normals=None):
     """Direct-sum potential at targets (default: targets = sources).
 
-    xs, ys : [ns] float64 source coordinates (ys > 0)
-    q      : [ns] or [n_vec, ns] charges (real or complex)
-    Z      : complex impedance (ignored for bc = "dirichlet" / "neumann", eq. (ddd1.2))
+    xs, ys  : [ns] float64 source coordinates (ys > 0)
+    q       : [ns] or [n_vec, ns] charges (real or complex)
+    Z       : complex impedance (ignored for bc = "dirichlet" / "neumann", eq. (ddd1.2))
+    normals : None, or (nx, ny) [ns] unit normals: then q are dipole densities and the sum is the
+              double layer sum_j q_j n_j . grad_{r_j} G(r_i, r_j) (``kernel.green_dlp``)
     Returns complex128 [nt] (or [n_vec, nt]).
     """
     xs = np.ascontiguousarray(xs, dtype=np.float64)
@@ -60,6 +68,9 @@ def potential(xs, ys, q, Z, xt=None, yt=None, workers: int | None = None,
         xt, yt = xs, ys
     xt = np.ascontiguousarray(xt, dtype=np.float64)
     yt = np.ascontiguousarray(yt, dtype=np.float64)
+    if normals is not None:
+        normals = (np.ascontiguousarray(normals[0], dtype=np.float64),
+                   np.ascontiguousarray(normals[1], dtype=np.float64))
     nt = xt.shape[0]
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
@@ -67,37 +78,19 @@ def potential(xs, ys, q, Z, xt=None, yt=None, workers: int | None = None,
     blocks = [(xt[i:i + target_block], yt[i:i + target_block], chunk)
               for i in range(0, nt, target_block)]
     if workers <= 1 or len(blocks) <= 1:
-        parts = [_block(b[0], b[1], xs, ys, q2, complex(Z), chunk, bc) for b in blocks]
+        parts = [_block(b[0], b[1], xs, ys, q2, complex(Z), chunk, bc, normals) for b in blocks]
     else:
         with ProcessPoolExecutor(max_workers=workers, initializer=_init_worker,
-                                 initargs=(xs, ys, q2, complex(Z), bc)) as ex:
+                                 initargs=(xs, ys, q2, complex(Z), bc, normals)) as ex:
             parts = list(ex.map(_work, blocks))
     out = np.concatenate(parts, axis=1) if parts else np.zeros((q2.shape[0], 0), np.complex128)
     return out[0] if squeeze else out
 
 
-def double_layer(xs, ys, nx, ny, mu, Z, xt=None, yt=None, bc: str = "robin", chunk: int = 1 << 12):
+def double_layer(xs, ys, nx, ny, mu, Z, xt=None, yt=None, bc: str = "robin", workers: int | None = None):
     """Double-layer potential sum_j mu_j n_j . grad_{r_j} G(r_i, r_j) (``kernel.green_dlp``) at
     the targets (default: the sources), mu real or complex [ns] or [n_vec, ns]."""
-    from .kernel import green_dlp
-    xs = np.asarray(xs, dtype=np.float64)
-    ys = np.asarray(ys, dtype=np.float64)
-    mu = np.asarray(mu)
-    squeeze = mu.ndim == 1
-    m2 = mu[None, :] if squeeze else mu
-    if xt is None:
-        xt, yt = xs, ys
-    xt = np.asarray(xt, dtype=np.float64)
-    yt = np.asarray(yt, dtype=np.float64)
-    out = np.zeros((m2.shape[0], xt.shape[0]), dtype=np.complex128)
-    for t0 in range(0, xt.shape[0], 64):
-        t1 = min(xt.shape[0], t0 + 64)
-        for s0 in range(0, xs.shape[0], chunk):
-            s1 = min(xs.shape[0], s0 + chunk)
-            K = green_dlp(xt[t0:t1, None], yt[t0:t1, None], xs[None, s0:s1], ys[None, s0:s1],
-                          np.asarray(nx)[None, s0:s1], np.asarray(ny)[None, s0:s1], Z, bc=bc)
-            out[:, t0:t1] += m2[:, s0:s1] @ K.T
-    return out[0] if squeeze else out
+    return potential(xs, ys, mu, Z, xt=xt, yt=yt, workers=workers, chunk=1 << 12, bc=bc, normals=(nx, ny))
 
 
 def potential_loops(xs, ys, q, Z, xt=None, yt=None, bc: str = "robin"):
