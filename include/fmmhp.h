@@ -232,6 +232,32 @@ fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, d
  *
  * A target that coincides with a source skips that source's free-space term in both.  Asynchronous
  * on stream. */
+/* The double-layer potential of dipole sources at the targets (every point, or the separate
+ * targets of fmmhp_plan_create_targets), the other layer potential of the boundary-integral uses of
+ * the Green's function in the paper's introduction:
+ *
+ *   phi_i = sum_j mu_j n_j . grad_{r_j} G(r_i, r_j)
+ *
+ * with G the plan's Green's function (Robin, eq. (ddGreensfunimp); Dirichlet or Neumann,
+ * eq. (ddd1.2)).  The free-space term is skipped where r_i == r_j, as for the potential.  The same
+ * tree and translations serve: the multipoles, the point-to-local terms, the near field and the
+ * surface sums take the derivative of each source's term along its normal.
+ *
+ *   n_vec        number of density vectors (>= 1), evaluated one after another
+ *   mu           [device] densities, [n_vec][n_src] real (mu_complex = 0) or [n_vec][n_src][2]
+ *                (re, im) interleaved (mu_complex = 1; phi[mu] = phi[Re mu] + i phi[Im mu])
+ *   nx, ny       [device] [n_src] source normals (the result is linear in them: a non-unit vector
+ *                scales its dipole), caller's point order
+ *   phi          [device] output, [n_vec][n_tgt][2]
+ *
+ * The first call allocates 16 bytes per point for the sorted normals (and, for complex densities or
+ * a plan with separate targets, the workspaces of fmmhp_eval_complex and fmmhp_eval).  Asynchronous
+ * on stream; not captured in a graph.  FMMHP_EINVAL for a NULL pointer, n_vec < 1 or mu_complex
+ * outside {0, 1}.
+ */
+fmmhp_status fmmhp_eval_double_layer(fmmhp_plan_t plan, int n_vec, const double *mu, int mu_complex,
+                                     const double *nx, const double *ny, double *phi, hipStream_t stream);
+
 fmmhp_status fmmhp_eval_field(fmmhp_plan_t plan, const double *q, double *phi, double *grad_x, double *grad_y,
                               hipStream_t stream);
 

@@ -83,6 +83,7 @@ _SIGNATURES = {
     "fmmhp_eval_complex": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_eval_field": [_P, _P, _P, _P, _P, _P],
+    "fmmhp_eval_double_layer": [_P, _INT, _P, _INT, _P, _P, _P, _P],
     "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
     "fmmhp_plan_export_tree": [_P] + [_P] * 18,
     "fmmhp_plan_destroy": [_P],
@@ -431,6 +432,33 @@ class HalfPlaneFMM:
                                                                raw[1].data_ptr(), raw[2].data_ptr(), _stream()))
         c = torch.view_as_complex(raw)
         return c[0], c[1], c[2]
+
+    def double_layer(self, mu: torch.Tensor, nx: torch.Tensor, ny: torch.Tensor) -> torch.Tensor:
+        """Double-layer potential sum_j mu_j n_j . grad_{r_j} G(r_i, r_j) at the targets for dipole
+        densities mu [N] or [n_vec, N] (real or complex) and source normals nx, ny [N].  Returns
+        complex128 [n_out] or [n_vec, n_out]."""
+        for name, t in (("mu", mu), ("nx", nx), ("ny", ny)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda:
+                raise TypeError(f"{name} must be a GPU tensor (no CPU path exists)")
+        if nx.is_complex() or ny.is_complex() or nx.numel() != self.n or ny.numel() != self.n:
+            raise ValueError(f"nx, ny must be real with {self.n} entries")
+        squeeze = mu.dim() == 1
+        m2 = mu.reshape(1, -1) if squeeze else mu
+        if m2.shape[-1] != self.n:
+            raise ValueError(f"mu has {m2.shape[-1]} points, plan has {self.n}")
+        nv = m2.shape[0]
+        cpx = m2.is_complex()
+        parts = (torch.view_as_real(m2.to(torch.complex128).contiguous()) if cpx
+                 else m2.to(torch.float64).contiguous())
+        nxd = nx.reshape(-1).to(torch.float64).contiguous()
+        nyd = ny.reshape(-1).to(torch.float64).contiguous()
+        raw = torch.empty((nv, self.n_out, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check("fmmhp_eval_double_layer",
+                   lib().fmmhp_eval_double_layer(self._plan, nv, parts.data_ptr(), int(cpx), nxd.data_ptr(),
+                                                 nyd.data_ptr(), raw.data_ptr(), _stream()))
+        phi = torch.view_as_complex(raw)
+        return phi[0] if squeeze else phi
 
     def backward(self, q: torch.Tensor, grad_phi: torch.Tensor, want_q=True, want_x=True,
                  want_y=True, want_lambda=True) -> dict:

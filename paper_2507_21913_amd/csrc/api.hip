@@ -319,6 +319,39 @@ fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, d
     return run_eval_complex(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
+fmmhp_status fmmhp_eval_double_layer(fmmhp_plan_t plan, int n_vec, const double *mu, int mu_complex,
+                                     const double *nx, const double *ny, double *phi, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (n_vec < 1 || !mu || !nx || !ny || !phi || (mu_complex != 0 && mu_complex != 1)) {
+        set_error("n_vec must be >= 1, mu_complex 0 or 1 and mu, nx, ny, phi non-NULL");
+        return FMMHP_EINVAL;
+    }
+    const int w = mu_complex ? 2 : 1;
+    if (plan->n_src == 0)
+        return run_eval_dlp(plan->arena, plan->tree, plan->sched, n_vec, mu, w, nx, ny, phi, stream);
+    // separate targets: densities and normals padded with zeros to all tree points
+    const int64_t n = plan->tree.n, ns = plan->n_src;
+    if (plan->pad_cap < n_vec) {
+        FMMHP_CHECK(plan->arena.alloc_n(&plan->qpad, (size_t)n_vec * n * 2, "padded charges"));
+        FMMHP_CHECK(plan->arena.alloc_n(&plan->phipad, (size_t)n_vec * n * 2, "potentials at all points"));
+        plan->pad_cap = n_vec;
+    }
+    if (!plan->npad) FMMHP_CHECK(plan->arena.alloc_n(&plan->npad, (size_t)2 * n, "padded normals"));
+    hipLaunchKernelGGL(k_pad_charges, dim3((unsigned)((n * w + 255) / 256)), dim3(256), 0, stream, mu, ns, n, w, n_vec,
+                       plan->qpad);
+    hipLaunchKernelGGL(k_pad_charges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, nx, ns, n, 1, 1,
+                       plan->npad);
+    hipLaunchKernelGGL(k_pad_charges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, ny, ns, n, 1, 1,
+                       plan->npad + n);
+    FMMHP_HIP(hipGetLastError());
+    FMMHP_CHECK(run_eval_dlp(plan->arena, plan->tree, plan->sched, n_vec, plan->qpad, w, plan->npad, plan->npad + n,
+                             plan->phipad, stream));
+    hipLaunchKernelGGL(k_take_targets, dim3((unsigned)((2 * (n - ns) + 255) / 256)), dim3(256), 0, stream,
+                       plan->phipad, ns, n, n_vec, phi);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
+}
+
 // pp [n][2] -> out [n - ns][2] (one vector)
 __global__ void k_take_targets2(const double *__restrict__ pp, int64_t ns, int64_t n, double *__restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

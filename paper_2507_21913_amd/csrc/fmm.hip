@@ -123,14 +123,19 @@ __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restri
 // ---------------------------------------------------------------------------------------------
 constexpr int kP2MSplit = 4;
 
-template <int PB>
+//
+// Dipole sources (DIP: density mu_j, normal n_j, potential mu_j n_j . grad_{r_j} G): the expansions
+// of this method are real-linear in the per-source terms q_j f_n(z_j), f_n(z) = (-(z - c)/rho)^n/n!,
+// and f_n is holomorphic, so n_j . grad f_n = nu_j f_n' with nu_j = n_x + i n_y; the multipole of a
+// dipole is w_n = mu_j nu_j (-1/rho) f_{n-1}(z_j) (w_0 = 0), and every translation is unchanged.
+template <int PB, bool DIP>
 __global__ __launch_bounds__(256) void k_p2m(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
                                              const int32_t *__restrict__ leaves, int nleaf, int nbox, int nv,
                                              const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
                                              const int32_t *__restrict__ by, const int32_t *__restrict__ first,
                                              const int32_t *__restrict__ count, const double *__restrict__ xs,
                                              const double *__restrict__ ys, const double *__restrict__ qs,
-                                             cplx *__restrict__ W) {
+                                             const double2 *__restrict__ nrm, cplx *__restrict__ W) {
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = gt / kP2MSplit, part = gt % kP2MSplit;
     const bool ok = t < nleaf;  // no early exit: every lane of a leaf group takes part in the butterfly
@@ -148,11 +153,21 @@ __global__ __launch_bounds__(256) void k_p2m(const InstInfo *__restrict__ ii, co
         const int f = first[b], e = f + count[b];
         for (int j = f + part; j < e; j += kP2MSplit) {
             const cplx mz = mk((c.re - xs[j]) * irho, (c.im - ys[j]) * irho);  // -(z_j - c) / rho
-            cplx term = mk(qs[(int64_t)j * nv + v], 0.0);
+            if (DIP) {
+                const double2 nj = nrm[j];
+                cplx term = (-irho * qs[(int64_t)j * nv + v]) * mk(nj.x, nj.y);  // mu nu (-1/rho) f_0
 #pragma unroll
-            for (int n = 0; n <= PB; ++n) {
-                w[n] += term;
-                term = term * mz * (1.0 / (n + 1));
+                for (int n = 1; n <= PB; ++n) {
+                    w[n] += term;
+                    term = term * mz * (1.0 / n);
+                }
+            } else {
+                cplx term = mk(qs[(int64_t)j * nv + v], 0.0);
+#pragma unroll
+                for (int n = 0; n <= PB; ++n) {
+                    w[n] += term;
+                    term = term * mz * (1.0 / (n + 1));
+                }
             }
         }
     }
@@ -656,8 +671,13 @@ __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nrow, cplx *
 // P2L (X list): sources of a coarse leaf straight into the local of a finer box.  One wave per
 // target box; lanes take source points, write their p + 1 contributions to LDS, and lane n sums
 // coefficient n over the chunk in a fixed order.
+// Dipole sources (DIP) take the derivative of these contributions along the source normal: the log
+// local is holomorphic in d = z_j - c_b (upper box) or in conj(z_j) - c_b (image), so the derivative
+// is nu d/dd (nu = n_x + i n_y, or its conjugate for the image), and for the reaction local
+// n_j . grad_{r_j} [n! rho^n I_n] = -(1/rho) i conj(nu) K_{n+1} (d_X I_n = i (n+1) I_{n+1},
+// d_Y I_n = -(n+1) I_{n+1}, from eq. (generalintegral)); the same holds for the mirrored G local.
 // ---------------------------------------------------------------------------------------------
-template <int PB>
+template <int PB, bool DIP>
 __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst, int nv,
                                             int nloc, int loc, const int32_t *__restrict__ xbox, int nbox,
                                             const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
@@ -665,7 +685,8 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                                             const int32_t *__restrict__ count, const int32_t *__restrict__ xoff,
                                             const int32_t *__restrict__ xent, const double *__restrict__ xs,
                                             const double *__restrict__ ys, const double *__restrict__ qs,
-                                            const double *__restrict__ fact, cplx *__restrict__ Lam) {
+                                            const double2 *__restrict__ nrm, const double *__restrict__ fact,
+                                            cplx *__restrict__ Lam) {
     __shared__ cplx contrib[64][PB + 1];
     const int b = xbox[blockIdx.x];
     const int v = blockIdx.y;  // charge vector
@@ -688,13 +709,23 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                 const double yj = img ? -ys[j] : ys[j];
                 const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
                 const double sgn = img ? ii[inst[b]].isg : -1.0;  // -(1/4pi) upper, +-(1/4pi) image
-                // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
-                out[0] = (sgn * kInv4Pi * q) * clog_(-d);
                 const cplx sig = rho * inv(d);
-                cplx pw = sig;
-                for (int n = 1; n <= PB; ++n) {
-                    out[n] = (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
-                    pw = pw * sig;
+                if (DIP) {
+                    // nu d/dd of the charge's local below: (nu / rho) n! sig^(n+1)
+                    const double2 nj = nrm[j];
+                    cplx pw = ((sgn * kInv4Pi * q / rho) * mk(nj.x, img ? -nj.y : nj.y)) * sig;
+                    for (int n = 0; n <= PB; ++n) {
+                        out[n] = fact[n] * pw;
+                        pw = pw * sig;
+                    }
+                } else {
+                    // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
+                    out[0] = (sgn * kInv4Pi * q) * clog_(-d);
+                    cplx pw = sig;
+                    for (int n = 1; n <= PB; ++n) {
+                        out[n] = (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
+                        pw = pw * sig;
+                    }
                 }
                 if (img && ii[inst[b]].react) {
                     // reaction S2L (eq. (LEcoefficients)) re-expanded in powers of (z - c_b):
@@ -705,11 +736,22 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                     const cplx zr = rho * Z;
                     cplx K = reaction_I0_general(Xs, Y, Z);
                     cplx F = mk(1.0, 0.0);
-                    out[0] += q * (loc == 0 ? K : conj(K));
-                    for (int n = 1; n <= PB; ++n) {
-                        F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
-                        K = F * kInv2Pi + zr * K;
-                        out[n] += q * mul_ipow(loc == 0 ? K : conj(K), n);
+                    if (DIP) {
+                        // lambda_(n-1) += -(mu conj(nu) / rho) i^n K_n, n = 1 .. p + 1
+                        const double2 nj = nrm[j];
+                        const cplx cn = (-q / rho) * mk(nj.x, -nj.y);
+                        for (int n = 1; n <= PB + 1; ++n) {
+                            F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
+                            K = F * kInv2Pi + zr * K;
+                            out[n - 1] += cn * mul_ipow(loc == 0 ? K : conj(K), n);
+                        }
+                    } else {
+                        out[0] += q * (loc == 0 ? K : conj(K));
+                        for (int n = 1; n <= PB; ++n) {
+                            F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
+                            K = F * kInv2Pi + zr * K;
+                            out[n] += q * mul_ipow(loc == 0 ? K : conj(K), n);
+                        }
                     }
                 }
             } else {
@@ -863,10 +905,14 @@ __device__ __forceinline__ cplx block_sum(cplx v) {
     return mk(sr[0], si[0]);
 }
 
+// Surface sums s = sum_j q_j e^{-Z(y_j - i x_j)}; for dipoles (DIP) the normal derivative of each
+// term, mu_j Z (i n_x - n_y) e^{-Z(y_j - i x_j)} (the exponential is holomorphic in z_j).
+template <bool DIP>
 __global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict__ xs, const double *__restrict__ ys,
                                                        const double *__restrict__ qs, int nv,
                                                        const PtChunk *__restrict__ ch, int nch,
-                                                       const InstInfo *__restrict__ ii, cplx *__restrict__ part) {
+                                                       const InstInfo *__restrict__ ii, const double2 *__restrict__ nrm,
+                                                       cplx *__restrict__ part) {
     const PtChunk c = ch[blockIdx.x];
     const int v = blockIdx.y;
     const double Z = ii[c.inst].Z.re;
@@ -875,8 +921,15 @@ __global__ __launch_bounds__(256) void k_rank1_partial(const double *__restrict_
         const double e = qs[i * nv + v] * exp(-Z * ys[i]);
         double sn, cs;
         sincos(Z * xs[i], &sn, &cs);
-        ar += e * cs;
-        ai += e * sn;
+        if (DIP) {
+            const double2 nj = nrm[i];
+            const double ez = Z * e;
+            ar -= ez * (nj.y * cs + nj.x * sn);
+            ai += ez * (nj.x * cs - nj.y * sn);
+        } else {
+            ar += e * cs;
+            ai += e * sn;
+        }
     }
     const cplx t = block_sum(mk(ar, ai));
     if (threadIdx.x == 0) part[(int64_t)v * nch + blockIdx.x] = t;
@@ -902,7 +955,12 @@ __global__ __launch_bounds__(256) void k_rank1_final(const cplx *__restrict__ pa
 // the near-field sums and the surface term; k_leaf_w: the rarer W list (M2P).
 //
 // Each kernel has three modes: kPhi (the potential, in caller order), kGrad (the gradient
-// (d_x phi, d_y phi) only) and kPhiGrad (both).  Gradients follow from the same expansions: the
+// (d_x phi, d_y phi) only) and kPhiGrad (both); the near-field kernels have a fourth, kDip, the
+// double-layer potential of dipole sources (density q_j, normal n_j): the same sums with each
+// pair's kernel replaced by its derivative along the source normal,
+//   n . grad' (s/2pi) log|r - r'| = (s/2pi) (-n_x dx + t n_y dy) / r^2   (dx = x - x', dy = y + t y',
+//   t = -1 free, +1 image), and n . grad' I_0(X, Y) = -i conj(nu) I_1(X, Y), n . grad' I_0(-X, Y) =
+//   i nu I_1(-X, Y), nu = n_x + i n_y.  Gradients follow from the same expansions: the
 // far field is 2 Re H + surface (real impedance) or H + conj(G) with H, G holomorphic in the
 // target z, so d_x = 2 Re H', d_y = -2 Im H' (resp. d_x = H' + conj(G'), d_y = i H' - i conj(G'));
 // the surface term i e^{-Z(y + ix)} s has d_x = Z e^{-Z(y+ix)} s and d_y = -i Z e^{-Z(y+ix)} s.
@@ -910,9 +968,10 @@ __global__ __launch_bounds__(256) void k_rank1_final(const cplx *__restrict__ pa
 // d_x I_0(X, Y) = i I_1(X, Y), d_y I_0(X, Y) = -I_1(X, Y), I_1 = 1 / (2 pi w) + Z I_0, w = Y - iX
 // (differentiating eq. (generalintegral) under the integral; eq. (integralrecursion) for n = 1).
 // ---------------------------------------------------------------------------------------------
-enum LeafMode { kPhi = 0, kGrad = 1, kPhiGrad = 2 };
+enum LeafMode { kPhi = 0, kGrad = 1, kPhiGrad = 2, kDip = 3 };
 __host__ __device__ constexpr bool has_phi(int m) { return m != kGrad; }
-__host__ __device__ constexpr bool has_grad(int m) { return m != kPhi; }
+__host__ __device__ constexpr bool has_grad(int m) { return m == kGrad || m == kPhiGrad; }
+__host__ __device__ constexpr bool is_dip(int m) { return m == kDip; }
 
 struct LeafArgs {
     const InstInfo *ii;      // [n_inst]
@@ -939,6 +998,7 @@ struct LeafArgs {
     cplx *gx, *gy;           // [n] gradient, caller order (gradient modes)
     const int2 *u2;          // per U entry: (first point, point count | image << 31) of its source box
     double isg;              // sign of the image log term: +1 (Robin, Dirichlet), -1 (Neumann)
+    const double2 *nrm;      // [n] source normals (sorted order), kDip only
 };
 
 // Near field, log terms of the U list: one thread per target (sorted order, grid-stride over the
@@ -971,6 +1031,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
         int2 fc = u2[e];
         int2 fn = e + 1 < e1 ? u2[e + 1] : fc;  // range of entry e + 1
         double2 pj = xy[fc.x];
+        double2 nj = is_dip(MODE) ? a.nrm[fc.x] : make_double2(0.0, 0.0);
         double qj[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) qj[v] = qs[(int64_t)fc.x * NV + v];
@@ -983,6 +1044,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
             for (int j = j0; j < jend; ++j) {
                 const int jp = j + 1 < jend ? j + 1 : jnext;
                 const double2 pn = xy[jp];
+                const double2 nn = is_dip(MODE) ? a.nrm[jp] : make_double2(0.0, 0.0);
                 double qn[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) qn[v] = qs[(int64_t)jp * NV + v];
@@ -991,7 +1053,11 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 // r2 = 0 only for a coincident free pair, skipped (eq. (1.2)), or between two
                 // target-only points on y = 0 (no charge); image distances to sources are positive
                 const bool nz = r2 > 0.0;
-                if (has_phi(MODE)) {
+                if (is_dip(MODE)) {
+                    const double kv = nz ? sg * rcp_pos(nz ? r2 : 1.0) * fma(ysg * nj.y, dy, -nj.x * dx) : 0.0;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], kv, acc[v]);
+                } else if (has_phi(MODE)) {
                     const double sl = sg * log_tab(nz ? r2 : 1.0, tab);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], nz ? sl : 0.0, acc[v]);
@@ -1007,6 +1073,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                     qc += nz ? 0.0 : qj[0];
                 }
                 pj = pn;
+                nj = nn;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) qj[v] = qn[v];
             }
@@ -1016,8 +1083,9 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
             if (e + 1 < e1) fn = u2[e + 1];
         }
         if (has_phi(MODE)) {
+            constexpr double kc = is_dip(MODE) ? kInv2Pi : kInv4Pi;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * acc[v], 0.0);
+            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + i] = make_double2(kc * acc[v], 0.0);
         }
         if (has_grad(MODE)) {
 #pragma unroll
@@ -1064,7 +1132,12 @@ __global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
                     const double dx = x - pj.x, dy = y - pj.y;
                     const double r2 = fma(dx, dx, dy * dy);
                     const bool nz = r2 > 0.0;  // skip the self pair (eq. (1.2))
-                    if (has_phi(MODE)) {
+                    if (is_dip(MODE)) {
+                        const double2 nj = a.nrm[j];
+                        const double kv = nz ? -rcp_pos(nz ? r2 : 1.0) * fma(nj.x, dx, nj.y * dy) : 0.0;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], kv, lfree[v]);
+                    } else if (has_phi(MODE)) {
                         const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) lfree[v] = fma(qs[(int64_t)j * NV + v], lg, lfree[v]);
@@ -1088,7 +1161,12 @@ __global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
                     const double r2 = fma(dx, dx, dy * dy);
                     // r2 = 0 only between two target-only points on y = 0 (no charge): skipped
                     const bool nz = r2 > 0.0;
-                    if (has_phi(MODE)) {
+                    if (is_dip(MODE)) {
+                        const double2 nj = a.nrm[j];
+                        const double kv = nz ? rcp_pos(nz ? r2 : 1.0) * fma(nj.y, dy, -nj.x * dx) : 0.0;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], kv, limg[v]);
+                    } else if (has_phi(MODE)) {
                         const double lg = nz ? log_tab(nz ? r2 : 1.0, tab) : 0.0;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) limg[v] = fma(qs[(int64_t)j * NV + v], lg, limg[v]);
@@ -1107,9 +1185,10 @@ __global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
             }
         }
         if (has_phi(MODE)) {
+            constexpr double kc = is_dip(MODE) ? kInv2Pi : kInv4Pi;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                a.near[(int64_t)v * a.n + i] = make_double2(kInv4Pi * (a.isg * limg[v] - lfree[v]), 0.0);
+                a.near[(int64_t)v * a.n + i] = make_double2(kc * (a.isg * limg[v] - lfree[v]), 0.0);
         }
         if (has_grad(MODE)) {
 #pragma unroll
@@ -1327,6 +1406,23 @@ __global__ __launch_bounds__(64) void k_near_reaction(LeafArgs a) {
             const double dx = x - a.xs[j], dy = y + a.ys[j];
             if (!(dy > 0.0)) continue;  // two target-only points on y = 0 (no charge)
             const cplx I = reaction_I0_near(dx, dy, Z);
+            if (is_dip(MODE)) {
+                // -i conj(nu) I_1(X, Y) (+ i nu I_1(-X, Y) with a complex impedance)
+                const double2 nj = a.nrm[j];
+                const cplx I1 = kInv2Pi * inv(mk(dy, -dx)) + Z * I;
+                cplx hv = mk(-nj.y, -nj.x) * I1;
+                if (a.nloc != 1) {
+                    const cplx I1m = kInv2Pi * inv(mk(dy, dx)) + Z * reaction_I0_near(-dx, dy, Z);
+                    hv += mk(-nj.y, nj.x) * I1m;
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double qj = a.qs[(int64_t)j * NV + v];
+                    sr[v] += qj * hv.re;
+                    si[v] += qj * hv.im;
+                }
+                continue;
+            }
             if (has_grad(MODE)) {
                 const cplx I1 = kInv2Pi * inv(mk(dy, -dx)) + Z * I;
 #pragma unroll
@@ -2069,6 +2165,8 @@ struct PassOut {
 // from blockIdx.y; the near-field kernels share each pair's kernel value among the NV vectors.
 template <int PB, int MODE, int NV>
 static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
+    constexpr bool DIP = is_dip(MODE);
+    constexpr int LM = DIP ? (int)kPhi : MODE;
     const int nbox = T.nbox;
     Marks mk_;
     FMMHP_CHECK(mk_.init(S));
@@ -2081,7 +2179,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
                 T.off[0],    T.ent[0],  T.off[2], T.ent[2], S.W,      S.Lam,    S.invfact, S.fact,
                 S.bc == 0 ? S.rank1 : nullptr,
                 S.wpts,      S.n_wpts,  S.rpts,   S.logtab, S.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
-                out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0};
+                out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0, S.nrm};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
@@ -2098,17 +2196,17 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_HIP(hipGetLastError());
     // the surface sums also need only the sorted charges
     if (S.nloc == 1 && S.bc == 0 && S.rank1_side) {
-        hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, S.side, T.xs, T.ys, S.qs, NV, S.rch,
-                           S.n_rch, S.inst_info, S.red);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rank1_partial<DIP>), dim3(S.n_rch, NV), dim3(256), 0, S.side, T.xs,
+                           T.ys, S.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, S.red);
         hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, S.side, S.red, S.n_rch, S.inst_ch,
                            T.n_inst, S.rank1);
         FMMHP_HIP(hipGetLastError());
     }
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
     FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB>), dim3(nblk((int64_t)T.nleaf * kP2MSplit, 256), NV), dim3(256), 0, s,
-                       S.inst_info, T.inst, S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count, T.xs,
-                       T.ys, S.qs, S.W);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB, DIP>), dim3(nblk((int64_t)T.nleaf * kP2MSplit, 256), NV), dim3(256),
+                       0, s, S.inst_info, T.inst, S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count,
+                       T.xs, T.ys, S.qs, S.nrm, S.W);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
     // M2L (+ image M2L, P2L) over the levels [l0, l1) of the tree on stream st
@@ -2136,9 +2234,9 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
         if (x1 > x0)
             for (int loc = 0; loc < S.nloc; ++loc)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB>), dim3(x1 - x0, NV), dim3(64), 0, st, S.inst_info, T.inst,
-                                   NV, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count, T.off[3],
-                                   T.ent[3], T.xs, T.ys, S.qs, S.fact, S.Lam);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP>), dim3(x1 - x0, NV), dim3(64), 0, st, S.inst_info,
+                                   T.inst, NV, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count,
+                                   T.off[3], T.ent[3], T.xs, T.ys, S.qs, S.nrm, S.fact, S.Lam);
         FMMHP_HIP(hipGetLastError());
         return FMMHP_OK;
     };
@@ -2201,17 +2299,18 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
     if (S.nloc == 1 && S.bc == 0 && !S.rank1_side) {
-        hipLaunchKernelGGL(k_rank1_partial, dim3(S.n_rch, NV), dim3(256), 0, s, T.xs, T.ys, S.qs, NV, S.rch, S.n_rch,
-                           S.inst_info, S.red);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rank1_partial<DIP>), dim3(S.n_rch, NV), dim3(256), 0, s, T.xs, T.ys,
+                           S.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, S.red);
         hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, s, S.red, S.n_rch, S.inst_ch, T.n_inst,
                            S.rank1);
         FMMHP_HIP(hipGetLastError());
     }
     FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, MODE>), dim3(nblk(T.n, 256), NV), dim3(256), 0, s, la);
+    // dipoles differ from charges only in the source terms: the L2P and M2P kernels are the potential's
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, LM>), dim3(nblk(T.n, 256), NV), dim3(256), 0, s, la);
     if (S.n_wpts > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, MODE>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, s, la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_NEAR, s));
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
@@ -2328,6 +2427,50 @@ fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const
                            S.cq);
         FMMHP_HIP(hipGetLastError());
         FMMHP_CHECK(run_eval(A, T, S, 2, S.cq, S.cphi, s));
+        hipLaunchKernelGGL(k_combine_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, S.cphi, T.n,
+                           phi + (int64_t)v * 2 * T.n);
+        FMMHP_HIP(hipGetLastError());
+    }
+    return FMMHP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Double-layer potential: dipole densities with normals, one vector per pass (the kDip mode of the
+// source kernels; every translation is shared with the potential).  Complex densities are split
+// into two real vectors as for complex charges.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_gather_nrm(const double *__restrict__ nx, const double *__restrict__ ny,
+                             const int32_t *__restrict__ perm, int64_t n, double2 *__restrict__ nrm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    nrm[i] = make_double2(nx[o], ny[o]);
+}
+
+fmmhp_status run_eval_dlp(Arena &A, const Tree &T, Sched &S, int nvec, const double *mu, int w, const double *nx,
+                          const double *ny, double *phi, hipStream_t s) {
+    if (!S.nrm) FMMHP_CHECK(A.alloc_n(&S.nrm, (size_t)T.n, "sorted normals"));
+    hipLaunchKernelGGL(k_gather_nrm, dim3(nblk(T.n, 256)), dim3(256), 0, s, nx, ny, T.perm, T.n, S.nrm);
+    FMMHP_HIP(hipGetLastError());
+    if (w == 2 && !S.cq) {
+        FMMHP_CHECK(A.alloc_n(&S.cq, (size_t)2 * T.n, "complex-charge split"));
+        FMMHP_CHECK(A.alloc_n(&S.cphi, (size_t)4 * T.n, "complex-charge potentials"));
+    }
+    for (int v = 0; v < nvec; ++v) {
+        if (w == 1) {
+            PassOut o;
+            o.phi = phi + (int64_t)v * 2 * T.n;
+            FMMHP_CHECK((run_pass<kDip, 1>(T, S, mu + (int64_t)v * T.n, o, s)));
+            continue;
+        }
+        hipLaunchKernelGGL(k_split_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, mu + (int64_t)v * 2 * T.n, T.n,
+                           S.cq);
+        FMMHP_HIP(hipGetLastError());
+        for (int h = 0; h < 2; ++h) {
+            PassOut o;
+            o.phi = S.cphi + (int64_t)h * 2 * T.n;
+            FMMHP_CHECK((run_pass<kDip, 1>(T, S, S.cq + (int64_t)h * T.n, o, s)));
+        }
         hipLaunchKernelGGL(k_combine_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, S.cphi, T.n,
                            phi + (int64_t)v * 2 * T.n);
         FMMHP_HIP(hipGetLastError());

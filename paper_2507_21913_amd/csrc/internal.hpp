@@ -195,6 +195,7 @@ struct Sched {
     cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
     BwdWork bw;
     double *cq = nullptr, *cphi = nullptr;  // complex-charge workspace ([2][n], [2][n][2])
+    double2 *nrm = nullptr;         // [n] source normals in sorted order (double-layer evaluation)
     // recorded evaluation (FMMHP_FLAG_GRAPH)
     bool use_graph = false;
     struct {
@@ -219,6 +220,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
 void apply_launch_shape(Sched &S, int near_walk, int near_groups);
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
+// Double-layer potential of nvec dipole densities mu ([nvec][n], w = 1 real or 2 complex) with
+// source normals nx, ny [n], all in caller order.
+fmmhp_status run_eval_dlp(Arena &A, const Tree &T, Sched &S, int nvec, const double *mu, int w, const double *nx,
+                          const double *ny, double *phi, hipStream_t s);
 fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                               hipStream_t stream);
 
@@ -250,6 +255,7 @@ struct fmmhp_plan_s {
     int64_t n_src = 0;
     double *qpad = nullptr, *phipad = nullptr;  // [cap][n] (x2 for complex charges), [cap][n][2]
     double *gpad = nullptr;                     // [2][n][2] gradients at all points (fmmhp_eval_field)
+    double *npad = nullptr;                     // [2][n] normals padded to all points (double layer)
     int pad_cap = 0;
     int p_req, leaf_size, max_level;
     double lambda_re, lambda_im;
