@@ -136,6 +136,7 @@ __global__ __launch_bounds__(256) void k_p2m(const InstInfo *__restrict__ ii, co
                                              const int32_t *__restrict__ count, const double *__restrict__ xs,
                                              const double *__restrict__ ys, const double *__restrict__ qs,
                                              const double2 *__restrict__ nrm, cplx *__restrict__ W) {
+    __builtin_amdgcn_s_setprio(3);  // upward pass: the critical path
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = gt / kP2MSplit, part = gt % kP2MSplit;
     const bool ok = t < nleaf;  // no early exit: every lane of a leaf group takes part in the butterfly
@@ -185,7 +186,9 @@ __global__ __launch_bounds__(256) void k_p2m(const InstInfo *__restrict__ ii, co
 }
 
 // ---------------------------------------------------------------------------------------------
-// M2M.  A block takes kM2MParents consecutive boxes of a level; their children are a contiguous
+// M2M.  (P2M and M2M raise their waves' issue priority: the upward pass is the critical path of
+// an evaluation while the near field and the deep-level M2L run beside it on other streams.)
+// A block takes kM2MParents consecutive boxes of a level; their children are a contiguous
 // range of the next level, whose multipoles are staged in LDS once.  Thread (parent, n) then forms
 // w^P_n = sum_children sum_{m<=n} (-eps)^{n-m}/(n-m)! 2^-m w^c_m.
 // k_m2m runs one level; k_m2m_sub runs every level below a cut level, one block per subtree
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(256) void k_m2m(int lo, int nb, int nbox, const int
                                              const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
                                              const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                              cplx *__restrict__ W) {
+    __builtin_amdgcn_s_setprio(3);  // upward pass: the critical path
     __shared__ M2MShared<PB> sh;
     extern __shared__ cplx dyn_lds[];  // (PB + 1) x 4 kM2MParents
     W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
@@ -332,6 +336,7 @@ __global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restric
                                                  const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
                                                  const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                                  cplx *__restrict__ W) {
+    __builtin_amdgcn_s_setprio(3);  // upward pass: the critical path
     __shared__ M2MShared<PB> sh;
     __shared__ SubShared ss;
     extern __shared__ cplx dyn_lds[];  // (PB + 1) x ld: slot i, coefficient m at [m * ld + i]
