@@ -28,9 +28,9 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X fp64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per k_m2l launch measured with rocprofv3 counter runs (2.00 x FETCH_SIZE + 1.00 x
+# HBM bytes of k_m2l per evaluation measured with rocprofv3 counter runs (2.00 x FETCH_SIZE + 1.00 x
 # WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
-# (p, leaf size): reported only while the kernels are the ones that were measured.
+# (p, leaf size): reported (per launch) only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
 M2L_TRAFFIC = {("79d8e549df1bfeca", 20, 32): 167.1e6}
 
@@ -262,6 +262,7 @@ def main():
     torch.cuda.synchronize()
     ms_instrumented = e0.elapsed_time(e1) / a.steps
     phases, nev = plan.phase_times()
+    m2l_ms_sum, m2l_launches = plan.m2l_kernel_times()
     plan.set_timing(False)
     phase_avg = {k: v / max(1, nev) for k, v in phases.items()}
 
@@ -288,17 +289,24 @@ def main():
 
     # roofline of the dominant kernel, from algorithmic work per launch / measured launch time
     P1 = info["p"] + 1
-    m2l_flops = 8.0 * P1 * P1 * (info["m2l_pairs"][0] + info["m2l_pairs"][1])
-    # dominant kernel: the one with the most algorithmic work per launch (the near field runs
+    # k_m2l: the upper-source pairs, (p + 1)^2 complex FMA (8 flops) each; image pairs are k_m2l_img's
+    m2l_flops = 8.0 * P1 * P1 * info["m2l_pairs"][0]
+    # dominant kernel: the one with the most algorithmic work per evaluation (the near field runs
     # concurrently on its own stream, so phase durations overlap)
     near_flops = 27.0 * (info["p2p_pairs"][0] + info["p2p_pairs"][1])
     dom = "m2l" if m2l_flops >= near_flops else "near"
-    if dom == "m2l":
-        achieved = m2l_flops / (phase_avg["m2l"] * 1e-3) / 1e12
+    if dom == "m2l" and m2l_launches > 0:
+        # k_m2l runs as up to two launches per evaluation (deep levels on a second stream, coarse
+        # levels on the eval stream), each bracketed by HIP events on its own stream
+        per_eval = m2l_launches / max(1, nev)
+        fl = m2l_flops / per_eval
+        avg_ms = m2l_ms_sum / m2l_launches
+        achieved = fl / (avg_ms * 1e-3) / 1e12
         traffic = M2L_TRAFFIC.get((eval_source_hash(), info["p"], leaf_use))
         roof = {"kernel": "k_m2l", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "flops_per_launch": m2l_flops}
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None if traffic is None else traffic / per_eval,
+                "flops_per_launch": fl, "launches_per_eval": per_eval, "avg_launch_us": avg_ms * 1e3}
     else:
         # near field (k_near): 27 float64 flops per pair, counted from its compiled inner loop
         # (12 FMA incl. the table-assisted log, 2 add, 1 mul); image-source pairs counted alike
@@ -392,6 +400,28 @@ def main():
                           "bwd_over_fwd": (ms_fb - ms) / ms,
                           "outputs": "phi; dl/dq, dl/dx, dl/dy",
                           "bwd_with_dl_dZ_wall_ms": bwd_lambda_ms}
+        # the double-layer potential of the same densities with seeded unit normals, same plan
+        nxh, nyh = workloads.source_normals(w.n, seed=7)
+        nxd, nyd = (torch.as_tensor(v, device=dev) for v in (nxh, nyh))
+        for _ in range(2):
+            dl = plan.double_layer(q, nxd, nyd)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(nb):
+            dl = plan.double_layer(q, nxd, nyd)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_dl = e0.elapsed_time(e1) / nb
+        rel_dl = None
+        if g is not None:
+            from golden_io import load_dlp
+            gd = load_dlp("uniform_1m")
+            if gd is not None:
+                rel_dl = float(np.linalg.norm(dl.cpu().numpy()[gd[0]] - gd[1]) / np.linalg.norm(gd[1]))
+        res["double_layer"] = {"mpts_s": w.n / (ms_dl * 1e-3) / 1e6, "ms_per_step": ms_dl,
+                               "normals": "workloads.source_normals(N, seed=7)",
+                               "rel_l2_vs_oracle_sample": rel_dl}
+        del dl
         res["example2"] = example2_extra(dev)
         if not a.no_batched:
             plan.close()

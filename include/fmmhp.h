@@ -319,6 +319,13 @@ fmmhp_status fmmhp_plan_set_timing(fmmhp_plan_t plan, int enable);
  * events.  ms: [host] FMMHP_NUM_PHASES doubles; n_evals: [host], may be NULL. */
 fmmhp_status fmmhp_plan_phase_times(fmmhp_plan_t plan, double *ms, int64_t *n_evals);
 
+/* Totals since timing was enabled of the upper-source M2L kernel alone (profiling aid): ms = summed
+ * device milliseconds of its launches, each bracketed by HIP events on the stream it runs on (it
+ * runs as up to two launches per charge-vector pass: the deepest levels on a second stream, the
+ * coarse levels on the eval stream, concurrently with the near field), n_launches = their number.
+ * Waits for the recorded events.  ms: [host] one double; n_launches: [host], may be NULL. */
+fmmhp_status fmmhp_plan_m2l_kernel_times(fmmhp_plan_t plan, double *ms, int64_t *n_launches);
+
 /* Release the plan and its device memory.  Synchronises the device.  plan may be NULL (no-op). */
 fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan);
 

@@ -91,6 +91,7 @@ _SIGNATURES = {
     "fmmhp_reaction_integrals": [_I64, _P, _P, _INT, _D, _D, _P, _P],
     "fmmhp_plan_set_timing": [_P, _INT],
     "fmmhp_plan_phase_times": [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)],
+    "fmmhp_plan_m2l_kernel_times": [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)],
     "fmmhp_tune": [_I64, _P, _P, _P, _D, _D, _D, _INT, _P, _INT, _INT, ctypes.POINTER(Opts),
                    ctypes.POINTER(_D), ctypes.POINTER(_D), _P],
     "fmmhp_status_string": [_INT],
@@ -206,6 +207,13 @@ def fmmhp_plan_phase_times(plan) -> tuple[dict, int]:
     n = _I64()
     _check("fmmhp_plan_phase_times", lib().fmmhp_plan_phase_times(plan, ms, ctypes.byref(n)))
     return {k: ms[i] for i, k in enumerate(PHASES)}, n.value
+
+
+def fmmhp_plan_m2l_kernel_times(plan) -> tuple[float, int]:
+    ms = _D()
+    n = _I64()
+    _check("fmmhp_plan_m2l_kernel_times", lib().fmmhp_plan_m2l_kernel_times(plan, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def fmmhp_plan_export_tree(plan) -> dict:
@@ -384,6 +392,10 @@ class HalfPlaneFMM:
     def phase_times(self) -> tuple[dict, int]:
         """(ms per phase summed since set_timing(True), number of vectors evaluated)."""
         return fmmhp_plan_phase_times(self._plan)
+
+    def m2l_kernel_times(self) -> tuple[float, int]:
+        """(summed ms of the upper-source M2L kernel's launches since set_timing(True), launches)."""
+        return fmmhp_plan_m2l_kernel_times(self._plan)
 
     def __call__(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """phi = A q.  q: [N] or [n_vec, N], real or complex.  Returns complex128 [n_out] or

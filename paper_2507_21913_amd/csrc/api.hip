@@ -455,7 +455,8 @@ fmmhp_status fmmhp_plan_set_timing(fmmhp_plan_t plan, int enable) {
     Sched &S = plan->sched;
     if (!S.events) {
         S.events = new (std::nothrow) std::vector<hipEvent_t>();
-        if (!S.events) {
+        S.m2l_n = new (std::nothrow) std::vector<int>();
+        if (!S.events || !S.m2l_n) {
             set_error("host allocation failed");
             return FMMHP_ENOMEM;
         }
@@ -463,6 +464,8 @@ fmmhp_status fmmhp_plan_set_timing(fmmhp_plan_t plan, int enable) {
     FMMHP_CHECK(collect_phase_times(S));
     for (double &v : S.phase_ms) v = 0.0;
     S.timed_evals = 0;
+    S.m2l_kernel_ms = 0.0;
+    S.m2l_launches = 0;
     S.timing = enable != 0;
     return FMMHP_OK;
 }
@@ -476,6 +479,18 @@ fmmhp_status fmmhp_plan_phase_times(fmmhp_plan_t plan, double *ms, int64_t *n_ev
     FMMHP_CHECK(collect_phase_times(plan->sched));
     for (int k = 0; k < FMMHP_NUM_PHASES; ++k) ms[k] = plan->sched.phase_ms[k];
     if (n_evals) *n_evals = plan->sched.timed_evals;
+    return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_plan_m2l_kernel_times(fmmhp_plan_t plan, double *ms, int64_t *n_launches) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!ms) {
+        set_error("ms is NULL");
+        return FMMHP_EINVAL;
+    }
+    FMMHP_CHECK(collect_phase_times(plan->sched));
+    *ms = plan->sched.m2l_kernel_ms;
+    if (n_launches) *n_launches = plan->sched.m2l_launches;
     return FMMHP_OK;
 }
 
@@ -527,6 +542,8 @@ fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
         delete plan->sched.events;
         plan->sched.events = nullptr;
     }
+    delete plan->sched.m2l_n;
+    plan->sched.m2l_n = nullptr;
     if (plan->sched.ev_fork) (void)hipEventDestroy(plan->sched.ev_fork);
     if (plan->sched.ev_join) (void)hipEventDestroy(plan->sched.ev_join);
     if (plan->sched.side) (void)hipStreamDestroy(plan->sched.side);

@@ -2133,6 +2133,8 @@ struct Marks {
     hipEvent_t ev[FMMHP_NUM_PHASES + 1];  // main-stream boundaries; the NEAR slot pair is unused
     hipEvent_t near0 = nullptr, near1 = nullptr;
     hipEvent_t deep0 = nullptr, deep1 = nullptr;  // deep-level M2L on the second stream
+    hipEvent_t km[4] = {nullptr, nullptr, nullptr, nullptr};  // k_m2l launches: deep (0, 1), coarse (2, 3)
+    bool km_rec[2] = {false, false};
     bool on = false;
     fmmhp_status init(const Sched &S) {
         on = S.timing;
@@ -2142,19 +2144,39 @@ struct Marks {
         FMMHP_HIP(hipEventCreate(&near1));
         FMMHP_HIP(hipEventCreate(&deep0));
         FMMHP_HIP(hipEventCreate(&deep1));
+        for (auto &e : km) FMMHP_HIP(hipEventCreate(&e));
+        return FMMHP_OK;
+    }
+    // bracket one k_m2l launch (k = 0 deep, 1 coarse) on its stream
+    fmmhp_status km_mark(int k, int end, hipStream_t st) {
+        if (!on) return FMMHP_OK;
+        FMMHP_HIP(hipEventRecord(km[2 * k + end], st));
+        km_rec[k] = true;
         return FMMHP_OK;
     }
     fmmhp_status mark(int k, hipStream_t s) {
         if (on) FMMHP_HIP(hipEventRecord(ev[k], s));
         return FMMHP_OK;
     }
-    void commit(const Sched &S) {
-        if (!on) return;
+    fmmhp_status commit(const Sched &S, hipStream_t s) {
+        if (!on) return FMMHP_OK;
+        int n = 0;
+        for (int k = 0; k < 2; ++k) {
+            if (km_rec[k]) {
+                ++n;
+            } else {  // no launch: an empty pair
+                FMMHP_HIP(hipEventRecord(km[2 * k], s));
+                FMMHP_HIP(hipEventRecord(km[2 * k + 1], s));
+            }
+        }
         for (auto &e : ev) S.events->push_back(e);
         S.events->push_back(near0);
         S.events->push_back(near1);
         S.events->push_back(deep0);
         S.events->push_back(deep1);
+        for (auto &e : km) S.events->push_back(e);
+        S.m2l_n->push_back(n);
+        return FMMHP_OK;
     }
 };
 
@@ -2227,8 +2249,11 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
             } else {
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
                            S.tile_mask, S.Tfree, S.Lfree, S.logside,  S.W,            S.Lam,      S.nloc};
+                const int which = st == s ? 1 : 0;
+                FMMHP_CHECK(mk_.km_mark(which, 0, st));
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)), 0,
                                    st, ma);
+                FMMHP_CHECK(mk_.km_mark(which, 1, st));
             }
         }
         const int i0 = S.ibox_lev[l0], i1 = S.ibox_lev[l1];
@@ -2319,7 +2344,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_NEAR, s));
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));
-    mk_.commit(S);
+    FMMHP_CHECK(mk_.commit(S, s));
     return FMMHP_OK;
 }
 
@@ -2619,9 +2644,9 @@ fmmhp_status run_field(Arena &A, const Tree &T, Sched &S, const double *q, doubl
 fmmhp_status collect_phase_times(Sched &S) {
     if (!S.events) return FMMHP_OK;
     auto &ev = *S.events;
-    // group: main-stream boundaries [0, NUM_PHASES], near pair, deep-M2L pair
-    const int G = FMMHP_NUM_PHASES + 5;
-    for (size_t g0 = 0; g0 + G <= ev.size(); g0 += G) {
+    // group: main-stream boundaries [0, NUM_PHASES], near pair, deep-M2L pair, k_m2l pairs
+    const int G = FMMHP_NUM_PHASES + 9;
+    for (size_t g0 = 0, gi = 0; g0 + G <= ev.size(); g0 += G, ++gi) {
         const size_t n0 = g0 + FMMHP_NUM_PHASES + 1, d0 = n0 + 2;
         FMMHP_HIP(hipEventSynchronize(ev[g0 + FMMHP_NUM_PHASES]));
         FMMHP_HIP(hipEventSynchronize(ev[n0 + 1]));
@@ -2640,9 +2665,18 @@ fmmhp_status collect_phase_times(Sched &S) {
             S.phase_ms[k] += ms;
         }
         S.timed_evals += 1;
+        const size_t k0 = d0 + 2;
+        for (int k = 0; k < 2; ++k) {
+            FMMHP_HIP(hipEventSynchronize(ev[k0 + 2 * k + 1]));
+            float ms = 0.f;
+            FMMHP_HIP(hipEventElapsedTime(&ms, ev[k0 + 2 * k], ev[k0 + 2 * k + 1]));
+            S.m2l_kernel_ms += ms;
+        }
+        S.m2l_launches += (*S.m2l_n)[gi];
     }
     for (auto e : ev) (void)hipEventDestroy(e);
     ev.clear();
+    S.m2l_n->clear();
     return FMMHP_OK;
 }
 

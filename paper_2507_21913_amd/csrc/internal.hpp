@@ -210,9 +210,12 @@ struct Sched {
     int64_t m2l_pairs[2] = {0, 0};
     // phase timing (profiling aid)
     bool timing = false;
-    std::vector<hipEvent_t> *events = nullptr;   // groups of (FMMHP_NUM_PHASES + 1)
+    std::vector<hipEvent_t> *events = nullptr;   // per timed pass: phase boundaries, near, deep, k_m2l pairs
+    std::vector<int> *m2l_n = nullptr;            // per timed pass: k_m2l launches (0, 1 or 2)
     double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t timed_evals = 0;
+    double m2l_kernel_ms = 0.0;                   // summed k_m2l launch durations since timing was enabled
+    int64_t m2l_launches = 0;
 };
 
 // Zs: [T.n_inst] impedance of each instance (host)

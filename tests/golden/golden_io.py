@@ -21,6 +21,19 @@ def grad_path_for(name: str) -> str:
     return os.path.join(HERE, f"{name}_grad_sample{N_SAMPLE}.txt")
 
 
+def dlp_path_for(name: str) -> str:
+    return os.path.join(HERE, f"{name}_dlp_sample{N_SAMPLE}.txt")
+
+
+def load_dlp(name: str):
+    """(indices, complex values) from a stored double-layer file, or None if absent."""
+    p = dlp_path_for(name)
+    if not os.path.exists(p):
+        return None
+    a = np.loadtxt(p, comments="#")
+    return a[:, 0].astype(np.int64), a[:, 1] + 1j * a[:, 2]
+
+
 def forest_path() -> str:
     return os.path.join(HERE, "batched_forest_direct_sample.txt")
 

@@ -5,7 +5,7 @@ Calls only the CPU oracle (``oracle.direct``, ``oracle.grad``) and the seeded ge
 targets against ALL sources, written as text (index, Re phi, Im phi); for the differentiation
 workload also the direct-sum gradients at a sample of indices (index, dl/dq, dl/dx, dl/dy).
 
-    python tests/golden/make_golden.py [name ... | grad:name ... | forest | example2]
+    python tests/golden/make_golden.py [name ... | grad:name ... | dlp:name ... | forest | example2]
 
 The readers (load, load_grad, load_forest) live in golden_io.py, which imports no oracle code.
 """
@@ -74,6 +74,27 @@ def write_grad(name: str) -> str:
     return p
 
 
+def write_dlp(name: str) -> str:
+    """The double-layer potential of the workload's charges as dipole densities, with the seeded
+    normals of ``workloads.source_normals(N, seed=7)``, at the sampled targets against all sources."""
+    from golden_io import dlp_path_for
+    w = GOLDEN[name]()
+    nx, ny = workloads.source_normals(w.n, seed=7)
+    idx = workloads.sample_targets(w.n, N_SAMPLE)
+    t0 = time.time()
+    phi = D.double_layer(w.x, w.y, nx, ny, w.q[0], w.impedance, xt=w.x[idx], yt=w.y[idx])
+    dt = time.time() - t0
+    p = dlp_path_for(name)
+    with open(p, "w") as f:
+        f.write(f"# oracle double layer, workload {name} (seed 1, N={w.n}, impedance {w.impedance}), densities "
+                f"= charges, normals source_normals(N, seed=7), {N_SAMPLE} sampled targets x all sources; "
+                f"columns: index re im\n")
+        for i, v in zip(idx, phi):
+            f.write(f"{int(i)} {v.real:.17e} {v.imag:.17e}\n")
+    print(f"{name} double layer: {dt:.1f} s -> {p}", flush=True)
+    return p
+
+
 FOREST_SAMPLE = {"instances": (0, 137, 300, 511), "vectors": (0, 63), "targets": 32}
 
 
@@ -116,9 +137,12 @@ def write_example2() -> str:
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN] + ["forest", "example2"]):
+    for name in (sys.argv[1:] or list(GOLDEN) + ["grad:" + k for k in GRAD_GOLDEN]
+                 + ["dlp:uniform_1m", "forest", "example2"]):
         if name.startswith("grad:"):
             write_grad(name[5:])
+        elif name.startswith("dlp:"):
+            write_dlp(name[4:])
         elif name == "forest":
             write_forest()
         elif name == "example2":

@@ -5,7 +5,10 @@ configuration bench.py times (p = 30, leaf 40):
 * potentials against the oracle's direct sum at 256 stored sample targets (all sources), written
   by tests/golden/make_golden.py: rel-l2 <= 1e-10;
 * for a real impedance, the imaginary part at ALL targets against its exact O(N) closed form;
-* error vs p decreasing geometrically (p = 10, 20, 30).
+* error vs p decreasing geometrically (p = 10, 20, 30);
+* the double-layer potential of the uniform workload (its charges as densities, seeded normals)
+  against the oracle at the same stored sample targets, at p = 20 / leaf 32 (the bench's shape) and
+  p = 30 / leaf 40.
 """
 import os
 import sys
@@ -20,7 +23,7 @@ from oracle import direct as D
 from oracle import tree as T
 
 sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
-from golden_io import load  # noqa: E402
+from golden_io import load, load_dlp  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -108,3 +111,19 @@ def test_diff_1m_potential():
     print(f"diff_1m p=30 impedance 2: rel-l2 {err:.3e}, Im max rel {err_im:.3e}", flush=True)
     assert err < 1e-10
     assert err_im < 1e-12
+
+
+@pytest.mark.parametrize("p,leaf,tol", [(20, 32, 1e-8), (30, 40, 1e-11)])
+def test_uniform_1m_double_layer_vs_oracle_sample(uniform, p, leaf, tol):
+    w, x, y, q = uniform
+    g = load_dlp("uniform_1m")
+    if g is None:
+        pytest.skip("stored double-layer values absent (tests/golden/make_golden.py dlp:uniform_1m)")
+    idx, ref = g
+    nx, ny = workloads.source_normals(w.n, seed=7)
+    plan = F.HalfPlaneFMM(x, y, 1.0, p=p, leaf_size=leaf)
+    got = plan.double_layer(q, _t(nx), _t(ny)).cpu().numpy()
+    plan.close()
+    err = D.rel_l2(got[idx], ref)
+    print(f"uniform 1M double layer p={p} leaf={leaf}: rel-l2 at 256 samples {err:.2e}", flush=True)
+    assert np.all(np.isfinite(got)) and err < tol

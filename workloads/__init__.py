@@ -183,6 +183,12 @@ def example2_sized(n_total: int):
     return example2(n_source, nx, ny)
 
 
+def source_normals(n: int, seed: int = 7):
+    """Unit normals (nx, ny) at n source points, angles uniform on [0, 2 pi) (double-layer inputs)."""
+    th = np.random.default_rng(seed).uniform(0.0, 2.0 * np.pi, n)
+    return np.cos(th), np.sin(th)
+
+
 def sample_targets(n: int, k: int, seed: int = 12345) -> np.ndarray:
     """Fixed-seed sorted subset of k target indices out of n."""
     rng = np.random.default_rng(seed)
