@@ -261,6 +261,22 @@ fmmhp_status fmmhp_eval_double_layer(fmmhp_plan_t plan, int n_vec, const double 
 fmmhp_status fmmhp_eval_field(fmmhp_plan_t plan, const double *q, double *phi, double *grad_x, double *grad_y,
                               hipStream_t stream);
 
+/* The normal derivative of the potential of one real charge vector at the targets, for the
+ * second-kind boundary-integral uses of the paper's introduction:
+ *
+ *   dphi_i = n_i . grad phi(r_i) = n_x d_x phi + n_y d_y phi,
+ *
+ * from the field of fmmhp_eval_field (same expansions, same coincidence rule).
+ *
+ *   q        [device] [n_src] real charges
+ *   nx, ny   [device] [n_tgt] target normals (the result is linear in them)
+ *   dphi     [device] output, [n_tgt][2] complex
+ *
+ * The first call allocates 48 bytes per target of workspace (plus that of fmmhp_eval_field).
+ * Asynchronous on stream.  FMMHP_EINVAL for a NULL pointer. */
+fmmhp_status fmmhp_eval_normal_derivative(fmmhp_plan_t plan, const double *q, const double *nx, const double *ny,
+                                          double *dphi, hipStream_t stream);
+
 /* Adjoint of fmmhp_eval for one real charge vector: gradients of a real loss l of phi with respect
  * to the charges, the point positions and the impedance (the reverse-mode step of phi = A q; the
  * paper's Green's function, eqs. (1.2) and (reactdecomposition), differentiated).

@@ -84,6 +84,7 @@ _SIGNATURES = {
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_eval_field": [_P, _P, _P, _P, _P, _P],
     "fmmhp_eval_double_layer": [_P, _INT, _P, _INT, _P, _P, _P, _P],
+    "fmmhp_eval_normal_derivative": [_P, _P, _P, _P, _P, _P],
     "fmmhp_plan_info": [_P, ctypes.POINTER(PlanStats)],
     "fmmhp_plan_export_tree": [_P] + [_P] * 18,
     "fmmhp_plan_destroy": [_P],
@@ -444,6 +445,26 @@ class HalfPlaneFMM:
                                                                raw[1].data_ptr(), raw[2].data_ptr(), _stream()))
         c = torch.view_as_complex(raw)
         return c[0], c[1], c[2]
+
+    def normal_derivative(self, q: torch.Tensor, nx: torch.Tensor, ny: torch.Tensor) -> torch.Tensor:
+        """n . grad phi at the targets for one real charge vector q [N] and target normals nx, ny
+        [n_out]: complex128 [n_out]."""
+        for name, t in (("q", q), ("nx", nx), ("ny", ny)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.is_complex():
+                raise TypeError(f"{name} must be a real GPU tensor")
+        if q.numel() != self.n:
+            raise ValueError(f"q has {q.numel()} points, plan has {self.n}")
+        if nx.numel() != self.n_out or ny.numel() != self.n_out:
+            raise ValueError(f"nx, ny must have {self.n_out} entries (one per target)")
+        qd = q.reshape(-1).to(torch.float64).contiguous()
+        nxd = nx.reshape(-1).to(torch.float64).contiguous()
+        nyd = ny.reshape(-1).to(torch.float64).contiguous()
+        raw = torch.empty((self.n_out, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check("fmmhp_eval_normal_derivative",
+                   lib().fmmhp_eval_normal_derivative(self._plan, qd.data_ptr(), nxd.data_ptr(), nyd.data_ptr(),
+                                                      raw.data_ptr(), _stream()))
+        return torch.view_as_complex(raw)
 
     def double_layer(self, mu: torch.Tensor, nx: torch.Tensor, ny: torch.Tensor) -> torch.Tensor:
         """Double-layer potential sum_j mu_j n_j . grad_{r_j} G(r_i, r_j) at the targets for dipole

@@ -389,6 +389,33 @@ fmmhp_status fmmhp_eval_field(fmmhp_plan_t plan, const double *q, double *phi, d
     return FMMHP_OK;
 }
 
+// dphi[i] = nx[i] g[0][i] + ny[i] g[1][i] (complex, [n][2])
+__global__ void k_normal_combine(const double *__restrict__ gx, const double *__restrict__ gy,
+                                 const double *__restrict__ nx, const double *__restrict__ ny, int64_t n,
+                                 double *__restrict__ dphi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dphi[2 * i] = fma(nx[i], gx[2 * i], ny[i] * gy[2 * i]);
+    dphi[2 * i + 1] = fma(nx[i], gx[2 * i + 1], ny[i] * gy[2 * i + 1]);
+}
+
+fmmhp_status fmmhp_eval_normal_derivative(fmmhp_plan_t plan, const double *q, const double *nx, const double *ny,
+                                          double *dphi, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!q || !nx || !ny || !dphi) {
+        set_error("q, nx, ny and dphi must be non-NULL");
+        return FMMHP_EINVAL;
+    }
+    const int64_t nt = plan->tree.n - plan->n_src;
+    if (!plan->ndwork) FMMHP_CHECK(plan->arena.alloc_n(&plan->ndwork, (size_t)6 * nt, "normal-derivative workspace"));
+    double *w = plan->ndwork;
+    FMMHP_CHECK(fmmhp_eval_field(plan, q, w, w + 2 * nt, w + 4 * nt, stream));
+    hipLaunchKernelGGL(k_normal_combine, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, w + 2 * nt,
+                       w + 4 * nt, nx, ny, nt, dphi);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
+}
+
 fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
                             double *grad_x, double *grad_y, double *grad_lambda, hipStream_t stream) {
     FMMHP_CHECK(check_plan(plan));

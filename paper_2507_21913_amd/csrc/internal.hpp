@@ -259,6 +259,7 @@ struct fmmhp_plan_s {
     double *qpad = nullptr, *phipad = nullptr;  // [cap][n] (x2 for complex charges), [cap][n][2]
     double *gpad = nullptr;                     // [2][n][2] gradients at all points (fmmhp_eval_field)
     double *npad = nullptr;                     // [2][n] normals padded to all points (double layer)
+    double *ndwork = nullptr;                   // [3][n_tgt][2] field at the targets (normal derivative)
     int pad_cap = 0;
     int p_req, leaf_size, max_level;
     double lambda_re, lambda_im;

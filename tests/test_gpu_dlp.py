@@ -151,3 +151,32 @@ def test_invalid_arguments():
     with pytest.raises(ValueError):
         plan.double_layer(m, a[:-1], b)
     plan.close()
+
+
+@pytest.mark.parametrize("Z", [1.0, 1.0 + 0.5j])
+def test_normal_derivative_at_targets(ex2, Z):
+    """fmmhp_eval_normal_derivative at the Example 2 mesh with seeded target normals, against the
+    oracle's field at the same targets projected on the normals."""
+    from oracle import grad as GR
+    d = ex2
+    th = np.random.default_rng(17).uniform(0.0, 2.0 * np.pi, d["tgt_x"].size)
+    tnx, tny = np.cos(th), np.sin(th)
+    plan = F.HalfPlaneFMM.with_targets(_t(d["src_x"]), _t(d["src_y"]), _t(d["tgt_x"]), _t(d["tgt_y"]), Z,
+                                       p=30, leaf_size=24)
+    got = plan.normal_derivative(_t(d["q"]), _t(tnx), _t(tny)).cpu().numpy()
+    plan.close()
+    gx, gy = GR.field_at(d["src_x"], d["src_y"], d["q"], Z, d["tgt_x"], d["tgt_y"], workers=8)
+    ref = tnx * gx + tny * gy
+    err = D.rel_l2(got, ref)
+    print(f"Z={Z} normal derivative at the Example 2 mesh: rel-l2 {err:.2e}", flush=True)
+    assert err < 1e-10
+
+
+def test_normal_derivative_sources_as_targets():
+    from oracle import grad as GR
+    x, y, nx, ny, mu = _problem(3000, 23)
+    plan = F.HalfPlaneFMM(_t(x), _t(y), 2.0, p=30, leaf_size=20)
+    got = plan.normal_derivative(_t(mu), _t(nx), _t(ny)).cpu().numpy()
+    plan.close()
+    rx, ry = GR.potential_gradient(x, y, mu, 2.0)
+    assert D.rel_l2(got, nx * rx + ny * ry) < 1e-10
