@@ -1046,6 +1046,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
             const double sg = fc.y < 0 ? a.isg : -1.0;  // image: +-log|r - r_img|, free: - log|r - r'|
             const bool last = e + 1 >= e1;
             const int jnext = last ? jend - 1 : fn.x;  // the point loaded after this entry's last
+#pragma unroll 2
             for (int j = j0; j < jend; ++j) {
                 const int jp = j + 1 < jend ? j + 1 : jnext;
                 const double2 pn = xy[jp];
@@ -1063,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], kv, acc[v]);
                 } else if (has_phi(MODE)) {
-                    const double sl = sg * log_tab(nz ? r2 : 1.0, tab);
+                    const double sl = sg * log_tab(r2, tab);  // finite for r2 = 0, masked below
 #pragma unroll
                     for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], nz ? sl : 0.0, acc[v]);
                 }

@@ -77,7 +77,8 @@ __device__ __forceinline__ double log_pos(double x) {
 // x = 2^e m, m in [1, 2); the top 9 bits of the mantissa select c_k = 1 + (k + 1/2)/512, and
 // log x = e ln 2 + L_k + log1p(t),  t = m r_k - 1,  r_k = fl(1/c_k),  L_k = -log(r_k),
 // with |t| <= 2^-10 so that log1p(t) = t - t^2/2 + t^3/3 - t^4/4 + t^5/5 leaves an error below
-// 2^-62.  The table entries (r_k, L_k) are built on the host by log_table_entry.
+// 2^-62.  The table entries (r_k, L_k) are built on the host by log_table_entry.  For x = +0 the
+// result is finite (about -709), so a caller may evaluate it unconditionally and mask the result.
 constexpr int kLogTable = 512;
 
 inline void log_table_entry(int k, double *r, double *L) {
