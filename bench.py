@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
 # (p, leaf size): reported (per launch) only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
-M2L_TRAFFIC = {("79d8e549df1bfeca", 20, 32): 167.1e6}
+M2L_TRAFFIC = {("4b4a0c03f9064b6e", 20, 32): 167.5e6}
 
 
 def eval_source_hash() -> str:
@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--p", type=int, default=0, help="truncation order (0: autotune for --tol)")
     ap.add_argument("--leaf", type=int, default=0, help="leaf size (0: autotune, or 40 with --p)")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--near-walk", type=int, default=0,
+                    help="near-field launch shape with --p (0: library default; see fmmhp_opts)")
+    ap.add_argument("--near-groups", type=int, default=0)
     ap.add_argument("--no-p30", action="store_true", help="skip the extra p=30 measurement")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -227,8 +230,10 @@ def main():
         tuned["tune_s"] = time.perf_counter() - t0
         p_use, leaf_use = tuned["p"], tuned["leaf_size"]
         shape = {"near_walk": tuned["near_walk"], "near_groups": tuned["near_groups"]}
-    elif a.leaf == 0:
-        leaf_use = 40
+    else:
+        if a.leaf == 0:
+            leaf_use = 40
+        shape = {"near_walk": a.near_walk, "near_groups": a.near_groups}
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
