@@ -134,6 +134,8 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
         (void)hipStreamSynchronize(stream);
         if (p->sched.ev_fork) (void)hipEventDestroy(p->sched.ev_fork);
         if (p->sched.ev_join) (void)hipEventDestroy(p->sched.ev_join);
+        if (p->sched.ev_up) (void)hipEventDestroy(p->sched.ev_up);
+
         if (p->sched.side) (void)hipStreamDestroy(p->sched.side);
         if (p->sched.side2) (void)hipStreamDestroy(p->sched.side2);
         if (p->sched.ev_deep_ready) (void)hipEventDestroy(p->sched.ev_deep_ready);
@@ -573,6 +575,8 @@ fmmhp_status fmmhp_plan_destroy(fmmhp_plan_t plan) {
     plan->sched.m2l_n = nullptr;
     if (plan->sched.ev_fork) (void)hipEventDestroy(plan->sched.ev_fork);
     if (plan->sched.ev_join) (void)hipEventDestroy(plan->sched.ev_join);
+    if (plan->sched.ev_up) (void)hipEventDestroy(plan->sched.ev_up);
+
     if (plan->sched.side) (void)hipStreamDestroy(plan->sched.side);
     if (plan->sched.side2) (void)hipStreamDestroy(plan->sched.side2);
     if (plan->sched.ev_deep_ready) (void)hipEventDestroy(plan->sched.ev_deep_ready);

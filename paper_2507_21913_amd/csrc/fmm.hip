@@ -627,8 +627,10 @@ __global__ __launch_bounds__(256) void k_m2l_f32(M2L32Args a) {
 }
 
 // Image V entries (target boxes in the two rows nearest y = 0 at each level): log M2L of the image
-// box plus the reaction M2L, one thread per (target box, output coefficient); adds to the locals
-// written by k_m2l.
+// box plus the reaction M2L; kImgSplit consecutive lanes per (target box, output coefficient), each
+// summing every kImgSplit-th V entry, combined by a butterfly; adds to the locals written by k_m2l.
+constexpr int kImgSplit = 4;
+
 template <int PB>
 __global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restrict__ ibox, int nbox, int nloc,
                                                  const int32_t *__restrict__ ibase,
@@ -638,38 +640,52 @@ __global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restr
                                                  const double *__restrict__ logside, double isg,
                                                  const cplx *__restrict__ W, cplx *__restrict__ Lam) {
     constexpr int NTP = m2l_row(PB);
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nib * (PB + 1)) return;
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gt / kImgSplit, part = gt % kImgSplit;
+    const bool ok = t < nib * (PB + 1);  // no early exit: every lane of a group joins the butterfly
     W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
     Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;
-    const int b = ibox[t % nib], n = t / nib;
-    const int l = ibase[b];  // table block of the box's (instance, level)
-    const double ll = logside[b] * kInv4Pi;
+    const int b = ok ? ibox[t % nib] : 0, n = ok ? t / nib : 0;
     cplx aH = mk(0.0, 0.0), aG = mk(0.0, 0.0), a0 = mk(0.0, 0.0);
-    for (int e = vimg_off[b]; e < vimg_off[b + 1]; ++e) {
-        const int code = vimg_ent[e];
-        const int src = code >> 5, is = code & 31;
-        const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
-        const cplx *tg = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
+    if (ok) {
+        const int l = ibase[b];  // table block of the box's (instance, level)
+        const double ll = logside[b] * kInv4Pi;
+        for (int e = vimg_off[b] + part; e < vimg_off[b + 1]; e += kImgSplit) {
+            const int code = vimg_ent[e];
+            const int src = code >> 5, is = code & 31;
+            const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
+            const cplx *tg = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
 #pragma unroll
-        for (int m = 0; m <= PB; ++m) {
-            const cplx wm = conj(W[(int64_t)m * nbox + src]);
-            cfma(aH, th[m], wm);
-            if (nloc == 2) cfma(aG, tg[m], wm);
+            for (int m = 0; m <= PB; ++m) {
+                const cplx wm = conj(W[(int64_t)m * nbox + src]);
+                cfma(aH, th[m], wm);
+                if (nloc == 2) cfma(aG, tg[m], wm);
+            }
+            if (n == 0) cfma(a0, Limg[is] + mk(isg * ll, 0.0), conj(W[src]));
         }
-        if (n == 0) cfma(a0, Limg[is] + mk(isg * ll, 0.0), conj(W[src]));
     }
-    Lam[(int64_t)n * nbox + b] += a0 - aH;
-    if (nloc == 2) Lam[(int64_t)(PB + 1) * nbox + (int64_t)n * nbox + b] += a0 - aG;
+    cplx r = a0 - aH, rg = a0 - aG;
+    for (int off = 1; off < kImgSplit; off <<= 1) {
+        r.re += __shfl_xor(r.re, off);
+        r.im += __shfl_xor(r.im, off);
+        if (nloc == 2) {
+            rg.re += __shfl_xor(rg.re, off);
+            rg.im += __shfl_xor(rg.im, off);
+        }
+    }
+    if (ok && part == 0) {
+        Lam[(int64_t)n * nbox + b] += r;
+        if (nloc == 2) Lam[(int64_t)(PB + 1) * nbox + (int64_t)n * nbox + b] += rg;
+    }
 }
 
 __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nrow, cplx *__restrict__ Lam) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nb = hi - lo;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = hi - lo;
     if (i >= nb * ncoef * nrow) return;
-    const int b = lo + i % nb;
-    const int r = i / nb;  // (vector * nloc + loc) * ncoef + n
-    Lam[(int64_t)r * nbox + b] = mk(0.0, 0.0);
+    const int64_t b = lo + i % nb;
+    const int64_t r = i / nb;  // (vector * nloc + loc) * ncoef + n
+    Lam[r * nbox + b] = mk(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1277,7 +1293,8 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
 }
 
 // W list for the targets whose leaf has one: multipoles of smaller non-adjacent boxes evaluated
-// at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to the outputs.
+// at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to the near-field
+// sums (before k_leaf reads them).
 template <int PB, int MODE>
 __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1356,19 +1373,21 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
             }
         }
     }
-    const int64_t o = a.perm[i];
+    // into the near-field sums of the target (sorted order), which k_leaf adds to the far field
     if (has_phi(MODE)) {
-        double *out = a.phi + (int64_t)v * 2 * a.n;
+        double2 *nr = a.near + (int64_t)v * a.n + i;
+        double2 hv = *nr;
         if (a.nloc == 1) {
-            out[2 * o] += 2.0 * H.re;
+            hv.x += 2.0 * H.re;
         } else {
-            const cplx hv = H + conj(G);
-            out[2 * o] += hv.re;
-            out[2 * o + 1] += hv.im;
+            const cplx c = H + conj(G);
+            hv.x += c.re;
+            hv.y += c.im;
         }
+        *nr = hv;
     }
     if (has_grad(MODE)) {
-        cplx *gx = a.gx + (int64_t)v * a.n + o, *gy = a.gy + (int64_t)v * a.n + o;
+        cplx *gx = a.near_gx + (int64_t)v * a.n + i, *gy = a.near_gy + (int64_t)v * a.n + i;
         if (a.nloc == 1) {
             *gx += mk(2.0 * Hd.re, 0.0);
             *gy += mk(-2.0 * Hd.im, 0.0);
@@ -1844,37 +1863,50 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         FMMHP_CHECK(to_host(cfirst, T.child_first, nbox, s));
         FMMHP_CHECK(to_host(nch, T.nchild, nbox, s));
         FMMHP_HIP(hipStreamSynchronize(s));
-        const int lc = S.sub_level, r0 = T.lev_start[lc];
-        S.n_sub = T.lev_start[lc + 1] - r0;
-        S.sub_nlev = T.depth - lc + 1;
-        std::vector<int2> rng((size_t)S.n_sub * S.sub_nlev, make_int2(0, 0));
-        for (int r = 0; r < S.n_sub; ++r) {
-            int a = r0 + r, b = a + 1;
-            for (int k = 0; k < S.sub_nlev && a < b; ++k) {
-                rng[(size_t)r * S.sub_nlev + k] = make_int2(a, b);
-                int na = -1, nb = -1;
-                for (int x = a; x < b; ++x)
-                    if (!leaf[x]) {
-                        if (na < 0) na = cfirst[x];
-                        nb = cfirst[x] + nch[x];
-                    }
-                if (na < 0) break;
-                a = na;
-                b = nb;
+        // box ranges per level of the subtrees rooted at the boxes of level lr, nlev levels deep;
+        // returns the largest subtree's box count
+        auto subtree_ranges = [&](int lr, int nlev, std::vector<int2> &rng) {
+            const int r0 = T.lev_start[lr], nr = T.lev_start[lr + 1] - r0;
+            rng.assign((size_t)nr * nlev, make_int2(0, 0));
+            int maxtot = 0;
+            for (int r = 0; r < nr; ++r) {
+                int a = r0 + r, b = a + 1, tot = 0;
+                for (int k = 0; k < nlev && a < b; ++k) {
+                    rng[(size_t)r * nlev + k] = make_int2(a, b);
+                    tot += b - a;
+                    int na = -1, nb = -1;
+                    for (int x = a; x < b; ++x)
+                        if (!leaf[x]) {
+                            if (na < 0) na = cfirst[x];
+                            nb = cfirst[x] + nch[x];
+                        }
+                    if (na < 0) break;
+                    a = na;
+                    b = nb;
+                }
+                maxtot = std::max(maxtot, tot);
             }
-        }
+            return maxtot;
+        };
+        const int lc = S.sub_level;
+        S.n_sub = T.lev_start[lc + 1] - T.lev_start[lc];
+        S.sub_nlev = T.depth - lc + 1;
+        std::vector<int2> rng;
+        const int maxtot = subtree_ranges(lc, S.sub_nlev, rng);
         FMMHP_CHECK(to_dev(A, &S.sub_rng, rng, "subtree ranges", s));
         // resident LDS rows: enough for the largest subtree, within 48 KB of expansions per block
-        int maxtot = 0;
-        for (int r = 0; r < S.n_sub; ++r) {
-            int tot = 0;
-            for (int k = 0; k < S.sub_nlev; ++k)
-                tot += rng[(size_t)r * S.sub_nlev + k].y - rng[(size_t)r * S.sub_nlev + k].x;
-            maxtot = std::max(maxtot, tot);
-        }
         const int cap = std::min(kSubMaxSlots, (int)(48 * 1024 / ((PB + 1) * sizeof(cplx))));
         S.sub_ld_m2m = std::max(4 * kM2MParents, std::min(maxtot, cap));
         S.sub_ld_l2l = std::max(kL2LChildren, std::min(maxtot * S.nloc, cap));
+        // the L2L levels 4..lc in one launch of level-3-rooted subtrees (after level 3's own L2L)
+        if (lc >= 5) {
+            S.top_nlev = lc - 3 + 1;
+            S.n_top = T.lev_start[4] - T.lev_start[3];
+            std::vector<int2> trng;
+            const int tmax = subtree_ranges(3, S.top_nlev, trng);
+            FMMHP_CHECK(to_dev(A, &S.top_rng, trng, "top subtree ranges", s));
+            S.top_ld_l2l = std::max(kL2LChildren, std::min(tmax * S.nloc, cap));
+        }
     }
     {
         std::vector<int32_t> woff, first, wp, rl;
@@ -2112,6 +2144,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     }
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
     FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_up, hipEventDisableTiming));
     hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
     FMMHP_HIP(hipGetLastError());
     FMMHP_HIP(hipStreamSynchronize(s));
@@ -2231,7 +2264,6 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         FMMHP_HIP(hipGetLastError());
     }
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
-    FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB, DIP>), dim3(nblk((int64_t)T.nleaf * kP2MSplit, 256), NV), dim3(256),
                        0, s, S.inst_info, T.inst, S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count,
                        T.xs, T.ys, S.qs, S.nrm, S.W);
@@ -2259,7 +2291,8 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         }
         const int i0 = S.ibox_lev[l0], i1 = S.ibox_lev[l1];
         if (i1 > i0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>), dim3(nblk((int64_t)(i1 - i0) * (PB + 1), 256), NV),
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>),
+                               dim3(nblk((int64_t)(i1 - i0) * (PB + 1) * kImgSplit, 256), NV),
                                dim3(256), 0, st, i1 - i0, S.ibox + i0, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
                                S.TimgH, S.TimgG, S.Limg, S.logside, S.bc == 2 ? -1.0 : 1.0, S.W, S.Lam);
         const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
@@ -2299,10 +2332,22 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         if (ld > 0 && l == lf) FMMHP_CHECK(fork_deep());
     }
     FMMHP_HIP(hipGetLastError());
+    // the W list (M2P) needs every multipole and adds into the near-field sums.  With the plain
+    // near-field walk (chosen when the far field dominates, so the near-field stream has slack) it
+    // runs on that stream once the upward pass is done; otherwise on the main stream before k_leaf.
+    const bool w_side = S.n_wpts > 0 && S.near_walk == 2;
+    if (w_side) {
+        FMMHP_HIP(hipEventRecord(S.ev_up, s));
+        FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_up, 0));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, S.side,
+                           la);
+        FMMHP_HIP(hipGetLastError());
+    }
+    FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
     {
         const int lo = T.lev_start[1], hi = T.lev_start[2];
-        const int tot = (hi - lo) * (PB + 1) * S.nloc * NV;
+        const int64_t tot = (int64_t)(hi - lo) * (PB + 1) * S.nloc * NV;
         if (tot > 0)
             hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc * NV,
                                S.Lam);
@@ -2311,14 +2356,21 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_L2L, s));
     const int l2l_end = lc > 0 ? lc : T.depth;
-    for (int l = 3; l <= l2l_end; ++l) {
-        if (ld > 0 && l == ld) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
+    // with a top subtree pass, levels 4..lc run in one launch after level 3's
+    const int l2l_last = S.n_top > 0 ? 3 : l2l_end;
+    if (S.n_top > 0 && ld > 0 && ld <= l2l_end) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
+    for (int l = 3; l <= l2l_last; ++l) {
+        if (S.n_top == 0 && ld > 0 && l == ld) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256),
                                (PB + 1) * kL2LChildren * sizeof(cplx), s, lo, nb,
                                nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     }
+    if (S.n_top > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_top, NV), dim3(256),
+                           (PB + 1) * S.top_ld_l2l * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_l2l, nbox,
+                           S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
     if (ld > 0 && ld > l2l_end) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
     if (lc > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_sub, NV), dim3(256),
@@ -2338,10 +2390,10 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     }
     FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
+    if (S.n_wpts > 0 && !w_side)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, s, la);
     // dipoles differ from charges only in the source terms: the L2P and M2P kernels are the potential's
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, LM>), dim3(nblk(T.n, 256), NV), dim3(256), 0, s, la);
-    if (S.n_wpts > 0)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, s, la);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_NEAR, s));
     FMMHP_CHECK(mk_.mark(FMMHP_NUM_PHASES, s));

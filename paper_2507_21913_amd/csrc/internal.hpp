@@ -166,7 +166,11 @@ struct Sched {
     int n_sub = 0, sub_nlev = 0;    // subtrees (the boxes of the cut level), levels cut..depth
     int2 *sub_rng = nullptr;        // [n_sub][sub_nlev] box range of each subtree per level
     int sub_ld_m2m = 0, sub_ld_l2l = 0;  // LDS expansion slots of the subtree passes
+    // L2L of levels 4..cut in one launch: subtrees rooted at level 3 (0 subtrees: one launch per level)
+    int n_top = 0, top_nlev = 0, top_ld_l2l = 0;
+    int2 *top_rng = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_up = nullptr;  // upward pass done (main stream)
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     bool m2l_fp32 = false;          // FMMHP_FLAG_M2L_FP32: upper-source M2L on the FP32 matrix cores
