@@ -1062,6 +1062,9 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
             const double sg = fc.y < 0 ? a.isg : -1.0;  // image: +-log|r - r_img|, free: - log|r - r'|
             const bool last = e + 1 >= e1;
             const int jnext = last ? jend - 1 : fn.x;  // the point loaded after this entry's last
+            double ea[NV];  // this entry's sum, its sign applied once after the loop
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ea[v] = 0.0;
 #pragma unroll 2
             for (int j = j0; j < jend; ++j) {
                 const int jp = j + 1 < jend ? j + 1 : jnext;
@@ -1076,13 +1079,13 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 // target-only points on y = 0 (no charge); image distances to sources are positive
                 const bool nz = r2 > 0.0;
                 if (is_dip(MODE)) {
-                    const double kv = nz ? sg * rcp_pos(nz ? r2 : 1.0) * fma(ysg * nj.y, dy, -nj.x * dx) : 0.0;
+                    const double kv = nz ? rcp_pos(nz ? r2 : 1.0) * fma(ysg * nj.y, dy, -nj.x * dx) : 0.0;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], kv, acc[v]);
+                    for (int v = 0; v < NV; ++v) ea[v] = fma(qj[v], kv, ea[v]);
                 } else if (has_phi(MODE)) {
-                    const double sl = sg * log_tab(r2, tab);  // finite for r2 = 0, masked below
+                    const double lg = log_tab(r2, tab);  // finite for r2 = 0, masked below
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] = fma(qj[v], nz ? sl : 0.0, acc[v]);
+                    for (int v = 0; v < NV; ++v) ea[v] = fma(qj[v], nz ? lg : 0.0, ea[v]);
                 }
                 if (has_grad(MODE)) {
                     const double sr = sg * rcp_pos(nz ? r2 : 1.0);
@@ -1098,6 +1101,10 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
                 nj = nn;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) qj[v] = qn[v];
+            }
+            if (has_phi(MODE)) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = fma(sg, ea[v], acc[v]);
             }
             if (last) break;
             ++e;
