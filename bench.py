@@ -179,6 +179,24 @@ def batched_extra(dev, p, leaf, steps):
         info = plan.info()
         res["tree"] = {"nbox": info["nbox"], "depth": info["depth"], "device_bytes": info["device_bytes"]}
         plan.close()
+        # the same forest with the upper-source M2L on the FP32 matrix cores
+        plan = F.HalfPlaneFMM.batched(xt, yt, off, lams.tolist(), p=p, leaf_size=leaf, graph=True, m2l_fp32=True)
+        out = torch.empty((nv, n), dtype=torch.complex128, device=dev)
+        plan(qt, out=out)
+        st.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            plan(qt, out=out)
+        e1.record(st)
+        st.synchronize()
+        ms32 = e0.elapsed_time(e1) / steps
+        r32 = {"ms_per_step": ms32, "mpts_s": n * nv / (ms32 * 1e-3) / 1e6, "over_fp64": ms / ms32}
+        if g is not None:
+            got = np.array([out[v, off[k] + i].item() for k, v, i in zip(ks, vs, idx)])
+            r32["rel_l2_vs_oracle_sample"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res["m2l_fp32"] = r32
+        del out
+        plan.close()
     # plain: one plan per instance, one vector at a time (vector 0 timed; the others are the same work)
     plans = [F.HalfPlaneFMM(xt[off[k]:off[k + 1]], yt[off[k]:off[k + 1]], float(lams[k]), p=p, leaf_size=leaf)
              for k in range(len(lams))]
