@@ -1718,7 +1718,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     S.m2l_pairs[0] = S.m2l_pairs[1] = 0;
     for (size_t e = 0; e < vent.size(); ++e) S.m2l_pairs[vent[e] & 1] += 1;
 
-    // M2L slots
+    // M2L slots: vslot[b * kNumSlots + o] = upper V source of box b at offset slot o, or -1
     std::vector<int32_t> vslot((size_t)kNumSlots * nbox, -1);
     std::vector<int32_t> vimg_off(nbox + 1, 0), vimg_ent;
     for (int b = 0; b < nbox; ++b) {
@@ -1733,7 +1733,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 return FMMHP_EUNSUPPORTED;
             }
             if (!img) {
-                vslot[(size_t)slot_of(dx, dy) * nbox + b] = c;
+                vslot[(size_t)b * kNumSlots + slot_of(dx, dy)] = c;
             } else {
                 if (dy > -1) {
                     set_error("internal: image V entry above its target");
@@ -1768,6 +1768,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     {
         std::vector<int32_t> seq;                  // boxes grouped by (level, class), Morton order
         std::vector<int32_t> uniq;
+        std::vector<int32_t> pos(nbox, -1);        // a source's index in uniq (reset after each tile)
         S.tile_lev.assign(T.depth + 2, 0);
         for (int l = 2; l <= T.depth; ++l) {
         S.tile_lev[l] = (int)tlev.size();
@@ -1781,15 +1782,20 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         }
         for (size_t ti = 0; ti < todo.size(); ++ti) {
             const int lo = todo[ti].first, hi = todo[ti].second;
+            // distinct sources of the tile, ascending
             uniq.clear();
-            for (int q = lo; q < hi; ++q)
-                for (int o = 0; o < kNumSlots; ++o) {
-                    const int c = vslot[(size_t)o * nbox + seq[q]];
-                    if (c >= 0) uniq.push_back(c);
-                }
+            for (int q = lo; q < hi; ++q) {
+                const int32_t *vs = &vslot[(size_t)seq[q] * kNumSlots];
+                for (int o = 0; o < kNumSlots; ++o)
+                    if (vs[o] >= 0 && pos[vs[o]] < 0) {
+                        pos[vs[o]] = 0;
+                        uniq.push_back(vs[o]);
+                    }
+            }
             std::sort(uniq.begin(), uniq.end());
-            uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+            for (int i = 0; i < (int)uniq.size(); ++i) pos[uniq[i]] = i;
             if ((int)uniq.size() > (S.m2l_fp32 ? kM2LMaxSrc32 : kM2LMaxSrc)) {
+                for (int c : uniq) pos[c] = -1;
                 const int mid = lo + (hi - lo) / 2;
                 todo.push_back({lo, mid});
                 todo.push_back({mid, hi});
@@ -1803,14 +1809,14 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 const int b = q < hi ? seq[q] : -1;
                 tiles.push_back(b);
                 if (b < 0) continue;
+                const int32_t *vs = &vslot[(size_t)b * kNumSlots];
                 for (int o = 0; o < kNumSlots; ++o) {
-                    const int c = vslot[(size_t)o * nbox + b];
-                    if (c < 0) continue;
-                    const int li = (int)(std::lower_bound(uniq.begin(), uniq.end(), c) - uniq.begin());
-                    tslot[t0 + (size_t)o * kTile + lane] = (int16_t)li;
+                    if (vs[o] < 0) continue;
+                    tslot[t0 + (size_t)o * kTile + lane] = (int16_t)pos[vs[o]];
                     msk |= 1ull << o;
                 }
             }
+            for (int c : uniq) pos[c] = -1;
             tlev.push_back(level[seq[lo]]);
             tmask.push_back(msk);
             tsrc.insert(tsrc.end(), uniq.begin(), uniq.end());
