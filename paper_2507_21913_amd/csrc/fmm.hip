@@ -40,6 +40,7 @@
 #include <map>
 #include <cmath>
 #include <complex>
+#include <thread>
 
 #include "internal.hpp"
 #include "special.hpp"
@@ -1762,66 +1763,97 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     // of a tile walk the same offset slots.  A tile whose distinct upper V sources do not fit the
     // LDS staging buffer is split in halves.  The FP32 matrix-core M2L stages all coefficients at
     // once and takes consecutive boxes of all classes (fewer distinct sources per tile).
+    // The tiles are built by host threads, each taking whole initial tiles (and their halves).
     std::vector<int32_t> tiles, tlev, tsoff(1, 0), tsrc;
     std::vector<int16_t> tslot;
     std::vector<uint64_t> tmask;
     {
-        std::vector<int32_t> seq;                  // boxes grouped by (level, class), Morton order
-        std::vector<int32_t> uniq;
-        std::vector<int32_t> pos(nbox, -1);        // a source's index in uniq (reset after each tile)
-        S.tile_lev.assign(T.depth + 2, 0);
+        struct TileOut {
+            std::vector<int32_t> boxes, src, nsrc, lev;  // kTile boxes (-1 padded) and sources per tile
+            std::vector<int16_t> slot;                    // kNumSlots x kTile per tile
+            std::vector<uint64_t> mask;
+        };
+        std::vector<int32_t> seq;                          // boxes grouped by (level, class), Morton order
+        std::vector<std::pair<int, int>> init;             // initial tiles: [lo, hi) ranges of seq
+        std::vector<int> init_lev(T.depth + 2, 0);         // first initial tile of each level
         for (int l = 2; l <= T.depth; ++l) {
-        S.tile_lev[l] = (int)tlev.size();
-        std::vector<std::pair<int, int>> todo;     // [lo, hi) ranges of seq (this level)
-        for (int cls = 0; cls < (S.m2l_fp32 ? 1 : 4); ++cls) {
-            const int g0 = (int)seq.size();
-            for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b)
-                if (S.m2l_fp32 || ((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
-            for (int a0 = g0; a0 < (int)seq.size(); a0 += kTile)
-                todo.push_back({a0, std::min(a0 + kTile, (int)seq.size())});
+            init_lev[l] = (int)init.size();
+            for (int cls = 0; cls < (S.m2l_fp32 ? 1 : 4); ++cls) {
+                const int g0 = (int)seq.size();
+                for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b)
+                    if (S.m2l_fp32 || ((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
+                for (int a0 = g0; a0 < (int)seq.size(); a0 += kTile)
+                    init.push_back({a0, std::min(a0 + kTile, (int)seq.size())});
+            }
         }
-        for (size_t ti = 0; ti < todo.size(); ++ti) {
-            const int lo = todo[ti].first, hi = todo[ti].second;
-            // distinct sources of the tile, ascending
+        init_lev[T.depth + 1] = (int)init.size();
+        const int max_src = S.m2l_fp32 ? kM2LMaxSrc32 : kM2LMaxSrc;
+        std::vector<TileOut> outs(init.size());
+        // one range: its distinct sources ascending; halves while they do not fit the LDS staging
+        auto build_range = [&](auto &&self, int lo, int hi, std::vector<int32_t> &pos, std::vector<int32_t> &uniq,
+                               TileOut &o) -> void {
             uniq.clear();
             for (int q = lo; q < hi; ++q) {
                 const int32_t *vs = &vslot[(size_t)seq[q] * kNumSlots];
-                for (int o = 0; o < kNumSlots; ++o)
-                    if (vs[o] >= 0 && pos[vs[o]] < 0) {
-                        pos[vs[o]] = 0;
-                        uniq.push_back(vs[o]);
+                for (int k = 0; k < kNumSlots; ++k)
+                    if (vs[k] >= 0 && pos[vs[k]] < 0) {
+                        pos[vs[k]] = 0;
+                        uniq.push_back(vs[k]);
                     }
+            }
+            if ((int)uniq.size() > max_src && hi - lo > 1) {
+                for (int c : uniq) pos[c] = -1;
+                const int mid = lo + (hi - lo) / 2;
+                self(self, lo, mid, pos, uniq, o);
+                self(self, mid, hi, pos, uniq, o);
+                return;
             }
             std::sort(uniq.begin(), uniq.end());
             for (int i = 0; i < (int)uniq.size(); ++i) pos[uniq[i]] = i;
-            if ((int)uniq.size() > (S.m2l_fp32 ? kM2LMaxSrc32 : kM2LMaxSrc)) {
-                for (int c : uniq) pos[c] = -1;
-                const int mid = lo + (hi - lo) / 2;
-                todo.push_back({lo, mid});
-                todo.push_back({mid, hi});
-                continue;
-            }
-            const size_t t0 = tslot.size();
-            tslot.resize(t0 + (size_t)kNumSlots * kTile, (int16_t)-1);
+            const size_t t0 = o.slot.size();
+            o.slot.resize(t0 + (size_t)kNumSlots * kTile, (int16_t)-1);
             uint64_t msk = 0;
             for (int lane = 0; lane < kTile; ++lane) {
                 const int q = lo + lane;
                 const int b = q < hi ? seq[q] : -1;
-                tiles.push_back(b);
+                o.boxes.push_back(b);
                 if (b < 0) continue;
                 const int32_t *vs = &vslot[(size_t)b * kNumSlots];
-                for (int o = 0; o < kNumSlots; ++o) {
-                    if (vs[o] < 0) continue;
-                    tslot[t0 + (size_t)o * kTile + lane] = (int16_t)pos[vs[o]];
-                    msk |= 1ull << o;
+                for (int k = 0; k < kNumSlots; ++k) {
+                    if (vs[k] < 0) continue;
+                    o.slot[t0 + (size_t)k * kTile + lane] = (int16_t)pos[vs[k]];
+                    msk |= 1ull << k;
                 }
             }
             for (int c : uniq) pos[c] = -1;
-            tlev.push_back(level[seq[lo]]);
-            tmask.push_back(msk);
-            tsrc.insert(tsrc.end(), uniq.begin(), uniq.end());
-            tsoff.push_back((int32_t)tsrc.size());
-        }
+            o.lev.push_back(level[seq[lo]]);
+            o.mask.push_back(msk);
+            o.src.insert(o.src.end(), uniq.begin(), uniq.end());
+            o.nsrc.push_back((int32_t)uniq.size());
+        };
+        const int nthr = (int)std::max<size_t>(1, std::min<size_t>({init.size(), (size_t)16,
+                                                                      (size_t)std::max(1u, std::thread::hardware_concurrency())}));
+        auto worker = [&](int tid) {
+            std::vector<int32_t> pos(nbox, -1), uniq;
+            for (size_t i = tid; i < init.size(); i += nthr)
+                build_range(build_range, init[i].first, init[i].second, pos, uniq, outs[i]);
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthr; ++t) pool.emplace_back(worker, t);
+        worker(0);
+        for (auto &th : pool) th.join();
+        S.tile_lev.assign(T.depth + 2, 0);
+        for (int l = 2; l <= T.depth; ++l) {
+            S.tile_lev[l] = (int)tlev.size();
+            for (int i = init_lev[l]; i < init_lev[l + 1]; ++i) {
+                const TileOut &o = outs[i];
+                tiles.insert(tiles.end(), o.boxes.begin(), o.boxes.end());
+                tslot.insert(tslot.end(), o.slot.begin(), o.slot.end());
+                tmask.insert(tmask.end(), o.mask.begin(), o.mask.end());
+                tlev.insert(tlev.end(), o.lev.begin(), o.lev.end());
+                tsrc.insert(tsrc.end(), o.src.begin(), o.src.end());
+                for (int32_t c : o.nsrc) tsoff.push_back(tsoff.back() + c);
+            }
         }
         S.tile_lev[T.depth + 1] = (int)tlev.size();
         S.tile_lev[0] = S.tile_lev[1] = 0;
