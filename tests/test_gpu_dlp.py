@@ -180,3 +180,22 @@ def test_normal_derivative_sources_as_targets():
     plan.close()
     rx, ry = GR.potential_gradient(x, y, mu, 2.0)
     assert D.rel_l2(got, nx * rx + ny * ry) < 1e-10
+
+
+def test_degenerate_sizes_and_zero_normals():
+    """One source, two coincident sources, leaf size 1, and zero normals (an exactly zero layer)."""
+    rng = np.random.default_rng(31)
+    cases = [(np.array([0.4]), np.array([0.2])),
+             (np.array([0.4, 0.4, 0.7]), np.array([0.2, 0.2, 0.05])),
+             (rng.uniform(0, 1, 50), rng.uniform(1e-3, 1, 50))]
+    for leaf, (x, y) in zip((40, 40, 1), cases):
+        th = rng.uniform(0, 2 * np.pi, x.size)
+        nx, ny, mu = np.cos(th), np.sin(th), rng.standard_normal(x.size)
+        for Z in (1.0, 1.0 + 0.5j):
+            plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=30, leaf_size=leaf)
+            got = plan.double_layer(_t(mu), _t(nx), _t(ny)).cpu().numpy()
+            zero = plan.double_layer(_t(mu), _t(np.zeros_like(nx)), _t(np.zeros_like(ny))).cpu().numpy()
+            plan.close()
+            ref = D.double_layer(x, y, nx, ny, mu, Z, workers=1)
+            assert np.all(np.isfinite(got)) and D.rel_l2(got, ref) < 1e-12, (x.size, Z)
+            assert np.all(zero == 0.0)
