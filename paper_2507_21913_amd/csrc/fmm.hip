@@ -1951,6 +1951,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             const int tmax = subtree_ranges(3, S.top_nlev, trng);
             FMMHP_CHECK(to_dev(A, &S.top_rng, trng, "top subtree ranges", s));
             S.top_ld_l2l = std::max(kL2LChildren, std::min(tmax * S.nloc, cap));
+            S.top_ld_m2m = std::max(4 * kM2MParents, std::min(tmax, cap));
         }
     }
     {
@@ -2368,7 +2369,17 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_sub, NV), dim3(256),
                            (PB + 1) * S.sub_ld_m2m * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_m2m, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
     if (ld > 0 && lf > T.depth - 1) FMMHP_CHECK(fork_deep());
-    for (int l = (lc > 0 ? lc : T.depth) - 1; l >= 2; --l) {
+    // above the cut: with a top subtree pass, the parents of levels 3..lc-1 in one launch (subtrees
+    // rooted at level 3, the cut level's multipoles their inputs), then level 2
+    int l_top = (lc > 0 ? lc : T.depth) - 1;
+    if (S.n_top > 0) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_top, NV), dim3(256),
+                           (PB + 1) * S.top_ld_m2m * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_m2m, nbox,
+                           T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+        if (ld > 0 && lf >= 3 && lf <= l_top) FMMHP_CHECK(fork_deep());
+        l_top = 2;
+    }
+    for (int l = l_top; l >= 2; --l) {
         const int lo = T.lev_start[l], nb = T.lev_start[l + 1] - lo;
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256),

@@ -167,7 +167,7 @@ struct Sched {
     int2 *sub_rng = nullptr;        // [n_sub][sub_nlev] box range of each subtree per level
     int sub_ld_m2m = 0, sub_ld_l2l = 0;  // LDS expansion slots of the subtree passes
     // L2L of levels 4..cut in one launch: subtrees rooted at level 3 (0 subtrees: one launch per level)
-    int n_top = 0, top_nlev = 0, top_ld_l2l = 0;
+    int n_top = 0, top_nlev = 0, top_ld_l2l = 0, top_ld_m2m = 0;  // (the same subtrees serve the M2M)
     int2 *top_rng = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_up = nullptr;  // upward pass done (main stream)
