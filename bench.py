@@ -340,6 +340,33 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                 "flops_per_launch": fl}
 
+    # the same evaluation with every kernel on one stream: each k_m2l launch's duration is its own
+    # (the concurrent schedule above shares the CUs with the near field)
+    alone = None
+    if dom == "m2l":
+        plan_s = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, serial=True, **shape)
+        for _ in range(2):
+            plan_s(q, out=out)
+        plan_s.set_timing(True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(a.steps):
+            plan_s(q, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / a.steps
+        m2l_ms_s, n_s = plan_s.m2l_kernel_times()
+        plan_s.set_timing(False)
+        plan_s.close()
+        if n_s > 0:
+            per_eval_s = n_s / max(1, a.steps)
+            avg_s = m2l_ms_s / n_s
+            ach_s = (m2l_flops / per_eval_s) / (avg_s * 1e-3) / 1e12
+            alone = {"kernel": "k_m2l", "schedule": "every kernel on one stream (FMMHP_FLAG_SERIAL)",
+                     "achieved": ach_s, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach_s / PEAK_FP64_TFLOPS, "avg_launch_us": avg_s * 1e3,
+                     "launches_per_eval": per_eval_s, "ms_per_step_serial": ms_s}
+
     res = {
         "metric": "Mpts/s FMM eval at 1M pts, rel-l2 1e-10 vs direct; fwd+bwd and batched vs plain",
         "value": w.n / (ms * 1e-3) / 1e6,
@@ -360,6 +387,8 @@ def main():
                    "near_walk": info["near_walk"], "near_groups": info["near_groups"]},
         "roofline": roof,
     }
+    if alone is not None:
+        res["roofline_alone"] = alone
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, a.cpu_sample)
     if not a.quiet_extra:

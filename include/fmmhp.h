@@ -65,8 +65,8 @@ typedef struct {
                        fmmhp_plan_info reports the order actually used. */
     int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
     int max_level;  /* deepest tree level, 1..30 (1..27 for a forest); 0 selects the maximum */
-    unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH, FMMHP_FLAG_M2L_FP32 and one of
-                       FMMHP_FLAG_DIRICHLET, FMMHP_FLAG_NEUMANN */
+    unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH, FMMHP_FLAG_M2L_FP32,
+                       FMMHP_FLAG_SERIAL and one of FMMHP_FLAG_DIRICHLET, FMMHP_FLAG_NEUMANN */
     /* Launch shape of the near field (the U-list sums), which runs beside the far-field kernels on
      * a bounded grid.  Neither changes what is computed beyond rounding; fmmhp_tune picks both by
      * timing.  0 selects the default for the plan's p. */
@@ -96,6 +96,10 @@ typedef struct {
  * the two may be set. */
 #define FMMHP_FLAG_DIRICHLET 4u
 #define FMMHP_FLAG_NEUMANN 8u
+/* Every kernel of an evaluation on the caller's stream, one after another, instead of the near field
+ * and the deep-level M2L on streams of their own beside the rest: a profiling aid (each kernel's
+ * duration is then its own, not shared with concurrent kernels); slower. */
+#define FMMHP_FLAG_SERIAL 16u
 
 typedef struct {
     int64_t n;              /* number of points */

@@ -29,6 +29,7 @@ FLAG_GRAPH = 1   # fmmhp_opts.flags: record evaluations into a HIP graph and rep
 FLAG_M2L_FP32 = 2  # fmmhp_opts.flags: upper-source M2L on the FP32 matrix cores (~1e-7 relative)
 FLAG_DIRICHLET = 4  # fmmhp_opts.flags: Dirichlet half-plane kernel (eq. (ddd1.2), image term +)
 FLAG_NEUMANN = 8    # fmmhp_opts.flags: Neumann half-plane kernel (eq. (ddd1.2), image term -)
+FLAG_SERIAL = 16    # fmmhp_opts.flags: every kernel on the eval stream (profiling aid)
 _BC_FLAGS = {"robin": 0, "dirichlet": FLAG_DIRICHLET, "neumann": FLAG_NEUMANN}
 
 
@@ -301,10 +302,11 @@ class HalfPlaneFMM:
     near_walk, near_groups   near-field launch shape (0: default; see fmmhp_opts)
     bc          "robin" (the impedance condition), "dirichlet" or "neumann" (eq. (ddd1.2); the
                 impedance is then ignored)
+    serial      every kernel on the eval stream, one after another (profiling aid; slower)
     """
 
     def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False,
-                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0, bc="robin"):
+                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0, bc="robin", serial=False):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         self.n = int(x.shape[0])
@@ -312,7 +314,8 @@ class HalfPlaneFMM:
         self._x, self._y = x, y
         lr, li = _split_impedance(impedance)
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc)
+                    | (FLAG_SERIAL if serial else 0),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             if pass_images:

@@ -89,7 +89,8 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     if (opts) o = *opts;
     if (o.max_level == 0) o.max_level = lb;
     if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
-        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32 | FMMHP_FLAG_DIRICHLET | FMMHP_FLAG_NEUMANN)) != 0 ||
+        (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32 | FMMHP_FLAG_DIRICHLET | FMMHP_FLAG_NEUMANN |
+                     FMMHP_FLAG_SERIAL)) != 0 ||
         (o.flags & FMMHP_FLAG_DIRICHLET && o.flags & FMMHP_FLAG_NEUMANN) || o.near_walk < 0 || o.near_walk > 2 ||
         o.near_groups < 0 || o.near_groups > 16) {
         set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0..3, "
@@ -119,6 +120,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
         st = build_tree(p->arena, p->tree, n_inst, off, x, y, img_x, img_y, src_end, o.leaf_size, o.max_level,
                         stream);
     p->sched.m2l_fp32 = (o.flags & FMMHP_FLAG_M2L_FP32) != 0;
+    p->sched.serial = (o.flags & FMMHP_FLAG_SERIAL) != 0;
     p->sched.bc = (o.flags & FMMHP_FLAG_DIRICHLET) ? 1 : (o.flags & FMMHP_FLAG_NEUMANN) ? 2 : 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
     if (st == FMMHP_OK) apply_launch_shape(p->sched, o.near_walk, o.near_groups);

@@ -2272,6 +2272,8 @@ struct PassOut {
 // from blockIdx.y; the near-field kernels share each pair's kernel value among the NV vectors.
 template <int PB, int MODE, int NV>
 static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
+    // the near field and the deep-level M2L run on streams of their own (all on s when serial)
+    hipStream_t side_ = S.serial ? s : S.side, side2_ = S.serial ? s : S.side2;
     constexpr bool DIP = is_dip(MODE);
     constexpr int LM = DIP ? (int)kPhi : MODE;
     const int nbox = T.nbox;
@@ -2288,35 +2290,35 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
                 S.wpts,      S.n_wpts,  S.rpts,   S.logtab, S.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
                 out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0, S.nrm};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
-    FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_fork, 0));
-    if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, S.side));
+    FMMHP_HIP(hipStreamWaitEvent(side_, S.ev_fork, 0));
+    if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, side_));
     // a bounded grid (a few workgroups per CU) leaves room on every CU for the far-field kernels
     // running concurrently on the main stream
     const dim3 near_grid((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks));
     if (S.near_walk == 2)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_plain<MODE, NV>), near_grid, dim3(256), 0, S.side, la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_plain<MODE, NV>), near_grid, dim3(256), 0, side_, la);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), near_grid, dim3(256), 0, S.side, la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), near_grid, dim3(256), 0, side_, la);
     if (S.n_rpts > 0 && S.bc == 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
-                           S.side, la);
+                           side_, la);
     FMMHP_HIP(hipGetLastError());
     // the surface sums also need only the sorted charges
     if (S.nloc == 1 && S.bc == 0 && S.rank1_side) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rank1_partial<DIP>), dim3(S.n_rch, NV), dim3(256), 0, S.side, T.xs,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rank1_partial<DIP>), dim3(S.n_rch, NV), dim3(256), 0, side_, T.xs,
                            T.ys, S.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, S.red);
-        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, S.side, S.red, S.n_rch, S.inst_ch,
+        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, side_, S.red, S.n_rch, S.inst_ch,
                            T.n_inst, S.rank1);
         FMMHP_HIP(hipGetLastError());
     }
-    if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, S.side));
+    if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, side_));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB, DIP>), dim3(nblk((int64_t)T.nleaf * kP2MSplit, 256), NV), dim3(256),
                        0, s, S.inst_info, T.inst, S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count,
                        T.xs, T.ys, S.qs, S.nrm, S.W);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
     // M2L (+ image M2L, P2L) over the levels [l0, l1) of the tree on stream st
-    auto far_levels = [&](int l0, int l1, hipStream_t st) -> fmmhp_status {
+    auto far_levels = [&](int l0, int l1, hipStream_t st, bool deep) -> fmmhp_status {
         const int t0 = S.tile_lev[l0], t1 = S.tile_lev[l1];
         if (t1 > t0) {
             constexpr int CH = m2l_chunk(PB);
@@ -2328,7 +2330,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
             } else {
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
                            S.tile_mask, S.Tfree, S.Lfree, S.logside,  S.W,            S.Lam,      S.nloc};
-                const int which = st == s ? 1 : 0;
+                const int which = deep ? 0 : 1;
                 FMMHP_CHECK(mk_.km_mark(which, 0, st));
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)), 0,
                                    st, ma);
@@ -2354,11 +2356,11 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     const int ld = S.deep_level;
     auto fork_deep = [&]() -> fmmhp_status {
         FMMHP_HIP(hipEventRecord(S.ev_deep_ready, s));
-        FMMHP_HIP(hipStreamWaitEvent(S.side2, S.ev_deep_ready, 0));
-        if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.deep0, S.side2));
-        FMMHP_CHECK(far_levels(ld, T.depth + 1, S.side2));
-        if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.deep1, S.side2));
-        FMMHP_HIP(hipEventRecord(S.ev_deep_done, S.side2));
+        FMMHP_HIP(hipStreamWaitEvent(side2_, S.ev_deep_ready, 0));
+        if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.deep0, side2_));
+        FMMHP_CHECK(far_levels(ld, T.depth + 1, side2_, true));
+        if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.deep1, side2_));
+        FMMHP_HIP(hipEventRecord(S.ev_deep_done, side2_));
         return FMMHP_OK;
     };
     // fork point: once the deep multipoles exist, or (S.fork_late) after the whole upward pass
@@ -2394,12 +2396,12 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     const bool w_side = S.n_wpts > 0 && S.near_walk == 2;
     if (w_side) {
         FMMHP_HIP(hipEventRecord(S.ev_up, s));
-        FMMHP_HIP(hipStreamWaitEvent(S.side, S.ev_up, 0));
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, S.side,
+        FMMHP_HIP(hipStreamWaitEvent(side_, S.ev_up, 0));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, side_,
                            la);
         FMMHP_HIP(hipGetLastError());
     }
-    FMMHP_HIP(hipEventRecord(S.ev_join, S.side));
+    FMMHP_HIP(hipEventRecord(S.ev_join, side_));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2L, s));
     {
         const int lo = T.lev_start[1], hi = T.lev_start[2];
@@ -2408,7 +2410,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
             hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc * NV,
                                S.Lam);
     }
-    FMMHP_CHECK(far_levels(2, ld > 0 ? ld : T.depth + 1, s));
+    FMMHP_CHECK(far_levels(2, ld > 0 ? ld : T.depth + 1, s, false));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_L2L, s));
     const int l2l_end = lc > 0 ? lc : T.depth;

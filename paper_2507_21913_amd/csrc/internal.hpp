@@ -161,6 +161,7 @@ struct Sched {
     int near_walk = 1;              // near-field walk: 1 prefetching, 2 plain
     int64_t near_blocks = 512;      // near-field grid (workgroups)
     bool fork_late = false;         // start the deep M2L after the whole upward pass
+    bool serial = false;            // every kernel on the eval stream (FMMHP_FLAG_SERIAL)
     bool rank1_side = true;         // surface sums on the near-field stream
     int sub_level = 0;              // cut level of the subtree M2M / L2L passes (0: one launch per level)
     int n_sub = 0, sub_nlev = 0;    // subtrees (the boxes of the cut level), levels cut..depth

@@ -89,3 +89,20 @@ def test_tune_returns_a_shape():
     info = plan.info()
     assert (info["near_walk"], info["near_groups"]) == (r["near_walk"], r["near_groups"])
     plan.close()
+
+
+@pytest.mark.parametrize("Z", [1.0, 1.0 + 0.5j])
+def test_serial_schedule_same_results(Z):
+    """FMMHP_FLAG_SERIAL (every kernel on the eval stream) computes the same sums: bitwise equal
+    potentials, and the k_m2l launch timing counts two launches per evaluation."""
+    x, y, q = _problem(20000, 17)
+    out = {}
+    for serial in (False, True):
+        plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=20, leaf_size=16, serial=serial)
+        plan.set_timing(True)
+        out[serial] = plan(_t(q[0])).cpu().numpy()
+        ms, n = plan.m2l_kernel_times()
+        plan.set_timing(False)
+        plan.close()
+        assert ms > 0.0 and n >= 1
+    assert np.array_equal(out[False], out[True])
