@@ -129,6 +129,46 @@ def example2_extra(dev, sizes=(4000, 1 << 16, 1 << 20), p=10, leaf=32, reps=10):
     return out
 
 
+def curve_extra(dev, steps):
+    """The nonuniform workload with a complex impedance (N = 4,194,304: 80% within 1e-3 of the curve
+    y = 0.3 + 0.1 sin(6 pi x), 20% uniform; impedance 1 + 0.5i; p = 30, leaf 40): evaluation time and
+    rel-l2 against the stored oracle sample."""
+    import numpy as np
+    import torch
+
+    import paper_2507_21913_amd as F
+    import workloads
+    from golden_io import load
+
+    w = workloads.curve_4m(seed=1)
+    x, y, q = (torch.as_tensor(v, device=dev) for v in (w.x, w.y, w.q[0]))
+    t0 = time.perf_counter()
+    plan = F.HalfPlaneFMM(x, y, w.impedance, p=w.p, leaf_size=w.leaf_size)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    out = torch.empty(w.n, dtype=torch.complex128, device=dev)
+    for _ in range(2):
+        plan(q, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan(q, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": "curve_4m: N=4,194,304, 80% within 1e-3 of y = 0.3 + 0.1 sin(6 pi x), impedance 1+0.5i",
+           "p": w.p, "leaf_size": w.leaf_size, "ms_per_step": ms, "mpts_s": w.n / (ms * 1e-3) / 1e6,
+           "plan_ms": plan_ms, "depth": plan.info()["depth"]}
+    g = load("curve_4m")
+    if g is not None:
+        got = out.cpu().numpy()[g[0]]
+        res["rel_l2_vs_oracle_sample"] = float(np.linalg.norm(got - g[1]) / np.linalg.norm(g[1]))
+    plan.close()
+    return res
+
+
 def batched_extra(dev, p, leaf, steps):
     """The batched workload (512 instances, N_k log-uniform in [1e3, 2e5], impedances log-uniform
     in [0.1, 10], 64 charge vectors): one forest plan evaluating all instances and vectors in the
@@ -475,6 +515,7 @@ def main():
                                "rel_l2_vs_oracle_sample": rel_dl}
         del dl
         res["example2"] = example2_extra(dev)
+        res["curve_4m"] = curve_extra(dev, max(2, a.steps // 2))
         if not a.no_batched:
             plan.close()
             del out
