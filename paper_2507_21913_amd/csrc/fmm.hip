@@ -1894,26 +1894,21 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     // level, instance, Morton prefix).
     S.sub_level = 0;
     {
-        int cus = 0, dev = 0;
-        FMMHP_HIP(hipGetDevice(&dev));
-        FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        for (int l = 3; l < T.depth; ++l)
-            if (T.lev_start[l + 1] - T.lev_start[l] >= 4 * std::max(1, cus)) {
-                S.sub_level = l;
-                break;
-            }
-    }
-    if (S.sub_level > 0) {
         std::vector<int32_t> cfirst, nch;
         FMMHP_CHECK(to_host(cfirst, T.child_first, nbox, s));
         FMMHP_CHECK(to_host(nch, T.nchild, nbox, s));
         FMMHP_HIP(hipStreamSynchronize(s));
+        int cus = 0, dev = 0;
+        FMMHP_HIP(hipGetDevice(&dev));
+        FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         // box ranges per level of the subtrees rooted at the boxes of level lr, nlev levels deep;
-        // returns the largest subtree's box count
-        auto subtree_ranges = [&](int lr, int nlev, std::vector<int2> &rng) {
+        // returns the largest subtree's box count; nonres (if given) gets the number of boxes in
+        // subtrees of more than cap boxes
+        auto subtree_ranges = [&](int lr, int nlev, std::vector<int2> &rng, int cap_, int64_t *nonres) {
             const int r0 = T.lev_start[lr], nr = T.lev_start[lr + 1] - r0;
             rng.assign((size_t)nr * nlev, make_int2(0, 0));
             int maxtot = 0;
+            if (nonres) *nonres = 0;
             for (int r = 0; r < nr; ++r) {
                 int a = r0 + r, b = a + 1, tot = 0;
                 for (int k = 0; k < nlev && a < b; ++k) {
@@ -1930,28 +1925,48 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                     b = nb;
                 }
                 maxtot = std::max(maxtot, tot);
+                if (nonres && tot > cap_) *nonres += tot;
             }
             return maxtot;
         };
-        const int lc = S.sub_level;
-        S.n_sub = T.lev_start[lc + 1] - T.lev_start[lc];
-        S.sub_nlev = T.depth - lc + 1;
-        std::vector<int2> rng;
-        const int maxtot = subtree_ranges(lc, S.sub_nlev, rng);
-        FMMHP_CHECK(to_dev(A, &S.sub_rng, rng, "subtree ranges", s));
         // resident LDS rows: enough for the largest subtree, within 48 KB of expansions per block
         const int cap = std::min(kSubMaxSlots, (int)(48 * 1024 / ((PB + 1) * sizeof(cplx))));
-        S.sub_ld_m2m = std::max(4 * kM2MParents, std::min(maxtot, cap));
-        S.sub_ld_l2l = std::max(kL2LChildren, std::min(maxtot * S.nloc, cap));
-        // the L2L levels 4..lc in one launch of level-3-rooted subtrees (after level 3's own L2L)
-        if (lc >= 5) {
-            S.top_nlev = lc - 3 + 1;
-            S.n_top = T.lev_start[4] - T.lev_start[3];
-            std::vector<int2> trng;
-            const int tmax = subtree_ranges(3, S.top_nlev, trng);
-            FMMHP_CHECK(to_dev(A, &S.top_rng, trng, "top subtree ranges", s));
-            S.top_ld_l2l = std::max(kL2LChildren, std::min(tmax * S.nloc, cap));
-            S.top_ld_m2m = std::max(4 * kM2MParents, std::min(tmax, cap));
+        // the cut: the first level (>= 3) with at least four boxes per CU whose subtrees nearly all
+        // fit in LDS (at most 5% of the boxes below the cut in larger ones, which take the slower
+        // level-by-level path inside their block); deep narrow trees with no such level run one
+        // launch per level instead
+        std::vector<int2> rng;
+        int maxtot = 0;
+        for (int l = 3; l < T.depth; ++l) {
+            if (T.lev_start[l + 1] - T.lev_start[l] < 4 * std::max(1, cus)) continue;
+            int64_t nonres = 0;
+            const int mt = subtree_ranges(l, T.depth - l + 1, rng, cap, &nonres);
+            if (nonres * 20 <= (int64_t)(T.lev_start[T.depth + 1] - T.lev_start[l])) {
+                S.sub_level = l;
+                maxtot = mt;
+                break;
+            }
+        }
+        if (S.sub_level > 0) {
+            const int lc = S.sub_level;
+            S.n_sub = T.lev_start[lc + 1] - T.lev_start[lc];
+            S.sub_nlev = T.depth - lc + 1;
+            FMMHP_CHECK(to_dev(A, &S.sub_rng, rng, "subtree ranges", s));
+            S.sub_ld_m2m = std::max(4 * kM2MParents, std::min(maxtot, cap));
+            S.sub_ld_l2l = std::max(kL2LChildren, std::min(maxtot * S.nloc, cap));
+            // the L2L levels 4..lc in one launch of level-3-rooted subtrees (after level 3's own L2L)
+            // (only when those subtrees fit in LDS)
+            if (lc >= 5) {
+                std::vector<int2> trng;
+                const int tmax = subtree_ranges(3, lc - 3 + 1, trng, cap, nullptr);
+                if (tmax <= cap) {
+                    S.top_nlev = lc - 3 + 1;
+                    S.n_top = T.lev_start[4] - T.lev_start[3];
+                    FMMHP_CHECK(to_dev(A, &S.top_rng, trng, "top subtree ranges", s));
+                    S.top_ld_l2l = std::max(kL2LChildren, std::min(tmax * S.nloc, cap));
+                    S.top_ld_m2m = std::max(4 * kM2MParents, std::min(tmax, cap));
+                }
+            }
         }
     }
     {
