@@ -1023,10 +1023,30 @@ struct LeafArgs {
     const double2 *nrm;      // [n] source normals (sorted order), kDip only
 };
 
-// Near field, log terms of the U list: one thread per target (sorted order, grid-stride over the
-// targets).  NV charge vectors share each pair's kernel value.  The thread loads each source point
-// (and the next U entry's range) one step ahead of its use, so that the memory latency overlaps
-// the arithmetic; free-space and image terms go into one signed sum,
+// The hardware places workgroup b on XCD b % 8, and each XCD has its own L2.  xcd_chunks gives a
+// grid-stride loop over nch chunks whose workgroups on one XCD walk one contiguous range of chunks
+// (XCD x holds the x-th eighth), so that the workgroups sharing an L2 work on neighbouring leaves,
+// whose U lists share source points.  Every chunk is taken exactly once for any grid size.
+constexpr int kXcds = 8;
+struct XcdChunks {
+    int64_t c0, c1;  // this workgroup's first chunk, end of its XCD's range
+    int step;        // workgroups on this XCD
+};
+__device__ __forceinline__ XcdChunks xcd_chunks(int64_t nch) {
+    const int G = gridDim.x, X = G < kXcds ? G : kXcds;
+    const int x = blockIdx.x % X;
+    const int64_t base = nch / X, rem = nch % X;
+    XcdChunks r;
+    r.step = G / X + (x < G % X ? 1 : 0);
+    r.c0 = x * base + (x < rem ? x : rem) + blockIdx.x / X;
+    r.c1 = (x + 1) * base + (x + 1 < rem ? x + 1 : rem);
+    return r;
+}
+
+// Near field, log terms of the U list: one thread per target (sorted order; workgroups take chunks
+// of blockDim targets by xcd_chunks).  NV charge vectors share each pair's kernel value.  The
+// thread loads each source point (and the next U entry's range) one step ahead of its use, so that
+// the memory latency overlaps the arithmetic; free-space and image terms go into one signed sum,
 // (1/4 pi) sum_j q_j (log r_img^2 - log r^2).
 template <int MODE, int NV>
 __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
@@ -1039,7 +1059,10 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     const double2 *__restrict__ tab = s_logtab;
     const double *__restrict__ qs = a.qs;
     const int2 *__restrict__ u2 = a.u2;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const XcdChunks ch = xcd_chunks((a.n + blockDim.x - 1) / blockDim.x);
+    for (int64_t c = ch.c0; c < ch.c1; c += ch.step) {
+        const int64_t i = c * blockDim.x + threadIdx.x;
+        if (i >= a.n) break;
         const int b = a.leaf_of[i];
         const double2 pi = a.xy[i];
         const double x = pi.x, y = pi.y;
