@@ -442,14 +442,23 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
             sW[idx] = W[(int64_t)(m0 + mm) * a.nbox + a.tile_src[s0 + sj]];
         }
         __syncthreads();
+        // the walk over the tile's slots loads the next slot's source index before this slot's
+        // arithmetic, so that its memory latency is hidden
         uint64_t rest = mask;
-        while (rest) {
-            const int o = __builtin_ctzll(rest);
+        int o = rest ? __builtin_ctzll(rest) : 0;
+        rest &= rest - 1;
+        int li = mask ? slot[o * kTile] : -1;
+        for (bool go = mask != 0; go;) {
+            go = rest != 0;
+            const int on = go ? __builtin_ctzll(rest) : o;  // the last slot reloads its own index
             rest &= rest - 1;
-            const int li = slot[o * kTile];
-            if (li < 0) continue;
-            const cplx *T = a.Tfree + o * NTP + n0 + m0;
-            const cplx *w = sW + li;
+            const int lin = slot[on * kTile];
+            const int oc = o, lc = li;
+            o = on;
+            li = lin;
+            if (lc < 0) continue;
+            const cplx *T = a.Tfree + oc * NTP + n0 + m0;
+            const cplx *w = sW + lc;
 #pragma unroll
             for (int mm = 0; mm < kM2LPhase; ++mm) {
                 if (mm < mc) {
@@ -458,7 +467,7 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
                     for (int k = 0; k < CH; ++k) cfma(acc[k], T[k + mm], wm);
                 }
             }
-            if (ph == 0 && n0 == 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), w[0]);
+            if (ph == 0 && n0 == 0) cfma(acc0, a.Lfree[oc] - mk(ll, 0.0), w[0]);
         }
     }
     if (b < 0) return;
@@ -1812,7 +1821,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         init_lev[T.depth + 1] = (int)init.size();
         const int max_src = S.m2l_fp32 ? kM2LMaxSrc32 : kM2LMaxSrc;
         std::vector<TileOut> outs(init.size());
-        // one range: its distinct sources ascending; halves while they do not fit the LDS staging
+        // one range: its distinct sources; halves while they do not fit the LDS staging
         auto build_range = [&](auto &&self, int lo, int hi, std::vector<int32_t> &pos, std::vector<int32_t> &uniq,
                                TileOut &o) -> void {
             uniq.clear();
@@ -1831,7 +1840,12 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 self(self, mid, hi, pos, uniq, o);
                 return;
             }
-            std::sort(uniq.begin(), uniq.end());
+            // sources by child class, then box: at one slot the lanes of a one-class tile read
+            // nearly consecutive LDS entries (few bank conflicts)
+            std::sort(uniq.begin(), uniq.end(), [&](int32_t u, int32_t v) {
+                const int cu = (bx[u] & 1) | ((by[u] & 1) << 1), cv = (bx[v] & 1) | ((by[v] & 1) << 1);
+                return cu != cv ? cu < cv : u < v;
+            });
             for (int i = 0; i < (int)uniq.size(); ++i) pos[uniq[i]] = i;
             const size_t t0 = o.slot.size();
             o.slot.resize(t0 + (size_t)kNumSlots * kTile, (int16_t)-1);
