@@ -375,8 +375,9 @@ fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *
  * The error of a candidate is measured, not modelled: the FMM potential is compared with the
  * GPU direct sum (fmmhp_direct_eval) at `sample` fixed targets (indices floor(k n / sample)),
  * for the given charges.  For each candidate leaf size the smallest p in {5, 10, ..., 40} whose
- * relative l2 error is at most tol is kept, and the (p, leaf) pair with the fastest median
- * fmmhp_eval time (n_vec vectors) wins.
+ * relative l2 error is at most tol is kept, and the (p, leaf) pair with the fastest
+ * fmmhp_eval time (n_vec vectors) wins; an eval time is the median over three rounds of the mean
+ * of five back-to-back evaluations (the steady state of a loop of evaluations).
  *
  *   n, x, y, lambda_re, lambda_im   as for fmmhp_plan_create ([device] x, y)
  *   q            [device] [n] charges used for the trial evaluations
@@ -385,7 +386,9 @@ fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *
  *   leaf_sizes   [host] candidate leaf sizes (n_leaf entries), or NULL for {24, 32, 40, 48, 64, 96}
  *   sample       targets in the accuracy sample, 1..n (0 selects min(n, 256))
  *   best         [host] receives the chosen options (p, leaf_size, and the launch shape
- *                near_walk, near_groups timed on the chosen plan; max_level 0, flags 0)
+ *                near_walk, near_groups timed on the chosen plan, four shapes in turn over three
+ *                rounds; a shape other than the default needs to be more than 2% faster;
+ *                max_level 0, flags 0)
  *   err, eval_ms [host, may be NULL] the chosen pair's measured error and median eval time
  * Returns FMMHP_EUNSUPPORTED if no candidate reaches tol at p = 40.  Synchronises the stream;
  * allocates and frees its own temporaries. */

@@ -46,21 +46,40 @@ struct DevTmp {
     }
 };
 
-// Median of five timed evaluations (n_vec vectors).
+// Median over three rounds of the mean time of five back-to-back evaluations (n_vec vectors),
+// after one untimed evaluation: the steady state of a loop of evaluations, in which one
+// evaluation's first kernels overlap the tail of the one before.
 static fmmhp_status median_ms(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipEvent_t e0,
                               hipEvent_t e1, hipStream_t s, double *med) {
+    constexpr int kRounds = 3, kPerRound = 5;
+    FMMHP_CHECK(fmmhp_eval(plan, n_vec, q, phi, s));
     std::vector<float> t;
-    for (int r = 0; r < 5; ++r) {
+    for (int r = 0; r < kRounds; ++r) {
         FMMHP_HIP(hipEventRecord(e0, s));
-        FMMHP_CHECK(fmmhp_eval(plan, n_vec, q, phi, s));
+        for (int k = 0; k < kPerRound; ++k) FMMHP_CHECK(fmmhp_eval(plan, n_vec, q, phi, s));
         FMMHP_HIP(hipEventRecord(e1, s));
         FMMHP_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         FMMHP_HIP(hipEventElapsedTime(&ms, e0, e1));
-        t.push_back(ms);
+        t.push_back(ms / kPerRound);
     }
     std::sort(t.begin(), t.end());
     *med = t[t.size() / 2];
+    return FMMHP_OK;
+}
+
+// Mean time of five back-to-back evaluations after one untimed evaluation.
+static fmmhp_status mean_ms(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipEvent_t e0,
+                            hipEvent_t e1, hipStream_t s, double *ms_out) {
+    constexpr int kPerRound = 5;
+    FMMHP_CHECK(fmmhp_eval(plan, n_vec, q, phi, s));
+    FMMHP_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < kPerRound; ++k) FMMHP_CHECK(fmmhp_eval(plan, n_vec, q, phi, s));
+    FMMHP_HIP(hipEventRecord(e1, s));
+    FMMHP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FMMHP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / kPerRound;
     return FMMHP_OK;
 }
 
@@ -150,26 +169,37 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
             (void)fmmhp_plan_destroy(plan);
         }
     }
-    // launch shape of the near field on the chosen plan
+    // launch shape of the near field on the chosen plan: the shapes are timed in turn over three
+    // rounds (so that a drift of the clocks favours none), each by the median of its rounds; another
+    // shape replaces the library default only when it is more than 2% faster
     if (st == FMMHP_OK && best_ms < INFINITY) {
         fmmhp_plan_t plan = nullptr;
         st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &bo, s, &plan);
         if (st == FMMHP_OK) {
-            static const int kShapes[][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}};
-            double shape_ms = INFINITY;
-            for (const auto &sh : kShapes) {
-                apply_launch_shape(plan->sched, sh[0], sh[1]);
-                double med = INFINITY;
-                st = median_ms(plan, n_vec, qv, phi, e0, e1, s, &med);
-                if (st != FMMHP_OK) break;
-                if (med < shape_ms) {
-                    shape_ms = med;
-                    bo.near_walk = sh[0];
-                    bo.near_groups = sh[1];
+            constexpr int kShapes = 4, kRounds = 3;
+            static const int shapes[kShapes][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}};
+            const int def_walk = plan->sched.PB >= 30 ? 2 : 1, def_groups = def_walk == 2 ? 4 : 2;
+            double t[kShapes][kRounds];
+            for (int r = 0; r < kRounds && st == FMMHP_OK; ++r)
+                for (int k = 0; k < kShapes && st == FMMHP_OK; ++k) {
+                    apply_launch_shape(plan->sched, shapes[k][0], shapes[k][1]);
+                    st = mean_ms(plan, n_vec, qv, phi, e0, e1, s, &t[k][r]);
                 }
+            if (st == FMMHP_OK) {
+                double med[kShapes];
+                int kd = 0, kb = 0;
+                for (int k = 0; k < kShapes; ++k) {
+                    std::sort(t[k], t[k] + kRounds);
+                    med[k] = t[k][kRounds / 2];
+                    if (shapes[k][0] == def_walk && shapes[k][1] == def_groups) kd = k;
+                    if (med[k] < med[kb]) kb = k;
+                }
+                const int k = med[kb] < 0.98 * med[kd] ? kb : kd;
+                bo.near_walk = shapes[k][0];
+                bo.near_groups = shapes[k][1];
+                best_ms = med[k];
             }
             (void)fmmhp_plan_destroy(plan);
-            if (st == FMMHP_OK) best_ms = shape_ms;
         }
     }
     (void)hipEventDestroy(e0);
