@@ -106,3 +106,23 @@ def test_serial_schedule_same_results(Z):
         plan.close()
         assert ms > 0.0 and n >= 1
     assert np.array_equal(out[False], out[True])
+
+
+@pytest.mark.parametrize("n,groups", [(1500, 2), (70001, 1), (70001, 2)])
+def test_xcd_chunk_mapping_covers_every_target(n, groups):
+    """The prefetching walk's workgroups take 256-target chunks by XCD (one contiguous range of
+    chunks per XCD): with fewer chunks than eight workgroups (n = 1500), more chunks than
+    workgroups with a remainder (70,001 targets, 274 chunks, 256 workgroups) and more workgroups
+    than chunks, every target's near-field sums must equal the plain walk's (which takes targets
+    by plain grid stride), so no chunk is skipped or taken twice."""
+    x, y, q = _problem(n, 11)
+    res = {}
+    for w, g in ((1, groups), (2, 4)):
+        plan = F.HalfPlaneFMM(_t(x), _t(y), 1.0 + 0.25j, p=20, leaf_size=32, near_walk=w, near_groups=g)
+        res[w] = plan(_t(q[0])).cpu().numpy()
+        plan.close()
+    diff = np.abs(res[1] - res[2])
+    scale = np.max(np.abs(res[2]))
+    print(f"n={n} groups={groups}: max |walk1 - walk2| / max|phi| {diff.max() / scale:.2e}", flush=True)
+    assert np.all(np.isfinite(res[1]))
+    assert diff.max() <= 1e-12 * scale
