@@ -137,8 +137,8 @@ enum {
 };
 
 /* Build a plan: the adaptive quadtree over the points and their images, interaction lists and
- * translation tables (Algorithm 1: "generate image coordinates", "generate an adaptive hierarchical
- * tree ... and pre-compute some tables").
+ * translation tables (Algorithm 1, its image, tree and table steps; tables from eq.
+ * (integralrecursion)).
  *
  *   n              number of points (sources = targets), 1 <= n < 2^31
  *   x, y           [device] point coordinates, y > 0, finite
@@ -209,6 +209,7 @@ fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const d
  */
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
                         hipStream_t stream);
+
 
 /* Evaluate phi = A q for n_vec complex charge vectors: the operator is linear over the reals in the
  * charges, so phi[q] = phi[Re q] + i phi[Im q], computed as two real passes and combined on the

@@ -3,9 +3,9 @@
  * and its U/V/W/X interaction lists.  CPU ORACLE: test infrastructure only;
  * nothing in the GPU library links, includes or calls this file.
  *
- * Algorithm 1 (Section 2.2) builds "an adaptive hierarchical tree structure
- * with target points and image source points" and the FMM uses the
- * interaction lists of the classic adaptive FMM.  The paper leaves the details
+ * Algorithm 1 (Section 2.2) builds one adaptive tree over the target points
+ * and the image source points, and the FMM uses the interaction lists of the
+ * classic adaptive FMM.  The paper leaves the details
  * open; this file fixes them (the "tree spec") so that a second, independent
  * build can be compared with it bit for bit:
  *

@@ -328,6 +328,7 @@ class HalfPlaneFMM:
         self.impedance = complex(lr, li)
         self.n_inst = 1
         self.n_out = self.n
+        self._graph = bool(graph)
 
     @classmethod
     def with_targets(cls, xs, ys, xt, yt, impedance, p=20, leaf_size=40, max_level=0, graph=False,
@@ -352,6 +353,7 @@ class HalfPlaneFMM:
                                                    xt.data_ptr(), yt.data_ptr(), lr, li, opts, _stream())
         self.impedance = complex(lr, li)
         self.n_inst = 1
+        self._graph = bool(graph)
         return self
 
     @classmethod
@@ -382,6 +384,7 @@ class HalfPlaneFMM:
                                                  opts, _stream())
         self.impedance = imps[0] if self.n_inst == 1 else imps
         self.n_out = self.n
+        self._graph = bool(graph)
         return self
 
     def info(self) -> dict:
@@ -417,6 +420,11 @@ class HalfPlaneFMM:
             parts = q2.to(torch.float64).contiguous()
         direct_out = (out is not None and out.dtype == torch.complex128 and out.is_contiguous()
                       and out.device == self.device and out.numel() == nv * self.n_out)
+        if getattr(self, "_graph", False) and not direct_out:
+            # the recorded graph is keyed on the charge and output pointers: a fresh output tensor per
+            # call would re-record it every time
+            raise ValueError("a plan built with graph=True needs out= (a contiguous complex128 tensor with "
+                             f"{nv * self.n_out} elements on {self.device}) so that replays reuse one graph")
         if direct_out:
             raw = torch.view_as_real(out)
         else:

@@ -2323,7 +2323,8 @@ struct PassOut {
 // One pass over NV charge vectors q [NV][n] (caller order).  Far-field kernels take the vector
 // from blockIdx.y; the near-field kernels share each pair's kernel value among the NV vectors.
 template <int PB, int MODE, int NV>
-static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
+static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, const double *q, const PassOut &out,
+                              hipStream_t s) {
     // the near field and the deep-level M2L run on streams of their own (all on s when serial)
     hipStream_t side_ = S.serial ? s : S.side, side2_ = S.serial ? s : S.side2;
     constexpr bool DIP = is_dip(MODE);
@@ -2332,14 +2333,14 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     Marks mk_;
     FMMHP_CHECK(mk_.init(S));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2M, s));
-    hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, NV, S.qs);
+    hipLaunchKernelGGL(k_gather_q, dim3(nblk(T.n, 256)), dim3(256), 0, s, q, T.perm, T.n, NV, ws.qs);
     // the near field needs only the sorted charges: run it on the side stream, concurrently with
     // the far-field chain, and join before the final leaf kernel
     LeafArgs la{S.inst_info, T.inst,    T.n_inst, NV,       T.n,      nbox,     S.nloc,   T.xs,     T.ys,
-                S.qs,        S.xy,      T.perm,   T.leaf_of, T.level, T.bx,     T.by,     T.first,  T.count,
-                T.off[0],    T.ent[0],  T.off[2], T.ent[2], S.W,      S.Lam,    S.invfact, S.fact,
-                S.bc == 0 ? S.rank1 : nullptr,
-                S.wpts,      S.n_wpts,  S.rpts,   S.logtab, S.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
+                ws.qs,        S.xy,      T.perm,   T.leaf_of, T.level, T.bx,     T.by,     T.first,  T.count,
+                T.off[0],    T.ent[0],  T.off[2], T.ent[2], ws.W,      ws.Lam,    S.invfact, S.fact,
+                S.bc == 0 ? ws.rank1 : nullptr,
+                S.wpts,      S.n_wpts,  S.rpts,   S.logtab, ws.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
                 out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0, S.nrm};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(side_, S.ev_fork, 0));
@@ -2358,15 +2359,15 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     // the surface sums also need only the sorted charges
     if (S.nloc == 1 && S.bc == 0 && S.rank1_side) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rank1_partial<DIP>), dim3(S.n_rch, NV), dim3(256), 0, side_, T.xs,
-                           T.ys, S.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, S.red);
-        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, side_, S.red, S.n_rch, S.inst_ch,
-                           T.n_inst, S.rank1);
+                           T.ys, ws.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, ws.red);
+        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, side_, ws.red, S.n_rch, S.inst_ch,
+                           T.n_inst, ws.rank1);
         FMMHP_HIP(hipGetLastError());
     }
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near1, side_));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<PB, DIP>), dim3(nblk((int64_t)T.nleaf * kP2MSplit, 256), NV), dim3(256),
                        0, s, S.inst_info, T.inst, S.leaves, T.nleaf, nbox, NV, T.level, T.bx, T.by, T.first, T.count,
-                       T.xs, T.ys, S.qs, S.nrm, S.W);
+                       T.xs, T.ys, ws.qs, S.nrm, ws.W);
     FMMHP_HIP(hipGetLastError());
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_M2M, s));
     // M2L (+ image M2L, P2L) over the levels [l0, l1) of the tree on stream st
@@ -2377,11 +2378,11 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
             static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
             if (S.m2l_fp32) {
                 M2L32Args ma{nbox,    t0,        S.tiles, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
-                             S.Bf32,  S.Lfree,   S.logside, S.fact,       S.W,        S.Lam,       S.nloc};
+                             S.Bf32,  S.Lfree,   S.logside, S.fact,       ws.W,        ws.Lam,       S.nloc};
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(t1 - t0, NV), dim3(256), 0, st, ma);
             } else {
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
-                           S.tile_mask, S.Tfree, S.Lfree, S.logside,  S.W,            S.Lam,      S.nloc};
+                           S.tile_mask, S.Tfree, S.Lfree, S.logside,  ws.W,            ws.Lam,      S.nloc};
                 const int which = deep ? 0 : 1;
                 FMMHP_CHECK(mk_.km_mark(which, 0, st));
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)), 0,
@@ -2394,13 +2395,13 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>),
                                dim3(nblk((int64_t)(i1 - i0) * (PB + 1) * kImgSplit, 256), NV),
                                dim3(256), 0, st, i1 - i0, S.ibox + i0, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
-                               S.TimgH, S.TimgG, S.Limg, S.logside, S.bc == 2 ? -1.0 : 1.0, S.W, S.Lam);
+                               S.TimgH, S.TimgG, S.Limg, S.logside, S.bc == 2 ? -1.0 : 1.0, ws.W, ws.Lam);
         const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
         if (x1 > x0)
             for (int loc = 0; loc < S.nloc; ++loc)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP>), dim3(x1 - x0, NV), dim3(64), 0, st, S.inst_info,
                                    T.inst, NV, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count,
-                                   T.off[3], T.ent[3], T.xs, T.ys, S.qs, S.nrm, S.fact, S.Lam);
+                                   T.off[3], T.ent[3], T.xs, T.ys, ws.qs, S.nrm, S.fact, ws.Lam);
         FMMHP_HIP(hipGetLastError());
         return FMMHP_OK;
     };
@@ -2421,7 +2422,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     if (lc > 0 && lf >= lc) lf = T.depth;  // inside the subtree pass: fork right after it
     if (lc > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_sub, NV), dim3(256),
-                           (PB + 1) * S.sub_ld_m2m * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_m2m, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+                           (PB + 1) * S.sub_ld_m2m * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_m2m, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
     if (ld > 0 && lf > T.depth - 1) FMMHP_CHECK(fork_deep());
     // above the cut: with a top subtree pass, the parents of levels 3..lc-1 in one launch (subtrees
     // rooted at level 3, the cut level's multipoles their inputs), then level 2
@@ -2429,7 +2430,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     if (S.n_top > 0) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_top, NV), dim3(256),
                            (PB + 1) * S.top_ld_m2m * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_m2m, nbox,
-                           T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+                           T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
         if (ld > 0 && lf >= 3 && lf <= l_top) FMMHP_CHECK(fork_deep());
         l_top = 2;
     }
@@ -2438,7 +2439,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m<PB>), dim3(nblk(nb, kM2MParents), NV), dim3(256),
                                (PB + 1) * 4 * kM2MParents * sizeof(cplx), s, lo, nb,
-                               nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, S.W);
+                               nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
         if (ld > 0 && l == lf) FMMHP_CHECK(fork_deep());
     }
     FMMHP_HIP(hipGetLastError());
@@ -2460,7 +2461,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         const int64_t tot = (int64_t)(hi - lo) * (PB + 1) * S.nloc * NV;
         if (tot > 0)
             hipLaunchKernelGGL(k_zero_lam, dim3(nblk(tot, 256)), dim3(256), 0, s, lo, hi, nbox, PB + 1, S.nloc * NV,
-                               S.Lam);
+                               ws.Lam);
     }
     FMMHP_CHECK(far_levels(2, ld > 0 ? ld : T.depth + 1, s, false));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_P2L, s));
@@ -2475,16 +2476,16 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
         if (nb > 0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l<PB>), dim3(nblk(nb, kL2LChildren), NV), dim3(256),
                                (PB + 1) * kL2LChildren * sizeof(cplx), s, lo, nb,
-                               nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+                               nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, ws.Lam);
     }
     if (S.n_top > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_top, NV), dim3(256),
                            (PB + 1) * S.top_ld_l2l * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_l2l, nbox,
-                           S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+                           S.nloc, T.parent, T.bx, T.by, S.E_l2l, ws.Lam);
     if (ld > 0 && ld > l2l_end) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
     if (lc > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_sub, NV), dim3(256),
-                           (PB + 1) * S.sub_ld_l2l * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_l2l, nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, S.Lam);
+                           (PB + 1) * S.sub_ld_l2l * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_l2l, nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, ws.Lam);
     if (mk_.on && ld == 0) {
         FMMHP_HIP(hipEventRecord(mk_.deep0, s));
         FMMHP_HIP(hipEventRecord(mk_.deep1, s));
@@ -2493,9 +2494,9 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_SURF, s));
     if (S.nloc == 1 && S.bc == 0 && !S.rank1_side) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rank1_partial<DIP>), dim3(S.n_rch, NV), dim3(256), 0, s, T.xs, T.ys,
-                           S.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, S.red);
-        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, s, S.red, S.n_rch, S.inst_ch, T.n_inst,
-                           S.rank1);
+                           ws.qs, NV, S.rch, S.n_rch, S.inst_info, S.nrm, ws.red);
+        hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, NV), dim3(256), 0, s, ws.red, S.n_rch, S.inst_ch, T.n_inst,
+                           ws.rank1);
         FMMHP_HIP(hipGetLastError());
     }
     FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
@@ -2512,16 +2513,17 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const double *q, co
 }
 
 template <int MODE, int NV>
-static fmmhp_status run_pass(const Tree &T, const Sched &S, const double *q, const PassOut &out, hipStream_t s) {
+static fmmhp_status run_pass(const Tree &T, const Sched &S, const VecWs &ws, const double *q, const PassOut &out,
+                             hipStream_t s) {
     switch (S.PB) {
-        case 5: return eval_pass<5, MODE, NV>(T, S, q, out, s);
-        case 10: return eval_pass<10, MODE, NV>(T, S, q, out, s);
-        case 15: return eval_pass<15, MODE, NV>(T, S, q, out, s);
-        case 20: return eval_pass<20, MODE, NV>(T, S, q, out, s);
-        case 25: return eval_pass<25, MODE, NV>(T, S, q, out, s);
-        case 30: return eval_pass<30, MODE, NV>(T, S, q, out, s);
-        case 35: return eval_pass<35, MODE, NV>(T, S, q, out, s);
-        case 40: return eval_pass<40, MODE, NV>(T, S, q, out, s);
+        case 5: return eval_pass<5, MODE, NV>(T, S, ws, q, out, s);
+        case 10: return eval_pass<10, MODE, NV>(T, S, ws, q, out, s);
+        case 15: return eval_pass<15, MODE, NV>(T, S, ws, q, out, s);
+        case 20: return eval_pass<20, MODE, NV>(T, S, ws, q, out, s);
+        case 25: return eval_pass<25, MODE, NV>(T, S, ws, q, out, s);
+        case 30: return eval_pass<30, MODE, NV>(T, S, ws, q, out, s);
+        case 35: return eval_pass<35, MODE, NV>(T, S, ws, q, out, s);
+        case 40: return eval_pass<40, MODE, NV>(T, S, ws, q, out, s);
         default:
             set_error("internal: no kernels compiled for p = %d", S.PB);
             return FMMHP_EUNSUPPORTED;
@@ -2532,15 +2534,16 @@ static fmmhp_status run_pass(const Tree &T, const Sched &S, const double *q, con
 // Per-vector workspace (multipoles, locals, sorted charges, near-field sums, surface sums) for nv
 // vectors at once; grown on demand, owned by the plan.
 static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
-    if (S.nv_cap >= nv) return FMMHP_OK;
+    VecWs &w = S.ws;
+    if (w.cap >= nv) return FMMHP_OK;
     const size_t nb = (size_t)T.nbox, P1 = (size_t)S.PB + 1;
-    FMMHP_CHECK(A.alloc_n(&S.W, nv * P1 * nb, "multipoles"));
-    FMMHP_CHECK(A.alloc_n(&S.Lam, nv * (size_t)S.nloc * P1 * nb, "locals"));
-    FMMHP_CHECK(A.alloc_n(&S.qs, nv * (size_t)T.n, "sorted charges"));
-    FMMHP_CHECK(A.alloc_n(&S.near, nv * (size_t)T.n, "near-field sums"));
-    FMMHP_CHECK(A.alloc_n(&S.red, nv * (size_t)S.n_rch, "surface partial sums"));
-    FMMHP_CHECK(A.alloc_n(&S.rank1, nv * (size_t)T.n_inst, "surface sums"));
-    S.nv_cap = nv;
+    FMMHP_CHECK(A.alloc_n(&w.W, nv * P1 * nb, "multipoles"));
+    FMMHP_CHECK(A.alloc_n(&w.Lam, nv * (size_t)S.nloc * P1 * nb, "locals"));
+    FMMHP_CHECK(A.alloc_n(&w.qs, nv * (size_t)T.n, "sorted charges"));
+    FMMHP_CHECK(A.alloc_n(&w.near, nv * (size_t)T.n, "near-field sums"));
+    FMMHP_CHECK(A.alloc_n(&w.red, nv * (size_t)S.n_rch, "surface partial sums"));
+    FMMHP_CHECK(A.alloc_n(&w.rank1, nv * (size_t)T.n_inst, "surface sums"));
+    w.cap = nv;
     return FMMHP_OK;
 }
 
@@ -2550,12 +2553,12 @@ static fmmhp_status enqueue_eval(const Tree &T, const Sched &S, int nvec, const 
     for (; v + kVecChunk <= nvec; v += kVecChunk) {
         PassOut o;
         o.phi = phi + (int64_t)v * 2 * T.n;
-        FMMHP_CHECK((run_pass<kPhi, kVecChunk>(T, S, q + (int64_t)v * T.n, o, s)));
+        FMMHP_CHECK((run_pass<kPhi, kVecChunk>(T, S, S.ws, q + (int64_t)v * T.n, o, s)));
     }
     for (; v < nvec; ++v) {
         PassOut o;
         o.phi = phi + (int64_t)v * 2 * T.n;
-        FMMHP_CHECK((run_pass<kPhi, 1>(T, S, q + (int64_t)v * T.n, o, s)));
+        FMMHP_CHECK((run_pass<kPhi, 1>(T, S, S.ws, q + (int64_t)v * T.n, o, s)));
     }
     return FMMHP_OK;
 }
@@ -2653,7 +2656,7 @@ fmmhp_status run_eval_dlp(Arena &A, const Tree &T, Sched &S, int nvec, const dou
         if (w == 1) {
             PassOut o;
             o.phi = phi + (int64_t)v * 2 * T.n;
-            FMMHP_CHECK((run_pass<kDip, 1>(T, S, mu + (int64_t)v * T.n, o, s)));
+            FMMHP_CHECK((run_pass<kDip, 1>(T, S, S.ws, mu + (int64_t)v * T.n, o, s)));
             continue;
         }
         hipLaunchKernelGGL(k_split_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, mu + (int64_t)v * 2 * T.n, T.n,
@@ -2662,7 +2665,7 @@ fmmhp_status run_eval_dlp(Arena &A, const Tree &T, Sched &S, int nvec, const dou
         for (int h = 0; h < 2; ++h) {
             PassOut o;
             o.phi = S.cphi + (int64_t)h * 2 * T.n;
-            FMMHP_CHECK((run_pass<kDip, 1>(T, S, S.cq + (int64_t)h * T.n, o, s)));
+            FMMHP_CHECK((run_pass<kDip, 1>(T, S, S.ws, S.cq + (int64_t)h * T.n, o, s)));
         }
         hipLaunchKernelGGL(k_combine_complex, dim3(nblk(T.n, 256)), dim3(256), 0, s, S.cphi, T.n,
                            phi + (int64_t)v * 2 * T.n);
@@ -2767,13 +2770,13 @@ fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, co
         po.gx = b.gx3;
         po.gy = b.gy3;
         po.qc = b.qc;
-        FMMHP_CHECK((run_pass<kPhiGrad, 3>(T, S, b.q3, po, s)));
+        FMMHP_CHECK((run_pass<kPhiGrad, 3>(T, S, S.ws, b.q3, po, s)));
     } else {
         // dl/dq only: the potentials of Re conj(g) and Im conj(g)
         for (int v = 1; v < 3; ++v) {
             PassOut po;
             po.phi = (double *)(b.phi3 + v * n);
-            FMMHP_CHECK((run_pass<kPhi, 1>(T, S, b.q3 + v * n, po, s)));
+            FMMHP_CHECK((run_pass<kPhi, 1>(T, S, S.ws, b.q3 + v * n, po, s)));
         }
     }
     BwdArgs ba{S.inst_info, S.rch,         T.xs,          T.ys,          T.perm,    q,      g,
@@ -2801,7 +2804,7 @@ fmmhp_status run_field(Arena &A, const Tree &T, Sched &S, const double *q, doubl
     po.phi = phi;
     po.gx = gx;
     po.gy = gy;
-    return run_pass<kPhiGrad, 1>(T, S, q, po, s);
+    return run_pass<kPhiGrad, 1>(T, S, S.ws, q, po, s);
 }
 
 fmmhp_status collect_phase_times(Sched &S) {

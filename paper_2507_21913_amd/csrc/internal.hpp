@@ -121,6 +121,17 @@ struct BwdWork {
     cplx *red = nullptr;                  // [n chunks + n_inst] reduction partials + results
 };
 
+// Per-vector workspace of an evaluation pass over up to cap charge vectors.
+struct VecWs {
+    int cap = 0;
+    cplx *W = nullptr;              // [nv][PB + 1][nbox] multipoles
+    cplx *Lam = nullptr;            // [nv][nloc][PB + 1][nbox] locals
+    double *qs = nullptr;           // [n][nv] sorted charges, vectors interleaved
+    double2 *near = nullptr;        // [nv][n] near-field sums
+    cplx *red = nullptr;            // [nv][n_rch] surface partial sums
+    cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
+};
+
 // Evaluation schedule and tables derived from the tree.
 struct Sched {
     int PB = 0;                     // compiled truncation order
@@ -151,7 +162,6 @@ struct Sched {
     int2 *u2 = nullptr;             // [U entries] (first point, count | image << 31) of the source box
     double2 *xy = nullptr;          // [n] sorted (x, y) pairs
     double2 *logtab = nullptr;      // near-field log table
-    double2 *near = nullptr;        // [nv_cap][n] near-field sums
     hipStream_t side = nullptr;     // side stream for the near field (default priority)
     hipStream_t side2 = nullptr;    // second side stream: M2L of the deep levels (default priority)
     hipEvent_t ev_deep_ready = nullptr, ev_deep_done = nullptr;
@@ -191,13 +201,7 @@ struct Sched {
     int n_rch = 0;
     PtChunk *rch = nullptr;         // [n_rch]
     int32_t *inst_ch = nullptr;     // [n_inst + 1] chunk range of each instance
-    // workspace for nv_cap charge vectors
-    int nv_cap = 0;
-    cplx *W = nullptr;              // [nv][PB + 1][nbox]
-    cplx *Lam = nullptr;            // [nv][nloc][PB + 1][nbox]
-    double *qs = nullptr;           // [n][nv] sorted charges, vectors interleaved
-    cplx *red = nullptr;            // [nv][n_rch] surface partial sums
-    cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
+    VecWs ws;                       // workspace of the plan's own evaluations
     BwdWork bw;
     double *cq = nullptr, *cphi = nullptr;  // complex-charge workspace ([2][n], [2][n][2])
     double2 *nrm = nullptr;         // [n] source normals in sorted order (double-layer evaluation)
@@ -228,6 +232,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
 void apply_launch_shape(Sched &S, int near_walk, int near_groups);
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
+
 // Double-layer potential of nvec dipole densities mu ([nvec][n], w = 1 real or 2 complex) with
 // source normals nx, ny [n], all in caller order.
 fmmhp_status run_eval_dlp(Arena &A, const Tree &T, Sched &S, int nvec, const double *mu, int w, const double *nx,

@@ -1,6 +1,6 @@
 // GPU construction of the adaptive quadtree over the points and their images, and of the
-// U/V/W/X interaction lists (Algorithm 1: "generate an adaptive hierarchical tree structure with
-// target points and image source points").
+// U/V/W/X interaction lists (Algorithm 1, tree step: one tree over the target points and the
+// image sources).
 //
 // Tree rules (fixed here because the paper leaves them open):
 //  * root square [x_lo, x_lo + S] x [-S/2, S/2], x_lo = min x, S = max(max x - x_lo, 2 max y):

@@ -128,7 +128,7 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
     int p_start = 5;
     fmmhp_status st = FMMHP_OK;
     for (int li = 0; li < n_leaf && st == FMMHP_OK; ++li) {
-        for (int p = p_start; p <= FMMHP_MAX_P; p += 5) {
+        for (int p = p_start; p <= FMMHP_MAX_P && st == FMMHP_OK; p += 5) {
             fmmhp_opts o{p, leaf_sizes[li], 0, 0, 0, 0};
             fmmhp_plan_t plan = nullptr;
             st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &o, s, &plan);
@@ -140,7 +140,8 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
             st = fmmhp_eval(plan, 1, q, phi, s);
             if (st == FMMHP_OK) {
                 hipLaunchKernelGGL(k_gather_phi, dim3((m + 127) / 128), dim3(128), 0, s, phi, n, m, got);
-                if (hipMemcpyAsync(hgot.data(), got, hgot.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                if (hipGetLastError() != hipSuccess ||
+                    hipMemcpyAsync(hgot.data(), got, hgot.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
                         hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess) {
                     set_error("autotuner: device copy failed");

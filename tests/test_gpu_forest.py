@@ -175,12 +175,18 @@ def test_graph_replays_match_eager():
             torch.cuda.synchronize()
         # new buffers: a new recording (2 q: every operation scales exactly, so 2 phi bitwise)
         q2 = _t(2.0 * q)
-        out2 = plan(q2)
+        out2 = torch.empty_like(out)
+        plan(q2, out=out2)
         st.synchronize()
         assert np.array_equal(out2.cpu().numpy(), 2.0 * ref)
+        # a graph plan needs an output buffer of its own (else every call would re-record)
+        with pytest.raises(ValueError):
+            plan(qt)
     # the null stream runs eagerly
     plan_null = F.HalfPlaneFMM.batched(_t(x), _t(y), off, imps, p=20, leaf_size=24, graph=True)
-    assert np.array_equal(plan_null(_t(q)).cpu().numpy(), ref)
+    out3 = torch.empty_like(out)
+    plan_null(_t(q), out=out3)
+    assert np.array_equal(out3.cpu().numpy(), ref)
     plan.close()
     plan_null.close()
     eager.close()

@@ -1,5 +1,5 @@
-"""GPU parity at the full workload sizes (1,048,576 and 4,194,304 points), in the launch
-configuration bench.py times (p = 30, leaf 40):
+"""GPU parity at the full workload sizes (1,048,576 and 4,194,304 points) at p = 30, leaf 40 (the
+benchmark's own plan, p = 20 / leaf 32, is covered by test_gpu_headline.py):
 
 * tree and interaction lists bit-exact against the reference build;
 * potentials against the oracle's direct sum at 256 stored sample targets (all sources), written
