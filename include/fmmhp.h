@@ -210,6 +210,31 @@ fmmhp_status fmmhp_batch_plan_create(int n_inst, const int64_t *offsets, const d
 fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
                         hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): fmmhp_eval with each pass's per-vector workspace (multipoles,
+ * locals, sorted charges, near-field and surface sums) taken from a static device array of the
+ * library, FMMHP_NOALLOC_SCRATCH_BYTES (128 MiB) per device, instead of the plan's memory.  Calls no
+ * hipMalloc, hipFree or allocating routine; launches eagerly on stream (the plan's graph flag is
+ * not used).  Same arguments, layout, ordering and results as fmmhp_eval, for plans whose points are
+ * the targets (fmmhp_plan_create, fmmhp_batch_plan_create).
+ *
+ * Eight vectors share a pass when their workspace fits the array, else vectors run one at a time;
+ * the workspace of one vector is 16 (p + 1)(1 + nloc) bytes per box plus 24 bytes per point (nloc =
+ * 1 for a real impedance, 2 for a complex one, p rounded up to a multiple of 5).  The plan's device
+ * must be the current device.  The first call on a device looks up the array's address there
+ * (hipGetSymbolAddress); each device holds the array until the process ends.  Every call on a device
+ * shares that device's array and leaves its contents behind; evaluations overwrite all of the
+ * workspace they read, so nothing needs clearing, but calls that overlap on one device (different
+ * streams or host threads) race and give wrong results.
+ *
+ * Errors: FMMHP_EINVAL for the arguments fmmhp_eval rejects, or when one vector's workspace exceeds
+ * the array; FMMHP_EUNSUPPORTED for plans with separate targets; FMMHP_ESTATE when phase timing is on
+ * (fmmhp_plan_set_timing) or the plan's device is not current; FMMHP_EHIP when the address lookup
+ * fails.
+ */
+#define FMMHP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+fmmhp_status fmmhp_eval_noalloc(fmmhp_plan_t plan, int n_vec, const double *q, double *phi,
+                                hipStream_t stream);
 
 /* Evaluate phi = A q for n_vec complex charge vectors: the operator is linear over the reals in the
  * charges, so phi[q] = phi[Re q] + i phi[Im q], computed as two real passes and combined on the

@@ -81,6 +81,7 @@ _SIGNATURES = {
     "fmmhp_plan_create_targets": [_I64, _P, _P, _I64, _P, _P, _D, _D, ctypes.POINTER(Opts), _P,
                                   ctypes.POINTER(_P)],
     "fmmhp_eval": [_P, _INT, _P, _P, _P],
+    "fmmhp_eval_noalloc": [_P, _INT, _P, _P, _P],
     "fmmhp_eval_complex": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_eval_field": [_P, _P, _P, _P, _P, _P],
@@ -176,6 +177,14 @@ def fmmhp_batch_plan_create(n_inst, offsets, x_ptr, y_ptr, lambdas, opts, stream
 
 def fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream):
     _check("fmmhp_eval", lib().fmmhp_eval(plan, n_vec, q_ptr, phi_ptr, stream))
+
+
+def fmmhp_eval_noalloc(plan, n_vec, q_ptr, phi_ptr, stream):
+    """fmmhp_eval with its workspace in the library's static device scratch (no allocation)."""
+    _check("fmmhp_eval_noalloc", lib().fmmhp_eval_noalloc(plan, n_vec, q_ptr, phi_ptr, stream))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20  # FMMHP_NOALLOC_SCRATCH_BYTES
 
 
 def fmmhp_backward(plan, q_ptr, grad_phi_ptr, grad_q_ptr, grad_x_ptr, grad_y_ptr, want_lambda,
@@ -618,4 +627,5 @@ __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functi
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
            "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune",
-           "fmmhp_backward", "potential", "fmmhp_batch_plan_create", "fmmhp_eval_complex"]
+           "fmmhp_backward", "potential", "fmmhp_batch_plan_create", "fmmhp_eval_complex",
+           "fmmhp_eval_noalloc", "NOALLOC_SCRATCH_BYTES"]

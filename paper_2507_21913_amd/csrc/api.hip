@@ -313,6 +313,25 @@ fmmhp_status fmmhp_eval(fmmhp_plan_t plan, int n_vec, const double *q, double *p
     return run_eval(plan->arena, plan->tree, plan->sched, n_vec, q, phi, stream);
 }
 
+fmmhp_status fmmhp_eval_noalloc(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (n_vec < 1 || !q || !phi) {
+        set_error("n_vec must be >= 1 and q, phi non-NULL");
+        return FMMHP_EINVAL;
+    }
+    if (plan->n_src > 0) {
+        set_error("fmmhp_eval_noalloc: plans with separate targets are not supported");
+        return FMMHP_EUNSUPPORTED;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) {
+        (void)hipGetLastError();
+        set_error("fmmhp_eval_noalloc: the plan's device %d is not the current device (%d)", plan->device, dev);
+        return FMMHP_ESTATE;
+    }
+    return run_eval_noalloc(plan->tree, plan->sched, dev, n_vec, q, phi, stream);
+}
+
 fmmhp_status fmmhp_eval_complex(fmmhp_plan_t plan, int n_vec, const double *q, double *phi, hipStream_t stream) {
     FMMHP_CHECK(check_plan(plan));
     if (n_vec < 1 || !q || !phi) {

@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <complex>
 #include <thread>
@@ -2559,6 +2560,101 @@ static fmmhp_status enqueue_eval(const Tree &T, const Sched &S, int nvec, const 
         PassOut o;
         o.phi = phi + (int64_t)v * 2 * T.n;
         FMMHP_CHECK((run_pass<kPhi, 1>(T, S, S.ws, q + (int64_t)v * T.n, o, s)));
+    }
+    return FMMHP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Evaluation without allocation (fmmhp_eval_noalloc).  The per-vector workspace of each pass is
+// carved from a file-scope device array instead of the plan's arena.  Host code never uses the
+// array's name as an address: hipGetSymbolAddress gives its address on each device once, and that
+// pointer is what the kernels receive.  Every evaluation fully overwrites the workspace it reads
+// (P2M and M2M write every multipole, the M2L writes the locals of every box of levels >= 2 and
+// level 1 is cleared, the near-field and surface kernels write every sum), so nothing needs clearing
+// between calls.  Calls that overlap on one device share the array and race.
+// ---------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Address of the scratch array on device dev (the current device), looked up once per device.
+static fmmhp_status scratch_on(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d outside the no-allocation scratch table (0..%d)", dev, kMaxDevices - 1);
+        return FMMHP_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error("hipGetSymbolAddress of the no-allocation scratch failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return FMMHP_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return FMMHP_OK;
+}
+
+// Bytes of a pass workspace for nv vectors (each array aligned to 256 bytes); carves it from base
+// when base is given.
+static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char *base, VecWs *w) {
+    const size_t nb = (size_t)T.nbox, P1 = (size_t)S.PB + 1;
+    const size_t sizes[6] = {nv * P1 * nb * sizeof(cplx), nv * (size_t)S.nloc * P1 * nb * sizeof(cplx),
+                             nv * (size_t)T.n * sizeof(double), nv * (size_t)T.n * sizeof(double2),
+                             nv * (size_t)S.n_rch * sizeof(cplx), nv * (size_t)T.n_inst * sizeof(cplx)};
+    size_t off[6], at = 0;
+    for (int k = 0; k < 6; ++k) {
+        off[k] = at;
+        at += (sizes[k] + 255) / 256 * 256;
+    }
+    if (base) {
+        w->cap = nv;
+        w->W = (cplx *)(base + off[0]);
+        w->Lam = (cplx *)(base + off[1]);
+        w->qs = (double *)(base + off[2]);
+        w->near = (double2 *)(base + off[3]);
+        w->red = (cplx *)(base + off[4]);
+        w->rank1 = (cplx *)(base + off[5]);
+    }
+    return at;
+}
+
+fmmhp_status run_eval_noalloc(const Tree &T, const Sched &S, int device, int nvec, const double *q, double *phi,
+                              hipStream_t s) {
+    if (S.timing) {
+        set_error("fmmhp_eval_noalloc: phase timing is on for this plan (its events would be created per call)");
+        return FMMHP_ESTATE;
+    }
+    const size_t one = vec_ws_layout(T, S, 1, nullptr, nullptr);
+    if (one > kNoAllocScratchBytes) {
+        set_error("fmmhp_eval_noalloc: the plan needs %zu bytes of workspace per charge vector, more than the %zu "
+                  "bytes of the no-allocation scratch",
+                  one, (size_t)kNoAllocScratchBytes);
+        return FMMHP_EINVAL;
+    }
+    unsigned char *base = nullptr;
+    FMMHP_CHECK(scratch_on(device, &base));
+    VecWs w1, w8;
+    vec_ws_layout(T, S, 1, base, &w1);
+    const bool wide = nvec >= kVecChunk && vec_ws_layout(T, S, kVecChunk, nullptr, nullptr) <= kNoAllocScratchBytes;
+    if (wide) vec_ws_layout(T, S, kVecChunk, base, &w8);
+    int v = 0;
+    if (wide)
+        for (; v + kVecChunk <= nvec; v += kVecChunk) {
+            PassOut o;
+            o.phi = phi + (int64_t)v * 2 * T.n;
+            FMMHP_CHECK((run_pass<kPhi, kVecChunk>(T, S, w8, q + (int64_t)v * T.n, o, s)));
+        }
+    for (; v < nvec; ++v) {
+        PassOut o;
+        o.phi = phi + (int64_t)v * 2 * T.n;
+        FMMHP_CHECK((run_pass<kPhi, 1>(T, S, w1, q + (int64_t)v * T.n, o, s)));
     }
     return FMMHP_OK;
 }

@@ -15,6 +15,7 @@ constexpr int kLBits = 30;        // integer cell bits per axis of the root squa
 constexpr int kLBitsForest = 27;  // the same in a forest (instance index in the top key bits)
 constexpr int kMaxInstances = 512;
 constexpr int kVecChunk = 8;        // charge vectors evaluated together
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;  // device scratch of fmmhp_eval_noalloc
 constexpr int64_t kSurfChunk = 2048;  // points per partial sum of the surface term
 constexpr double kMaxTablePZ = 24.0;   // |Z| * distance covered by the M2L tables
 constexpr double kMaxDevicePZ = 12.0;  // the same for the device-side I_n recursion (W, X lists)
@@ -232,7 +233,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
 void apply_launch_shape(Sched &S, int near_walk, int near_groups);
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
-
+// The same evaluation with each pass's workspace in the library's static device scratch (no
+// allocation); device is the plan's device, which must be current.
+fmmhp_status run_eval_noalloc(const Tree &T, const Sched &S, int device, int nvec, const double *q, double *phi,
+                              hipStream_t stream);
 // Double-layer potential of nvec dipole densities mu ([nvec][n], w = 1 real or 2 complex) with
 // source normals nx, ny [n], all in caller order.
 fmmhp_status run_eval_dlp(Arena &A, const Tree &T, Sched &S, int nvec, const double *mu, int w, const double *nx,
