@@ -490,16 +490,30 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
 // contraction is a real GEMM in the 2x2 embedding of complex numbers:
 //   [Re acc, Im acc](64 x 2(p+1)) += [Re w'', Im w''](64 x 2(p+1)) * [[Re T'', Im T''], [-Im T'', Re T'']]
 // with the factorial scaling w''_m = m! w_m, T''_{nm} = T_{n+m} / (n! m!), acc''_n = lambda_n / n!,
-// which keeps every operand within FP32 range (|T''_{nm}| <= 2^-(n+m) for separated boxes).  Each
-// wave owns 16 target boxes (one 16-row M tile) and runs v_mfma_f32_16x16x4f32 over K (= 2(p+1)
-// padded to a multiple of 4) and N (padded to a multiple of 16); the FP32 sums of one slot are
-// added into FP64 accumulators before the next slot.  The log term of lambda_0 stays in FP64.
-// Lane layout of the instruction: A[i][k] from lane 16 k + i, B[k][j] from lane 16 k + j,
-// D[4 (l / 16) + r][l % 16] in element r of lane l.
+// which keeps every operand within FP32 range (|T''_{nm}| <= 2^-(n+m) for separated boxes).  The
+// FP32 sums of one slot are added into FP64 accumulators before the next slot; the log term of
+// lambda_0 stays in FP64.
+//
+// Instruction: v_mfma_f32_16x16x1f32, four independent 16 x 16 rank-one updates (blocks).  Lane l
+// gives A[block l / 16][row l % 16] and B[block l / 16][column l % 16]; element r of lane l holds
+// D[block r / 4][row 4 (l / 16) + r % 4][column l % 16] (layout measured on the device).  The four
+// blocks are the four 16-target row groups of a 64-target tile (lane l: target l), all with the
+// same operator column block, so one instruction is a 64 x 16 x 1 step.  Wave pair w of the workgroup
+// owns output columns [16 w, 16 w + 16), its two waves taking every other used slot (their sums
+// joined through LDS at the end); K = 2(p+1) steps per slot run as two independent accumulation
+// chains; the other dimension is not padded (2(p+1) columns padded to 16 only).
+// (v_mfma_f32_16x16x4f32, the 16 x 16 x 4 single-block form, issues at about a fifth of this rate on
+// gfx950.)  The operator column of the next slot is prefetched from global memory (the [slot]
+// [column][k] table stays in L2) while the current slot runs; the tile's sources, all coefficients,
+// and its (slot, target) -> source map are staged in LDS once, so waves walk their slots without
+// barriers or global loads on the path to the instructions.
 // ---------------------------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__host__ __device__ constexpr int m2l32_kp(int PB) { return ((2 * (PB + 1) + 3) / 4) * 4; }
+// Row length of a source in the FP32 M2L: 2(p+1) embedded coefficients, the low parts of Re w_0 and
+// Im w_0, zero padding to a multiple of 4.
+__host__ __device__ constexpr int m2l32_kp(int PB) { return ((2 * (PB + 1) + 2 + 3) / 4) * 4; }
 __host__ __device__ constexpr int m2l32_np(int PB) { return ((2 * (PB + 1) + 15) / 16) * 16; }
 
 struct M2L32Args {
@@ -508,131 +522,205 @@ struct M2L32Args {
     const int32_t *tiles, *tile_src_off, *tile_src;
     const int16_t *tile_slot;
     const uint64_t *tile_mask;
-    const float *B;          // [kNumSlots][KP][NP] embedded scaled operators
+    const float *B;          // [kNumSlots][NP][KP] embedded scaled operators, column-major per slot
     const cplx *Lfree;
     const double *logside;
     const double *fact;      // n!
-    const cplx *W;           // [nv][PB + 1][nbox]
+    const float *Wf;         // [nv][nbox][KP] FP32 source rows (k_w_f32)
     cplx *Lam;               // [nv][nloc][PB + 1][nbox]
     int nloc;
 };
 
+// One K pass of a slot: A from the target's source row in LDS (the zero row when the target has
+// no source at this slot), B from the prefetched operator column; two accumulation chains.
+template <int K, int KQ>
+__device__ __forceinline__ void m2l32_slot(const float4 *__restrict__ ar, const float4 (&bc)[KQ], double (&acc)[16]) {
+    f32x16 d0, d1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d0[r] = d1[r] = 0.f;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const float4 av = ar[q];
+        if (4 * q + 0 < K) d0 = __builtin_amdgcn_mfma_f32_16x16x1f32(av.x, bc[q].x, d0, 0, 0, 0);
+        if (4 * q + 1 < K) d1 = __builtin_amdgcn_mfma_f32_16x16x1f32(av.y, bc[q].y, d1, 0, 0, 0);
+        if (4 * q + 2 < K) d0 = __builtin_amdgcn_mfma_f32_16x16x1f32(av.z, bc[q].z, d0, 0, 0, 0);
+        if (4 * q + 3 < K) d1 = __builtin_amdgcn_mfma_f32_16x16x1f32(av.w, bc[q].w, d1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += (double)(d0[r] + d1[r]);
+}
+
+// FP32 source rows of the matrix-core M2L for the boxes [lo, hi): row b = [Re w''_0..p, Im w''_0..p]
+// (w''_m = m! w_m, FP32), then w_0 - (its FP32 part) for the real and imaginary parts (so that the
+// log term recovers w_0 in FP64 to about 2^-48), zero padding.  Written once per evaluation, so that
+// each M2L tile stages a source with contiguous 16-byte loads.
 template <int PB>
-__global__ __launch_bounds__(256) void k_m2l_f32(M2L32Args a) {
-    constexpr int P1 = PB + 1, KP = m2l32_kp(PB), NP = m2l32_np(PB);
-    constexpr int KS = KP / 4, NT = NP / 16;
-    constexpr int BSZ = KP * NP, BPER = (BSZ + 255) / 256;
-    __shared__ float sA[kM2LMaxSrc32 * KP];
-    __shared__ float sB[2][BSZ];
+__global__ __launch_bounds__(256) void k_w_f32(int lo, int hi, int nbox, const double *__restrict__ fact,
+                                               const cplx *__restrict__ W, float *__restrict__ Wf) {
+    constexpr int P1 = PB + 1, K = 2 * P1, KP = m2l32_kp(PB);
+    const int b = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= hi) return;
+    W += (int64_t)blockIdx.y * P1 * nbox;  // charge vector
+    Wf += (int64_t)blockIdx.y * nbox * KP;
+    float row[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) row[k] = 0.f;
+#pragma unroll
+    for (int m = 0; m < P1; ++m) {
+        const cplx w = W[(int64_t)m * nbox + b];
+        row[m] = (float)(fact[m] * w.re);
+        row[P1 + m] = (float)(fact[m] * w.im);
+        if (m == 0) {
+            row[K] = (float)(w.re - (double)row[0]);
+            row[K + 1] = (float)(w.im - (double)row[P1]);
+        }
+    }
+    float4 *dst = (float4 *)(Wf + (int64_t)b * KP);
+#pragma unroll
+    for (int q = 0; q < KP / 4; ++q) dst[q] = make_float4(row[4 * q], row[4 * q + 1], row[4 * q + 2], row[4 * q + 3]);
+}
+
+template <int PB>
+__global__ __launch_bounds__(128 * (m2l32_np(PB) / 16)) void k_m2l_f32(M2L32Args a) {
+    constexpr int P1 = PB + 1, K = 2 * P1, KP = m2l32_kp(PB), NP = m2l32_np(PB), NT = NP / 16;
+    constexpr int KQ = KP / 4, NW = 2 * NT;  // waves: two per column block, taking alternate slots
+    static_assert((kM2LMaxSrc + 1) * KQ * 16 >= NT * 64 * 16 * 8, "the partial sums reuse the source rows");
+    static_assert(kNumSlots * kTile * 2 % 16 == 0, "the slot table is copied in 16-byte pieces");
+    __shared__ float4 sA4[(kM2LMaxSrc + 1) * KQ];   // source rows, then one zero row
+    __shared__ int4 s_slot4[kNumSlots * kTile / 8]; // (slot, target) -> source
     __shared__ cplx s_acc0[kTile];
+    __shared__ cplx s_lfree[kNumSlots];
+    __shared__ int32_t s_box[kTile];                // the tile's target boxes
+    __shared__ int32_t s_src[kM2LMaxSrc];           // the tile's source boxes
+    const float *sA = (const float *)sA4;
+    const int16_t *s_slot = (const int16_t *)s_slot4;
     const int tile = blockIdx.x + a.tile0;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int r = lane & 15, kq = lane >> 4;
-    const cplx *W = a.W + (int64_t)blockIdx.y * P1 * a.nbox;  // charge vector
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const float *Wf = a.Wf + (int64_t)blockIdx.y * a.nbox * KP;  // charge vector
     cplx *Lam = a.Lam + (int64_t)blockIdx.y * a.nloc * P1 * a.nbox;
     const int s0 = a.tile_src_off[tile];
     const int ns = a.tile_src_off[tile + 1] - s0;
     const uint64_t mask = a.tile_mask[tile];
-    const int16_t *slot = a.tile_slot + (int64_t)tile * kNumSlots * kTile;
-    // stage the tile's sources: scaled, embedded, FP32
-    for (int idx = tid; idx < KP * ns; idx += 256) {
-        const int k = idx / ns, sj = idx - k * ns;
-        float v = 0.f;
-        if (k < 2 * P1) {
-            const int m = k < P1 ? k : k - P1;
-            const cplx w = W[(int64_t)m * a.nbox + a.tile_src[s0 + sj]];
-            v = (float)(a.fact[m] * (k < P1 ? w.re : w.im));
-        }
-        sA[sj * KP + k] = v;
+    // prologue in two rounds of independent loads: first the tile's tables (slot map, boxes, source
+    // indices, log-term constants), then the source rows (scaled, embedded FP32) and a zero row
+    {
+        const int4 *g = (const int4 *)(a.tile_slot + (int64_t)tile * kNumSlots * kTile);
+        for (int i = tid; i < kNumSlots * kTile / 8; i += 64 * NW) s_slot4[i] = g[i];
+        if (tid < kTile) s_box[tid] = a.tiles[tile * kTile + tid];
+        if (tid < kNumSlots) s_lfree[tid] = a.Lfree[tid];
+        for (int sj = tid; sj < ns; sj += 64 * NW) s_src[sj] = a.tile_src[s0 + sj];
     }
-    // log term of lambda_0 in FP64, one lane per target
+    __syncthreads();
+    for (int sj = tid; sj < ns; sj += 2 * 64 * NW) {
+        const int sj2 = sj + 64 * NW;
+        const float4 *r1 = (const float4 *)(Wf + (int64_t)s_src[sj] * KP);
+        const float4 *r2 = sj2 < ns ? (const float4 *)(Wf + (int64_t)s_src[sj2] * KP) : r1;
+        float4 v1[KQ], v2[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            v1[q] = r1[q];
+            v2[q] = r2[q];
+        }
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) sA4[sj * KQ + q] = v1[q];
+        if (sj2 < ns) {
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) sA4[sj2 * KQ + q] = v2[q];
+        }
+    }
+    for (int q = tid; q < KQ; q += 64 * NW) sA4[ns * KQ + q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int b_own = s_box[lane];
+    const double ll = wave == 0 && b_own >= 0 ? a.logside[b_own] * kInv4Pi : 0.0;
+    __syncthreads();
+    // log term of lambda_0 in FP64, one lane per target (wave 0): w_0 from its FP32 part and remainder
     if (wave == 0) {
-        const int b = a.tiles[tile * kTile + lane];
-        const double ll = b >= 0 ? a.logside[b] * kInv4Pi : 0.0;
         cplx acc0 = mk(0.0, 0.0);
         uint64_t rest = mask;
         while (rest) {
             const int o = __builtin_ctzll(rest);
             rest &= rest - 1;
-            const int li = slot[o * kTile + lane];
-            if (li >= 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), W[a.tile_src[s0 + li]]);
+            const int li = s_slot[o * kTile + lane];
+            if (li >= 0) {
+                const float *row = sA + li * KP;
+                const cplx w0 = mk((double)row[0] + (double)row[K], (double)row[P1] + (double)row[K + 1]);
+                cfma(acc0, s_lfree[o] - mk(ll, 0.0), w0);
+            }
         }
         s_acc0[lane] = acc0;
     }
-    f32x4 acc[NT];
-    double acc64[NT][4];
+    double acc[16];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc64[nt][i] = 0.0;
-    }
-    // operator of the first slot into buffer 0; later ones are prefetched into registers while
-    // the current slot runs, then stored to the other buffer
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    const int nt = wave % NT, half = wave / NT;
+    const int col = 16 * nt + (lane & 15);  // operator column of this lane in all four blocks
+    const bool im = col >= P1;
+    const int n = im ? col - P1 : col;       // output coefficient of the column (col < K)
+    const double fn = col < K ? a.fact[n] : 0.0;
+    const float4 *Bcol = (const float4 *)(a.B + (int64_t)col * KP);
+    constexpr int64_t kSlotQ = (int64_t)NP * KQ;  // float4 per slot
+    auto row_of = [&](int o) -> const float4 * {
+        const int li = s_slot[o * kTile + lane];
+        return sA4 + (li >= 0 ? li : ns) * KQ;
+    };
+    // this wave's used slots (every other one, ascending), operator columns in two register buffers
+    // (ping-pong): the column of the next slot loads while the current one runs
     uint64_t rest = mask;
-    int o = rest ? __builtin_ctzll(rest) : 0;
-    if (rest)
-        for (int e = tid; e < BSZ; e += 256) sB[0][e] = a.B[(int64_t)o * BSZ + e];
-    __syncthreads();
-    int buf = 0;
-    const int16_t *myslot = slot + wave * 16 + r;  // target row r of this wave's M tile
-    while (rest) {
-        rest &= rest - 1;
-        const int onext = rest ? __builtin_ctzll(rest) : -1;
-        float pre[BPER];
-        if (onext >= 0) {
-#pragma unroll
-            for (int q = 0; q < BPER; ++q) {
-                const int e = tid + 256 * q;
-                pre[q] = e < BSZ ? a.B[(int64_t)onext * BSZ + e] : 0.f;
-            }
+    int rc = 0;  // used slots passed so far
+    auto next = [&]() -> int {  // the next used slot of this half, or -1
+        while (rest) {
+            const int o = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            if ((rc++ & 1) == half) return o;
         }
-        const int li = myslot[o * kTile];
-        const float *arow = sA + (li >= 0 ? li : 0) * KP + kq;
-        const float *bcol = sB[buf] + kq * NP + r;
+        return -1;
+    };
+    float4 b0[KQ], b1[KQ];
+    int o0 = next();
+    if (o0 >= 0) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float av = li >= 0 ? arow[4 * ks] : 0.f;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bcol[4 * ks * NP + 16 * nt], acc[nt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc64[nt][i] += (double)acc[nt][i];
-            acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-        if (onext >= 0) {
-#pragma unroll
-            for (int q = 0; q < BPER; ++q) {
-                const int e = tid + 256 * q;
-                if (e < BSZ) sB[buf ^ 1][e] = pre[q];
-            }
-        }
-        __syncthreads();
-        buf ^= 1;
-        o = onext;
+        for (int q = 0; q < KQ; ++q) b0[q] = Bcol[o0 * kSlotQ + q];
     }
-    // lambda_n = -n! acc''_n (+ the log term for n = 0)
+    while (o0 >= 0) {
+        const int o1 = next();
+        if (o1 >= 0) {
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) b1[q] = Bcol[o1 * kSlotQ + q];
+        }
+        m2l32_slot<K, KQ>(row_of(o0), b0, acc);
+        if (o1 < 0) break;
+        o0 = next();
+        if (o0 >= 0) {
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) b0[q] = Bcol[o0 * kSlotQ + q];
+        }
+        m2l32_slot<K, KQ>(row_of(o1), b1, acc);
+    }
+    // the second half's sums join the first's through LDS (the source rows are no longer needed)
+    __syncthreads();
+    double *sred = (double *)sA4;
+    if (half == 1) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sred[(nt * 16 + e) * 64 + lane] = acc[e];
+    }
+    __syncthreads();
+    if (half == 1) return;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] += sred[(nt * 16 + e) * 64 + lane];
+    // lambda_n = -n! acc''_n (+ the log term for n = 0); element e: target 16 (e/4) + 4 (l/16) + e%4.
+    // Box indices and log terms come from LDS, so the stores do not wait on memory loads.
+    if (col >= K) return;
     const int64_t stride = (int64_t)P1 * a.nbox;
+    double *out = (double *)(Lam + (int64_t)n * a.nbox) + (im ? 1 : 0);
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int c = 16 * nt + r;
-        if (c >= 2 * P1) continue;
-        const bool im = c >= P1;
-        const int n = im ? c - P1 : c;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int t = wave * 16 + 4 * kq + i;
-            const int b = a.tiles[tile * kTile + t];
-            if (b < 0) continue;
-            double v = -a.fact[n] * acc64[nt][i];
-            if (n == 0) v += im ? s_acc0[t].im : s_acc0[t].re;
-            double *dst = (double *)(Lam + (int64_t)n * a.nbox + b) + (im ? 1 : 0);
-            *dst = v;
-            if (a.nloc == 2) *((double *)(Lam + stride + (int64_t)n * a.nbox + b) + (im ? 1 : 0)) = v;
+    for (int e = 0; e < 16; ++e) {
+        const int t = 16 * (e >> 2) + 4 * (lane >> 4) + (e & 3);
+        const int b = s_box[t];
+        double v = -fn * acc[e];
+        if (n == 0) v += im ? s_acc0[t].im : s_acc0[t].re;
+        if (b >= 0) {
+            out[2 * (int64_t)b] = v;
+            if (a.nloc == 2) out[2 * (stride + b)] = v;
         }
     }
 }
@@ -1794,8 +1882,8 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     // M2L tiles: up to kTile boxes of one level and one child class (bx & 1, by & 1), consecutive in
     // Morton order.  Boxes of one class have the same V offsets away from boundaries, so the lanes
     // of a tile walk the same offset slots.  A tile whose distinct upper V sources do not fit the
-    // LDS staging buffer is split in halves.  The FP32 matrix-core M2L stages all coefficients at
-    // once and takes consecutive boxes of all classes (fewer distinct sources per tile).
+    // LDS staging buffer is split in halves.  The FP32 matrix-core M2L builds its tiles the same way
+    // with a smaller source cap (it stages all coefficients of the sources at once, in FP32).
     // The tiles are built by host threads, each taking whole initial tiles (and their halves).
     std::vector<int32_t> tiles, tlev, tsoff(1, 0), tsrc;
     std::vector<int16_t> tslot;
@@ -1811,16 +1899,16 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         std::vector<int> init_lev(T.depth + 2, 0);         // first initial tile of each level
         for (int l = 2; l <= T.depth; ++l) {
             init_lev[l] = (int)init.size();
-            for (int cls = 0; cls < (S.m2l_fp32 ? 1 : 4); ++cls) {
+            for (int cls = 0; cls < 4; ++cls) {
                 const int g0 = (int)seq.size();
                 for (int b = T.lev_start[l]; b < T.lev_start[l + 1]; ++b)
-                    if (S.m2l_fp32 || ((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
+                    if (((bx[b] & 1) | ((by[b] & 1) << 1)) == cls) seq.push_back(b);
                 for (int a0 = g0; a0 < (int)seq.size(); a0 += kTile)
                     init.push_back({a0, std::min(a0 + kTile, (int)seq.size())});
             }
         }
         init_lev[T.depth + 1] = (int)init.size();
-        const int max_src = S.m2l_fp32 ? kM2LMaxSrc32 : kM2LMaxSrc;
+        const int max_src = kM2LMaxSrc;
         std::vector<TileOut> outs(init.size());
         // one range: its distinct sources; halves while they do not fit the LDS staging
         auto build_range = [&](auto &&self, int lo, int hi, std::vector<int32_t> &pos, std::vector<int32_t> &uniq,
@@ -2055,7 +2143,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         }
     FMMHP_CHECK(to_dev(A, &S.Tfree, Tfree, "Tfree", s));
     if (S.m2l_fp32) {
-        // FP32 matrix-core operators: B[o][k][c] of the 2x2 embedding of T''_{nm} = T_{n+m} / (n! m!)
+        // FP32 matrix-core operators: B[o][c][k] (column c, row k) of the 2x2 embedding of
+        // T''_{nm} = T_{n+m} / (n! m!); rows k = m (Re w''_m) and P1 + m (Im w''_m), columns c = n
+        // (Re acc''_n) and P1 + n (Im acc''_n), zero padding
         const int P1 = PB + 1, KP = m2l32_kp(PB), NP = m2l32_np(PB);
         std::vector<float> B((size_t)kNumSlots * KP * NP, 0.f);
         for (int o = 0; o < kNumSlots; ++o)
@@ -2065,10 +2155,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                     const double sc = ifact[n] * ifact[m];
                     const float tr = (float)(t.re * sc), ti = (float)(t.im * sc);
                     float *Bo = B.data() + (size_t)o * KP * NP;
-                    Bo[(size_t)m * NP + n] = tr;
-                    Bo[(size_t)m * NP + P1 + n] = ti;
-                    Bo[(size_t)(P1 + m) * NP + n] = -ti;
-                    Bo[(size_t)(P1 + m) * NP + P1 + n] = tr;
+                    Bo[(size_t)n * KP + m] = tr;
+                    Bo[(size_t)(P1 + n) * KP + m] = ti;
+                    Bo[(size_t)n * KP + P1 + m] = -ti;
+                    Bo[(size_t)(P1 + n) * KP + P1 + m] = tr;
                 }
         FMMHP_CHECK(to_dev(A, &S.Bf32, B, "FP32 M2L operators", s));
     }
@@ -2378,9 +2468,14 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
             constexpr int CH = m2l_chunk(PB);
             static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
             if (S.m2l_fp32) {
+                // FP32 rows of the sources (V sources are boxes of the same levels)
+                const int b0 = T.lev_start[l0], b1 = T.lev_start[l1];
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_w_f32<PB>), dim3(nblk(b1 - b0, 256), NV), dim3(256), 0, st, b0, b1,
+                                   nbox, S.fact, ws.W, ws.Wf);
                 M2L32Args ma{nbox,    t0,        S.tiles, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
-                             S.Bf32,  S.Lfree,   S.logside, S.fact,       ws.W,        ws.Lam,       S.nloc};
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(t1 - t0, NV), dim3(256), 0, st, ma);
+                             S.Bf32,  S.Lfree,   S.logside, S.fact,       ws.Wf,       ws.Lam,       S.nloc};
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(t1 - t0, NV), dim3(128 * (m2l32_np(PB) / 16)),
+                                   0, st, ma);
             } else {
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
                            S.tile_mask, S.Tfree, S.Lfree, S.logside,  ws.W,            ws.Lam,      S.nloc};
@@ -2544,6 +2639,7 @@ static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
     FMMHP_CHECK(A.alloc_n(&w.near, nv * (size_t)T.n, "near-field sums"));
     FMMHP_CHECK(A.alloc_n(&w.red, nv * (size_t)S.n_rch, "surface partial sums"));
     FMMHP_CHECK(A.alloc_n(&w.rank1, nv * (size_t)T.n_inst, "surface sums"));
+    if (S.m2l_fp32) FMMHP_CHECK(A.alloc_n(&w.Wf, nv * nb * (size_t)m2l32_kp(S.PB), "FP32 M2L source rows"));
     w.cap = nv;
     return FMMHP_OK;
 }
@@ -2605,11 +2701,12 @@ static fmmhp_status scratch_on(int dev, unsigned char **out) {
 // when base is given.
 static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char *base, VecWs *w) {
     const size_t nb = (size_t)T.nbox, P1 = (size_t)S.PB + 1;
-    const size_t sizes[6] = {nv * P1 * nb * sizeof(cplx), nv * (size_t)S.nloc * P1 * nb * sizeof(cplx),
+    const size_t sizes[7] = {nv * P1 * nb * sizeof(cplx), nv * (size_t)S.nloc * P1 * nb * sizeof(cplx),
                              nv * (size_t)T.n * sizeof(double), nv * (size_t)T.n * sizeof(double2),
-                             nv * (size_t)S.n_rch * sizeof(cplx), nv * (size_t)T.n_inst * sizeof(cplx)};
-    size_t off[6], at = 0;
-    for (int k = 0; k < 6; ++k) {
+                             nv * (size_t)S.n_rch * sizeof(cplx), nv * (size_t)T.n_inst * sizeof(cplx),
+                             S.m2l_fp32 ? nv * nb * (size_t)m2l32_kp(S.PB) * sizeof(float) : 0};
+    size_t off[7], at = 0;
+    for (int k = 0; k < 7; ++k) {
         off[k] = at;
         at += (sizes[k] + 255) / 256 * 256;
     }
@@ -2621,6 +2718,7 @@ static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char
         w->near = (double2 *)(base + off[3]);
         w->red = (cplx *)(base + off[4]);
         w->rank1 = (cplx *)(base + off[5]);
+        w->Wf = S.m2l_fp32 ? (float *)(base + off[6]) : nullptr;
     }
     return at;
 }

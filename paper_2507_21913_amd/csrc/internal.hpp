@@ -25,7 +25,6 @@ constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2
 constexpr int kM2LChunkMax = 8;   // at most this many output coefficients per M2L wave
 constexpr int kM2LPhase = 4;      // multipole coefficients staged in LDS per phase
 constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 4 * 400 * 16 B)
-constexpr int kM2LMaxSrc32 = 200; // the same for the FP32 matrix-core M2L (all coefficients staged)
 
 // Waves per M2L workgroup, each owning m2l_chunk(PB) consecutive output coefficients: the fewest
 // waves of at most kM2LChunkMax outputs, with the outputs spread evenly over them.
@@ -131,6 +130,7 @@ struct VecWs {
     double2 *near = nullptr;        // [nv][n] near-field sums
     cplx *red = nullptr;            // [nv][n_rch] surface partial sums
     cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
+    float *Wf = nullptr;            // [nv][nbox][KP] FP32 source rows of the matrix-core M2L
 };
 
 // Evaluation schedule and tables derived from the tree.
