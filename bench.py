@@ -27,12 +27,19 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X fp64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X fp32 matrix peak
 
 # HBM bytes of k_m2l per evaluation measured with rocprofv3 counter runs (2.00 x FETCH_SIZE + 1.00 x
 # WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
 # (p, leaf size): reported (per launch) only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
 M2L_TRAFFIC = {("218cec624acb0313", 20, 32): 164.8e6}
+
+
+def M2L_ALG_BYTES(info):
+    """Algorithmic HBM bytes of k_m2l per evaluation: every box's multipole read once and its local
+    written once (16 (p + 1) bytes each)."""
+    return 2.0 * 16.0 * (info["p"] + 1) * info["nbox"]
 
 
 def eval_source_hash() -> str:
@@ -67,18 +74,43 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """(logical CPUs of the host, CPUs this process may run on, CPU model)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    if not model:
+        import platform
+        model = platform.processor() or platform.machine()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return os.cpu_count() or 1, avail, model
+
+
 def cpu_baseline(w, k):
-    """Time the CPU oracle (plain float64 direct sum) on k sampled targets x all sources."""
+    """Time the CPU oracle (plain float64 direct sum) on k sampled targets x all sources, one worker
+    process per host core this process may use, at most 16 (the host-core share of one GPU on the
+    machines this runs on)."""
     import workloads
     from oracle import direct as D
+    nproc, avail, model = host_cpu()
+    workers = max(1, min(16, avail))
     idx = workloads.sample_targets(w.n, k, seed=777)
-    workers = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     D.potential(w.x, w.y, w.q[0], w.impedance, xt=w.x[idx], yt=w.y[idx], workers=workers)
     dt = time.perf_counter() - t0
     return {"value": k / dt / 1e6, "unit": "Mpts/s", "cores": workers, "kind": "oracle",
             "sample": f"{k} targets x {w.n} sources (direct sum, float64), {dt:.1f} s",
-            "extrapolated_full_s": dt * w.n / k}
+            "extrapolated_full_s": dt * w.n / k, "host_nproc": nproc, "host_cpus_available": avail,
+            "cpu_model": model}
 
 
 def example2_extra(dev, sizes=(4000, 1 << 16, 1 << 20), p=10, leaf=32, reps=10):
@@ -166,6 +198,74 @@ def curve_extra(dev, steps):
         got = out.cpu().numpy()[g[0]]
         res["rel_l2_vs_oracle_sample"] = float(np.linalg.norm(got - g[1]) / np.linalg.norm(g[1]))
     plan.close()
+    return res
+
+
+def fwd_bwd_extra(dev, p, leaf, shape, steps):
+    """The differentiation workload (N = 1,048,576 uniform in [0,1] x [0.01,1.01], charges U[-1,1],
+    impedance 2, loss l = Re sum_i conj(g_i) phi_i with g = w + i w', w, w' ~ N(0, 1)) on the plan the
+    benchmark times: the plain FP64 forward, and forward + fmmhp_backward_device (dl/dq, dl/dx, dl/dy
+    and dl/dZ, the impedance gradient left on the device) in one timed loop; gradients against the
+    oracle's stored direct-sum sample at 256 indices, dl/dZ against a central difference of the GPU
+    forward."""
+    import numpy as np
+    import torch
+
+    import paper_2507_21913_amd as F
+    import workloads
+    from golden_io import load_grad
+
+    w = workloads.diff_1m(seed=1)
+    g = w.extra["loss_w"] + 1j * w.extra["loss_w_im"]
+    x, y, q = (torch.as_tensor(v, device=dev) for v in (w.x, w.y, w.q[0]))
+    gg = torch.as_tensor(g, device=dev)
+    plan = F.HalfPlaneFMM(x, y, w.impedance, p=p, leaf_size=leaf, **shape)
+    out = torch.empty(w.n, dtype=torch.complex128, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_f = timed(lambda: plan(q, out=out))
+
+    def fb():
+        plan(q, out=out)
+        return plan.backward(q, gg, lambda_on_device=True)
+
+    ms_fb = timed(fb)
+    r = fb()
+    torch.cuda.synchronize()
+    res = {"workload": "diff_1m: N=1,048,576 uniform in [0,1]x[0.01,1.01], charges U[-1,1], impedance 2.0, "
+                       "g = w + i w' (standard normal)",
+           "p": plan.info()["p"], "leaf_size": leaf, "fwd_ms": ms_f, "ms_per_step": ms_fb,
+           "mpts_s": w.n / (ms_fb * 1e-3) / 1e6, "bwd_over_fwd": (ms_fb - ms_f) / ms_f,
+           "outputs": "phi; dl/dq, dl/dx, dl/dy, dl/dZ (on the device, no host synchronisation)"}
+    gr = load_grad("diff_1m")
+    if gr is not None:
+        idx, ref = gr
+        res["grad_rel_l2_vs_oracle_sample"] = {
+            k: float(np.linalg.norm(r[k].cpu().numpy()[idx] - ref[:, j]) / np.linalg.norm(ref[:, j]))
+            for j, k in enumerate(("q", "x", "y"))}
+    dlz = r["lambda"].cpu().numpy()[0, 0]
+    plan.close()
+    hz = 1e-5 * w.impedance
+    ls = []
+    for Zs in (w.impedance + hz, w.impedance - hz):
+        p2 = F.HalfPlaneFMM(x, y, Zs, p=p, leaf_size=leaf, **shape)
+        ls.append(float(torch.sum(torch.view_as_real(p2(q)) * torch.view_as_real(gg)).item()))
+        p2.close()
+    fd = (ls[0] - ls[1]) / (2 * hz)
+    res["dl_dReZ"] = float(dlz)
+    res["dl_dReZ_rel_vs_central_difference"] = float(abs(dlz - fd) / abs(fd))
     return res
 
 
@@ -287,7 +387,8 @@ def main():
         tuned = F.tune(x, y, q, w.impedance, tol=a.tol)
         tuned["tune_s"] = time.perf_counter() - t0
         p_use, leaf_use = tuned["p"], tuned["leaf_size"]
-        shape = {"near_walk": tuned["near_walk"], "near_groups": tuned["near_groups"]}
+        shape = {"near_walk": tuned["near_walk"], "near_groups": tuned["near_groups"],
+                 "m2l_fp32": tuned["m2l_fp32"]}
     else:
         if a.leaf == 0:
             leaf_use = 40
@@ -369,7 +470,11 @@ def main():
         roof = {"kernel": "k_m2l", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": None if traffic is None else traffic / per_eval,
+                "schedule": "concurrent: the launches share the GPU with the near field (the kernel alone: "
+                            "roofline_alone)",
                 "flops_per_launch": fl, "launches_per_eval": per_eval, "avg_launch_us": avg_ms * 1e3}
+        if traffic is not None:
+            roof["traffic_over_algorithmic"] = traffic / M2L_ALG_BYTES(info)
     else:
         # near field (k_near): 27 float64 flops per pair, counted from its compiled inner loop
         # (12 FMA incl. the table-assisted log, 2 add, 1 mul); image-source pairs counted alike
@@ -383,6 +488,7 @@ def main():
     # the same evaluation with every kernel on one stream: each k_m2l launch's duration is its own
     # (the concurrent schedule above shares the CUs with the near field)
     alone = None
+    roof_near = None
     if dom == "m2l":
         plan_s = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, serial=True, **shape)
         for _ in range(2):
@@ -396,8 +502,18 @@ def main():
         torch.cuda.synchronize()
         ms_s = e0.elapsed_time(e1) / a.steps
         m2l_ms_s, n_s = plan_s.m2l_kernel_times()
+        ph_s, nev_s = plan_s.phase_times()
         plan_s.set_timing(False)
         plan_s.close()
+        # the near field alone (its phase on the one stream: k_near, the reaction pairs and the surface
+        # sums), 27 flops per pair as in the dominant-kernel fallback below
+        near_ms = ph_s["near"] / max(1, nev_s)
+        near_fl = 27.0 * (info["p2p_pairs"][0] + info["p2p_pairs"][1])
+        roof_near = {"kernel": "k_near (+ k_near_reaction, surface sums)", "bound": "alu",
+                     "schedule": "every kernel on one stream (FMMHP_FLAG_SERIAL)",
+                     "achieved": near_fl / (near_ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": near_fl / (near_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                     "phase_us": near_ms * 1e3, "flops": near_fl, "pairs": info["p2p_pairs"]}
         if n_s > 0:
             per_eval_s = n_s / max(1, a.steps)
             avg_s = m2l_ms_s / n_s
@@ -429,12 +545,13 @@ def main():
     }
     if alone is not None:
         res["roofline_alone"] = alone
+        res["roofline_near_alone"] = roof_near
+    if tuned:
+        res["autotune"] = tuned
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, a.cpu_sample)
     if not a.quiet_extra:
         res["rel_l2_vs_oracle_sample"] = rel
-        if tuned:
-            res["autotune"] = tuned
         if not a.no_p30 and not (p_use == 30 and leaf_use == 40):
             plan30 = F.HalfPlaneFMM(x, y, w.impedance, p=30, leaf_size=40)
             for _ in range(2):
@@ -453,45 +570,45 @@ def main():
                                  "rel_l2_vs_oracle_sample": rel30}
             plan30.close()
         # the same evaluation with the upper-source M2L on the FP32 matrix cores
-        plan32 = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, m2l_fp32=True)
+        plan32 = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, m2l_fp32=True,
+                                **{k: v for k, v in shape.items() if k != "m2l_fp32"})
         for _ in range(2):
             plan32(q, out=out)
-        plan32.set_timing(True)
         torch.cuda.synchronize()
         e0.record()
-        for _ in range(10):
+        for _ in range(a.steps):
             plan32(q, out=out)
         e1.record()
         torch.cuda.synchronize()
-        ms32 = e0.elapsed_time(e1) / 10
+        ms32 = e0.elapsed_time(e1) / a.steps
+        plan32.set_timing(True)
+        for _ in range(5):
+            plan32(q, out=out)
         ph32, nev32 = plan32.phase_times()
         rel32 = None
         if g is not None:
             rel32 = float(np.linalg.norm(out.cpu().numpy()[g[0]] - g[1]) / np.linalg.norm(g[1]))
-        res["m2l_fp32"] = {"mpts_s": w.n / (ms32 * 1e-3) / 1e6, "ms_per_step": ms32,
-                           "m2l_ms": ph32["m2l"] / max(1, nev32), "rel_l2_vs_oracle_sample": rel32}
         plan32.close()
-        # forward + adjoint (dl/dq, dl/dx, dl/dy, dl/dZ) for one incoming gradient, same plan
-        rng = np.random.default_rng(7)
-        gg = torch.as_tensor(rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n), device=dev)
+        # the matrix-core M2L alone (serial plan): its launches' time against the FP32 matrix peak
+        plan32s = F.HalfPlaneFMM(x, y, w.impedance, p=p_use, leaf_size=leaf_use, m2l_fp32=True, serial=True)
         for _ in range(2):
-            plan.backward(q, gg, want_lambda=False)
+            plan32s(q, out=out)
+        plan32s.set_timing(True)
+        for _ in range(10):
+            plan32s(q, out=out)
         torch.cuda.synchronize()
+        k32_ms, k32_n = plan32s.m2l_kernel_times()
+        plan32s.close()
+        k32_eval_ms = k32_ms / 10.0
+        res["m2l_fp32"] = {"mpts_s": w.n / (ms32 * 1e-3) / 1e6, "ms_per_step": ms32, "over_fp64": ms / ms32,
+                           "m2l_phase_ms": ph32["m2l"] / max(1, nev32), "rel_l2_vs_oracle_sample": rel32,
+                           "kernel_alone_us_per_eval": k32_eval_ms * 1e3,
+                           "kernel_alone_frac_fp32_matrix_peak": m2l_flops / (k32_eval_ms * 1e-3) / 1e12
+                           / PEAK_FP32_MATRIX_TFLOPS,
+                           "kernel_alone_note": "algorithmic flops 8 (p+1)^2 per upper V pair over the summed "
+                                                "duration of the FP32 row conversion and matrix-core M2L launches"}
         nb = max(1, a.steps // 4)
-        e0.record()
-        for _ in range(nb):
-            plan(q, out=out)
-            plan.backward(q, gg, want_lambda=False)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_fb = e0.elapsed_time(e1) / nb
-        t0 = time.perf_counter()
-        plan.backward(q, gg)
-        bwd_lambda_ms = (time.perf_counter() - t0) * 1e3
-        res["fwd_bwd"] = {"mpts_s": w.n / (ms_fb * 1e-3) / 1e6, "ms_per_step": ms_fb,
-                          "bwd_over_fwd": (ms_fb - ms) / ms,
-                          "outputs": "phi; dl/dq, dl/dx, dl/dy",
-                          "bwd_with_dl_dZ_wall_ms": bwd_lambda_ms}
+        res["fwd_bwd"] = fwd_bwd_extra(dev, p_use, leaf_use, shape, max(2, a.steps // 2))
         # the double-layer potential of the same densities with seeded unit normals, same plan
         nxh, nyh = workloads.source_normals(w.n, seed=7)
         nxd, nyd = (torch.as_tensor(v, device=dev) for v in (nxh, nyh))

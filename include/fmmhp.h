@@ -332,6 +332,14 @@ fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *gr
                             double *grad_q, double *grad_x, double *grad_y,
                             double *grad_lambda, hipStream_t stream);
 
+/* fmmhp_backward with the impedance gradient left on the device, for training loops that must not
+ * synchronise the host: identical gradients, and grad_lambda is a [device] output [n_inst][2]
+ * (dl/dRe Z_k, dl/dIm Z_k), written by a kernel on stream; the call never synchronises.  (The
+ * reduction of eq. (reactdecomposition)'s homogeneity sums runs on the device either way; only
+ * the place the result lands differs.)  Errors as for fmmhp_backward. */
+fmmhp_status fmmhp_backward_device(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
+                                   double *grad_x, double *grad_y, double *grad_lambda, hipStream_t stream);
+
 /* Plan statistics (sizes, root square, order in use).  stats: [host]. */
 fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *stats);
 
@@ -369,7 +377,8 @@ fmmhp_status fmmhp_plan_phase_times(fmmhp_plan_t plan, double *ms, int64_t *n_ev
  * device milliseconds of its launches, each bracketed by HIP events on the stream it runs on (it
  * runs as up to two launches per charge-vector pass: the deepest levels on a second stream, the
  * coarse levels on the eval stream, concurrently with the near field), n_launches = their number.
- * Waits for the recorded events.  ms: [host] one double; n_launches: [host], may be NULL. */
+ * With FMMHP_FLAG_M2L_FP32 each bracket covers the FP32 source-row conversion and the matrix-core
+ * M2L of those levels.  Waits for the recorded events.  ms: [host] one double; n_launches: [host], may be NULL. */
 fmmhp_status fmmhp_plan_m2l_kernel_times(fmmhp_plan_t plan, double *ms, int64_t *n_launches);
 
 /* Release the plan and its device memory.  Synchronises the device.  plan may be NULL (no-op). */
@@ -413,8 +422,10 @@ fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *
  *   sample       targets in the accuracy sample, 1..n (0 selects min(n, 256))
  *   best         [host] receives the chosen options (p, leaf_size, and the launch shape
  *                near_walk, near_groups timed on the chosen plan, four shapes in turn over three
- *                rounds; a shape other than the default needs to be more than 2% faster;
- *                max_level 0, flags 0)
+ *                rounds; a shape other than the default needs to be more than 2% faster; then
+ *                the M2L form: flags gets FMMHP_FLAG_M2L_FP32 when the FP32 matrix-core M2L on that
+ *                plan and shape still meets tol against the direct sum and is more than 2%
+ *                faster; max_level 0)
  *   err, eval_ms [host, may be NULL] the chosen pair's measured error and median eval time
  * Returns FMMHP_EUNSUPPORTED if no candidate reaches tol at p = 40.  Synchronises the stream;
  * allocates and frees its own temporaries. */

@@ -84,6 +84,7 @@ _SIGNATURES = {
     "fmmhp_eval_noalloc": [_P, _INT, _P, _P, _P],
     "fmmhp_eval_complex": [_P, _INT, _P, _P, _P],
     "fmmhp_backward": [_P, _P, _P, _P, _P, _P, _P, _P],
+    "fmmhp_backward_device": [_P, _P, _P, _P, _P, _P, _P, _P],
     "fmmhp_eval_field": [_P, _P, _P, _P, _P, _P],
     "fmmhp_eval_double_layer": [_P, _INT, _P, _INT, _P, _P, _P, _P],
     "fmmhp_eval_normal_derivative": [_P, _P, _P, _P, _P, _P],
@@ -276,19 +277,89 @@ def fmmhp_tune(n, x_ptr, y_ptr, q_ptr, lambda_re, lambda_im, tol, n_vec, leaf_si
                                           la, nl, sample, ctypes.byref(best), ctypes.byref(err),
                                           ctypes.byref(ms), stream))
     return {"p": best.p, "leaf_size": best.leaf_size, "near_walk": best.near_walk,
-            "near_groups": best.near_groups, "rel_l2": err.value, "eval_ms": ms.value}
+            "near_groups": best.near_groups, "m2l_fp32": bool(best.flags & FLAG_M2L_FP32),
+            "rel_l2": err.value, "eval_ms": ms.value}
 
 
-def tune(x, y, q, impedance, tol=1e-10, n_vec=1, leaf_sizes=None, sample=0) -> dict:
-    """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error, and the
-    near-field launch shape (near_walk, near_groups) by timing the chosen plan."""
+# --- autotuner cache --------------------------------------------------------------------------
+# The tuner's choices persist in a JSON file keyed by the GPU, the point count (power-of-two bucket),
+# the impedance class, the tolerance, the number of vectors and a hash of the library sources, so a
+# second run on the same kind of problem skips the search.  Default file: tune_cache.json beside
+# this module; FMMHP_TUNE_CACHE names another (an empty value disables the cache).
+TUNE_CACHE_PATH = os.path.join(_HERE, "tune_cache.json")
+
+
+def _source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(_HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def tune_cache_key(n, impedance, tol, n_vec, device=None) -> str:
+    import math
+    z = complex(impedance)
+    name = torch.cuda.get_device_name(device)
+    nb = int(round(math.log2(max(1, int(n)))))
+    zc = f"{'complex' if z.imag != 0 else 'real'}:1e{int(math.floor(math.log10(abs(z)) * 2)) / 2:g}"
+    return f"{name}|n~2^{nb}|Z {zc}|tol {tol:g}|nvec {int(n_vec)}|src {_source_hash()}"
+
+
+def _cache_path():
+    p = os.environ.get("FMMHP_TUNE_CACHE")
+    if p is None:
+        return TUNE_CACHE_PATH
+    return p or None
+
+
+def _cache_load(path) -> dict:
+    import json
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _cache_store(path, key, value):
+    import json
+    d = _cache_load(path)
+    d[key] = value
+    tmp = f"{path}.{os.getpid()}.tmp"
+    try:
+        with open(tmp, "w") as fh:
+            json.dump(d, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def tune(x, y, q, impedance, tol=1e-10, n_vec=1, leaf_sizes=None, sample=0, use_cache=True) -> dict:
+    """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error, the near-field
+    launch shape (near_walk, near_groups) and the M2L form (m2l_fp32) by timing the chosen plan.
+    With use_cache the choice is read from (and written to) the tuner's JSON cache; "cached" in the
+    result says which."""
     x = _dev_f64(x, "x")
     y = _dev_f64(y, "y")
     q = _dev_f64(q, "q")
     lr, li = _split_impedance(impedance)
+    path = _cache_path() if use_cache and not leaf_sizes and not sample else None
+    key = tune_cache_key(x.shape[0], complex(lr, li), tol, n_vec, x.device) if path else None
+    if path:
+        hit = _cache_load(path).get(key)
+        if hit is not None:
+            return dict(hit, cached=True, cache_key=key)
     with torch.cuda.device(x.device):
-        return fmmhp_tune(x.shape[0], x.data_ptr(), y.data_ptr(), q.data_ptr(), lr, li, tol, n_vec,
-                          leaf_sizes, sample, _stream())
+        r = fmmhp_tune(x.shape[0], x.data_ptr(), y.data_ptr(), q.data_ptr(), lr, li, tol, n_vec,
+                       leaf_sizes, sample, _stream())
+    if path:
+        _cache_store(path, key, r)
+    return dict(r, cached=False, cache_key=key)
 
 
 # --- tensor-level helpers --------------------------------------------------------------------
@@ -514,9 +585,11 @@ class HalfPlaneFMM:
         return phi[0] if squeeze else phi
 
     def backward(self, q: torch.Tensor, grad_phi: torch.Tensor, want_q=True, want_x=True,
-                 want_y=True, want_lambda=True) -> dict:
+                 want_y=True, want_lambda=True, lambda_on_device=False) -> dict:
         """Gradients of a real loss l given g = dl/dRe phi + i dl/dIm phi (complex [N]) for real
-        charges q [N]: {"q", "x", "y": float64 [N], "lambda": complex dl/dRe Z + i dl/dIm Z}."""
+        charges q [N]: {"q", "x", "y": float64 [N], "lambda": complex dl/dRe Z + i dl/dIm Z}.
+        With lambda_on_device the impedance gradient stays on the GPU (fmmhp_backward_device, no
+        host synchronisation): "lambda" is then a float64 tensor [n_inst, 2] of (dl/dRe Z, dl/dIm Z)."""
         if not isinstance(q, torch.Tensor) or not q.is_cuda or q.is_complex():
             raise TypeError("q must be a real GPU tensor")
         if q.numel() != self.n or grad_phi.numel() != self.n:
@@ -531,6 +604,14 @@ class HalfPlaneFMM:
                 ptr[k] = out[k].data_ptr()
             else:
                 ptr[k] = None
+        if want_lambda and lambda_on_device:
+            dl = torch.empty((self.n_inst, 2), dtype=torch.float64, device=self.device)
+            with torch.cuda.device(self.device):
+                _check("fmmhp_backward_device",
+                       lib().fmmhp_backward_device(self._plan, qd.data_ptr(), gr.data_ptr(), ptr["q"], ptr["x"],
+                                                   ptr["y"], dl.data_ptr(), _stream()))
+            out["lambda"] = dl
+            return out
         with torch.cuda.device(self.device):
             gl = fmmhp_backward(self._plan, qd.data_ptr(), gr.data_ptr(), ptr["q"], ptr["x"],
                                 ptr["y"], bool(want_lambda), _stream(), self.n_inst)

@@ -454,7 +454,7 @@ fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *gr
     // Dirichlet and Neumann kernels do not depend on an impedance: its gradient is zero
     const bool want_z = grad_lambda && plan->sched.bc == 0;
     FMMHP_CHECK(run_backward(plan->arena, plan->tree, plan->sched, q, grad_phi, grad_q, grad_x, grad_y,
-                             want_z ? zsum.data() : nullptr, stream));
+                             want_z ? zsum.data() : nullptr, nullptr, stream));
     if (grad_lambda) {
         // per instance: dl_c/dZ_k = zsum_k / Z_k;  (dl/dRe Z_k, dl/dIm Z_k) = (Re, -Im) of it
         for (int k = 0; k < plan->tree.n_inst; ++k) {
@@ -464,6 +464,26 @@ fmmhp_status fmmhp_backward(fmmhp_plan_t plan, const double *q, const double *gr
         }
     }
     return FMMHP_OK;
+}
+
+fmmhp_status fmmhp_backward_device(fmmhp_plan_t plan, const double *q, const double *grad_phi, double *grad_q,
+                                   double *grad_x, double *grad_y, double *grad_lambda, hipStream_t stream) {
+    FMMHP_CHECK(check_plan(plan));
+    if (!q || !grad_phi) {
+        set_error("q and grad_phi must be non-NULL");
+        return FMMHP_EINVAL;
+    }
+    if (plan->n_src > 0) {
+        set_error("fmmhp_backward_device is not available for plans with separate targets");
+        return FMMHP_EUNSUPPORTED;
+    }
+    if (grad_lambda && plan->sched.bc != 0) {
+        // Dirichlet and Neumann kernels do not depend on an impedance: its gradient is zero
+        FMMHP_CHECK(zero_f64(grad_lambda, 2 * (int64_t)plan->tree.n_inst, stream));
+        grad_lambda = nullptr;
+    }
+    return run_backward(plan->arena, plan->tree, plan->sched, q, grad_phi, grad_q, grad_x, grad_y, nullptr,
+                        grad_lambda, stream);
 }
 
 fmmhp_status fmmhp_plan_info(fmmhp_plan_t plan, fmmhp_plan_stats *st) {

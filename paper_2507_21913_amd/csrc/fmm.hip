@@ -2467,19 +2467,22 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
         if (t1 > t0) {
             constexpr int CH = m2l_chunk(PB);
             static_assert(m2l_waves(PB) * CH >= PB + 1, "M2L waves must cover all output coefficients");
+            const int which = deep ? 0 : 1;
             if (S.m2l_fp32) {
-                // FP32 rows of the sources (V sources are boxes of the same levels)
+                // FP32 rows of the sources (V sources are boxes of the same levels); the event pair
+                // brackets the conversion and the matrix-core M2L together
                 const int b0 = T.lev_start[l0], b1 = T.lev_start[l1];
+                FMMHP_CHECK(mk_.km_mark(which, 0, st));
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_w_f32<PB>), dim3(nblk(b1 - b0, 256), NV), dim3(256), 0, st, b0, b1,
                                    nbox, S.fact, ws.W, ws.Wf);
                 M2L32Args ma{nbox,    t0,        S.tiles, S.tile_src_off, S.tile_src, S.tile_slot, S.tile_mask,
                              S.Bf32,  S.Lfree,   S.logside, S.fact,       ws.Wf,       ws.Lam,       S.nloc};
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_f32<PB>), dim3(t1 - t0, NV), dim3(128 * (m2l32_np(PB) / 16)),
                                    0, st, ma);
+                FMMHP_CHECK(mk_.km_mark(which, 1, st));
             } else {
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
                            S.tile_mask, S.Tfree, S.Lfree, S.logside,  ws.W,            ws.Lam,      S.nloc};
-                const int which = deep ? 0 : 1;
                 FMMHP_CHECK(mk_.km_mark(which, 0, st));
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)), 0,
                                    st, ma);
@@ -2947,12 +2950,35 @@ static fmmhp_status ensure_bwd(Arena &A, const Tree &T, Sched &S) {
     return FMMHP_OK;
 }
 
+__global__ void k_zero_f64(double *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// Clears n doubles with a kernel (safe under graph capture, unlike a memset node).
+fmmhp_status zero_f64(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return FMMHP_OK;
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
+    FMMHP_HIP(hipGetLastError());
+    return FMMHP_OK;
+}
+
+// (dl/dRe Z_k, dl/dIm Z_k) = (Re, -Im) of zsum_k / Z_k per instance (the homogeneity sums of the adjoint)
+__global__ void k_dl_dz(const cplx *__restrict__ zsum, const InstInfo *__restrict__ ii, int n_inst,
+                        double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const cplx d = zsum[k] * inv(ii[k].Z);
+    out[2 * k] = d.re;
+    out[2 * k + 1] = -d.im;
+}
+
 fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
-                          double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t s) {
+                          double *grad_x, double *grad_y, cplx *zsum_host, double *dlz_dev, hipStream_t s) {
     FMMHP_CHECK(ensure_bwd(A, T, S));
     FMMHP_CHECK(ensure_vec_ws(A, T, S, 3));  // multipoles, locals, sums for the three vectors
     BwdWork &b = S.bw;
-    const bool pos = grad_x || grad_y || zsum_host;
+    const bool pos = grad_x || grad_y || zsum_host || dlz_dev;
     if (!pos && !grad_q) return FMMHP_OK;
     const int64_t n = T.n;
     hipLaunchKernelGGL(k_stack3, dim3(nblk(n, 256)), dim3(256), 0, s, q, g, n, b.q3);
@@ -2979,10 +3005,17 @@ fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, co
                pos ? 1 : 0};
     hipLaunchKernelGGL(k_bwd_combine, dim3(S.n_rch), dim3(256), 0, s, ba);
     FMMHP_HIP(hipGetLastError());
-    if (zsum_host) {
+    if (zsum_host || dlz_dev) {
         hipLaunchKernelGGL(k_rank1_final, dim3(T.n_inst, 1), dim3(256), 0, s, b.red, S.n_rch, S.inst_ch, T.n_inst,
                            b.red + S.n_rch);
         FMMHP_HIP(hipGetLastError());
+    }
+    if (dlz_dev) {
+        hipLaunchKernelGGL(k_dl_dz, dim3(nblk(T.n_inst, 256)), dim3(256), 0, s, b.red + S.n_rch, S.inst_info,
+                           T.n_inst, dlz_dev);
+        FMMHP_HIP(hipGetLastError());
+    }
+    if (zsum_host) {
         FMMHP_HIP(hipMemcpyAsync(zsum_host, b.red + S.n_rch, T.n_inst * sizeof(cplx), hipMemcpyDeviceToHost, s));
         FMMHP_HIP(hipStreamSynchronize(s));
     }

@@ -246,8 +246,13 @@ fmmhp_status run_eval_complex(Arena &A, const Tree &T, Sched &S, int nvec, const
 
 fmmhp_status run_field(Arena &A, const Tree &T, Sched &S, const double *q, double *phi, cplx *gx, cplx *gy,
                        hipStream_t stream);
+// Clears n doubles on stream with a kernel (no memset node under graph capture).
+fmmhp_status zero_f64(double *p, int64_t n, hipStream_t stream);
+
+// zsum_host: per-instance homogeneity sums copied to the host (the call synchronises), or null;
+// dlz_dev: (dl/dRe Z_k, dl/dIm Z_k) written on the device instead (no synchronisation), or null.
 fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, const double *g, double *grad_q,
-                          double *grad_x, double *grad_y, cplx *zsum_host, hipStream_t stream);
+                          double *grad_x, double *grad_y, cplx *zsum_host, double *dlz_dev, hipStream_t stream);
 
 fmmhp_status collect_phase_times(Sched &S);
 fmmhp_status run_direct(int64_t ns, const double *sx, const double *sy, int nvec, const double *q,

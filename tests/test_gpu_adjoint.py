@@ -210,3 +210,32 @@ def test_backward_diff_1m_vs_oracle_sample():
     ez = abs(r["lambda"].real - fd) / abs(fd)
     print(f"diff_1m dl/dRe Z {r['lambda'].real:.12e} vs central difference {fd:.12e}: rel {ez:.2e}", flush=True)
     assert ez < 1e-7
+
+
+def test_backward_device_equals_backward():
+    """fmmhp_backward_device: the same gradients as fmmhp_backward (bitwise for q, x, y; dl/dZ to
+    rounding), the impedance gradient written on the device per instance, for a plain plan and a
+    forest."""
+    x, y, q, g = _uniform(3000, 71)
+    for Z in (1.5, 1.0 + 0.5j):
+        plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=20, leaf_size=32)
+        a = plan.backward(_t(q), _t(g))
+        b = plan.backward(_t(q), _t(g), lambda_on_device=True)
+        plan.close()
+        for k in ("q", "x", "y"):
+            assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()), k
+        dl = b["lambda"].cpu().numpy()
+        assert dl.shape == (1, 2)
+        # the same sums; Z_k's reciprocal and the product are rounded on the device instead of the host
+        assert np.allclose(dl[0], [a["lambda"].real, a["lambda"].imag], rtol=1e-14, atol=0)
+    sizes = [1200, 800, 1500]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    xs, ys, qs, gs = (np.concatenate(v) for v in zip(*[_uniform(m, 80 + k) for k, m in enumerate(sizes)]))
+    imps = [0.5, 2.0, 1.0 + 0.3j]
+    plan = F.HalfPlaneFMM.batched(_t(xs), _t(ys), off, imps, p=20, leaf_size=24)
+    a = plan.backward(_t(qs), _t(gs))
+    b = plan.backward(_t(qs), _t(gs), lambda_on_device=True)
+    plan.close()
+    dl = b["lambda"].cpu().numpy()
+    for k in range(3):
+        assert np.allclose(dl[k], [a["lambda"][k].real, a["lambda"][k].imag], rtol=1e-14, atol=0), k

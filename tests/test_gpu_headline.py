@@ -3,8 +3,9 @@
 * the uniform 1,048,576-point workload at the plan the benchmark runs (p = 20, leaf 32, prefetching
   near walk on two workgroups per CU): rel-l2 <= 1e-10 against the oracle's stored direct-sum
   sample, and the exact imaginary part at every target;
-* the autotuner: the plan it returns for tolerances 1e-8 and 1e-10 meets that tolerance against
-  the oracle's stored sample (not only against its own GPU direct-sum estimate);
+* the autotuner: the plan it returns for tolerances 1e-8 and 1e-10 (p, leaf size, near-field shape
+  and M2L form) meets that tolerance against the oracle's stored sample (not only against its own
+  GPU direct-sum estimate), and its JSON cache returns the same choice on a second call;
 * the full batched workload (512 instances, 18.3 M points, 64 charge vectors, one forest plan with
   a recorded graph): every stored oracle sample (4 instances x 2 vectors x 32 targets) within 1e-10
   for the FP64 path and 1e-6 for the FP32 matrix-core M2L.
@@ -58,17 +59,29 @@ def test_uniform_1m_bench_plan_vs_oracle(uniform):
 @pytest.mark.parametrize("tol", [1e-8, 1e-10])
 def test_tuned_plan_meets_tolerance_vs_oracle(uniform, tol):
     w, x, y, q = uniform
-    r = F.tune(x, y, q, 1.0, tol=tol)
+    r = F.tune(x, y, q, 1.0, tol=tol, use_cache=False)
     print(f"tune tol={tol:g}: {r}", flush=True)
-    assert r["rel_l2"] <= tol
+    assert r["rel_l2"] <= tol and not r["cached"]
     plan = F.HalfPlaneFMM(x, y, 1.0, p=r["p"], leaf_size=r["leaf_size"], near_walk=r["near_walk"],
-                          near_groups=r["near_groups"])
+                          near_groups=r["near_groups"], m2l_fp32=r["m2l_fp32"])
     phi = plan(q).cpu().numpy()
     plan.close()
     idx, ref = load("uniform_1m")
     err = D.rel_l2(phi[idx], ref)
     print(f"tuned plan (p={r['p']}, leaf={r['leaf_size']}): rel-l2 vs oracle sample {err:.3e}", flush=True)
     assert err <= tol
+
+
+def test_tune_cache_roundtrip(uniform, tmp_path, monkeypatch):
+    w, x, y, q = uniform
+    monkeypatch.setenv("FMMHP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    a = F.tune(x, y, q, 1.0, tol=1e-6)
+    b = F.tune(x, y, q, 1.0, tol=1e-6)
+    assert not a["cached"] and b["cached"] and a["cache_key"] == b["cache_key"]
+    for k in ("p", "leaf_size", "near_walk", "near_groups", "m2l_fp32", "rel_l2"):
+        assert a[k] == b[k], k
+    c = F.tune(x, y, q, 1.0 + 0.5j, tol=1e-6, use_cache=True)  # another impedance class: a new entry
+    assert not c["cached"] and c["cache_key"] != a["cache_key"]
 
 
 @pytest.fixture(scope="module")
