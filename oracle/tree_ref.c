@@ -330,8 +330,9 @@ TreeRef *tree_ref_build(int64_t n, const double *x, const double *y, int leaf_si
             if (visit(&q, &up) || visit(&q, &dn)) goto fail_lists;
         }
         for (int j = 0; j < 4; ++j) {
-            qsort(lists[j].v + before[j], (size_t)(lists[j].n - before[j]), sizeof(int32_t),
-                  cmp_i32);
+            if (lists[j].n > before[j]) /* a list may still be empty (NULL storage) */
+                qsort(lists[j].v + before[j], (size_t)(lists[j].n - before[j]), sizeof(int32_t),
+                      cmp_i32);
             t->off[j][k + 1] = lists[j].n;
         }
     }
