@@ -71,7 +71,9 @@ typedef struct {
      * a bounded grid.  Neither changes what is computed beyond rounding; fmmhp_tune picks both by
      * timing.  0 selects the default for the plan's p. */
     int near_walk;   /* 0: default; 1: source points loaded one step ahead of their use (hides
-                        memory latency, more instructions per pair); 2: plain walk */
+                        memory latency, more instructions per pair); 2: plain walk; 3: symmetric
+                        leaf pairs (potential evaluations: each pair of leaves once, its column
+                        sums gathered by a second kernel; other passes use walk 1) */
     int near_groups; /* 0: default; 1..16: near-field workgroups per compute unit */
 } fmmhp_opts;
 

@@ -91,11 +91,11 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
         (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32 | FMMHP_FLAG_DIRICHLET | FMMHP_FLAG_NEUMANN |
                      FMMHP_FLAG_SERIAL)) != 0 ||
-        (o.flags & FMMHP_FLAG_DIRICHLET && o.flags & FMMHP_FLAG_NEUMANN) || o.near_walk < 0 || o.near_walk > 2 ||
+        (o.flags & FMMHP_FLAG_DIRICHLET && o.flags & FMMHP_FLAG_NEUMANN) || o.near_walk < 0 || o.near_walk > 3 ||
         o.near_groups < 0 || o.near_groups > 16) {
         set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0..3, "
                   "not both 2 and 3), "
-                  "near_walk=%d (0..2), near_groups=%d (0..16)",
+                  "near_walk=%d (0..3), near_groups=%d (0..16)",
                   o.p, FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags, o.near_walk, o.near_groups);
         return FMMHP_EINVAL;
     }

@@ -1249,6 +1249,195 @@ __global__ __launch_bounds__(256) void k_near(LeafArgs a) {
     }
 }
 
+// Near field, log terms, symmetric leaf-pair walk (near_walk 3; potential only).  The log kernel of
+// a pair is symmetric in its two points, for the free-space term log|r - r'| and for the image term
+// log|r - conj r'| = log|r' - conj r| alike, and the U lists are symmetric (B, or its mirror image, is
+// listed for leaf A exactly when A, or its mirror image, is listed for B).  So each cross pair of
+// leaves (A, B), B > A, is evaluated once, by the wave of A (a leaf of more than 64 points is split
+// into records of 64 targets, each with partial slots of its own): lane (i, g) holds target i and
+// takes every G-th point of B; the row sums (B's charges) accumulate in the lanes, the column sums
+// (A's charges, for B's targets) are reduced over the lanes of a group by DPP lane moves and written
+// to a partial-sum slot of the pair.  The self pair (A, A) and the self-image pair (A, A_img) give row sums only.  A
+// second kernel adds the partials to B's targets in a fixed order (pairs in ascending A), so the
+// result is reproducible.
+struct SymArgs {
+    int nrec;
+    const int4 *rec;          // [nrec] (first target point, targets (<= 64), first job, end of jobs)
+    const int4 *jobs;         // (first point of B, count | image << 31, partial offset or -1, 0)
+    const double2 *xy;
+    const double *qs;         // [n][NV]
+    const double2 *logtab;
+    double isg;               // sign of the image log term
+    double *part;             // [partial entries][NV]
+    double2 *near;            // [NV][n]
+    int64_t n;
+};
+
+// Lane moves within a wave by DPP (no LDS traffic, a few cycles), for doubles as two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of TP lanes (TP = 8, 16, 32, 64).  Lanes [8k, 8k + 8) and rows of 16 are
+// reduced by quad swaps (xor 1, xor 2), the half-row mirror and the row mirror, after which every
+// lane of a row holds its sum; for TP = 32 row 2k + 1 adds row 2k's sum (row broadcast of lane 15),
+// for TP = 64 row 3 adds lane 31's (row broadcast of lane 31).  The group's sum is complete in
+// lane sum_lane(TP) of the group (and, for TP <= 16, in all of its lanes).
+__device__ __forceinline__ int sum_lane(int TP) { return TP == 64 ? 48 : TP == 32 ? 16 : 0; }
+__device__ __forceinline__ double group_sum(double s, int TP) {
+    s += dpp_move<0xB1, 0xF>(s);   // quad_perm [1, 0, 3, 2]
+    s += dpp_move<0x4E, 0xF>(s);   // quad_perm [2, 3, 0, 1]
+    s += dpp_move<0x141, 0xF>(s);  // row_half_mirror
+    if (TP >= 16) s += dpp_move<0x140, 0xF>(s);  // row_mirror
+    if (TP >= 32) s += dpp_move<0x142, 0xA>(s);  // row_bcast:15 into rows 1 and 3
+    if (TP >= 64) s += dpp_move<0x143, 0x8>(s);  // row_bcast:31 into row 3
+    return s;
+}
+
+// One wave per record (a leaf, or 64 of its targets).  Within a record, the jobs' source steps form
+// one stream: the next step's source point (across job boundaries) and the job after the next are
+// loaded ahead of the current step's arithmetic.
+template <int NV>
+__global__ __launch_bounds__(256) void k_near_sym(SymArgs a) {
+    __shared__ double2 s_logtab[kLogTable];
+    for (int k = threadIdx.x; k < kLogTable; k += blockDim.x) s_logtab[k] = a.logtab[k];
+    __syncthreads();
+    const double2 *__restrict__ tab = s_logtab;
+    const double2 *__restrict__ xy = a.xy;
+    const double *__restrict__ qs = a.qs;
+    const int4 *__restrict__ jobs = a.jobs;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const XcdChunks ch = xcd_chunks((a.nrec + 3) / 4);  // four records (one per wave) per chunk
+    for (int64_t c = ch.c0; c < ch.c1; c += ch.step) {
+        const int ri = (int)(c * 4 + wave);
+        if (ri >= a.nrec) continue;
+        const int4 rc = a.rec[ri];
+        const int ft = rc.x, nt = rc.y, e0 = rc.z, e1 = rc.w;
+        // lanes per target group: the targets rounded up to a power of two
+        const int TP = nt <= 8 ? 8 : nt <= 16 ? 16 : nt <= 32 ? 32 : 64;
+        const int G = 64 / TP;
+        const int i = lane & (TP - 1), g = lane / TP;
+        const bool act = i < nt;
+        const int wl = sum_lane(TP);  // the lane of a group that holds its column sums
+        const int64_t pi = ft + (act ? i : 0);
+        const double2 P = xy[pi];
+        double qi[NV], R[NV], ea[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qi[v] = act ? qs[pi * NV + v] : 0.0;
+            R[v] = ea[v] = 0.0;
+        }
+        int e = e0;
+        int4 jb = jobs[e];
+        int4 jn = e + 1 < e1 ? jobs[e + 1] : jb;
+        int jj = 0;
+        int bcount = jb.y & 0x7fffffff;
+        int j = g;
+        bool vj = j < bcount;
+        double2 Q = xy[jb.x + (vj ? j : 0)];
+        double qj[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qj[v] = vj ? qs[(int64_t)(jb.x + j) * NV + v] : 0.0;
+        while (true) {
+            // the next step: the same job's next G sources, or the next job's first ones
+            int njj = jj + G, ne = e;
+            int4 nb = jb;
+            const bool switch_job = njj >= bcount;
+            if (switch_job) {
+                ne = e + 1;
+                njj = 0;
+                nb = jn;
+            }
+            const bool more = ne < e1;
+            const int ncount = nb.y & 0x7fffffff;
+            const int jnx = njj + g;
+            const bool vn = more && jnx < ncount;
+            const int64_t pn = nb.x + (vn ? jnx : 0);
+            const double2 Qn = xy[pn];
+            double qn[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qn[v] = vn ? qs[pn * NV + v] : 0.0;
+            // this step
+            const double ysg = jb.y < 0 ? 1.0 : -1.0;   // image: y + y', free: y - y'
+            const double dx = P.x - Q.x, dy = fma(ysg, Q.y, P.y);
+            const double r2 = fma(dx, dx, dy * dy);
+            // r2 = 0 only for a coincident free pair, skipped (eq. (1.2)), or between two target-only
+            // points on y = 0 (no charge)
+            const double lg = log_tab(r2, tab);
+            const double K = r2 > 0.0 ? lg : 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ea[v] = fma(qj[v], K, ea[v]);
+            const double sg = jb.y < 0 ? a.isg : -1.0;  // image: +-log|r - r_img|, free: - log|r - r'|
+            if (jb.z >= 0) {
+                double cv[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) cv[v] = group_sum(qi[v] * K, TP);
+                if (i == wl && vj) {
+                    double *dst = a.part + ((int64_t)jb.z + j) * NV;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) dst[v] = sg * cv[v];
+                }
+            }
+            if (switch_job) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    R[v] = fma(sg, ea[v], R[v]);
+                    ea[v] = 0.0;
+                }
+                if (!more) break;
+                e = ne;
+                jb = jn;
+                jn = e + 1 < e1 ? jobs[e + 1] : jb;
+                bcount = ncount;
+            }
+            jj = njj;
+            j = jnx;
+            vj = vn;
+            Q = Qn;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qj[v] = qn[v];
+        }
+        // the G groups of a target hold parts of its row sum
+        for (int off = TP; off < 64; off <<= 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) R[v] += __shfl_xor(R[v], off);
+        }
+        if (g == 0 && act) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + ft + i] = make_double2(kInv4Pi * R[v], 0.0);
+        }
+    }
+}
+
+// Adds the column sums of the cross pairs (A, B), A < B, to B's targets, pairs in ascending A.
+template <int NV>
+__global__ __launch_bounds__(256) void k_near_gather(int64_t n, const int32_t *__restrict__ leaf_of,
+                                                     const int32_t *__restrict__ first,
+                                                     const int32_t *__restrict__ in_off,
+                                                     const int32_t *__restrict__ in_ent,
+                                                     const double *__restrict__ part, double2 *__restrict__ near) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int B = leaf_of[i];
+    const int e0 = in_off[B], e1 = in_off[B + 1];
+    if (e1 == e0) return;
+    const int jb = (int)(i - first[B]);
+    double sv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sv[v] = 0.0;
+    for (int e = e0; e < e1; ++e) {
+        const double *src = part + ((int64_t)in_ent[e] + jb) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sv[v] += src[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) near[(int64_t)v * n + i].x += kInv4Pi * sv[v];
+}
+
 // The same sums with a plain walk: the U list entry by entry, a source point loaded where it is
 // used (fewer instructions per pair; the memory latency is hidden by other waves only), free-space
 // and image terms in separate sums.
@@ -2305,6 +2494,69 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         FMMHP_HIP(hipGetLastError());
     }
 
+    // Symmetric near-field walk: records of at most 64 targets (a leaf, or a piece of a larger one),
+    // each with its jobs (the self pair, the self-image pair when listed, each cross pair with
+    // B > A); the cross jobs of a record own partial slots for B's points.  Per leaf B, the slots
+    // of its cross pairs in ascending A (and record).  Every cross pair's mirror entry is checked; a
+    // list that is not symmetric leaves the walk off for this plan.
+    {
+        std::vector<int32_t> first_h;
+        FMMHP_CHECK(to_host(first_h, T.first, (size_t)nbox, s));
+        FMMHP_HIP(hipStreamSynchronize(s));
+        std::vector<int4> recs, jobs;
+        std::vector<int32_t> in_cnt((size_t)nbox + 1, 0);
+        int64_t npart = 0;
+        bool ok = true;
+        for (int la = 0; la < nbox && ok; ++la) {
+            if (uoff[la + 1] == uoff[la]) continue;
+            for (int e = uoff[la]; e < uoff[la + 1] && ok; ++e) {
+                const int lb = uent[e] >> 1, img = uent[e] & 1;
+                if (lb > la && !std::binary_search(uent.begin() + uoff[lb], uent.begin() + uoff[lb + 1], 2 * la + img))
+                    ok = false;
+            }
+            for (int t0 = 0; t0 < cnt[la] && ok; t0 += 64) {
+                const int e0 = (int)jobs.size();
+                for (int e = uoff[la]; e < uoff[la + 1]; ++e) {
+                    const int lb = uent[e] >> 1, img = uent[e] & 1;
+                    if (lb < la) continue;
+                    const int code = (int)(((unsigned)cnt[lb]) | ((unsigned)img << 31));
+                    if (lb == la) {
+                        jobs.push_back(make_int4(first_h[lb], code, -1, 0));
+                        continue;
+                    }
+                    jobs.push_back(make_int4(first_h[lb], code, (int)npart, 0));
+                    in_cnt[lb + 1] += 1;
+                    npart += cnt[lb];
+                }
+                if (npart >= ((int64_t)1 << 31) || jobs.size() >= ((size_t)1 << 31)) ok = false;
+                recs.push_back(make_int4(first_h[la] + t0, std::min(64, cnt[la] - t0), e0, (int)jobs.size()));
+            }
+        }
+        S.sym_ok = ok && !recs.empty();
+        if (S.sym_ok) {
+            for (int b = 0; b < nbox; ++b) in_cnt[b + 1] += in_cnt[b];
+            // each box's slots in the order the jobs were made (A ascending, then record)
+            std::vector<int32_t> in_ent((size_t)in_cnt[nbox]), fill(in_cnt.begin(), in_cnt.end() - 1);
+            size_t k = 0;
+            for (int la = 0; la < nbox; ++la) {
+                if (uoff[la + 1] == uoff[la]) continue;
+                for (int t0 = 0; t0 < cnt[la]; t0 += 64)
+                    for (int e = uoff[la]; e < uoff[la + 1]; ++e) {
+                        const int lb = uent[e] >> 1;
+                        if (lb < la) continue;
+                        const int4 &jb = jobs[k++];
+                        if (lb > la) in_ent[fill[lb]++] = jb.z;
+                    }
+            }
+            S.sym_nrec = (int)recs.size();
+            S.sym_npart = npart;
+            FMMHP_CHECK(to_dev(A, &S.sym_rec, recs, "symmetric walk records", s));
+            FMMHP_CHECK(to_dev(A, &S.sym_jobs, jobs, "symmetric walk jobs", s));
+            FMMHP_CHECK(to_dev(A, &S.sym_in_off, in_cnt, "symmetric walk gather offsets", s));
+            FMMHP_CHECK(to_dev(A, &S.sym_in, in_ent, "symmetric walk gather entries", s));
+        }
+    }
+
     // surface-term chunks: at most kSurfChunk points, within one instance
     {
         std::vector<PtChunk> ch;
@@ -2439,9 +2691,20 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     // a bounded grid (a few workgroups per CU) leaves room on every CU for the far-field kernels
     // running concurrently on the main stream
     const dim3 near_grid((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks));
-    if (S.near_walk == 2)
+    if constexpr (MODE == kPhi) {
+        if (S.near_walk == 3 && S.sym_ok && ws.part) {
+            SymArgs sa{S.sym_nrec, S.sym_rec, S.sym_jobs, S.xy, ws.qs, S.logtab, S.bc == 2 ? -1.0 : 1.0,
+                       ws.part,    ws.near,   T.n};
+            const dim3 sym_grid((unsigned)std::min<int64_t>(nblk(S.sym_nrec, 4), S.near_blocks));
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_sym<NV>), sym_grid, dim3(256), 0, side_, sa);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_gather<NV>), dim3(nblk(T.n, 256)), dim3(256), 0, side_, T.n,
+                               T.leaf_of, T.first, S.sym_in_off, S.sym_in, ws.part, ws.near);
+        }
+    }
+    const bool sym_walk = MODE == kPhi && S.near_walk == 3 && S.sym_ok && ws.part;
+    if (!sym_walk && S.near_walk == 2)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_plain<MODE, NV>), near_grid, dim3(256), 0, side_, la);
-    else
+    else if (!sym_walk)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near<MODE, NV>), near_grid, dim3(256), 0, side_, la);
     if (S.n_rpts > 0 && S.bc == 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_reaction<MODE, NV>), dim3((unsigned)S.n_rpts), dim3(64), 0,
@@ -2643,8 +2906,16 @@ static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
     FMMHP_CHECK(A.alloc_n(&w.red, nv * (size_t)S.n_rch, "surface partial sums"));
     FMMHP_CHECK(A.alloc_n(&w.rank1, nv * (size_t)T.n_inst, "surface sums"));
     if (S.m2l_fp32) FMMHP_CHECK(A.alloc_n(&w.Wf, nv * nb * (size_t)m2l32_kp(S.PB), "FP32 M2L source rows"));
+    w.part = nullptr;  // the symmetric walk's partial sums come with the walk (ensure_sym_part)
     w.cap = nv;
     return FMMHP_OK;
+}
+
+// Partial sums of the symmetric near-field walk for the plan's workspace, allocated when the walk is
+// in use (walk 3 on a plan whose lists allow it).
+static fmmhp_status ensure_sym_part(Arena &A, Sched &S) {
+    if (!(S.near_walk == 3 && S.sym_ok) || S.ws.part) return FMMHP_OK;
+    return A.alloc_n(&S.ws.part, (size_t)S.ws.cap * S.sym_npart, "near-field pair partial sums");
 }
 
 static fmmhp_status enqueue_eval(const Tree &T, const Sched &S, int nvec, const double *q, double *phi,
@@ -2704,12 +2975,13 @@ static fmmhp_status scratch_on(int dev, unsigned char **out) {
 // when base is given.
 static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char *base, VecWs *w) {
     const size_t nb = (size_t)T.nbox, P1 = (size_t)S.PB + 1;
-    const size_t sizes[7] = {nv * P1 * nb * sizeof(cplx), nv * (size_t)S.nloc * P1 * nb * sizeof(cplx),
+    const size_t sizes[8] = {nv * P1 * nb * sizeof(cplx), nv * (size_t)S.nloc * P1 * nb * sizeof(cplx),
                              nv * (size_t)T.n * sizeof(double), nv * (size_t)T.n * sizeof(double2),
                              nv * (size_t)S.n_rch * sizeof(cplx), nv * (size_t)T.n_inst * sizeof(cplx),
-                             S.m2l_fp32 ? nv * nb * (size_t)m2l32_kp(S.PB) * sizeof(float) : 0};
-    size_t off[7], at = 0;
-    for (int k = 0; k < 7; ++k) {
+                             S.m2l_fp32 ? nv * nb * (size_t)m2l32_kp(S.PB) * sizeof(float) : 0,
+                             S.sym_ok && S.near_walk == 3 ? nv * (size_t)S.sym_npart * sizeof(double) : 0};
+    size_t off[8], at = 0;
+    for (int k = 0; k < 8; ++k) {
         off[k] = at;
         at += (sizes[k] + 255) / 256 * 256;
     }
@@ -2722,6 +2994,7 @@ static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char
         w->red = (cplx *)(base + off[4]);
         w->rank1 = (cplx *)(base + off[5]);
         w->Wf = S.m2l_fp32 ? (float *)(base + off[6]) : nullptr;
+        w->part = S.sym_ok && S.near_walk == 3 ? (double *)(base + off[7]) : nullptr;
     }
     return at;
 }
@@ -2762,6 +3035,7 @@ fmmhp_status run_eval_noalloc(const Tree &T, const Sched &S, int device, int nve
 
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi, hipStream_t s) {
     if (nvec >= kVecChunk) FMMHP_CHECK(ensure_vec_ws(A, T, S, kVecChunk));
+    FMMHP_CHECK(ensure_sym_part(A, S));
     if (!S.use_graph || S.timing || s == nullptr) return enqueue_eval(T, S, nvec, q, phi, s);
     auto &G = S.graph;
     if (!(G.exec && G.q == q && G.phi == phi && G.nvec == nvec && G.stream == s)) {

@@ -131,6 +131,7 @@ struct VecWs {
     cplx *red = nullptr;            // [nv][n_rch] surface partial sums
     cplx *rank1 = nullptr;          // [nv][n_inst] surface sums
     float *Wf = nullptr;            // [nv][nbox][KP] FP32 source rows of the matrix-core M2L
+    double *part = nullptr;         // [partial entries][nv] column sums of the symmetric near-field walk
 };
 
 // Evaluation schedule and tables derived from the tree.
@@ -169,7 +170,14 @@ struct Sched {
     int deep_level = 0;             // first level of the deep M2L part (0: no split)
     std::vector<int> tile_lev, ibox_lev, xbox_lev;  // per-level ranges of tiles, image-V and X boxes
     int cus = 1;                    // compute units of the device
-    int near_walk = 1;              // near-field walk: 1 prefetching, 2 plain
+    int near_walk = 1;              // near-field walk: 1 prefetching, 2 plain, 3 symmetric leaf pairs
+    // symmetric leaf-pair walk (potential passes): leaves with a U list, their jobs, gather lists
+    bool sym_ok = false;
+    int sym_nrec = 0;
+    int64_t sym_npart = 0;          // partial-sum entries per vector
+    int4 *sym_rec = nullptr;        // (first target, targets, first job, end of jobs) per record
+    int4 *sym_jobs = nullptr;       // (first point of B, count | image << 31, partial slot or -1, 0)
+    int32_t *sym_in_off = nullptr, *sym_in = nullptr;  // per box: its partial slots (gather)
     int64_t near_blocks = 512;      // near-field grid (workgroups)
     bool fork_late = false;         // start the deep M2L after the whole upward pass
     bool serial = false;            // every kernel on the eval stream (FMMHP_FLAG_SERIAL)

@@ -30,6 +30,7 @@ constexpr double kInv4Pi = 0.07957747154594766788;
 constexpr double kEulerGamma = 0.57721566490153286061;
 constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 with its low 32 bits cleared
 constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+constexpr double kLn2 = 6.93147180559945309417e-01;    // ln 2 rounded to double
 
 // 1 / x for a positive normal double whose reciprocal is normal: the hardware reciprocal refined by
 // two Newton steps (each squares the relative error).
@@ -76,9 +77,12 @@ __device__ __forceinline__ double log_pos(double x) {
 // Table-assisted natural logarithm of a positive finite double (the near-field pair loop).
 // x = 2^e m, m in [1, 2); the top 9 bits of the mantissa select c_k = 1 + (k + 1/2)/512, and
 // log x = e ln 2 + L_k + log1p(t),  t = m r_k - 1,  r_k = fl(1/c_k),  L_k = -log(r_k),
-// with |t| <= 2^-10 so that log1p(t) = t - t^2/2 + t^3/3 - t^4/4 + t^5/5 leaves an error below
-// 2^-62.  The table entries (r_k, L_k) are built on the host by log_table_entry.  For x = +0 the
-// result is finite (about -709), so a caller may evaluate it unconditionally and mask the result.
+// with |t| <= 2^-10, so that log1p(t) = t - t^2/2 + t^3/3 leaves an error below t^4/4 <= 2^-42
+// (2.3e-13, absolute) and e ln 2 in one rounding adds at most |e| 2^-54: a pair's log term is
+// good to ~2.5e-13, which moves a potential built from ~150 such terms by ~1e-12 at most, four
+// orders below the 1e-10 accuracy target.  The table entries (r_k, L_k) are built on the host by
+// log_table_entry.  For x = +0 the result is finite (about -709), so a caller may evaluate it
+// unconditionally and mask the result.
 constexpr int kLogTable = 512;
 
 inline void log_table_entry(int k, double *r, double *L) {
@@ -95,13 +99,9 @@ __device__ __forceinline__ double log_tab(double x, const double2 *__restrict__ 
     const double m = __longlong_as_double((u & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
     const double2 rl = tab[k];
     const double t = fma(m, rl.x, -1.0);
-    double p = 1.0 / 5.0;
-    p = fma(p, t, -1.0 / 4.0);
-    p = fma(p, t, 1.0 / 3.0);
-    p = fma(p, t, -1.0 / 2.0);
+    double p = fma(1.0 / 3.0, t, -1.0 / 2.0);
     p = fma(p, t, 1.0);
-    const double ed = (double)e;
-    return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(t, p, rl.y)));
+    return fma((double)e, kLn2, fma(t, p, rl.y));
 }
 
 // 1 / (k k!) for k = 1..32: coefficients of the power series of Ei.

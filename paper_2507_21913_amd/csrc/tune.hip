@@ -178,9 +178,9 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
         fmmhp_plan_t plan = nullptr;
         st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &bo, s, &plan);
         if (st == FMMHP_OK) {
-            constexpr int kShapes = 4, kRounds = 3;
-            static const int shapes[kShapes][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}};
-            const int def_walk = plan->sched.PB >= 30 ? 2 : 1, def_groups = def_walk == 2 ? 4 : 2;
+            constexpr int kShapes = 6, kRounds = 3;
+            static const int shapes[kShapes][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}, {3, 2}, {3, 4}};
+            const int def_walk = plan->sched.near_walk, def_groups = (int)(plan->sched.near_blocks / plan->sched.cus);
             double t[kShapes][kRounds];
             for (int r = 0; r < kRounds && st == FMMHP_OK; ++r)
                 for (int k = 0; k < kShapes && st == FMMHP_OK; ++k) {

@@ -75,7 +75,7 @@ DRIVER = textwrap.dedent("""
         st.append(L.fmmhp_plan_create(10, fake, fake, None, None, re, im, ctypes.byref(good), None, ctypes.byref(h)))
         L.fmmhp_last_error_message()
     for o in (F.Opts(0, 40, 0, 0), F.Opts(41, 40, 0, 0), F.Opts(20, 0, 0, 0), F.Opts(20, 40, 31, 0),
-              F.Opts(20, 40, 0, 64), F.Opts(20, 40, 0, 12), F.Opts(20, 40, 0, 0, 3, 0), F.Opts(20, 40, 0, 0, 0, 17)):
+              F.Opts(20, 40, 0, 64), F.Opts(20, 40, 0, 12), F.Opts(20, 40, 0, 0, 4, 0), F.Opts(20, 40, 0, 0, 0, 17)):
         st.append(L.fmmhp_plan_create(10, fake, fake, None, None, 1.0, 0.0, ctypes.byref(o), None, ctypes.byref(h)))
         L.fmmhp_last_error_message()
     st.append(L.fmmhp_plan_create_targets(0, fake, fake, 10, fake, fake, 1.0, 0.0, ctypes.byref(good), None,
