@@ -388,7 +388,7 @@ def main():
         tuned["tune_s"] = time.perf_counter() - t0
         p_use, leaf_use = tuned["p"], tuned["leaf_size"]
         shape = {"near_walk": tuned["near_walk"], "near_groups": tuned["near_groups"],
-                 "m2l_fp32": tuned["m2l_fp32"]}
+                 "m2l_fp32": tuned["m2l_fp32"], "m2l_form": tuned.get("m2l_form")}
     else:
         if a.leaf == 0:
             leaf_use = 40

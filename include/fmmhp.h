@@ -66,14 +66,18 @@ typedef struct {
     int leaf_size;  /* a box with more than leaf_size points is split (>= 1) */
     int max_level;  /* deepest tree level, 1..30 (1..27 for a forest); 0 selects the maximum */
     unsigned flags; /* 0, or a combination of FMMHP_FLAG_GRAPH, FMMHP_FLAG_M2L_FP32,
-                       FMMHP_FLAG_SERIAL and one of FMMHP_FLAG_DIRICHLET, FMMHP_FLAG_NEUMANN */
+                       FMMHP_FLAG_SERIAL, one of FMMHP_FLAG_M2L_VECTOR, FMMHP_FLAG_M2L_MFMA and
+                       one of FMMHP_FLAG_DIRICHLET, FMMHP_FLAG_NEUMANN */
     /* Launch shape of the near field (the U-list sums), which runs beside the far-field kernels on
      * a bounded grid.  Neither changes what is computed beyond rounding; fmmhp_tune picks both by
      * timing.  0 selects the default for the plan's p. */
     int near_walk;   /* 0: default; 1: source points loaded one step ahead of their use (hides
                         memory latency, more instructions per pair); 2: plain walk; 3: symmetric
                         leaf pairs (potential evaluations: each pair of leaves once, its column
-                        sums gathered by a second kernel; other passes use walk 1) */
+                        sums gathered by a second kernel; other passes use walk 1); 4: symmetric
+                        leaf pairs with the pairs blocked in registers (each lane holds up to 8
+                        targets; column sums reduced over a few lanes; potential evaluations,
+                        other passes use walk 1) */
     int near_groups; /* 0: default; 1..16: near-field workgroups per compute unit */
 } fmmhp_opts;
 
@@ -102,6 +106,13 @@ typedef struct {
  * and the deep-level M2L on streams of their own beside the rest: a profiling aid (each kernel's
  * duration is then its own, not shared with concurrent kernels); slower. */
 #define FMMHP_FLAG_SERIAL 16u
+/* Form of the FP64 M2L of upper sources (eq. (truncatedM2Lcoef) and the log-kernel M2L).  By default
+ * it runs on the vector ALUs (one lane per target box, operators in scalar registers) for p < 30 and
+ * on the FP64 matrix cores (v_mfma_f64_16x16x4f64, complex numbers as 2 x 2 real blocks) for p >= 30;
+ * each flag forces one form (not both).  The same sums in another order (agreement to rounding).
+ * Ignored with FMMHP_FLAG_M2L_FP32. */
+#define FMMHP_FLAG_M2L_VECTOR 32u
+#define FMMHP_FLAG_M2L_MFMA 64u
 
 typedef struct {
     int64_t n;              /* number of points */

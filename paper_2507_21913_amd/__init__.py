@@ -30,6 +30,19 @@ FLAG_M2L_FP32 = 2  # fmmhp_opts.flags: upper-source M2L on the FP32 matrix cores
 FLAG_DIRICHLET = 4  # fmmhp_opts.flags: Dirichlet half-plane kernel (eq. (ddd1.2), image term +)
 FLAG_NEUMANN = 8    # fmmhp_opts.flags: Neumann half-plane kernel (eq. (ddd1.2), image term -)
 FLAG_SERIAL = 16    # fmmhp_opts.flags: every kernel on the eval stream (profiling aid)
+FLAG_M2L_VECTOR = 32  # fmmhp_opts.flags: FP64 M2L on the vector ALUs (default for p < 30)
+FLAG_M2L_MFMA = 64    # fmmhp_opts.flags: FP64 M2L on the matrix cores (default for p >= 30)
+
+
+def _m2l_flag(form):
+    """fmmhp_opts.flags bits of an M2L form: None (by order), "vector" or "mfma"."""
+    if form is None:
+        return 0
+    if form == "vector":
+        return FLAG_M2L_VECTOR
+    if form == "mfma":
+        return FLAG_M2L_MFMA
+    raise ValueError("m2l_form must be None, 'vector' or 'mfma'")
 _BC_FLAGS = {"robin": 0, "dirichlet": FLAG_DIRICHLET, "neumann": FLAG_NEUMANN}
 
 
@@ -278,6 +291,8 @@ def fmmhp_tune(n, x_ptr, y_ptr, q_ptr, lambda_re, lambda_im, tol, n_vec, leaf_si
                                           ctypes.byref(ms), stream))
     return {"p": best.p, "leaf_size": best.leaf_size, "near_walk": best.near_walk,
             "near_groups": best.near_groups, "m2l_fp32": bool(best.flags & FLAG_M2L_FP32),
+            "m2l_form": ("vector" if best.flags & FLAG_M2L_VECTOR else
+                         "mfma" if best.flags & FLAG_M2L_MFMA else None),
             "rel_l2": err.value, "eval_ms": ms.value}
 
 
@@ -341,7 +356,8 @@ def _cache_store(path, key, value):
 
 def tune(x, y, q, impedance, tol=1e-10, n_vec=1, leaf_sizes=None, sample=0, use_cache=True) -> dict:
     """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error, the near-field
-    launch shape (near_walk, near_groups) and the M2L form (m2l_fp32) by timing the chosen plan.
+    launch shape (near_walk, near_groups) and the M2L form (m2l_form: None for the default by
+    order, "vector" or "mfma"; m2l_fp32) by timing the chosen plan.
     With use_cache the choice is read from (and written to) the tuner's JSON cache; "cached" in the
     result says which."""
     x = _dev_f64(x, "x")
@@ -383,10 +399,13 @@ class HalfPlaneFMM:
     bc          "robin" (the impedance condition), "dirichlet" or "neumann" (eq. (ddd1.2); the
                 impedance is then ignored)
     serial      every kernel on the eval stream, one after another (profiling aid; slower)
+    m2l_form    FP64 M2L form: None (vector ALUs for p < 30, matrix cores from p = 30), "vector"
+                or "mfma" (the same sums in another order)
     """
 
     def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False,
-                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0, bc="robin", serial=False):
+                 graph=False, m2l_fp32=False, near_walk=0, near_groups=0, bc="robin", serial=False,
+                 m2l_form=None):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         self.n = int(x.shape[0])
@@ -395,7 +414,7 @@ class HalfPlaneFMM:
         lr, li = _split_impedance(impedance)
         opts = Opts(int(p), int(leaf_size), int(max_level),
                     (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc)
-                    | (FLAG_SERIAL if serial else 0),
+                    | (FLAG_SERIAL if serial else 0) | _m2l_flag(m2l_form),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             if pass_images:
@@ -438,7 +457,7 @@ class HalfPlaneFMM:
 
     @classmethod
     def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False,
-                m2l_fp32=False, near_walk=0, near_groups=0, bc="robin"):
+                m2l_fp32=False, near_walk=0, near_groups=0, bc="robin", m2l_form=None):
         """A forest plan over n_inst independent instances: points offsets[k]..offsets[k+1]-1 of
         (x, y) form instance k with impedance impedances[k].  Evaluation takes charges for all
         points (instance after instance) and runs every instance in the same launches."""
@@ -457,7 +476,8 @@ class HalfPlaneFMM:
         if len(imps) != self.n_inst:
             raise ValueError("one impedance per instance")
         opts = Opts(int(p), int(leaf_size), int(max_level),
-                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc),
+                    (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc)
+                    | _m2l_flag(m2l_form),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,

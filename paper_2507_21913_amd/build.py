@@ -23,6 +23,8 @@ FLAGS = [
     # packed fp32 arithmetic stays off in every kernel of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast",
+    # matrix-core accumulators in VGPRs: loop-carried MFMA sums are not copied to and from AGPRs
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -90,12 +90,13 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     if (o.max_level == 0) o.max_level = lb;
     if (o.p < 1 || o.p > FMMHP_MAX_P || o.leaf_size < 1 || o.max_level < 1 || o.max_level > lb ||
         (o.flags & ~(FMMHP_FLAG_GRAPH | FMMHP_FLAG_M2L_FP32 | FMMHP_FLAG_DIRICHLET | FMMHP_FLAG_NEUMANN |
-                     FMMHP_FLAG_SERIAL)) != 0 ||
-        (o.flags & FMMHP_FLAG_DIRICHLET && o.flags & FMMHP_FLAG_NEUMANN) || o.near_walk < 0 || o.near_walk > 3 ||
+                     FMMHP_FLAG_SERIAL | FMMHP_FLAG_M2L_VECTOR | FMMHP_FLAG_M2L_MFMA)) != 0 ||
+        (o.flags & FMMHP_FLAG_DIRICHLET && o.flags & FMMHP_FLAG_NEUMANN) ||
+        (o.flags & FMMHP_FLAG_M2L_VECTOR && o.flags & FMMHP_FLAG_M2L_MFMA) || o.near_walk < 0 || o.near_walk > 4 ||
         o.near_groups < 0 || o.near_groups > 16) {
-        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (bits 0..3, "
-                  "not both 2 and 3), "
-                  "near_walk=%d (0..3), near_groups=%d (0..16)",
+        set_error("options out of range: p=%d (1..%d), leaf_size=%d (>=1), max_level=%d (1..%d), flags=%u (FMMHP_FLAG_* bits, "
+                  "not both DIRICHLET and NEUMANN, not both M2L_VECTOR and M2L_MFMA), "
+                  "near_walk=%d (0..4), near_groups=%d (0..16)",
                   o.p, FMMHP_MAX_P, o.leaf_size, o.max_level, lb, o.flags, o.near_walk, o.near_groups);
         return FMMHP_EINVAL;
     }
@@ -121,6 +122,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
                         stream);
     p->sched.m2l_fp32 = (o.flags & FMMHP_FLAG_M2L_FP32) != 0;
     p->sched.serial = (o.flags & FMMHP_FLAG_SERIAL) != 0;
+    p->sched.m2l_form = (o.flags & FMMHP_FLAG_M2L_VECTOR) ? 1 : (o.flags & FMMHP_FLAG_M2L_MFMA) ? 2 : 0;
     p->sched.bc = (o.flags & FMMHP_FLAG_DIRICHLET) ? 1 : (o.flags & FMMHP_FLAG_NEUMANN) ? 2 : 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
     if (st == FMMHP_OK) apply_launch_shape(p->sched, o.near_walk, o.near_groups);

@@ -486,6 +486,171 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// M2L of upper sources on the FP64 matrix cores (the default for p >= kM2LMfmaOrder, or with
+// FMMHP_FLAG_M2L_MFMA).  On gfx950 an FP64 matrix instruction (16 x 16 x 4, 2048 flops) occupies the
+// SIMD's matrix unit for 64 cycles: the same FP64 rate as the vector ALUs, so this form wins only where
+// its padding is small: 2(p+1) output columns padded to 16 and p+1 source coefficients to 4 keep
+// 94% of the instructions' work at p = 30 but 77% at p = 20.
+// Per offset slot the tile's contraction acc_n += sum_m T_{n+m} w_m is a real GEMM in the 2x2
+// embedding of complex numbers,
+//   D[target][2n + c] += sum_m (Re w_m B[2m][2n + c] + Im w_m B[2m + 1][2n + c]),
+//   B[2m][2n] = B[2m + 1][2n + 1] = Re T_{n+m},  B[2m][2n + 1] = -B[2m + 1][2n] = Im T_{n+m},
+// run as v_mfma_f64_16x16x4f64 (lane layout measured on the device: A[i][k] from lane i + 16k,
+// B[k][j] from lane j + 16k, D[i][j] in element i / 4 of lane j + 16 (i % 4)).  The K order makes
+// every lane read whole complex numbers: at step s lane group g = l / 16 takes source coefficient
+// m = 4s + g, the step's first instruction its real part with row 2m of B, the second its imaginary
+// part with row 2m + 1, both rows from the one complex T_{n+m}.  Wave cb of the workgroup owns the
+// output columns [16 cb, 16 cb + 16) (coefficients 8 cb .. 8 cb + 7) of all 64 targets of the tile:
+// four 16-row blocks, four independent accumulators.  The tile's sources are staged in LDS SPP steps
+// (4 SPP coefficients) at a time, with a zero row for targets that have no source at a slot; the
+// operator values of the next used slot are loaded (the table stays in L2) while the current slot's
+// instructions run.
+// ---------------------------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfSteps = 1;        // steps of 4 source coefficients staged in LDS per phase
+
+
+template <int PB, int SPP>
+__global__ __launch_bounds__(64 * mf_ncb(PB)) void k_m2l_mf(M2LArgs a) {
+    constexpr int P1 = PB + 1, NCB = mf_ncb(PB), NKS = mf_nks(PB), NTP = m2l_row(PB);
+    constexpr int MPH = 4 * SPP;                        // source coefficients per phase
+    constexpr int NPH = (NKS + SPP - 1) / SPP;
+    constexpr int NTH = 64 * NCB;
+    static_assert(kNumSlots * kTile % 8 == 0, "the slot table is copied in 16-byte pieces");
+    static_assert(8 * NCB + MPH * NPH - 1 <= NTP, "operator rows cover every padded (n, m) pair");
+    __shared__ cplx sW[MPH * (kM2LMaxSrc + 1)];         // [coefficient][source], row ns all zeros
+    __shared__ int4 s_slot4[kNumSlots * kTile / 8];     // (slot, target) -> source, or -1
+    __shared__ int32_t s_box[kTile];                    // the tile's target boxes
+    __shared__ int32_t s_src[kM2LMaxSrc];               // the tile's source boxes
+    __shared__ cplx s_acc0[kTile];                      // log term of lambda_0 per target
+    const int16_t *s_slot = (const int16_t *)s_slot4;
+    const int tile = blockIdx.x + a.tile0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int cb = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const cplx *W = a.W + (int64_t)blockIdx.y * P1 * a.nbox;  // charge vector
+    cplx *Lam = a.Lam + (int64_t)blockIdx.y * a.nloc * P1 * a.nbox;
+    const int s0 = a.tile_src_off[tile];
+    const int ns = a.tile_src_off[tile + 1] - s0;
+    const int ns1 = ns + 1;
+    const uint64_t mask = a.tile_mask[tile];
+    {
+        const int4 *gs = (const int4 *)(a.tile_slot + (int64_t)tile * kNumSlots * kTile);
+        for (int i = tid; i < kNumSlots * kTile / 8; i += NTH) s_slot4[i] = gs[i];
+        if (tid < kTile) s_box[tid] = a.tiles[tile * kTile + tid];
+        for (int sj = tid; sj < ns; sj += NTH) s_src[sj] = a.tile_src[s0 + sj];
+    }
+    const int g = lane >> 4, c = lane & 15;
+    const int nb = 8 * cb + (c >> 1);  // output coefficient of this lane's column
+    const bool odd = (c & 1) != 0;     // the column holds imaginary parts
+    f64x4 acc[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    cplx acc0 = mk(0.0, 0.0);  // wave 0: the log term of the lane's target
+#pragma unroll 1
+    for (int ph = 0; ph < NPH; ++ph) {
+        const int m0 = ph * MPH;
+        __syncthreads();
+        for (int idx = tid; idx < MPH * ns1; idx += NTH) {
+            const int mm = idx / ns1, sj = idx - mm * ns1;
+            cplx v = mk(0.0, 0.0);
+            if (sj < ns && m0 + mm <= PB) v = W[(int64_t)(m0 + mm) * a.nbox + s_src[sj]];
+            sW[idx] = v;
+        }
+        __syncthreads();
+        if (ph == 0 && cb == 0) {
+            const int bo = s_box[lane];
+            const double ll = bo >= 0 ? a.logside[bo] * kInv4Pi : 0.0;
+            uint64_t rest = mask;
+            while (rest) {
+                const int o = __builtin_ctzll(rest);
+                rest &= rest - 1;
+                const int li = s_slot[o * kTile + lane];
+                if (li >= 0) cfma(acc0, a.Lfree[o] - mk(ll, 0.0), sW[li]);
+            }
+        }
+        if (mask == 0) continue;
+        const cplx *Tb = a.Tfree + nb + m0 + g;  // this lane's operator value: Tb[o NTP + 4 st]
+        const cplx *sWg = sW + g * ns1;          // this lane's coefficient row of step 0
+        // software pipeline over the used slots: the slot map, source values and operator values of
+        // the next slot are loaded before the current slot's instructions issue (one basic block per
+        // slot, so that the loads stay ahead of the matrix instructions)
+        uint64_t rest = mask;
+        int o = __builtin_ctzll(rest);
+        rest &= rest - 1;
+        cplx tc[SPP], wc[SPP][4];
+#pragma unroll
+        for (int st = 0; st < SPP; ++st) tc[st] = Tb[o * NTP + 4 * st];
+        {
+            int row[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int li = s_slot[o * kTile + 16 * rb + c];
+                row[rb] = li >= 0 ? li : ns;
+            }
+#pragma unroll
+            for (int st = 0; st < SPP; ++st)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) wc[st][rb] = sWg[4 * st * ns1 + row[rb]];
+        }
+        int left = __builtin_popcountll(mask);
+        do {
+            const int on = rest ? __builtin_ctzll(rest) : o;  // the last slot reloads its own values
+            rest &= rest - 1;
+            cplx tn[SPP], wn[SPP][4];
+            int row[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int li = s_slot[on * kTile + 16 * rb + c];
+                row[rb] = li >= 0 ? li : ns;
+            }
+#pragma unroll
+            for (int st = 0; st < SPP; ++st) tn[st] = Tb[on * NTP + 4 * st];
+#pragma unroll
+            for (int st = 0; st < SPP; ++st)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) wn[st][rb] = sWg[4 * st * ns1 + row[rb]];
+#pragma unroll
+            for (int st = 0; st < SPP; ++st) {
+                const double b1 = odd ? tc[st].im : tc[st].re;
+                const double b2 = odd ? tc[st].re : -tc[st].im;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[st][rb].re, b1, acc[rb], 0, 0, 0);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[st][rb].im, b2, acc[rb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int st = 0; st < SPP; ++st) {
+                tc[st] = tn[st];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) wc[st][rb] = wn[st][rb];
+            }
+            o = on;
+        } while (--left > 0);
+    }
+    if (cb == 0) s_acc0[lane] = acc0;
+    __syncthreads();
+    if (nb > PB) return;  // padding columns
+    // lambda_n = -acc_n (+ the log term for n = 0); element r of block rb: target 16 rb + 4 r + g
+    const int64_t stride = (int64_t)P1 * a.nbox;
+    double *out = (double *)(Lam + (int64_t)nb * a.nbox) + (odd ? 1 : 0);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = 16 * rb + 4 * r + g;
+            const int b = s_box[t];
+            double v = -acc[rb][r];
+            if (nb == 0) v += odd ? s_acc0[t].im : s_acc0[t].re;
+            if (b >= 0) {
+                out[2 * (int64_t)b] = v;
+                if (a.nloc == 2) out[2 * (stride + b)] = v;
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------------------------
 // M2L of upper sources on the FP32 matrix cores (FMMHP_FLAG_M2L_FP32).  Per offset slot the tile's
 // contraction is a real GEMM in the 2x2 embedding of complex numbers:
 //   [Re acc, Im acc](64 x 2(p+1)) += [Re w'', Im w''](64 x 2(p+1)) * [[Re T'', Im T''], [-Im T'', Re T'']]
@@ -1409,6 +1574,148 @@ __global__ __launch_bounds__(256) void k_near_sym(SymArgs a) {
         if (g == 0 && act) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) a.near[(int64_t)v * a.n + ft + i] = make_double2(kInv4Pi * R[v], 0.0);
+        }
+    }
+}
+
+// Near field, log terms, symmetric leaf pairs with the pairs blocked in registers (near_walk 4;
+// potential passes).  The records, jobs and partial slots are those of walk 3.  A record's lanes form
+// IA target groups (consecutive lanes) by JG = 64 / IA source groups, IA the smallest power of two
+// with IA * kBlkTargets >= the record's targets: lane (ig, jg) holds the targets ig, ig + IA, ...
+// (at most kBlkTargets, in registers) and takes the source points jg, jg + JG, ... of the record's
+// job stream (the points of its jobs one after another, a step may span several jobs).  Each pair
+// adds to the lane's row sums (the charges of the source point, with the job's sign); for a cross
+// pair the column sum over the lane's targets is reduced over the IA lanes of the source group by
+// DPP lane moves (none when IA = 1) and written to the pair's partial slot.  The row sums of a
+// target are reduced over its JG lanes once per record.
+constexpr int kBlkTargets = 8;
+
+// Sum over aligned groups of IA = 1, 2, 4 or 8 consecutive lanes (every lane of a group gets it).
+__device__ __forceinline__ double lane_group_sum(double s, int IA) {
+    if (IA >= 2) s += dpp_move<0xB1, 0xF>(s);   // quad_perm [1, 0, 3, 2]
+    if (IA >= 4) s += dpp_move<0x4E, 0xF>(s);   // quad_perm [2, 3, 0, 1]
+    if (IA >= 8) s += dpp_move<0x141, 0xF>(s);  // row_half_mirror
+    return s;
+}
+
+// One record with TI targets per lane (compile-time, so that a step's TI pair evaluations are
+// straight-line code whose table loads issue together).
+template <int NV, int TI>
+__device__ __forceinline__ void near_blk_record(const SymArgs &a, const double2 *__restrict__ tab, int lane, int ft,
+                                                int nt, int e0, int e1, int IA) {
+    const double2 *__restrict__ xy = a.xy;
+    const double *__restrict__ qs = a.qs;
+    const int4 *__restrict__ jobs = a.jobs;
+    const int JG = 64 / IA;
+    const int ig = lane & (IA - 1), jg = lane / IA;
+    double tx[TI], ty[TI], tq[TI][NV], R[TI][NV];
+#pragma unroll
+    for (int k = 0; k < TI; ++k) {
+        const int i = ig + IA * k;
+        const bool act = i < nt;
+        const double2 P = xy[ft + (act ? i : 0)];
+        tx[k] = P.x;
+        ty[k] = P.y;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            tq[k][v] = act ? qs[(int64_t)(ft + i) * NV + v] : 0.0;
+            R[k][v] = 0.0;
+        }
+    }
+    int tot = 0;  // points in the record's job stream
+    for (int e = e0; e < e1; ++e) tot += jobs[e].y & 0x7fffffff;
+    // the lane's job: index, stream position of its first point, the job itself
+    int e = e0, js = 0;
+    int4 jb = jobs[e0];
+    for (int p0 = 0; p0 < tot; p0 += JG) {
+        const int p = p0 + jg;
+        const bool valid = p < tot;
+        while (valid && p >= js + (jb.y & 0x7fffffff)) {
+            js += jb.y & 0x7fffffff;
+            jb = jobs[++e];
+        }
+        const int j = jb.x + (valid ? p - js : 0);
+        const bool img = jb.y < 0;
+        const double ysg = img ? 1.0 : -1.0;    // image: y + y', free: y - y'
+        const double sg = img ? a.isg : -1.0;  // image: +-log|r - r_img|, free: - log|r - r'|
+        const double2 Q = xy[j];
+        double qj[NV], cs[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qj[v] = valid ? sg * qs[(int64_t)j * NV + v] : 0.0;
+            cs[v] = 0.0;
+        }
+        double K[TI];
+#pragma unroll
+        for (int k = 0; k < TI; ++k) {
+            const double dx = tx[k] - Q.x, dy = fma(ysg, Q.y, ty[k]);
+            const double r2 = fma(dx, dx, dy * dy);
+            // r2 = 0 only for a coincident free pair, skipped (eq. (1.2)), or between two target-only
+            // points on y = 0 (no charge)
+            const double lg = log_tab(r2, tab);
+            K[k] = r2 > 0.0 ? lg : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < TI; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                R[k][v] = fma(qj[v], K[k], R[k][v]);
+                cs[v] = fma(tq[k][v], K[k], cs[v]);
+            }
+        // the source group's column sums (all IA lanes share p, hence the job)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cs[v] = lane_group_sum(cs[v], IA);
+        if (valid && ig == 0 && jb.z >= 0) {
+            double *dst = a.part + ((int64_t)jb.z + (p - js)) * NV;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[v] = sg * cs[v];
+        }
+    }
+    // a target's row sum is spread over its JG lanes (stride IA)
+    for (int off = IA; off < 64; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < TI; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) R[k][v] += __shfl_xor(R[k][v], off);
+    }
+    if (jg == 0) {
+#pragma unroll
+        for (int k = 0; k < TI; ++k) {
+            const int i = ig + IA * k;
+            if (i < nt) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    a.near[(int64_t)v * a.n + ft + i] = make_double2(kInv4Pi * R[k][v], 0.0);
+            }
+        }
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256, 4) void k_near_blk(SymArgs a) {
+    constexpr int TM = kBlkTargets;
+    static_assert(TM == 8, "the dispatch below covers 1..8 targets per lane");
+    __shared__ double2 s_logtab[kLogTable];
+    for (int k = threadIdx.x; k < kLogTable; k += blockDim.x) s_logtab[k] = a.logtab[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const XcdChunks ch = xcd_chunks((a.nrec + 3) / 4);  // four records (one per wave) per chunk
+    for (int64_t c = ch.c0; c < ch.c1; c += ch.step) {
+        const int ri = (int)(c * 4 + wave);
+        if (ri >= a.nrec) continue;
+        const int4 rc = a.rec[ri];
+        const int ft = rc.x, nt = rc.y, e0 = rc.z, e1 = rc.w;
+        const int IA = nt <= TM ? 1 : nt <= 2 * TM ? 2 : nt <= 4 * TM ? 4 : 8;
+        switch ((nt + IA - 1) / IA) {  // targets of lane group 0 (the others hold as many or one fewer)
+        case 1: near_blk_record<NV, 1>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        case 2: near_blk_record<NV, 2>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        case 3: near_blk_record<NV, 3>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        case 4: near_blk_record<NV, 4>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        case 5: near_blk_record<NV, 5>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        case 6: near_blk_record<NV, 6>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        case 7: near_blk_record<NV, 7>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
+        default: near_blk_record<NV, 8>(a, s_logtab, lane, ft, nt, e0, e1, IA); break;
         }
     }
 }
@@ -2691,17 +2998,26 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     // a bounded grid (a few workgroups per CU) leaves room on every CU for the far-field kernels
     // running concurrently on the main stream
     const dim3 near_grid((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks));
+    // walk 4 keeps each lane's targets and row sums in registers: single-vector passes only (the
+    // others take walk 1)
+    const bool sym_walk = MODE == kPhi && S.sym_ok && ws.part && (S.near_walk == 3 || (S.near_walk == 4 && NV == 1));
     if constexpr (MODE == kPhi) {
-        if (S.near_walk == 3 && S.sym_ok && ws.part) {
+        if (sym_walk) {
             SymArgs sa{S.sym_nrec, S.sym_rec, S.sym_jobs, S.xy, ws.qs, S.logtab, S.bc == 2 ? -1.0 : 1.0,
                        ws.part,    ws.near,   T.n};
             const dim3 sym_grid((unsigned)std::min<int64_t>(nblk(S.sym_nrec, 4), S.near_blocks));
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_sym<NV>), sym_grid, dim3(256), 0, side_, sa);
+            if constexpr (NV == 1) {
+                if (S.near_walk == 4)
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_blk<NV>), sym_grid, dim3(256), 0, side_, sa);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_sym<NV>), sym_grid, dim3(256), 0, side_, sa);
+            } else {
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_sym<NV>), sym_grid, dim3(256), 0, side_, sa);
+            }
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_gather<NV>), dim3(nblk(T.n, 256)), dim3(256), 0, side_, T.n,
                                T.leaf_of, T.first, S.sym_in_off, S.sym_in, ws.part, ws.near);
         }
     }
-    const bool sym_walk = MODE == kPhi && S.near_walk == 3 && S.sym_ok && ws.part;
     if (!sym_walk && S.near_walk == 2)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_plain<MODE, NV>), near_grid, dim3(256), 0, side_, la);
     else if (!sym_walk)
@@ -2747,8 +3063,12 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
                            S.tile_mask, S.Tfree, S.Lfree, S.logside,  ws.W,            ws.Lam,      S.nloc};
                 FMMHP_CHECK(mk_.km_mark(which, 0, st));
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)), 0,
-                                   st, ma);
+                if (!(S.m2l_form == 2 || (S.m2l_form == 0 && PB >= kM2LMfmaOrder)))
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)),
+                                       0, st, ma);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_mf<PB, kMfSteps>), dim3(t1 - t0, NV),
+                                       dim3(64 * mf_ncb(PB)), 0, st, ma);
                 FMMHP_CHECK(mk_.km_mark(which, 1, st));
             }
         }
@@ -2914,7 +3234,7 @@ static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
 // Partial sums of the symmetric near-field walk for the plan's workspace, allocated when the walk is
 // in use (walk 3 on a plan whose lists allow it).
 static fmmhp_status ensure_sym_part(Arena &A, Sched &S) {
-    if (!(S.near_walk == 3 && S.sym_ok) || S.ws.part) return FMMHP_OK;
+    if (!((S.near_walk == 3 || S.near_walk == 4) && S.sym_ok) || S.ws.part) return FMMHP_OK;
     return A.alloc_n(&S.ws.part, (size_t)S.ws.cap * S.sym_npart, "near-field pair partial sums");
 }
 
@@ -2979,7 +3299,7 @@ static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char
                              nv * (size_t)T.n * sizeof(double), nv * (size_t)T.n * sizeof(double2),
                              nv * (size_t)S.n_rch * sizeof(cplx), nv * (size_t)T.n_inst * sizeof(cplx),
                              S.m2l_fp32 ? nv * nb * (size_t)m2l32_kp(S.PB) * sizeof(float) : 0,
-                             S.sym_ok && S.near_walk == 3 ? nv * (size_t)S.sym_npart * sizeof(double) : 0};
+                             S.sym_ok && (S.near_walk == 3 || S.near_walk == 4) ? nv * (size_t)S.sym_npart * sizeof(double) : 0};
     size_t off[8], at = 0;
     for (int k = 0; k < 8; ++k) {
         off[k] = at;
@@ -2994,7 +3314,7 @@ static size_t vec_ws_layout(const Tree &T, const Sched &S, int nv, unsigned char
         w->red = (cplx *)(base + off[4]);
         w->rank1 = (cplx *)(base + off[5]);
         w->Wf = S.m2l_fp32 ? (float *)(base + off[6]) : nullptr;
-        w->part = S.sym_ok && S.near_walk == 3 ? (double *)(base + off[7]) : nullptr;
+        w->part = S.sym_ok && (S.near_walk == 3 || S.near_walk == 4) ? (double *)(base + off[7]) : nullptr;
     }
     return at;
 }

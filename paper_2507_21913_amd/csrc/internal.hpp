@@ -24,6 +24,7 @@ constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
 constexpr int kM2LChunkMax = 8;   // at most this many output coefficients per M2L wave
 constexpr int kM2LPhase = 4;      // multipole coefficients staged in LDS per phase
+constexpr int kM2LMfmaOrder = 30; // default FP64 M2L form: matrix cores from this compiled order on
 constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 4 * 400 * 16 B)
 
 // Waves per M2L workgroup, each owning m2l_chunk(PB) consecutive output coefficients: the fewest
@@ -31,9 +32,19 @@ constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 4 * 400 *
 __host__ __device__ constexpr int m2l_waves(int PB) { return (PB + kM2LChunkMax) / kM2LChunkMax; }
 __host__ __device__ constexpr int m2l_chunk(int PB) { return (PB + m2l_waves(PB)) / m2l_waves(PB); }
 
-// M2L operator rows are zero-padded so that every chunk reads in bounds:
-// m2l_waves(PB) * m2l_chunk(PB) + PB entries.
-__host__ __device__ constexpr int m2l_row(int PB) { return m2l_waves(PB) * m2l_chunk(PB) + PB; }
+// Matrix-core FP64 M2L: column blocks of 16 embedded outputs (8 complex coefficients each) and steps
+// of 4 complex source coefficients.
+__host__ __device__ constexpr int mf_ncb(int PB) { return (2 * (PB + 1) + 15) / 16; }
+__host__ __device__ constexpr int mf_nks(int PB) { return (PB + 4) / 4; }
+
+// M2L operator rows are zero-padded so that every reader stays in bounds: the vector kernel's chunks
+// read up to m2l_waves(PB) * m2l_chunk(PB) + PB entries, the matrix-core kernel's padded
+// (output, source) coefficient pairs up to index 8 mf_ncb(PB) + 4 mf_nks(PB) - 2.
+__host__ __device__ constexpr int m2l_row(int PB) {
+    return m2l_waves(PB) * m2l_chunk(PB) + PB > 8 * mf_ncb(PB) + 4 * mf_nks(PB) - 1
+               ? m2l_waves(PB) * m2l_chunk(PB) + PB
+               : 8 * mf_ncb(PB) + 4 * mf_nks(PB) - 1;
+}
 
 void set_error(const char *fmt, ...);
 
@@ -194,6 +205,8 @@ struct Sched {
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     bool m2l_fp32 = false;          // FMMHP_FLAG_M2L_FP32: upper-source M2L on the FP32 matrix cores
+    int m2l_form = 0;               // FP64 M2L of upper sources: 0 by order (matrix cores for p >= 30),
+                                    // 1 vector ALUs (k_m2l), 2 matrix cores (k_m2l_mf)
     float *Bf32 = nullptr;          // [kNumSlots][KP][NP] embedded scaled operators (FP32 M2L)
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)
     cplx *TimgH = nullptr;          // [blocks][kNumImgSlots][m2l_row(PB)]

@@ -179,7 +179,7 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
         st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &bo, s, &plan);
         if (st == FMMHP_OK) {
             constexpr int kShapes = 6, kRounds = 3;
-            static const int shapes[kShapes][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}, {3, 2}, {3, 4}};
+            static const int shapes[kShapes][2] = {{1, 2}, {1, 4}, {2, 4}, {2, 8}, {4, 4}, {4, 8}};
             const int def_walk = plan->sched.near_walk, def_groups = (int)(plan->sched.near_blocks / plan->sched.cus);
             double t[kShapes][kRounds];
             for (int r = 0; r < kRounds && st == FMMHP_OK; ++r)
@@ -203,6 +203,35 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
             }
             (void)fmmhp_plan_destroy(plan);
         }
+    }
+    // FP64 M2L form: the other of the vector-ALU and matrix-core forms on the chosen plan and launch
+    // shape (the same sums in another order), kept when it is more than 2% faster
+    if (st == FMMHP_OK && best_ms < INFINITY) {
+        fmmhp_opts of = bo;
+        fmmhp_plan_t plan = nullptr;
+        st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &bo, s, &plan);
+        if (st == FMMHP_OK) {
+            // the form the chosen plan uses
+            const bool mf = (bo.flags & FMMHP_FLAG_M2L_MFMA) ||
+                            (!(bo.flags & FMMHP_FLAG_M2L_VECTOR) && plan->sched.PB >= kM2LMfmaOrder);
+            (void)fmmhp_plan_destroy(plan);
+            plan = nullptr;
+            of.flags = (bo.flags & ~(FMMHP_FLAG_M2L_VECTOR | FMMHP_FLAG_M2L_MFMA)) |
+                       (mf ? FMMHP_FLAG_M2L_VECTOR : FMMHP_FLAG_M2L_MFMA);
+            st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &of, s, &plan);
+        }
+        if (st == FMMHP_OK) {
+            double t[3];
+            for (int r = 0; r < 3 && st == FMMHP_OK; ++r) st = mean_ms(plan, n_vec, qv, phi, e0, e1, s, &t[r]);
+            if (st == FMMHP_OK) {
+                std::sort(t, t + 3);
+                if (t[1] < 0.98 * best_ms) {
+                    bo = of;
+                    best_ms = t[1];
+                }
+            }
+        }
+        if (plan) (void)fmmhp_plan_destroy(plan);
     }
     // M2L form: the FP32 matrix-core M2L (FMMHP_FLAG_M2L_FP32) on the chosen plan and launch shape, kept
     // when its error against the direct sum still meets the tolerance and it is more than 2% faster

@@ -51,7 +51,8 @@ def test_plan_create_validation():
                                    ctypes.byref(h)) == st
     # options
     for o in (F.Opts(0, 40, 0, 0), F.Opts(41, 40, 0, 0), F.Opts(20, 0, 0, 0), F.Opts(20, 40, 31, 0),
-              F.Opts(20, 40, -1, 0), F.Opts(20, 40, 0, 32), F.Opts(20, 40, 0, 12), F.Opts(20, 40, 0, 0, 4, 0),
+              F.Opts(20, 40, -1, 0), F.Opts(20, 40, 0, 128), F.Opts(20, 40, 0, 12), F.Opts(20, 40, 0, 96),
+              F.Opts(20, 40, 0, 0, 5, 0),
               F.Opts(20, 40, 0, 0, -1, 0),
               F.Opts(20, 40, 0, 0, 0, 17), F.Opts(20, 40, 0, 0, 1, -2)):
         assert L.fmmhp_plan_create(10, fake, fake, None, None, 1.0, 0.0, ctypes.byref(o), None,

@@ -1,8 +1,9 @@
 """GPU checks of the near-field launch shapes (fmmhp_opts.near_walk, near_groups): every shape
 computes the same sums (only the order of additions differs), for the potential, several charge
 vectors at once and the adjoint; the defaults depend on p; the autotuner returns a valid shape.
-Walk 3 (symmetric leaf pairs) is also checked on leaves of more than 64 points, forests, separate
-targets, the Dirichlet and Neumann kernels, coincident points, and two evaluations in a row.
+Walks 3 and 4 (symmetric leaf pairs; walk 4 with the pairs blocked in registers) are also checked on
+leaves of more than 64 points, forests, separate targets, the Dirichlet and Neumann kernels,
+coincident points, and two evaluations in a row.
 """
 import numpy as np
 import pytest
@@ -13,7 +14,7 @@ from oracle import direct as D
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-SHAPES = [(1, 1), (1, 2), (1, 16), (2, 4), (2, 8), (3, 1), (3, 2), (3, 16), (0, 0)]
+SHAPES = [(1, 1), (1, 2), (1, 16), (2, 4), (2, 8), (3, 1), (3, 2), (3, 16), (4, 1), (4, 2), (4, 16), (0, 0)]
 
 
 def _t(a):
@@ -59,13 +60,13 @@ def test_shapes_agree_multivector_and_adjoint():
     rng = np.random.default_rng(1)
     g = rng.standard_normal(x.size) + 1j * rng.standard_normal(x.size)
     res = {}
-    for w, gr in [(1, 2), (2, 4), (3, 2)]:
+    for w, gr in [(1, 2), (2, 4), (3, 2), (4, 2)]:
         plan = F.HalfPlaneFMM(_t(x), _t(y), 2.0, p=20, leaf_size=24, near_walk=w, near_groups=gr)
         phi = plan(_t(q)).cpu().numpy()
         b = plan.backward(_t(q[0]), _t(g))
         res[w] = (phi, {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in b.items()})
         plan.close()
-    for w in (2, 3):
+    for w in (2, 3, 4):
         for v in range(9):
             assert D.rel_l2(res[1][0][v], res[w][0][v]) < 1e-13, (w, v)
         for k in ("q", "x", "y"):
@@ -86,7 +87,7 @@ def test_tune_returns_a_shape():
     x, y, q = _problem(20000, 5)
     r = F.tune(_t(x), _t(y), _t(q[0]), 1.0, tol=1e-8, leaf_sizes=[24, 40])
     print("tune:", r, flush=True)
-    assert r["near_walk"] in (1, 2, 3) and 1 <= r["near_groups"] <= 16
+    assert r["near_walk"] in (1, 2, 3, 4) and 1 <= r["near_groups"] <= 16
     plan = F.HalfPlaneFMM(_t(x), _t(y), 1.0, p=r["p"], leaf_size=r["leaf_size"], near_walk=r["near_walk"],
                           near_groups=r["near_groups"])
     info = plan.info()
@@ -131,9 +132,10 @@ def test_xcd_chunk_mapping_covers_every_target(n, groups):
     assert diff.max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("walk", [3, 4])
 @pytest.mark.parametrize("bc", ["robin", "dirichlet", "neumann"])
-def test_symmetric_walk_large_leaves_and_conditions(bc):
-    """Walk 3 with leaves of up to 96 points (chunks of 64 targets share one lane layout), with
+def test_symmetric_walk_large_leaves_and_conditions(bc, walk):
+    """Walks 3 and 4 with leaves of up to 96 points (chunks of 64 targets share one lane layout), with
     max_level 4 (leaves far above leaf_size, many coincident-free pairs), and the three boundary
     conditions (image sign), against the oracle and walk 1."""
     x, y, q = _problem(8000, 23, nvec=2)
@@ -141,21 +143,22 @@ def test_symmetric_walk_large_leaves_and_conditions(bc):
     ref = D.potential(x, y, q[1], Z, workers=8, bc=bc)
     for leaf, lmax in ((96, 0), (32, 4)):
         res = {}
-        for w in (1, 3):
+        for w in (1, walk):
             plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=20, leaf_size=leaf, max_level=lmax, near_walk=w,
                                   near_groups=2, bc=bc)
             res[w] = plan(_t(q)).cpu().numpy()
             plan(_t(q))  # a second evaluation reuses the partial sums' workspace
             res[w] = plan(_t(q)).cpu().numpy()
             plan.close()
-        err = D.rel_l2(res[3][1], ref)
-        print(f"{bc} leaf {leaf} max_level {lmax}: walk 3 rel-l2 vs oracle {err:.2e}, vs walk 1 "
-              f"{D.rel_l2(res[3], res[1]):.2e}", flush=True)
-        assert err < 1e-9 and D.rel_l2(res[3], res[1]) < 1e-13
+        err = D.rel_l2(res[walk][1], ref)
+        print(f"{bc} leaf {leaf} max_level {lmax}: walk {walk} rel-l2 vs oracle {err:.2e}, vs walk 1 "
+              f"{D.rel_l2(res[walk], res[1]):.2e}", flush=True)
+        assert err < 1e-9 and D.rel_l2(res[walk], res[1]) < 1e-13
 
 
-def test_symmetric_walk_forest_and_targets():
-    """Walk 3 on a forest (pairs never cross instances) and on a plan with separate targets (the
+@pytest.mark.parametrize("walk", [3, 4])
+def test_symmetric_walk_forest_and_targets(walk):
+    """Walks 3 and 4 on a forest (pairs never cross instances) and on a plan with separate targets (the
     target-only points carry no charge) against walk 1 and the oracle."""
     sizes = [1800, 600, 2500]
     imps = [0.5, 3.0, 1.0 + 0.4j]
@@ -168,23 +171,23 @@ def test_symmetric_walk_forest_and_targets():
     off = np.concatenate([[0], np.cumsum(sizes)])
     X, Y, Q = np.concatenate(xs), np.concatenate(ys), np.concatenate(qs, axis=1)
     res = {}
-    for w in (1, 3):
+    for w in (1, walk):
         plan = F.HalfPlaneFMM.batched(_t(X), _t(Y), off, imps, p=20, leaf_size=24, near_walk=w, near_groups=2)
         res[w] = plan(_t(Q)).cpu().numpy()
         plan.close()
-    assert D.rel_l2(res[3], res[1]) < 1e-13
+    assert D.rel_l2(res[walk], res[1]) < 1e-13
     for k in range(3):
         ref = D.potential(xs[k], ys[k], qs[k][5], imps[k], workers=8)
-        assert D.rel_l2(res[3][5, off[k]:off[k + 1]], ref) < 1e-10, k
+        assert D.rel_l2(res[walk][5, off[k]:off[k + 1]], ref) < 1e-10, k
     x, y, q = _problem(3000, 51)
     rng = np.random.default_rng(2)
     xt, yt = rng.uniform(0.0, 1.0, 900), rng.uniform(0.0, 0.3, 900)
     yt[:30] = 0.0
     out = {}
-    for w in (1, 3):
+    for w in (1, walk):
         plan = F.HalfPlaneFMM.with_targets(_t(x), _t(y), _t(xt), _t(yt), 1.0, p=20, leaf_size=16, near_walk=w,
                                            near_groups=2)
         out[w] = plan(_t(q[0])).cpu().numpy()
         plan.close()
     ref = D.potential(x, y, q[0], 1.0, xt=xt, yt=yt, workers=8)
-    assert D.rel_l2(out[3], ref) < 1e-10 and D.rel_l2(out[3], out[1]) < 1e-13
+    assert D.rel_l2(out[walk], ref) < 1e-10 and D.rel_l2(out[walk], out[1]) < 1e-13

@@ -1,0 +1,131 @@
+"""GPU parity of the FP64 matrix-core M2L of upper sources (v_mfma_f64_16x16x4f64; the default form
+from p = 30, forced by FMMHP_FLAG_M2L_MFMA below) against the CPU oracle's direct sum and
+against the vector-ALU M2L (FMMHP_FLAG_M2L_VECTOR), which computes the same sums of
+eq. (truncatedM2Lcoef) and the log-kernel M2L in another order.
+
+Cases: every compiled truncation order (p = 5 .. 40: one to six column blocks, partial last
+coefficient steps), real and complex impedances, an adaptive point set whose tiles are partly
+filled and whose lanes lack sources at some slots, several charge vectors in one pass, a forest of
+instances with different impedances, the Dirichlet and Neumann kernels, and a duplicate-heavy set.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2507_21913_amd as F
+import workloads
+from oracle import direct as D
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def _band(n, seed):
+    """Half the points in a band near y = 0 (adaptive leaves, image entries), the rest uniform."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    x = np.concatenate([rng.uniform(0.0, 1.0, m), rng.uniform(0.0, 1.0, n - m)])
+    y = np.concatenate([rng.uniform(1e-3, 0.05, m), rng.uniform(1e-3, 1.0, n - m)])
+    return x, y, rng.standard_normal(n)
+
+
+def _pair(x, y, q, Z, **kw):
+    """(matrix-core result, vector-ALU result) of one evaluation."""
+    out = []
+    for form in ("mfma", "vector"):
+        plan = F.HalfPlaneFMM(_t(x), _t(y), Z, m2l_form=form, **kw)
+        out.append(plan(_t(q)).cpu().numpy())
+        plan.close()
+    return out
+
+
+@pytest.mark.parametrize("p", [5, 10, 15, 20, 25, 30, 35, 40])
+def test_every_order_matches_vector_path(p):
+    x, y, q = _band(6000, 100 + p)
+    mf, vec = _pair(x, y, q, 1.0 + 0.5j, p=p, leaf_size=16)
+    err = D.rel_l2(mf, vec)
+    print(f"p={p}: matrix-core vs vector M2L rel-l2 {err:.2e}", flush=True)
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("Z", [1.0, 1.0 + 0.5j, 2.0, 0.3 + 1.1j])
+def test_matches_oracle_at_p30(Z):
+    x, y, q = _band(8000, 7)
+    plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=30, leaf_size=20)  # the matrix-core form by default
+    got = plan(_t(q)).cpu().numpy()
+    plan.close()
+    ref = D.potential(x, y, q, Z, workers=8)
+    err = D.rel_l2(got, ref)
+    print(f"Z={Z}: rel-l2 vs oracle {err:.2e}", flush=True)
+    assert err < 1e-10
+
+
+def test_plain_small_p20_vs_oracle():
+    w = workloads.plain_small()
+    plan = F.HalfPlaneFMM(_t(w.x), _t(w.y), w.impedance, p=20, leaf_size=40, m2l_form="mfma")
+    got = plan(_t(w.q[0])).cpu().numpy()
+    plan.close()
+    ref = D.potential(w.x, w.y, w.q[0], w.impedance, workers=8)
+    assert D.rel_l2(got, ref) < 1e-10
+
+
+def test_several_vectors_equal_single_vector():
+    x, y, _ = _band(5000, 3)
+    q = np.random.default_rng(4).standard_normal((11, x.size))
+    plan = F.HalfPlaneFMM(_t(x), _t(y), 1.0, p=20, leaf_size=24, m2l_form="mfma")
+    many = plan(_t(q)).cpu().numpy()
+    one = np.stack([plan(_t(q[v])).cpu().numpy() for v in (0, 7, 10)])
+    plan.close()
+    # the same kernels per vector: bitwise equal
+    assert np.array_equal(many[[0, 7, 10]], one)
+    mf, vec = _pair(x, y, q, 1.0, p=20, leaf_size=24)
+    assert D.rel_l2(mf, vec) < 1e-13
+
+
+def test_forest_matches_vector_path():
+    rng = np.random.default_rng(9)
+    sizes = [1500, 40, 3000, 700]
+    xs, ys = [], []
+    for n in sizes:
+        xs.append(rng.uniform(0, 1, n))
+        ys.append(rng.uniform(0.01, 1.01, n))
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    off = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+    Zs = [0.5, 3.0, 1.0 + 0.5j, 8.0]
+    q = rng.standard_normal((3, x.size))
+    out = []
+    for form in ("mfma", "vector"):
+        plan = F.HalfPlaneFMM.batched(_t(x), _t(y), off, Zs, p=20, leaf_size=20, m2l_form=form)
+        out.append(plan(_t(q)).cpu().numpy())
+        plan.close()
+    assert D.rel_l2(out[0], out[1]) < 1e-13
+    # one instance against the oracle
+    k = 2
+    a, b = off[k], off[k + 1]
+    ref = D.potential(x[a:b], y[a:b], q[1, a:b], Zs[k], workers=8)
+    assert D.rel_l2(out[0][1, a:b], ref) < 1e-10
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+def test_boundary_conditions_match_vector_path(bc):
+    x, y, q = _band(4000, 21)
+    mf, vec = _pair(x, y, q, 1.0, p=20, leaf_size=16, bc=bc)
+    assert D.rel_l2(mf, vec) < 1e-13
+
+
+def test_coincident_points_and_tiny_sets():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 1, 3000)
+    y = rng.uniform(1e-3, 1, 3000)
+    x[1000:2000] = x[0:1000]
+    y[1000:2000] = y[0:1000]
+    q = rng.standard_normal(3000)
+    mf, vec = _pair(x, y, q, 1.0 + 0.5j, p=25, leaf_size=8)
+    assert D.rel_l2(mf, vec) < 1e-13
+    for n in (1, 2, 65):
+        mf, vec = _pair(x[:n], y[:n], q[:n], 1.0, p=20, leaf_size=1)
+        assert D.rel_l2(mf, vec) < 1e-13 or np.linalg.norm(vec) == 0.0
