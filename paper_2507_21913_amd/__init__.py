@@ -457,7 +457,7 @@ class HalfPlaneFMM:
 
     @classmethod
     def batched(cls, x, y, offsets, impedances, p=20, leaf_size=40, max_level=0, graph=False,
-                m2l_fp32=False, near_walk=0, near_groups=0, bc="robin", m2l_form=None):
+                m2l_fp32=False, near_walk=0, near_groups=0, bc="robin", m2l_form=None, serial=False):
         """A forest plan over n_inst independent instances: points offsets[k]..offsets[k+1]-1 of
         (x, y) form instance k with impedance impedances[k].  Evaluation takes charges for all
         points (instance after instance) and runs every instance in the same launches."""
@@ -477,7 +477,7 @@ class HalfPlaneFMM:
             raise ValueError("one impedance per instance")
         opts = Opts(int(p), int(leaf_size), int(max_level),
                     (FLAG_GRAPH if graph else 0) | (FLAG_M2L_FP32 if m2l_fp32 else 0) | _bc_flag(bc)
-                    | _m2l_flag(m2l_form),
+                    | _m2l_flag(m2l_form) | (FLAG_SERIAL if serial else 0),
                     int(near_walk), int(near_groups))
         with torch.cuda.device(self.device):
             self._plan = fmmhp_batch_plan_create(self.n_inst, offsets, x.data_ptr(), y.data_ptr(), imps,

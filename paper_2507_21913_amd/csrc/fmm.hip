@@ -331,8 +331,28 @@ __device__ __forceinline__ int sub_level_of(const SubShared &ss, int nlev, int i
     return k;
 }
 
+// M2M of the parents [c.x, c.y) of one level for each chunk c (at most kM2MParents parents): the
+// subtrees too large for LDS, one launch per level, deepest first.
 template <int PB>
-__global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restrict__ rng, int ld, int nbox,
+__global__ __launch_bounds__(256) void k_m2m_chunks(const int2 *__restrict__ chunks, int nbox,
+                                                    const int32_t *__restrict__ leaf,
+                                                    const int32_t *__restrict__ child_first,
+                                                    const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
+                                                    const int32_t *__restrict__ by, const cplx *__restrict__ E,
+                                                    cplx *__restrict__ W) {
+    __builtin_amdgcn_s_setprio(3);  // upward pass: the critical path
+    __shared__ M2MShared<PB> sh;
+    extern __shared__ cplx dyn_lds[];  // (PB + 1) x 4 kM2MParents
+    W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
+    const int2 c = chunks[blockIdx.x];
+    m2m_parents<PB>(sh, dyn_lds, 4 * kM2MParents, c.x, c.y, nbox, leaf, child_first, nchild, bx, by, W);
+}
+
+// skip_big: a subtree whose expansions do not fit the block's LDS rows is left to k_m2m_chunks
+// (otherwise the block runs it level by level itself).
+template <int PB>
+__global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restrict__ rng, int ld, int skip_big, int nbox,
                                                  const int32_t *__restrict__ leaf,
                                                  const int32_t *__restrict__ child_first,
                                                  const int32_t *__restrict__ nchild, const int32_t *__restrict__ bx,
@@ -349,6 +369,7 @@ __global__ __launch_bounds__(256) void k_m2m_sub(int nlev, const int2 *__restric
     sub_ranges(ss, R, nlev);
     const int tot = ss.base[nlev];
     if (tot > ld) {
+        if (skip_big) return;
         for (int k = nlev - 2; k >= 0; --k) {
             const int2 r = R[k];
             for (int p0 = r.x; p0 < r.y; p0 += kM2MParents)
@@ -891,55 +912,85 @@ __global__ __launch_bounds__(128 * (m2l32_np(PB) / 16)) void k_m2l_f32(M2L32Args
 }
 
 // Image V entries (target boxes in the two rows nearest y = 0 at each level): log M2L of the image
-// box plus the reaction M2L; kImgSplit consecutive lanes per (target box, output coefficient), each
-// summing every kImgSplit-th V entry, combined by a butterfly; adds to the locals written by k_m2l.
-constexpr int kImgSplit = 4;
-
-template <int PB>
-__global__ __launch_bounds__(256) void k_m2l_img(int nib, const int32_t *__restrict__ ibox, int nbox, int nloc,
-                                                 const int32_t *__restrict__ ibase,
-                                                 const int32_t *__restrict__ vimg_off,
-                                                 const int32_t *__restrict__ vimg_ent, const cplx *__restrict__ TH,
-                                                 const cplx *__restrict__ TG, const cplx *__restrict__ Limg,
-                                                 const double *__restrict__ logside, double isg,
-                                                 const cplx *__restrict__ W, cplx *__restrict__ Lam) {
+// box plus the reaction M2L, added to the locals written by k_m2l.  One 64-lane block per target box
+// and all vectors of the pass: lane (g, n) computes output coefficient n from every G-th V entry
+// (G = 64 / (p + 1) groups), reading the entry's operator row coalesced across n; the groups' sums
+// are joined through LDS.
+template <int PB, int NV>
+__global__ __launch_bounds__(64) void k_m2l_img(const int32_t *__restrict__ ibox, int nbox, int nloc,
+                                                const int32_t *__restrict__ ibase,
+                                                const int32_t *__restrict__ vimg_off,
+                                                const int32_t *__restrict__ vimg_ent, const cplx *__restrict__ TH,
+                                                const cplx *__restrict__ TG, const cplx *__restrict__ Limg,
+                                                const double *__restrict__ logside, double isg,
+                                                const cplx *__restrict__ W, cplx *__restrict__ Lam) {
     constexpr int NTP = m2l_row(PB);
-    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = gt / kImgSplit, part = gt % kImgSplit;
-    const bool ok = t < nib * (PB + 1);  // no early exit: every lane of a group joins the butterfly
-    W += (int64_t)blockIdx.y * (PB + 1) * nbox;  // charge vector
-    Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;
-    const int b = ok ? ibox[t % nib] : 0, n = ok ? t / nib : 0;
-    cplx aH = mk(0.0, 0.0), aG = mk(0.0, 0.0), a0 = mk(0.0, 0.0);
-    if (ok) {
-        const int l = ibase[b];  // table block of the box's (instance, level)
-        const double ll = logside[b] * kInv4Pi;
-        for (int e = vimg_off[b] + part; e < vimg_off[b + 1]; e += kImgSplit) {
+    constexpr int P1 = PB + 1;
+    constexpr int G = 64 / P1;
+    static_assert(G >= 1, "one group of p + 1 lanes fits a wave");
+    __shared__ cplx red[G > 1 ? G - 1 : 1][NV][2][P1];
+    const int b = ibox[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int g = lane / P1, n = lane - g * P1;
+    const int l = ibase[b];  // table block of the box's (instance, level)
+    const double ll = logside[b] * kInv4Pi;
+    cplx aH[NV], aG[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) aH[v] = aG[v] = mk(0.0, 0.0);
+    if (g < G) {
+        for (int e = vimg_off[b] + g; e < vimg_off[b + 1]; e += G) {
             const int code = vimg_ent[e];
             const int src = code >> 5, is = code & 31;
             const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
             const cplx *tg = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
-#pragma unroll
+            // all loads of an entry in flight for one vector; fewer registers with several
+#pragma unroll(NV == 1 ? 8 : 2)
             for (int m = 0; m <= PB; ++m) {
-                const cplx wm = conj(W[(int64_t)m * nbox + src]);
-                cfma(aH, th[m], wm);
-                if (nloc == 2) cfma(aG, tg[m], wm);
+                const cplx t = th[m];
+                const cplx tq = nloc == 2 ? tg[m] : mk(0.0, 0.0);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const cplx wm = conj(W[((int64_t)v * P1 + m) * nbox + src]);
+                    cfma(aH[v], t, wm);
+                    if (nloc == 2) cfma(aG[v], tq, wm);
+                }
             }
-            if (n == 0) cfma(a0, Limg[is] + mk(isg * ll, 0.0), conj(W[src]));
+            if (n == 0) {  // the log term: lambda_0 += (L + log side) conj(w_0), entered with the sign of -a
+                const cplx f = -(Limg[is] + mk(isg * ll, 0.0));
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const cplx w0 = conj(W[(int64_t)v * P1 * nbox + src]);
+                    cfma(aH[v], f, w0);
+                    cfma(aG[v], f, w0);
+                }
+            }
         }
     }
-    cplx r = a0 - aH, rg = a0 - aG;
-    for (int off = 1; off < kImgSplit; off <<= 1) {
-        r.re += __shfl_xor(r.re, off);
-        r.im += __shfl_xor(r.im, off);
-        if (nloc == 2) {
-            rg.re += __shfl_xor(rg.re, off);
-            rg.im += __shfl_xor(rg.im, off);
+    if (G > 1) {
+        if (g >= 1 && g < G) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                red[g - 1][v][0][n] = aH[v];
+                red[g - 1][v][1][n] = aG[v];
+            }
+        }
+        __syncthreads();
+        if (g == 0) {
+            for (int h = 0; h + 1 < G; ++h)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    aH[v] += red[h][v][0][n];
+                    aG[v] += red[h][v][1][n];
+                }
         }
     }
-    if (ok && part == 0) {
-        Lam[(int64_t)n * nbox + b] += r;
-        if (nloc == 2) Lam[(int64_t)(PB + 1) * nbox + (int64_t)n * nbox + b] += rg;
+    if (g == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            cplx *Lv = Lam + (int64_t)v * nloc * P1 * nbox;
+            Lv[(int64_t)n * nbox + b] += -aH[v];
+            if (nloc == 2) Lv[(int64_t)P1 * nbox + (int64_t)n * nbox + b] += -aG[v];
+        }
     }
 }
 
@@ -962,8 +1013,8 @@ __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nrow, cplx *
 // n_j . grad_{r_j} [n! rho^n I_n] = -(1/rho) i conj(nu) K_{n+1} (d_X I_n = i (n+1) I_{n+1},
 // d_Y I_n = -(n+1) I_{n+1}, from eq. (generalintegral)); the same holds for the mirrored G local.
 // ---------------------------------------------------------------------------------------------
-template <int PB, bool DIP>
-__global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst, int nv,
+template <int PB, bool DIP, int NV>
+__global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
                                             int nloc, int loc, const int32_t *__restrict__ xbox, int nbox,
                                             const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
                                             const int32_t *__restrict__ by, const int32_t *__restrict__ first,
@@ -972,16 +1023,20 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                                             const double *__restrict__ ys, const double *__restrict__ qs,
                                             const double2 *__restrict__ nrm, const double *__restrict__ fact,
                                             cplx *__restrict__ Lam) {
+    // lane j of a chunk writes its source point's terms for unit charge (they do not depend on the
+    // charge vector); lane n <= PB then adds sum_j q_j^(v) term_j[n] for every vector v of the pass
     __shared__ cplx contrib[64][PB + 1];
+    __shared__ double sq[64][NV];
     const int b = xbox[blockIdx.x];
-    const int v = blockIdx.y;  // charge vector
     const int lane = threadIdx.x;
     const int l = level[b];
     const Geo g = geo_of(ii, inst[b]);
     const cplx Z = ii[inst[b]].Z;
     const cplx cb = centre_of(g, l, bx[b], by[b]);
     const double rho = 0.5 * side_of(g, l);
-    cplx acc = mk(0.0, 0.0);
+    cplx acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = mk(0.0, 0.0);
     for (int e = xoff[b]; e < xoff[b + 1]; ++e) {
         const int code = xent[e];
         const int c = code >> 1, img = code & 1;
@@ -990,7 +1045,8 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
             const int j = jb + lane;
             cplx *out = contrib[lane];
             if (j < j1) {
-                const double q = qs[(int64_t)j * nv + v];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sq[lane][v] = qs[(int64_t)j * NV + v];
                 const double yj = img ? -ys[j] : ys[j];
                 const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
                 const double sgn = img ? ii[inst[b]].isg : -1.0;  // -(1/4pi) upper, +-(1/4pi) image
@@ -998,17 +1054,17 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                 if (DIP) {
                     // nu d/dd of the charge's local below: (nu / rho) n! sig^(n+1)
                     const double2 nj = nrm[j];
-                    cplx pw = ((sgn * kInv4Pi * q / rho) * mk(nj.x, img ? -nj.y : nj.y)) * sig;
+                    cplx pw = ((sgn * kInv4Pi / rho) * mk(nj.x, img ? -nj.y : nj.y)) * sig;
                     for (int n = 0; n <= PB; ++n) {
                         out[n] = fact[n] * pw;
                         pw = pw * sig;
                     }
                 } else {
                     // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
-                    out[0] = (sgn * kInv4Pi * q) * clog_(-d);
+                    out[0] = (sgn * kInv4Pi) * clog_(-d);
                     cplx pw = sig;
                     for (int n = 1; n <= PB; ++n) {
-                        out[n] = (-sgn * kInv4Pi * q * fact[n - 1]) * pw;
+                        out[n] = (-sgn * kInv4Pi * fact[n - 1]) * pw;
                         pw = pw * sig;
                     }
                 }
@@ -1024,31 +1080,44 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                     if (DIP) {
                         // lambda_(n-1) += -(mu conj(nu) / rho) i^n K_n, n = 1 .. p + 1
                         const double2 nj = nrm[j];
-                        const cplx cn = (-q / rho) * mk(nj.x, -nj.y);
+                        const cplx cn = (-1.0 / rho) * mk(nj.x, -nj.y);
                         for (int n = 1; n <= PB + 1; ++n) {
                             F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
                             K = F * kInv2Pi + zr * K;
                             out[n - 1] += cn * mul_ipow(loc == 0 ? K : conj(K), n);
                         }
                     } else {
-                        out[0] += q * (loc == 0 ? K : conj(K));
+                        out[0] += loc == 0 ? K : conj(K);
                         for (int n = 1; n <= PB; ++n) {
                             F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
                             K = F * kInv2Pi + zr * K;
-                            out[n] += q * mul_ipow(loc == 0 ? K : conj(K), n);
+                            out[n] += mul_ipow(loc == 0 ? K : conj(K), n);
                         }
                     }
                 }
             } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sq[lane][v] = 0.0;
                 for (int n = 0; n <= PB; ++n) out[n] = mk(0.0, 0.0);
             }
             __syncthreads();
-            if (lane <= PB)
-                for (int k = 0; k < 64; ++k) acc += contrib[k][lane];
+            if (lane <= PB) {
+                const int kn = j1 - jb < 64 ? j1 - jb : 64;
+#pragma unroll 2
+                for (int k = 0; k < kn; ++k) {
+                    const cplx t = contrib[k][lane];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] += sq[k][v] * t;
+                }
+            }
             __syncthreads();
         }
     }
-    if (lane <= PB) Lam[((int64_t)v * nloc + loc) * (PB + 1) * nbox + (int64_t)lane * nbox + b] += acc;
+    if (lane <= PB) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            Lam[((int64_t)v * nloc + loc) * (PB + 1) * nbox + (int64_t)lane * nbox + b] += acc[v];
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1118,8 +1187,25 @@ __global__ __launch_bounds__(256) void k_l2l(int lo, int nb, int nbox, int nloc,
                      Lam);
 }
 
+// L2L of the children [c.x, c.y) of one level for each chunk c (at most kL2LChildren children): the
+// subtrees too large for LDS, one launch per level, top level first.
 template <int PB>
-__global__ __launch_bounds__(256) void k_l2l_sub(int nlev, const int2 *__restrict__ rng, int ld, int nbox, int nloc,
+__global__ __launch_bounds__(256) void k_l2l_chunks(const int2 *__restrict__ chunks, int nbox, int nloc,
+                                                    const int32_t *__restrict__ parent, const int32_t *__restrict__ bx,
+                                                    const int32_t *__restrict__ by, const cplx *__restrict__ E,
+                                                    cplx *__restrict__ Lam) {
+    __shared__ L2LShared<PB> sh;
+    extern __shared__ cplx dyn_lds[];  // (PB + 1) x kL2LChildren
+    Lam += (int64_t)blockIdx.y * nloc * (PB + 1) * nbox;  // charge vector
+    for (int k = threadIdx.x; k < 4 * (PB + 1); k += blockDim.x) sh.sE[k] = E[k];
+    const int2 c = chunks[blockIdx.x];
+    l2l_children<PB>(sh, dyn_lds, kL2LChildren, c.x, c.y - c.x, nbox, nloc, parent, bx, by, Lam);
+}
+
+// skip_big: a subtree whose locals do not fit the block's LDS rows is left to k_l2l_chunks.
+template <int PB>
+__global__ __launch_bounds__(256) void k_l2l_sub(int nlev, const int2 *__restrict__ rng, int ld, int skip_big, int nbox,
+                                                 int nloc,
                                                  const int32_t *__restrict__ parent, const int32_t *__restrict__ bx,
                                                  const int32_t *__restrict__ by, const cplx *__restrict__ E,
                                                  cplx *__restrict__ Lam) {
@@ -1133,6 +1219,7 @@ __global__ __launch_bounds__(256) void k_l2l_sub(int nlev, const int2 *__restric
     sub_ranges(ss, R, nlev);
     const int tot = ss.base[nlev];
     if (tot * nloc > ld) {
+        if (skip_big) return;
         for (int k = 1; k < nlev; ++k) {
             const int2 r = R[k];
             for (int c0 = r.x; c0 < r.y; c0 += kL2LChildren)
@@ -1920,19 +2007,22 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
 // W list for the targets whose leaf has one: multipoles of smaller non-adjacent boxes evaluated
 // at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to the near-field
 // sums (before k_leaf reads them).
-template <int PB, int MODE>
+template <int PB, int MODE, int NV>
 __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n_wpts) return;
-    const int v = blockIdx.y;  // charge vector
-    const cplx *__restrict__ Wv = a.W + (int64_t)v * (PB + 1) * a.nbox;
+    // one thread per target, every charge vector of the pass: the geometric factors (powers of
+    // tau, the logarithm, the reaction integrals) are computed once for all vectors
+    const int64_t vstride = (int64_t)(PB + 1) * a.nbox;
     const int64_t i = a.wpts[t];
     const int b = a.leaf_of[i];
     const Geo g = geo_of(a.ii, a.inst[b]);
     const cplx Zk = a.ii[a.inst[b]].Z;
     const double x = a.xs[i], y = a.ys[i];
     const cplx z = mk(x, y);
-    cplx H = mk(0.0, 0.0), G = mk(0.0, 0.0), Hd = mk(0.0, 0.0), Gd = mk(0.0, 0.0);
+    cplx H[NV], G[NV], Hd[NV], Gd[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) H[v] = G[v] = Hd[v] = Gd[v] = mk(0.0, 0.0);
     for (int e = a.woff[b]; e < a.woff[b + 1]; ++e) {
         const int code = a.went[e];
         const int d = code >> 1, img = code & 1;
@@ -1945,26 +2035,37 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
         const cplx tau = -rd * idz;
         // u = w0 log(z - c) - sum_k (k-1)! tau^k w_k,  u' = (w0 + sum_k k! tau^k w_k) / (z - c)
         // (conjugated w for the image box)
-        cplx w0 = Wv[d];
-        if (img) w0 = conj(w0);
-        cplx u = mk(0.0, 0.0), ud = w0;
-        if (has_phi(MODE)) u = w0 * clog_(dz);
-        cplx pw = tau;
+        const cplx lg = has_phi(MODE) ? clog_(dz) : mk(0.0, 0.0);
+        cplx u[NV], ud[NV];
 #pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            cplx w0 = a.W[(int64_t)v * vstride + d];
+            if (img) w0 = conj(w0);
+            u[v] = has_phi(MODE) ? w0 * lg : mk(0.0, 0.0);
+            ud[v] = w0;
+        }
+        cplx pw = tau;
         for (int k = 1; k <= PB; ++k) {
-            cplx wk = Wv[(int64_t)k * a.nbox + d];
-            if (img) wk = conj(wk);
-            const cplx pk = pw * wk;
-            if (has_phi(MODE)) u -= a.fact[k - 1] * pk;
-            if (has_grad(MODE)) ud += a.fact[k] * pk;
+            const double fk1 = a.fact[k - 1], fk = a.fact[k];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                cplx wk = a.W[(int64_t)v * vstride + (int64_t)k * a.nbox + d];
+                if (img) wk = conj(wk);
+                const cplx pk = pw * wk;
+                if (has_phi(MODE)) u[v] -= fk1 * pk;
+                if (has_grad(MODE)) ud[v] += fk * pk;
+            }
             pw = pw * tau;
         }
         const double sgn = (img ? a.ii[a.inst[b]].isg : -1.0) * kInv4Pi;
-        H += sgn * u;
-        G += sgn * u;
-        ud = sgn * (ud * idz);
-        Hd += ud;
-        Gd += ud;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            H[v] += sgn * u[v];
+            G[v] += sgn * u[v];
+            const cplx udv = sgn * (ud[v] * idz);
+            Hd[v] += udv;
+            Gd[v] += udv;
+        }
         if (img && a.ii[a.inst[b]].react) {
             // reaction ME (eq. (truncatedME)) of the image box: sum_n alpha_n I_n(x - x'_c, y - y'_c),
             // alpha_n = rho^n (-i)^n conj(mu_n) = i^n n! rho^n conj(w_n); with K_n = n! rho^n I_n its
@@ -1976,49 +2077,62 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
                 const cplx zr = rd * Zk;
                 cplx K = reaction_I0_general(Xs, Y, Zk);
                 cplx F = mk(1.0, 0.0);
-                cplx acc = mk(0.0, 0.0), accd = mk(0.0, 0.0);
-                if (has_phi(MODE)) acc = (pass == 0 ? K : conj(K)) * conj(Wv[d]);
-                constexpr int NTOP = has_grad(MODE) ? PB + 1 : PB;
+                cplx acc[NV], accd[NV];
+                const cplx K0 = pass == 0 ? K : conj(K);
 #pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    acc[v] = has_phi(MODE) ? K0 * conj(a.W[(int64_t)v * vstride + d]) : mk(0.0, 0.0);
+                    accd[v] = mk(0.0, 0.0);
+                }
+                constexpr int NTOP = has_grad(MODE) ? PB + 1 : PB;
                 for (int n = 1; n <= NTOP; ++n) {
                     F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
                     K = F * kInv2Pi + zr * K;
                     const cplx Kn = mul_ipow(pass == 0 ? K : conj(K), n);
-                    if (has_phi(MODE) && n <= PB) acc += Kn * conj(Wv[(int64_t)n * a.nbox + d]);
-                    if (has_grad(MODE)) accd += Kn * conj(Wv[(int64_t)(n - 1) * a.nbox + d]);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const cplx *Wv = a.W + (int64_t)v * vstride;
+                        if (has_phi(MODE) && n <= PB) acc[v] += Kn * conj(Wv[(int64_t)n * a.nbox + d]);
+                        if (has_grad(MODE)) accd[v] += Kn * conj(Wv[(int64_t)(n - 1) * a.nbox + d]);
+                    }
                 }
-                accd = accd * (1.0 / rd);
-                if (pass == 0) {
-                    H += acc;
-                    Hd += accd;
-                } else {
-                    G += acc;
-                    Gd += accd;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (pass == 0) {
+                        H[v] += acc[v];
+                        Hd[v] += accd[v] * (1.0 / rd);
+                    } else {
+                        G[v] += acc[v];
+                        Gd[v] += accd[v] * (1.0 / rd);
+                    }
                 }
             }
         }
     }
     // into the near-field sums of the target (sorted order), which k_leaf adds to the far field
-    if (has_phi(MODE)) {
-        double2 *nr = a.near + (int64_t)v * a.n + i;
-        double2 hv = *nr;
-        if (a.nloc == 1) {
-            hv.x += 2.0 * H.re;
-        } else {
-            const cplx c = H + conj(G);
-            hv.x += c.re;
-            hv.y += c.im;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (has_phi(MODE)) {
+            double2 *nr = a.near + (int64_t)v * a.n + i;
+            double2 hv = *nr;
+            if (a.nloc == 1) {
+                hv.x += 2.0 * H[v].re;
+            } else {
+                const cplx c = H[v] + conj(G[v]);
+                hv.x += c.re;
+                hv.y += c.im;
+            }
+            *nr = hv;
         }
-        *nr = hv;
-    }
-    if (has_grad(MODE)) {
-        cplx *gx = a.near_gx + (int64_t)v * a.n + i, *gy = a.near_gy + (int64_t)v * a.n + i;
-        if (a.nloc == 1) {
-            *gx += mk(2.0 * Hd.re, 0.0);
-            *gy += mk(-2.0 * Hd.im, 0.0);
-        } else {
-            *gx += Hd + conj(Gd);
-            *gy += mul_ipow(Hd - conj(Gd), 1);
+        if (has_grad(MODE)) {
+            cplx *gx = a.near_gx + (int64_t)v * a.n + i, *gy = a.near_gy + (int64_t)v * a.n + i;
+            if (a.nloc == 1) {
+                *gx += mk(2.0 * Hd[v].re, 0.0);
+                *gy += mk(-2.0 * Hd[v].im, 0.0);
+            } else {
+                *gx += Hd[v] + conj(Gd[v]);
+                *gy += mul_ipow(Hd[v] - conj(Gd[v]), 1);
+            }
         }
     }
 }
@@ -2559,7 +2673,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         // launch per level instead
         std::vector<int2> rng;
         int maxtot = 0;
-        for (int l = 3; l < T.depth; ++l) {
+        // a forest runs one launch per level: its many small subtrees, each set up once per charge
+        // vector, make the subtree blocks slower than the plain level launches there
+        for (int l = 3; l < T.depth && T.n_inst == 1; ++l) {
             if (T.lev_start[l + 1] - T.lev_start[l] < 4 * std::max(1, cus)) continue;
             int64_t nonres = 0;
             const int mt = subtree_ranges(l, T.depth - l + 1, rng, cap, &nonres);
@@ -2569,21 +2685,88 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 break;
             }
         }
+        // consecutive subtrees whose boxes together fit the LDS rows run in one block: their box
+        // ranges at each level are contiguous (boxes are ordered by level, instance, Morton prefix),
+        // so a group is handled like one subtree with several roots.  Subtrees larger than the rows
+        // stay alone.  Returns the largest group's box count among those that fit.
+        auto group_subtrees = [&](std::vector<int2> &r, int nlev, int lim, int *ngroups) {
+            const int nr = (int)(r.size() / nlev);
+            std::vector<int2> g;
+            int gmax = 0, i = 0;
+            auto size_of = [&](int k) {
+                int t = 0;
+                for (int l = 0; l < nlev; ++l) t += r[(size_t)k * nlev + l].y - r[(size_t)k * nlev + l].x;
+                return t;
+            };
+            while (i < nr) {
+                int tot = size_of(i), j = i + 1;
+                if (tot <= lim)
+                    for (int t; j < nr && (t = size_of(j)) <= lim && tot + t <= lim; ++j) tot += t;
+                for (int l = 0; l < nlev; ++l) {
+                    int a = 0, b = 0;
+                    for (int k = i; k < j; ++k) {
+                        const int2 q = r[(size_t)k * nlev + l];
+                        if (q.y > q.x) {
+                            if (b == 0) a = q.x;
+                            b = q.y;
+                        }
+                    }
+                    g.push_back(make_int2(a, b));
+                }
+                if (tot <= lim) gmax = std::max(gmax, tot);
+                i = j;
+            }
+            r.swap(g);
+            *ngroups = (int)(r.size() / nlev);
+            return gmax;
+        };
+        S.m2m_ch_lev.assign(T.depth + 2, 0);
+        S.l2l_ch_lev.assign(T.depth + 2, 0);
         if (S.sub_level > 0) {
             const int lc = S.sub_level;
-            S.n_sub = T.lev_start[lc + 1] - T.lev_start[lc];
             S.sub_nlev = T.depth - lc + 1;
+            maxtot = group_subtrees(rng, S.sub_nlev, cap, &S.n_sub);
             FMMHP_CHECK(to_dev(A, &S.sub_rng, rng, "subtree ranges", s));
             S.sub_ld_m2m = std::max(4 * kM2MParents, std::min(maxtot, cap));
             S.sub_ld_l2l = std::max(kL2LChildren, std::min(maxtot * S.nloc, cap));
+            // the subtrees whose expansions do not fit those rows: their parents (M2M) and children
+            // (L2L) level by level in chunks, so that all of them run in parallel
+            {
+                const int nl = S.sub_nlev;
+                std::vector<std::vector<int2>> mc(T.depth + 1), lcx(T.depth + 1);
+                for (int r = 0; r < S.n_sub; ++r) {
+                    const int2 *R = &rng[(size_t)r * nl];
+                    int tot = 0;
+                    for (int k = 0; k < nl; ++k) tot += R[k].y - R[k].x;
+                    if (tot > S.sub_ld_m2m)
+                        for (int k = 0; k + 1 < nl; ++k)
+                            for (int a0 = R[k].x; a0 < R[k].y; a0 += kM2MParents)
+                                mc[lc + k].push_back(make_int2(a0, std::min(a0 + kM2MParents, R[k].y)));
+                    if (tot * S.nloc > S.sub_ld_l2l)
+                        for (int k = 1; k < nl; ++k)
+                            for (int a0 = R[k].x; a0 < R[k].y; a0 += kL2LChildren)
+                                lcx[lc + k].push_back(make_int2(a0, std::min(a0 + kL2LChildren, R[k].y)));
+                }
+                std::vector<int2> mall, lall;
+                for (int l = 0; l <= T.depth; ++l) {
+                    S.m2m_ch_lev[l] = (int)mall.size();
+                    S.l2l_ch_lev[l] = (int)lall.size();
+                    mall.insert(mall.end(), mc[l].begin(), mc[l].end());
+                    lall.insert(lall.end(), lcx[l].begin(), lcx[l].end());
+                }
+                S.m2m_ch_lev[T.depth + 1] = (int)mall.size();
+                S.l2l_ch_lev[T.depth + 1] = (int)lall.size();
+                if (!mall.empty()) FMMHP_CHECK(to_dev(A, &S.m2m_ch, mall, "M2M chunks", s));
+                if (!lall.empty()) FMMHP_CHECK(to_dev(A, &S.l2l_ch, lall, "L2L chunks", s));
+            }
             // the L2L levels 4..lc in one launch of level-3-rooted subtrees (after level 3's own L2L)
             // (only when those subtrees fit in LDS)
             if (lc >= 5) {
                 std::vector<int2> trng;
-                const int tmax = subtree_ranges(3, lc - 3 + 1, trng, cap, nullptr);
+                int tmax = subtree_ranges(3, lc - 3 + 1, trng, cap, nullptr);
                 if (tmax <= cap) {
                     S.top_nlev = lc - 3 + 1;
-                    S.n_top = T.lev_start[4] - T.lev_start[3];
+                    tmax = group_subtrees(trng, S.top_nlev, cap / S.nloc, &S.n_top);
                     FMMHP_CHECK(to_dev(A, &S.top_rng, trng, "top subtree ranges", s));
                     S.top_ld_l2l = std::max(kL2LChildren, std::min(tmax * S.nloc, cap));
                     S.top_ld_m2m = std::max(4 * kM2MParents, std::min(tmax, cap));
@@ -3074,15 +3257,14 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
         }
         const int i0 = S.ibox_lev[l0], i1 = S.ibox_lev[l1];
         if (i1 > i0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB>),
-                               dim3(nblk((int64_t)(i1 - i0) * (PB + 1) * kImgSplit, 256), NV),
-                               dim3(256), 0, st, i1 - i0, S.ibox + i0, nbox, S.nloc, S.ibase, S.vimg_off, S.vimg_ent,
-                               S.TimgH, S.TimgG, S.Limg, S.logside, S.bc == 2 ? -1.0 : 1.0, ws.W, ws.Lam);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB, NV>), dim3(i1 - i0), dim3(64), 0, st, S.ibox + i0, nbox,
+                               S.nloc, S.ibase, S.vimg_off, S.vimg_ent, S.TimgH, S.TimgG, S.Limg, S.logside,
+                               S.bc == 2 ? -1.0 : 1.0, ws.W, ws.Lam);
         const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
         if (x1 > x0)
             for (int loc = 0; loc < S.nloc; ++loc)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP>), dim3(x1 - x0, NV), dim3(64), 0, st, S.inst_info,
-                                   T.inst, NV, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count,
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP, NV>), dim3(x1 - x0), dim3(64), 0, st, S.inst_info,
+                                   T.inst, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count,
                                    T.off[3], T.ent[3], T.xs, T.ys, ws.qs, S.nrm, S.fact, ws.Lam);
         FMMHP_HIP(hipGetLastError());
         return FMMHP_OK;
@@ -3102,16 +3284,26 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     const int lc = S.sub_level;
     int lf = S.fork_late ? 2 : ld;
     if (lc > 0 && lf >= lc) lf = T.depth;  // inside the subtree pass: fork right after it
-    if (lc > 0)
+    if (lc > 0) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_sub, NV), dim3(256),
-                           (PB + 1) * S.sub_ld_m2m * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_m2m, nbox, T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
+                           (PB + 1) * S.sub_ld_m2m * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_m2m, 1, nbox,
+                           T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
+        // the subtrees too large for LDS: one launch per parent level, deepest first
+        for (int l = T.depth - 1; l >= lc; --l) {
+            const int c0 = S.m2m_ch_lev[l], c1 = S.m2m_ch_lev[l + 1];
+            if (c1 > c0)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_chunks<PB>), dim3(c1 - c0, NV), dim3(256),
+                                   (PB + 1) * 4 * kM2MParents * sizeof(cplx), s, S.m2m_ch + c0, nbox, T.leaf,
+                                   T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
+        }
+    }
     if (ld > 0 && lf > T.depth - 1) FMMHP_CHECK(fork_deep());
     // above the cut: with a top subtree pass, the parents of levels 3..lc-1 in one launch (subtrees
     // rooted at level 3, the cut level's multipoles their inputs), then level 2
     int l_top = (lc > 0 ? lc : T.depth) - 1;
     if (S.n_top > 0) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2m_sub<PB>), dim3(S.n_top, NV), dim3(256),
-                           (PB + 1) * S.top_ld_m2m * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_m2m, nbox,
+                           (PB + 1) * S.top_ld_m2m * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_m2m, 0, nbox,
                            T.leaf, T.child_first, T.nchild, T.bx, T.by, S.E_m2m, ws.W);
         if (ld > 0 && lf >= 3 && lf <= l_top) FMMHP_CHECK(fork_deep());
         l_top = 2;
@@ -3132,7 +3324,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     if (w_side) {
         FMMHP_HIP(hipEventRecord(S.ev_up, s));
         FMMHP_HIP(hipStreamWaitEvent(side_, S.ev_up, 0));
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, side_,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM, NV>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, side_,
                            la);
         FMMHP_HIP(hipGetLastError());
     }
@@ -3162,12 +3354,22 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     }
     if (S.n_top > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_top, NV), dim3(256),
-                           (PB + 1) * S.top_ld_l2l * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_l2l, nbox,
+                           (PB + 1) * S.top_ld_l2l * sizeof(cplx), s, S.top_nlev, S.top_rng, S.top_ld_l2l, 0, nbox,
                            S.nloc, T.parent, T.bx, T.by, S.E_l2l, ws.Lam);
     if (ld > 0 && ld > l2l_end) FMMHP_HIP(hipStreamWaitEvent(s, S.ev_deep_done, 0));
-    if (lc > 0)
+    if (lc > 0) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_sub<PB>), dim3(S.n_sub, NV), dim3(256),
-                           (PB + 1) * S.sub_ld_l2l * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_l2l, nbox, S.nloc, T.parent, T.bx, T.by, S.E_l2l, ws.Lam);
+                           (PB + 1) * S.sub_ld_l2l * sizeof(cplx), s, S.sub_nlev, S.sub_rng, S.sub_ld_l2l, 1, nbox,
+                           S.nloc, T.parent, T.bx, T.by, S.E_l2l, ws.Lam);
+        // the subtrees too large for LDS: one launch per child level, top level first
+        for (int l = lc + 1; l <= T.depth; ++l) {
+            const int c0 = S.l2l_ch_lev[l], c1 = S.l2l_ch_lev[l + 1];
+            if (c1 > c0)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2l_chunks<PB>), dim3(c1 - c0, NV), dim3(256),
+                                   (PB + 1) * kL2LChildren * sizeof(cplx), s, S.l2l_ch + c0, nbox, S.nloc, T.parent,
+                                   T.bx, T.by, S.E_l2l, ws.Lam);
+        }
+    }
     if (mk_.on && ld == 0) {
         FMMHP_HIP(hipEventRecord(mk_.deep0, s));
         FMMHP_HIP(hipEventRecord(mk_.deep1, s));
@@ -3184,7 +3386,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     FMMHP_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     FMMHP_CHECK(mk_.mark(FMMHP_PHASE_LEAF, s));
     if (S.n_wpts > 0 && !w_side)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM>), dim3(nblk(S.n_wpts, 128), NV), dim3(128), 0, s, la);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf_w<PB, LM, NV>), dim3(nblk(S.n_wpts, 128)), dim3(128), 0, s, la);
     // dipoles differ from charges only in the source terms: the L2P and M2P kernels are the potential's
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_leaf<PB, LM>), dim3(nblk(T.n, 256), NV), dim3(256), 0, s, la);
     FMMHP_HIP(hipGetLastError());

@@ -197,6 +197,9 @@ struct Sched {
     int n_sub = 0, sub_nlev = 0;    // subtrees (the boxes of the cut level), levels cut..depth
     int2 *sub_rng = nullptr;        // [n_sub][sub_nlev] box range of each subtree per level
     int sub_ld_m2m = 0, sub_ld_l2l = 0;  // LDS expansion slots of the subtree passes
+    // subtrees below the cut too large for those slots: parent (M2M) and child (L2L) chunks by level
+    int2 *m2m_ch = nullptr, *l2l_ch = nullptr;
+    std::vector<int> m2m_ch_lev, l2l_ch_lev;  // [depth + 2] first chunk of each level
     // L2L of levels 4..cut in one launch: subtrees rooted at level 3 (0 subtrees: one launch per level)
     int n_top = 0, top_nlev = 0, top_ld_l2l = 0, top_ld_m2m = 0;  // (the same subtrees serve the M2M)
     int2 *top_rng = nullptr;
