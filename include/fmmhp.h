@@ -106,11 +106,10 @@ typedef struct {
  * and the deep-level M2L on streams of their own beside the rest: a profiling aid (each kernel's
  * duration is then its own, not shared with concurrent kernels); slower. */
 #define FMMHP_FLAG_SERIAL 16u
-/* Form of the FP64 M2L of upper sources (eq. (truncatedM2Lcoef) and the log-kernel M2L).  By default
- * it runs on the vector ALUs (one lane per target box, operators in scalar registers) for p < 30 and
- * on the FP64 matrix cores (v_mfma_f64_16x16x4f64, complex numbers as 2 x 2 real blocks) for p >= 30;
- * each flag forces one form (not both).  The same sums in another order (agreement to rounding).
- * Ignored with FMMHP_FLAG_M2L_FP32. */
+/* Form of the FP64 M2L of upper sources (eq. (truncatedM2Lcoef) and the log-kernel M2L): the vector
+ * ALUs (one lane per target box, operators in scalar registers; the default) or the FP64 matrix cores
+ * (v_mfma_f64_16x16x4f64, complex numbers as 2 x 2 real blocks); at most one of the two flags.  The
+ * same sums in another order (agreement to rounding).  Ignored with FMMHP_FLAG_M2L_FP32. */
 #define FMMHP_FLAG_M2L_VECTOR 32u
 #define FMMHP_FLAG_M2L_MFMA 64u
 

@@ -30,12 +30,12 @@ FLAG_M2L_FP32 = 2  # fmmhp_opts.flags: upper-source M2L on the FP32 matrix cores
 FLAG_DIRICHLET = 4  # fmmhp_opts.flags: Dirichlet half-plane kernel (eq. (ddd1.2), image term +)
 FLAG_NEUMANN = 8    # fmmhp_opts.flags: Neumann half-plane kernel (eq. (ddd1.2), image term -)
 FLAG_SERIAL = 16    # fmmhp_opts.flags: every kernel on the eval stream (profiling aid)
-FLAG_M2L_VECTOR = 32  # fmmhp_opts.flags: FP64 M2L on the vector ALUs (default for p < 30)
-FLAG_M2L_MFMA = 64    # fmmhp_opts.flags: FP64 M2L on the matrix cores (default for p >= 30)
+FLAG_M2L_VECTOR = 32  # fmmhp_opts.flags: FP64 M2L on the vector ALUs (the default form)
+FLAG_M2L_MFMA = 64    # fmmhp_opts.flags: FP64 M2L on the matrix cores
 
 
 def _m2l_flag(form):
-    """fmmhp_opts.flags bits of an M2L form: None (by order), "vector" or "mfma"."""
+    """fmmhp_opts.flags bits of an M2L form: None (the library default), "vector" or "mfma"."""
     if form is None:
         return 0
     if form == "vector":
@@ -356,8 +356,8 @@ def _cache_store(path, key, value):
 
 def tune(x, y, q, impedance, tol=1e-10, n_vec=1, leaf_sizes=None, sample=0, use_cache=True) -> dict:
     """Pick (p, leaf_size) for these points and impedance at a target rel-l2 error, the near-field
-    launch shape (near_walk, near_groups) and the M2L form (m2l_form: None for the default by
-    order, "vector" or "mfma"; m2l_fp32) by timing the chosen plan.
+    launch shape (near_walk, near_groups) and the M2L form (m2l_form: None for the default,
+    "vector" or "mfma"; m2l_fp32) by timing the chosen plan.
     With use_cache the choice is read from (and written to) the tuner's JSON cache; "cached" in the
     result says which."""
     x = _dev_f64(x, "x")
@@ -399,8 +399,8 @@ class HalfPlaneFMM:
     bc          "robin" (the impedance condition), "dirichlet" or "neumann" (eq. (ddd1.2); the
                 impedance is then ignored)
     serial      every kernel on the eval stream, one after another (profiling aid; slower)
-    m2l_form    FP64 M2L form: None (vector ALUs for p < 30, matrix cores from p = 30), "vector"
-                or "mfma" (the same sums in another order)
+    m2l_form    FP64 M2L form: None (the default: vector ALUs), "vector" or "mfma" (the same sums
+                in another order)
     """
 
     def __init__(self, x, y, impedance, p=20, leaf_size=40, max_level=0, pass_images=False,

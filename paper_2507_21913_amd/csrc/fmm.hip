@@ -507,11 +507,11 @@ __global__ __launch_bounds__(64 * m2l_waves(PB)) void k_m2l(M2LArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// M2L of upper sources on the FP64 matrix cores (the default for p >= kM2LMfmaOrder, or with
-// FMMHP_FLAG_M2L_MFMA).  On gfx950 an FP64 matrix instruction (16 x 16 x 4, 2048 flops) occupies the
-// SIMD's matrix unit for 64 cycles: the same FP64 rate as the vector ALUs, so this form wins only where
-// its padding is small: 2(p+1) output columns padded to 16 and p+1 source coefficients to 4 keep
-// 94% of the instructions' work at p = 30 but 77% at p = 20.
+// M2L of upper sources on the FP64 matrix cores (FMMHP_FLAG_M2L_MFMA; the tuner times it against the
+// vector form).  On gfx950 an FP64 matrix instruction (16 x 16 x 4, 2048 flops) occupies the SIMD's
+// matrix unit for 64 cycles: the same FP64 rate as the vector ALUs, and the 2x2 embedding padded to
+// 16 output columns and 4 source coefficients keeps 77% of the instructions' work at p = 20 (94% at
+// p = 30): this form has been measured slower than k_m2l at p = 20 and p = 30.
 // Per offset slot the tile's contraction acc_n += sum_m T_{n+m} w_m is a real GEMM in the 2x2
 // embedding of complex numbers,
 //   D[target][2n + c] += sum_m (Re w_m B[2m][2n + c] + Im w_m B[2m + 1][2n + c]),
@@ -912,26 +912,31 @@ __global__ __launch_bounds__(128 * (m2l32_np(PB) / 16)) void k_m2l_f32(M2L32Args
 }
 
 // Image V entries (target boxes in the two rows nearest y = 0 at each level): log M2L of the image
-// box plus the reaction M2L, added to the locals written by k_m2l.  One 64-lane block per target box
-// and all vectors of the pass: lane (g, n) computes output coefficient n from every G-th V entry
-// (G = 64 / (p + 1) groups), reading the entry's operator row coalesced across n; the groups' sums
-// are joined through LDS.
+// box plus the reaction M2L, added to the locals written by k_m2l.  One block per target box and all
+// vectors of the pass: lane (g, n) computes output coefficient n from every G-th V entry of the box
+// (G = min(kImgThreads / (p + 1), kImgGroups) groups), reading the entry's operator row coalesced
+// across n; the groups' sums are joined through LDS in a fixed order.  The same partition for any
+// number of vectors, so a vector's result does not depend on the others in its pass.
+constexpr int kImgThreads = 256;
+constexpr int kImgGroups = 8;
+
 template <int PB, int NV>
-__global__ __launch_bounds__(64) void k_m2l_img(const int32_t *__restrict__ ibox, int nbox, int nloc,
-                                                const int32_t *__restrict__ ibase,
-                                                const int32_t *__restrict__ vimg_off,
-                                                const int32_t *__restrict__ vimg_ent, const cplx *__restrict__ TH,
-                                                const cplx *__restrict__ TG, const cplx *__restrict__ Limg,
-                                                const double *__restrict__ logside, double isg,
-                                                const cplx *__restrict__ W, cplx *__restrict__ Lam) {
+__global__ __launch_bounds__(kImgThreads) void k_m2l_img(const int32_t *__restrict__ ibox, int nbox, int nloc,
+                                                         const int32_t *__restrict__ ibase,
+                                                         const int32_t *__restrict__ vimg_off,
+                                                         const int32_t *__restrict__ vimg_ent,
+                                                         const cplx *__restrict__ TH, const cplx *__restrict__ TG,
+                                                         const cplx *__restrict__ Limg,
+                                                         const double *__restrict__ logside, double isg,
+                                                         const cplx *__restrict__ W, cplx *__restrict__ Lam) {
     constexpr int NTP = m2l_row(PB);
     constexpr int P1 = PB + 1;
-    constexpr int G = 64 / P1;
-    static_assert(G >= 1, "one group of p + 1 lanes fits a wave");
-    __shared__ cplx red[G > 1 ? G - 1 : 1][NV][2][P1];
+    constexpr int G = kImgThreads / P1 < kImgGroups ? kImgThreads / P1 : kImgGroups;
+    static_assert(G >= 1, "one group of p + 1 lanes fits the block");
+    __shared__ cplx red[G > 1 ? G - 1 : 1][2][P1];
     const int b = ibox[blockIdx.x];
-    const int lane = threadIdx.x;
-    const int g = lane / P1, n = lane - g * P1;
+    const int tid = threadIdx.x;
+    const int g = tid / P1, n = tid - g * P1;
     const int l = ibase[b];  // table block of the box's (instance, level)
     const double ll = logside[b] * kInv4Pi;
     cplx aH[NV], aG[NV];
@@ -943,7 +948,7 @@ __global__ __launch_bounds__(64) void k_m2l_img(const int32_t *__restrict__ ibox
             const int src = code >> 5, is = code & 31;
             const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
             const cplx *tg = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
-            // all loads of an entry in flight for one vector; fewer registers with several
+            // several loads of an entry in flight for one vector; fewer registers with several
 #pragma unroll(NV == 1 ? 8 : 2)
             for (int m = 0; m <= PB; ++m) {
                 const cplx t = th[m];
@@ -966,27 +971,23 @@ __global__ __launch_bounds__(64) void k_m2l_img(const int32_t *__restrict__ ibox
             }
         }
     }
-    if (G > 1) {
-        if (g >= 1 && g < G) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                red[g - 1][v][0][n] = aH[v];
-                red[g - 1][v][1][n] = aG[v];
+    for (int v = 0; v < NV; ++v) {
+        if (G > 1) {
+            if (v > 0) __syncthreads();  // the previous vector's sums have been read
+            if (g >= 1 && g < G) {
+                red[g - 1][0][n] = aH[v];
+                red[g - 1][1][n] = aG[v];
+            }
+            __syncthreads();
+            if (g == 0) {
+                for (int h = 0; h + 1 < G; ++h) {
+                    aH[v] += red[h][0][n];
+                    aG[v] += red[h][1][n];
+                }
             }
         }
-        __syncthreads();
         if (g == 0) {
-            for (int h = 0; h + 1 < G; ++h)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    aH[v] += red[h][v][0][n];
-                    aG[v] += red[h][v][1][n];
-                }
-        }
-    }
-    if (g == 0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
             cplx *Lv = Lam + (int64_t)v * nloc * P1 * nbox;
             Lv[(int64_t)n * nbox + b] += -aH[v];
             if (nloc == 2) Lv[(int64_t)P1 * nbox + (int64_t)n * nbox + b] += -aG[v];
@@ -2045,6 +2046,7 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
             ud[v] = w0;
         }
         cplx pw = tau;
+#pragma unroll(NV == 1 ? PB : 2)
         for (int k = 1; k <= PB; ++k) {
             const double fk1 = a.fact[k - 1], fk = a.fact[k];
 #pragma unroll
@@ -2085,6 +2087,7 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
                     accd[v] = mk(0.0, 0.0);
                 }
                 constexpr int NTOP = has_grad(MODE) ? PB + 1 : PB;
+#pragma unroll(NV == 1 ? NTOP : 2)
                 for (int n = 1; n <= NTOP; ++n) {
                     F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
                     K = F * kInv2Pi + zr * K;
@@ -3246,7 +3249,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
                 M2LArgs ma{nbox,    t0,      S.tiles,   S.tile_level, S.tile_src_off, S.tile_src, S.tile_slot,
                            S.tile_mask, S.Tfree, S.Lfree, S.logside,  ws.W,            ws.Lam,      S.nloc};
                 FMMHP_CHECK(mk_.km_mark(which, 0, st));
-                if (!(S.m2l_form == 2 || (S.m2l_form == 0 && PB >= kM2LMfmaOrder)))
+                if (S.m2l_form != 2)
                     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l<PB, CH>), dim3(t1 - t0, NV), dim3(64 * m2l_waves(PB)),
                                        0, st, ma);
                 else
@@ -3257,7 +3260,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
         }
         const int i0 = S.ibox_lev[l0], i1 = S.ibox_lev[l1];
         if (i1 > i0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB, NV>), dim3(i1 - i0), dim3(64), 0, st, S.ibox + i0, nbox,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB, NV>), dim3(i1 - i0), dim3(kImgThreads), 0, st, S.ibox + i0, nbox,
                                S.nloc, S.ibase, S.vimg_off, S.vimg_ent, S.TimgH, S.TimgG, S.Limg, S.logside,
                                S.bc == 2 ? -1.0 : 1.0, ws.W, ws.Lam);
         const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];

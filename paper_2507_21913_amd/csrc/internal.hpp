@@ -24,7 +24,6 @@ constexpr int kNumSlots = 49;     // 7 x 7 same-level offsets, |dx|, |dy| <= 3
 constexpr int kNumImgSlots = 21;  // image offsets: dx in [-3, 3], dy in {-3, -2, -1}
 constexpr int kM2LChunkMax = 8;   // at most this many output coefficients per M2L wave
 constexpr int kM2LPhase = 4;      // multipole coefficients staged in LDS per phase
-constexpr int kM2LMfmaOrder = 30; // default FP64 M2L form: matrix cores from this compiled order on
 constexpr int kM2LMaxSrc = 400;   // distinct V sources per tile (LDS: 4 * 400 * 16 B)
 
 // Waves per M2L workgroup, each owning m2l_chunk(PB) consecutive output coefficients: the fewest
@@ -208,8 +207,8 @@ struct Sched {
     // tables
     cplx *Tfree = nullptr;          // [kNumSlots][m2l_row(PB)]
     bool m2l_fp32 = false;          // FMMHP_FLAG_M2L_FP32: upper-source M2L on the FP32 matrix cores
-    int m2l_form = 0;               // FP64 M2L of upper sources: 0 by order (matrix cores for p >= 30),
-                                    // 1 vector ALUs (k_m2l), 2 matrix cores (k_m2l_mf)
+    int m2l_form = 0;               // FP64 M2L of upper sources: 0 default (vector ALUs), 1 vector ALUs
+                                    // (k_m2l), 2 matrix cores (k_m2l_mf)
     float *Bf32 = nullptr;          // [kNumSlots][KP][NP] embedded scaled operators (FP32 M2L)
     cplx *Lfree = nullptr;          // [kNumSlots]   (offset part of the log term)
     cplx *TimgH = nullptr;          // [blocks][kNumImgSlots][m2l_row(PB)]

@@ -212,8 +212,7 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
         st = fmmhp_plan_create(n, x, y, nullptr, nullptr, lambda_re, lambda_im, &bo, s, &plan);
         if (st == FMMHP_OK) {
             // the form the chosen plan uses
-            const bool mf = (bo.flags & FMMHP_FLAG_M2L_MFMA) ||
-                            (!(bo.flags & FMMHP_FLAG_M2L_VECTOR) && plan->sched.PB >= kM2LMfmaOrder);
+            const bool mf = plan->sched.m2l_form == 2;
             (void)fmmhp_plan_destroy(plan);
             plan = nullptr;
             of.flags = (bo.flags & ~(FMMHP_FLAG_M2L_VECTOR | FMMHP_FLAG_M2L_MFMA)) |

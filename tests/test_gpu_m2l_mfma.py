@@ -1,5 +1,5 @@
-"""GPU parity of the FP64 matrix-core M2L of upper sources (v_mfma_f64_16x16x4f64; the default form
-from p = 30, forced by FMMHP_FLAG_M2L_MFMA below) against the CPU oracle's direct sum and
+"""GPU parity of the FP64 matrix-core M2L of upper sources (v_mfma_f64_16x16x4f64,
+FMMHP_FLAG_M2L_MFMA) against the CPU oracle's direct sum and
 against the vector-ALU M2L (FMMHP_FLAG_M2L_VECTOR), which computes the same sums of
 eq. (truncatedM2Lcoef) and the log-kernel M2L in another order.
 
@@ -55,7 +55,7 @@ def test_every_order_matches_vector_path(p):
 @pytest.mark.parametrize("Z", [1.0, 1.0 + 0.5j, 2.0, 0.3 + 1.1j])
 def test_matches_oracle_at_p30(Z):
     x, y, q = _band(8000, 7)
-    plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=30, leaf_size=20)  # the matrix-core form by default
+    plan = F.HalfPlaneFMM(_t(x), _t(y), Z, p=30, leaf_size=20, m2l_form="mfma")
     got = plan(_t(q)).cpu().numpy()
     plan.close()
     ref = D.potential(x, y, q, Z, workers=8)
