@@ -1004,120 +1004,218 @@ __global__ void k_zero_lam(int lo, int hi, int nbox, int ncoef, int nrow, cplx *
     Lam[r * nbox + b] = mk(0.0, 0.0);
 }
 
+// Lane moves within a wave by DPP (no LDS traffic, a few cycles), for doubles as two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of IA = 1, 2, 4 or 8 consecutive lanes (every lane of a group gets it).
+__device__ __forceinline__ double lane_group_sum(double s, int IA) {
+    if (IA >= 2) s += dpp_move<0xB1, 0xF>(s);   // quad_perm [1, 0, 3, 2]
+    if (IA >= 4) s += dpp_move<0x4E, 0xF>(s);   // quad_perm [2, 3, 0, 1]
+    if (IA >= 8) s += dpp_move<0x141, 0xF>(s);  // row_half_mirror
+    return s;
+}
+
 // ---------------------------------------------------------------------------------------------
-// P2L (X list): sources of a coarse leaf straight into the local of a finer box.  One wave per
-// target box; lanes take source points, write their p + 1 contributions to LDS, and lane n sums
-// coefficient n over the chunk in a fixed order.
+// P2L (X list): sources of a coarse leaf straight into the local of a finer box.  A wave takes a
+// group of X boxes of one level (consecutive boxes whose X sources total at most 64, or one larger
+// box) and walks the group's sources in chunks of 64, one source per lane in the order (box, list
+// entry, point).  Each lane computes its source's terms for unit charge, 8 coefficients at a time
+// and for every local of the plan, into LDS; then lane (k, g) sums coefficient k of each box of the
+// chunk over the box's rows g, g + 8, ..., times the charges of every vector of the pass, and the 8
+// partial sums meet by lane moves.  The log terms are shared by the H and G locals.
 // Dipole sources (DIP) take the derivative of these contributions along the source normal: the log
 // local is holomorphic in d = z_j - c_b (upper box) or in conj(z_j) - c_b (image), so the derivative
 // is nu d/dd (nu = n_x + i n_y, or its conjugate for the image), and for the reaction local
 // n_j . grad_{r_j} [n! rho^n I_n] = -(1/rho) i conj(nu) K_{n+1} (d_X I_n = i (n+1) I_{n+1},
 // d_Y I_n = -(n+1) I_{n+1}, from eq. (generalintegral)); the same holds for the mirrored G local.
 // ---------------------------------------------------------------------------------------------
+constexpr int kP2LPhase = 8;   // coefficients per LDS phase with reaction rows (16 without)
+constexpr int kP2LRows = 72;   // row stride of the 8-coefficient layout (68 in the 16-coefficient one)
+
 template <int PB, bool DIP, int NV>
 __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
-                                            int nloc, int loc, const int32_t *__restrict__ xbox, int nbox,
+                                            int nloc, const int4 *__restrict__ grp, const int4 *__restrict__ gent,
+                                            const int32_t *__restrict__ xbox, int nbox,
                                             const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
                                             const int32_t *__restrict__ by, const int32_t *__restrict__ first,
-                                            const int32_t *__restrict__ count, const int32_t *__restrict__ xoff,
-                                            const int32_t *__restrict__ xent, const double *__restrict__ xs,
-                                            const double *__restrict__ ys, const double *__restrict__ qs,
-                                            const double2 *__restrict__ nrm, const double *__restrict__ fact,
-                                            cplx *__restrict__ Lam) {
-    // lane j of a chunk writes its source point's terms for unit charge (they do not depend on the
-    // charge vector); lane n <= PB then adds sum_j q_j^(v) term_j[n] for every vector v of the pass
-    __shared__ cplx contrib[64][PB + 1];
+                                            const double *__restrict__ xs, const double *__restrict__ ys,
+                                            const double *__restrict__ qs, const double2 *__restrict__ nrm,
+                                            const double *__restrict__ fact, cplx *__restrict__ Lam) {
+    constexpr int P1 = PB + 1;
+    // [local][coefficient in phase][source row], 2 x 8 coefficients or 1 x 16 (row strides 72, 68)
+    __shared__ cplx C[2 * kP2LPhase * kP2LRows];
     __shared__ double sq[64][NV];
-    const int b = xbox[blockIdx.x];
     const int lane = threadIdx.x;
-    const int l = level[b];
-    const Geo g = geo_of(ii, inst[b]);
-    const cplx Z = ii[inst[b]].Z;
-    const cplx cb = centre_of(g, l, bx[b], by[b]);
-    const double rho = 0.5 * side_of(g, l);
-    cplx acc[NV];
+    const int4 gd = grp[blockIdx.x], gn = grp[blockIdx.x + 1];
+    const int gs = gd.x, K = gd.y, eg1 = gn.z;
+    const int g8 = lane & 7, kq = lane >> 3;  // summing lane: source group, coefficient in phase
+    int elo = gd.z;                            // first list entry of the current chunk
+    for (int F = 0; F < K; F += 64) {
+        const int f = F + lane;
+        // the chunk's entries {code, slot, first row}: at most 64 (every entry holds a source), in
+        // order of first row; lane f takes the last one starting at or before f
+        const int ne = eg1 - elo < 64 ? eg1 - elo : 64;
+        const int4 en = lane < ne ? gent[elo + lane] : make_int4(0, 0, 0, 0);
+        int my = 0;
+        for (int t = 1; t < ne; ++t) {
+            const int st = __builtin_amdgcn_readlane(en.z, t);
+            if (st > F + 63) break;
+            if (st <= f) my = t;
+        }
+        const int code = __shfl(en.x, my), s = __shfl(en.y, my), f0 = __shfl(en.z, my);
+        {
+            // first entry of the next chunk: lane 63's, or the one after it if that starts the chunk
+            const int m63 = __builtin_amdgcn_readlane(my, 63);
+            const int nx = elo + m63 + 1;
+            const int stn = nx < eg1 ? gent[nx].z : 0x7fffffff;
+            elo = stn <= F + 64 ? nx : elo + m63;
+        }
+        const bool act = f < K;
+        // the lane's source, target box and the state of its term recursions
+        const int c = code >> 1, img = act ? code & 1 : 0;
+        const int j = act ? first[c] + (f - f0) : 0;
+        const int b = xbox[gs + (act ? s : 0)];
+        const int l = level[b];
+        const int k = inst[b];
+        const Geo g = geo_of(ii, k);
+        const cplx cb = centre_of(g, l, bx[b], by[b]);
+        const double rho = 0.5 * side_of(g, l);
+        const bool rx = act && img && ii[k].react;
+        cplx sig = mk(0.0, 0.0), pw = mk(0.0, 0.0), l0 = mk(0.0, 0.0);
+        double sgn = 0.0;
+        cplx sw[2], Fr[2], Kr[2], zr = mk(0.0, 0.0), cn = mk(0.0, 0.0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = mk(0.0, 0.0);
-    for (int e = xoff[b]; e < xoff[b + 1]; ++e) {
-        const int code = xent[e];
-        const int c = code >> 1, img = code & 1;
-        const int j0 = first[c], j1 = j0 + count[c];
-        for (int jb = j0; jb < j1; jb += 64) {
-            const int j = jb + lane;
-            cplx *out = contrib[lane];
-            if (j < j1) {
+        for (int lc = 0; lc < 2; ++lc) sw[lc] = Fr[lc] = Kr[lc] = mk(0.0, 0.0);
+        if (act) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sq[lane][v] = qs[(int64_t)j * NV + v];
-                const double yj = img ? -ys[j] : ys[j];
-                const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
-                const double sgn = img ? ii[inst[b]].isg : -1.0;  // -(1/4pi) upper, +-(1/4pi) image
-                const cplx sig = rho * inv(d);
-                if (DIP) {
-                    // nu d/dd of the charge's local below: (nu / rho) n! sig^(n+1)
-                    const double2 nj = nrm[j];
-                    cplx pw = ((sgn * kInv4Pi / rho) * mk(nj.x, img ? -nj.y : nj.y)) * sig;
-                    for (int n = 0; n <= PB; ++n) {
-                        out[n] = fact[n] * pw;
-                        pw = pw * sig;
-                    }
-                } else {
-                    // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
-                    out[0] = (sgn * kInv4Pi) * clog_(-d);
-                    cplx pw = sig;
-                    for (int n = 1; n <= PB; ++n) {
-                        out[n] = (-sgn * kInv4Pi * fact[n - 1]) * pw;
-                        pw = pw * sig;
-                    }
-                }
-                if (img && ii[inst[b]].react) {
-                    // reaction S2L (eq. (LEcoefficients)) re-expanded in powers of (z - c_b):
-                    // lambda_n += i^n n! rho^n q I_n(x_c - x_j, y_c + y_j)  (G: conj of I_n(-X, Y))
-                    const double X = cb.re - xs[j], Y = cb.im + ys[j];
-                    const double Xs = loc == 0 ? X : -X;
-                    const cplx sw = rho * inv(mk(Y, -Xs));
-                    const cplx zr = rho * Z;
-                    cplx K = reaction_I0_general(Xs, Y, Z);
-                    cplx F = mk(1.0, 0.0);
-                    if (DIP) {
-                        // lambda_(n-1) += -(mu conj(nu) / rho) i^n K_n, n = 1 .. p + 1
-                        const double2 nj = nrm[j];
-                        const cplx cn = (-1.0 / rho) * mk(nj.x, -nj.y);
-                        for (int n = 1; n <= PB + 1; ++n) {
-                            F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
-                            K = F * kInv2Pi + zr * K;
-                            out[n - 1] += cn * mul_ipow(loc == 0 ? K : conj(K), n);
-                        }
-                    } else {
-                        out[0] += loc == 0 ? K : conj(K);
-                        for (int n = 1; n <= PB; ++n) {
-                            F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
-                            K = F * kInv2Pi + zr * K;
-                            out[n] += mul_ipow(loc == 0 ? K : conj(K), n);
-                        }
-                    }
-                }
+            for (int v = 0; v < NV; ++v) sq[lane][v] = qs[(int64_t)j * NV + v];
+            const double yj = img ? -ys[j] : ys[j];
+            const cplx d = mk(xs[j] - cb.re, yj - cb.im);   // source - centre
+            sgn = img ? ii[k].isg : -1.0;                     // -(1/4pi) upper, +-(1/4pi) image
+            sig = rho * inv(d);
+            if (DIP) {
+                // nu d/dd of the charge's local below: (nu / rho) n! sig^(n+1)
+                const double2 nj = nrm[j];
+                pw = ((sgn * kInv4Pi / rho) * mk(nj.x, img ? -nj.y : nj.y)) * sig;
             } else {
+                // local of log(z - z_j) about c_b: log(c_b - z_j) - sum_n (z - c_b)^n / (n (z_j - c_b)^n)
+                l0 = (sgn * kInv4Pi) * clog_(-d);
+                pw = sig;
+            }
+            if (rx) {
+                // reaction S2L (eq. (LEcoefficients)) re-expanded in powers of (z - c_b):
+                // lambda_n += i^n n! rho^n q I_n(x_c - x_j, y_c + y_j)  (G: conj of I_n(-X, Y))
+                const double X = cb.re - xs[j], Y = cb.im + ys[j];
+                const cplx Z = ii[k].Z;
+                zr = rho * Z;
+                if (DIP) {
+                    const double2 nj = nrm[j];
+                    cn = (-1.0 / rho) * mk(nj.x, -nj.y);  // lambda_(n-1) += -(mu conj(nu) / rho) i^n K_n
+                }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sq[lane][v] = 0.0;
-                for (int n = 0; n <= PB; ++n) out[n] = mk(0.0, 0.0);
+                for (int lc = 0; lc < 2; ++lc) {
+                    if (lc == nloc) break;
+                    const double Xs = lc == 0 ? X : -X;
+                    sw[lc] = rho * inv(mk(Y, -Xs));
+                    Kr[lc] = reaction_I0_general(Xs, Y, Z);
+                    Fr[lc] = mk(1.0, 0.0);
+                }
+            }
+        }
+        // every load of the chunk has landed before the phases: otherwise the compiler's merged wait
+        // state keeps a count wait in each coefficient step, which from the second phase on also
+        // waits for the previous phase's local adds
+        __builtin_amdgcn_s_waitcnt(0);
+        // box slots present in this chunk
+        const int sa = __builtin_amdgcn_readlane(s, 0);
+        const int sb = __builtin_amdgcn_readlane(s, K - F < 64 ? K - F - 1 : 63);
+        // Without reaction rows the G terms equal the H terms: one set of terms, one sum added to
+        // every local, 16 coefficients a phase summed by 4 lanes each.  With reaction rows, every
+        // local has its own terms, 8 coefficients a phase summed by 8 lanes each.  Row strides keep
+        // the 16 lanes of an LDS access on distinct banks in either layout.
+        const bool mixed = __ballot(rx) != 0;
+        const int ph = mixed ? kP2LPhase : 2 * kP2LPhase;
+        const int nl = mixed ? nloc : 1;
+        const int G = mixed ? 8 : 4;
+        const int rs = mixed ? kP2LRows : kP2LRows - 4;
+        const int gq = lane & (G - 1), kq = mixed ? lane >> 3 : lane >> 2;
+        for (int m0 = 0; m0 <= PB; m0 += ph) {
+            if (act) {
+#pragma unroll
+                for (int kk = 0; kk < 2 * kP2LPhase; ++kk) {
+                    const int m = m0 + kk;
+                    if (kk == ph || m > PB) break;
+                    cplx t;
+                    if (DIP) {
+                        t = fact[m] * pw;
+                        pw = pw * sig;
+                    } else if (m == 0) {
+                        t = l0;
+                    } else {
+                        t = (-sgn * kInv4Pi * fact[m - 1]) * pw;
+                        pw = pw * sig;
+                    }
+#pragma unroll
+                    for (int lc = 0; lc < 2; ++lc) {
+                        if (lc == nl) break;
+                        cplx u = t;
+                        if (rx) {
+                            const int n = DIP ? m + 1 : m;  // order of I_n this coefficient takes
+                            if (n > 0) {
+                                Fr[lc] = Fr[lc] * sw[lc] * (n > 1 ? (double)(n - 1) : 1.0);  // (n-1)! sw^n
+                                Kr[lc] = Fr[lc] * kInv2Pi + zr * Kr[lc];
+                            }
+                            const cplx kn = mul_ipow(lc == 0 ? Kr[lc] : conj(Kr[lc]), n);
+                            u += DIP ? cn * kn : kn;
+                        }
+                        C[(lc * ph + kk) * rs + lane] = u;
+                    }
+                }
             }
             __syncthreads();
-            if (lane <= PB) {
-                const int kn = j1 - jb < 64 ? j1 - jb : 64;
-#pragma unroll 2
-                for (int k = 0; k < kn; ++k) {
-                    const cplx t = contrib[k][lane];
+            const int m = m0 + kq;
+            for (int sl = sa; sl <= sb; ++sl) {
+                const uint64_t msk = __ballot(act && s == sl);
+                const int r0 = __builtin_ctzll(msk), r1 = 64 - __builtin_clzll(msk);
+                const int bsl = __builtin_amdgcn_readlane(b, r0);  // the slot's box, from its first row
+                for (int lc = 0; lc < nl; ++lc) {
+                    const cplx *Ck = C + (lc * ph + kq) * rs;
+                    cplx acc[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] += sq[k][v] * t;
+                    for (int v = 0; v < NV; ++v) acc[v] = mk(0.0, 0.0);
+#pragma unroll 2
+                    for (int r = r0 + gq; r < r1; r += G) {
+                        const cplx t = Ck[r];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[v] += sq[r][v] * t;
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        acc[v].re = lane_group_sum(acc[v].re, G);
+                        acc[v].im = lane_group_sum(acc[v].im, G);
+                    }
+                    // only this wave adds to the box's locals here, one lane per coefficient in
+                    // program order, so the sums stay deterministic; the adds return nothing and the
+                    // wave does not wait for them
+                    if (gq == 0 && m <= PB && kq < ph) {
+                        for (int ld = mixed ? lc : 0; ld < (mixed ? lc + 1 : nloc); ++ld) {
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) {
+                                cplx *dst = Lam + (((int64_t)v * nloc + ld) * P1 + m) * nbox + bsl;
+                                unsafeAtomicAdd(&dst->re, acc[v].re);
+                                unsafeAtomicAdd(&dst->im, acc[v].im);
+                            }
+                        }
+                    }
                 }
             }
             __syncthreads();
         }
-    }
-    if (lane <= PB) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            Lam[((int64_t)v * nloc + loc) * (PB + 1) * nbox + (int64_t)lane * nbox + b] += acc[v];
     }
 }
 
@@ -1526,13 +1624,6 @@ struct SymArgs {
     int64_t n;
 };
 
-// Lane moves within a wave by DPP (no LDS traffic, a few cycles), for doubles as two 32-bit halves.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
 
 // Sum over aligned groups of TP lanes (TP = 8, 16, 32, 64).  Lanes [8k, 8k + 8) and rows of 16 are
 // reduced by quad swaps (xor 1, xor 2), the half-row mirror and the row mirror, after which every
@@ -1678,13 +1769,6 @@ __global__ __launch_bounds__(256) void k_near_sym(SymArgs a) {
 // target are reduced over its JG lanes once per record.
 constexpr int kBlkTargets = 8;
 
-// Sum over aligned groups of IA = 1, 2, 4 or 8 consecutive lanes (every lane of a group gets it).
-__device__ __forceinline__ double lane_group_sum(double s, int IA) {
-    if (IA >= 2) s += dpp_move<0xB1, 0xF>(s);   // quad_perm [1, 0, 3, 2]
-    if (IA >= 4) s += dpp_move<0x4E, 0xF>(s);   // quad_perm [2, 3, 0, 1]
-    if (IA >= 8) s += dpp_move<0x141, 0xF>(s);  // row_half_mirror
-    return s;
-}
 
 // One record with TI targets per lane (compile-time, so that a step's TI pair evaluations are
 // straight-line code whose table loads issue together).
@@ -2441,7 +2525,8 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     FMMHP_CHECK(to_host(voff, T.off[1], (size_t)nbox + 1, s));
     FMMHP_CHECK(to_host(vent, T.ent[1], (size_t)T.len[1], s));
     FMMHP_CHECK(to_host(xoff, T.off[3], (size_t)nbox + 1, s));
-    std::vector<int32_t> uoff, uent, cnt;
+    std::vector<int32_t> uoff, uent, cnt, xent;
+    FMMHP_CHECK(to_host(xent, T.ent[3], (size_t)T.len[3], s));
     FMMHP_CHECK(to_host(uoff, T.off[0], (size_t)nbox + 1, s));
     FMMHP_CHECK(to_host(uent, T.ent[0], (size_t)T.len[0], s));
     FMMHP_CHECK(to_host(cnt, T.count, (size_t)nbox, s));
@@ -2613,9 +2698,33 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     }
     S.nxbox = (int)xb.size();
     FMMHP_CHECK(to_dev(A, &S.xbox, xb, "xbox", s));
-    S.xbox_lev.assign(T.depth + 2, 0);
-    for (int l = 0; l <= T.depth + 1; ++l)
-        S.xbox_lev[l] = (int)(std::lower_bound(xb.begin(), xb.end(), T.lev_start[std::max(1, std::min(l, T.depth + 1))]) - xb.begin());
+    // P2L groups: consecutive X boxes of a level while their sources total at most one chunk of 64;
+    // per group its list entries that hold sources, {code, box slot, first row}, in row order
+    {
+        std::vector<int4> grp, gent;
+        S.xgrp_lev.assign(T.depth + 2, 0);
+        int l = 0;
+        for (int i = 0; i < (int)xb.size(); ++i) {
+            const int b = xb[i];
+            int kb = 0;
+            for (int e = xoff[b]; e < xoff[b + 1]; ++e) kb += cnt[xent[e] >> 1];
+            const bool new_level = level[b] != l;
+            while (level[b] > l) S.xgrp_lev[++l] = (int)grp.size();
+            if (new_level || grp.empty() || grp.back().y + kb > 64)
+                grp.push_back(make_int4(i, 0, (int)gent.size(), 0));
+            int4 &g = grp.back();
+            for (int e = xoff[b]; e < xoff[b + 1]; ++e) {
+                const int k = cnt[xent[e] >> 1];
+                if (k == 0) continue;
+                gent.push_back(make_int4(xent[e], i - g.x, g.y, 0));
+                g.y += k;
+            }
+        }
+        while (l < T.depth + 1) S.xgrp_lev[++l] = (int)grp.size();
+        grp.push_back(make_int4((int)xb.size(), 0, (int)gent.size(), 0));
+        FMMHP_CHECK(to_dev(A, &S.xgrp, grp, "P2L groups", s));
+        FMMHP_CHECK(to_dev(A, &S.xgent, gent, "P2L group entries", s));
+    }
     // deep split: the finest levels holding at least half of the M2L tiles run on a second stream
     // as soon as their multipoles exist, beside the rest of the upward pass
     S.deep_level = 0;
@@ -2929,10 +3038,9 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     // P2L (X list) and M2P (W list) run the double-precision recursion on the device: keep
     // |Z| * distance within the range where it loses at most ~4 digits
     {
-        std::vector<int32_t> went, xent, woff2;
+        std::vector<int32_t> went, woff2;
         FMMHP_CHECK(to_host(woff2, T.off[2], (size_t)nbox + 1, s));
         FMMHP_CHECK(to_host(went, T.ent[2], (size_t)T.len[2], s));
-        FMMHP_CHECK(to_host(xent, T.ent[3], (size_t)T.len[3], s));
         FMMHP_HIP(hipStreamSynchronize(s));
         double wxmax = 0.0;
         auto reach = [&](int b, int c) {  // |Z| * (centre distance to the image of c + half diagonals)
@@ -3263,12 +3371,11 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB, NV>), dim3(i1 - i0), dim3(kImgThreads), 0, st, S.ibox + i0, nbox,
                                S.nloc, S.ibase, S.vimg_off, S.vimg_ent, S.TimgH, S.TimgG, S.Limg, S.logside,
                                S.bc == 2 ? -1.0 : 1.0, ws.W, ws.Lam);
-        const int x0 = S.xbox_lev[l0], x1 = S.xbox_lev[l1];
+        const int x0 = S.xgrp_lev[l0], x1 = S.xgrp_lev[l1];
         if (x1 > x0)
-            for (int loc = 0; loc < S.nloc; ++loc)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP, NV>), dim3(x1 - x0), dim3(64), 0, st, S.inst_info,
-                                   T.inst, S.nloc, loc, S.xbox + x0, nbox, T.level, T.bx, T.by, T.first, T.count,
-                                   T.off[3], T.ent[3], T.xs, T.ys, ws.qs, S.nrm, S.fact, ws.Lam);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP, NV>), dim3(x1 - x0), dim3(64), 0, st, S.inst_info, T.inst,
+                               S.nloc, S.xgrp + x0, S.xgent, S.xbox, nbox, T.level, T.bx, T.by, T.first, T.xs, T.ys,
+                               ws.qs, S.nrm, S.fact, ws.Lam);
         FMMHP_HIP(hipGetLastError());
         return FMMHP_OK;
     };

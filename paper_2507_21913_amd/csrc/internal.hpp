@@ -178,7 +178,7 @@ struct Sched {
     hipStream_t side2 = nullptr;    // second side stream: M2L of the deep levels (default priority)
     hipEvent_t ev_deep_ready = nullptr, ev_deep_done = nullptr;
     int deep_level = 0;             // first level of the deep M2L part (0: no split)
-    std::vector<int> tile_lev, ibox_lev, xbox_lev;  // per-level ranges of tiles, image-V and X boxes
+    std::vector<int> tile_lev, ibox_lev;  // per-level ranges of tiles and image-V boxes
     int cus = 1;                    // compute units of the device
     int near_walk = 1;              // near-field walk: 1 prefetching, 2 plain, 3 symmetric leaf pairs
     // symmetric leaf-pair walk (potential passes): leaves with a U list, their jobs, gather lists
@@ -198,6 +198,11 @@ struct Sched {
     int sub_ld_m2m = 0, sub_ld_l2l = 0;  // LDS expansion slots of the subtree passes
     // subtrees below the cut too large for those slots: parent (M2M) and child (L2L) chunks by level
     int2 *m2m_ch = nullptr, *l2l_ch = nullptr;
+    // P2L groups: {first X box (index into xbox), X sources of the group, first entry of xgent, 0},
+    // one sentinel {nxbox, 0, entries, 0}; groups never cross a level (xgrp_lev[l] = first group of
+    // level l).  xgent: {list entry code, box slot in the group, first row in the group, 0}
+    int4 *xgrp = nullptr, *xgent = nullptr;
+    std::vector<int> xgrp_lev;
     std::vector<int> m2m_ch_lev, l2l_ch_lev;  // [depth + 2] first chunk of each level
     // L2L of levels 4..cut in one launch: subtrees rooted at level 3 (0 subtrees: one launch per level)
     int n_top = 0, top_nlev = 0, top_ld_l2l = 0, top_ld_m2m = 0;  // (the same subtrees serve the M2M)
