@@ -1470,6 +1470,7 @@ struct LeafArgs {
     const int2 *u2;          // per U entry: (first point, point count | image << 31) of its source box
     double isg;              // sign of the image log term: +1 (Robin, Dirichlet), -1 (Neumann)
     const double2 *nrm;      // [n] source normals (sorted order), kDip only
+    int sorted_out;          // phi, gx, gy in sorted order instead (outputs an internal pass reads)
 };
 
 // The hardware places workgroup b on XCD b % 8, and each XCD has its own L2.  xcd_chunks gives a
@@ -2020,7 +2021,8 @@ __global__ __launch_bounds__(256) void k_near_plain(LeafArgs a) {
     }
 }
 
-// L2P of the local(s), plus the near-field sums and the surface term; writes caller order.
+// L2P of the local(s), plus the near-field sums and the surface term; writes caller order (sorted
+// order for a pass whose outputs only the adjoint's combination reads).
 template <int PB, int MODE>
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2062,7 +2064,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
             Gd = irho * hd;
         }
     }
-    const int64_t o = a.perm[i];
+    const int64_t o = a.sorted_out ? i : a.perm[i];
     cplx E = mk(0.0, 0.0);  // e^{-Z(y + ix)} s (real impedance)
     if (a.nloc == 1 && a.rank1) E = cexp_(-(Zk * mk(y, x))) * a.rank1[(int64_t)v * a.n_inst + k];
     if (has_phi(MODE)) {
@@ -3262,6 +3264,7 @@ struct PassOut {
     double *phi = nullptr;      // [nv][n][2]
     cplx *gx = nullptr, *gy = nullptr;
     double *qc = nullptr;
+    bool sorted = false;  // outputs in sorted (tree) order instead of caller order
 };
 
 // One pass over NV charge vectors q [NV][n] (caller order).  Far-field kernels take the vector
@@ -3285,7 +3288,8 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
                 T.off[0],    T.ent[0],  T.off[2], T.ent[2], ws.W,      ws.Lam,    S.invfact, S.fact,
                 S.bc == 0 ? ws.rank1 : nullptr,
                 S.wpts,      S.n_wpts,  S.rpts,   S.logtab, ws.near,   S.bw.near_gx, S.bw.near_gy, out.qc,
-                out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0, S.nrm};
+                out.phi,     out.gx,    out.gy,   S.u2,     S.bc == 2 ? -1.0 : 1.0, S.nrm,
+                out.sorted ? 1 : 0};
     FMMHP_HIP(hipEventRecord(S.ev_fork, s));
     FMMHP_HIP(hipStreamWaitEvent(side_, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, side_));
@@ -3807,10 +3811,10 @@ struct BwdArgs {
     const PtChunk *ch;           // point chunks, each within one instance
     const double *xs, *ys;
     const int32_t *perm;
-    const double *q, *g;         // caller order
-    const cplx *phr, *phi_i;     // Phi[Re c], Phi[Im c]            (caller order)
-    const cplx *gxq, *gyq;       // grad Phi[q]
-    const cplx *gxr, *gyr, *gxi, *gyi;  // grad Phi[Re c], grad Phi[Im c]
+    const double *q3;            // [n][3] (q, Re c, Im c), c = conj(g), sorted
+    const cplx *phr, *phi_i;     // Phi[Re c], Phi[Im c]            (sorted)
+    const cplx *gxq, *gyq;       // grad Phi[q]                     (sorted)
+    const cplx *gxr, *gyr, *gxi, *gyi;  // grad Phi[Re c], grad Phi[Im c] (sorted)
     const double *qc;            // sorted
     double *grad_q, *grad_x, *grad_y;
     cplx *part;                  // [n chunks] partial sums of the impedance identity
@@ -3823,16 +3827,17 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs a) {
     const PtChunk ch = a.ch[blockIdx.x];
     const double x0 = a.ii[ch.inst].x_lo + 0.5 * a.ii[ch.inst].S;
     double ar = 0.0, ai = 0.0;
+    // every input in sorted order (contiguous); only the gradients are scattered to caller order
     for (int64_t i = ch.start + threadIdx.x; i < ch.end; i += 256) {
         const int64_t o = a.perm[i];
-        if (a.grad_q) a.grad_q[o] = a.phr[o].re - a.phi_i[o].im;
+        if (a.grad_q) a.grad_q[o] = a.phr[i].re - a.phi_i[i].im;
         if (!a.want_pos) continue;
-        const cplx c = mk(a.g[2 * o], -a.g[2 * o + 1]);
-        const double qv = a.q[o];
-        const cplx gcx = a.gxr[o] + mul_ipow(a.gxi[o], 1);
-        const cplx gcy = a.gyr[o] + mul_ipow(a.gyi[o], 1);
-        const cplx Dx = c * a.gxq[o] + qv * gcx;
-        const cplx Dy = c * a.gyq[o] + qv * gcy;
+        const cplx c = mk(a.q3[3 * i + 1], a.q3[3 * i + 2]);
+        const double qv = a.q3[3 * i];
+        const cplx gcx = a.gxr[i] + mul_ipow(a.gxi[i], 1);
+        const cplx gcy = a.gyr[i] + mul_ipow(a.gyi[i], 1);
+        const cplx Dx = c * a.gxq[i] + qv * gcx;
+        const cplx Dy = c * a.gyq[i] + qv * gcy;
         if (a.grad_x) a.grad_x[o] = Dx.re;
         if (a.grad_y) a.grad_y[o] = Dy.re;
         const cplx v = (a.xs[i] - x0) * Dx + a.ys[i] * Dy - kInv2Pi * (a.qc[i] * c);
@@ -3896,16 +3901,19 @@ fmmhp_status run_backward(Arena &A, const Tree &T, Sched &S, const double *q, co
         po.gx = b.gx3;
         po.gy = b.gy3;
         po.qc = b.qc;
+        po.sorted = true;
         FMMHP_CHECK((run_pass<kPhiGrad, 3>(T, S, S.ws, b.q3, po, s)));
     } else {
         // dl/dq only: the potentials of Re conj(g) and Im conj(g)
         for (int v = 1; v < 3; ++v) {
             PassOut po;
             po.phi = (double *)(b.phi3 + v * n);
+            po.sorted = true;
             FMMHP_CHECK((run_pass<kPhi, 1>(T, S, S.ws, b.q3 + v * n, po, s)));
         }
     }
-    BwdArgs ba{S.inst_info, S.rch,         T.xs,          T.ys,          T.perm,    q,      g,
+    // the pass left its charges sorted and interleaved in S.ws.qs: (q, Re c, Im c) per point
+    BwdArgs ba{S.inst_info, S.rch,         T.xs,          T.ys,          T.perm,    S.ws.qs,
                b.phi3 + n,  b.phi3 + 2 * n, b.gx3,         b.gy3,         b.gx3 + n, b.gy3 + n,
                b.gx3 + 2 * n, b.gy3 + 2 * n, b.qc,         grad_q,        grad_x,    grad_y, b.red,
                pos ? 1 : 0};
