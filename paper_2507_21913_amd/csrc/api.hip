@@ -125,7 +125,7 @@ static fmmhp_status create_plan(int n_inst, const int64_t *off, const double *x,
     p->sched.m2l_form = (o.flags & FMMHP_FLAG_M2L_VECTOR) ? 1 : (o.flags & FMMHP_FLAG_M2L_MFMA) ? 2 : 0;
     p->sched.bc = (o.flags & FMMHP_FLAG_DIRICHLET) ? 1 : (o.flags & FMMHP_FLAG_NEUMANN) ? 2 : 0;
     if (st == FMMHP_OK) st = build_schedule(p->arena, p->tree, p->sched, pick_bucket(o.p), Zs, stream);
-    if (st == FMMHP_OK) apply_launch_shape(p->sched, o.near_walk, o.near_groups);
+    if (st == FMMHP_OK) st = apply_launch_shape(p->arena, p->tree, p->sched, o.near_walk, o.near_groups, stream);
     p->sched.use_graph = (o.flags & FMMHP_FLAG_GRAPH) != 0;
     if (st == FMMHP_OK) {
         hipError_t e = hipStreamSynchronize(stream);

@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <memory>
 #include <map>
 #include <mutex>
 #include <cmath>
@@ -2518,6 +2520,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     const bool react = S.bc == 0;
     const double isg = S.bc == 2 ? -1.0 : 1.0;
     const int nbox = T.nbox;
+    if (nbox >= (1 << 28)) {  // the tile builder packs a box index and its class into one int32
+        set_error("%d boxes: the schedule supports fewer than 2^28", nbox);
+        return FMMHP_EUNSUPPORTED;
+    }
     std::vector<int32_t> level, bx, by, leaf, voff, vent, xoff, binst;
     FMMHP_CHECK(to_host(binst, T.inst, nbox, s));
     FMMHP_CHECK(to_host(level, T.level, nbox, s));
@@ -2540,31 +2546,62 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     S.m2l_pairs[0] = S.m2l_pairs[1] = 0;
     for (size_t e = 0; e < vent.size(); ++e) S.m2l_pairs[vent[e] & 1] += 1;
 
-    // M2L slots: vslot[b * kNumSlots + o] = upper V source of box b at offset slot o, or -1
-    std::vector<int32_t> vslot((size_t)kNumSlots * nbox, -1);
+    // Host threads for the slot table and the M2L tiles (each takes whole box ranges or tiles)
+    const int nthr = (int)std::max<size_t>(1, std::min<size_t>((size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency())));
+    auto run_threads = [&](auto &&fn) {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthr; ++t) pool.emplace_back(fn, t);
+        fn(0);
+        for (auto &th : pool) th.join();
+    };
+    // M2L slots: vslot[b * kNumSlots + o] = upper V source of box b at offset slot o, or -1; image
+    // V entries (source << 5 | slot) per box.  Threads take contiguous box ranges.
+    std::unique_ptr<int32_t[]> vslot(new int32_t[(size_t)kNumSlots * std::max(1, nbox)]);
     std::vector<int32_t> vimg_off(nbox + 1, 0), vimg_ent;
-    for (int b = 0; b < nbox; ++b) {
-        const int l = level[b];
-        for (int e = voff[b]; e < voff[b + 1]; ++e) {
-            const int c = vent[e] >> 1, img = vent[e] & 1;
-            const int dx = bx[c] - bx[b];
-            const int cy = img ? ((1 << l) - 1 - by[c]) : by[c];
-            const int dy = cy - by[b];
-            if (dx < -3 || dx > 3 || dy < -3 || dy > 3) {
-                set_error("internal: V entry outside the 7x7 offset block");
-                return FMMHP_EUNSUPPORTED;
-            }
-            if (!img) {
-                vslot[(size_t)b * kNumSlots + slot_of(dx, dy)] = c;
-            } else {
-                if (dy > -1) {
-                    set_error("internal: image V entry above its target");
-                    return FMMHP_EUNSUPPORTED;
+    {
+        std::vector<std::vector<int32_t>> img_t(nthr);
+        std::atomic<int> bad{0};  // 1: V entry outside the 7 x 7 block, 2: image entry above its target
+        run_threads([&](int t) {
+            const int b0 = (int)((int64_t)nbox * t / nthr), b1 = (int)((int64_t)nbox * (t + 1) / nthr);
+            std::fill(vslot.get() + (size_t)b0 * kNumSlots, vslot.get() + (size_t)b1 * kNumSlots, -1);
+            std::vector<int32_t> &out = img_t[t];
+            for (int b = b0; b < b1; ++b) {
+                const int l = level[b];
+                for (int e = voff[b]; e < voff[b + 1]; ++e) {
+                    const int c = vent[e] >> 1, img = vent[e] & 1;
+                    const int dx = bx[c] - bx[b];
+                    const int cy = img ? ((1 << l) - 1 - by[c]) : by[c];
+                    const int dy = cy - by[b];
+                    if (dx < -3 || dx > 3 || dy < -3 || dy > 3) {
+                        bad = 1;
+                        continue;
+                    }
+                    if (!img) {
+                        vslot[(size_t)b * kNumSlots + slot_of(dx, dy)] = c;
+                    } else {
+                        if (dy > -1) bad = 2;
+                        out.push_back((c << 5) | slot_of(dx, dy));
+                    }
                 }
-                vimg_ent.push_back((c << 5) | slot_of(dx, dy));
+                vimg_off[b + 1] = (int32_t)out.size();
             }
+        });
+        if (bad == 1) {
+            set_error("internal: V entry outside the 7x7 offset block");
+            return FMMHP_EUNSUPPORTED;
         }
-        vimg_off[b + 1] = (int32_t)vimg_ent.size();
+        if (bad == 2) {
+            set_error("internal: image V entry above its target");
+            return FMMHP_EUNSUPPORTED;
+        }
+        // per-range counts to offsets, then the ranges' entries in box order
+        int32_t base = 0;
+        for (int t = 0; t < nthr; ++t) {
+            const int b0 = (int)((int64_t)nbox * t / nthr), b1 = (int)((int64_t)nbox * (t + 1) / nthr);
+            for (int b = b0; b < b1; ++b) vimg_off[b + 1] += base;
+            base += (int32_t)img_t[t].size();
+            vimg_ent.insert(vimg_ent.end(), img_t[t].begin(), img_t[t].end());
+        }
     }
     FMMHP_CHECK(to_dev(A, &S.vimg_off, vimg_off, "vimg_off", s));
     {
@@ -2615,7 +2652,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                                TileOut &o) -> void {
             uniq.clear();
             for (int q = lo; q < hi; ++q) {
-                const int32_t *vs = &vslot[(size_t)seq[q] * kNumSlots];
+                const int32_t *vs = vslot.get() + (size_t)seq[q] * kNumSlots;
                 for (int k = 0; k < kNumSlots; ++k)
                     if (vs[k] >= 0 && pos[vs[k]] < 0) {
                         pos[vs[k]] = 0;
@@ -2631,10 +2668,10 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             }
             // sources by child class, then box: at one slot the lanes of a one-class tile read
             // nearly consecutive LDS entries (few bank conflicts)
-            std::sort(uniq.begin(), uniq.end(), [&](int32_t u, int32_t v) {
-                const int cu = (bx[u] & 1) | ((by[u] & 1) << 1), cv = (bx[v] & 1) | ((by[v] & 1) << 1);
-                return cu != cv ? cu < cv : u < v;
-            });
+            // (class, box) as one key, class above bit 28 (box indices stay below 2^28)
+            for (int32_t &u : uniq) u |= ((bx[u] & 1) | ((by[u] & 1) << 1)) << 28;
+            std::sort(uniq.begin(), uniq.end());
+            for (int32_t &u : uniq) u &= (1 << 28) - 1;
             for (int i = 0; i < (int)uniq.size(); ++i) pos[uniq[i]] = i;
             const size_t t0 = o.slot.size();
             o.slot.resize(t0 + (size_t)kNumSlots * kTile, (int16_t)-1);
@@ -2644,7 +2681,7 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
                 const int b = q < hi ? seq[q] : -1;
                 o.boxes.push_back(b);
                 if (b < 0) continue;
-                const int32_t *vs = &vslot[(size_t)b * kNumSlots];
+                const int32_t *vs = vslot.get() + (size_t)b * kNumSlots;
                 for (int k = 0; k < kNumSlots; ++k) {
                     if (vs[k] < 0) continue;
                     o.slot[t0 + (size_t)k * kTile + lane] = (int16_t)pos[vs[k]];
@@ -2657,31 +2694,40 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
             o.src.insert(o.src.end(), uniq.begin(), uniq.end());
             o.nsrc.push_back((int32_t)uniq.size());
         };
-        const int nthr = (int)std::max<size_t>(1, std::min<size_t>({init.size(), (size_t)16,
-                                                                      (size_t)std::max(1u, std::thread::hardware_concurrency())}));
-        auto worker = [&](int tid) {
+        run_threads([&](int tid) {
             std::vector<int32_t> pos(nbox, -1), uniq;
             for (size_t i = tid; i < init.size(); i += nthr)
                 build_range(build_range, init[i].first, init[i].second, pos, uniq, outs[i]);
-        };
-        std::vector<std::thread> pool;
-        for (int t = 1; t < nthr; ++t) pool.emplace_back(worker, t);
-        worker(0);
-        for (auto &th : pool) th.join();
-        S.tile_lev.assign(T.depth + 2, 0);
-        for (int l = 2; l <= T.depth; ++l) {
-            S.tile_lev[l] = (int)tlev.size();
-            for (int i = init_lev[l]; i < init_lev[l + 1]; ++i) {
-                const TileOut &o = outs[i];
-                tiles.insert(tiles.end(), o.boxes.begin(), o.boxes.end());
-                tslot.insert(tslot.end(), o.slot.begin(), o.slot.end());
-                tmask.insert(tmask.end(), o.mask.begin(), o.mask.end());
-                tlev.insert(tlev.end(), o.lev.begin(), o.lev.end());
-                tsrc.insert(tsrc.end(), o.src.begin(), o.src.end());
-                for (int32_t c : o.nsrc) tsoff.push_back(tsoff.back() + c);
-            }
+        });
+        // the initial tiles' outputs in order (levels ascending): offsets, then threads copy
+        const size_t ni = init.size();
+        std::vector<size_t> at(ni + 1, 0), as(ni + 1, 0);  // tiles before initial tile i, sources before it
+        for (size_t i = 0; i < ni; ++i) {
+            at[i + 1] = at[i] + outs[i].lev.size();
+            as[i + 1] = as[i] + outs[i].src.size();
         }
-        S.tile_lev[T.depth + 1] = (int)tlev.size();
+        const size_t ntile = at[ni];
+        tiles.resize(ntile * kTile);
+        tslot.resize(ntile * kNumSlots * kTile);
+        tmask.resize(ntile);
+        tlev.resize(ntile);
+        tsrc.resize(as[ni]);
+        tsoff.resize(ntile + 1);
+        tsoff[0] = 0;
+        run_threads([&](int tid) {
+            for (size_t i = tid; i < ni; i += nthr) {
+                const TileOut &o = outs[i];
+                std::copy(o.boxes.begin(), o.boxes.end(), tiles.begin() + at[i] * kTile);
+                std::copy(o.slot.begin(), o.slot.end(), tslot.begin() + at[i] * kNumSlots * kTile);
+                std::copy(o.mask.begin(), o.mask.end(), tmask.begin() + at[i]);
+                std::copy(o.lev.begin(), o.lev.end(), tlev.begin() + at[i]);
+                std::copy(o.src.begin(), o.src.end(), tsrc.begin() + as[i]);
+                int32_t off = (int32_t)as[i];
+                for (size_t k = 0; k < o.nsrc.size(); ++k) tsoff[at[i] + k + 1] = (off += o.nsrc[k]);
+            }
+        });
+        S.tile_lev.assign(T.depth + 2, 0);
+        for (int l = 2; l <= T.depth + 1; ++l) S.tile_lev[l] = (int)at[init_lev[l]];
         S.tile_lev[0] = S.tile_lev[1] = 0;
     }
     S.ntiles = (int)tlev.size();
@@ -3097,14 +3143,57 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         FMMHP_HIP(hipGetLastError());
     }
 
+    // surface-term chunks: at most kSurfChunk points, within one instance
+    {
+        std::vector<PtChunk> ch;
+        std::vector<int32_t> ich(T.n_inst + 1, 0);
+        for (int k = 0; k < T.n_inst; ++k) {
+            for (int64_t a0 = T.inst_off[k]; a0 < T.inst_off[k + 1]; a0 += kSurfChunk)
+                ch.push_back(PtChunk{a0, std::min(T.inst_off[k + 1], a0 + kSurfChunk), k, 0});
+            ich[k + 1] = (int32_t)ch.size();
+        }
+        S.n_rch = (int)ch.size();
+        FMMHP_CHECK(to_dev(A, &S.rch, ch, "surface chunks", s));
+        FMMHP_CHECK(to_dev(A, &S.inst_ch, ich, "instance chunk ranges", s));
+    }
+    // workspace
+    FMMHP_CHECK(ensure_vec_ws(A, T, S, 1));
+    FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
+    FMMHP_HIP(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking));
+    FMMHP_HIP(hipStreamCreateWithFlags(&S.side2, hipStreamNonBlocking));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_deep_ready, hipEventDisableTiming));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_deep_done, hipEventDisableTiming));
+    {
+        int dev = 0, cus = 0;
+        FMMHP_HIP(hipGetDevice(&dev));
+        FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        S.cus = std::max(1, cus);
+    }
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
+    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_up, hipEventDisableTiming));
+    hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
+    FMMHP_HIP(hipGetLastError());
+    FMMHP_HIP(hipStreamSynchronize(s));
+    return FMMHP_OK;
+}
+
+// Schedule of the symmetric near-field walks (near_walk 3 and 4), built the first time a plan
+// selects one of them.
+static fmmhp_status build_sym_walk(Arena &A, const Tree &T, Sched &S, hipStream_t s) {
+    const int nbox = T.nbox;
+    S.sym_built = true;
     // Symmetric near-field walk: records of at most 64 targets (a leaf, or a piece of a larger one),
     // each with its jobs (the self pair, the self-image pair when listed, each cross pair with
     // B > A); the cross jobs of a record own partial slots for B's points.  Per leaf B, the slots
     // of its cross pairs in ascending A (and record).  Every cross pair's mirror entry is checked; a
     // list that is not symmetric leaves the walk off for this plan.
     {
-        std::vector<int32_t> first_h;
+        std::vector<int32_t> first_h, uoff, uent, cnt;
         FMMHP_CHECK(to_host(first_h, T.first, (size_t)nbox, s));
+        FMMHP_CHECK(to_host(uoff, T.off[0], (size_t)nbox + 1, s));
+        FMMHP_CHECK(to_host(uent, T.ent[0], (size_t)T.len[0], s));
+        FMMHP_CHECK(to_host(cnt, T.count, (size_t)nbox, s));
         FMMHP_HIP(hipStreamSynchronize(s));
         std::vector<int4> recs, jobs;
         std::vector<int32_t> in_cnt((size_t)nbox + 1, 0);
@@ -3160,38 +3249,6 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         }
     }
 
-    // surface-term chunks: at most kSurfChunk points, within one instance
-    {
-        std::vector<PtChunk> ch;
-        std::vector<int32_t> ich(T.n_inst + 1, 0);
-        for (int k = 0; k < T.n_inst; ++k) {
-            for (int64_t a0 = T.inst_off[k]; a0 < T.inst_off[k + 1]; a0 += kSurfChunk)
-                ch.push_back(PtChunk{a0, std::min(T.inst_off[k + 1], a0 + kSurfChunk), k, 0});
-            ich[k + 1] = (int32_t)ch.size();
-        }
-        S.n_rch = (int)ch.size();
-        FMMHP_CHECK(to_dev(A, &S.rch, ch, "surface chunks", s));
-        FMMHP_CHECK(to_dev(A, &S.inst_ch, ich, "instance chunk ranges", s));
-    }
-    // workspace
-    FMMHP_CHECK(ensure_vec_ws(A, T, S, 1));
-    FMMHP_CHECK(A.alloc_n(&S.xy, (size_t)T.n, "sorted coordinates (x, y)"));
-    FMMHP_HIP(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking));
-    FMMHP_HIP(hipStreamCreateWithFlags(&S.side2, hipStreamNonBlocking));
-    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_deep_ready, hipEventDisableTiming));
-    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_deep_done, hipEventDisableTiming));
-    {
-        int dev = 0, cus = 0;
-        FMMHP_HIP(hipGetDevice(&dev));
-        FMMHP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        S.cus = std::max(1, cus);
-    }
-    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
-    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
-    FMMHP_HIP(hipEventCreateWithFlags(&S.ev_up, hipEventDisableTiming));
-    hipLaunchKernelGGL(k_pack_xy, dim3(nblk(T.n, 256)), dim3(256), 0, s, T.xs, T.ys, T.n, S.xy);
-    FMMHP_HIP(hipGetLastError());
-    FMMHP_HIP(hipStreamSynchronize(s));
     return FMMHP_OK;
 }
 
@@ -3199,11 +3256,13 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
 // groups: workgroups per CU of its bounded grid.  0 selects the default: the prefetching walk on
 // two workgroups per CU, or for p >= 30 (far-field kernels heavy enough that the near field's
 // instruction count matters more than its latency) the plain walk on four.
-void apply_launch_shape(Sched &S, int walk, int groups) {
+fmmhp_status apply_launch_shape(Arena &A, const Tree &T, Sched &S, int walk, int groups, hipStream_t s) {
     if (walk == 0) walk = S.PB >= 30 ? 2 : 1;
     if (groups == 0) groups = walk == 2 ? 4 : 2;
+    if ((walk == 3 || walk == 4) && !S.sym_built) FMMHP_CHECK(build_sym_walk(A, T, S, s));
     S.near_walk = walk;
     S.near_blocks = (int64_t)groups * S.cus;
+    return FMMHP_OK;
 }
 
 // Phase markers: when timing is on, one event per phase boundary on the eval stream.

@@ -183,6 +183,7 @@ struct Sched {
     int near_walk = 1;              // near-field walk: 1 prefetching, 2 plain, 3 symmetric leaf pairs
     // symmetric leaf-pair walk (potential passes): leaves with a U list, their jobs, gather lists
     bool sym_ok = false;
+    bool sym_built = false;  // the symmetric walks' schedule has been built (on first use)
     int sym_nrec = 0;
     int64_t sym_npart = 0;          // partial-sum entries per vector
     int4 *sym_rec = nullptr;        // (first target, targets, first job, end of jobs) per record
@@ -258,7 +259,7 @@ struct Sched {
 
 // Zs: [T.n_inst] impedance of each instance (host)
 fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cplx *Zs, hipStream_t stream);
-void apply_launch_shape(Sched &S, int near_walk, int near_groups);
+fmmhp_status apply_launch_shape(Arena &A, const Tree &T, Sched &S, int near_walk, int near_groups, hipStream_t s);
 fmmhp_status run_eval(Arena &A, const Tree &T, Sched &S, int nvec, const double *q, double *phi,
                       hipStream_t stream);
 // The same evaluation with each pass's workspace in the library's static device scratch (no

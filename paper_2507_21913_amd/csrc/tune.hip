@@ -184,8 +184,8 @@ extern "C" fmmhp_status fmmhp_tune(int64_t n, const double *x, const double *y, 
             double t[kShapes][kRounds];
             for (int r = 0; r < kRounds && st == FMMHP_OK; ++r)
                 for (int k = 0; k < kShapes && st == FMMHP_OK; ++k) {
-                    apply_launch_shape(plan->sched, shapes[k][0], shapes[k][1]);
-                    st = mean_ms(plan, n_vec, qv, phi, e0, e1, s, &t[k][r]);
+                    st = apply_launch_shape(plan->arena, plan->tree, plan->sched, shapes[k][0], shapes[k][1], s);
+                    if (st == FMMHP_OK) st = mean_ms(plan, n_vec, qv, phi, e0, e1, s, &t[k][r]);
                 }
             if (st == FMMHP_OK) {
                 double med[kShapes];
