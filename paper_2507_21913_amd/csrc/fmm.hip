@@ -915,81 +915,97 @@ __global__ __launch_bounds__(128 * (m2l32_np(PB) / 16)) void k_m2l_f32(M2L32Args
 
 // Image V entries (target boxes in the two rows nearest y = 0 at each level): log M2L of the image
 // box plus the reaction M2L, added to the locals written by k_m2l.  One block per target box and all
-// vectors of the pass: lane (g, n) computes output coefficient n from every G-th V entry of the box
-// (G = min(kImgThreads / (p + 1), kImgGroups) groups), reading the entry's operator row coalesced
-// across n; the groups' sums are joined through LDS in a fixed order.  The same partition for any
-// number of vectors, so a vector's result does not depend on the others in its pass.
+// vectors of the pass: entry group g (G = min(kImgThreads / (p + 1), kImgGroups) groups) sums every
+// G-th V entry of the box, lane n of its thread group computing output coefficient n and reading the
+// entry's operator row coalesced across n; the groups' sums are joined through LDS in a fixed order.
+// The same partition for any number of vectors, so a vector's result does not depend on the others
+// in its pass.
 constexpr int kImgThreads = 256;
 constexpr int kImgGroups = 8;
+// Threads of a block: 256 for one vector; 64 for several (each thread then holds every vector's
+// sums, and a small block keeps more boxes in flight per CU).
+__host__ __device__ constexpr int img_threads(int nv) { return nv == 1 ? kImgThreads : 64; }
 
 template <int PB, int NV>
-__global__ __launch_bounds__(kImgThreads) void k_m2l_img(const int32_t *__restrict__ ibox, int nbox, int nloc,
-                                                         const int32_t *__restrict__ ibase,
-                                                         const int32_t *__restrict__ vimg_off,
-                                                         const int32_t *__restrict__ vimg_ent,
-                                                         const cplx *__restrict__ TH, const cplx *__restrict__ TG,
-                                                         const cplx *__restrict__ Limg,
-                                                         const double *__restrict__ logside, double isg,
-                                                         const cplx *__restrict__ W, cplx *__restrict__ Lam) {
+__global__ __launch_bounds__(img_threads(NV)) void k_m2l_img(const int32_t *__restrict__ ibox, int nbox, int nloc,
+                                                             const int32_t *__restrict__ ibase,
+                                                             const int32_t *__restrict__ vimg_off,
+                                                             const int32_t *__restrict__ vimg_ent,
+                                                             const cplx *__restrict__ TH, const cplx *__restrict__ TG,
+                                                             const cplx *__restrict__ Limg,
+                                                             const double *__restrict__ logside, double isg,
+                                                             const cplx *__restrict__ W, cplx *__restrict__ Lam) {
     constexpr int NTP = m2l_row(PB);
     constexpr int P1 = PB + 1;
+    // G entry groups (entry e in group e mod G), the same for every vector count so that the sums
+    // are formed in one order; GT thread groups of p + 1 lanes each take groups tg + k GT in turn
     constexpr int G = kImgThreads / P1 < kImgGroups ? kImgThreads / P1 : kImgGroups;
-    static_assert(G >= 1, "one group of p + 1 lanes fits the block");
-    __shared__ cplx red[G > 1 ? G - 1 : 1][2][P1];
+    constexpr int GT = img_threads(NV) / P1 < G ? img_threads(NV) / P1 : G;
+    static_assert(G >= 1 && GT >= 1, "one group of p + 1 lanes fits the block");
+    __shared__ cplx red[G > 1 ? G - 1 : 1][NV][2][P1];
     const int b = ibox[blockIdx.x];
     const int tid = threadIdx.x;
-    const int g = tid / P1, n = tid - g * P1;
+    const int tg = tid / P1, n = tid - tg * P1;
     const int l = ibase[b];  // table block of the box's (instance, level)
     const double ll = logside[b] * kInv4Pi;
     cplx aH[NV], aG[NV];
+    if (tg < GT) {
+        // this thread group's entry groups, highest first: thread group 0 ends on group 0, whose
+        // sums stay in registers; every other group's sums go to LDS
+        for (int g = tg + ((G - 1 - tg) / GT) * GT; g >= 0; g -= GT) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) aH[v] = aG[v] = mk(0.0, 0.0);
-    if (g < G) {
-        for (int e = vimg_off[b] + g; e < vimg_off[b + 1]; e += G) {
-            const int code = vimg_ent[e];
-            const int src = code >> 5, is = code & 31;
-            const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
-            const cplx *tg = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
-            // several loads of an entry in flight for one vector; fewer registers with several
+            for (int v = 0; v < NV; ++v) aH[v] = aG[v] = mk(0.0, 0.0);
+            for (int e = vimg_off[b] + g; e < vimg_off[b + 1]; e += G) {
+                const int code = vimg_ent[e];
+                const int src = code >> 5, is = code & 31;
+                const cplx *th = TH + ((int64_t)l * kNumImgSlots + is) * NTP + n;
+                const cplx *tg_ = TG + ((int64_t)l * kNumImgSlots + is) * NTP + n;
+                // several loads of an entry in flight for one vector; fewer registers with several
 #pragma unroll(NV == 1 ? 8 : 2)
-            for (int m = 0; m <= PB; ++m) {
-                const cplx t = th[m];
-                const cplx tq = nloc == 2 ? tg[m] : mk(0.0, 0.0);
+                for (int m = 0; m <= PB; ++m) {
+                    const cplx t = th[m];
+                    const cplx tq = nloc == 2 ? tg_[m] : mk(0.0, 0.0);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const cplx wm = conj(W[((int64_t)v * P1 + m) * nbox + src]);
-                    cfma(aH[v], t, wm);
-                    if (nloc == 2) cfma(aG[v], tq, wm);
+                    for (int v = 0; v < NV; ++v) {
+                        const cplx wm = conj(W[((int64_t)v * P1 + m) * nbox + src]);
+                        cfma(aH[v], t, wm);
+                        if (nloc == 2) cfma(aG[v], tq, wm);
+                    }
+                }
+                if (n == 0) {  // the log term: lambda_0 += (L + log side) conj(w_0), entered with the sign of -a
+                    const cplx f = -(Limg[is] + mk(isg * ll, 0.0));
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const cplx w0 = conj(W[(int64_t)v * P1 * nbox + src]);
+                        cfma(aH[v], f, w0);
+                        cfma(aG[v], f, w0);
+                    }
                 }
             }
-            if (n == 0) {  // the log term: lambda_0 += (L + log side) conj(w_0), entered with the sign of -a
-                const cplx f = -(Limg[is] + mk(isg * ll, 0.0));
+            if (g >= 1) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const cplx w0 = conj(W[(int64_t)v * P1 * nbox + src]);
-                    cfma(aH[v], f, w0);
-                    cfma(aG[v], f, w0);
+                    red[g - 1][v][0][n] = aH[v];
+                    red[g - 1][v][1][n] = aG[v];
                 }
             }
         }
     }
+    // the groups' sums meet in thread group 0, groups in ascending order for every vector
+    if (G > 1) {
+        __syncthreads();
+        if (tg == 0) {
+            for (int h = 0; h + 1 < G; ++h)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        if (G > 1) {
-            if (v > 0) __syncthreads();  // the previous vector's sums have been read
-            if (g >= 1 && g < G) {
-                red[g - 1][0][n] = aH[v];
-                red[g - 1][1][n] = aG[v];
-            }
-            __syncthreads();
-            if (g == 0) {
-                for (int h = 0; h + 1 < G; ++h) {
-                    aH[v] += red[h][0][n];
-                    aG[v] += red[h][1][n];
+                for (int v = 0; v < NV; ++v) {
+                    aH[v] += red[h][v][0][n];
+                    aG[v] += red[h][v][1][n];
                 }
-            }
         }
-        if (g == 0) {
+    }
+    if (tg == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
             cplx *Lv = Lam + (int64_t)v * nloc * P1 * nbox;
             Lv[(int64_t)n * nbox + b] += -aH[v];
             if (nloc == 2) Lv[(int64_t)P1 * nbox + (int64_t)n * nbox + b] += -aG[v];
@@ -2093,6 +2109,38 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
     }
 }
 
+// Steps of the W-list evaluation below: term k of the log-kernel multipole (powers of tau) and
+// term n of the reaction ME (the I_n recursion), for every vector of the pass.
+template <int MODE, int NV>
+__device__ __forceinline__ void leafw_log_step(const LeafArgs &a, int64_t vstride, int d, int img, int k, cplx &pw,
+                                               const cplx &tau, cplx (&u)[NV], cplx (&ud)[NV]) {
+    const double fk1 = a.fact[k - 1], fk = a.fact[k];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        cplx wk = a.W[(int64_t)v * vstride + (int64_t)k * a.nbox + d];
+        if (img) wk = conj(wk);
+        const cplx pk = pw * wk;
+        if (has_phi(MODE)) u[v] -= fk1 * pk;
+        if (has_grad(MODE)) ud[v] += fk * pk;
+    }
+    pw = pw * tau;
+}
+
+template <int PB, int MODE, int NV>
+__device__ __forceinline__ void leafw_react_step(const LeafArgs &a, int64_t vstride, int d, int pass, int n,
+                                                 const cplx &sw, const cplx &zr, cplx &F, cplx &K, cplx (&acc)[NV],
+                                                 cplx (&accd)[NV]) {
+    F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
+    K = F * kInv2Pi + zr * K;
+    const cplx Kn = mul_ipow(pass == 0 ? K : conj(K), n);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const cplx *Wv = a.W + (int64_t)v * vstride;
+        if (has_phi(MODE) && n <= PB) acc[v] += Kn * conj(Wv[(int64_t)n * a.nbox + d]);
+        if (has_grad(MODE)) accd[v] += Kn * conj(Wv[(int64_t)(n - 1) * a.nbox + d]);
+    }
+}
+
 // W list for the targets whose leaf has one: multipoles of smaller non-adjacent boxes evaluated
 // at the target (log kernel, and the paper's reaction ME for image boxes).  Adds to the near-field
 // sums (before k_leaf reads them).
@@ -2134,18 +2182,13 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
             ud[v] = w0;
         }
         cplx pw = tau;
-#pragma unroll(NV == 1 ? PB : 2)
-        for (int k = 1; k <= PB; ++k) {
-            const double fk1 = a.fact[k - 1], fk = a.fact[k];
+        // one vector: the k loop unrolled in full; several: the compiler's own choice (unrolling a
+        // body that already spans every vector crowds the registers)
+        if constexpr (NV == 1) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                cplx wk = a.W[(int64_t)v * vstride + (int64_t)k * a.nbox + d];
-                if (img) wk = conj(wk);
-                const cplx pk = pw * wk;
-                if (has_phi(MODE)) u[v] -= fk1 * pk;
-                if (has_grad(MODE)) ud[v] += fk * pk;
-            }
-            pw = pw * tau;
+            for (int k = 1; k <= PB; ++k) leafw_log_step<MODE, NV>(a, vstride, d, img, k, pw, tau, u, ud);
+        } else {
+            for (int k = 1; k <= PB; ++k) leafw_log_step<MODE, NV>(a, vstride, d, img, k, pw, tau, u, ud);
         }
         const double sgn = (img ? a.ii[a.inst[b]].isg : -1.0) * kInv4Pi;
 #pragma unroll
@@ -2175,17 +2218,13 @@ __global__ __launch_bounds__(128) void k_leaf_w(LeafArgs a) {
                     accd[v] = mk(0.0, 0.0);
                 }
                 constexpr int NTOP = has_grad(MODE) ? PB + 1 : PB;
-#pragma unroll(NV == 1 ? NTOP : 2)
-                for (int n = 1; n <= NTOP; ++n) {
-                    F = F * sw * (n > 1 ? (double)(n - 1) : 1.0);
-                    K = F * kInv2Pi + zr * K;
-                    const cplx Kn = mul_ipow(pass == 0 ? K : conj(K), n);
+                if constexpr (NV == 1) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const cplx *Wv = a.W + (int64_t)v * vstride;
-                        if (has_phi(MODE) && n <= PB) acc[v] += Kn * conj(Wv[(int64_t)n * a.nbox + d]);
-                        if (has_grad(MODE)) accd[v] += Kn * conj(Wv[(int64_t)(n - 1) * a.nbox + d]);
-                    }
+                    for (int n = 1; n <= NTOP; ++n)
+                        leafw_react_step<PB, MODE, NV>(a, vstride, d, pass, n, sw, zr, F, K, acc, accd);
+                } else {
+                    for (int n = 1; n <= NTOP; ++n)
+                        leafw_react_step<PB, MODE, NV>(a, vstride, d, pass, n, sw, zr, F, K, acc, accd);
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -3431,7 +3470,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
         }
         const int i0 = S.ibox_lev[l0], i1 = S.ibox_lev[l1];
         if (i1 > i0)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB, NV>), dim3(i1 - i0), dim3(kImgThreads), 0, st, S.ibox + i0, nbox,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_m2l_img<PB, NV>), dim3(i1 - i0), dim3(img_threads(NV)), 0, st, S.ibox + i0, nbox,
                                S.nloc, S.ibase, S.vimg_off, S.vimg_ent, S.TimgH, S.TimgG, S.Limg, S.logside,
                                S.bc == 2 ? -1.0 : 1.0, ws.W, ws.Lam);
         const int x0 = S.xgrp_lev[l0], x1 = S.xgrp_lev[l1];
