@@ -1030,6 +1030,13 @@ __device__ __forceinline__ double dpp_move(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Lane l's value of x in every lane (l uniform; reads the lane's register whatever the exec mask).
+__device__ __forceinline__ double read_lane_f64(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
 // Sum over aligned groups of IA = 1, 2, 4 or 8 consecutive lanes (every lane of a group gets it).
 __device__ __forceinline__ double lane_group_sum(double s, int IA) {
     if (IA >= 2) s += dpp_move<0xB1, 0xF>(s);   // quad_perm [1, 0, 3, 2]
@@ -1055,28 +1062,99 @@ __device__ __forceinline__ double lane_group_sum(double s, int IA) {
 constexpr int kP2LPhase = 8;   // coefficients per LDS phase with reaction rows (16 without)
 constexpr int kP2LRows = 72;   // row stride of the 8-coefficient layout (68 in the 16-coefficient one)
 
+// Plan-time tables of the P2L: each group entry's first source point (w), and each X box's centre,
+// half side and instance, so that a chunk's loads depend only on its group entries.
+__global__ void k_xgent_first(int64_t m, int4 *__restrict__ gent, const int32_t *__restrict__ first) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) gent[e].w = first[gent[e].x >> 1];
+}
+
+__global__ void k_xgeo(int nx, const int32_t *__restrict__ xbox, const InstInfo *__restrict__ ii,
+                       const int32_t *__restrict__ inst, const int32_t *__restrict__ level,
+                       const int32_t *__restrict__ bx, const int32_t *__restrict__ by, double4 *__restrict__ xgeo) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx) return;
+    const int b = xbox[i], l = level[b], k = inst[b];
+    const Geo g = geo_of(ii, k);
+    const cplx cb = centre_of(g, l, bx[b], by[b]);
+    xgeo[i] = make_double4(cb.re, cb.im, 0.5 * side_of(g, l), (double)k);
+}
+
+// A box slot's sums for several vectors: lane group vg takes vectors vg VPL .. vg VPL + VPL - 1 of
+// the coefficient row Ck and forms, per vector, the G row-group sums that the single-vector lanes
+// form (group g: rows r0 + g, r0 + g + G, ...) and joins them in the order of their lane-move tree,
+// so that every vector's result is bitwise the one of a single-vector pass.
+template <int PB, int NV, int G, int VPL>
+__device__ __forceinline__ void p2l_slot_vectors(const cplx *Ck, const double (*sq)[NV], int r0, int r1, int vg,
+                                                 int m, int ld0, int ld1, int nloc, int nbox, int bsl,
+                                                 cplx *__restrict__ Lam) {
+    constexpr int P1 = PB + 1;
+    cplx pg[G][VPL];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < VPL; ++u) pg[g][u] = mk(0.0, 0.0);
+    // a block's G rows are loaded together (at a valid row past the end) and added in row order
+    for (int r = r0; r < r1; r += G) {
+        cplx t[G];
+        double qv[G][VPL];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int rr = r + g < r1 ? r + g : r1 - 1;
+            t[g] = Ck[rr];
+#pragma unroll
+            for (int u = 0; u < VPL; ++u) {
+                const int v = vg * VPL + u;
+                qv[g][u] = sq[rr][v < NV ? v : 0];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (r + g < r1) {
+#pragma unroll
+                for (int u = 0; u < VPL; ++u)
+                    if (vg * VPL + u < NV) pg[g][u] += qv[g][u] * t[g];
+            }
+        }
+    }
+    if (m > PB) return;
+#pragma unroll
+    for (int u = 0; u < VPL; ++u) {
+        const int v = vg * VPL + u;
+        if (v >= NV) continue;
+        cplx a = (pg[0][u] + pg[1][u]) + (pg[2][u] + pg[3][u]);
+        if constexpr (G == 8) a = a + ((pg[4][u] + pg[5][u]) + (pg[6][u] + pg[7][u]));
+        for (int ld = ld0; ld < ld1; ++ld) {
+            cplx *dst = Lam + (((int64_t)v * nloc + ld) * P1 + m) * nbox + bsl;
+            unsafeAtomicAdd(&dst->re, a.re);
+            unsafeAtomicAdd(&dst->im, a.im);
+        }
+    }
+}
+
 template <int PB, bool DIP, int NV>
 __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, const int32_t *__restrict__ inst,
                                             int nloc, const int4 *__restrict__ grp, const int4 *__restrict__ gent,
-                                            const int32_t *__restrict__ xbox, int nbox,
-                                            const int32_t *__restrict__ level, const int32_t *__restrict__ bx,
-                                            const int32_t *__restrict__ by, const int32_t *__restrict__ first,
-                                            const double *__restrict__ xs, const double *__restrict__ ys,
+                                            const int32_t *__restrict__ xbox, const double4 *__restrict__ xgeo,
+                                            int nbox, const double *__restrict__ xs, const double *__restrict__ ys,
                                             const double *__restrict__ qs, const double2 *__restrict__ nrm,
                                             const double *__restrict__ fact, cplx *__restrict__ Lam) {
     constexpr int P1 = PB + 1;
-    // [local][coefficient in phase][source row], 2 x 8 coefficients or 1 x 16 (row strides 72, 68)
+    // [local][coefficient in phase][source row], 2 x 8 coefficients or 1 x 16 (row strides 72 and 68
+    // with one vector, 65 with several)
     __shared__ cplx C[2 * kP2LPhase * kP2LRows];
     __shared__ double sq[64][NV];
     const int lane = threadIdx.x;
+    // n! in lane n: the term loops read it by lane moves (a scalar load there would wait for the
+    // LDS writes before it, which count on the same counter)
+    const double fact_l = lane <= PB ? fact[lane] : 0.0;
     const int4 gd = grp[blockIdx.x], gn = grp[blockIdx.x + 1];
     const int gs = gd.x, K = gd.y, eg1 = gn.z;
-    const int g8 = lane & 7, kq = lane >> 3;  // summing lane: source group, coefficient in phase
     int elo = gd.z;                            // first list entry of the current chunk
     for (int F = 0; F < K; F += 64) {
         const int f = F + lane;
-        // the chunk's entries {code, slot, first row}: at most 64 (every entry holds a source), in
-        // order of first row; lane f takes the last one starting at or before f
+        // the chunk's entries {code, slot, first row, first source point}: at most 64 (every entry
+        // holds a source), in order of first row; lane f takes the last one starting at or before f
         const int ne = eg1 - elo < 64 ? eg1 - elo : 64;
         const int4 en = lane < ne ? gent[elo + lane] : make_int4(0, 0, 0, 0);
         int my = 0;
@@ -1085,7 +1163,7 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
             if (st > F + 63) break;
             if (st <= f) my = t;
         }
-        const int code = __shfl(en.x, my), s = __shfl(en.y, my), f0 = __shfl(en.z, my);
+        const int code = __shfl(en.x, my), s = __shfl(en.y, my), f0 = __shfl(en.z, my), j0 = __shfl(en.w, my);
         {
             // first entry of the next chunk: lane 63's, or the one after it if that starts the chunk
             const int m63 = __builtin_amdgcn_readlane(my, 63);
@@ -1095,14 +1173,13 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
         }
         const bool act = f < K;
         // the lane's source, target box and the state of its term recursions
-        const int c = code >> 1, img = act ? code & 1 : 0;
-        const int j = act ? first[c] + (f - f0) : 0;
+        const int img = act ? code & 1 : 0;
+        const int j = act ? j0 + (f - f0) : 0;
         const int b = xbox[gs + (act ? s : 0)];
-        const int l = level[b];
-        const int k = inst[b];
-        const Geo g = geo_of(ii, k);
-        const cplx cb = centre_of(g, l, bx[b], by[b]);
-        const double rho = 0.5 * side_of(g, l);
+        const double4 bg = xgeo[gs + (act ? s : 0)];  // target box: centre, half side, instance
+        const cplx cb = mk(bg.x, bg.y);
+        const double rho = bg.z;
+        const int k = (int)bg.w;
         const bool rx = act && img && ii[k].react;
         cplx sig = mk(0.0, 0.0), pw = mk(0.0, 0.0), l0 = mk(0.0, 0.0);
         double sgn = 0.0;
@@ -1160,7 +1237,7 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
         const int ph = mixed ? kP2LPhase : 2 * kP2LPhase;
         const int nl = mixed ? nloc : 1;
         const int G = mixed ? 8 : 4;
-        const int rs = mixed ? kP2LRows : kP2LRows - 4;
+        const int rs = NV > 1 ? kP2LRows - 7 : mixed ? kP2LRows : kP2LRows - 4;
         const int gq = lane & (G - 1), kq = mixed ? lane >> 3 : lane >> 2;
         for (int m0 = 0; m0 <= PB; m0 += ph) {
             if (act) {
@@ -1170,12 +1247,12 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                     if (kk == ph || m > PB) break;
                     cplx t;
                     if (DIP) {
-                        t = fact[m] * pw;
+                        t = read_lane_f64(fact_l, m) * pw;
                         pw = pw * sig;
                     } else if (m == 0) {
                         t = l0;
                     } else {
-                        t = (-sgn * kInv4Pi * fact[m - 1]) * pw;
+                        t = (-sgn * kInv4Pi * read_lane_f64(fact_l, m - 1)) * pw;
                         pw = pw * sig;
                     }
 #pragma unroll
@@ -1202,15 +1279,43 @@ __global__ __launch_bounds__(64) void k_p2l(const InstInfo *__restrict__ ii, con
                 const int r0 = __builtin_ctzll(msk), r1 = 64 - __builtin_clzll(msk);
                 const int bsl = __builtin_amdgcn_readlane(b, r0);  // the slot's box, from its first row
                 for (int lc = 0; lc < nl; ++lc) {
+                    if constexpr (NV > 1) {
+                        // lane (coefficient, vector group); row stride 65: the 16 coefficient rows
+                        // of an access fall on distinct banks
+                        const int kv = lane & (ph - 1), vg = lane / ph;
+                        const cplx *Cv = C + (lc * ph + kv) * rs;
+                        const int ld0 = mixed ? lc : 0, ld1 = mixed ? lc + 1 : nloc;
+                        if (mixed)
+                            p2l_slot_vectors<PB, NV, 8, (NV + 7) / 8>(Cv, sq, r0, r1, vg, m0 + kv, ld0, ld1, nloc,
+                                                                       nbox, bsl, Lam);
+                        else
+                            p2l_slot_vectors<PB, NV, 4, (NV + 3) / 4>(Cv, sq, r0, r1, vg, m0 + kv, ld0, ld1, nloc,
+                                                                       nbox, bsl, Lam);
+                        continue;
+                    }
                     const cplx *Ck = C + (lc * ph + kq) * rs;
                     cplx acc[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) acc[v] = mk(0.0, 0.0);
-#pragma unroll 2
-                    for (int r = r0 + gq; r < r1; r += G) {
-                        const cplx t = Ck[r];
+                    // four of the lane's rows loaded together (at a valid row past the end), added
+                    // in row order
+                    for (int r = r0 + gq; r < r1; r += 4 * G) {
+                        cplx t[4];
+                        double qv[4][NV];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) acc[v] += sq[r][v] * t;
+                        for (int i = 0; i < 4; ++i) {
+                            const int ri = r + i * G < r1 ? r + i * G : r;
+                            t[i] = Ck[ri];
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) qv[i][v] = sq[ri][v];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (r + i * G < r1) {
+#pragma unroll
+                                for (int v = 0; v < NV; ++v) acc[v] += qv[i][v] * t[i];
+                            }
+                        }
                     }
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
@@ -2811,6 +2916,11 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         grp.push_back(make_int4((int)xb.size(), 0, (int)gent.size(), 0));
         FMMHP_CHECK(to_dev(A, &S.xgrp, grp, "P2L groups", s));
         FMMHP_CHECK(to_dev(A, &S.xgent, gent, "P2L group entries", s));
+        FMMHP_CHECK(A.alloc_n(&S.xgeo, xb.size(), "P2L box geometry"));
+        if (!gent.empty())
+            hipLaunchKernelGGL(k_xgent_first, dim3(nblk((int64_t)gent.size(), 256)), dim3(256), 0, s,
+                               (int64_t)gent.size(), S.xgent, T.first);
+        FMMHP_HIP(hipGetLastError());  // (xgeo is filled once the instance table is on the device)
     }
     // deep split: the finest levels holding at least half of the M2L tiles run on a second stream
     // as soon as their multipoles exist, beside the rest of the upward pass
@@ -3048,6 +3158,11 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
         std::vector<InstInfo> ii(T.n_inst);
         for (int k = 0; k < T.n_inst; ++k) ii[k] = InstInfo{T.inst_xlo[k], T.inst_S[k], Zs[k], isg, react ? 1 : 0, 0};
         FMMHP_CHECK(to_dev(A, &S.inst_info, ii, "instance info", s));
+        if (S.nxbox > 0) {  // P2L box geometry (the instance table is needed)
+            hipLaunchKernelGGL(k_xgeo, dim3(nblk((int64_t)S.nxbox, 256)), dim3(256), 0, s, S.nxbox, S.xbox,
+                               S.inst_info, T.inst, T.level, T.bx, T.by, S.xgeo);
+            FMMHP_HIP(hipGetLastError());
+        }
     }
 
     // image M2L tables: one block of kNumImgSlots operators per (instance, level) that has image V
@@ -3392,8 +3507,13 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
     FMMHP_HIP(hipStreamWaitEvent(side_, S.ev_fork, 0));
     if (mk_.on) FMMHP_HIP(hipEventRecord(mk_.near0, side_));
     // a bounded grid (a few workgroups per CU) leaves room on every CU for the far-field kernels
-    // running concurrently on the main stream
-    const dim3 near_grid((unsigned)std::min<int64_t>(nblk(T.n, 256), S.near_blocks));
+    // running concurrently on the main stream.  The launch shape is tuned on potentials; the near
+    // fields of gradients and double layers do several times the work per pair and take at least
+    // kNearHeavyGroups workgroups per CU (eight-vector potentials measured slower so).
+    constexpr bool heavy_near = MODE != kPhi;
+    const int64_t near_blocks = heavy_near ? std::max<int64_t>(S.near_blocks, (int64_t)kNearHeavyGroups * S.cus)
+                                           : S.near_blocks;
+    const dim3 near_grid((unsigned)std::min<int64_t>(nblk(T.n, 256), near_blocks));
     // walk 4 keeps each lane's targets and row sums in registers: single-vector passes only (the
     // others take walk 1)
     const bool sym_walk = MODE == kPhi && S.sym_ok && ws.part && (S.near_walk == 3 || (S.near_walk == 4 && NV == 1));
@@ -3401,7 +3521,7 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
         if (sym_walk) {
             SymArgs sa{S.sym_nrec, S.sym_rec, S.sym_jobs, S.xy, ws.qs, S.logtab, S.bc == 2 ? -1.0 : 1.0,
                        ws.part,    ws.near,   T.n};
-            const dim3 sym_grid((unsigned)std::min<int64_t>(nblk(S.sym_nrec, 4), S.near_blocks));
+            const dim3 sym_grid((unsigned)std::min<int64_t>(nblk(S.sym_nrec, 4), near_blocks));
             if constexpr (NV == 1) {
                 if (S.near_walk == 4)
                     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_near_blk<NV>), sym_grid, dim3(256), 0, side_, sa);
@@ -3476,8 +3596,8 @@ static fmmhp_status eval_pass(const Tree &T, const Sched &S, const VecWs &ws, co
         const int x0 = S.xgrp_lev[l0], x1 = S.xgrp_lev[l1];
         if (x1 > x0)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2l<PB, DIP, NV>), dim3(x1 - x0), dim3(64), 0, st, S.inst_info, T.inst,
-                               S.nloc, S.xgrp + x0, S.xgent, S.xbox, nbox, T.level, T.bx, T.by, T.first, T.xs, T.ys,
-                               ws.qs, S.nrm, S.fact, ws.Lam);
+                               S.nloc, S.xgrp + x0, S.xgent, S.xbox, S.xgeo, nbox, T.xs, T.ys, ws.qs, S.nrm, S.fact,
+                               ws.Lam);
         FMMHP_HIP(hipGetLastError());
         return FMMHP_OK;
     };

@@ -15,6 +15,7 @@ constexpr int kLBits = 30;        // integer cell bits per axis of the root squa
 constexpr int kLBitsForest = 27;  // the same in a forest (instance index in the top key bits)
 constexpr int kMaxInstances = 512;
 constexpr int kVecChunk = 8;        // charge vectors evaluated together
+constexpr int kNearHeavyGroups = 8; // near-field workgroups per CU at least, for gradient and dipole passes
 constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;  // device scratch of fmmhp_eval_noalloc
 constexpr int64_t kSurfChunk = 2048;  // points per partial sum of the surface term
 constexpr double kMaxTablePZ = 24.0;   // |Z| * distance covered by the M2L tables
@@ -201,8 +202,10 @@ struct Sched {
     int2 *m2m_ch = nullptr, *l2l_ch = nullptr;
     // P2L groups: {first X box (index into xbox), X sources of the group, first entry of xgent, 0},
     // one sentinel {nxbox, 0, entries, 0}; groups never cross a level (xgrp_lev[l] = first group of
-    // level l).  xgent: {list entry code, box slot in the group, first row in the group, 0}
+    // level l).  xgent: {list entry code, box slot in the group, first row in the group, first
+    // source point}; xgeo: per X box {centre x, centre y, half side, instance}
     int4 *xgrp = nullptr, *xgent = nullptr;
+    double4 *xgeo = nullptr;
     std::vector<int> xgrp_lev;
     std::vector<int> m2m_ch_lev, l2l_ch_lev;  // [depth + 2] first chunk of each level
     // L2L of levels 4..cut in one launch: subtrees rooted at level 3 (0 subtrees: one launch per level)
