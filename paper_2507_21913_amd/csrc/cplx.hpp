@@ -13,21 +13,24 @@ __host__ __device__ __forceinline__ cplx mk(double r, double i) { return cplx{r,
 __host__ __device__ __forceinline__ cplx operator+(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 __host__ __device__ __forceinline__ cplx operator-(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
 __host__ __device__ __forceinline__ cplx operator-(cplx a) { return {-a.re, -a.im}; }
+// Products of two terms are written with one explicit fused multiply-add each: left to the
+// compiler, which of the two products gets fused can differ between copies of the same code (a loop
+// unrolled for one charge vector, rolled for eight), and with it the rounding.
 __host__ __device__ __forceinline__ cplx operator*(cplx a, cplx b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
 __host__ __device__ __forceinline__ cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
 __host__ __device__ __forceinline__ cplx operator*(cplx a, double s) { return {s * a.re, s * a.im}; }
 __host__ __device__ __forceinline__ cplx& operator+=(cplx& a, cplx b) { a.re += b.re; a.im += b.im; return a; }
 __host__ __device__ __forceinline__ cplx& operator-=(cplx& a, cplx b) { a.re -= b.re; a.im -= b.im; return a; }
 __host__ __device__ __forceinline__ cplx conj(cplx a) { return {a.re, -a.im}; }
-__host__ __device__ __forceinline__ double abs2(cplx a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ __forceinline__ double abs2(cplx a) { return fma(a.re, a.re, a.im * a.im); }
 __host__ __device__ __forceinline__ double cabs(cplx a) { return hypot(a.re, a.im); }
 __host__ __device__ __forceinline__ cplx inv(cplx a) {
     // 1/a with scaling to avoid overflow/underflow of |a|^2
     double s = fmax(fabs(a.re), fabs(a.im));
     double r = a.re / s, i = a.im / s;
-    double d = s * (r * r + i * i);
+    double d = s * fma(r, r, i * i);
     return {r / d, -i / d};
 }
 __host__ __device__ __forceinline__ cplx operator/(cplx a, cplx b) { return a * inv(b); }
