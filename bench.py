@@ -33,7 +33,7 @@ PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X fp32 matrix peak
 # WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
 # (p, leaf size): reported (per launch) only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
-M2L_TRAFFIC = {("0241f5ad8c468e1c", 20, 32): 159.0e6}
+M2L_TRAFFIC = {("04dfe0718a768d5b", 20, 32): 164.4e6}
 
 
 def M2L_ALG_BYTES(info):

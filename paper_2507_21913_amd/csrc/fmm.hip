@@ -3153,7 +3153,12 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     FMMHP_CHECK(to_dev(A, &S.Lfree, Lfree, "Lfree", s));
     {
         std::vector<double> ls(nbox);
-        for (int b = 0; b < nbox; ++b) ls[b] = std::log(ldexp(T.inst_S[binst[b]], -level[b]));  // log(2 rho)
+        // log(2 rho) per (instance, level), the same value for every box there
+        const int nl = T.depth + 1;
+        std::vector<double> lt((size_t)T.n_inst * nl);
+        for (int k = 0; k < T.n_inst; ++k)
+            for (int l = 0; l < nl; ++l) lt[(size_t)k * nl + l] = std::log(ldexp(T.inst_S[k], -l));
+        for (int b = 0; b < nbox; ++b) ls[b] = lt[(size_t)binst[b] * nl + level[b]];
         FMMHP_CHECK(to_dev(A, &S.logside, ls, "log side", s));
         std::vector<InstInfo> ii(T.n_inst);
         for (int k = 0; k < T.n_inst; ++k) ii[k] = InstInfo{T.inst_xlo[k], T.inst_S[k], Zs[k], isg, react ? 1 : 0, 0};
@@ -3186,51 +3191,57 @@ fmmhp_status build_schedule(Arena &A, const Tree &T, Sched &S, int PB, const cpl
     const size_t nblkimg = std::max<size_t>(1, blocks.size());
     std::vector<cplx> TH(nblkimg * kNumImgSlots * NTP, mk(0, 0)), TG(TH.size(), mk(0, 0)),
         Limg(kNumImgSlots, mk(0, 0));
-    std::vector<cplx> K(NT), Km(NT);
-    double pmax = 0.0;
     for (int dy = -3; dy <= -1; ++dy)
         for (int dx = -3; dx <= 3; ++dx) {
             const int is = slot_of(dx, dy);
             const C D((double)dx, (double)dy);
             Limg[is] = cx(isg * i4p * std::log(-D));
         }
-    for (size_t bi = 0; bi < blocks.size(); ++bi) {
-        const int k = blocks[bi].first, l = blocks[bi].second;
-        const cplx Z = Zs[k];
-        const C Zc(Z.re, Z.im);
-        const double sl = ldexp(T.inst_S[k], -l), rho = 0.5 * sl;
-        for (int dy = -3; dy <= -1; ++dy)
-            for (int dx = -3; dx <= 3; ++dx) {
-                if (std::abs(dx) <= 1 && dy == -1) continue;  // adjacent: never in V
-                const int is = slot_of(dx, dy);
-                const C D((double)dx, (double)dy);
-                const C t = 1.0 / (2.0 * D);
-                const double X = -dx * sl, Y = -dy * sl;
-                if (react) {
-                    pmax = std::max(pmax, std::abs(Zc) * std::hypot(X, Y));
-                    reaction_In_scaled_ld(X, Y, Z, rho, NT - 1, K.data());
-                    reaction_In_scaled_ld(-X, Y, Z, rho, NT - 1, Km.data());
-                } else {
-                    std::fill(K.begin(), K.end(), mk(0.0, 0.0));
-                    std::fill(Km.begin(), Km.end(), mk(0.0, 0.0));
-                }
-                C tj = t;
-                for (int j = 0; j < NT; ++j) {
-                    C fr(0.0, 0.0);
-                    if (j >= 1) {
-                        fr = isg * i4p * tj;
-                        tj = tj * t * (double)j;
+    // the blocks are independent (a forest has one per instance and level): host threads take them in
+    // turn, each with its own scratch and its own largest |Z| x separation
+    std::vector<double> pmax_t(nthr, 0.0);
+    run_threads([&](int th) {
+        std::vector<cplx> K(NT), Km(NT);
+        double &pmax = pmax_t[th];
+        for (size_t bi = th; bi < blocks.size(); bi += nthr) {
+            const int k = blocks[bi].first, l = blocks[bi].second;
+            const cplx Z = Zs[k];
+            const C Zc(Z.re, Z.im);
+            const double sl = ldexp(T.inst_S[k], -l), rho = 0.5 * sl;
+            for (int dy = -3; dy <= -1; ++dy)
+                for (int dx = -3; dx <= 3; ++dx) {
+                    if (std::abs(dx) <= 1 && dy == -1) continue;  // adjacent: never in V
+                    const int is = slot_of(dx, dy);
+                    const C D((double)dx, (double)dy);
+                    const C t = 1.0 / (2.0 * D);
+                    const double X = -dx * sl, Y = -dy * sl;
+                    if (react) {
+                        pmax = std::max(pmax, std::abs(Zc) * std::hypot(X, Y));
+                        reaction_In_scaled_ld(X, Y, Z, rho, NT - 1, K.data());
+                        reaction_In_scaled_ld(-X, Y, Z, rho, NT - 1, Km.data());
+                    } else {
+                        std::fill(K.begin(), K.end(), mk(0.0, 0.0));
+                        std::fill(Km.begin(), Km.end(), mk(0.0, 0.0));
                     }
-                    // - j! i^j K_j
-                    C ij(1.0, 0.0);
-                    for (int r = 0; r < (j & 3); ++r) ij *= C(0.0, 1.0);
-                    const C kp(K[j].re, K[j].im), km(Km[j].re, -Km[j].im);
-                    const size_t idx = (bi * kNumImgSlots + is) * NTP + j;
-                    TH[idx] = cx(fr - fact[j] * ij * kp);
-                    TG[idx] = cx(fr - fact[j] * ij * km);
+                    C tj = t;
+                    for (int j = 0; j < NT; ++j) {
+                        C fr(0.0, 0.0);
+                        if (j >= 1) {
+                            fr = isg * i4p * tj;
+                            tj = tj * t * (double)j;
+                        }
+                        // - j! i^j K_j
+                        C ij(1.0, 0.0);
+                        for (int r = 0; r < (j & 3); ++r) ij *= C(0.0, 1.0);
+                        const C kp(K[j].re, K[j].im), km(Km[j].re, -Km[j].im);
+                        const size_t idx = (bi * kNumImgSlots + is) * NTP + j;
+                        TH[idx] = cx(fr - fact[j] * ij * kp);
+                        TG[idx] = cx(fr - fact[j] * ij * km);
+                    }
                 }
-            }
-    }
+        }
+    });
+    const double pmax = *std::max_element(pmax_t.begin(), pmax_t.end());
     if (pmax > kMaxTablePZ) {
         set_error("impedance times box separation reaches %.3g at the coarsest level; the M2L tables "
                   "are accurate up to %.0f",
