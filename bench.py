@@ -34,6 +34,14 @@ PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X fp32 matrix peak
 # (p, leaf size): reported (per launch) only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
 M2L_TRAFFIC = {("04dfe0718a768d5b", 20, 32): 164.4e6}
+# k_near per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), same key
+NEAR_TRAFFIC = {("04dfe0718a768d5b", 20, 32): 52.4e6}
+
+
+def NEAR_ALG_BYTES(info):
+    """Algorithmic HBM bytes of the near field per evaluation: every point's coordinates and charge
+    read once (24 bytes) and its near-field sum written once (16 bytes)."""
+    return 40.0 * info["n"]
 
 
 def M2L_ALG_BYTES(info):
@@ -537,6 +545,11 @@ def main():
                      "achieved": near_fl / (near_ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": near_fl / (near_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
                      "phase_us": near_ms * 1e3, "flops": near_fl, "pairs": info["p2p_pairs"]}
+        nt = NEAR_TRAFFIC.get((eval_source_hash(), info["p"], leaf_use))
+        roof_near["traffic"] = nt
+        roof_near["traffic_kernel"] = "k_near (bytes per launch)"
+        if nt is not None:
+            roof_near["traffic_over_algorithmic"] = nt / NEAR_ALG_BYTES(info)
         if n_s > 0:
             per_eval_s = n_s / max(1, a.steps)
             avg_s = m2l_ms_s / n_s
