@@ -33,9 +33,9 @@ PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X fp32 matrix peak
 # WRITE_SIZE, the factors a plain 256 MiB copy gives), keyed by a hash of the evaluation sources and
 # (p, leaf size): reported (per launch) only while the kernels are the ones that were measured.
 # (k_m2l runs as two launches per evaluation, deep and coarse levels; the figures are their sum.)
-M2L_TRAFFIC = {("04dfe0718a768d5b", 20, 32): 164.4e6}
+M2L_TRAFFIC = {("40e128ed52690a09", 20, 32): 160.0e6}
 # k_near per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), same key
-NEAR_TRAFFIC = {("04dfe0718a768d5b", 20, 32): 52.4e6}
+NEAR_TRAFFIC = {("40e128ed52690a09", 20, 32): 52.4e6}
 
 
 def NEAR_ALG_BYTES(info):

@@ -1049,10 +1049,12 @@ __device__ __forceinline__ double lane_group_sum(double s, int IA) {
 // P2L (X list): sources of a coarse leaf straight into the local of a finer box.  A wave takes a
 // group of X boxes of one level (consecutive boxes whose X sources total at most 64, or one larger
 // box) and walks the group's sources in chunks of 64, one source per lane in the order (box, list
-// entry, point).  Each lane computes its source's terms for unit charge, 8 coefficients at a time
-// and for every local of the plan, into LDS; then lane (k, g) sums coefficient k of each box of the
-// chunk over the box's rows g, g + 8, ..., times the charges of every vector of the pass, and the 8
-// partial sums meet by lane moves.  The log terms are shared by the H and G locals.
+// entry, point).  Each lane computes its source's terms for unit charge into LDS, a phase of
+// coefficients at a time: 16 when the chunk has no reaction rows (the G local's terms then equal the
+// H local's), else 8 of every local.  With one vector, lane (k, g) sums coefficient k of each box of
+// the chunk over the box's rows g, g + G, ... (G = 4 or 8) times the charges, and the G partial sums
+// meet by lane moves; with several, lane (k, vector group) forms the same G partial sums itself and
+// joins them in the same order.  The sums are added to the locals by atomics that return nothing.
 // Dipole sources (DIP) take the derivative of these contributions along the source normal: the log
 // local is holomorphic in d = z_j - c_b (upper box) or in conj(z_j) - c_b (image), so the derivative
 // is nu d/dd (nu = n_x + i n_y, or its conjugate for the image), and for the reaction local
@@ -3777,7 +3779,7 @@ static fmmhp_status ensure_vec_ws(Arena &A, const Tree &T, Sched &S, int nv) {
 }
 
 // Partial sums of the symmetric near-field walk for the plan's workspace, allocated when the walk is
-// in use (walk 3 on a plan whose lists allow it).
+// in use (walk 3 or 4 on a plan whose lists allow it).
 static fmmhp_status ensure_sym_part(Arena &A, Sched &S) {
     if (!((S.near_walk == 3 || S.near_walk == 4) && S.sym_ok) || S.ws.part) return FMMHP_OK;
     return A.alloc_n(&S.ws.part, (size_t)S.ws.cap * S.sym_npart, "near-field pair partial sums");
