@@ -77,6 +77,8 @@ def parse():
                     help="targets of the oracle's direct sum timed for the CPU baseline")
     ap.add_argument("--quiet-extra", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--only", choices=("curve", "batched", "fwd_bwd"), default=None,
+                    help="run only that workload's measurement (for profiling it) and print its record")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -405,6 +407,18 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if a.only is not None:
+        sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))  # the stored oracle samples
+        # one secondary workload alone, on the plan the full run gives it (p = 20, leaf 32 and the
+        # library's default near-field shape for the differentiation workload, unless --p/--leaf)
+        if a.only == "curve":
+            r = curve_extra(dev, max(2, a.steps // 2))
+        elif a.only == "batched":
+            r = batched_extra(dev, 20, 32, 3)
+        else:
+            r = fwd_bwd_extra(dev, a.p or 20, a.leaf or 32, {}, max(2, a.steps // 2))
+        print(json.dumps({"only": a.only, "result": r}), flush=True)
+        return
     w = workloads.uniform_1m(seed=1, n=a.n, p=a.p, leaf_size=a.leaf)
     x = torch.as_tensor(w.x, device=dev)
     y = torch.as_tensor(w.y, device=dev)
