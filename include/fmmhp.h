@@ -78,7 +78,8 @@ typedef struct {
                         leaf pairs with the pairs blocked in registers (each lane holds up to 8
                         targets; column sums reduced over a few lanes; potential evaluations,
                         other passes use walk 1) */
-    int near_groups; /* 0: default; 1..16: near-field workgroups per compute unit */
+    int near_groups; /* 0: default; 1..16: near-field workgroups per compute unit (potential passes;
+                        gradient and double-layer passes take at least 8) */
 } fmmhp_opts;
 
 /* fmmhp_eval records its launches into a HIP graph on the first call with a given (n_vec, q, phi,
@@ -433,11 +434,13 @@ fmmhp_status fmmhp_reaction_integrals(int64_t m, const double *x, const double *
  *   leaf_sizes   [host] candidate leaf sizes (n_leaf entries), or NULL for {24, 32, 40, 48, 64, 96}
  *   sample       targets in the accuracy sample, 1..n (0 selects min(n, 256))
  *   best         [host] receives the chosen options (p, leaf_size, and the launch shape
- *                near_walk, near_groups timed on the chosen plan, four shapes in turn over three
- *                rounds; a shape other than the default needs to be more than 2% faster; then
- *                the M2L form: flags gets FMMHP_FLAG_M2L_FP32 when the FP32 matrix-core M2L on that
- *                plan and shape still meets tol against the direct sum and is more than 2%
- *                faster; max_level 0)
+ *                near_walk, near_groups timed on the chosen plan, six shapes (walks 1, 2 and 4 on
+ *                two to eight workgroups per CU) in turn over three rounds; a shape other than the
+ *                default needs to be more than 2% faster; then the FP64 M2L form: the other of
+ *                FMMHP_FLAG_M2L_VECTOR and FMMHP_FLAG_M2L_MFMA when more than 2% faster; then
+ *                flags gets FMMHP_FLAG_M2L_FP32 when the FP32 matrix-core M2L on that plan and
+ *                shape still meets tol against the direct sum and is more than 2% faster;
+ *                max_level 0)
  *   err, eval_ms [host, may be NULL] the chosen pair's measured error and median eval time
  * Returns FMMHP_EUNSUPPORTED if no candidate reaches tol at p = 40.  Synchronises the stream;
  * allocates and frees its own temporaries. */
