@@ -272,24 +272,27 @@ def fwd_bwd_extra(dev, p, leaf, shape, steps):
     xr, yr, qr = (v.clone().requires_grad_(True) for v in (x, y, q))
     lam = torch.tensor(complex(w.impedance).real, dtype=torch.float64, requires_grad=True)  # real impedance 2
 
-    def step():
+    def step(reuse):
         for t in (xr, yr, qr, lam):
             t.grad = None
-        ph = F.potential(xr, yr, qr, lam, p=p, leaf_size=leaf)
+        ph = F.potential(xr, yr, qr, lam, p=p, leaf_size=leaf, reuse_plan=reuse)
         loss = torch.sum(torch.view_as_real(ph) * torch.view_as_real(gg))
         loss.backward()
 
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n_ag = 3
-    for _ in range(n_ag):
-        step()
-    torch.cuda.synchronize()
-    ms_ag = (time.perf_counter() - t0) * 1e3 / n_ag
-    res["autograd_step"] = {"ms": ms_ag, "mpts_s": w.n / (ms_ag * 1e-3) / 1e6,
-                            "includes": "plan build + forward + backward (dl/dx, dl/dy, dl/dq, dl/dZ to the host)",
-                            "launch_shape": "library default"}
+    for key, reuse, n_ag, what in (
+            ("autograd_step", False, 3,
+             "plan build + forward + backward (dl/dx, dl/dy, dl/dq, dl/dZ to the host), as when the points move"),
+            ("autograd_step_same_points", True, 10,
+             "forward + backward on the plan potential() keeps for unchanged points (dl/dZ to the host)")):
+        step(reuse)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_ag):
+            step(reuse)
+        torch.cuda.synchronize()
+        ms_ag = (time.perf_counter() - t0) * 1e3 / n_ag
+        res[key] = {"ms": ms_ag, "mpts_s": w.n / (ms_ag * 1e-3) / 1e6, "includes": what,
+                    "launch_shape": "library default"}
     hz = 1e-5 * w.impedance
     ls = []
     for Zs in (w.impedance + hz, w.impedance - hz):

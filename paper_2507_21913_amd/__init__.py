@@ -652,13 +652,30 @@ class HalfPlaneFMM:
             pass
 
 
+# potential(): the last plan per device, reused while the same point tensors (unchanged in place:
+# torch's version counter), impedance and options come back.  The cached plan holds the point
+# tensors, so their memory cannot be reused by other tensors while it is cached; a replaced plan
+# closes once no autograd context holds it any more.
+_POT_PLANS: dict = {}
+
+
+def _potential_plan(x, y, lam, p, leaf_size, reuse):
+    key = (x.data_ptr(), y.data_ptr(), x._version, y._version, tuple(x.shape), lam, p, leaf_size)
+    hit = _POT_PLANS.get(x.device) if reuse else None
+    if hit is not None and hit[0] == key:
+        return hit[1]
+    plan = HalfPlaneFMM(x, y, lam, p=p, leaf_size=leaf_size)
+    if reuse:
+        _POT_PLANS[x.device] = (key, plan)
+    return plan
+
+
 class _PotentialFn(torch.autograd.Function):
     """phi = A(x, y, Z) q with the adjoint of fmmhp_backward."""
 
     @staticmethod
-    def forward(ctx, x, y, q, lam, p, leaf_size):
-        plan = HalfPlaneFMM(x.detach(), y.detach(), complex(lam.detach().cpu().item()), p=p,
-                            leaf_size=leaf_size)
+    def forward(ctx, x, y, q, lam, p, leaf_size, reuse):
+        plan = _potential_plan(x.detach(), y.detach(), complex(lam.detach().cpu().item()), p, leaf_size, reuse)
         phi = plan(q.detach())
         ctx.plan = plan
         ctx.lam_dtype = lam.dtype
@@ -674,19 +691,23 @@ class _PotentialFn(torch.autograd.Function):
         if nl:
             v = r["lambda"] if ctx.lam_dtype.is_complex else r["lambda"].real
             gl = torch.tensor(v, dtype=ctx.lam_dtype)
-        return r.get("x"), r.get("y"), r.get("q"), gl, None, None
+        return r.get("x"), r.get("y"), r.get("q"), gl, None, None, None
 
 
-def potential(x, y, q, impedance, p=20, leaf_size=40) -> torch.Tensor:
+def potential(x, y, q, impedance, p=20, leaf_size=40, reuse_plan=True) -> torch.Tensor:
     """Differentiable phi_i = sum_j q_j G(r_i, r_j) over the points (x, y) for real charges q:
     gradients flow to x, y, q and, when it is a tensor, to the impedance (real or complex).
-    The plan (tree, lists, tables) is rebuilt per call."""
+    The plan (tree, lists, tables) is built for the points and reused by later calls with the same
+    x and y tensors, not modified in place since, and the same impedance, p and leaf size (one plan
+    per device; reuse_plan=False builds a new one every call).  Changes to the points that bypass
+    torch's version counter (through .data, or by other libraries writing the memory) are not seen:
+    pass reuse_plan=False then."""
     if q.is_complex():
         raise TypeError("potential() takes real charges; use HalfPlaneFMM for complex ones")
     if not isinstance(impedance, torch.Tensor):
         impedance = torch.tensor(complex(impedance) if isinstance(impedance, complex) else float(impedance),
                                  dtype=torch.complex128 if isinstance(impedance, complex) else torch.float64)
-    return _PotentialFn.apply(x, y, q, impedance, int(p), int(leaf_size))
+    return _PotentialFn.apply(x, y, q, impedance, int(p), int(leaf_size), bool(reuse_plan))
 
 
 def direct(xs, ys, q, impedance, xt=None, yt=None) -> torch.Tensor:

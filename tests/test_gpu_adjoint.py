@@ -14,6 +14,7 @@ import torch
 
 import paper_2507_21913_amd as F
 import workloads
+from oracle import direct as D
 from oracle import grad as GR
 
 sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
@@ -239,3 +240,41 @@ def test_backward_device_equals_backward():
     dl = b["lambda"].cpu().numpy()
     for k in range(3):
         assert np.allclose(dl[k], [a["lambda"][k].real, a["lambda"][k].imag], rtol=1e-14, atol=0), k
+
+
+def test_potential_reuses_its_plan_for_unchanged_points():
+    x, y, q, g = _uniform(800, 17)
+    xt = _t(x).requires_grad_(True)
+    yt = _t(y).requires_grad_(True)
+    qt = _t(q).requires_grad_(True)
+    gt = _t(g)
+    lam = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
+
+    def run(reuse, charges):
+        for t in (xt, yt, qt, lam):
+            t.grad = None
+        phi = F.potential(xt, yt, charges, lam, p=20, leaf_size=16, reuse_plan=reuse)
+        (phi.real * gt.real + phi.imag * gt.imag).sum().backward()
+        return phi.detach().clone(), xt.grad.clone(), yt.grad.clone(), lam.grad.clone()
+
+    first = run(True, qt)
+    plan = F._POT_PLANS[xt.device][1]
+    again = run(True, qt)
+    assert F._POT_PLANS[xt.device][1] is plan  # same tensors, unchanged: the plan is reused
+    fresh = run(False, qt)
+    assert F._POT_PLANS[xt.device][1] is plan  # reuse_plan=False leaves the cache alone
+    for a, b, c in zip(first, again, fresh):
+        assert torch.equal(a, b) and torch.equal(a, c)
+    # an exact rescaling of the charges through the reused plan
+    doubled = run(True, qt * 2.0)
+    assert torch.equal(doubled[0], 2.0 * first[0])
+    # an in-place change of the points (version counter) or another order builds a new plan
+    with torch.no_grad():
+        xt.add_(1e-4)
+    moved = run(True, qt)
+    assert F._POT_PLANS[xt.device][1] is not plan
+    plan2 = F._POT_PLANS[xt.device][1]
+    ref = D.potential(xt.detach().cpu().numpy(), y, q, 2.0, workers=WORKERS)
+    assert _rel(moved[0].cpu().numpy(), ref) < 1e-10
+    F.potential(xt, yt, qt, lam, p=30, leaf_size=16)
+    assert F._POT_PLANS[xt.device][1] is not plan2
