@@ -670,6 +670,11 @@ def _potential_plan(x, y, lam, p, leaf_size, reuse):
     return plan
 
 
+def clear_potential_plans():
+    """Drop the plans potential() keeps for reuse (each closes once no autograd context holds it)."""
+    _POT_PLANS.clear()
+
+
 class _PotentialFn(torch.autograd.Function):
     """phi = A(x, y, Z) q with the adjoint of fmmhp_backward."""
 
@@ -749,5 +754,5 @@ __all__ = ["HalfPlaneFMM", "direct", "reaction_integrals", "lib", "header_functi
            "fmmhp_plan_info", "fmmhp_plan_export_tree", "fmmhp_plan_destroy",
            "fmmhp_direct_eval", "fmmhp_reaction_integrals", "MAX_P",
            "fmmhp_plan_set_timing", "fmmhp_plan_phase_times", "PHASES", "fmmhp_tune", "tune",
-           "fmmhp_backward", "potential", "fmmhp_batch_plan_create", "fmmhp_eval_complex",
+           "fmmhp_backward", "potential", "clear_potential_plans", "fmmhp_batch_plan_create", "fmmhp_eval_complex",
            "fmmhp_eval_noalloc", "NOALLOC_SCRATCH_BYTES"]

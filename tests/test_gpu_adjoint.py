@@ -278,3 +278,5 @@ def test_potential_reuses_its_plan_for_unchanged_points():
     assert _rel(moved[0].cpu().numpy(), ref) < 1e-10
     F.potential(xt, yt, qt, lam, p=30, leaf_size=16)
     assert F._POT_PLANS[xt.device][1] is not plan2
+    F.clear_potential_plans()
+    assert xt.device not in F._POT_PLANS
